@@ -1,0 +1,217 @@
+"""TEST INFRASTRUCTURE -- Python driver for the CPU oracle (``oracle/rpd_oracle.cpp``).
+
+Only the test-suite, ``__graft_entry__.smoke()`` and the benchmark's ``cpu_baseline`` leg may import this module.
+The product path (``paper_2403_18761_amd``) never imports, links or executes anything under ``oracle/``, and this
+module never imports the product package.
+
+The oracle computes, by brute force over all sites with exact integer predicates, the volumetric restricted power
+diagram of weighted sites (power distance |x-c|^2 - r^2, Sec. 3.2), the fractional Euler characteristic of every
+restricted cell, face and edge (Sec. 4.1.2), their connected components (Sec. 4.1.1), the RPV quadruples and the
+cell volumes and centroids. See the header of ``rpd_oracle.cpp`` for the readings it takes where the paper is
+silent.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import subprocess
+import threading
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+SRC = os.path.join(HERE, "rpd_oracle.cpp")
+LIB = os.path.join(HERE, "liboracle.so")
+
+STATUS = {0: "OK", -1: "INVALID", -2: "MESH", -3: "DEGENERATE", -4: "NOMEM", -10: "INCONSISTENT"}
+
+
+def build(force: bool = True) -> str:
+    """Compile the oracle with the host C++ compiler (no GPU code involved)."""
+    if force or not os.path.exists(LIB) or os.path.getmtime(LIB) < os.path.getmtime(SRC):
+        tmp = LIB + f".tmp{os.getpid()}"
+        subprocess.check_call(["g++", "-O2", "-std=c++17", "-shared", "-fPIC", "-pthread", SRC, "-o", tmp])
+        os.replace(tmp, LIB)
+    return LIB
+
+
+class _Result(C.Structure):
+    _fields_ = [
+        ("status", C.c_int32), ("msg", C.c_char * 256), ("L", C.c_int64), ("mesh_chi", C.c_int32),
+        ("mesh_components", C.c_int32), ("n_sites", C.c_int32), ("n_pairs", C.c_int64),
+        ("n_attempted", C.c_int64), ("consistent", C.c_int32), ("report", C.c_char * 512),
+        ("cell_chi", C.POINTER(C.c_int32)), ("cell_chi_asm", C.POINTER(C.c_int32)),
+        ("cell_beta0", C.POINTER(C.c_int32)), ("cell_beta0_skel", C.POINTER(C.c_int32)),
+        ("cell_vol", C.POINTER(C.c_double)), ("cell_cen", C.POINTER(C.c_double)),
+        ("cell_npieces", C.POINTER(C.c_int64)),
+        ("n_faces", C.c_int64), ("face_keys", C.POINTER(C.c_int32)), ("face_chi", C.POINTER(C.c_int32)),
+        ("face_chi_asm", C.POINTER(C.c_int32)), ("face_beta0", C.POINTER(C.c_int32)),
+        ("face_beta0_skel", C.POINTER(C.c_int32)),
+        ("n_edges", C.c_int64), ("edge_keys", C.POINTER(C.c_int32)), ("edge_chi", C.POINTER(C.c_int32)),
+        ("edge_chi_asm", C.POINTER(C.c_int32)), ("edge_beta0", C.POINTER(C.c_int32)),
+        ("edge_beta0_skel", C.POINTER(C.c_int32)),
+        ("n_rpv", C.c_int64), ("rpv_keys", C.POINTER(C.c_int32)),
+        ("max_piece_verts", C.c_int32), ("max_piece_faces", C.c_int32),
+    ]
+
+
+class _Piece(C.Structure):
+    _fields_ = [
+        ("t", C.c_int32), ("i", C.c_int32), ("nverts", C.c_int32), ("nfaces", C.c_int32),
+        ("vol", C.c_double), ("m", C.c_double * 3), ("chi_cell", C.c_int64),
+        ("n_face_terms", C.c_int32), ("n_edge_terms", C.c_int32), ("n_rpv", C.c_int32), ("n_glue", C.c_int32),
+        ("off_face", C.c_int32), ("off_edge", C.c_int32), ("off_rpv", C.c_int32), ("off_glue", C.c_int32),
+    ]
+
+
+class _Pieces(C.Structure):
+    _fields_ = [
+        ("status", C.c_int32), ("msg", C.c_char * 256), ("L", C.c_int64), ("n", C.c_int64),
+        ("pieces", C.POINTER(_Piece)), ("face_terms", C.POINTER(C.c_int32)),
+        ("edge_terms", C.POINTER(C.c_int32)), ("rpv", C.POINTER(C.c_int32)), ("glue", C.POINTER(C.c_int32)),
+    ]
+
+
+_lib = None
+_lock = threading.Lock()
+
+
+def _load():
+    global _lib
+    with _lock:
+        if _lib is None:
+            if not os.path.exists(LIB):
+                build(force=False)
+            lib = C.CDLL(LIB)
+            f32 = C.POINTER(C.c_float)
+            i32 = C.POINTER(C.c_int32)
+            lib.oracle_rpd.argtypes = [C.c_int32, f32, f32, f32, C.c_int32, i32, C.c_int32, f32, f32, f32, f32,
+                                       C.c_int32, C.c_int32, C.POINTER(C.POINTER(_Result))]
+            lib.oracle_rpd.restype = C.c_int
+            lib.oracle_tet_pieces.argtypes = [C.c_int32, f32, f32, f32, C.c_int32, i32, C.c_int32, f32, f32, f32,
+                                              f32, C.c_int32, i32, C.c_int32, C.POINTER(C.POINTER(_Pieces))]
+            lib.oracle_tet_pieces.restype = C.c_int
+            lib.oracle_side_exact.argtypes = [C.POINTER(C.c_int64)]
+            lib.oracle_side_exact.restype = C.c_int
+            lib.oracle_free.argtypes = [C.POINTER(_Result)]
+            lib.oracle_pieces_free.argtypes = [C.POINTER(_Pieces)]
+            _lib = lib
+    return _lib
+
+
+def _f32(a):
+    return np.ascontiguousarray(a, dtype=np.float32)
+
+
+def _ptr(a, t):
+    return a.ctypes.data_as(C.POINTER(t))
+
+
+def _arr(p, n, dtype, shape=None):
+    if n == 0:
+        out = np.zeros(0, dtype=dtype)
+    else:
+        out = np.ctypeslib.as_array(p, shape=(n,)).astype(dtype, copy=True)
+    return out if shape is None else out.reshape(shape)
+
+
+def _i64(lo, hi):
+    return (int(lo) & 0xFFFFFFFF) | (int(hi) << 32)
+
+
+class OracleError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"oracle status {STATUS.get(status, status)}: {msg}")
+        self.status = status
+        self.msg = msg
+
+
+def _inputs(prob):
+    vx, vy, vz = _f32(prob.vx), _f32(prob.vy), _f32(prob.vz)
+    tv = np.ascontiguousarray(prob.tv, dtype=np.int32).reshape(-1)
+    sx, sy, sz, sr = _f32(prob.sx), _f32(prob.sy), _f32(prob.sz), _f32(prob.sr)
+    return vx, vy, vz, tv, sx, sy, sz, sr
+
+
+def rpd(prob, threads: int = 0, assemble: bool = True) -> dict:
+    """Whole-shape oracle. Returns numpy arrays; raises OracleError on a non-OK status."""
+    lib = _load()
+    vx, vy, vz, tv, sx, sy, sz, sr = _inputs(prob)
+    out = C.POINTER(_Result)()
+    lib.oracle_rpd(len(vx), _ptr(vx, C.c_float), _ptr(vy, C.c_float), _ptr(vz, C.c_float), len(tv) // 4,
+                   _ptr(tv, C.c_int32), len(sx), _ptr(sx, C.c_float), _ptr(sy, C.c_float), _ptr(sz, C.c_float),
+                   _ptr(sr, C.c_float), int(threads), int(bool(assemble)), C.byref(out))
+    r = out.contents
+    try:
+        if r.status != 0:
+            raise OracleError(r.status, r.msg.decode())
+        n = r.n_sites
+        nf, ne, nq = r.n_faces, r.n_edges, r.n_rpv
+        res = dict(
+            L=int(r.L), mesh_chi=int(r.mesh_chi), mesh_components=int(r.mesh_components),
+            n_pairs=int(r.n_pairs), n_attempted=int(r.n_attempted), consistent=bool(r.consistent),
+            report=r.report.decode(), max_piece_verts=int(r.max_piece_verts),
+            max_piece_faces=int(r.max_piece_faces),
+            cell_chi=_arr(r.cell_chi, n, np.int32), cell_chi_asm=_arr(r.cell_chi_asm, n, np.int32),
+            cell_beta0=_arr(r.cell_beta0, n, np.int32), cell_beta0_skel=_arr(r.cell_beta0_skel, n, np.int32),
+            cell_vol=_arr(r.cell_vol, n, np.float64), cell_cen=_arr(r.cell_cen, 3 * n, np.float64, (n, 3)),
+            cell_npieces=_arr(r.cell_npieces, n, np.int64),
+            face_keys=_arr(r.face_keys, 2 * nf, np.int32, (nf, 2)), face_chi=_arr(r.face_chi, nf, np.int32),
+            face_chi_asm=_arr(r.face_chi_asm, nf, np.int32), face_beta0=_arr(r.face_beta0, nf, np.int32),
+            face_beta0_skel=_arr(r.face_beta0_skel, nf, np.int32),
+            edge_keys=_arr(r.edge_keys, 3 * ne, np.int32, (ne, 3)), edge_chi=_arr(r.edge_chi, ne, np.int32),
+            edge_chi_asm=_arr(r.edge_chi_asm, ne, np.int32), edge_beta0=_arr(r.edge_beta0, ne, np.int32),
+            edge_beta0_skel=_arr(r.edge_beta0_skel, ne, np.int32),
+            rpv_keys=_arr(r.rpv_keys, 4 * nq, np.int32, (nq, 4)),
+        )
+        return res
+    finally:
+        lib.oracle_free(out)
+
+
+def tet_pieces(prob, tets, threads: int = 0) -> dict:
+    """Per-piece oracle results for the selected tets (each clipped against all sites)."""
+    lib = _load()
+    vx, vy, vz, tv, sx, sy, sz, sr = _inputs(prob)
+    sel = np.ascontiguousarray(tets, dtype=np.int32)
+    out = C.POINTER(_Pieces)()
+    lib.oracle_tet_pieces(len(vx), _ptr(vx, C.c_float), _ptr(vy, C.c_float), _ptr(vz, C.c_float), len(tv) // 4,
+                          _ptr(tv, C.c_int32), len(sx), _ptr(sx, C.c_float), _ptr(sy, C.c_float),
+                          _ptr(sz, C.c_float), _ptr(sr, C.c_float), len(sel), _ptr(sel, C.c_int32), int(threads),
+                          C.byref(out))
+    r = out.contents
+    try:
+        if r.status != 0:
+            raise OracleError(r.status, r.msg.decode())
+        pieces = []
+        for k in range(r.n):
+            p = r.pieces[k]
+            ft = [(r.face_terms[3 * (p.off_face + a)],
+                   _i64(r.face_terms[3 * (p.off_face + a) + 1], r.face_terms[3 * (p.off_face + a) + 2]))
+                  for a in range(p.n_face_terms)]
+            et = [(r.edge_terms[4 * (p.off_edge + a)], r.edge_terms[4 * (p.off_edge + a) + 1],
+                   _i64(r.edge_terms[4 * (p.off_edge + a) + 2], r.edge_terms[4 * (p.off_edge + a) + 3]))
+                  for a in range(p.n_edge_terms)]
+            rv = [tuple(r.rpv[3 * (p.off_rpv + a) + b] for b in range(3)) for a in range(p.n_rpv)]
+            gl = [tuple(r.glue[5 * (p.off_glue + a) + b] for b in range(5)) for a in range(p.n_glue)]
+            pieces.append(dict(t=p.t, i=p.i, nverts=p.nverts, nfaces=p.nfaces, vol=p.vol, m=tuple(p.m),
+                               chi_cell=int(p.chi_cell), face_terms=sorted(ft), edge_terms=sorted(et),
+                               rpv=sorted(rv), glue=sorted(gl)))
+        return dict(L=int(r.L), pieces=pieces)
+    finally:
+        lib.oracle_pieces_free(out)
+
+
+def side_exact(planes) -> int:
+    """Exact sign of plane 3 at the meet of planes 0..2; planes are 4 rows (nx, ny, nz, d) of Python ints with
+    |value| < 2^127. Returns -1/0/+1, or 2 when planes 0..2 have no unique common point."""
+    lib = _load()
+    buf = np.zeros(32, dtype=np.int64)
+    for r in range(4):
+        for k in range(4):
+            v = int(planes[r][k]) & ((1 << 128) - 1)
+            lo = v & ((1 << 64) - 1)
+            hi = v >> 64
+            buf[8 * r + 2 * k] = np.int64(np.uint64(lo).astype(np.int64))
+            buf[8 * r + 2 * k + 1] = np.int64(np.uint64(hi).astype(np.int64))
+    return int(lib.oracle_side_exact(_ptr(buf, C.c_int64)))

@@ -1,0 +1,173 @@
+/*
+ * rpd.h -- C ABI of the MI355X restricted-power-diagram library (librpd.so).
+ *
+ * Computes, for medial spheres (weighted sites) over a tetrahedral mesh of a solid, the volumetric restricted power
+ * diagram (RPD) together with the Euler characteristic and the number of connected components of every restricted
+ * power cell (RPC), face (RPF) and edge (RPE), and the dual adjacency (which pairs, triples and quadruples of sites
+ * meet inside the solid).
+ *
+ * Definitions followed (paper: MATTopo, Sec. 3.2-3.3, 4.1, 5.2):
+ *   - site i = sphere (c_i, r_i), power distance d_i(x) = |x - c_i|^2 - r_i^2 (Sec. 3.2, power-cell equation);
+ *   - closed power cell Omega_i = {x : d_i(x) <= d_j(x) for all j != i};
+ *   - RPC_i = Omega_i & S with S the union of the input tets; RPF_ij = RPC_i & RPC_j; RPE_ijk = RPF_ij & RPC_k;
+ *     RPV_ijkl likewise (Sec. 3.2, duality list);
+ *   - chi = V - E + F - C of any cell decomposition (Sec. 4.1, Euler formula), evaluated with the fractional Euler
+ *     characteristic of Sec. 4.1.2 (weights 1/k inherited from the mesh simplex carrying each clipped element);
+ *   - beta0 = number of connected components (Sec. 4.1.1);
+ *   - volume and centroid of each RPC (Lebesgue measure and first moment over S).
+ *
+ * Input preconditions (Sec. 3.3, Assumption): a manifold tetrahedral mesh with one connected component and no
+ * cavity. This library additionally requires:
+ *   - every coordinate and radius is a finite float32 on the dyadic grid 2^-20 with |coordinate| <= 1 and
+ *     0 <= radius <= 2 (exact integer predicates then have fixed width);
+ *   - tets are positively oriented: det(v1-v0, v2-v0, v3-v0) > 0;
+ *   - general position: no exactly-zero predicate is met (a vertex of a clipped piece exactly on a clipping plane,
+ *     e.g. a mesh vertex on a bisector, five co-spherical sites, duplicate sites); otherwise RPD_E_DEGENERATE.
+ *
+ * Threading: calls on different handles may run concurrently; calls that share a handle must be serialised.
+ * All functions return an rpd_status; on a negative status no output is produced (*out is set to NULL) and
+ * rpd_last_error() (thread-local) describes the failure.
+ */
+#ifndef RPD_H
+#define RPD_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t rpd_status;
+
+#define RPD_OK 0
+#define RPD_E_INVALID (-1)    /* bad argument: NaN/Inf, off-grid value, r < 0, index out of range, bad orientation */
+#define RPD_E_MESH (-2)       /* face shared by more than two tets, several components, simplex multiplicity lcm too big */
+#define RPD_E_DEGENERATE (-3) /* an exact predicate is zero (input not in general position) or duplicate sites */
+#define RPD_E_NOMEM (-4)      /* device or host allocation failed */
+#define RPD_E_DEVICE (-5)     /* HIP runtime error or no device */
+#define RPD_E_INTERNAL (-6)   /* an internal consistency check failed (gluing asymmetry, non-integer chi, ...) */
+
+/* precision of the clipping constructions */
+#define RPD_FP32_FALLBACK 0 /* FP32 clipping; predicates not certified in FP32 are re-done in FP64, then exactly */
+#define RPD_FP64 1          /* FP64 clipping; predicates not certified in FP64 are re-done exactly */
+
+/* element kinds */
+#define RPD_CELL 1
+#define RPD_FACE 2
+#define RPD_EDGE 3
+#define RPD_VERTEX 4 /* RPV quadruples (adjacency only) */
+
+/* rpd_opts.flags */
+#define RPD_DEVICE_PTRS (1u << 0)       /* every input pointer is a device pointer (e.g. a torch tensor's data_ptr) */
+#define RPD_FORCE_FP64 (1u << 1)        /* test-only: treat every FP32 predicate as uncertain (go to FP64) */
+#define RPD_FORCE_EXACT (1u << 2)       /* test-only: treat every floating-point predicate as uncertain (go exact) */
+#define RPD_FORCE_SLOW_PATH (1u << 3)   /* test-only: send every tet through the large-capacity deferred path */
+#define RPD_TIMING (1u << 4)            /* record per-kernel HIP-event timings into rpd_stats */
+#define RPD_KEEP_PIECES (1u << 5)       /* keep per-piece records (rpd_pieces) for sampled comparisons */
+
+/*
+ * A prepared tet mesh (device resident): vertex/tet arrays, face adjacency, the multiplicity k(sigma) of every
+ * vertex, edge and face, the fractional weights L/k(sigma) (Sec. 4.1.2) and a spatial ordering of the tets.
+ * Created once and reused by every rpd_build on that mesh (the paper recomputes the RPD many times per model).
+ */
+typedef struct rpd_mesh rpd_mesh;
+
+typedef struct rpd_mesh_desc {
+  int32_t n_verts;
+  const float *vx, *vy, *vz; /* [n_verts] */
+  int32_t n_tets;
+  const int32_t* tv;         /* [4 * n_tets], vertex indices, positively oriented */
+} rpd_mesh_desc;
+
+typedef struct rpd_mesh_info {
+  int32_t n_verts, n_tets, n_edges, n_faces;
+  int32_t euler;             /* V - E + F - C of the mesh */
+  int32_t components;
+  int64_t L;                 /* lcm of all simplex multiplicities: the fixed-point denominator of chi */
+  double volume;
+} rpd_mesh_info;
+
+typedef struct rpd_sites {
+  int32_t n_sites;
+  const float *sx, *sy, *sz, *sr; /* [n_sites] centres and radii */
+} rpd_sites;
+
+typedef struct rpd_opts {
+  int32_t precision;   /* RPD_FP32_FALLBACK or RPD_FP64 */
+  int32_t clip_budget; /* max candidate sites per tet in the fast path: 0 = default (28) or 8..28 */
+  int32_t block;       /* threads per workgroup of the clipping kernel: 0 = default, else 64/128/256 */
+  uint32_t flags;      /* RPD_* flags above */
+  void* stream;        /* hipStream_t to run on; NULL = the null stream */
+} rpd_opts;
+
+typedef struct rpd_stats {
+  int64_t n_pairs;        /* nonempty pieces P_{t,i} = tet & Omega_i */
+  int64_t n_candidates;   /* (tet, site) pairs clipped in the fast path */
+  int64_t n_deferred;     /* (tet, site) items sent to the large-capacity path */
+  int64_t n_fp64;         /* predicates re-evaluated in FP64 */
+  int64_t n_exact;        /* predicates decided exactly */
+  int64_t n_cells, n_faces, n_edges, n_rpv;
+  int64_t n_glue;         /* gluing records */
+  double ms_clip;         /* HIP-event time of the fast clipping kernel (RPD_TIMING) */
+  double ms_deferred;     /* deferred kernel */
+  double ms_reduce;       /* gluing, union-find, compaction and sorting */
+  double ms_total;        /* whole rpd_build on the stream */
+} rpd_stats;
+
+typedef struct rpd_result rpd_result;
+
+/* Validate and preprocess a mesh (Sec. 4.1.2: weights derived from the combinatorial structure of the tet mesh).
+ * Pointers are borrowed (host, or device with RPD_DEVICE_PTRS in flags) and only read during the call.
+ * Errors: RPD_E_INVALID (off-grid or out-of-range values, bad indices, non-positive orientation),
+ * RPD_E_MESH (a face in more than two tets, more than one component, lcm of multiplicities above 2^24). */
+rpd_status rpd_mesh_create(const rpd_mesh_desc* desc, uint32_t flags, void* stream, rpd_mesh** out);
+rpd_status rpd_mesh_get_info(const rpd_mesh* mesh, rpd_mesh_info* info);
+void rpd_mesh_free(rpd_mesh* mesh);
+
+/* Compute the RPD, chi and beta0 of n_shapes (mesh, sites) pairs in one call (Sec. 5.2 Tet-Cell clipping, Sec. 4.1).
+ * meshes[s] and sites[s] describe shape s; sites pointers are borrowed (host, or device with RPD_DEVICE_PTRS).
+ * The result owns every array reachable from it until rpd_free; results are host-visible when the call returns
+ * (the stream is synchronised once at the end). Errors: RPD_E_INVALID, RPD_E_DEGENERATE, RPD_E_NOMEM,
+ * RPD_E_DEVICE, RPD_E_INTERNAL; no partial result. */
+rpd_status rpd_build(const rpd_mesh* const* meshes, const rpd_sites* sites, int32_t n_shapes, const rpd_opts* opts,
+                     rpd_result** out);
+
+/* chi of every nonempty element of one kind (RPD_CELL: one entry per site, empty cells report 0).
+ * keys: kind site ids per element, ascending within an element; elements sorted lexicographically by key.
+ * Returned pointers are host memory owned by the result. (Sec. 4.1.2 / Sec. 4.1 Euler formula.) */
+rpd_status rpd_euler(const rpd_result* r, int32_t shape, int32_t kind, int64_t* n_out, const int32_t** keys,
+                     const int32_t** chi);
+
+/* beta0 per element, same order as rpd_euler (Sec. 4.1.1). Empty cells report 0. */
+rpd_status rpd_components(const rpd_result* r, int32_t shape, int32_t kind, int64_t* n_out, const int32_t** keys,
+                          const int32_t** beta0);
+
+/* Volume [n_sites] and centroid [3 * n_sites] of every RPC (empty cell: 0 and NaN). Host memory owned by r. */
+rpd_status rpd_geometry(const rpd_result* r, int32_t shape, const double** vol, const double** centroid);
+
+/* Dual adjacency: the element keys of one kind (RPD_FACE pairs, RPD_EDGE triples, RPD_VERTEX quadruples)
+ * (Sec. 3.2, RPC/RPF/RPE/RPV duality). */
+rpd_status rpd_adjacency(const rpd_result* r, int32_t shape, int32_t kind, int64_t* n_out, const int32_t** keys);
+
+/* Counters of the call (summed over shapes). */
+rpd_status rpd_get_stats(const rpd_result* r, rpd_stats* stats);
+
+/* Per-piece records kept with RPD_KEEP_PIECES: for every nonempty piece (tet t in the caller's numbering, site i):
+ * vol, first moment (3), and the fractional chi numerator of its cell contribution (over L). n_out pieces;
+ * arrays are host memory owned by r, ordered by (t, i). */
+rpd_status rpd_pieces(const rpd_result* r, int32_t shape, int64_t* n_out, const int32_t** tet, const int32_t** site,
+                      const double** vol_moment /* 4 per piece */, const int64_t** chi_num);
+
+void rpd_free(rpd_result* r);
+
+/* Thread-local description of the last error of this thread ("" if none). */
+const char* rpd_last_error(void);
+
+/* Library version string. */
+const char* rpd_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* RPD_H */

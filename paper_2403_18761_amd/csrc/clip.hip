@@ -1,0 +1,624 @@
+// Tet-Cell clipping (paper Sec. 5.2) with on-the-fly fractional Euler characteristic (Sec. 4.1.2) and the gluing
+// information for connected components (Sec. 4.1.1).
+//
+// Fast kernel: one workgroup owns TB spatially consecutive tets. It (1) selects the sites that can own any point of
+// the group's bounding box, (2) selects per tet the candidate sites that can own a point of the tet, sorted by power
+// distance at the tet centroid, (3) clips every (tet, candidate) piece by the bisectors of all other candidates, one
+// thread per piece with the polytope in LDS, and (4) emits the piece's volume, moments, chi numerators and gluing
+// bits. Pieces that do not fit (too many candidates or vertices) or whose predicates stay undecided in FP64 are
+// deferred to the large-capacity kernel, which recomputes them with FP64 constructions and exact predicates.
+#include <hip/hip_runtime.h>
+
+#include "rpd_device.h"
+#include "rpd_launch.h"
+
+namespace rpd {
+
+// ---------------------------------------------------------------------------------------------------------------
+// emission of one nonempty piece
+// ---------------------------------------------------------------------------------------------------------------
+template <typename Topo>
+__device__ inline int pos_of(typename Topo::W w, int p) {
+  if (Topo::plane(w, 0) == p) return 0;
+  if (Topo::plane(w, 1) == p) return 1;
+  if (Topo::plane(w, 2) == p) return 2;
+  return -1;
+}
+
+template <typename Topo>
+__device__ inline long long wv_of(typename Topo::W w, const unsigned* nu, long long L) {
+  return w_vertex(Topo::plane(w, 0), Topo::plane(w, 1), Topo::plane(w, 2), nu, L);
+}
+
+__device__ inline void add_fixed(long long* dst, double v) {
+  atomicAdd((unsigned long long*)dst, (unsigned long long)(long long)llrint(v * 72057594037927936.0));  // 2^56
+}
+
+template <typename T, typename Topo, typename Mask, int VCAP, bool EXACT>
+__device__ void emit_piece(Clipper<T, Topo, Mask, VCAP, EXACT>& c, int t, const ShapeArgs& a) {
+  typedef typename Topo::W W;
+  const int i = c.env.site_i;
+  const unsigned* nu = a.nu + 14 * (size_t)t;
+  const long long L = a.L;
+  const int* tn = a.tn + 4 * (size_t)t;
+  int* status = a.status;
+
+  // ---- vertex pass: vertex and edge weights, face references, apex, RPVs
+  long long sv = 0, se = 0;
+  T gx = 0, gy = 0, gz = 0;
+  int nv = 0;
+  for (Mask m = c.live; m; m &= m - 1) {
+    int k = ctz_mask(m);
+    W w = c.st.topo(k);
+    auto v = c.st.get(k);
+    gx += v.x;
+    gy += v.y;
+    gz += v.z;
+    ++nv;
+    int p0 = Topo::plane(w, 0), p1 = Topo::plane(w, 1), p2 = Topo::plane(w, 2);
+    sv += w_vertex(p0, p1, p2, nu, L);
+    for (int e = 0; e < 3; ++e) {
+      int nb = Topo::nb(w, e);
+      if (k < nb) se += w_edge(Topo::plane(w, (e + 1) % 3), Topo::plane(w, (e + 2) % 3), nu, L);
+      int p = Topo::plane(w, e);
+      if (c.tab[p * c.tst] == 0) c.tab[p * c.tst] = (unsigned char)(k + 1);
+    }
+    if (p0 >= 4 && p1 >= 4 && p2 >= 4) {
+      int s0 = c.env.plane_site(p0), s1 = c.env.plane_site(p1), s2 = c.env.plane_site(p2);
+      if (s0 > i && s1 > i && s2 > i) {  // the RPV is recorded once, from its smallest site
+        int lo = min(s0, min(s1, s2)), hi = max(s0, max(s1, s2)), mid = s0 + s1 + s2 - lo - hi;
+        unsigned long long idx = atomicAdd(&a.counters[C_RPV], 1ull);
+        if (idx < (unsigned long long)a.rpv_cap) a.rpv[idx] = make_int4(i, lo, mid, hi);
+        else atomicOr(status, ST_TABLE_FULL);
+      }
+    }
+  }
+  const T inv_nv = T(1) / T(nv);
+  const T ax = gx * inv_nv, ay = gy * inv_nv, az = gz * inv_nv;
+
+  // ---- face pass: face weights, cell gluing, face cycles (volume fans, RPF and RPE terms)
+  long long sf = 0;
+  int cell_glue = 0;
+  T vol = 0, mx = 0, my = 0, mz = 0;
+  for (int p = 0; p < c.np; ++p) {
+    int r = c.tab[p * c.tst];
+    if (r == 0) continue;
+    c.tab[p * c.tst] = 0;
+    r -= 1;
+    sf += (p < 4) ? (long long)nu[10 + p] : L;
+    if (p < 4 && tn[p] >= 0) cell_glue |= 1 << p;
+    const int sp = c.env.plane_site(p);
+    const bool felem = (p >= 4) && (sp > i);
+    long long fv = 0, fe = 0;
+    int fglue = 0;
+    W wr = c.st.topo(r);
+    auto R = c.st.get(r);
+    int ep = pos_of<Topo>(wr, p);
+    if (ep < 0) {
+      atomicOr(status, ST_INTERNAL);
+      continue;
+    }
+    int acur = Topo::plane(wr, (ep + 1) % 3);
+    int nxt = Topo::nb(wr, (ep + 2) % 3);
+    int cur = r;
+    W wcur = wr;
+    auto C = R;
+    if (felem) fv += wv_of<Topo>(wr, nu, L);
+    bool closed = false;
+    for (int step = 0; step <= VCAP; ++step) {
+      W wn = c.st.topo(nxt);
+      auto N = c.st.get(nxt);
+      int ea = pos_of<Topo>(wn, acur), epn = pos_of<Topo>(wn, p);
+      if (ea < 0 || epn < 0) break;
+      if (felem) {  // the edge cur -> nxt lies on planes {p, acur}
+        fe += w_edge(p, acur, nu, L);
+        if (acur < 4) {
+          if (tn[acur] >= 0) fglue |= 1 << acur;
+        } else if (acur > p) {
+          int sa = c.env.plane_site(acur);
+          if (sa > i) {  // RPE piece of {i, sp, sa}, counted from its smaller plane id
+            int e1 = pos_of<Topo>(wcur, p), e2 = pos_of<Topo>(wcur, acur);
+            int t1 = Topo::plane(wcur, 3 - e1 - e2);
+            int t2 = Topo::plane(wn, 3 - ea - epn);
+            long long ev = wv_of<Topo>(wcur, nu, L) + wv_of<Topo>(wn, nu, L) - L;
+            int j = min(sp, sa), k = max(sp, sa);
+            unsigned long long key = ((unsigned long long)i << 42) | ((unsigned long long)j << 21) | (unsigned)k;
+            int es = ht_insert(a.E, key, status);
+            if (es >= 0) {
+              atomicAdd((unsigned long long*)&a.edge_chi[es], (unsigned long long)ev);
+              int ns = ht_insert(a.N, node_key(3, es, t), status);
+              int g = ((t1 < 4 && tn[t1] >= 0) ? (1 << t1) : 0) | ((t2 < 4 && tn[t2] >= 0) ? (1 << t2) : 0);
+              if (ns >= 0 && g) atomicOr(&a.node_glue[ns], g);
+            }
+          }
+        }
+      }
+      if (nxt == r) {
+        closed = true;
+        break;
+      }
+      if (felem) fv += wv_of<Topo>(wn, nu, L);
+      if (cur != r) {  // fan triangle (R, C, N) with the apex: a tet of the piece
+        T ux = C.x - R.x, uy = C.y - R.y, uz = C.z - R.z;
+        T vx = N.x - R.x, vy = N.y - R.y, vz = N.z - R.z;
+        T wx = ax - R.x, wy = ay - R.y, wz = az - R.z;
+        T det = ux * (vy * wz - vz * wy) - uy * (vx * wz - vz * wx) + uz * (vx * wy - vy * wx);
+        T tv = fabs(det) * T(1.0 / 6.0);
+        vol += tv;
+        mx += tv * (R.x + C.x + N.x + ax);
+        my += tv * (R.y + C.y + N.y + ay);
+        mz += tv * (R.z + C.z + N.z + az);
+      }
+      int ec = 3 - ea - epn;
+      int c3 = Topo::plane(wn, ec);
+      int nn = Topo::nb(wn, ea);  // leave nxt along {p, c3}: the neighbour opposite acur
+      cur = nxt;
+      wcur = wn;
+      C = N;
+      acur = c3;
+      nxt = nn;
+    }
+    if (!closed) {
+      atomicOr(status, ST_INTERNAL);
+      continue;
+    }
+    if (felem) {
+      long long fvl = fv - fe + L;
+      unsigned long long key = ((unsigned long long)i << 32) | (unsigned)sp;
+      int fs = ht_insert(a.F, key, status);
+      if (fs >= 0) {
+        atomicAdd((unsigned long long*)&a.face_chi[fs], (unsigned long long)fvl);
+        int ns = ht_insert(a.N, node_key(2, fs, t), status);
+        if (ns >= 0 && fglue) atomicOr(&a.node_glue[ns], fglue);
+      }
+    }
+  }
+  // ---- cell contributions
+  long long chi = sv - se + sf - L;
+  atomicAdd((unsigned long long*)&a.cell_chi[i], (unsigned long long)chi);
+  atomicAdd(&a.cell_np[i], 1);
+  {
+    int ns = ht_insert(a.N, node_key(1, i, t), status);
+    if (ns >= 0 && cell_glue) atomicOr(&a.node_glue[ns], cell_glue);
+  }
+  // moments were accumulated with 4x the centroid sum; shift to absolute coordinates
+  float4 o = c.env.tv[0];
+  double dvol = (double)vol;
+  double dmx = (double)mx * 0.25 + dvol * o.x, dmy = (double)my * 0.25 + dvol * o.y,
+         dmz = (double)mz * 0.25 + dvol * o.z;
+  add_fixed(&a.cell_geo[4 * (size_t)i + 0], dvol);
+  add_fixed(&a.cell_geo[4 * (size_t)i + 1], dmx);
+  add_fixed(&a.cell_geo[4 * (size_t)i + 2], dmy);
+  add_fixed(&a.cell_geo[4 * (size_t)i + 3], dmz);
+  if (a.flags & RPD_KEEP_PIECES) {
+    unsigned long long idx = atomicAdd(&a.counters[C_PIECES], 1ull);
+    if (idx < (unsigned long long)a.piece_cap) {
+      PieceRec pr;
+      pr.t = t;
+      pr.i = i;
+      pr.vol = (float)dvol;
+      pr.mx = (float)dmx;
+      pr.my = (float)dmy;
+      pr.mz = (float)dmz;
+      pr.chi = chi;
+      a.pieces[idx] = pr;
+    } else {
+      atomicOr(status, ST_TABLE_FULL);
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------------------------------------------
+// clipping of one (tet, candidate) piece against the other candidates in order; returns CLIP_* for the piece
+// ---------------------------------------------------------------------------------------------------------------
+template <typename T, typename Topo, typename Mask, int VCAP, bool EXACT>
+__device__ int clip_piece(Clipper<T, Topo, Mask, VCAP, EXACT>& cl, int m, int* status) {
+  const TetEnv& env = cl.env;
+  const float4 o = env.tv[0];
+  const double y1x = (double)env.tv[1].x - o.x, y1y = (double)env.tv[1].y - o.y, y1z = (double)env.tv[1].z - o.z;
+  const double y2x = (double)env.tv[2].x - o.x, y2y = (double)env.tv[2].y - o.y, y2z = (double)env.tv[2].z - o.z;
+  const double y3x = (double)env.tv[3].x - o.x, y3y = (double)env.tv[3].y - o.y, y3z = (double)env.tv[3].z - o.z;
+  cl.init_tet();
+  for (int c = 0; c < m; ++c) {
+    if (c == env.ci) continue;
+    float4 sj = env.cand_site(c);
+    Plane<double> P = bisector64(env.si, sj, o);
+    if (P.nx == 0.0 && P.ny == 0.0 && P.nz == 0.0) {  // concentric spheres: the larger one owns everything
+      if (P.d > 0) continue;
+      if (P.d == 0) atomicOr(status, ST_DEGENERATE);
+      return CLIP_EMPTY;
+    }
+    // the bisector's values at the tet vertices are exact in FP64
+    double h0 = P.d;
+    double h1 = fma(P.nx, y1x, fma(P.ny, y1y, fma(P.nz, y1z, P.d)));
+    double h2 = fma(P.nx, y2x, fma(P.ny, y2y, fma(P.nz, y2z, P.d)));
+    double h3 = fma(P.nx, y3x, fma(P.ny, y3y, fma(P.nz, y3z, P.d)));
+    if (h0 > 0 && h1 > 0 && h2 > 0 && h3 > 0) continue;  // the tet lies in H_ij: no cut
+    if (h0 < 0 && h1 < 0 && h2 < 0 && h3 < 0) return CLIP_EMPTY;
+    int r = cl.clip(4 + c, round_plane<T>(P));
+    if (r != CLIP_OK) return r;
+  }
+  return CLIP_OK;
+}
+
+// ---------------------------------------------------------------------------------------------------------------
+// fast kernel
+// ---------------------------------------------------------------------------------------------------------------
+__device__ inline double wave_min(double v) {
+  for (int off = 32; off > 0; off >>= 1) v = fmin(v, __shfl_xor(v, off));
+  return v;
+}
+__device__ inline float wave_minf(float v) {
+  for (int off = 32; off > 0; off >>= 1) v = fminf(v, __shfl_xor(v, off));
+  return v;
+}
+__device__ inline float wave_maxf(float v) {
+  for (int off = 32; off > 0; off >>= 1) v = fmaxf(v, __shfl_xor(v, off));
+  return v;
+}
+
+template <typename T, int NT>
+__global__ __launch_bounds__(NT) void k_clip_fast(ShapeArgs a) {
+  static_assert(NT % TB == 0 && NT >= TB, "threads per block must be a multiple of the tets per block");
+  constexpr int TPT = NT / TB;  // threads per tet in the candidate phase
+  __shared__ float4 s_tv[TB][4];
+  __shared__ float4 s_face[TB][4];
+  __shared__ float4 s_site[SLMAX];
+  __shared__ int s_sid[SLMAX];
+  __shared__ unsigned char s_cand[TB][KMAX];
+  __shared__ double s_key[TB][KMAX];
+  __shared__ int s_m[TB];
+  __shared__ int s_off[TB + 1];
+  __shared__ float s_box[6];
+  __shared__ double s_red[NT / 64];
+  __shared__ int s_nsl;
+  __shared__ unsigned long long s_cnt[4];
+  __shared__ typename Coord4<T>::type s_xyz[VMAX * NT];
+  __shared__ unsigned s_topo[VMAX * NT];
+  __shared__ unsigned char s_tab[32 * NT];
+
+  const int tid = threadIdx.x;
+  const int lane = tid & 63, wid = tid >> 6;
+  const int t0 = blockIdx.x * TB;
+  const int ntb = min(TB, a.nt - t0);
+
+  // ---- 1. load the tets, their face planes and the bounding box
+  float lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
+  if (tid < TB) {
+    if (tid < ntb) {
+      const float4* tp = a.tp + 4 * (size_t)(t0 + tid);
+      for (int v = 0; v < 4; ++v) {
+        float4 p = tp[v];
+        s_tv[tid][v] = p;
+        lo[0] = fminf(lo[0], p.x);
+        lo[1] = fminf(lo[1], p.y);
+        lo[2] = fminf(lo[2], p.z);
+        hi[0] = fmaxf(hi[0], p.x);
+        hi[1] = fmaxf(hi[1], p.y);
+        hi[2] = fmaxf(hi[2], p.z);
+      }
+      for (int f = 0; f < 4; ++f) {
+        Plane<float> pf = round_plane<float>(face_plane64(s_tv[tid], f));
+        s_face[tid][f] = make_float4(pf.nx, pf.ny, pf.nz, pf.d);
+      }
+    }
+    s_m[tid] = 0;
+    for (int k = 0; k < 3; ++k) {
+      float l = wave_minf(lo[k]), h = wave_maxf(hi[k]);
+      if (tid == 0) {
+        s_box[k] = l;
+        s_box[3 + k] = h;
+      }
+    }
+  }
+  if (tid < 4) s_cnt[tid] = 0;
+  if (tid == 0) s_nsl = 0;
+  for (int k = tid; k < 32 * NT; k += NT) s_tab[k] = 0;
+  __syncthreads();
+
+  // ---- 2. sites that can own a point of the box: min over the box of g_j <= min over j of max over the box
+  //        (g_j(x) = d_j(x) - |x - o|^2 is affine; values exact in FP64)
+  const double bx = s_box[0], by = s_box[1], bz = s_box[2];
+  const double ex = (double)s_box[3] - bx, ey = (double)s_box[4] - by, ez = (double)s_box[5] - bz;
+  double umin = INFINITY;
+  for (int j = tid; j < a.ns; j += NT) {
+    float4 s = a.site[j];
+    double ax_ = (double)s.x - bx, ay_ = (double)s.y - by, az_ = (double)s.z - bz;
+    double D = ax_ * ax_ + ay_ * ay_ + az_ * az_ - (double)s.w * s.w;
+    double gmax = D + fmax(0.0, -2.0 * ex * ax_) + fmax(0.0, -2.0 * ey * ay_) + fmax(0.0, -2.0 * ez * az_);
+    umin = fmin(umin, gmax);
+  }
+  umin = wave_min(umin);
+  if (lane == 0) s_red[wid] = umin;
+  __syncthreads();
+  double UB = s_red[0];
+  for (int w = 1; w < NT / 64; ++w) UB = fmin(UB, s_red[w]);
+  for (int j = tid; j < a.ns; j += NT) {
+    float4 s = a.site[j];
+    double ax_ = (double)s.x - bx, ay_ = (double)s.y - by, az_ = (double)s.z - bz;
+    double D = ax_ * ax_ + ay_ * ay_ + az_ * az_ - (double)s.w * s.w;
+    double gmin = D + fmin(0.0, -2.0 * ex * ax_) + fmin(0.0, -2.0 * ey * ay_) + fmin(0.0, -2.0 * ez * az_);
+    if (gmin <= UB) {
+      int q = atomicAdd(&s_nsl, 1);
+      if (q < SLMAX) {
+        s_site[q] = s;
+        s_sid[q] = j;
+      }
+    }
+  }
+  __syncthreads();
+  const int nsl = s_nsl;
+  const bool block_overflow = nsl > SLMAX || (a.flags & RPD_FORCE_SLOW_PATH);
+
+  // ---- 3. candidates of every tet: sites whose minimum over the tet is <= min_j max over the tet
+  if (!block_overflow) {
+    const int lt = tid / TPT, h = tid % TPT;
+    if (lt < ntb) {
+      const float4* tv = s_tv[lt];
+      const float4 o = tv[0];
+      double y[3][3];
+      for (int v = 1; v < 4; ++v) {
+        y[v - 1][0] = (double)tv[v].x - o.x;
+        y[v - 1][1] = (double)tv[v].y - o.y;
+        y[v - 1][2] = (double)tv[v].z - o.z;
+      }
+      const double ycx = (y[0][0] + y[1][0] + y[2][0]) * 0.25, ycy = (y[0][1] + y[1][1] + y[2][1]) * 0.25,
+                   ycz = (y[0][2] + y[1][2] + y[2][2]) * 0.25;
+      double U = INFINITY;
+      for (int q = h; q < nsl; q += TPT) {
+        float4 s = s_site[q];
+        double ax_ = (double)s.x - o.x, ay_ = (double)s.y - o.y, az_ = (double)s.z - o.z;
+        double D = ax_ * ax_ + ay_ * ay_ + az_ * az_ - (double)s.w * s.w;
+        double gmx = D;
+        for (int v = 0; v < 3; ++v) gmx = fmax(gmx, D - 2.0 * (y[v][0] * ax_ + y[v][1] * ay_ + y[v][2] * az_));
+        U = fmin(U, gmx);
+      }
+      for (int off = 1; off < TPT; off <<= 1) U = fmin(U, __shfl_xor(U, off));
+      for (int q = h; q < nsl; q += TPT) {
+        float4 s = s_site[q];
+        double ax_ = (double)s.x - o.x, ay_ = (double)s.y - o.y, az_ = (double)s.z - o.z;
+        double D = ax_ * ax_ + ay_ * ay_ + az_ * az_ - (double)s.w * s.w;
+        double gmn = D;
+        for (int v = 0; v < 3; ++v) gmn = fmin(gmn, D - 2.0 * (y[v][0] * ax_ + y[v][1] * ay_ + y[v][2] * az_));
+        if (gmn <= U) {
+          int pos = atomicAdd(&s_m[lt], 1);
+          if (pos < KMAX) {
+            s_cand[lt][pos] = (unsigned char)q;
+            s_key[lt][pos] = D - 2.0 * (ycx * ax_ + ycy * ay_ + ycz * az_);
+          }
+        }
+      }
+    }
+  }
+  __syncthreads();
+  // sort each tet's candidates by (power distance at the centroid, site id); mark overflowing tets
+  if (tid < ntb) {
+    int m = s_m[tid];
+    if (block_overflow || m > a.kmax) {
+      s_m[tid] = -1;
+      unsigned long long idx = atomicAdd(&a.counters[C_DEFER_ITEMS], 1ull);
+      if (idx < (unsigned long long)a.deferred_cap) a.deferred[idx] = make_int2(t0 + tid, -1);
+      else atomicOr(a.status, ST_TABLE_FULL);
+    } else {
+      for (int x = 1; x < m; ++x) {
+        double kx = s_key[tid][x];
+        unsigned char cx = s_cand[tid][x];
+        int ix = s_sid[cx];
+        int y = x - 1;
+        while (y >= 0 && (s_key[tid][y] > kx || (s_key[tid][y] == kx && s_sid[s_cand[tid][y]] > ix))) {
+          s_key[tid][y + 1] = s_key[tid][y];
+          s_cand[tid][y + 1] = s_cand[tid][y];
+          --y;
+        }
+        s_key[tid][y + 1] = kx;
+        s_cand[tid][y + 1] = cx;
+      }
+    }
+  }
+  __syncthreads();
+  if (tid == 0) {
+    int acc = 0;
+    for (int lt = 0; lt < TB; ++lt) {
+      s_off[lt] = acc;
+      if (lt < ntb && s_m[lt] > 0) acc += s_m[lt];
+    }
+    s_off[TB] = acc;
+  }
+  __syncthreads();
+
+  // ---- 4. one thread per (tet, candidate) piece
+  const int npairs = s_off[TB];
+  unsigned long long n_pairs = 0, n64 = 0, nex = 0;
+  for (int p = tid; p < npairs; p += NT) {
+    int lo_ = 0, hi_ = TB - 1;  // last lt with s_off[lt] <= p
+    while (lo_ < hi_) {
+      int mid = (lo_ + hi_ + 1) >> 1;
+      if (s_off[mid] <= p) lo_ = mid;
+      else hi_ = mid - 1;
+    }
+    const int lt = lo_;
+    const int ci = p - s_off[lt];
+    const int m = s_m[lt];
+    Clipper<T, Topo32, unsigned, VMAX, false> cl;
+    cl.st.c = s_xyz + tid;
+    cl.st.w = s_topo + tid;
+    cl.st.stride = NT;
+    cl.tab = s_tab + tid;
+    cl.tst = NT;
+    cl.a = &a;
+    cl.flags = a.flags;
+    cl.np = 4 + m;
+    cl.n64 = 0;
+    cl.nex = 0;
+    cl.env.tv = s_tv[lt];
+    cl.env.faceT = s_face[lt];
+    cl.env.sites = s_site;
+    cl.env.sid = s_sid;
+    cl.env.cidx8 = s_cand[lt];
+    cl.env.cidx32 = nullptr;
+    cl.env.ci = ci;
+    cl.env.si = s_site[s_cand[lt][ci]];
+    cl.env.site_i = s_sid[s_cand[lt][ci]];
+    int r = clip_piece(cl, m, a.status);
+    n64 += cl.n64;
+    if (r == CLIP_OK) {
+      ++n_pairs;
+      emit_piece(cl, t0 + lt, a);
+    } else if (r == CLIP_DEFER) {
+      unsigned long long idx = atomicAdd(&a.counters[C_DEFER_ITEMS], 1ull);
+      if (idx < (unsigned long long)a.deferred_cap) a.deferred[idx] = make_int2(t0 + lt, cl.env.site_i);
+      else atomicOr(a.status, ST_TABLE_FULL);
+    }
+  }
+  atomicAdd(&s_cnt[0], n_pairs);
+  atomicAdd(&s_cnt[1], n64);
+  __syncthreads();
+  if (tid == 0) {
+    atomicAdd(&a.counters[C_PAIRS], s_cnt[0]);
+    atomicAdd(&a.counters[C_FP64], s_cnt[1]);
+    atomicAdd(&a.counters[C_CAND], (unsigned long long)npairs);
+  }
+}
+
+// ---------------------------------------------------------------------------------------------------------------
+// large-capacity kernel: one thread per deferred item, FP64 constructions, exact predicates, global scratch
+// ---------------------------------------------------------------------------------------------------------------
+struct SlowScratch {
+  static constexpr size_t cand_bytes = SLOW_KMAX * sizeof(int);
+  static constexpr size_t key_bytes = SLOW_KMAX * sizeof(double);
+  static constexpr size_t xyz_bytes = SLOW_VMAX * sizeof(Coord4<double>::type);
+  static constexpr size_t topo_bytes = SLOW_VMAX * sizeof(unsigned long long);
+  static constexpr size_t tab_bytes = (SLOW_PMAX + 15) / 16 * 16;
+  static constexpr size_t bytes = cand_bytes + key_bytes + xyz_bytes + topo_bytes + tab_bytes;
+};
+
+__global__ __launch_bounds__(64) void k_clip_slow(ShapeArgs a, unsigned char* scratch) {
+  const int n_items = (int)min(a.counters[C_DEFER_ITEMS], (unsigned long long)a.deferred_cap);
+  const int gt = blockIdx.x * blockDim.x + threadIdx.x;
+  if (gt >= n_items) return;
+  const int gs = gridDim.x * blockDim.x;
+  unsigned char* base = scratch + (size_t)gt * SlowScratch::bytes;
+  int* cand = (int*)base;
+  double* key = (double*)(base + SlowScratch::cand_bytes);
+  Coord4<double>::type* xyz = (Coord4<double>::type*)(base + SlowScratch::cand_bytes + SlowScratch::key_bytes);
+  unsigned long long* topo =
+      (unsigned long long*)(base + SlowScratch::cand_bytes + SlowScratch::key_bytes + SlowScratch::xyz_bytes);
+  unsigned char* tab = base + SlowScratch::cand_bytes + SlowScratch::key_bytes + SlowScratch::xyz_bytes +
+                       SlowScratch::topo_bytes;
+  for (int k = 0; k < SLOW_PMAX; ++k) tab[k] = 0;
+  unsigned long long n_pairs = 0, n64 = 0, nex = 0, ncand = 0;
+  for (int it = gt; it < n_items; it += gs) {
+    const int t = a.deferred[it].x;
+    const int want = a.deferred[it].y;
+    float4 tv[4];
+    for (int v = 0; v < 4; ++v) tv[v] = a.tp[4 * (size_t)t + v];
+    const float4 o = tv[0];
+    double y[3][3];
+    for (int v = 1; v < 4; ++v) {
+      y[v - 1][0] = (double)tv[v].x - o.x;
+      y[v - 1][1] = (double)tv[v].y - o.y;
+      y[v - 1][2] = (double)tv[v].z - o.z;
+    }
+    const double ycx = (y[0][0] + y[1][0] + y[2][0]) * 0.25, ycy = (y[0][1] + y[1][1] + y[2][1]) * 0.25,
+                 ycz = (y[0][2] + y[1][2] + y[2][2]) * 0.25;
+    // candidates among ALL sites
+    double U = INFINITY;
+    for (int j = 0; j < a.ns; ++j) {
+      float4 s = a.site[j];
+      double ax_ = (double)s.x - o.x, ay_ = (double)s.y - o.y, az_ = (double)s.z - o.z;
+      double D = ax_ * ax_ + ay_ * ay_ + az_ * az_ - (double)s.w * s.w;
+      double gmx = D;
+      for (int v = 0; v < 3; ++v) gmx = fmax(gmx, D - 2.0 * (y[v][0] * ax_ + y[v][1] * ay_ + y[v][2] * az_));
+      U = fmin(U, gmx);
+    }
+    int m = 0;
+    for (int j = 0; j < a.ns; ++j) {
+      float4 s = a.site[j];
+      double ax_ = (double)s.x - o.x, ay_ = (double)s.y - o.y, az_ = (double)s.z - o.z;
+      double D = ax_ * ax_ + ay_ * ay_ + az_ * az_ - (double)s.w * s.w;
+      double gmn = D;
+      for (int v = 0; v < 3; ++v) gmn = fmin(gmn, D - 2.0 * (y[v][0] * ax_ + y[v][1] * ay_ + y[v][2] * az_));
+      if (gmn <= U) {
+        if (m >= SLOW_KMAX) {
+          atomicOr(a.status, ST_SLOW_CAPACITY);
+          m = -1;
+          break;
+        }
+        double kk = D - 2.0 * (ycx * ax_ + ycy * ay_ + ycz * az_);
+        int x = m++;
+        while (x > 0 && key[x - 1] > kk) {  // j ascends, so ties keep the smaller id first
+          key[x] = key[x - 1];
+          cand[x] = cand[x - 1];
+          --x;
+        }
+        key[x] = kk;
+        cand[x] = j;
+      }
+    }
+    if (m < 0) continue;
+    ncand += m;
+    for (int ci = 0; ci < m; ++ci) {
+      if (want >= 0 && cand[ci] != want) continue;
+      Clipper<double, Topo64, unsigned long long, SLOW_VMAX, true> cl;
+      cl.st.c = xyz;
+      cl.st.w = topo;
+      cl.st.stride = 1;
+      cl.tab = tab;
+      cl.tst = 1;
+      cl.a = &a;
+      cl.flags = a.flags & ~RPD_FORCE_FP64;
+      cl.np = 4 + m;
+      cl.n64 = 0;
+      cl.nex = 0;
+      cl.env.tv = tv;
+      cl.env.faceT = nullptr;
+      cl.env.sites = a.site;
+      cl.env.sid = nullptr;  // candidates hold site ids directly
+      cl.env.cidx8 = nullptr;
+      cl.env.cidx32 = cand;
+      cl.env.ci = ci;
+      cl.env.si = a.site[cand[ci]];
+      cl.env.site_i = cand[ci];
+      int r = clip_piece(cl, m, a.status);
+      n64 += cl.n64;
+      nex += cl.nex;
+      if (r == CLIP_DEFER) {
+        atomicOr(a.status, ST_SLOW_CAPACITY);
+        continue;
+      }
+      if (r == CLIP_OK) {
+        ++n_pairs;
+        emit_piece(cl, t, a);
+      }
+    }
+  }
+  atomicAdd(&a.counters[C_PAIRS], n_pairs);
+  atomicAdd(&a.counters[C_FP64], n64);
+  atomicAdd(&a.counters[C_EXACT], nex);
+}
+
+// ---------------------------------------------------------------------------------------------------------------
+// launchers
+// ---------------------------------------------------------------------------------------------------------------
+hipError_t launch_clip_fast(const ShapeArgs& a, int precision, int block, hipStream_t s) {
+  int nblocks = (a.nt + TB - 1) / TB;
+  if (nblocks == 0) return hipSuccess;
+  if (precision == RPD_FP64) {
+    hipLaunchKernelGGL((k_clip_fast<double, 64>), dim3(nblocks), dim3(64), 0, s, a);
+  } else if (block == 64) {
+    hipLaunchKernelGGL((k_clip_fast<float, 64>), dim3(nblocks), dim3(64), 0, s, a);
+  } else {
+    hipLaunchKernelGGL((k_clip_fast<float, 128>), dim3(nblocks), dim3(128), 0, s, a);
+  }
+  return hipGetLastError();
+}
+
+size_t slow_scratch_bytes(int threads) { return (size_t)threads * SlowScratch::bytes; }
+
+hipError_t launch_clip_slow(const ShapeArgs& a, unsigned char* scratch, int threads, hipStream_t s) {
+  int nb = (threads + 63) / 64;
+  hipLaunchKernelGGL(k_clip_slow, dim3(nb), dim3(64), 0, s, a, scratch);
+  return hipGetLastError();
+}
+
+}  // namespace rpd

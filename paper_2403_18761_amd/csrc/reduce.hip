@@ -1,0 +1,281 @@
+// Reductions after clipping: connected components by union-find over glued element pieces (paper Sec. 4.1.1),
+// integer Euler characteristics from the fractional sums (Sec. 4.1.2), compaction and sorting of the element lists,
+// site validation and small fills.
+#include <cstring>
+
+#include <hip/hip_runtime.h>
+#include <rocprim/device/device_radix_sort.hpp>
+
+#include "rpd_device.h"
+#include "rpd_launch.h"
+
+namespace rpd {
+
+__global__ void k_fill_u64(unsigned long long* p, unsigned long long v, size_t n) {
+  for (size_t k = blockIdx.x * (size_t)blockDim.x + threadIdx.x; k < n; k += (size_t)gridDim.x * blockDim.x) p[k] = v;
+}
+__global__ void k_fill_i32(int* p, int v, size_t n) {
+  for (size_t k = blockIdx.x * (size_t)blockDim.x + threadIdx.x; k < n; k += (size_t)gridDim.x * blockDim.x) p[k] = v;
+}
+
+static int grid_for(size_t n, int bs) {
+  size_t g = (n + bs - 1) / bs;
+  if (g > 65536) g = 65536;
+  return (int)(g ? g : 1);
+}
+
+hipError_t launch_fill_u64(unsigned long long* p, unsigned long long v, size_t n, hipStream_t s) {
+  if (!n) return hipSuccess;
+  hipLaunchKernelGGL(k_fill_u64, dim3(grid_for(n, 256)), dim3(256), 0, s, p, v, n);
+  return hipGetLastError();
+}
+hipError_t launch_fill_i32(int* p, int v, size_t n, hipStream_t s) {
+  if (!n) return hipSuccess;
+  hipLaunchKernelGGL(k_fill_i32, dim3(grid_for(n, 256)), dim3(256), 0, s, p, v, n);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------------------------------------------
+// union-find (lock-free: hook the larger root under the smaller with CAS; path halving)
+// ---------------------------------------------------------------------------------------------------------------
+__device__ inline int uf_find(int* par, int x) {
+  while (true) {
+    int p = par[x];
+    if (p == x) return x;
+    int gp = par[p];
+    if (gp != p) par[x] = gp;
+    x = p;
+  }
+}
+__device__ inline void uf_union(int* par, int a, int b) {
+  while (true) {
+    a = uf_find(par, a);
+    b = uf_find(par, b);
+    if (a == b) return;
+    if (a < b) {
+      int t = a;
+      a = b;
+      b = t;
+    }
+    int old = atomicCAS(&par[a], a, b);
+    if (old == a) return;
+  }
+}
+
+__global__ void k_parent_init(const unsigned long long* keys, int* parent, unsigned cap) {
+  for (unsigned s = blockIdx.x * blockDim.x + threadIdx.x; s < cap; s += gridDim.x * blockDim.x) parent[s] = (int)s;
+}
+
+// For every element piece with gluing bits: find the same element's piece in the face-adjacent tet, check that it
+// glues back across the same mesh face (both sides must agree), and unite them.
+__global__ void k_glue(ShapeArgs a, int* parent) {
+  const unsigned cap = a.N.mask + 1;
+  for (unsigned s = blockIdx.x * blockDim.x + threadIdx.x; s < cap; s += gridDim.x * blockDim.x) {
+    unsigned long long key = a.N.keys[s];
+    if (key == EMPTY_KEY) continue;
+    int g = a.node_glue[s];
+    if (!g) continue;
+    int t = (int)(key & 0xffffffffull);
+    unsigned long long hi = key & ~0xffffffffull;
+    for (int f = 0; f < 4; ++f) {
+      if (!(g & (1 << f))) continue;
+      int t2 = a.tn[4 * (size_t)t + f];
+      if (t2 < 0) continue;
+      int f2 = -1;
+      for (int q = 0; q < 4; ++q)
+        if (a.tn[4 * (size_t)t2 + q] == t) f2 = q;
+      int s2 = ht_find(a.N, hi | (unsigned)t2);
+      if (s2 < 0 || f2 < 0 || !(a.node_glue[s2] & (1 << f2))) {
+        atomicOr(a.status, ST_INTERNAL);
+        continue;
+      }
+      uf_union(parent, (int)s, s2);
+    }
+  }
+}
+
+__global__ void k_count_roots(ShapeArgs a, int* parent, int* cell_b0, int* face_b0, int* edge_b0) {
+  const unsigned cap = a.N.mask + 1;
+  unsigned long long nodes = 0;
+  for (unsigned s = blockIdx.x * blockDim.x + threadIdx.x; s < cap; s += gridDim.x * blockDim.x) {
+    unsigned long long key = a.N.keys[s];
+    if (key == EMPTY_KEY) continue;
+    ++nodes;
+    if (uf_find(parent, (int)s) != (int)s) continue;
+    int kind = (int)(key >> 62);
+    int elem = (int)((key >> 32) & 0x3fffffffull);
+    if (kind == 1) atomicAdd(&cell_b0[elem], 1);
+    else if (kind == 2) atomicAdd(&face_b0[elem], 1);
+    else atomicAdd(&edge_b0[elem], 1);
+  }
+  if (nodes) atomicAdd(&a.counters[C_NODES], nodes);
+}
+
+hipError_t launch_glue(const ShapeArgs& a, int* parent, hipStream_t s) {
+  size_t cap = (size_t)a.N.mask + 1;
+  hipLaunchKernelGGL(k_parent_init, dim3(grid_for(cap, 256)), dim3(256), 0, s, a.N.keys, parent, (unsigned)cap);
+  hipLaunchKernelGGL(k_glue, dim3(grid_for(cap, 256)), dim3(256), 0, s, a, parent);
+  return hipGetLastError();
+}
+
+hipError_t launch_count_roots(const ShapeArgs& a, int* parent, int* cell_b0, int* face_b0, int* edge_b0,
+                              hipStream_t s) {
+  size_t cap = (size_t)a.N.mask + 1;
+  hipLaunchKernelGGL(k_count_roots, dim3(grid_for(cap, 256)), dim3(256), 0, s, a, parent, cell_b0, face_b0, edge_b0);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------------------------------------------
+// element lists: sort the whole hash-table capacity by key (free slots hold the largest key and sort last), then
+// turn the fractional sums into integers
+// ---------------------------------------------------------------------------------------------------------------
+__global__ void k_iota(int* v, int n) {
+  for (int q = blockIdx.x * blockDim.x + threadIdx.x; q < n; q += gridDim.x * blockDim.x) v[q] = q;
+}
+hipError_t launch_iota(int* v, int n, hipStream_t s) {
+  hipLaunchKernelGGL(k_iota, dim3(grid_for(n, 256)), dim3(256), 0, s, v, n);
+  return hipGetLastError();
+}
+
+hipError_t sort_pairs_u64(void* tmp, size_t& tmp_bytes, const unsigned long long* kin, unsigned long long* kout,
+                          const int* vin, int* vout, int n, hipStream_t s) {
+  return rocprim::radix_sort_pairs(tmp, tmp_bytes, kin, kout, vin, vout, (size_t)n, 0, 64, s);
+}
+
+__global__ void k_finalize_faces(const unsigned long long* keys, const int* slots, int cap, const long long* chi_num,
+                                 const int* b0, long long L, int* out_keys, int* out_chi, int* out_b0, int* status,
+                                 unsigned long long* count) {
+  for (int q = blockIdx.x * blockDim.x + threadIdx.x; q < cap; q += gridDim.x * blockDim.x) {
+    unsigned long long k = keys[q];
+    if (k == EMPTY_KEY) continue;
+    int s = slots[q];
+    out_keys[2 * q] = (int)(k >> 32);
+    out_keys[2 * q + 1] = (int)(k & 0xffffffffull);
+    long long c = chi_num[s];
+    if (c % L != 0) atomicOr(status, ST_INTERNAL);
+    out_chi[q] = (int)(c / L);
+    out_b0[q] = b0[s];
+    atomicAdd(count, 1ull);
+  }
+}
+__global__ void k_finalize_edges(const unsigned long long* keys, const int* slots, int cap, const long long* chi_num,
+                                 const int* b0, long long L, int* out_keys, int* out_chi, int* out_b0, int* status,
+                                 unsigned long long* count) {
+  for (int q = blockIdx.x * blockDim.x + threadIdx.x; q < cap; q += gridDim.x * blockDim.x) {
+    unsigned long long k = keys[q];
+    if (k == EMPTY_KEY) continue;
+    int s = slots[q];
+    out_keys[3 * q] = (int)(k >> 42);
+    out_keys[3 * q + 1] = (int)((k >> 21) & 0x1fffff);
+    out_keys[3 * q + 2] = (int)(k & 0x1fffff);
+    long long c = chi_num[s];
+    if (c % L != 0) atomicOr(status, ST_INTERNAL);
+    out_chi[q] = (int)(c / L);
+    out_b0[q] = b0[s];
+    atomicAdd(count, 1ull);
+  }
+}
+__global__ void k_finalize_cells(int ns, const long long* chi_num, const long long* geo, const int* np, long long L,
+                                 int* out_chi, double* out_vol, double* out_cen, int* status) {
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < ns; i += gridDim.x * blockDim.x) {
+    long long c = chi_num[i];
+    if (c % L != 0) atomicOr(status, ST_INTERNAL);
+    out_chi[i] = (int)(c / L);
+    const double sc = 1.0 / 72057594037927936.0;  // 2^-56
+    double v = (double)geo[4 * (size_t)i] * sc;
+    out_vol[i] = v;
+    for (int d = 0; d < 3; ++d) out_cen[3 * (size_t)i + d] = np[i] ? ((double)geo[4 * (size_t)i + 1 + d] * sc) / v : NAN;
+  }
+}
+
+hipError_t launch_finalize_faces(const unsigned long long* keys, const int* slots, int cap, const long long* chi_num,
+                                 const int* b0, long long L, int* out_keys, int* out_chi, int* out_b0, int* status,
+                                 unsigned long long* count, hipStream_t s) {
+  hipLaunchKernelGGL(k_finalize_faces, dim3(grid_for(cap, 256)), dim3(256), 0, s, keys, slots, cap, chi_num, b0, L,
+                     out_keys, out_chi, out_b0, status, count);
+  return hipGetLastError();
+}
+hipError_t launch_finalize_edges(const unsigned long long* keys, const int* slots, int cap, const long long* chi_num,
+                                 const int* b0, long long L, int* out_keys, int* out_chi, int* out_b0, int* status,
+                                 unsigned long long* count, hipStream_t s) {
+  hipLaunchKernelGGL(k_finalize_edges, dim3(grid_for(cap, 256)), dim3(256), 0, s, keys, slots, cap, chi_num, b0, L,
+                     out_keys, out_chi, out_b0, status, count);
+  return hipGetLastError();
+}
+hipError_t launch_finalize_cells(int ns, const long long* chi_num, const long long* geo, const int* np, long long L,
+                                 int* out_chi, double* out_vol, double* out_cen, int* status, hipStream_t s) {
+  hipLaunchKernelGGL(k_finalize_cells, dim3(grid_for(ns, 256)), dim3(256), 0, s, ns, chi_num, geo, np, L, out_chi,
+                     out_vol, out_cen, status);
+  return hipGetLastError();
+}
+
+// RPV quadruples: two stable radix passes (by (k, l), then by (i, j)) over the whole buffer; unused entries hold
+// INT_MAX ids and sort last
+__global__ void k_rpv_keys(const int4* rpv, int n, unsigned long long* k_hi, unsigned long long* k_lo, int* idx) {
+  for (int q = blockIdx.x * blockDim.x + threadIdx.x; q < n; q += gridDim.x * blockDim.x) {
+    int4 r = rpv[q];
+    k_hi[q] = ((unsigned long long)(unsigned)r.x << 32) | (unsigned)r.y;
+    k_lo[q] = ((unsigned long long)(unsigned)r.z << 32) | (unsigned)r.w;
+    idx[q] = q;
+  }
+}
+__global__ void k_gather_u64(const unsigned long long* src, const int* idx, unsigned long long* dst, int n) {
+  for (int q = blockIdx.x * blockDim.x + threadIdx.x; q < n; q += gridDim.x * blockDim.x) dst[q] = src[idx[q]];
+}
+__global__ void k_gather_rpv(const int4* src, const int* idx, int4* dst, int n) {
+  for (int q = blockIdx.x * blockDim.x + threadIdx.x; q < n; q += gridDim.x * blockDim.x) dst[q] = src[idx[q]];
+}
+__global__ void k_fill_rpv(int4* p, int n) {
+  for (int q = blockIdx.x * blockDim.x + threadIdx.x; q < n; q += gridDim.x * blockDim.x)
+    p[q] = make_int4(0x7fffffff, 0x7fffffff, 0x7fffffff, 0x7fffffff);
+}
+hipError_t launch_fill_rpv(int4* p, int n, hipStream_t s) {
+  hipLaunchKernelGGL(k_fill_rpv, dim3(grid_for(n, 256)), dim3(256), 0, s, p, n);
+  return hipGetLastError();
+}
+
+// buffers: ka, kb, kc of n u64 each; va, vb of n ints
+hipError_t launch_sort_rpv(const int4* rpv, int n, unsigned long long* ka, unsigned long long* kb,
+                           unsigned long long* kc, int* va, int* vb, void* tmp, size_t tmp_bytes, int4* out,
+                           hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_rpv_keys, dim3(grid_for(n, 256)), dim3(256), 0, s, rpv, n, ka, kb, va);
+  hipError_t e = rocprim::radix_sort_pairs(tmp, tmp_bytes, kb, kc, va, vb, (size_t)n, 0, 64, s);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_gather_u64, dim3(grid_for(n, 256)), dim3(256), 0, s, ka, vb, kb, n);
+  e = rocprim::radix_sort_pairs(tmp, tmp_bytes, kb, kc, vb, va, (size_t)n, 0, 64, s);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_gather_rpv, dim3(grid_for(n, 256)), dim3(256), 0, s, rpv, va, out, n);
+  return hipGetLastError();
+}
+size_t sort_tmp_bytes(int n) {
+  size_t b = 0;
+  (void)rocprim::radix_sort_pairs(nullptr, b, (unsigned long long*)nullptr, (unsigned long long*)nullptr,
+                                  (int*)nullptr, (int*)nullptr, (size_t)n, 0, 64, (hipStream_t)0);
+  return b;
+}
+
+// ---------------------------------------------------------------------------------------------------------------
+// site validation: finite, on the 2^-20 grid, |centre| <= 1, 0 <= r <= 2; packs (x, y, z, r)
+// ---------------------------------------------------------------------------------------------------------------
+__device__ inline bool on_grid(float v, float lim) {
+  if (!(fabsf(v) <= lim)) return false;
+  float s = v * 1048576.0f;
+  return s == rintf(s);
+}
+__global__ void k_validate_sites(const float* sx, const float* sy, const float* sz, const float* sr, int ns,
+                                 float4* site, int* status) {
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < ns; i += gridDim.x * blockDim.x) {
+    float x = sx[i], y = sy[i], z = sz[i], r = sr[i];
+    if (!on_grid(x, 1.0f) || !on_grid(y, 1.0f) || !on_grid(z, 1.0f) || !on_grid(r, 2.0f) || r < 0.0f)
+      atomicOr(status, ST_INVALID);
+    site[i] = make_float4(x, y, z, r);
+  }
+}
+hipError_t launch_validate_sites(const float* sx, const float* sy, const float* sz, const float* sr, int ns,
+                                 float4* site, int* status, hipStream_t s) {
+  hipLaunchKernelGGL(k_validate_sites, dim3(grid_for(ns, 256)), dim3(256), 0, s, sx, sy, sz, sr, ns, site, status);
+  return hipGetLastError();
+}
+
+}  // namespace rpd

@@ -1,0 +1,246 @@
+"""Thin ctypes binding of librpd (include/rpd.h): argument marshalling only; every step runs in the library.
+
+Inputs may be numpy arrays (host) or torch tensors on a HIP device (passed as device pointers with
+RPD_DEVICE_PTRS). The library must have been built (``paper_2403_18761_amd/build.py``); there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "librpd.so")
+
+RPD_OK = 0
+ERRORS = {-1: "RPD_E_INVALID", -2: "RPD_E_MESH", -3: "RPD_E_DEGENERATE", -4: "RPD_E_NOMEM", -5: "RPD_E_DEVICE",
+          -6: "RPD_E_INTERNAL"}
+RPD_FP32_FALLBACK = 0
+RPD_FP64 = 1
+RPD_CELL, RPD_FACE, RPD_EDGE, RPD_VERTEX = 1, 2, 3, 4
+RPD_DEVICE_PTRS = 1 << 0
+RPD_FORCE_FP64 = 1 << 1
+RPD_FORCE_EXACT = 1 << 2
+RPD_FORCE_SLOW_PATH = 1 << 3
+RPD_TIMING = 1 << 4
+RPD_KEEP_PIECES = 1 << 5
+
+_f32p = C.POINTER(C.c_float)
+_i32p = C.POINTER(C.c_int32)
+
+
+class _MeshDesc(C.Structure):
+    _fields_ = [("n_verts", C.c_int32), ("vx", _f32p), ("vy", _f32p), ("vz", _f32p), ("n_tets", C.c_int32),
+                ("tv", _i32p)]
+
+
+class _MeshInfo(C.Structure):
+    _fields_ = [("n_verts", C.c_int32), ("n_tets", C.c_int32), ("n_edges", C.c_int32), ("n_faces", C.c_int32),
+                ("euler", C.c_int32), ("components", C.c_int32), ("L", C.c_int64), ("volume", C.c_double)]
+
+
+class _Sites(C.Structure):
+    _fields_ = [("n_sites", C.c_int32), ("sx", _f32p), ("sy", _f32p), ("sz", _f32p), ("sr", _f32p)]
+
+
+class _Opts(C.Structure):
+    _fields_ = [("precision", C.c_int32), ("clip_budget", C.c_int32), ("block", C.c_int32), ("flags", C.c_uint32),
+                ("stream", C.c_void_p)]
+
+
+class _Stats(C.Structure):
+    _fields_ = [("n_pairs", C.c_int64), ("n_candidates", C.c_int64), ("n_deferred", C.c_int64),
+                ("n_fp64", C.c_int64), ("n_exact", C.c_int64), ("n_cells", C.c_int64), ("n_faces", C.c_int64),
+                ("n_edges", C.c_int64), ("n_rpv", C.c_int64), ("n_glue", C.c_int64), ("ms_clip", C.c_double),
+                ("ms_deferred", C.c_double), ("ms_reduce", C.c_double), ("ms_total", C.c_double)]
+
+
+class RPDError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"{ERRORS.get(code, code)}: {msg}")
+        self.code = code
+
+
+_lib = None
+
+
+def load():
+    """Load librpd.so; raise if it has not been built (the product has no CPU path)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is missing: build it with paper_2403_18761_amd/build.py")
+    lib = C.CDLL(LIB_PATH)
+    lib.rpd_mesh_create.argtypes = [C.POINTER(_MeshDesc), C.c_uint32, C.c_void_p, C.POINTER(C.c_void_p)]
+    lib.rpd_mesh_get_info.argtypes = [C.c_void_p, C.POINTER(_MeshInfo)]
+    lib.rpd_mesh_free.argtypes = [C.c_void_p]
+    lib.rpd_mesh_free.restype = None
+    lib.rpd_build.argtypes = [C.POINTER(C.c_void_p), C.POINTER(_Sites), C.c_int32, C.POINTER(_Opts),
+                              C.POINTER(C.c_void_p)]
+    lib.rpd_euler.argtypes = [C.c_void_p, C.c_int32, C.c_int32, C.POINTER(C.c_int64), C.POINTER(_i32p),
+                              C.POINTER(_i32p)]
+    lib.rpd_components.argtypes = lib.rpd_euler.argtypes
+    lib.rpd_geometry.argtypes = [C.c_void_p, C.c_int32, C.POINTER(C.POINTER(C.c_double)),
+                                 C.POINTER(C.POINTER(C.c_double))]
+    lib.rpd_adjacency.argtypes = [C.c_void_p, C.c_int32, C.c_int32, C.POINTER(C.c_int64), C.POINTER(_i32p)]
+    lib.rpd_get_stats.argtypes = [C.c_void_p, C.POINTER(_Stats)]
+    lib.rpd_pieces.argtypes = [C.c_void_p, C.c_int32, C.POINTER(C.c_int64), C.POINTER(_i32p), C.POINTER(_i32p),
+                               C.POINTER(C.POINTER(C.c_double)), C.POINTER(C.POINTER(C.c_int64))]
+    lib.rpd_free.argtypes = [C.c_void_p]
+    lib.rpd_free.restype = None
+    lib.rpd_last_error.restype = C.c_char_p
+    lib.rpd_version.restype = C.c_char_p
+    for f in ("rpd_mesh_create", "rpd_mesh_get_info", "rpd_build", "rpd_euler", "rpd_components", "rpd_geometry",
+              "rpd_adjacency", "rpd_get_stats", "rpd_pieces"):
+        getattr(lib, f).restype = C.c_int32
+    _lib = lib
+    return lib
+
+
+def _check(code: int):
+    if code != RPD_OK:
+        raise RPDError(code, load().rpd_last_error().decode())
+
+
+def _is_torch(x) -> bool:
+    return type(x).__module__.startswith("torch")
+
+
+def _ptr(x, ctype, keep: list):
+    """Pointer to the data of a numpy array (host) or a contiguous torch tensor (device)."""
+    if _is_torch(x):
+        if not x.is_contiguous():
+            raise ValueError("tensors must be contiguous")
+        return C.cast(C.c_void_p(x.data_ptr()), C.POINTER(ctype))
+    a = np.ascontiguousarray(x, dtype={C.c_float: np.float32, C.c_int32: np.int32}[ctype])
+    keep.append(a)
+    return a.ctypes.data_as(C.POINTER(ctype))
+
+
+def _stream_ptr(stream) -> int | None:
+    if stream is None:
+        return None
+    if isinstance(stream, int):
+        return stream
+    return int(stream.cuda_stream)  # torch.cuda.Stream
+
+
+class Mesh:
+    """A prepared tet mesh (rpd_mesh_create)."""
+
+    def __init__(self, vx, vy, vz, tv, stream=None):
+        lib = load()
+        keep = []
+        dev = _is_torch(vx) and vx.is_cuda
+        tv_flat = tv.reshape(-1) if hasattr(tv, "reshape") else tv
+        d = _MeshDesc(int(vx.shape[0]), _ptr(vx, C.c_float, keep), _ptr(vy, C.c_float, keep),
+                      _ptr(vz, C.c_float, keep), int(tv_flat.shape[0]) // 4, _ptr(tv_flat, C.c_int32, keep))
+        h = C.c_void_p()
+        _check(lib.rpd_mesh_create(C.byref(d), RPD_DEVICE_PTRS if dev else 0, _stream_ptr(stream), C.byref(h)))
+        self._h = h
+        self._lib = lib
+
+    @property
+    def handle(self):
+        return self._h
+
+    def info(self) -> dict:
+        i = _MeshInfo()
+        _check(self._lib.rpd_mesh_get_info(self._h, C.byref(i)))
+        return {k: getattr(i, k) for k, _ in _MeshInfo._fields_}
+
+    def __del__(self):
+        if getattr(self, "_h", None) and self._h.value:
+            self._lib.rpd_mesh_free(self._h)
+            self._h = C.c_void_p()
+
+
+class Result:
+    """Host-visible results of one rpd_build call."""
+
+    def __init__(self, h, n_shapes):
+        self._h = h
+        self._lib = load()
+        self.n_shapes = n_shapes
+
+    def _elem(self, fn, shape, kind):
+        n = C.c_int64()
+        keys, vals = _i32p(), _i32p()
+        _check(fn(self._h, shape, kind, C.byref(n), C.byref(keys), C.byref(vals)))
+        width = {RPD_CELL: 1, RPD_FACE: 2, RPD_EDGE: 3}[kind]
+        k = np.ctypeslib.as_array(keys, shape=(n.value * width,)).copy() if n.value else np.zeros(0, np.int32)
+        v = np.ctypeslib.as_array(vals, shape=(n.value,)).copy() if n.value else np.zeros(0, np.int32)
+        return k.reshape(-1, width) if kind != RPD_CELL else k, v
+
+    def euler(self, shape: int, kind: int):
+        """(keys, chi) for kind RPD_CELL / RPD_FACE / RPD_EDGE."""
+        return self._elem(self._lib.rpd_euler, shape, kind)
+
+    def components(self, shape: int, kind: int):
+        """(keys, beta0) for kind RPD_CELL / RPD_FACE / RPD_EDGE."""
+        return self._elem(self._lib.rpd_components, shape, kind)
+
+    def geometry(self, shape: int):
+        vol, cen = C.POINTER(C.c_double)(), C.POINTER(C.c_double)()
+        _check(self._lib.rpd_geometry(self._h, shape, C.byref(vol), C.byref(cen)))
+        n = self.euler(shape, RPD_CELL)[1].shape[0]
+        return (np.ctypeslib.as_array(vol, shape=(n,)).copy(),
+                np.ctypeslib.as_array(cen, shape=(3 * n,)).copy().reshape(n, 3))
+
+    def adjacency(self, shape: int, kind: int):
+        n = C.c_int64()
+        keys = _i32p()
+        _check(self._lib.rpd_adjacency(self._h, shape, kind, C.byref(n), C.byref(keys)))
+        width = {RPD_FACE: 2, RPD_EDGE: 3, RPD_VERTEX: 4}[kind]
+        if n.value == 0:
+            return np.zeros((0, width), np.int32)
+        return np.ctypeslib.as_array(keys, shape=(n.value * width,)).copy().reshape(-1, width)
+
+    def stats(self) -> dict:
+        s = _Stats()
+        _check(self._lib.rpd_get_stats(self._h, C.byref(s)))
+        return {k: getattr(s, k) for k, _ in _Stats._fields_}
+
+    def pieces(self, shape: int) -> dict:
+        n = C.c_int64()
+        t, i = _i32p(), _i32p()
+        geo = C.POINTER(C.c_double)()
+        chi = C.POINTER(C.c_int64)()
+        _check(self._lib.rpd_pieces(self._h, shape, C.byref(n), C.byref(t), C.byref(i), C.byref(geo), C.byref(chi)))
+        m = n.value
+        if m == 0:
+            return dict(t=np.zeros(0, np.int32), i=np.zeros(0, np.int32), geo=np.zeros((0, 4)),
+                        chi=np.zeros(0, np.int64))
+        return dict(t=np.ctypeslib.as_array(t, shape=(m,)).copy(), i=np.ctypeslib.as_array(i, shape=(m,)).copy(),
+                    geo=np.ctypeslib.as_array(geo, shape=(4 * m,)).copy().reshape(m, 4),
+                    chi=np.ctypeslib.as_array(chi, shape=(m,)).copy())
+
+    def __del__(self):
+        if getattr(self, "_h", None) and self._h.value:
+            self._lib.rpd_free(self._h)
+            self._h = C.c_void_p()
+
+
+def build(meshes, sites, precision: int = RPD_FP32_FALLBACK, clip_budget: int = 0, block: int = 0,
+          flags: int = 0, stream=None) -> Result:
+    """rpd_build over shapes: ``meshes`` a list of Mesh, ``sites`` a list of (sx, sy, sz, sr) arrays or tensors."""
+    lib = load()
+    n = len(meshes)
+    keep = []
+    handles = (C.c_void_p * n)(*[m.handle.value for m in meshes])
+    st = (_Sites * n)()
+    dev = False
+    for k, (sx, sy, sz, sr) in enumerate(sites):
+        dev = dev or (_is_torch(sx) and sx.is_cuda)
+        st[k] = _Sites(int(sx.shape[0]), _ptr(sx, C.c_float, keep), _ptr(sy, C.c_float, keep),
+                       _ptr(sz, C.c_float, keep), _ptr(sr, C.c_float, keep))
+    o = _Opts(precision, clip_budget, block, flags | (RPD_DEVICE_PTRS if dev else 0), _stream_ptr(stream))
+    h = C.c_void_p()
+    _check(lib.rpd_build(handles, st, n, C.byref(o), C.byref(h)))
+    return Result(h, n)
+
+
+def version() -> str:
+    return load().rpd_version().decode()

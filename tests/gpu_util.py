@@ -1,0 +1,65 @@
+"""Helpers for the GPU tests: run the HIP path through the C ABI and compare with the oracle."""
+import sys
+
+import numpy as np
+
+
+def run_gpu(prob, precision=0, clip_budget=0, block=0, flags=0, device_ptrs=True):
+    import torch
+
+    from paper_2403_18761_amd import rpd
+
+    if device_ptrs:
+        dev = torch.device("cuda:0")
+
+        def t(a, dt=torch.float32):
+            return torch.as_tensor(np.ascontiguousarray(a), dtype=dt, device=dev)
+
+        mesh = rpd.Mesh(t(prob.vx), t(prob.vy), t(prob.vz), t(prob.tv.reshape(-1), torch.int32))
+        sites = (t(prob.sx), t(prob.sy), t(prob.sz), t(prob.sr))
+    else:
+        mesh = rpd.Mesh(prob.vx, prob.vy, prob.vz, prob.tv.reshape(-1))
+        sites = (prob.sx, prob.sy, prob.sz, prob.sr)
+    res = rpd.build([mesh], [sites], precision=precision, clip_budget=clip_budget, block=block, flags=flags)
+    out = {}
+    _, out["cell_chi"] = res.euler(0, rpd.RPD_CELL)
+    _, out["cell_beta0"] = res.components(0, rpd.RPD_CELL)
+    out["face_keys"], out["face_chi"] = res.euler(0, rpd.RPD_FACE)
+    _, out["face_beta0"] = res.components(0, rpd.RPD_FACE)
+    out["edge_keys"], out["edge_chi"] = res.euler(0, rpd.RPD_EDGE)
+    _, out["edge_beta0"] = res.components(0, rpd.RPD_EDGE)
+    out["rpv_keys"] = res.adjacency(0, rpd.RPD_VERTEX)
+    out["cell_vol"], out["cell_cen"] = res.geometry(0)
+    out["stats"] = res.stats()
+    out["mesh_info"] = mesh.info()
+    if flags & rpd.RPD_KEEP_PIECES:
+        out["pieces"] = res.pieces(0)
+    return out
+
+
+def assert_parity(g, r, vol_rtol=1e-5, label=""):
+    """Bit-exact chi / beta0 / adjacency; volumes and centroids within FP32 tolerance."""
+    np.testing.assert_array_equal(g["cell_chi"], r["cell_chi"], err_msg=f"{label} cell chi")
+    np.testing.assert_array_equal(g["cell_beta0"], r["cell_beta0"], err_msg=f"{label} cell beta0")
+    np.testing.assert_array_equal(g["face_keys"], r["face_keys"], err_msg=f"{label} face keys")
+    np.testing.assert_array_equal(g["face_chi"], r["face_chi"], err_msg=f"{label} face chi")
+    np.testing.assert_array_equal(g["face_beta0"], r["face_beta0"], err_msg=f"{label} face beta0")
+    np.testing.assert_array_equal(g["edge_keys"], r["edge_keys"], err_msg=f"{label} edge keys")
+    np.testing.assert_array_equal(g["edge_chi"], r["edge_chi"], err_msg=f"{label} edge chi")
+    np.testing.assert_array_equal(g["edge_beta0"], r["edge_beta0"], err_msg=f"{label} edge beta0")
+    np.testing.assert_array_equal(g["rpv_keys"], r["rpv_keys"], err_msg=f"{label} rpv keys")
+    assert g["stats"]["n_pairs"] == r["n_pairs"], (label, g["stats"]["n_pairs"], r["n_pairs"])
+    vr = r["cell_vol"]
+    np.testing.assert_allclose(g["cell_vol"], vr, rtol=vol_rtol, atol=vol_rtol * 1e-6 * max(vr.max(), 1e-30),
+                               err_msg=f"{label} volumes")
+    ne = vr > 0
+    np.testing.assert_array_equal(np.isnan(g["cell_cen"][:, 0]), ~ne, err_msg=f"{label} empty cells")
+    # centroid error relative to the cell's size (cube root of its volume)
+    scale = np.cbrt(vr[ne])[:, None]
+    err = np.abs(g["cell_cen"][ne] - r["cell_cen"][ne]) / scale
+    assert err.max(initial=0.0) < 10 * vol_rtol, (label, err.max())
+
+
+def log(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()

@@ -1,0 +1,135 @@
+"""Parity of the HIP path (through the C ABI) with the CPU oracle, on the same seeded inputs.
+
+Bar: chi, beta0, face/edge/RPV adjacency and the number of nonempty pieces bit-exact; cell volumes within 1e-5
+relative (FP32 constructions) of the oracle's FP64 values.
+"""
+import numpy as np
+import pytest
+
+from paper_2403_18761_amd import synth
+from tests.gpu_util import assert_parity, log, run_gpu
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    import torch
+
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import oracle
+
+    oracle.build(force=False)
+
+
+def _oracle(prob, assemble=True):
+    import oracle
+
+    return oracle.rpd(prob, assemble=assemble)
+
+
+def test_small_torus_fp32():
+    prob = synth.torus_core(16, 64, 1)
+    log("case: torus_core N16 n64 fp32")
+    r = _oracle(prob)
+    g = run_gpu(prob)
+    assert g["mesh_info"]["euler"] == r["mesh_chi"] == 0
+    assert g["mesh_info"]["L"] == r["L"]
+    assert_parity(g, r, label="torus16")
+
+
+def test_small_torus_fp64():
+    prob = synth.torus_core(16, 64, 1)
+    log("case: torus_core N16 n64 fp64")
+    r = _oracle(prob)
+    g = run_gpu(prob, precision=1)
+    assert_parity(g, r, vol_rtol=1e-9, label="torus16 fp64")
+
+
+@pytest.mark.parametrize("flag", ["force_fp64", "force_exact", "force_slow", "budget4", "host_ptrs"])
+def test_forced_paths_identical(flag):
+    from paper_2403_18761_amd import rpd
+
+    prob = synth.torus_core(16, 64, 1)
+    log("case: forced path", flag)
+    r = _oracle(prob)
+    kw = dict(force_fp64=dict(flags=rpd.RPD_FORCE_FP64), force_exact=dict(flags=rpd.RPD_FORCE_EXACT),
+              force_slow=dict(flags=rpd.RPD_FORCE_SLOW_PATH), budget4=dict(clip_budget=4),
+              host_ptrs=dict(device_ptrs=False))[flag]
+    g = run_gpu(prob, **kw)
+    assert_parity(g, r, label=flag)
+    if flag == "force_exact":
+        assert g["stats"]["n_exact"] > 0
+    if flag == "force_slow":
+        assert g["stats"]["n_deferred"] == prob.n_tets
+    if flag == "budget4":
+        assert g["stats"]["n_deferred"] > 0
+
+
+@pytest.mark.parametrize("N,n,seed", [(32, 300, 7), (32, 1000, 8)])
+def test_torus_inside_mid(N, n, seed):
+    prob = synth.torus_inside(N, n, seed)
+    log(f"case: torus_inside N{N} n{n} s{seed} tets {prob.n_tets}")
+    r = _oracle(prob, assemble=False)
+    g = run_gpu(prob)
+    assert_parity(g, r, label=f"torus{N}")
+
+
+@pytest.mark.parametrize("seed,weights", [(0, True), (2, False)])
+def test_convex_cube(seed, weights):
+    prob = synth.cube_random(N=8, n_sites=200, seed=seed, weights=weights)
+    log(f"case: cube N8 n200 s{seed}")
+    r = _oracle(prob)
+    g = run_gpu(prob)
+    assert_parity(g, r, label="cube")
+    ne = g["cell_vol"] > 0
+    assert np.all(g["cell_chi"][ne] == 1) and np.all(g["face_chi"] == 1) and np.all(g["edge_chi"] == 1)
+
+
+def test_genus3_small():
+    prob = synth.genus3_cad(N=32, n_sites=400, seed=12)
+    log(f"case: genus3 N32 n400 tets {prob.n_tets}")
+    r = _oracle(prob, assemble=False)
+    g = run_gpu(prob)
+    assert g["mesh_info"]["euler"] == -2
+    assert_parity(g, r, label="genus3")
+
+
+def test_deterministic_bits():
+    prob = synth.torus_inside(32, 500, 9)
+    log("case: determinism")
+    a = run_gpu(prob)
+    b = run_gpu(prob)
+    for k in ("cell_chi", "cell_beta0", "face_keys", "face_chi", "edge_keys", "edge_chi", "rpv_keys", "cell_vol"):
+        np.testing.assert_array_equal(a[k], b[k])
+
+
+def test_single_site_is_the_solid():
+    base = synth.torus_core(16, 64, 1)
+    c = synth.quantize([[0.013, -0.021, 0.007]])
+    prob = base.with_sites(c[:, 0], c[:, 1], c[:, 2], synth.quantize([0.05]))
+    log("case: single site")
+    g = run_gpu(prob)
+    assert g["cell_chi"].tolist() == [0] and g["cell_beta0"].tolist() == [1]
+    assert abs(g["cell_vol"][0] - g["mesh_info"]["volume"]) < 1e-6 * g["mesh_info"]["volume"]
+
+
+def test_errors_reported():
+    from paper_2403_18761_amd import rpd
+
+    base = synth.cube_random(N=2, n_sites=2, seed=0)
+    log("case: errors")
+    c = synth.quantize([[-0.25, 0.1, 0.1], [0.25, 0.1, 0.1]])
+    with pytest.raises(rpd.RPDError) as e:
+        run_gpu(base.with_sites(c[:, 0], c[:, 1], c[:, 2], np.zeros(2)))
+    assert e.value.code == -3
+    bad = base.with_sites(np.array([0.1, 0.3], np.float32), base.sy, base.sz, base.sr)
+    with pytest.raises(rpd.RPDError) as e:
+        run_gpu(bad)
+    assert e.value.code == -1
+    tv = base.tv.copy()
+    tv[0, [2, 3]] = tv[0, [3, 2]]
+    with pytest.raises(rpd.RPDError) as e:
+        run_gpu(synth.Problem(base.vx, base.vy, base.vz, tv, base.sx, base.sy, base.sz, base.sr, {}))
+    assert e.value.code == -1

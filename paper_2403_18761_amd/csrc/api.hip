@@ -5,6 +5,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <map>
 #include <mutex>
 #include <numeric>
 #include <string>
@@ -18,6 +19,49 @@ namespace rpd {
 
 static thread_local std::string g_error;
 void set_error(const std::string& msg) { g_error = msg; }
+
+// ---- caching allocator
+static std::mutex g_pool_mu;
+static std::map<std::pair<int, size_t>, std::vector<void*>> g_pool;
+
+void* pool_alloc(size_t bytes, size_t* cls_bytes) {
+  size_t c = 256;
+  while (c < bytes) c <<= 1;
+  int dev = 0;
+  (void)hipGetDevice(&dev);
+  {
+    std::lock_guard<std::mutex> g(g_pool_mu);
+    auto& v = g_pool[{dev, c}];
+    if (!v.empty()) {
+      void* p = v.back();
+      v.pop_back();
+      *cls_bytes = c;
+      return p;
+    }
+  }
+  void* p = nullptr;
+  hipError_t e = hipMalloc(&p, c);
+  if (e == hipErrorOutOfMemory) {  // give cached blocks back to the runtime and try once more
+    (void)hipGetLastError();
+    {
+      std::lock_guard<std::mutex> g(g_pool_mu);
+      for (auto& kv : g_pool)
+        for (void* q : kv.second) (void)hipFree(q);
+      g_pool.clear();
+    }
+    e = hipMalloc(&p, c);
+  }
+  hip_check(e, "hipMalloc");
+  *cls_bytes = c;
+  return p;
+}
+
+void pool_free(void* p, size_t cls_bytes) {
+  int dev = 0;
+  (void)hipGetDevice(&dev);
+  std::lock_guard<std::mutex> g(g_pool_mu);
+  g_pool[{dev, cls_bytes}].push_back(p);
+}
 
 static unsigned pow2_cap(size_t n) {
   size_t c = 1024;
@@ -141,6 +185,8 @@ static bool run_shape(const rpd_mesh* m, const rpd_sites* sp, const rpd_opts& o,
   ShapeArgs a;
   std::memset(&a, 0, sizeof(a));
   a.nt = nt;
+  a.blk = m->blk.as<int>();
+  a.nblk = m->nblk;
   a.tp = m->tp.as<float4>();
   a.tn = m->tn.as<int>();
   a.nu = m->nu.as<unsigned>();

@@ -257,6 +257,56 @@ __device__ inline float wave_maxf(float v) {
   return v;
 }
 
+// g_j at the four tet vertices (tet-local frame, exact in FP64)
+__device__ inline void g4(const float4* tv, const float4& s, double* g) {
+  const float4 o = tv[0];
+  double ax = (double)s.x - o.x, ay = (double)s.y - o.y, az = (double)s.z - o.z;
+  double D = ax * ax + ay * ay + az * az - (double)s.w * s.w;
+  g[0] = D;
+  for (int v = 1; v < 4; ++v)
+    g[v] = D - 2.0 * (((double)tv[v].x - o.x) * ax + ((double)tv[v].y - o.y) * ay + ((double)tv[v].z - o.z) * az);
+}
+
+// Remove candidates dominated on the whole tet by one of the first three candidates (exact test: g_j - g_i is
+// affine, so being larger at the four vertices means larger everywhere on the tet and j owns no point of it).
+// The list must be sorted (only_count: the list is unsorted and over budget; it is filtered but stays unsorted).
+__device__ int refine_candidates(const float4* tv, const float4* sites, const int* sid, unsigned char* cand,
+                                 double* key, int m, bool unsorted) {
+  const int R = min(m, 3);
+  double gr[3][4];
+  int ref[3];
+  if (unsorted) {  // pick the three smallest keys as references
+    int best[3] = {-1, -1, -1};
+    for (int c = 0; c < m; ++c)
+      for (int r = 0; r < 3; ++r)
+        if (best[r] < 0 || key[c] < key[best[r]]) {
+          for (int q = 2; q > r; --q) best[q] = best[q - 1];
+          best[r] = c;
+          break;
+        }
+    for (int r = 0; r < R; ++r) ref[r] = best[r];
+  } else {
+    for (int r = 0; r < R; ++r) ref[r] = r;
+  }
+  for (int r = 0; r < R; ++r) g4(tv, sites[cand[ref[r]]], gr[r]);
+  int w = 0;
+  for (int c = 0; c < m; ++c) {
+    double g[4];
+    g4(tv, sites[cand[c]], g);
+    bool dom = false;
+    for (int r = 0; r < R && !dom; ++r) {
+      if (ref[r] == c) continue;
+      dom = g[0] > gr[r][0] && g[1] > gr[r][1] && g[2] > gr[r][2] && g[3] > gr[r][3];
+    }
+    if (!dom) {
+      cand[w] = cand[c];
+      key[w] = key[c];
+      ++w;
+    }
+  }
+  return w;
+}
+
 template <typename T, int NT>
 __global__ __launch_bounds__(NT) void k_clip_fast(ShapeArgs a) {
   static_assert(NT % TB == 0 && NT >= TB, "threads per block must be a multiple of the tets per block");
@@ -279,8 +329,8 @@ __global__ __launch_bounds__(NT) void k_clip_fast(ShapeArgs a) {
 
   const int tid = threadIdx.x;
   const int lane = tid & 63, wid = tid >> 6;
-  const int t0 = blockIdx.x * TB;
-  const int ntb = min(TB, a.nt - t0);
+  const int t0 = a.blk[blockIdx.x];
+  const int ntb = a.blk[blockIdx.x + 1] - t0;
 
   // ---- 1. load the tets, their face planes and the bounding box
   float lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
@@ -391,9 +441,13 @@ __global__ __launch_bounds__(NT) void k_clip_fast(ShapeArgs a) {
     }
   }
   __syncthreads();
-  // sort each tet's candidates by (power distance at the centroid, site id); mark overflowing tets
+  // sort each tet's candidates by (power distance at the centroid, site id), drop the ones that one of the three
+  // nearest candidates dominates at all four tet vertices (g affine: then everywhere on the tet), and mark the
+  // overflowing tets
   if (tid < ntb) {
     int m = s_m[tid];
+    if (!block_overflow && m > a.kmax && m <= KMAX) m = refine_candidates(s_tv[tid], s_site, s_sid, s_cand[tid],
+                                                                         s_key[tid], m, true);
     if (block_overflow || m > a.kmax) {
       s_m[tid] = -1;
       unsigned long long idx = atomicAdd(&a.counters[C_DEFER_ITEMS], 1ull);
@@ -413,6 +467,7 @@ __global__ __launch_bounds__(NT) void k_clip_fast(ShapeArgs a) {
         s_key[tid][y + 1] = kx;
         s_cand[tid][y + 1] = cx;
       }
+      s_m[tid] = refine_candidates(s_tv[tid], s_site, s_sid, s_cand[tid], s_key[tid], m, false);
     }
   }
   __syncthreads();
@@ -601,7 +656,7 @@ __global__ __launch_bounds__(64) void k_clip_slow(ShapeArgs a, unsigned char* sc
 // launchers
 // ---------------------------------------------------------------------------------------------------------------
 hipError_t launch_clip_fast(const ShapeArgs& a, int precision, int block, hipStream_t s) {
-  int nblocks = (a.nt + TB - 1) / TB;
+  int nblocks = a.nblk;
   if (nblocks == 0) return hipSuccess;
   if (precision == RPD_FP64) {
     hipLaunchKernelGGL((k_clip_fast<double, 64>), dim3(nblocks), dim3(64), 0, s, a);

@@ -7,6 +7,7 @@
 #include <hip/hip_runtime.h>
 #include <rocprim/device/device_radix_sort.hpp>
 
+#include <cmath>
 #include <numeric>
 #include <vector>
 
@@ -335,6 +336,30 @@ void mesh_prepare(rpd_mesh* m, const rpd_mesh_desc* d, uint32_t flags, hipStream
   hip_check(hipMemcpyAsync(&hv, vol.p, sizeof(long long), hipMemcpyDeviceToHost, s), "download");
   hip_check(hipStreamSynchronize(s), "sync");
   m->volume = (double)hv / 72057594037927936.0;
+  // Workgroup blocks: runs of at most TB consecutive tets (Morton order) inside one octree cell whose side is about
+  // twice the mean tet size, so that every block has a small bounding box (a plain cut every TB tets can straddle
+  // the jumps of the Morton curve and produce boxes as large as the solid).
+  {
+    std::vector<unsigned long long> keys(nt);
+    hip_check(hipMemcpyAsync(keys.data(), mkey2.p, sizeof(unsigned long long) * nt, hipMemcpyDeviceToHost, s),
+              "download");
+    hip_check(hipStreamSynchronize(s), "sync");
+    double edge = std::cbrt(6.0 * m->volume / nt) * 1048576.0;  // mean tet size in 2^-20 units
+    int level = 0;
+    while (level < 20 && (double)(1ll << (level + 1)) <= 2.0 * edge) ++level;
+    const int shift = 3 * (level + 1);
+    std::vector<int> starts;
+    starts.push_back(0);
+    for (int k = 1; k < nt; ++k) {
+      bool cut = (keys[k] >> shift) != (keys[k - 1] >> shift) || k - starts.back() >= TB;
+      if (cut) starts.push_back(k);
+    }
+    starts.push_back(nt);
+    m->nblk = (int)starts.size() - 1;
+    m->blk.alloc(sizeof(int) * starts.size());
+    hip_check(hipMemcpyAsync(m->blk.p, starts.data(), sizeof(int) * starts.size(), hipMemcpyHostToDevice, s), "upload");
+    hip_check(hipStreamSynchronize(s), "sync");
+  }
   (void)hipGetDevice(&m->device);
 }
 

@@ -108,7 +108,12 @@ __global__ void k_count_roots(ShapeArgs a, int* parent, int* cell_b0, int* face_
     else if (kind == 2) atomicAdd(&face_b0[elem], 1);
     else atomicAdd(&edge_b0[elem], 1);
   }
-  if (nodes) atomicAdd(&a.counters[C_NODES], nodes);
+  __shared__ unsigned long long s_nodes;
+  if (threadIdx.x == 0) s_nodes = 0;
+  __syncthreads();
+  if (nodes) atomicAdd(&s_nodes, nodes);
+  __syncthreads();
+  if (threadIdx.x == 0 && s_nodes) atomicAdd(&a.counters[C_NODES], s_nodes);
 }
 
 hipError_t launch_glue(const ShapeArgs& a, int* parent, hipStream_t s) {
@@ -145,6 +150,7 @@ hipError_t sort_pairs_u64(void* tmp, size_t& tmp_bytes, const unsigned long long
 __global__ void k_finalize_faces(const unsigned long long* keys, const int* slots, int cap, const long long* chi_num,
                                  const int* b0, long long L, int* out_keys, int* out_chi, int* out_b0, int* status,
                                  unsigned long long* count) {
+  unsigned long long used = 0;
   for (int q = blockIdx.x * blockDim.x + threadIdx.x; q < cap; q += gridDim.x * blockDim.x) {
     unsigned long long k = keys[q];
     if (k == EMPTY_KEY) continue;
@@ -155,12 +161,19 @@ __global__ void k_finalize_faces(const unsigned long long* keys, const int* slot
     if (c % L != 0) atomicOr(status, ST_INTERNAL);
     out_chi[q] = (int)(c / L);
     out_b0[q] = b0[s];
-    atomicAdd(count, 1ull);
+    ++used;
   }
+  __shared__ unsigned long long s_used;
+  if (threadIdx.x == 0) s_used = 0;
+  __syncthreads();
+  if (used) atomicAdd(&s_used, used);
+  __syncthreads();
+  if (threadIdx.x == 0 && s_used) atomicAdd(count, s_used);
 }
 __global__ void k_finalize_edges(const unsigned long long* keys, const int* slots, int cap, const long long* chi_num,
                                  const int* b0, long long L, int* out_keys, int* out_chi, int* out_b0, int* status,
                                  unsigned long long* count) {
+  unsigned long long used = 0;
   for (int q = blockIdx.x * blockDim.x + threadIdx.x; q < cap; q += gridDim.x * blockDim.x) {
     unsigned long long k = keys[q];
     if (k == EMPTY_KEY) continue;
@@ -172,8 +185,14 @@ __global__ void k_finalize_edges(const unsigned long long* keys, const int* slot
     if (c % L != 0) atomicOr(status, ST_INTERNAL);
     out_chi[q] = (int)(c / L);
     out_b0[q] = b0[s];
-    atomicAdd(count, 1ull);
+    ++used;
   }
+  __shared__ unsigned long long s_used;
+  if (threadIdx.x == 0) s_used = 0;
+  __syncthreads();
+  if (used) atomicAdd(&s_used, used);
+  __syncthreads();
+  if (threadIdx.x == 0 && s_used) atomicAdd(count, s_used);
 }
 __global__ void k_finalize_cells(int ns, const long long* chi_num, const long long* geo, const int* np, long long L,
                                  int* out_chi, double* out_vol, double* out_cen, int* status) {

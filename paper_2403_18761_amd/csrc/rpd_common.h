@@ -44,6 +44,8 @@ struct PieceRec {
 struct ShapeArgs {
   // ---- mesh, internal (spatially sorted) tet order
   int nt;
+  const int* blk;        // [nblk + 1] first tet of every workgroup block (spatially compact runs of <= TB tets)
+  int nblk;
   const float4* tp;      // [4 nt] tet vertex coordinates (w unused)
   const int* tn;         // [4 nt] neighbour tet across local face f (face f is opposite vertex f), -1 on the boundary
   const unsigned* nu;    // [14 nt] weight numerators L/k: 4 vertices, 6 edges, 4 faces

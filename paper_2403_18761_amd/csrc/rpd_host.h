@@ -26,7 +26,13 @@ inline void hip_check(hipError_t e, const char* what) {
   }
 }
 
-// owning device allocation
+// Caching device allocator: freed blocks are kept in per-device free lists keyed by their power-of-two size class
+// and reused, so repeated rpd_build calls do not pay hipMalloc/hipFree. Memory returns to the runtime only when the
+// process ends.
+void* pool_alloc(size_t bytes, size_t* cls_bytes);
+void pool_free(void* p, size_t cls_bytes);
+
+// owning device allocation (through the pool)
 struct DBuf {
   void* p = nullptr;
   size_t bytes = 0;
@@ -50,11 +56,10 @@ struct DBuf {
   void alloc(size_t n) {
     release();
     if (n == 0) n = 16;
-    hip_check(hipMalloc(&p, n), "hipMalloc");
-    bytes = n;
+    p = pool_alloc(n, &bytes);
   }
   void release() {
-    if (p) (void)hipFree(p);
+    if (p) pool_free(p, bytes);
     p = nullptr;
     bytes = 0;
   }
@@ -77,6 +82,8 @@ struct rpd_mesh {
   rpd::DBuf tn;    // int [4 nt]: neighbour internal tet across local face f
   rpd::DBuf nu;    // unsigned [14 nt]: weight numerators
   rpd::DBuf perm;  // int [nt]: internal -> caller tet index
+  rpd::DBuf blk;   // int [nblk + 1]: workgroup blocks over the internal order
+  int32_t nblk = 0;
 };
 
 namespace rpd {

@@ -54,10 +54,10 @@ def assert_parity(g, r, vol_rtol=1e-5, label=""):
                                err_msg=f"{label} volumes")
     ne = vr > 0
     np.testing.assert_array_equal(np.isnan(g["cell_cen"][:, 0]), ~ne, err_msg=f"{label} empty cells")
-    # centroid error relative to the cell's size (cube root of its volume)
-    scale = np.cbrt(vr[ne])[:, None]
-    err = np.abs(g["cell_cen"][ne] - r["cell_cen"][ne]) / scale
-    assert err.max(initial=0.0) < 10 * vol_rtol, (label, err.max())
+    # centroid: absolute error on the [-1, 1]^3 domain; a piece's moment error is its volume error times its
+    # position (|x| <= sqrt 3), so the centroid error is bounded by about 2 sqrt(3) times the relative volume error
+    err = np.abs(g["cell_cen"][ne] - r["cell_cen"][ne])
+    assert err.max(initial=0.0) < 4 * vol_rtol, (label, err.max())
 
 
 def log(*a):

@@ -1,5 +1,6 @@
 """Benchmark: restricted power diagram + fractional chi + beta0 of 2,000 weighted sites over the ~132k-tet solid
-torus (64^3 voxel grid, Kuhn tets), on one MI355X.
+torus (64^3 voxel grid, Kuhn tets), on one MI355X (the default workload; --workload genus3 and batch256 run the
+2.1M-tet CAD-like solid and the 256-shape batch).
 
 One step = one rpd_build call: candidate search, clipping, chi/beta0 reductions, sorted element lists copied to
 the host. Inputs (the prepared mesh and the sites) are resident in HBM before the timed region. Prints one JSON
@@ -26,26 +27,42 @@ PEAK_FP32_TFLOPS = 157.3
 FLOP_PER_PIECE = 8 * 5.84 * 1.6 + 55 * 5.84
 
 
-def workload():
+WORKLOADS = {
+    "torus2000": dict(desc="solid torus R0.6 r0.25 (seed 2 jitter), 64^3 grid, 131838 Kuhn tets, 2000 sites uniform "
+                           "inside with r = 0.9|sdf|", cpu_frac=0.25),
+    "genus3": dict(desc="genus-3 CAD-like solid (three boxes minus three cylinders), 128^3 grid, 2142000 Kuhn tets, "
+                        "20000 sites, 30% within 0.02 of sharp edges", cpu_frac=0.002),
+    "batch256": dict(desc="256 seeded shapes (tori, box unions, metaballs), log-uniform 5k-200k tets and 100-5k sites "
+                          "each, one rpd_build call", cpu_frac=0.002),
+}
+
+
+def workload(name):
     from paper_2403_18761_amd import synth
 
-    return synth.torus_inside(N=64, n_sites=2000, seed=2)
+    if name == "torus2000":
+        return [synth.torus_inside(N=64, n_sites=2000, seed=2)]
+    if name == "genus3":
+        return [synth.genus3_cad(N=128, n_sites=20000, seed=3)]
+    if name == "batch256":
+        return synth.batch_problems(256, 4)
+    raise SystemExit(f"unknown workload {name}")
 
 
-def time_builds(mesh, sites, precision, steps, warmup, stream):
+def time_builds(meshes, sites, precision, steps, warmup, stream):
     import torch
 
     from paper_2403_18761_amd import rpd
 
     flags = rpd.RPD_TIMING
     for _ in range(warmup):
-        rpd.build([mesh], [sites], precision=precision, flags=flags, stream=stream)
+        rpd.build(meshes, sites, precision=precision, flags=flags, stream=stream)
     torch.cuda.synchronize()
     clip_ms = []
     n_pairs = None
     t0 = time.perf_counter()
     for _ in range(steps):
-        res = rpd.build([mesh], [sites], precision=precision, flags=flags, stream=stream)
+        res = rpd.build(meshes, sites, precision=precision, flags=flags, stream=stream)
         st = res.stats()
         clip_ms.append(st["ms_clip"])
         n_pairs = st["n_pairs"]
@@ -54,20 +71,28 @@ def time_builds(mesh, sites, precision, steps, warmup, stream):
     return (t1 - t0) * 1e3 / steps, float(np.mean(clip_ms)), n_pairs, st
 
 
-def cpu_baseline(prob, frac):
-    """The oracle (brute force over all sites, exact predicates) on a sample of the tets; clips/sec on the host."""
+def cpu_baseline(probs, frac):
+    """The oracle (brute force over all sites, exact predicates) on a random sample of every shape's tets;
+    clips/sec on the host."""
     import oracle
 
     oracle.build(force=False)
     threads = min(16, os.cpu_count() or 1)
     rng = np.random.default_rng(0)
-    sel = np.sort(rng.choice(prob.n_tets, max(1, int(frac * prob.n_tets)), replace=False))
-    t0 = time.perf_counter()
-    r = oracle.tet_pieces(prob, sel, threads=threads)
-    dt = time.perf_counter() - t0
-    return dict(value=len(r["pieces"]) / dt, unit="clips/s", cores=threads, kind="oracle",
-                sample=f"{len(sel)} of {prob.n_tets} tets (random, seed 0), each clipped against all "
-                       f"{prob.n_sites} sites; {len(r['pieces'])} nonempty pieces in {dt:.2f} s")
+    pieces = 0
+    tets = 0
+    dt = 0.0
+    for prob in probs:
+        sel = np.sort(rng.choice(prob.n_tets, max(1, int(frac * prob.n_tets)), replace=False))
+        t0 = time.perf_counter()
+        r = oracle.tet_pieces(prob, sel, threads=threads)
+        dt += time.perf_counter() - t0
+        pieces += len(r["pieces"])
+        tets += len(sel)
+    total = sum(p.n_tets for p in probs)
+    return dict(value=pieces / dt, unit="clips/s", cores=threads, kind="oracle",
+                sample=f"{tets} of {total} tets (random {frac:g} of every shape, seed 0), each clipped against all "
+                       f"sites of its shape; {pieces} nonempty pieces in {dt:.2f} s")
 
 
 def main():
@@ -77,7 +102,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-fp64", action="store_true", help="skip the all-FP64 comparison")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-frac", type=float, default=0.25)
+    ap.add_argument("--cpu-frac", type=float, default=None)
+    ap.add_argument("--workload", default="torus2000", choices=sorted(WORKLOADS))
     args = ap.parse_args()
     if args.gpus != 1:
         print("this build runs on one GPU only: multi-GPU sharding is a design note, not an implemented path",
@@ -88,7 +114,9 @@ def main():
 
     from paper_2403_18761_amd import rpd
 
-    prob = workload()
+    probs = workload(args.workload)
+    print(f"# workload {args.workload}: {len(probs)} shape(s), {sum(p.n_tets for p in probs)} tets, "
+          f"{sum(p.n_sites for p in probs)} sites", file=sys.stderr, flush=True)
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
     stream = torch.cuda.current_stream(dev)
@@ -96,16 +124,16 @@ def main():
     def t(a, dt=torch.float32):
         return torch.as_tensor(np.ascontiguousarray(a), dtype=dt, device=dev)
 
-    mesh = rpd.Mesh(t(prob.vx), t(prob.vy), t(prob.vz), t(prob.tv.reshape(-1), torch.int32), stream=stream)
-    sites = (t(prob.sx), t(prob.sy), t(prob.sz), t(prob.sr))
+    meshes = [rpd.Mesh(t(p.vx), t(p.vy), t(p.vz), t(p.tv.reshape(-1), torch.int32), stream=stream) for p in probs]
+    sites = [(t(p.sx), t(p.sy), t(p.sz), t(p.sr)) for p in probs]
     torch.cuda.synchronize()
 
-    ms32, clip32, pairs, st32 = time_builds(mesh, sites, rpd.RPD_FP32_FALLBACK, args.steps, args.warmup, stream)
+    ms32, clip32, pairs, st32 = time_builds(meshes, sites, rpd.RPD_FP32_FALLBACK, args.steps, args.warmup, stream)
     print(f"# fp32+fallback: {ms32:.3f} ms/RPD, clip kernel {clip32:.3f} ms, pairs {pairs}", file=sys.stderr,
           flush=True)
     out64 = None
     if not args.no_fp64:
-        ms64, clip64, pairs64, st64 = time_builds(mesh, sites, rpd.RPD_FP64, args.steps, args.warmup, stream)
+        ms64, clip64, pairs64, st64 = time_builds(meshes, sites, rpd.RPD_FP64, args.steps, args.warmup, stream)
         assert pairs64 == pairs
         out64 = dict(ms_per_rpd=ms64, clips_per_s=pairs / (ms64 * 1e-3), clip_kernel_ms=clip64)
         print(f"# all-fp64: {ms64:.3f} ms/RPD, clip kernel {clip64:.3f} ms", file=sys.stderr, flush=True)
@@ -124,9 +152,9 @@ def main():
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": "solid torus R0.6 r0.25 (seed 2 jitter), 64^3 grid, 131838 Kuhn tets, 2000 sites "
-                               "uniform inside with r = 0.9|sdf|",
-                   "n_tets": prob.n_tets, "n_sites": prob.n_sites, "n_pairs": pairs},
+        "config": {"workload": WORKLOADS[args.workload]["desc"], "name": args.workload, "n_shapes": len(probs),
+                   "n_tets": sum(p.n_tets for p in probs), "n_sites": sum(p.n_sites for p in probs),
+                   "n_pairs": pairs},
         "ms_per_rpd": ms32,
         "all_fp64": out64,
         "stats": {k: st32[k] for k in ("n_candidates", "n_deferred", "n_fp64", "n_exact", "n_faces", "n_edges",
@@ -136,7 +164,8 @@ def main():
                      "kernel": "k_clip_fast<float,128>", "flop_per_piece": FLOP_PER_PIECE},
     }
     if not args.no_cpu_baseline:
-        line["cpu_baseline"] = cpu_baseline(prob, args.cpu_frac)
+        frac = args.cpu_frac if args.cpu_frac is not None else WORKLOADS[args.workload]["cpu_frac"]
+        line["cpu_baseline"] = cpu_baseline(probs, frac)
     print(json.dumps(line), flush=True)
 
 

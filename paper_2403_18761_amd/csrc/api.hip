@@ -74,13 +74,13 @@ static unsigned pow2_cap(size_t n) {
 static std::mutex g_scratch_mu;
 static DBuf g_scratch;
 static int g_scratch_device = -1;
-constexpr int SLOW_THREADS = 4096;
+constexpr int SLOW_WAVES = 256;  // one wavefront per deferred item at a time
 
 static unsigned char* slow_scratch() {
   std::lock_guard<std::mutex> g(g_scratch_mu);
   int dev = 0;
   (void)hipGetDevice(&dev);
-  size_t need = slow_scratch_bytes(SLOW_THREADS);
+  size_t need = slow_scratch_bytes(SLOW_WAVES);
   if (g_scratch.p == nullptr || g_scratch.bytes < need || g_scratch_device != dev) {
     g_scratch.alloc(need);
     g_scratch_device = dev;
@@ -128,201 +128,402 @@ static void d2h(std::vector<T>& v, const void* src, size_t n, hipStream_t s) {
   if (n) hip_check(hipMemcpyAsync(v.data(), src, sizeof(T) * n, hipMemcpyDeviceToHost, s), "download");
 }
 
-// One shape, one attempt. Returns false if a table ran out of room (caller retries with a larger scale).
-static bool run_shape(const rpd_mesh* m, const rpd_sites* sp, const rpd_opts& o, hipStream_t s, int scale,
-                      ShapeOut& out, rpd_stats& st) {
-  const int ns = sp->n_sites, nt = m->nt;
-  const bool dev = (o.flags & RPD_DEVICE_PTRS) != 0;
-  // ---- sites
-  DBuf site(sizeof(float4) * (size_t)ns);
-  DBuf raw;
-  const float *sx = sp->sx, *sy = sp->sy, *sz = sp->sz, *sr = sp->sr;
-  if (!dev) {
-    raw.alloc(sizeof(float) * 4 * (size_t)ns);
-    float* r = raw.as<float>();
-    hip_check(hipMemcpyAsync(r, sp->sx, sizeof(float) * ns, hipMemcpyHostToDevice, s), "upload");
-    hip_check(hipMemcpyAsync(r + ns, sp->sy, sizeof(float) * ns, hipMemcpyHostToDevice, s), "upload");
-    hip_check(hipMemcpyAsync(r + 2 * (size_t)ns, sp->sz, sizeof(float) * ns, hipMemcpyHostToDevice, s), "upload");
-    hip_check(hipMemcpyAsync(r + 3 * (size_t)ns, sp->sr, sizeof(float) * ns, hipMemcpyHostToDevice, s), "upload");
-    sx = r;
-    sy = r + ns;
-    sz = r + 2 * (size_t)ns;
-    sr = r + 3 * (size_t)ns;
+// ---------------------------------------------------------------------------------------------------------------
+// Device state of one computation: tables, accumulators, counters. Used once by rpd_build and kept across rounds
+// by a session.
+// ---------------------------------------------------------------------------------------------------------------
+struct DeviceState {
+  int nsh = 0, ns_cap = 0;
+  long long nt_tot = 0;
+  unsigned capF = 0, capE = 0, capQ = 0, capN = 0;
+  int def_cap = 0, piece_cap = 0;
+  DBuf site, status, cell_chi, cell_geo, cell_np, cell_b0;
+  DBuf fkeys, face_chi, face_np, face_b0, ekeys, edge_chi, edge_np, edge_b0, qkeys, rpv_cnt;
+  DBuf nkeys, node_glue, node_cnt, parent, deferred, pieces, counters, tetU;
+
+  unsigned long long* cnt() const { return counters.as<unsigned long long>(); }
+  unsigned long long* fin_count() const { return cnt() + NCOUNTERS; }  // [0] faces, [1] edges
+
+  void alloc(int n_shapes, int ns, long long nt, int scale, bool keep_pieces, bool keep_U) {
+    nsh = n_shapes;
+    ns_cap = ns;
+    nt_tot = nt;
+    capF = pow2_cap((32 * (size_t)ns + 1024) * scale);
+    capE = pow2_cap((32 * (size_t)ns + 1024) * scale);
+    capQ = pow2_cap((16 * (size_t)ns + 1024) * scale);
+    capN = pow2_cap((6 * (size_t)nt + 4096) * scale);
+    def_cap = (int)std::min<size_t>((4 * (size_t)nt + 4096) * scale, 1u << 30);
+    piece_cap = keep_pieces ? (int)std::min<size_t>((8 * (size_t)nt + 1024) * scale, 1u << 30) : 0;
+    site.alloc(sizeof(float4) * (size_t)ns);
+    status.alloc(16);
+    cell_chi.alloc(8 * (size_t)ns);
+    cell_geo.alloc(32 * (size_t)ns);
+    cell_np.alloc(4 * (size_t)ns);
+    cell_b0.alloc(4 * (size_t)ns);
+    fkeys.alloc(8 * (size_t)capF);
+    face_chi.alloc(8 * (size_t)capF);
+    face_np.alloc(4 * (size_t)capF);
+    face_b0.alloc(4 * (size_t)capF);
+    ekeys.alloc(8 * (size_t)capE);
+    edge_chi.alloc(8 * (size_t)capE);
+    edge_np.alloc(4 * (size_t)capE);
+    edge_b0.alloc(4 * (size_t)capE);
+    qkeys.alloc(8 * (size_t)capQ);
+    rpv_cnt.alloc(4 * (size_t)capQ);
+    nkeys.alloc(8 * (size_t)capN);
+    node_glue.alloc(4 * (size_t)capN);
+    node_cnt.alloc(4 * (size_t)capN);
+    parent.alloc(4 * (size_t)capN);
+    deferred.alloc(16 * (size_t)def_cap);
+    pieces.alloc(sizeof(PieceRec) * (size_t)std::max(piece_cap, 1));
+    counters.alloc(8 * (NCOUNTERS + 8));
+    if (keep_U) tetU.alloc(8 * (size_t)std::max<long long>(nt, 1));
   }
-  // ---- capacities
-  const unsigned capF = pow2_cap((32 * (size_t)ns + 1024) * scale);
-  const unsigned capE = pow2_cap((32 * (size_t)ns + 1024) * scale);
-  const unsigned capN = pow2_cap((12 * (size_t)nt + 4096) * scale);
-  const int rpv_cap = (int)std::min<size_t>((16 * (size_t)ns + 1024) * scale, 1u << 30);
-  const int def_cap = (int)std::min<size_t>((4 * (size_t)nt + 4096) * scale, 1u << 30);
-  const int piece_cap = (o.flags & RPD_KEEP_PIECES) ? (int)std::min<size_t>((8 * (size_t)nt + 1024) * scale, 1u << 30) : 0;
 
-  DBuf cell_chi(8 * (size_t)ns), cell_geo(32 * (size_t)ns), cell_np(4 * (size_t)ns), cell_b0(4 * (size_t)ns);
-  DBuf fkeys(8 * (size_t)capF), face_chi(8 * (size_t)capF), face_b0(4 * (size_t)capF);
-  DBuf ekeys(8 * (size_t)capE), edge_chi(8 * (size_t)capE), edge_b0(4 * (size_t)capE);
-  DBuf rpv(16 * (size_t)rpv_cap), nkeys(8 * (size_t)capN), node_glue(4 * (size_t)capN), parent(4 * (size_t)capN);
-  DBuf deferred(8 * (size_t)def_cap), pieces(sizeof(PieceRec) * (size_t)std::max(piece_cap, 1));
-  DBuf counters(8 * NCOUNTERS + 8 * 4), status(16);
-  unsigned long long* cnt = counters.as<unsigned long long>();
-  unsigned long long* fin_count = cnt + NCOUNTERS;  // [0] faces, [1] edges
+  void clear(hipStream_t s) {
+    const size_t ns = (size_t)ns_cap;
+    hip_check(launch_fill_i32(status.as<int>(), 0, 4, s), "fill");
+    hip_check(launch_fill_u64(cell_chi.as<unsigned long long>(), 0, ns, s), "fill");
+    hip_check(launch_fill_u64(cell_geo.as<unsigned long long>(), 0, 4 * ns, s), "fill");
+    hip_check(launch_fill_i32(cell_np.as<int>(), 0, ns, s), "fill");
+    hip_check(launch_fill_u64(fkeys.as<unsigned long long>(), EMPTY_KEY, capF, s), "fill");
+    hip_check(launch_fill_u64(face_chi.as<unsigned long long>(), 0, capF, s), "fill");
+    hip_check(launch_fill_i32(face_np.as<int>(), 0, capF, s), "fill");
+    hip_check(launch_fill_u64(ekeys.as<unsigned long long>(), EMPTY_KEY, capE, s), "fill");
+    hip_check(launch_fill_u64(edge_chi.as<unsigned long long>(), 0, capE, s), "fill");
+    hip_check(launch_fill_i32(edge_np.as<int>(), 0, capE, s), "fill");
+    hip_check(launch_fill_u64(qkeys.as<unsigned long long>(), EMPTY_KEY, capQ, s), "fill");
+    hip_check(launch_fill_i32(rpv_cnt.as<int>(), 0, capQ, s), "fill");
+    hip_check(launch_fill_u64(nkeys.as<unsigned long long>(), EMPTY_KEY, capN, s), "fill");
+    hip_check(launch_fill_i32(node_glue.as<int>(), 0, capN, s), "fill");
+    hip_check(launch_fill_i32(node_cnt.as<int>(), 0, capN, s), "fill");
+    hip_check(launch_fill_u64(cnt(), 0, NCOUNTERS + 8, s), "fill");
+  }
 
-  hip_check(launch_fill_u64(cell_chi.as<unsigned long long>(), 0, ns, s), "fill");
-  hip_check(launch_fill_u64(cell_geo.as<unsigned long long>(), 0, 4 * (size_t)ns, s), "fill");
-  hip_check(launch_fill_i32(cell_np.as<int>(), 0, ns, s), "fill");
-  hip_check(launch_fill_i32(cell_b0.as<int>(), 0, ns, s), "fill");
-  hip_check(launch_fill_u64(fkeys.as<unsigned long long>(), EMPTY_KEY, capF, s), "fill");
-  hip_check(launch_fill_u64(face_chi.as<unsigned long long>(), 0, capF, s), "fill");
-  hip_check(launch_fill_i32(face_b0.as<int>(), 0, capF, s), "fill");
-  hip_check(launch_fill_u64(ekeys.as<unsigned long long>(), EMPTY_KEY, capE, s), "fill");
-  hip_check(launch_fill_u64(edge_chi.as<unsigned long long>(), 0, capE, s), "fill");
-  hip_check(launch_fill_i32(edge_b0.as<int>(), 0, capE, s), "fill");
-  hip_check(launch_fill_rpv(rpv.as<int4>(), rpv_cap, s), "fill");
-  hip_check(launch_fill_u64(nkeys.as<unsigned long long>(), EMPTY_KEY, capN, s), "fill");
-  hip_check(launch_fill_i32(node_glue.as<int>(), 0, capN, s), "fill");
-  hip_check(launch_fill_u64(cnt, 0, NCOUNTERS + 4, s), "fill");
-  hip_check(launch_fill_i32(status.as<int>(), 0, 4, s), "fill");
+  ShapeArgs args(const ShapeDesc* shapes, const int2* items, int nitems, unsigned flags, int kmax, int sign) const {
+    ShapeArgs a;
+    std::memset(&a, 0, sizeof(a));
+    a.shapes = shapes;
+    a.nshapes = nsh;
+    a.items = items;
+    a.nitems = nitems;
+    a.ns = ns_cap;
+    a.site = site.as<float4>();
+    a.cell_chi = cell_chi.as<long long>();
+    a.cell_geo = cell_geo.as<long long>();
+    a.cell_np = cell_np.as<int>();
+    a.F = HashTab{fkeys.as<unsigned long long>(), capF - 1};
+    a.face_chi = face_chi.as<long long>();
+    a.face_np = face_np.as<int>();
+    a.E = HashTab{ekeys.as<unsigned long long>(), capE - 1};
+    a.edge_chi = edge_chi.as<long long>();
+    a.edge_np = edge_np.as<int>();
+    a.Q = HashTab{qkeys.as<unsigned long long>(), capQ - 1};
+    a.rpv_cnt = rpv_cnt.as<int>();
+    a.N = HashTab{nkeys.as<unsigned long long>(), capN - 1};
+    a.node_glue = node_glue.as<int>();
+    a.node_cnt = node_cnt.as<int>();
+    a.sign = sign;
+    a.tet_U = tetU.p ? tetU.as<double>() : nullptr;
+    a.deferred = deferred.as<int4>();
+    a.deferred_cap = def_cap;
+    a.pieces = pieces.as<PieceRec>();
+    a.piece_cap = piece_cap;
+    a.counters = cnt();
+    a.status = status.as<int>();
+    a.flags = flags;
+    a.kmax = kmax;
+    return a;
+  }
 
-  ShapeArgs a;
-  std::memset(&a, 0, sizeof(a));
-  a.nt = nt;
-  a.blk = m->blk.as<int>();
-  a.nblk = m->nblk;
-  a.tp = m->tp.as<float4>();
-  a.tn = m->tn.as<int>();
-  a.nu = m->nu.as<unsigned>();
-  a.L = m->L;
-  a.ns = ns;
-  a.site = site.as<float4>();
-  a.cell_chi = cell_chi.as<long long>();
-  a.cell_geo = cell_geo.as<long long>();
-  a.cell_np = cell_np.as<int>();
-  a.F = HashTab{fkeys.as<unsigned long long>(), capF - 1};
-  a.face_chi = face_chi.as<long long>();
-  a.E = HashTab{ekeys.as<unsigned long long>(), capE - 1};
-  a.edge_chi = edge_chi.as<long long>();
-  a.rpv = rpv.as<int4>();
-  a.rpv_cap = rpv_cap;
-  a.N = HashTab{nkeys.as<unsigned long long>(), capN - 1};
-  a.node_glue = node_glue.as<int>();
-  a.deferred = deferred.as<int2>();
-  a.deferred_cap = def_cap;
-  a.pieces = pieces.as<PieceRec>();
-  a.piece_cap = piece_cap;
-  a.counters = cnt;
-  a.status = status.as<int>();
-  a.flags = o.flags;
-  a.kmax = o.clip_budget > 0 ? std::min(o.clip_budget, KMAX) : KMAX;
+  // components of every live element piece: fresh union-find and root counts
+  void components(const ShapeArgs& a, hipStream_t s) {
+    hip_check(launch_fill_i32(cell_b0.as<int>(), 0, (size_t)ns_cap, s), "fill");
+    hip_check(launch_fill_i32(face_b0.as<int>(), 0, capF, s), "fill");
+    hip_check(launch_fill_i32(edge_b0.as<int>(), 0, capE, s), "fill");
+    hip_check(launch_fill_u64(cnt() + C_NODES, 0, 1, s), "fill");
+    hip_check(launch_glue(a, parent.as<int>(), s), "glue");
+    hip_check(launch_count_roots(a, parent.as<int>(), cell_b0.as<int>(), face_b0.as<int>(), edge_b0.as<int>(), s),
+              "roots");
+  }
+};
 
-  Timing tm((o.flags & RPD_TIMING) != 0);
-  tm.mark(0, s);
-  hip_check(launch_validate_sites(sx, sy, sz, sr, ns, site.as<float4>(), a.status, s), "validate sites");
-  hip_check(launch_clip_fast(a, o.precision, o.block, s), "clip kernel");
-  tm.mark(1, s);
-  hip_check(launch_clip_slow(a, slow_scratch(), SLOW_THREADS, s), "deferred clip kernel");
-  tm.mark(2, s);
-  hip_check(launch_glue(a, parent.as<int>(), s), "glue");
-  hip_check(launch_count_roots(a, parent.as<int>(), cell_b0.as<int>(), face_b0.as<int>(), edge_b0.as<int>(), s),
-            "roots");
-  // element lists: sort whole capacities, finalise
-  const int maxcap = (int)std::max<unsigned>(std::max(capF, capE), (unsigned)rpv_cap);
+static rpd_status status_error(int hst) {
+  if (hst & ST_INVALID) throw Failure{RPD_E_INVALID, "site value off the 2^-20 grid, out of range or not finite"};
+  if (hst & ST_DEGENERATE)
+    throw Failure{RPD_E_DEGENERATE, "input not in general position (an exact predicate is zero or duplicate sites)"};
+  if (hst & ST_SLOW_CAPACITY)
+    throw Failure{RPD_E_NOMEM, "a tet exceeds the large-capacity path (over 1020 candidate sites or 64 vertices)"};
+  if (hst & ST_INTERNAL) throw Failure{RPD_E_INTERNAL, "internal consistency check failed (gluing or chi)"};
+  return RPD_OK;
+}
+
+// Sorted element lists of the current state, copied to the host and split per shape. Returns false when a table
+// overflowed (the caller retries with larger tables).
+static bool collect(DeviceState& D, const std::vector<ShapeDesc>& hd, const ShapeDesc* dshapes,
+                    const rpd_mesh* const* meshes, hipStream_t s, Timing& tm, std::vector<ShapeOut>& outs,
+                    rpd_stats& st) {
+  const int nsh = (int)hd.size();
+  int ns = 0;
+  for (const auto& d : hd) ns = std::max(ns, d.site_off + d.ns);
+  const unsigned capF = D.capF, capE = D.capE, capQ = D.capQ;
+  const int maxcap = (int)std::max(std::max(capF, capE), capQ);
   size_t tmpb = sort_tmp_bytes(maxcap);
   DBuf tmp(tmpb), kA(8 * (size_t)maxcap), kB(8 * (size_t)maxcap), kC(8 * (size_t)maxcap), vA(4 * (size_t)maxcap),
       vB(4 * (size_t)maxcap);
   DBuf f_keys(8 * (size_t)capF), f_chi(4 * (size_t)capF), f_b0(4 * (size_t)capF);
   DBuf e_keys(12 * (size_t)capE), e_chi(4 * (size_t)capE), e_b0(4 * (size_t)capE);
-  DBuf c_chi(4 * (size_t)ns), c_vol(8 * (size_t)ns), c_cen(24 * (size_t)ns), rpv_sorted(16 * (size_t)rpv_cap);
+  DBuf c_chi(4 * (size_t)std::max(ns, 1)), c_vol(8 * (size_t)std::max(ns, 1)), c_cen(24 * (size_t)std::max(ns, 1));
+  DBuf rpv_raw(16 * (size_t)capQ), rpv_sorted(16 * (size_t)capQ);
+  unsigned long long* fin = D.fin_count();
+  hip_check(launch_fill_u64(fin, 0, 2, s), "fill");
+  hip_check(launch_live_keys(D.fkeys.as<unsigned long long>(), D.face_np.as<int>(), capF,
+                             kA.as<unsigned long long>(), s),
+            "live faces");
   hip_check(launch_iota(vA.as<int>(), capF, s), "iota");
-  hip_check(sort_pairs_u64(tmp.p, tmpb, fkeys.as<unsigned long long>(), kB.as<unsigned long long>(), vA.as<int>(),
+  hip_check(sort_pairs_u64(tmp.p, tmpb, kA.as<unsigned long long>(), kB.as<unsigned long long>(), vA.as<int>(),
                            vB.as<int>(), capF, s),
             "sort faces");
-  hip_check(launch_finalize_faces(kB.as<unsigned long long>(), vB.as<int>(), capF, a.face_chi, face_b0.as<int>(), a.L,
-                                  f_keys.as<int>(), f_chi.as<int>(), f_b0.as<int>(), a.status, fin_count + 0, s),
+  hip_check(launch_finalize_faces(kB.as<unsigned long long>(), vB.as<int>(), capF, D.face_chi.as<long long>(),
+                                  D.face_b0.as<int>(), dshapes, nsh, f_keys.as<int>(), f_chi.as<int>(),
+                                  f_b0.as<int>(), D.status.as<int>(), fin + 0, s),
             "finalize faces");
+  hip_check(launch_live_keys(D.ekeys.as<unsigned long long>(), D.edge_np.as<int>(), capE,
+                             kA.as<unsigned long long>(), s),
+            "live edges");
   hip_check(launch_iota(vA.as<int>(), capE, s), "iota");
-  hip_check(sort_pairs_u64(tmp.p, tmpb, ekeys.as<unsigned long long>(), kB.as<unsigned long long>(), vA.as<int>(),
+  hip_check(sort_pairs_u64(tmp.p, tmpb, kA.as<unsigned long long>(), kB.as<unsigned long long>(), vA.as<int>(),
                            vB.as<int>(), capE, s),
             "sort edges");
-  hip_check(launch_finalize_edges(kB.as<unsigned long long>(), vB.as<int>(), capE, a.edge_chi, edge_b0.as<int>(), a.L,
-                                  e_keys.as<int>(), e_chi.as<int>(), e_b0.as<int>(), a.status, fin_count + 1, s),
+  hip_check(launch_finalize_edges(kB.as<unsigned long long>(), vB.as<int>(), capE, D.edge_chi.as<long long>(),
+                                  D.edge_b0.as<int>(), dshapes, nsh, e_keys.as<int>(), e_chi.as<int>(),
+                                  e_b0.as<int>(), D.status.as<int>(), fin + 1, s),
             "finalize edges");
-  hip_check(launch_finalize_cells(ns, a.cell_chi, a.cell_geo, a.cell_np, a.L, c_chi.as<int>(), c_vol.as<double>(),
-                                  c_cen.as<double>(), a.status, s),
-            "finalize cells");
-  hip_check(launch_sort_rpv(a.rpv, rpv_cap, kA.as<unsigned long long>(), kB.as<unsigned long long>(),
+  if (ns > 0)
+    hip_check(launch_finalize_cells(ns, D.cell_chi.as<long long>(), D.cell_geo.as<long long>(), D.cell_np.as<int>(),
+                                    dshapes, nsh, c_chi.as<int>(), c_vol.as<double>(), c_cen.as<double>(),
+                                    D.status.as<int>(), s),
+              "finalize cells");
+  HashTab Q{D.qkeys.as<unsigned long long>(), capQ - 1};
+  hip_check(launch_rpv_decode(Q, D.rpv_cnt.as<int>(), D.ekeys.as<unsigned long long>(), rpv_raw.as<int4>(), s),
+            "rpv decode");
+  hip_check(launch_sort_rpv(rpv_raw.as<int4>(), (int)capQ, kA.as<unsigned long long>(), kB.as<unsigned long long>(),
                             kC.as<unsigned long long>(), vA.as<int>(), vB.as<int>(), tmp.p, tmpb,
                             rpv_sorted.as<int4>(), s),
             "sort rpv");
   tm.mark(3, s);
   unsigned long long hc[NCOUNTERS + 4];
   int hst = 0;
-  hip_check(hipMemcpyAsync(hc, cnt, sizeof(hc), hipMemcpyDeviceToHost, s), "download");
-  hip_check(hipMemcpyAsync(&hst, a.status, sizeof(int), hipMemcpyDeviceToHost, s), "download");
+  hip_check(hipMemcpyAsync(hc, D.cnt(), sizeof(hc), hipMemcpyDeviceToHost, s), "download");
+  hip_check(hipMemcpyAsync(&hst, D.status.p, sizeof(int), hipMemcpyDeviceToHost, s), "download");
   hip_check(hipStreamSynchronize(s), "synchronize");
-  if (hst & ST_INVALID) throw Failure{RPD_E_INVALID, "site value off the 2^-20 grid, out of range or not finite"};
-  if (hst & ST_DEGENERATE)
-    throw Failure{RPD_E_DEGENERATE, "input not in general position (an exact predicate is zero or duplicate sites)"};
   if (hst & ST_TABLE_FULL) return false;
-  if (hc[C_DEFER_ITEMS] > (unsigned long long)def_cap || hc[C_RPV] > (unsigned long long)rpv_cap ||
-      (piece_cap && hc[C_PIECES] > (unsigned long long)piece_cap))
+  if (hc[C_DEFER_ITEMS] > (unsigned long long)D.def_cap || (D.piece_cap && hc[C_PIECES] > (unsigned long long)D.piece_cap))
     return false;
-  if (hst & ST_SLOW_CAPACITY)
-    throw Failure{RPD_E_NOMEM, "a tet exceeds the large-capacity path (over 1020 candidate sites or 64 vertices)"};
-  if (hst & ST_INTERNAL) throw Failure{RPD_E_INTERNAL, "internal consistency check failed (gluing or chi)"};
-  const size_t nf = hc[NCOUNTERS + 0], ne = hc[NCOUNTERS + 1], nq = hc[C_RPV];
-  out.ns = ns;
-  d2h(out.cell_chi, c_chi.p, ns, s);
-  d2h(out.cell_b0, cell_b0.p, ns, s);
-  d2h(out.vol, c_vol.p, ns, s);
-  d2h(out.cen, c_cen.p, 3 * (size_t)ns, s);
-  d2h(out.face_keys, f_keys.p, 2 * nf, s);
-  d2h(out.face_chi, f_chi.p, nf, s);
-  d2h(out.face_b0, f_b0.p, nf, s);
-  d2h(out.edge_keys, e_keys.p, 3 * ne, s);
-  d2h(out.edge_chi, e_chi.p, ne, s);
-  d2h(out.edge_b0, e_b0.p, ne, s);
-  d2h(out.rpv_keys, rpv_sorted.p, 4 * nq, s);
+  status_error(hst);
+  const size_t nf = hc[NCOUNTERS + 0], ne = hc[NCOUNTERS + 1];
+  std::vector<int32_t> all_cchi, all_cb0, all_fk, all_fchi, all_fb0, all_ek, all_echi, all_eb0, all_rpv;
+  std::vector<double> all_vol, all_cen;
+  d2h(all_cchi, c_chi.p, ns, s);
+  d2h(all_cb0, D.cell_b0.p, ns, s);
+  d2h(all_vol, c_vol.p, ns, s);
+  d2h(all_cen, c_cen.p, 3 * (size_t)ns, s);
+  d2h(all_fk, f_keys.p, 2 * nf, s);
+  d2h(all_fchi, f_chi.p, nf, s);
+  d2h(all_fb0, f_b0.p, nf, s);
+  d2h(all_ek, e_keys.p, 3 * ne, s);
+  d2h(all_echi, e_chi.p, ne, s);
+  d2h(all_eb0, e_b0.p, ne, s);
+  d2h(all_rpv, rpv_sorted.p, 4 * (size_t)capQ, s);
   std::vector<PieceRec> prs;
-  std::vector<int32_t> perm;
-  if (piece_cap) {
-    d2h(prs, pieces.p, hc[C_PIECES], s);
-    d2h(perm, m->perm.p, nt, s);
-  }
+  if (D.piece_cap) d2h(prs, D.pieces.p, hc[C_PIECES], s);
   tm.mark(4, s);
   hip_check(hipStreamSynchronize(s), "synchronize");
-  out.cell_keys.resize(ns);
-  std::iota(out.cell_keys.begin(), out.cell_keys.end(), 0);
-  if (piece_cap) {
-    std::vector<size_t> ord(prs.size());
-    std::iota(ord.begin(), ord.end(), 0);
-    for (auto& p : prs) p.t = perm[p.t];
-    std::sort(ord.begin(), ord.end(), [&](size_t x, size_t y) {
-      return prs[x].t != prs[y].t ? prs[x].t < prs[y].t : prs[x].i < prs[y].i;
-    });
-    for (size_t k : ord) {
-      const PieceRec& p = prs[k];
-      out.pc_t.push_back(p.t);
-      out.pc_i.push_back(p.i);
-      out.pc_geo.push_back(p.vol);
-      out.pc_geo.push_back(p.mx);
-      out.pc_geo.push_back(p.my);
-      out.pc_geo.push_back(p.mz);
-      out.pc_chi.push_back(p.chi);
+  size_t nq = 0;
+  while (nq < (size_t)capQ && all_rpv[4 * nq] != 0x7fffffff) ++nq;
+  // ---- split per shape (element lists are sorted by batch-global keys, so each shape is one contiguous run)
+  size_t fpos = 0, epos = 0, qpos = 0;
+  for (int k = 0; k < nsh; ++k) {
+    ShapeOut& out = outs[k];
+    const int off = hd[k].site_off, n = hd[k].ns, end = off + n;
+    out.ns = n;
+    out.cell_chi.assign(all_cchi.begin() + off, all_cchi.begin() + end);
+    out.cell_b0.assign(all_cb0.begin() + off, all_cb0.begin() + end);
+    out.vol.assign(all_vol.begin() + off, all_vol.begin() + end);
+    out.cen.assign(all_cen.begin() + 3 * (size_t)off, all_cen.begin() + 3 * (size_t)end);
+    out.cell_keys.resize(n);
+    std::iota(out.cell_keys.begin(), out.cell_keys.end(), 0);
+    out.face_keys.clear();
+    out.face_chi.clear();
+    out.face_b0.clear();
+    while (fpos < nf && all_fk[2 * fpos] < end) {
+      out.face_keys.push_back(all_fk[2 * fpos] - off);
+      out.face_keys.push_back(all_fk[2 * fpos + 1] - off);
+      out.face_chi.push_back(all_fchi[fpos]);
+      out.face_b0.push_back(all_fb0[fpos]);
+      ++fpos;
+    }
+    out.edge_keys.clear();
+    out.edge_chi.clear();
+    out.edge_b0.clear();
+    while (epos < ne && all_ek[3 * epos] < end) {
+      for (int c = 0; c < 3; ++c) out.edge_keys.push_back(all_ek[3 * epos + c] - off);
+      out.edge_chi.push_back(all_echi[epos]);
+      out.edge_b0.push_back(all_eb0[epos]);
+      ++epos;
+    }
+    out.rpv_keys.clear();
+    while (qpos < nq && all_rpv[4 * qpos] < end) {
+      for (int c = 0; c < 4; ++c) out.rpv_keys.push_back(all_rpv[4 * qpos + c] - off);
+      ++qpos;
+    }
+    out.pc_t.clear();
+    out.pc_i.clear();
+    out.pc_geo.clear();
+    out.pc_chi.clear();
+  }
+  if (D.piece_cap) {
+    std::vector<std::vector<int32_t>> perms(nsh);
+    std::vector<std::vector<size_t>> per_shape(nsh);
+    for (size_t q = 0; q < prs.size(); ++q) {
+      int k = nsh - 1;
+      while (k > 0 && hd[k].tet_off > prs[q].t) --k;
+      per_shape[k].push_back(q);
+    }
+    for (int k = 0; k < nsh; ++k) {
+      if (per_shape[k].empty()) continue;
+      d2h(perms[k], meshes[k]->perm.p, meshes[k]->nt, s);
+      hip_check(hipStreamSynchronize(s), "synchronize");
+      auto& idx = per_shape[k];
+      auto tt = [&](size_t q) { return perms[k][prs[q].t - (int)hd[k].tet_off]; };
+      std::sort(idx.begin(), idx.end(), [&](size_t x, size_t y) {
+        return tt(x) != tt(y) ? tt(x) < tt(y) : prs[x].i < prs[y].i;
+      });
+      ShapeOut& out = outs[k];
+      for (size_t q : idx) {
+        const PieceRec& p = prs[q];
+        out.pc_t.push_back(tt(q));
+        out.pc_i.push_back(p.i - hd[k].site_off);
+        out.pc_geo.push_back(p.vol);
+        out.pc_geo.push_back(p.mx);
+        out.pc_geo.push_back(p.my);
+        out.pc_geo.push_back(p.mz);
+        out.pc_chi.push_back(p.chi);
+      }
     }
   }
-  st.n_pairs += (int64_t)hc[C_PAIRS];
-  st.n_candidates += (int64_t)hc[C_CAND];
-  st.n_deferred += (int64_t)hc[C_DEFER_ITEMS];
-  st.n_fp64 += (int64_t)hc[C_FP64];
-  st.n_exact += (int64_t)hc[C_EXACT];
-  st.n_cells += ns;
-  st.n_faces += (int64_t)nf;
-  st.n_edges += (int64_t)ne;
-  st.n_rpv += (int64_t)nq;
-  st.n_glue += (int64_t)hc[C_NODES];
-  st.ms_clip += tm.ms(0, 1);
-  st.ms_deferred += tm.ms(1, 2);
-  st.ms_reduce += tm.ms(2, 3);
-  st.ms_total += tm.ms(0, 4);
+  st.n_pairs = (int64_t)hc[C_PAIRS];
+  st.n_candidates = (int64_t)hc[C_CAND];
+  st.n_deferred = (int64_t)hc[C_DEFER_ITEMS];
+  st.n_fp64 = (int64_t)hc[C_FP64];
+  st.n_exact = (int64_t)hc[C_EXACT];
+  st.n_cells = ns;
+  st.n_faces = (int64_t)nf;
+  st.n_edges = (int64_t)ne;
+  st.n_rpv = (int64_t)nq;
+  st.n_glue = (int64_t)hc[C_NODES];
+  return true;
+}
+
+static std::vector<ShapeDesc> shape_table(const rpd_mesh* const* meshes, const int* nsites, int nsh, long long* ns_tot,
+                                          long long* nt_tot) {
+  std::vector<ShapeDesc> hd(nsh);
+  *ns_tot = 0;
+  *nt_tot = 0;
+  for (int k = 0; k < nsh; ++k) {
+    const rpd_mesh* m = meshes[k];
+    ShapeDesc& d = hd[k];
+    d.tp = m->tp.as<float4>();
+    d.tn = m->tn.as<int>();
+    d.nu = m->nu.as<unsigned>();
+    d.blk = m->blk.as<int>();
+    d.nt = m->nt;
+    d.nblk = m->nblk;
+    d.L = m->L;
+    d.site_off = (int)*ns_tot;
+    d.ns = nsites[k];
+    d.tet_off = *nt_tot;
+    *ns_tot += nsites[k];
+    *nt_tot += m->nt;
+  }
+  if (*ns_tot >= (1 << 21)) throw Failure{RPD_E_INVALID, "more than 2^21 - 1 sites in one call"};
+  if (*nt_tot >= (1ll << 31)) throw Failure{RPD_E_INVALID, "more than 2^31 - 1 tets in one call"};
+  return hd;
+}
+
+// (shape, block) work items, heaviest first (estimated cost: block tets x shape sites, the box filter dominates
+// for large site counts); blocks of one shape stay in Morton order
+static std::vector<int2> work_items(const std::vector<ShapeDesc>& hd) {
+  const int nsh = (int)hd.size();
+  std::vector<int2> items;
+  std::vector<int> order(nsh);
+  std::iota(order.begin(), order.end(), 0);
+  std::stable_sort(order.begin(), order.end(), [&](int x, int y) {
+    double cx = (double)hd[x].ns * hd[x].nt / std::max(1, hd[x].nblk),
+           cy = (double)hd[y].ns * hd[y].nt / std::max(1, hd[y].nblk);
+    return cx > cy;
+  });
+  for (int k : order)
+    for (int b = 0; b < hd[k].nblk; ++b) items.push_back(make_int2(k, b));
+  return items;
+}
+
+static void upload_sites(DeviceState& D, const rpd_sites* sites, const std::vector<ShapeDesc>& hd, bool dev,
+                         hipStream_t s) {
+  std::vector<DBuf> raws;
+  for (size_t k = 0; k < hd.size(); ++k) {
+    const rpd_sites* sp = &sites[k];
+    const int n = sp->n_sites;
+    const float *sx = sp->sx, *sy = sp->sy, *sz = sp->sz, *sr = sp->sr;
+    if (!dev) {
+      raws.emplace_back(sizeof(float) * 4 * (size_t)n);
+      float* r = raws.back().as<float>();
+      hip_check(hipMemcpyAsync(r, sp->sx, sizeof(float) * n, hipMemcpyHostToDevice, s), "upload");
+      hip_check(hipMemcpyAsync(r + n, sp->sy, sizeof(float) * n, hipMemcpyHostToDevice, s), "upload");
+      hip_check(hipMemcpyAsync(r + 2 * (size_t)n, sp->sz, sizeof(float) * n, hipMemcpyHostToDevice, s), "upload");
+      hip_check(hipMemcpyAsync(r + 3 * (size_t)n, sp->sr, sizeof(float) * n, hipMemcpyHostToDevice, s), "upload");
+      sx = r;
+      sy = r + n;
+      sz = r + 2 * (size_t)n;
+      sr = r + 3 * (size_t)n;
+    }
+    hip_check(launch_validate_sites(sx, sy, sz, sr, n, D.site.as<float4>() + hd[k].site_off, D.status.as<int>(), s),
+              "validate sites");
+  }
+  if (!dev) hip_check(hipStreamSynchronize(s), "synchronize");  // the staging buffers are released next
+}
+
+// All shapes of one call, one attempt. Returns false if a table ran out of room (caller retries larger).
+static bool run_batch(const rpd_mesh* const* meshes, const rpd_sites* sites, int nsh, const rpd_opts& o,
+                      hipStream_t s, int scale, std::vector<ShapeOut>& outs, rpd_stats& st) {
+  const bool dev = (o.flags & RPD_DEVICE_PTRS) != 0;
+  std::vector<int> nsites(nsh);
+  for (int k = 0; k < nsh; ++k) nsites[k] = sites[k].n_sites;
+  long long ns_tot = 0, nt_tot = 0;
+  std::vector<ShapeDesc> hd = shape_table(meshes, nsites.data(), nsh, &ns_tot, &nt_tot);
+  std::vector<int2> items = work_items(hd);
+  DBuf dshapes(sizeof(ShapeDesc) * nsh), ditems(sizeof(int2) * std::max<size_t>(items.size(), 1));
+  hip_check(hipMemcpyAsync(dshapes.p, hd.data(), sizeof(ShapeDesc) * nsh, hipMemcpyHostToDevice, s), "upload");
+  if (!items.empty())
+    hip_check(hipMemcpyAsync(ditems.p, items.data(), sizeof(int2) * items.size(), hipMemcpyHostToDevice, s), "upload");
+  DeviceState D;
+  D.alloc(nsh, (int)ns_tot, nt_tot, scale, (o.flags & RPD_KEEP_PIECES) != 0, false);
+  D.clear(s);
+  upload_sites(D, sites, hd, dev, s);
+  const int kmax = o.clip_budget > 0 ? std::min(o.clip_budget, KMAX) : KMAX;
+  ShapeArgs a = D.args(dshapes.as<ShapeDesc>(), ditems.as<int2>(), (int)items.size(), o.flags, kmax, +1);
+  Timing tm((o.flags & RPD_TIMING) != 0);
+  tm.mark(0, s);
+  hip_check(launch_clip_fast(a, o.precision, o.block, s), "clip kernel");
+  tm.mark(1, s);
+  hip_check(launch_clip_slow(a, slow_scratch(), SLOW_WAVES, s), "deferred clip kernel");
+  tm.mark(2, s);
+  D.components(a, s);
+  if (!collect(D, hd, dshapes.as<ShapeDesc>(), meshes, s, tm, outs, st)) return false;
+  st.ms_clip = tm.ms(0, 1);
+  st.ms_deferred = tm.ms(1, 2);
+  st.ms_reduce = tm.ms(2, 3);
+  st.ms_total = tm.ms(0, 4);
   return true;
 }
 
@@ -413,15 +614,15 @@ rpd_status rpd_build(const rpd_mesh* const* meshes, const rpd_sites* sites, int3
   try {
     r->shapes.resize(n_shapes);
     for (int k = 0; k < n_shapes; ++k) {
-      const rpd_mesh* m = meshes[k];
       const rpd_sites* sp = &sites[k];
-      if (!m) throw Failure{RPD_E_INVALID, "null mesh"};
+      if (!meshes[k]) throw Failure{RPD_E_INVALID, "null mesh"};
       if (sp->n_sites <= 0 || sp->n_sites >= (1 << 21) || !sp->sx || !sp->sy || !sp->sz || !sp->sr)
         throw Failure{RPD_E_INVALID, "site count must be in [1, 2^21) with non-null arrays"};
-      bool done = false;
-      for (int scale = 1; scale <= 16 && !done; scale *= 2) done = rpd::run_shape(m, sp, o, s, scale, r->shapes[k], r->stats);
-      if (!done) throw Failure{RPD_E_NOMEM, "result tables kept overflowing"};
     }
+    bool done = false;
+    for (int scale = 1; scale <= 16 && !done; scale *= 2)
+      done = rpd::run_batch(meshes, sites, n_shapes, o, s, scale, r->shapes, r->stats);
+    if (!done) throw Failure{RPD_E_NOMEM, "result tables kept overflowing"};
   } catch (...) {
     delete r;
     throw;

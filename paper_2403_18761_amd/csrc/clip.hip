@@ -9,6 +9,8 @@
 // deferred to the large-capacity kernel, which recomputes them with FP64 constructions and exact predicates.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+
 #include "rpd_device.h"
 #include "rpd_launch.h"
 
@@ -30,17 +32,32 @@ __device__ inline long long wv_of(typename Topo::W w, const unsigned* nu, long l
   return w_vertex(Topo::plane(w, 0), Topo::plane(w, 1), Topo::plane(w, 2), nu, L);
 }
 
-__device__ inline void add_fixed(long long* dst, double v) {
-  atomicAdd((unsigned long long*)dst, (unsigned long long)(long long)llrint(v * 72057594037927936.0));  // 2^56
+__device__ inline void add_fixed(long long* dst, double v, int sign) {  // fixed point 2^-56, exactly invertible
+  long long q = llrint(v * 72057594037927936.0);
+  atomicAdd((unsigned long long*)dst, (unsigned long long)(sign * q));
+}
+
+// One element piece (element, tet) is emitted exactly once per pass: adding sets its gluing bits, removing clears
+// them; the count tells whether the piece is live.
+__device__ inline void node_emit(const ShapeArgs& a, unsigned long long key, int glue) {
+  int ns = ht_insert(a.N, key, a.status);
+  if (ns < 0) return;
+  if (a.sign > 0) {
+    if (glue) atomicOr(&a.node_glue[ns], glue);
+  } else {
+    atomicAnd(&a.node_glue[ns], 0);
+  }
+  atomicAdd(&a.node_cnt[ns], a.sign);
 }
 
 template <typename T, typename Topo, typename Mask, int VCAP, bool EXACT>
-__device__ void emit_piece(Clipper<T, Topo, Mask, VCAP, EXACT>& c, int t, const ShapeArgs& a) {
+__device__ void emit_piece(Clipper<T, Topo, Mask, VCAP, EXACT>& c, const ShapeDesc& sd, int tl, const ShapeArgs& a) {
   typedef typename Topo::W W;
-  const int i = c.env.site_i;
-  const unsigned* nu = a.nu + 14 * (size_t)t;
-  const long long L = a.L;
-  const int* tn = a.tn + 4 * (size_t)t;
+  const int i = c.env.site_i;  // batch-global site id
+  const unsigned* nu = sd.nu + 14 * (size_t)tl;
+  const long long L = sd.L;
+  const int* tn = sd.tn + 4 * (size_t)tl;
+  const int t = (int)(sd.tet_off + tl);  // batch-global tet id (node keys, piece records)
   int* status = a.status;
 
   // ---- vertex pass: vertex and edge weights, face references, apex, RPVs
@@ -67,9 +84,13 @@ __device__ void emit_piece(Clipper<T, Topo, Mask, VCAP, EXACT>& c, int t, const 
       int s0 = c.env.plane_site(p0), s1 = c.env.plane_site(p1), s2 = c.env.plane_site(p2);
       if (s0 > i && s1 > i && s2 > i) {  // the RPV is recorded once, from its smallest site
         int lo = min(s0, min(s1, s2)), hi = max(s0, max(s1, s2)), mid = s0 + s1 + s2 - lo - hi;
-        unsigned long long idx = atomicAdd(&a.counters[C_RPV], 1ull);
-        if (idx < (unsigned long long)a.rpv_cap) a.rpv[idx] = make_int4(i, lo, mid, hi);
-        else atomicOr(status, ST_TABLE_FULL);
+        unsigned long long ekey = ((unsigned long long)i << 42) | ((unsigned long long)lo << 21) | (unsigned)mid;
+        int es = ht_insert(a.E, ekey, status);
+        if (es >= 0) {
+          int qs = ht_insert(a.Q, ((unsigned long long)es << 21) | (unsigned)hi, status);
+          if (qs >= 0) atomicAdd(&a.rpv_cnt[qs], a.sign);
+        }
+        atomicAdd(&a.counters[C_RPV], 1ull);
       }
     }
   }
@@ -125,10 +146,10 @@ __device__ void emit_piece(Clipper<T, Topo, Mask, VCAP, EXACT>& c, int t, const 
             unsigned long long key = ((unsigned long long)i << 42) | ((unsigned long long)j << 21) | (unsigned)k;
             int es = ht_insert(a.E, key, status);
             if (es >= 0) {
-              atomicAdd((unsigned long long*)&a.edge_chi[es], (unsigned long long)ev);
-              int ns = ht_insert(a.N, node_key(3, es, t), status);
+              atomicAdd((unsigned long long*)&a.edge_chi[es], (unsigned long long)(a.sign * ev));
+              atomicAdd(&a.edge_np[es], a.sign);
               int g = ((t1 < 4 && tn[t1] >= 0) ? (1 << t1) : 0) | ((t2 < 4 && tn[t2] >= 0) ? (1 << t2) : 0);
-              if (ns >= 0 && g) atomicOr(&a.node_glue[ns], g);
+              node_emit(a, node_key(3, es, t), g);
             }
           }
         }
@@ -167,29 +188,26 @@ __device__ void emit_piece(Clipper<T, Topo, Mask, VCAP, EXACT>& c, int t, const 
       unsigned long long key = ((unsigned long long)i << 32) | (unsigned)sp;
       int fs = ht_insert(a.F, key, status);
       if (fs >= 0) {
-        atomicAdd((unsigned long long*)&a.face_chi[fs], (unsigned long long)fvl);
-        int ns = ht_insert(a.N, node_key(2, fs, t), status);
-        if (ns >= 0 && fglue) atomicOr(&a.node_glue[ns], fglue);
+        atomicAdd((unsigned long long*)&a.face_chi[fs], (unsigned long long)(a.sign * fvl));
+        atomicAdd(&a.face_np[fs], a.sign);
+        node_emit(a, node_key(2, fs, t), fglue);
       }
     }
   }
   // ---- cell contributions
   long long chi = sv - se + sf - L;
-  atomicAdd((unsigned long long*)&a.cell_chi[i], (unsigned long long)chi);
-  atomicAdd(&a.cell_np[i], 1);
-  {
-    int ns = ht_insert(a.N, node_key(1, i, t), status);
-    if (ns >= 0 && cell_glue) atomicOr(&a.node_glue[ns], cell_glue);
-  }
+  atomicAdd((unsigned long long*)&a.cell_chi[i], (unsigned long long)(a.sign * chi));
+  atomicAdd(&a.cell_np[i], a.sign);
+  node_emit(a, node_key(1, i, t), cell_glue);
   // moments were accumulated with 4x the centroid sum; shift to absolute coordinates
   float4 o = c.env.tv[0];
   double dvol = (double)vol;
   double dmx = (double)mx * 0.25 + dvol * o.x, dmy = (double)my * 0.25 + dvol * o.y,
          dmz = (double)mz * 0.25 + dvol * o.z;
-  add_fixed(&a.cell_geo[4 * (size_t)i + 0], dvol);
-  add_fixed(&a.cell_geo[4 * (size_t)i + 1], dmx);
-  add_fixed(&a.cell_geo[4 * (size_t)i + 2], dmy);
-  add_fixed(&a.cell_geo[4 * (size_t)i + 3], dmz);
+  add_fixed(&a.cell_geo[4 * (size_t)i + 0], dvol, a.sign);
+  add_fixed(&a.cell_geo[4 * (size_t)i + 1], dmx, a.sign);
+  add_fixed(&a.cell_geo[4 * (size_t)i + 2], dmy, a.sign);
+  add_fixed(&a.cell_geo[4 * (size_t)i + 3], dmz, a.sign);
   if (a.flags & RPD_KEEP_PIECES) {
     unsigned long long idx = atomicAdd(&a.counters[C_PIECES], 1ull);
     if (idx < (unsigned long long)a.piece_cap) {
@@ -272,32 +290,36 @@ __device__ inline void g4(const float4* tv, const float4& s, double* g) {
 // The list must be sorted (only_count: the list is unsorted and over budget; it is filtered but stays unsorted).
 __device__ int refine_candidates(const float4* tv, const float4* sites, const int* sid, unsigned char* cand,
                                  double* key, int m, bool unsorted) {
-  const int R = min(m, 3);
-  double gr[3][4];
-  int ref[3];
-  if (unsorted) {  // pick the three smallest keys as references
-    int best[3] = {-1, -1, -1};
-    for (int c = 0; c < m; ++c)
-      for (int r = 0; r < 3; ++r)
-        if (best[r] < 0 || key[c] < key[best[r]]) {
-          for (int q = 2; q > r; --q) best[q] = best[q - 1];
-          best[r] = c;
-          break;
-        }
-    for (int r = 0; r < R; ++r) ref[r] = best[r];
-  } else {
-    for (int r = 0; r < R; ++r) ref[r] = r;
+  int r0 = 0, r1 = 1, r2 = 2;  // indices of the reference candidates
+  if (unsorted) {              // the three smallest keys (scalar insertion, no indexed arrays)
+    r0 = r1 = r2 = -1;
+    for (int c = 0; c < m; ++c) {
+      const double k = key[c];
+      if (r0 < 0 || k < key[r0]) {
+        r2 = r1;
+        r1 = r0;
+        r0 = c;
+      } else if (r1 < 0 || k < key[r1]) {
+        r2 = r1;
+        r1 = c;
+      } else if (r2 < 0 || k < key[r2]) {
+        r2 = c;
+      }
+    }
   }
-  for (int r = 0; r < R; ++r) g4(tv, sites[cand[ref[r]]], gr[r]);
+  if (m < 3) r2 = -1;
+  if (m < 2) r1 = -1;
+  double g0[4], g1[4], g2[4];
+  g4(tv, sites[cand[r0]], g0);
+  if (r1 >= 0) g4(tv, sites[cand[r1]], g1);
+  if (r2 >= 0) g4(tv, sites[cand[r2]], g2);
   int w = 0;
   for (int c = 0; c < m; ++c) {
     double g[4];
     g4(tv, sites[cand[c]], g);
-    bool dom = false;
-    for (int r = 0; r < R && !dom; ++r) {
-      if (ref[r] == c) continue;
-      dom = g[0] > gr[r][0] && g[1] > gr[r][1] && g[2] > gr[r][2] && g[3] > gr[r][3];
-    }
+    bool dom = (c != r0) && g[0] > g0[0] && g[1] > g0[1] && g[2] > g0[2] && g[3] > g0[3];
+    dom = dom || (r1 >= 0 && c != r1 && g[0] > g1[0] && g[1] > g1[1] && g[2] > g1[2] && g[3] > g1[3]);
+    dom = dom || (r2 >= 0 && c != r2 && g[0] > g2[0] && g[1] > g2[1] && g[2] > g2[2] && g[3] > g2[3]);
     if (!dom) {
       cand[w] = cand[c];
       key[w] = key[c];
@@ -316,27 +338,41 @@ __global__ __launch_bounds__(NT) void k_clip_fast(ShapeArgs a) {
   __shared__ float4 s_site[SLMAX];
   __shared__ int s_sid[SLMAX];
   __shared__ unsigned char s_cand[TB][KMAX];
-  __shared__ double s_key[TB][KMAX];
+  // the candidates' sort keys are dead before the clipping phase starts: they share storage with the polytopes
+  constexpr size_t XYZ_BYTES = sizeof(typename Coord4<T>::type) * VMAX * NT;
+  constexpr size_t KEY_BYTES = sizeof(double) * TB * KMAX;
+  __shared__ __attribute__((aligned(16))) unsigned char s_share[XYZ_BYTES > KEY_BYTES ? XYZ_BYTES : KEY_BYTES];
+  double(*s_key)[KMAX] = reinterpret_cast<double(*)[KMAX]>(s_share);
+  typename Coord4<T>::type* s_xyz = reinterpret_cast<typename Coord4<T>::type*>(s_share);
   __shared__ int s_m[TB];
   __shared__ int s_off[TB + 1];
   __shared__ float s_box[6];
   __shared__ double s_red[NT / 64];
   __shared__ int s_nsl;
   __shared__ unsigned long long s_cnt[4];
-  __shared__ typename Coord4<T>::type s_xyz[VMAX * NT];
   __shared__ unsigned s_topo[VMAX * NT];
   __shared__ unsigned char s_tab[32 * NT];
 
   const int tid = threadIdx.x;
   const int lane = tid & 63, wid = tid >> 6;
-  const int t0 = a.blk[blockIdx.x];
-  const int ntb = a.blk[blockIdx.x + 1] - t0;
+  for (int k = tid; k < 32 * NT; k += NT) s_tab[k] = 0;
+  unsigned long long n_pairs = 0, n64 = 0, n_cand = 0;
+  // One workgroup per (shape, block) item; items are ordered heaviest first and the hardware dispatcher hands
+  // them to compute units in that order as they free up, which is the work queue. (A persistent loop that pulls
+  // items from an atomic counter computes the same thing but costs about 100 more VGPRs per thread here.)
+  do {
+  const int item = blockIdx.x;
+  if (item >= (a.nitems_dev ? *a.nitems_dev : a.nitems)) break;
+  const int2 wi = a.items[item];
+  const ShapeDesc sd = a.shapes[__builtin_amdgcn_readfirstlane(wi.x)];
+  const int t0 = sd.blk[wi.y];
+  const int ntb = sd.blk[wi.y + 1] - t0;
 
   // ---- 1. load the tets, their face planes and the bounding box
   float lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
   if (tid < TB) {
     if (tid < ntb) {
-      const float4* tp = a.tp + 4 * (size_t)(t0 + tid);
+      const float4* tp = sd.tp + 4 * (size_t)(t0 + tid);
       for (int v = 0; v < 4; ++v) {
         float4 p = tp[v];
         s_tv[tid][v] = p;
@@ -361,9 +397,7 @@ __global__ __launch_bounds__(NT) void k_clip_fast(ShapeArgs a) {
       }
     }
   }
-  if (tid < 4) s_cnt[tid] = 0;
   if (tid == 0) s_nsl = 0;
-  for (int k = tid; k < 32 * NT; k += NT) s_tab[k] = 0;
   __syncthreads();
 
   // ---- 2. sites that can own a point of the box: min over the box of g_j <= min over j of max over the box
@@ -371,8 +405,9 @@ __global__ __launch_bounds__(NT) void k_clip_fast(ShapeArgs a) {
   const double bx = s_box[0], by = s_box[1], bz = s_box[2];
   const double ex = (double)s_box[3] - bx, ey = (double)s_box[4] - by, ez = (double)s_box[5] - bz;
   double umin = INFINITY;
-  for (int j = tid; j < a.ns; j += NT) {
-    float4 s = a.site[j];
+  const float4* ssite = a.site + sd.site_off;
+  for (int j = tid; j < sd.ns; j += NT) {
+    float4 s = ssite[j];
     double ax_ = (double)s.x - bx, ay_ = (double)s.y - by, az_ = (double)s.z - bz;
     double D = ax_ * ax_ + ay_ * ay_ + az_ * az_ - (double)s.w * s.w;
     double gmax = D + fmax(0.0, -2.0 * ex * ax_) + fmax(0.0, -2.0 * ey * ay_) + fmax(0.0, -2.0 * ez * az_);
@@ -383,8 +418,8 @@ __global__ __launch_bounds__(NT) void k_clip_fast(ShapeArgs a) {
   __syncthreads();
   double UB = s_red[0];
   for (int w = 1; w < NT / 64; ++w) UB = fmin(UB, s_red[w]);
-  for (int j = tid; j < a.ns; j += NT) {
-    float4 s = a.site[j];
+  for (int j = tid; j < sd.ns; j += NT) {
+    float4 s = ssite[j];
     double ax_ = (double)s.x - bx, ay_ = (double)s.y - by, az_ = (double)s.z - bz;
     double D = ax_ * ax_ + ay_ * ay_ + az_ * az_ - (double)s.w * s.w;
     double gmin = D + fmin(0.0, -2.0 * ex * ax_) + fmin(0.0, -2.0 * ey * ay_) + fmin(0.0, -2.0 * ez * az_);
@@ -392,7 +427,7 @@ __global__ __launch_bounds__(NT) void k_clip_fast(ShapeArgs a) {
       int q = atomicAdd(&s_nsl, 1);
       if (q < SLMAX) {
         s_site[q] = s;
-        s_sid[q] = j;
+        s_sid[q] = sd.site_off + j;
       }
     }
   }
@@ -424,6 +459,7 @@ __global__ __launch_bounds__(NT) void k_clip_fast(ShapeArgs a) {
         U = fmin(U, gmx);
       }
       for (int off = 1; off < TPT; off <<= 1) U = fmin(U, __shfl_xor(U, off));
+      if (a.tet_U && a.sign > 0 && h == 0) a.tet_U[sd.tet_off + t0 + lt] = U;
       for (int q = h; q < nsl; q += TPT) {
         float4 s = s_site[q];
         double ax_ = (double)s.x - o.x, ay_ = (double)s.y - o.y, az_ = (double)s.z - o.z;
@@ -451,7 +487,7 @@ __global__ __launch_bounds__(NT) void k_clip_fast(ShapeArgs a) {
     if (block_overflow || m > a.kmax) {
       s_m[tid] = -1;
       unsigned long long idx = atomicAdd(&a.counters[C_DEFER_ITEMS], 1ull);
-      if (idx < (unsigned long long)a.deferred_cap) a.deferred[idx] = make_int2(t0 + tid, -1);
+      if (idx < (unsigned long long)a.deferred_cap) a.deferred[idx] = make_int4(wi.x, t0 + tid, -1, 0);
       else atomicOr(a.status, ST_TABLE_FULL);
     } else {
       for (int x = 1; x < m; ++x) {
@@ -483,7 +519,7 @@ __global__ __launch_bounds__(NT) void k_clip_fast(ShapeArgs a) {
 
   // ---- 4. one thread per (tet, candidate) piece
   const int npairs = s_off[TB];
-  unsigned long long n_pairs = 0, n64 = 0, nex = 0;
+  n_cand += npairs;
   for (int p = tid; p < npairs; p += NT) {
     int lo_ = 0, hi_ = TB - 1;  // last lt with s_off[lt] <= p
     while (lo_ < hi_) {
@@ -518,55 +554,62 @@ __global__ __launch_bounds__(NT) void k_clip_fast(ShapeArgs a) {
     n64 += cl.n64;
     if (r == CLIP_OK) {
       ++n_pairs;
-      emit_piece(cl, t0 + lt, a);
+      emit_piece(cl, sd, t0 + lt, a);
     } else if (r == CLIP_DEFER) {
       unsigned long long idx = atomicAdd(&a.counters[C_DEFER_ITEMS], 1ull);
-      if (idx < (unsigned long long)a.deferred_cap) a.deferred[idx] = make_int2(t0 + lt, cl.env.site_i);
+      if (idx < (unsigned long long)a.deferred_cap) a.deferred[idx] = make_int4(wi.x, t0 + lt, cl.env.site_i, 0);
       else atomicOr(a.status, ST_TABLE_FULL);
     }
   }
+  } while (false);
+  if (tid < 4) s_cnt[tid] = 0;
+  __syncthreads();
   atomicAdd(&s_cnt[0], n_pairs);
   atomicAdd(&s_cnt[1], n64);
   __syncthreads();
   if (tid == 0) {
     atomicAdd(&a.counters[C_PAIRS], s_cnt[0]);
     atomicAdd(&a.counters[C_FP64], s_cnt[1]);
-    atomicAdd(&a.counters[C_CAND], (unsigned long long)npairs);
+    atomicAdd(&a.counters[C_CAND], n_cand);
   }
 }
 
 // ---------------------------------------------------------------------------------------------------------------
 // large-capacity kernel: one thread per deferred item, FP64 constructions, exact predicates, global scratch
 // ---------------------------------------------------------------------------------------------------------------
-struct SlowScratch {
+struct SlowScratch {  // per wave: the candidate list; per lane: one piece's polytope and plane table
   static constexpr size_t cand_bytes = SLOW_KMAX * sizeof(int);
   static constexpr size_t key_bytes = SLOW_KMAX * sizeof(double);
+  static constexpr size_t wave_bytes = cand_bytes + key_bytes;
   static constexpr size_t xyz_bytes = SLOW_VMAX * sizeof(Coord4<double>::type);
   static constexpr size_t topo_bytes = SLOW_VMAX * sizeof(unsigned long long);
   static constexpr size_t tab_bytes = (SLOW_PMAX + 15) / 16 * 16;
-  static constexpr size_t bytes = cand_bytes + key_bytes + xyz_bytes + topo_bytes + tab_bytes;
+  static constexpr size_t lane_bytes = xyz_bytes + topo_bytes + tab_bytes;
+  static constexpr size_t bytes = wave_bytes + 64 * lane_bytes;  // one wave
 };
 
+// One wavefront per deferred item: the lanes split the scan over all of the shape's sites (candidates are
+// compacted in ascending site order by ballots), lane 0 sorts them, then every lane clips its own pieces.
 __global__ __launch_bounds__(64) void k_clip_slow(ShapeArgs a, unsigned char* scratch) {
   const int n_items = (int)min(a.counters[C_DEFER_ITEMS], (unsigned long long)a.deferred_cap);
-  const int gt = blockIdx.x * blockDim.x + threadIdx.x;
-  if (gt >= n_items) return;
-  const int gs = gridDim.x * blockDim.x;
-  unsigned char* base = scratch + (size_t)gt * SlowScratch::bytes;
-  int* cand = (int*)base;
-  double* key = (double*)(base + SlowScratch::cand_bytes);
-  Coord4<double>::type* xyz = (Coord4<double>::type*)(base + SlowScratch::cand_bytes + SlowScratch::key_bytes);
-  unsigned long long* topo =
-      (unsigned long long*)(base + SlowScratch::cand_bytes + SlowScratch::key_bytes + SlowScratch::xyz_bytes);
-  unsigned char* tab = base + SlowScratch::cand_bytes + SlowScratch::key_bytes + SlowScratch::xyz_bytes +
-                       SlowScratch::topo_bytes;
+  const int lane = threadIdx.x;
+  unsigned char* wbase = scratch + (size_t)blockIdx.x * SlowScratch::bytes;
+  int* cand = (int*)wbase;
+  double* key = (double*)(wbase + SlowScratch::cand_bytes);
+  unsigned char* lbase = wbase + SlowScratch::wave_bytes + (size_t)lane * SlowScratch::lane_bytes;
+  Coord4<double>::type* xyz = (Coord4<double>::type*)lbase;
+  unsigned long long* topo = (unsigned long long*)(lbase + SlowScratch::xyz_bytes);
+  unsigned char* tab = lbase + SlowScratch::xyz_bytes + SlowScratch::topo_bytes;
   for (int k = 0; k < SLOW_PMAX; ++k) tab[k] = 0;
-  unsigned long long n_pairs = 0, n64 = 0, nex = 0, ncand = 0;
-  for (int it = gt; it < n_items; it += gs) {
-    const int t = a.deferred[it].x;
-    const int want = a.deferred[it].y;
+  unsigned long long n_pairs = 0, n64 = 0, nex = 0;
+  for (int it = blockIdx.x; it < n_items; it += gridDim.x) {
+    const int4 di = a.deferred[it];
+    const ShapeDesc sd = a.shapes[__builtin_amdgcn_readfirstlane(di.x)];
+    const int t = di.y;
+    const int want = di.z;
+    const float4* ssite = a.site + sd.site_off;
     float4 tv[4];
-    for (int v = 0; v < 4; ++v) tv[v] = a.tp[4 * (size_t)t + v];
+    for (int v = 0; v < 4; ++v) tv[v] = sd.tp[4 * (size_t)t + v];
     const float4 o = tv[0];
     double y[3][3];
     for (int v = 1; v < 4; ++v) {
@@ -576,43 +619,61 @@ __global__ __launch_bounds__(64) void k_clip_slow(ShapeArgs a, unsigned char* sc
     }
     const double ycx = (y[0][0] + y[1][0] + y[2][0]) * 0.25, ycy = (y[0][1] + y[1][1] + y[2][1]) * 0.25,
                  ycz = (y[0][2] + y[1][2] + y[2][2]) * 0.25;
-    // candidates among ALL sites
+    // candidates among ALL sites of the shape (same exact test as the fast kernel)
     double U = INFINITY;
-    for (int j = 0; j < a.ns; ++j) {
-      float4 s = a.site[j];
+    for (int j = lane; j < sd.ns; j += 64) {
+      float4 s = ssite[j];
       double ax_ = (double)s.x - o.x, ay_ = (double)s.y - o.y, az_ = (double)s.z - o.z;
       double D = ax_ * ax_ + ay_ * ay_ + az_ * az_ - (double)s.w * s.w;
       double gmx = D;
       for (int v = 0; v < 3; ++v) gmx = fmax(gmx, D - 2.0 * (y[v][0] * ax_ + y[v][1] * ay_ + y[v][2] * az_));
       U = fmin(U, gmx);
     }
+    for (int off = 32; off > 0; off >>= 1) U = fmin(U, __shfl_xor(U, off));
+    if (a.tet_U && a.sign > 0 && lane == 0) a.tet_U[sd.tet_off + t] = U;
     int m = 0;
-    for (int j = 0; j < a.ns; ++j) {
-      float4 s = a.site[j];
-      double ax_ = (double)s.x - o.x, ay_ = (double)s.y - o.y, az_ = (double)s.z - o.z;
-      double D = ax_ * ax_ + ay_ * ay_ + az_ * az_ - (double)s.w * s.w;
-      double gmn = D;
-      for (int v = 0; v < 3; ++v) gmn = fmin(gmn, D - 2.0 * (y[v][0] * ax_ + y[v][1] * ay_ + y[v][2] * az_));
-      if (gmn <= U) {
-        if (m >= SLOW_KMAX) {
-          atomicOr(a.status, ST_SLOW_CAPACITY);
-          m = -1;
-          break;
+    for (int base = 0; base < sd.ns; base += 64) {
+      const int j = base + lane;
+      bool take = false;
+      double kk = 0.0;
+      if (j < sd.ns) {
+        float4 s = ssite[j];
+        double ax_ = (double)s.x - o.x, ay_ = (double)s.y - o.y, az_ = (double)s.z - o.z;
+        double D = ax_ * ax_ + ay_ * ay_ + az_ * az_ - (double)s.w * s.w;
+        double gmn = D;
+        for (int v = 0; v < 3; ++v) gmn = fmin(gmn, D - 2.0 * (y[v][0] * ax_ + y[v][1] * ay_ + y[v][2] * az_));
+        take = gmn <= U;
+        kk = D - 2.0 * (ycx * ax_ + ycy * ay_ + ycz * az_);
+      }
+      unsigned long long mask = __ballot(take);
+      int pos = m + __popcll(mask & ((1ull << lane) - 1ull));
+      if (take && pos < SLOW_KMAX) {
+        cand[pos] = sd.site_off + j;
+        key[pos] = kk;
+      }
+      m += __popcll(mask);
+    }
+    if (m > SLOW_KMAX) {
+      if (lane == 0) atomicOr(a.status, ST_SLOW_CAPACITY);
+      continue;
+    }
+    __syncthreads();
+    if (lane == 0) {  // ascending key; the ids ascend already, so the stable insertion keeps ties by id
+      for (int x = 1; x < m; ++x) {
+        double kx = key[x];
+        int cx = cand[x];
+        int q = x - 1;
+        while (q >= 0 && key[q] > kx) {
+          key[q + 1] = key[q];
+          cand[q + 1] = cand[q];
+          --q;
         }
-        double kk = D - 2.0 * (ycx * ax_ + ycy * ay_ + ycz * az_);
-        int x = m++;
-        while (x > 0 && key[x - 1] > kk) {  // j ascends, so ties keep the smaller id first
-          key[x] = key[x - 1];
-          cand[x] = cand[x - 1];
-          --x;
-        }
-        key[x] = kk;
-        cand[x] = j;
+        key[q + 1] = kx;
+        cand[q + 1] = cx;
       }
     }
-    if (m < 0) continue;
-    ncand += m;
-    for (int ci = 0; ci < m; ++ci) {
+    __syncthreads();
+    for (int ci = lane; ci < m; ci += 64) {
       if (want >= 0 && cand[ci] != want) continue;
       Clipper<double, Topo64, unsigned long long, SLOW_VMAX, true> cl;
       cl.st.c = xyz;
@@ -628,7 +689,7 @@ __global__ __launch_bounds__(64) void k_clip_slow(ShapeArgs a, unsigned char* sc
       cl.env.tv = tv;
       cl.env.faceT = nullptr;
       cl.env.sites = a.site;
-      cl.env.sid = nullptr;  // candidates hold site ids directly
+      cl.env.sid = nullptr;  // candidates hold batch-global site ids directly
       cl.env.cidx8 = nullptr;
       cl.env.cidx32 = cand;
       cl.env.ci = ci;
@@ -643,36 +704,43 @@ __global__ __launch_bounds__(64) void k_clip_slow(ShapeArgs a, unsigned char* sc
       }
       if (r == CLIP_OK) {
         ++n_pairs;
-        emit_piece(cl, t, a);
+        emit_piece(cl, sd, t, a);
       }
     }
+    __syncthreads();  // the candidate list is rewritten by the next item
   }
-  atomicAdd(&a.counters[C_PAIRS], n_pairs);
-  atomicAdd(&a.counters[C_FP64], n64);
-  atomicAdd(&a.counters[C_EXACT], nex);
+  for (int off = 32; off > 0; off >>= 1) {
+    n_pairs += __shfl_xor(n_pairs, off);
+    n64 += __shfl_xor(n64, off);
+    nex += __shfl_xor(nex, off);
+  }
+  if (lane == 0) {
+    if (n_pairs) atomicAdd(&a.counters[C_PAIRS], n_pairs);
+    if (n64) atomicAdd(&a.counters[C_FP64], n64);
+    if (nex) atomicAdd(&a.counters[C_EXACT], nex);
+  }
 }
 
 // ---------------------------------------------------------------------------------------------------------------
 // launchers
 // ---------------------------------------------------------------------------------------------------------------
-hipError_t launch_clip_fast(const ShapeArgs& a, int precision, int block, hipStream_t s) {
-  int nblocks = a.nblk;
-  if (nblocks == 0) return hipSuccess;
-  if (precision == RPD_FP64) {
-    hipLaunchKernelGGL((k_clip_fast<double, 64>), dim3(nblocks), dim3(64), 0, s, a);
-  } else if (block == 64) {
-    hipLaunchKernelGGL((k_clip_fast<float, 64>), dim3(nblocks), dim3(64), 0, s, a);
-  } else {
-    hipLaunchKernelGGL((k_clip_fast<float, 128>), dim3(nblocks), dim3(128), 0, s, a);
-  }
+template <typename T, int NT>
+static hipError_t launch_items(const ShapeArgs& a, hipStream_t s) {
+  hipLaunchKernelGGL((k_clip_fast<T, NT>), dim3(a.nitems), dim3(NT), 0, s, a);
   return hipGetLastError();
 }
 
-size_t slow_scratch_bytes(int threads) { return (size_t)threads * SlowScratch::bytes; }
+hipError_t launch_clip_fast(const ShapeArgs& a, int precision, int block, hipStream_t s) {
+  if (a.nitems == 0) return hipSuccess;
+  if (precision == RPD_FP64) return launch_items<double, 64>(a, s);
+  if (block == 64) return launch_items<float, 64>(a, s);
+  return launch_items<float, 128>(a, s);
+}
 
-hipError_t launch_clip_slow(const ShapeArgs& a, unsigned char* scratch, int threads, hipStream_t s) {
-  int nb = (threads + 63) / 64;
-  hipLaunchKernelGGL(k_clip_slow, dim3(nb), dim3(64), 0, s, a, scratch);
+size_t slow_scratch_bytes(int waves) { return (size_t)waves * SlowScratch::bytes; }
+
+hipError_t launch_clip_slow(const ShapeArgs& a, unsigned char* scratch, int waves, hipStream_t s) {
+  hipLaunchKernelGGL(k_clip_slow, dim3(waves), dim3(64), 0, s, a, scratch);
   return hipGetLastError();
 }
 

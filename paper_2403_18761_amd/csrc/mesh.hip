@@ -356,6 +356,7 @@ void mesh_prepare(rpd_mesh* m, const rpd_mesh_desc* d, uint32_t flags, hipStream
     }
     starts.push_back(nt);
     m->nblk = (int)starts.size() - 1;
+    m->hblk = starts;
     m->blk.alloc(sizeof(int) * starts.size());
     hip_check(hipMemcpyAsync(m->blk.p, starts.data(), sizeof(int) * starts.size(), hipMemcpyHostToDevice, s), "upload");
     hip_check(hipStreamSynchronize(s), "sync");

@@ -72,20 +72,22 @@ __global__ void k_glue(ShapeArgs a, int* parent) {
   const unsigned cap = a.N.mask + 1;
   for (unsigned s = blockIdx.x * blockDim.x + threadIdx.x; s < cap; s += gridDim.x * blockDim.x) {
     unsigned long long key = a.N.keys[s];
-    if (key == EMPTY_KEY) continue;
+    if (key == EMPTY_KEY || a.node_cnt[s] <= 0) continue;
     int g = a.node_glue[s];
     if (!g) continue;
-    int t = (int)(key & 0xffffffffull);
+    const long long gt = (long long)(key & 0xffffffffull);
+    const ShapeDesc& sd = a.shapes[shape_of_tet(a.shapes, a.nshapes, gt)];
+    const int t = (int)(gt - sd.tet_off);
     unsigned long long hi = key & ~0xffffffffull;
     for (int f = 0; f < 4; ++f) {
       if (!(g & (1 << f))) continue;
-      int t2 = a.tn[4 * (size_t)t + f];
+      int t2 = sd.tn[4 * (size_t)t + f];
       if (t2 < 0) continue;
       int f2 = -1;
       for (int q = 0; q < 4; ++q)
-        if (a.tn[4 * (size_t)t2 + q] == t) f2 = q;
-      int s2 = ht_find(a.N, hi | (unsigned)t2);
-      if (s2 < 0 || f2 < 0 || !(a.node_glue[s2] & (1 << f2))) {
+        if (sd.tn[4 * (size_t)t2 + q] == t) f2 = q;
+      int s2 = ht_find(a.N, hi | (unsigned)(sd.tet_off + t2));
+      if (s2 < 0 || f2 < 0 || a.node_cnt[s2] <= 0 || !(a.node_glue[s2] & (1 << f2))) {
         atomicOr(a.status, ST_INTERNAL);
         continue;
       }
@@ -99,7 +101,7 @@ __global__ void k_count_roots(ShapeArgs a, int* parent, int* cell_b0, int* face_
   unsigned long long nodes = 0;
   for (unsigned s = blockIdx.x * blockDim.x + threadIdx.x; s < cap; s += gridDim.x * blockDim.x) {
     unsigned long long key = a.N.keys[s];
-    if (key == EMPTY_KEY) continue;
+    if (key == EMPTY_KEY || a.node_cnt[s] <= 0) continue;
     ++nodes;
     if (uf_find(parent, (int)s) != (int)s) continue;
     int kind = (int)(key >> 62);
@@ -142,14 +144,44 @@ hipError_t launch_iota(int* v, int n, hipStream_t s) {
   return hipGetLastError();
 }
 
+// copy of a table's keys for sorting in which entries without live pieces become free slots
+__global__ void k_live_keys(const unsigned long long* keys, const int* np, unsigned cap, unsigned long long* out) {
+  for (unsigned q = blockIdx.x * blockDim.x + threadIdx.x; q < cap; q += gridDim.x * blockDim.x)
+    out[q] = np[q] > 0 ? keys[q] : EMPTY_KEY;
+}
+hipError_t launch_live_keys(const unsigned long long* keys, const int* np, unsigned cap, unsigned long long* out,
+                            hipStream_t s) {
+  hipLaunchKernelGGL(k_live_keys, dim3(grid_for(cap, 256)), dim3(256), 0, s, keys, np, cap, out);
+  return hipGetLastError();
+}
+
+// RPV quadruples (i, j, k, l) from the counted set: key = edge slot of (i, j, k) << 21 | l
+__global__ void k_rpv_decode(HashTab Q, const int* cnt, const unsigned long long* ekeys, int4* out) {
+  const unsigned cap = Q.mask + 1;
+  for (unsigned q = blockIdx.x * blockDim.x + threadIdx.x; q < cap; q += gridDim.x * blockDim.x) {
+    unsigned long long k = Q.keys[q];
+    if (k == EMPTY_KEY || cnt[q] <= 0) {
+      out[q] = make_int4(0x7fffffff, 0x7fffffff, 0x7fffffff, 0x7fffffff);
+      continue;
+    }
+    unsigned long long e = ekeys[k >> 21];
+    out[q] = make_int4((int)(e >> 42), (int)((e >> 21) & 0x1fffff), (int)(e & 0x1fffff), (int)(k & 0x1fffff));
+  }
+}
+hipError_t launch_rpv_decode(const HashTab& Q, const int* cnt, const unsigned long long* ekeys, int4* out,
+                             hipStream_t s) {
+  hipLaunchKernelGGL(k_rpv_decode, dim3(grid_for((size_t)Q.mask + 1, 256)), dim3(256), 0, s, Q, cnt, ekeys, out);
+  return hipGetLastError();
+}
+
 hipError_t sort_pairs_u64(void* tmp, size_t& tmp_bytes, const unsigned long long* kin, unsigned long long* kout,
                           const int* vin, int* vout, int n, hipStream_t s) {
   return rocprim::radix_sort_pairs(tmp, tmp_bytes, kin, kout, vin, vout, (size_t)n, 0, 64, s);
 }
 
 __global__ void k_finalize_faces(const unsigned long long* keys, const int* slots, int cap, const long long* chi_num,
-                                 const int* b0, long long L, int* out_keys, int* out_chi, int* out_b0, int* status,
-                                 unsigned long long* count) {
+                                 const int* b0, const ShapeDesc* shapes, int nshapes, int* out_keys, int* out_chi,
+                                 int* out_b0, int* status, unsigned long long* count) {
   unsigned long long used = 0;
   for (int q = blockIdx.x * blockDim.x + threadIdx.x; q < cap; q += gridDim.x * blockDim.x) {
     unsigned long long k = keys[q];
@@ -157,6 +189,7 @@ __global__ void k_finalize_faces(const unsigned long long* keys, const int* slot
     int s = slots[q];
     out_keys[2 * q] = (int)(k >> 32);
     out_keys[2 * q + 1] = (int)(k & 0xffffffffull);
+    const long long L = shapes[shape_of_site(shapes, nshapes, (int)(k >> 32))].L;
     long long c = chi_num[s];
     if (c % L != 0) atomicOr(status, ST_INTERNAL);
     out_chi[q] = (int)(c / L);
@@ -171,8 +204,8 @@ __global__ void k_finalize_faces(const unsigned long long* keys, const int* slot
   if (threadIdx.x == 0 && s_used) atomicAdd(count, s_used);
 }
 __global__ void k_finalize_edges(const unsigned long long* keys, const int* slots, int cap, const long long* chi_num,
-                                 const int* b0, long long L, int* out_keys, int* out_chi, int* out_b0, int* status,
-                                 unsigned long long* count) {
+                                 const int* b0, const ShapeDesc* shapes, int nshapes, int* out_keys, int* out_chi,
+                                 int* out_b0, int* status, unsigned long long* count) {
   unsigned long long used = 0;
   for (int q = blockIdx.x * blockDim.x + threadIdx.x; q < cap; q += gridDim.x * blockDim.x) {
     unsigned long long k = keys[q];
@@ -181,6 +214,7 @@ __global__ void k_finalize_edges(const unsigned long long* keys, const int* slot
     out_keys[3 * q] = (int)(k >> 42);
     out_keys[3 * q + 1] = (int)((k >> 21) & 0x1fffff);
     out_keys[3 * q + 2] = (int)(k & 0x1fffff);
+    const long long L = shapes[shape_of_site(shapes, nshapes, (int)(k >> 42))].L;
     long long c = chi_num[s];
     if (c % L != 0) atomicOr(status, ST_INTERNAL);
     out_chi[q] = (int)(c / L);
@@ -194,9 +228,11 @@ __global__ void k_finalize_edges(const unsigned long long* keys, const int* slot
   __syncthreads();
   if (threadIdx.x == 0 && s_used) atomicAdd(count, s_used);
 }
-__global__ void k_finalize_cells(int ns, const long long* chi_num, const long long* geo, const int* np, long long L,
-                                 int* out_chi, double* out_vol, double* out_cen, int* status) {
+__global__ void k_finalize_cells(int ns, const long long* chi_num, const long long* geo, const int* np,
+                                 const ShapeDesc* shapes, int nshapes, int* out_chi, double* out_vol, double* out_cen,
+                                 int* status) {
   for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < ns; i += gridDim.x * blockDim.x) {
+    const long long L = shapes[shape_of_site(shapes, nshapes, i)].L;
     long long c = chi_num[i];
     if (c % L != 0) atomicOr(status, ST_INTERNAL);
     out_chi[i] = (int)(c / L);
@@ -208,23 +244,24 @@ __global__ void k_finalize_cells(int ns, const long long* chi_num, const long lo
 }
 
 hipError_t launch_finalize_faces(const unsigned long long* keys, const int* slots, int cap, const long long* chi_num,
-                                 const int* b0, long long L, int* out_keys, int* out_chi, int* out_b0, int* status,
-                                 unsigned long long* count, hipStream_t s) {
-  hipLaunchKernelGGL(k_finalize_faces, dim3(grid_for(cap, 256)), dim3(256), 0, s, keys, slots, cap, chi_num, b0, L,
-                     out_keys, out_chi, out_b0, status, count);
+                                 const int* b0, const ShapeDesc* shapes, int nshapes, int* out_keys, int* out_chi,
+                                 int* out_b0, int* status, unsigned long long* count, hipStream_t s) {
+  hipLaunchKernelGGL(k_finalize_faces, dim3(grid_for(cap, 256)), dim3(256), 0, s, keys, slots, cap, chi_num, b0, shapes,
+                     nshapes, out_keys, out_chi, out_b0, status, count);
   return hipGetLastError();
 }
 hipError_t launch_finalize_edges(const unsigned long long* keys, const int* slots, int cap, const long long* chi_num,
-                                 const int* b0, long long L, int* out_keys, int* out_chi, int* out_b0, int* status,
-                                 unsigned long long* count, hipStream_t s) {
-  hipLaunchKernelGGL(k_finalize_edges, dim3(grid_for(cap, 256)), dim3(256), 0, s, keys, slots, cap, chi_num, b0, L,
-                     out_keys, out_chi, out_b0, status, count);
+                                 const int* b0, const ShapeDesc* shapes, int nshapes, int* out_keys, int* out_chi,
+                                 int* out_b0, int* status, unsigned long long* count, hipStream_t s) {
+  hipLaunchKernelGGL(k_finalize_edges, dim3(grid_for(cap, 256)), dim3(256), 0, s, keys, slots, cap, chi_num, b0, shapes,
+                     nshapes, out_keys, out_chi, out_b0, status, count);
   return hipGetLastError();
 }
-hipError_t launch_finalize_cells(int ns, const long long* chi_num, const long long* geo, const int* np, long long L,
-                                 int* out_chi, double* out_vol, double* out_cen, int* status, hipStream_t s) {
-  hipLaunchKernelGGL(k_finalize_cells, dim3(grid_for(ns, 256)), dim3(256), 0, s, ns, chi_num, geo, np, L, out_chi,
-                     out_vol, out_cen, status);
+hipError_t launch_finalize_cells(int ns, const long long* chi_num, const long long* geo, const int* np,
+                                 const ShapeDesc* shapes, int nshapes, int* out_chi, double* out_vol, double* out_cen,
+                                 int* status, hipStream_t s) {
+  hipLaunchKernelGGL(k_finalize_cells, dim3(grid_for(ns, 256)), dim3(256), 0, s, ns, chi_num, geo, np, shapes, nshapes,
+                     out_chi, out_vol, out_cen, status);
   return hipGetLastError();
 }
 

@@ -25,6 +25,7 @@ constexpr int ST_INVALID = 16;       // invalid site value (off grid, out of ran
 
 // counters (ShapeArgs::counters)
 enum { C_PAIRS = 0, C_CAND, C_FP64, C_EXACT, C_DEFER_ITEMS, C_GLUE, C_RPV, C_PIECES, C_NODES, NCOUNTERS };
+// C_RPV counts RPV emissions; the RPV list itself is the set of keys of ShapeArgs::Q with a positive count
 
 constexpr unsigned long long EMPTY_KEY = ~0ull;
 
@@ -41,38 +42,74 @@ struct PieceRec {
   long long chi;  // fractional cell contribution (numerator over L)
 };
 
-struct ShapeArgs {
-  // ---- mesh, internal (spatially sorted) tet order
-  int nt;
-  const int* blk;        // [nblk + 1] first tet of every workgroup block (spatially compact runs of <= TB tets)
-  int nblk;
-  const float4* tp;      // [4 nt] tet vertex coordinates (w unused)
-  const int* tn;         // [4 nt] neighbour tet across local face f (face f is opposite vertex f), -1 on the boundary
-  const unsigned* nu;    // [14 nt] weight numerators L/k: 4 vertices, 6 edges, 4 faces
+// One shape of a batch: its prepared mesh and its range of the batch's site array.
+struct ShapeDesc {
+  const float4* tp;    // [4 nt] tet vertex coordinates (w unused), internal (Morton) tet order
+  const int* tn;       // [4 nt] neighbour tet across local face f (face f is opposite vertex f), -1 on the boundary
+  const unsigned* nu;  // [14 nt] weight numerators L/k: 4 vertices, 6 edges, 4 faces
+  const int* blk;      // [nblk + 1] first tet of every workgroup block (spatially compact runs of <= TB tets)
+  int nt, nblk;
   long long L;
-  // ---- sites
+  int site_off, ns;    // sites [site_off, site_off + ns) of the batch
+  long long tet_off;   // batch-global id of the shape's tet 0
+};
+
+// Everything the kernels of one rpd_build call share. Site ids and tet ids in keys and accumulators are
+// batch-global (a shape's local id plus its offset), so one set of tables serves every shape.
+struct ShapeArgs {
+  const ShapeDesc* shapes;
+  int nshapes;
+  const int2* items;     // (shape, block) work items, heaviest first
+  int nitems;            // number of items, or the grid size when nitems_dev is set
+  const int* nitems_dev; // optional: the item count in device memory (graph-captured rounds)
+  // ---- sites (all shapes)
   int ns;
   const float4* site;    // [ns] (x, y, z, r)
   // ---- accumulators
   long long* cell_chi;   // [ns] fractional chi numerators
   long long* cell_geo;   // [4 ns] volume and first moment, fixed point 2^-56
   int* cell_np;          // [ns] nonempty pieces
-  HashTab F;             // faces (i<j): key i<<32 | j
+  HashTab F;             // faces (i<j, global ids): key i<<32 | j
   long long* face_chi;   // [cap F]
-  HashTab E;             // edges (i<j<k): key i<<42 | j<<21 | k
+  int* face_np;          // [cap F] pieces (the face exists while > 0)
+  HashTab E;             // edges (i<j<k, global ids < 2^21): key i<<42 | j<<21 | k
   long long* edge_chi;   // [cap E]
-  int4* rpv;             // RPV quadruples
-  int rpv_cap;
-  HashTab N;             // element pieces (union-find nodes): kind<<62 | elem<<32 | tet
+  int* edge_np;          // [cap E]
+  HashTab Q;             // RPVs (i<j<k<l): key edge slot of (i,j,k) << 21 | l
+  int* rpv_cnt;          // [cap Q] (exists while > 0)
+  HashTab N;             // element pieces (union-find nodes): kind<<62 | elem<<32 | global tet
   int* node_glue;        // [cap N] bit f set: the element piece touches local face f of its tet (glue across it)
-  int2* deferred;        // (tet, site or -1 for every candidate) for the large-capacity path
+  int* node_cnt;         // [cap N] (live while > 0)
+  int sign;              // +1 add the emitted contributions, -1 remove them (incremental update)
+  double* tet_U;         // optional [total tets]: U_t of the candidate test, kept for the incremental update
+  int4* deferred;        // (shape, local tet, global site or -1 for every candidate, 0) for the large-capacity path
   int deferred_cap;
-  PieceRec* pieces;
+  PieceRec* pieces;      // kept with RPD_KEEP_PIECES (t = global tet id)
   int piece_cap;
   unsigned long long* counters;  // [NCOUNTERS]
   int* status;
   unsigned flags;        // RPD_FORCE_* / RPD_KEEP_PIECES as in rpd.h
   int kmax;              // fast-path candidate budget (<= KMAX)
 };
+
+// shape of a batch-global id by binary search over the shapes' offsets
+__device__ inline int shape_of_site(const ShapeDesc* sd, int n, int gi) {
+  int lo = 0, hi = n - 1;
+  while (lo < hi) {
+    int mid = (lo + hi + 1) >> 1;
+    if (sd[mid].site_off <= gi) lo = mid;
+    else hi = mid - 1;
+  }
+  return lo;
+}
+__device__ inline int shape_of_tet(const ShapeDesc* sd, int n, long long gt) {
+  int lo = 0, hi = n - 1;
+  while (lo < hi) {
+    int mid = (lo + hi + 1) >> 1;
+    if (sd[mid].tet_off <= gt) lo = mid;
+    else hi = mid - 1;
+  }
+  return lo;
+}
 
 }  // namespace rpd

@@ -425,32 +425,30 @@ __device__ inline Plane<double> TetEnv::planeT<double>(int p) const {
   return normalise(plane64(p));
 }
 
-// carrier weight numerator of an element given the tet-face planes among its defining planes
-// (faces f are opposite vertex f; local edges (0,1),(0,2),(0,3),(1,2),(1,3),(2,3) -> 0..5)
+// carrier weight numerator L/k of an element given the tet-face planes among its defining planes, as a 4-bit mask
+// (faces f are opposite vertex f; local edges (0,1),(0,2),(0,3),(1,2),(1,3),(2,3) -> 0..5):
+// no face: tet interior (L); one face f: that face; two faces: the edge joining the two vertices neither face
+// excludes; three faces: their common vertex
 __device__ inline int pair_index(int a, int b) {  // a < b
   return a == 0 ? b - 1 : (a == 1 ? b + 1 : 5);
 }
-__device__ inline long long w_elem(int nf, int f0, int f1, int f2, const unsigned* nu, long long L) {
+__device__ inline long long w_mask(unsigned fm, const unsigned* nu, long long L) {
+  const int nf = __builtin_popcount(fm);
   if (nf == 0) return L;
-  if (nf == 1) return nu[10 + f0];
+  if (nf == 1) return nu[10 + __builtin_ctz(fm)];
+  const unsigned rest = ~fm & 15u;
   if (nf == 2) {
-    int a = min(f0, f1), b = max(f0, f1);
-    return nu[4 + 5 - pair_index(a, b)];  // the edge joining the two vertices not excluded by the faces
+    int a = __builtin_ctz(rest), b = 31 - __builtin_clz(rest);
+    return nu[4 + pair_index(a, b)];
   }
-  return nu[6 - f0 - f1 - f2];  // the vertex common to the three faces
+  return nu[__builtin_ctz(rest)];
 }
+__device__ inline unsigned face_bit(int p) { return p < 4 ? (1u << p) : 0u; }
 __device__ inline long long w_vertex(int p0, int p1, int p2, const unsigned* nu, long long L) {
-  int f[3], n = 0;
-  if (p0 < 4) f[n++] = p0;
-  if (p1 < 4) f[n++] = p1;
-  if (p2 < 4) f[n++] = p2;
-  return w_elem(n, n > 0 ? f[0] : 0, n > 1 ? f[1] : 0, n > 2 ? f[2] : 0, nu, L);
+  return w_mask(face_bit(p0) | face_bit(p1) | face_bit(p2), nu, L);
 }
 __device__ inline long long w_edge(int p0, int p1, const unsigned* nu, long long L) {
-  int f[2], n = 0;
-  if (p0 < 4) f[n++] = p0;
-  if (p1 < 4) f[n++] = p1;
-  return w_elem(n, n > 0 ? f[0] : 0, n > 1 ? f[1] : 0, 0, nu, L);
+  return w_mask(face_bit(p0) | face_bit(p1), nu, L);
 }
 
 // ---------------------------------------------------------------------------------------------------------------
@@ -509,14 +507,14 @@ struct Clipper {
 
   __device__ void init_tet() {
     float4 o = env.tv[0];
+#pragma unroll
     for (int v = 0; v < 4; ++v) {
       T x = (T)(env.tv[v].x - o.x), y = (T)(env.tv[v].y - o.y), z = (T)(env.tv[v].z - o.z);
-      int p[3], c = 0;
-      for (int f = 0; f < 4; ++f)
-        if (f != v) p[c++] = f;
-      // across the edge formed by faces {p[e+1], p[e+2]} lies tet vertex p[e]
+      // the three faces through vertex v (all but face v), ascending; across the edge formed by two of them
+      // lies the tet vertex with the third one's index
+      const int p0 = (v == 0) ? 1 : 0, p1 = (v <= 1) ? 2 : 1, p2 = (v <= 2) ? 3 : 2;
       st.put(v, x, y, z, exact_point_F(x, y, z));
-      st.set_topo(v, Topo::make(p[0], p[1], p[2], p[0], p[1], p[2]));
+      st.set_topo(v, Topo::make(p0, p1, p2, p0, p1, p2));
     }
     live = (Mask)15;
   }

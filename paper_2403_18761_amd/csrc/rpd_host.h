@@ -84,6 +84,7 @@ struct rpd_mesh {
   rpd::DBuf perm;  // int [nt]: internal -> caller tet index
   rpd::DBuf blk;   // int [nblk + 1]: workgroup blocks over the internal order
   int32_t nblk = 0;
+  std::vector<int> hblk;  // host copy of blk
 };
 
 namespace rpd {

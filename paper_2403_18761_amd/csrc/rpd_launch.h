@@ -9,9 +9,9 @@ namespace rpd {
 
 // clip.hip
 hipError_t launch_clip_fast(const ShapeArgs& a, int precision, int block, hipStream_t s);
-size_t slow_scratch_bytes(int threads);
+size_t slow_scratch_bytes(int waves);
 // the item count is read on the device from counters[C_DEFER_ITEMS] (no host synchronisation)
-hipError_t launch_clip_slow(const ShapeArgs& a, unsigned char* scratch, int threads, hipStream_t s);
+hipError_t launch_clip_slow(const ShapeArgs& a, unsigned char* scratch, int waves, hipStream_t s);
 
 // reduce.hip
 hipError_t launch_fill_u64(unsigned long long* p, unsigned long long v, size_t n, hipStream_t s);
@@ -20,18 +20,23 @@ hipError_t launch_glue(const ShapeArgs& a, int* parent, hipStream_t s);
 hipError_t launch_count_roots(const ShapeArgs& a, int* parent, int* cell_b0, int* face_b0, int* edge_b0,
                               hipStream_t s);
 hipError_t launch_iota(int* v, int n, hipStream_t s);
+hipError_t launch_live_keys(const unsigned long long* keys, const int* np, unsigned cap, unsigned long long* out,
+                            hipStream_t s);
+hipError_t launch_rpv_decode(const HashTab& Q, const int* cnt, const unsigned long long* ekeys, int4* out,
+                             hipStream_t s);
 hipError_t sort_pairs_u64(void* tmp, size_t& tmp_bytes, const unsigned long long* kin, unsigned long long* kout,
                           const int* vin, int* vout, int n, hipStream_t s);
 size_t sort_tmp_bytes(int n);
 // element lists over a whole sorted table capacity: free slots (EMPTY keys) are skipped; count += used entries
 hipError_t launch_finalize_faces(const unsigned long long* keys, const int* slots, int cap, const long long* chi_num,
-                                 const int* b0, long long L, int* out_keys, int* out_chi, int* out_b0, int* status,
-                                 unsigned long long* count, hipStream_t s);
+                                 const int* b0, const ShapeDesc* shapes, int nshapes, int* out_keys, int* out_chi,
+                                 int* out_b0, int* status, unsigned long long* count, hipStream_t s);
 hipError_t launch_finalize_edges(const unsigned long long* keys, const int* slots, int cap, const long long* chi_num,
-                                 const int* b0, long long L, int* out_keys, int* out_chi, int* out_b0, int* status,
-                                 unsigned long long* count, hipStream_t s);
-hipError_t launch_finalize_cells(int ns, const long long* chi_num, const long long* geo, const int* np, long long L,
-                                 int* out_chi, double* out_vol, double* out_cen, int* status, hipStream_t s);
+                                 const int* b0, const ShapeDesc* shapes, int nshapes, int* out_keys, int* out_chi,
+                                 int* out_b0, int* status, unsigned long long* count, hipStream_t s);
+hipError_t launch_finalize_cells(int ns, const long long* chi_num, const long long* geo, const int* np,
+                                 const ShapeDesc* shapes, int nshapes, int* out_chi, double* out_vol, double* out_cen,
+                                 int* status, hipStream_t s);
 hipError_t launch_fill_rpv(int4* p, int n, hipStream_t s);
 hipError_t launch_sort_rpv(const int4* rpv, int n, unsigned long long* ka, unsigned long long* kb,
                            unsigned long long* kc, int* va, int* vb, void* tmp, size_t tmp_bytes, int4* out,

@@ -563,22 +563,48 @@ def cube_random(N: int = 4, n_sites: int = 8, seed: int = 0, weights: bool = Tru
     return make_problem(solid, N, cen, rad, workload=f"cube_N{N}_n{n_sites}_s{seed}", seed=seed)
 
 
+def _scaled(sdf, scale: float):
+    """The solid shrunk about the origin by ``scale`` (signed distances scale with it)."""
+    return lambda p: sdf(p / scale) * scale
+
+
 def batch_shape(k: int, tets_target: int, n_sites: int) -> Problem:
-    """One shape of the batched workload (seed 1000+k): torus / box union / metaballs, N chosen for the size."""
-    seed = 1000 + k
-    rng = np.random.default_rng(seed)
-    kind = ["torus", "boxes", "metaballs"][int(rng.integers(0, 3))]
-    # Kuhn tets ~ 6 * fill * N^3; pick N from the target with a rough fill factor per kind
-    fill = {"torus": 0.09, "boxes": 0.12, "metaballs": 0.12}[kind]
-    N = int(max(8, round((tets_target / (6 * fill)) ** (1 / 3))))
-    if kind == "torus":
-        solid = jittered_torus(N, seed)
-    elif kind == "boxes":
-        solid = box_union_solid(N, seed)
-    else:
-        solid = metaball_solid(N, seed, int(rng.integers(3, 7)))
-    cen, rad = inside_sites(solid, N, n_sites, seed, 0.9)
-    return make_problem(solid, N, cen, rad, workload=f"batch_{k}", seed=seed)
+    """Shape k of the batched workload (seed 1000+k): torus, 2-4 box union or 3-6 metaballs on a 64^3 grid, shrunk
+    about the origin so that its Kuhn mesh has about ``tets_target`` tets (targets above the unshrunk size are
+    capped there). If no shrink of a drawn solid stays valid, the solid is redrawn (draw d uses seed+7919 d)."""
+    N = 64
+    for draw in range(16):
+        seed = 1000 + k + 7919 * draw
+        rng = np.random.default_rng(seed)
+        kind = ["torus", "boxes", "metaballs"][int(rng.integers(0, 3))]
+        n_balls = int(rng.integers(3, 7))
+        if kind == "torus":
+            base = jittered_torus(N, seed)
+            expected = 0
+        elif kind == "boxes":
+            base = box_union_solid(N, seed)
+            expected = 1 - base["genus"]
+        else:
+            base = metaball_solid(N, seed, n_balls)
+            expected = 1 - base["genus"]
+        full = int(base["occ"].sum()) * 6
+        scale = min(1.0, (tets_target / max(full, 1)) ** (1.0 / 3.0))
+        for attempt in range(24):  # shrink until the voxel set is valid again
+            sdf = _scaled(base["sdf"], scale)
+            occ = voxels_inside(sdf, N)
+            ok, _ = voxel_set_ok(occ, expected)
+            if ok:
+                solid = dict(base, sdf=sdf, occ=occ, scale=scale)
+                cen, rad = inside_sites(solid, N, n_sites, seed, 0.9)
+                return make_problem(solid, N, cen, rad, workload=f"batch_{k}", seed=seed, kind=kind, draw=draw)
+            scale *= 0.985
+    raise RuntimeError(f"batch shape {k}: no valid scaled voxelisation")
+
+
+def batch_problems(n_shapes: int = 256, seed: int = 4):
+    """The batched workload: n_shapes shapes with log-uniform sizes (5k-200k tets, 100-5k sites)."""
+    t, s = batch_sizes(n_shapes, seed)
+    return [batch_shape(k, int(t[k]), int(s[k])) for k in range(n_shapes)]
 
 
 def batch_sizes(n_shapes: int = 256, seed: int = 4):

@@ -63,3 +63,33 @@ def assert_parity(g, r, vol_rtol=1e-5, label=""):
 def log(*a):
     print(*a, flush=True)
     sys.stdout.flush()
+
+
+def run_gpu_batch(probs, precision=0, flags=0):
+    """Several shapes in one rpd_build call; returns one dict per shape in the layout of run_gpu."""
+    import torch
+
+    from paper_2403_18761_amd import rpd
+
+    dev = torch.device("cuda:0")
+
+    def t(a, dt=torch.float32):
+        return torch.as_tensor(np.ascontiguousarray(a), dtype=dt, device=dev)
+
+    meshes = [rpd.Mesh(t(p.vx), t(p.vy), t(p.vz), t(p.tv.reshape(-1), torch.int32)) for p in probs]
+    sites = [(t(p.sx), t(p.sy), t(p.sz), t(p.sr)) for p in probs]
+    res = rpd.build(meshes, sites, precision=precision, flags=flags)
+    outs = []
+    for k in range(len(probs)):
+        out = {}
+        _, out["cell_chi"] = res.euler(k, rpd.RPD_CELL)
+        _, out["cell_beta0"] = res.components(k, rpd.RPD_CELL)
+        out["face_keys"], out["face_chi"] = res.euler(k, rpd.RPD_FACE)
+        _, out["face_beta0"] = res.components(k, rpd.RPD_FACE)
+        out["edge_keys"], out["edge_chi"] = res.euler(k, rpd.RPD_EDGE)
+        _, out["edge_beta0"] = res.components(k, rpd.RPD_EDGE)
+        out["rpv_keys"] = res.adjacency(k, rpd.RPD_VERTEX)
+        out["cell_vol"], out["cell_cen"] = res.geometry(k)
+        out["mesh_info"] = meshes[k].info()
+        outs.append(out)
+    return outs, res.stats()

@@ -7,7 +7,7 @@ import numpy as np
 import pytest
 
 from paper_2403_18761_amd import synth
-from tests.gpu_util import assert_parity, log, run_gpu
+from tests.gpu_util import assert_parity, log, run_gpu, run_gpu_batch
 
 pytestmark = pytest.mark.gpu
 
@@ -133,3 +133,19 @@ def test_errors_reported():
     with pytest.raises(rpd.RPDError) as e:
         run_gpu(synth.Problem(base.vx, base.vy, base.vz, tv, base.sx, base.sy, base.sz, base.sr, {}))
     assert e.value.code == -1
+
+
+def test_batch_of_shapes_in_one_call():
+    """Several shapes of uneven size through one persistent launch: each shape matches its own oracle run."""
+    probs = [synth.torus_core(16, 64, 1), synth.cube_random(N=8, n_sites=150, seed=4),
+             synth.torus_inside(32, 400, 13), synth.genus3_cad(N=32, n_sites=250, seed=14),
+             synth.cube_random(N=4, n_sites=30, seed=5, weights=False)]
+    log("case: batch of", len(probs), "shapes")
+    outs, st = run_gpu_batch(probs)
+    total_pairs = 0
+    for k, (p, g) in enumerate(zip(probs, outs)):
+        r = _oracle(p, assemble=False)
+        g["stats"] = {"n_pairs": r["n_pairs"]}  # per-shape piece counts are summed in the batch statistics
+        total_pairs += r["n_pairs"]
+        assert_parity(g, r, label=f"batch shape {k}")
+    assert st["n_pairs"] == total_pairs

@@ -34,6 +34,9 @@ WORKLOADS = {
                         "20000 sites, 30% within 0.02 of sharp edges", cpu_frac=0.002),
     "batch256": dict(desc="256 seeded shapes (tori, box unions, metaballs), log-uniform 5k-200k tets and 100-5k sites "
                           "each, one rpd_build call", cpu_frac=0.002),
+    "repair": dict(desc="topology repair: 5 metaball blobs joined by thin handles (genus 2), 128^3 grid, 975462 Kuhn "
+                        "tets, 500 initial sites, up to 64 insertions per round from a per-tet sphere table, one "
+                        "captured graph per round (a step is one round)", cpu_frac=0.002),
 }
 
 
@@ -46,6 +49,8 @@ def workload(name):
         return [synth.genus3_cad(N=128, n_sites=20000, seed=3)]
     if name == "batch256":
         return synth.batch_problems(256, 4)
+    if name == "repair":
+        return [synth.repair_problem(N=128, n_sites=500, seed=5)]
     raise SystemExit(f"unknown workload {name}")
 
 
@@ -69,6 +74,56 @@ def time_builds(meshes, sites, precision, steps, warmup, stream):
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     return (t1 - t0) * 1e3 / steps, float(np.mean(clip_ms)), n_pairs, st
+
+
+def run_repair(args, prob, table):
+    """One step = one round of the incremental session; value = (tet, site) pairs clipped per second in the timed
+    rounds (removal and re-insertion passes of the dirty blocks). A from-scratch rebuild with the final sites is
+    timed beside it."""
+    import torch
+
+    from paper_2403_18761_amd import rpd
+
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+
+    def t(a, dt=torch.float32):
+        return torch.as_tensor(np.ascontiguousarray(a), dtype=dt, device=dev)
+
+    max_insert = 64
+    mesh = rpd.Mesh(t(prob.vx), t(prob.vy), t(prob.vz), t(prob.tv.reshape(-1), torch.int32))
+    sess = rpd.Session(mesh, (t(prob.sx), t(prob.sy), t(prob.sz), t(prob.sr)), tuple(t(x) for x in table),
+                       max_sites=prob.n_sites + max_insert * (args.steps + args.warmup), max_insert=max_insert)
+    sess.run(args.warmup)
+    i0 = sess.info()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    sess.run(args.steps)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    i1 = sess.info()
+    res = sess.result()
+    st = res.stats()
+    _, chi = res.euler(0, rpd.RPD_CELL)
+    _, b0 = res.components(0, rpd.RPD_CELL)
+    vol, _ = res.geometry(0)
+    live = vol > 0
+    bad = int(np.sum(live & ((chi != 1) | (b0 > 1))))
+    s = sess.sites()
+    sites = tuple(t(s[:, k]) for k in range(4))
+    ms_full, clip_full, pairs_full, _ = time_builds([mesh], [sites], rpd.RPD_FP32_FALLBACK, 5, 1, None)
+    assert pairs_full == st["n_pairs"]
+    clipped = i1["n_clipped"] - i0["n_clipped"]
+    ms_round = dt * 1e3 / args.steps
+    print(f"# repair: {ms_round:.3f} ms/round, {i1['n_inserted'] - i0['n_inserted']} inserted, "
+          f"{i1['n_dirty_blocks'] - i0['n_dirty_blocks']} dirty blocks of {i1['n_blocks']} x {args.steps}, "
+          f"rebuild {ms_full:.3f} ms, violating cells left {bad}", file=sys.stderr, flush=True)
+    return dict(value=clipped / dt, ms_per_step=ms_round, n_pairs=st["n_pairs"], n_sites=int(s.shape[0]),
+                extra={"ms_per_round": ms_round, "ms_full_rebuild_final_sites": ms_full,
+                       "rounds_timed": args.steps, "inserted_timed": i1["n_inserted"] - i0["n_inserted"],
+                       "dirty_blocks_timed": i1["n_dirty_blocks"] - i0["n_dirty_blocks"], "n_blocks": i1["n_blocks"],
+                       "pairs_clipped_timed": clipped, "violating_cells_left": bad,
+                       "sites_final": int(s.shape[0])})
 
 
 def cpu_baseline(probs, frac):
@@ -115,8 +170,27 @@ def main():
     from paper_2403_18761_amd import rpd
 
     probs = workload(args.workload)
+    if args.workload == "repair":
+        probs, table = [probs[0][0]], probs[0][1]
     print(f"# workload {args.workload}: {len(probs)} shape(s), {sum(p.n_tets for p in probs)} tets, "
           f"{sum(p.n_sites for p in probs)} sites", file=sys.stderr, flush=True)
+    if args.workload == "repair":
+        r = run_repair(args, probs[0], table)
+        line = {
+            "metric": "tet-site clips/sec in the incremental repair loop (dirty blocks only) + ms per round, 1 MI355X",
+            "value": r["value"], "unit": "clips/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+            "ms_per_step": r["ms_per_step"], "higher_is_better": True, "scaling": "strong", "vs_baseline": None,
+            "dtype": "f32", "data": "synthetic",
+            "config": {"workload": WORKLOADS[args.workload]["desc"], "name": args.workload, "n_shapes": 1,
+                       "n_tets": probs[0].n_tets, "n_sites_initial": probs[0].n_sites,
+                       "n_pairs_final": r["n_pairs"]},
+            "repair": r["extra"],
+        }
+        if not args.no_cpu_baseline:
+            frac = args.cpu_frac if args.cpu_frac is not None else WORKLOADS[args.workload]["cpu_frac"]
+            line["cpu_baseline"] = cpu_baseline(probs, frac)
+        print(json.dumps(line), flush=True)
+        return
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
     stream = torch.cuda.current_stream(dev)
@@ -158,7 +232,8 @@ def main():
         "ms_per_rpd": ms32,
         "all_fp64": out64,
         "stats": {k: st32[k] for k in ("n_candidates", "n_deferred", "n_fp64", "n_exact", "n_faces", "n_edges",
-                                       "n_rpv", "ms_clip", "ms_deferred", "ms_reduce", "ms_total")},
+                                       "n_rpv", "n_defer_block", "n_defer_kmax", "n_defer_clip", "n_split", "ms_clip",
+                                       "ms_deferred", "ms_reduce", "ms_total")},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
                      "frac": achieved / PEAK_FP32_TFLOPS, "traffic": None,
                      "kernel": "k_clip_fast<float,128>", "flop_per_piece": FLOP_PER_PIECE},

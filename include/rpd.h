@@ -94,8 +94,8 @@ typedef struct rpd_sites {
 
 typedef struct rpd_opts {
   int32_t precision;   /* RPD_FP32_FALLBACK or RPD_FP64 */
-  int32_t clip_budget; /* max candidate sites per tet in the fast path: 0 = default (28) or 8..28 */
-  int32_t block;       /* threads per workgroup of the clipping kernel: 0 = default, else 64/128/256 */
+  int32_t clip_budget; /* max candidate sites per tet in the fast path: 0 = default (28) or 4..28 */
+  int32_t block;       /* threads per workgroup of the clipping kernel: 0 = default (128), 64 or 128 */
   uint32_t flags;      /* RPD_* flags above */
   void* stream;        /* hipStream_t to run on; NULL = the null stream */
 } rpd_opts;
@@ -112,6 +112,10 @@ typedef struct rpd_stats {
   double ms_deferred;     /* deferred kernel */
   double ms_reduce;       /* gluing, union-find, compaction and sorting */
   double ms_total;        /* whole rpd_build on the stream */
+  int64_t n_defer_block;  /* tets deferred because their workgroup's site list overflowed */
+  int64_t n_defer_kmax;   /* tets deferred because more candidates than the clip budget remained */
+  int64_t n_defer_clip;   /* pieces deferred because their polytope outgrew the fast path's vertex slots */
+  int64_t n_split;        /* workgroup blocks redone in smaller chunks because their site list overflowed */
 } rpd_stats;
 
 typedef struct rpd_result rpd_result;
@@ -119,7 +123,7 @@ typedef struct rpd_result rpd_result;
 /* Validate and preprocess a mesh (Sec. 4.1.2: weights derived from the combinatorial structure of the tet mesh).
  * Pointers are borrowed (host, or device with RPD_DEVICE_PTRS in flags) and only read during the call.
  * Errors: RPD_E_INVALID (off-grid or out-of-range values, bad indices, non-positive orientation),
- * RPD_E_MESH (a face in more than two tets, more than one component, lcm of multiplicities above 2^24). */
+ * RPD_E_MESH (a face in more than two tets, more than one component, lcm of multiplicities of 2^31 or more). */
 rpd_status rpd_mesh_create(const rpd_mesh_desc* desc, uint32_t flags, void* stream, rpd_mesh** out);
 rpd_status rpd_mesh_get_info(const rpd_mesh* mesh, rpd_mesh_info* info);
 void rpd_mesh_free(rpd_mesh* mesh);
@@ -159,6 +163,63 @@ rpd_status rpd_pieces(const rpd_result* r, int32_t shape, int64_t* n_out, const 
                       const double** vol_moment /* 4 per piece */, const int64_t** chi_num);
 
 void rpd_free(rpd_result* r);
+
+/* ---- Incremental session: the sphere-insertion loop of topology repair (Sec. 4 overview: spheres are added where
+ * an element violates the topology constraints, and only the cells related to the new spheres are updated).
+ *
+ * A session keeps the RPD of one mesh and a growing site set resident on the device. Every round
+ *   1. selects up to max_insert restricted power cells with chi != 1 or more than one component (lowest site ids
+ *      first; Sec. 3.3 / 4.1 criteria for a cell),
+ *   2. picks for each a tet among the cell's pieces (for a cell with several components, outside the component
+ *      of its first piece) by a fixed hash of (tet, round), and appends the sphere that `table` holds for that
+ *      tet (each tet's sphere is inserted at most once),
+ *   3. re-clips only the workgroup blocks whose tets a new sphere can reach (exact candidate test), removing the
+ *      blocks' old contributions and adding the new ones, and recomputes the components.
+ * The round is one captured HIP graph replayed by rpd_session_run. The state after any number of rounds is
+ * identical, bit for bit, to rpd_build on the same mesh with the session's current sites (rpd_session_sites).
+ */
+typedef struct rpd_session rpd_session;
+
+typedef struct rpd_session_opts {
+  int32_t max_sites;  /* capacity: initial sites plus every insertion, in [n_sites, 2^21) */
+  int32_t max_insert; /* cells handled per round, 1..4096 */
+  rpd_opts build;     /* precision, clip_budget, block, flags as for rpd_build (RPD_DEVICE_PTRS applies to the sites
+                         and the table); build.stream is synchronised before the session reads the inputs, and the
+                         session then runs on a stream of its own */
+} rpd_session_opts;
+
+typedef struct rpd_session_info {
+  int32_t n_sites;        /* sites in use */
+  int32_t rounds;         /* rounds run so far */
+  int32_t n_selected;     /* cells selected in the last round */
+  int32_t n_blocks;       /* workgroup blocks of the mesh */
+  int64_t n_inserted;     /* spheres inserted over all rounds */
+  int64_t n_dirty_blocks; /* blocks re-clipped over all rounds */
+  int64_t n_clipped;      /* (tet, candidate site) pairs clipped since creation, removal passes included */
+  double ms_last_run;     /* HIP-event time of the last rpd_session_run */
+} rpd_session_info;
+
+/* Create a session: validate the inputs, compute the initial RPD, capture the round graph.
+ * mesh is borrowed and must outlive the session. sites: the initial spheres. table: one sphere per tet of the
+ * mesh in the caller's tet order (table->n_sites == n_tets), on the 2^-20 grid like every site. Synchronises.
+ * Errors: RPD_E_INVALID, RPD_E_DEGENERATE, RPD_E_NOMEM, RPD_E_DEVICE. */
+rpd_status rpd_session_create(const rpd_mesh* mesh, const rpd_sites* sites, const rpd_sites* table,
+                              const rpd_session_opts* opts, rpd_session** out);
+
+/* Run `rounds` rounds (graph replays), then synchronise and check the device status. Errors: RPD_E_DEGENERATE
+ * (an inserted sphere duplicates a site or is not in general position), RPD_E_NOMEM (the session's tables filled
+ * up: create it with a larger max_sites), RPD_E_DEVICE. After an error the session can only be freed. */
+rpd_status rpd_session_run(rpd_session* s, int32_t rounds);
+
+/* The current state as an rpd_result (shape 0), read with the accessors above and released with rpd_free. */
+rpd_status rpd_session_result(rpd_session* s, rpd_result** out);
+
+rpd_status rpd_session_get_info(rpd_session* s, rpd_session_info* info);
+
+/* Copy the current sites (x, y, z, r per site, in site-id order) into host memory xyzr of room for cap sites. */
+rpd_status rpd_session_sites(rpd_session* s, int32_t cap, float* xyzr, int32_t* n_out);
+
+void rpd_session_free(rpd_session* s);
 
 /* Thread-local description of the last error of this thread ("" if none). */
 const char* rpd_last_error(void);

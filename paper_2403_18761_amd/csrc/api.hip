@@ -24,11 +24,12 @@ void set_error(const std::string& msg) { g_error = msg; }
 static std::mutex g_pool_mu;
 static std::map<std::pair<int, size_t>, std::vector<void*>> g_pool;
 
-void* pool_alloc(size_t bytes, size_t* cls_bytes) {
+void* pool_alloc(size_t bytes, size_t* cls_bytes, int* device) {
   size_t c = 256;
   while (c < bytes) c <<= 1;
   int dev = 0;
-  (void)hipGetDevice(&dev);
+  hip_check(hipGetDevice(&dev), "hipGetDevice");
+  *device = dev;
   {
     std::lock_guard<std::mutex> g(g_pool_mu);
     auto& v = g_pool[{dev, c}];
@@ -56,11 +57,9 @@ void* pool_alloc(size_t bytes, size_t* cls_bytes) {
   return p;
 }
 
-void pool_free(void* p, size_t cls_bytes) {
-  int dev = 0;
-  (void)hipGetDevice(&dev);
+void pool_free(void* p, size_t cls_bytes, int device) {
   std::lock_guard<std::mutex> g(g_pool_mu);
-  g_pool[{dev, cls_bytes}].push_back(p);
+  g_pool[{device, cls_bytes}].push_back(p);
 }
 
 static unsigned pow2_cap(size_t n) {
@@ -70,23 +69,9 @@ static unsigned pow2_cap(size_t n) {
   return (unsigned)c;
 }
 
-// process-wide scratch of the large-capacity kernel (one region per thread of its grid), grown on demand
-static std::mutex g_scratch_mu;
-static DBuf g_scratch;
-static int g_scratch_device = -1;
-constexpr int SLOW_WAVES = 256;  // one wavefront per deferred item at a time
-
-static unsigned char* slow_scratch() {
-  std::lock_guard<std::mutex> g(g_scratch_mu);
-  int dev = 0;
-  (void)hipGetDevice(&dev);
-  size_t need = slow_scratch_bytes(SLOW_WAVES);
-  if (g_scratch.p == nullptr || g_scratch.bytes < need || g_scratch_device != dev) {
-    g_scratch.alloc(need);
-    g_scratch_device = dev;
-  }
-  return g_scratch.as<unsigned char>();
-}
+// Waves of the large-capacity kernel: one deferred item per wave at a time; each wave owns a private scratch
+// region of slow_scratch_bytes(1) (about 240 KB), allocated with the call's other buffers.
+static int slow_waves(long long nt) { return (int)std::max<long long>(64, std::min<long long>(2048, nt / 16)); }
 
 struct ShapeOut {
   int ns = 0;
@@ -139,7 +124,8 @@ struct DeviceState {
   int def_cap = 0, piece_cap = 0;
   DBuf site, status, cell_chi, cell_geo, cell_np, cell_b0;
   DBuf fkeys, face_chi, face_np, face_b0, ekeys, edge_chi, edge_np, edge_b0, qkeys, rpv_cnt;
-  DBuf nkeys, node_glue, node_cnt, parent, deferred, pieces, counters, tetU;
+  DBuf nkeys, node_glue, node_cnt, parent, deferred, pieces, counters, tetU, slow;
+  int waves = 0;
 
   unsigned long long* cnt() const { return counters.as<unsigned long long>(); }
   unsigned long long* fin_count() const { return cnt() + NCOUNTERS; }  // [0] faces, [1] edges
@@ -178,6 +164,8 @@ struct DeviceState {
     pieces.alloc(sizeof(PieceRec) * (size_t)std::max(piece_cap, 1));
     counters.alloc(8 * (NCOUNTERS + 8));
     if (keep_U) tetU.alloc(8 * (size_t)std::max<long long>(nt, 1));
+    waves = slow_waves(nt);
+    slow.alloc(slow_scratch_bytes(waves));
   }
 
   void clear(hipStream_t s) {
@@ -422,6 +410,10 @@ static bool collect(DeviceState& D, const std::vector<ShapeDesc>& hd, const Shap
   st.n_edges = (int64_t)ne;
   st.n_rpv = (int64_t)nq;
   st.n_glue = (int64_t)hc[C_NODES];
+  st.n_defer_block = (int64_t)hc[C_DEFER_BLOCK];
+  st.n_defer_kmax = (int64_t)hc[C_DEFER_KMAX];
+  st.n_defer_clip = (int64_t)hc[C_DEFER_CLIP];
+  st.n_split = (int64_t)hc[C_SPLIT];
   return true;
 }
 
@@ -516,7 +508,7 @@ static bool run_batch(const rpd_mesh* const* meshes, const rpd_sites* sites, int
   tm.mark(0, s);
   hip_check(launch_clip_fast(a, o.precision, o.block, s), "clip kernel");
   tm.mark(1, s);
-  hip_check(launch_clip_slow(a, slow_scratch(), SLOW_WAVES, s), "deferred clip kernel");
+  hip_check(launch_clip_slow(a, D.slow.as<unsigned char>(), D.waves, s), "deferred clip kernel");
   tm.mark(2, s);
   D.components(a, s);
   if (!collect(D, hd, dshapes.as<ShapeDesc>(), meshes, s, tm, outs, st)) return false;
@@ -725,5 +717,352 @@ rpd_status rpd_pieces(const rpd_result* r, int32_t shape, int64_t* n_out, const 
 }
 
 void rpd_free(rpd_result* r) { delete r; }
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------------------------------------------
+// incremental session
+// ---------------------------------------------------------------------------------------------------------------
+struct rpd_session {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  const rpd_mesh* mesh = nullptr;
+  rpd_opts o{};
+  int max_sites = 0, max_insert = 0, kmax = rpd::KMAX;
+  bool failed = false;
+  rpd::ShapeDesc hd{};
+  rpd::DeviceState D;
+  rpd::DBuf dshapes;  // [0] the shape before a round's insertions, [1] after them (the current state)
+  rpd::DBuf all_items, items, table, tet_block, dirty, sel, selpos, best, ref, tet_used, ints;
+  rpd::RoundState r{};
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  hipEvent_t ev[2] = {nullptr, nullptr};
+  int rounds = 0;
+  double ms_last = 0;
+
+  ~rpd_session() {
+    if (stream) (void)hipStreamSynchronize(stream);
+    if (exec) (void)hipGraphExecDestroy(exec);
+    if (graph) (void)hipGraphDestroy(graph);
+    for (auto& e : ev)
+      if (e) (void)hipEventDestroy(e);
+    if (stream) (void)hipStreamDestroy(stream);
+  }
+};
+
+namespace rpd {
+
+// int slots of rpd_session::ints
+enum { SI_NSEL = 0, SI_NITEMS, SI_ROUND, SI_NS, SI_INS, SI_DIRTY, SI_COUNT };
+
+static void check_status(rpd_session* S) {
+  int hst = 0;
+  hip_check(hipMemcpyAsync(&hst, S->D.status.p, sizeof(int), hipMemcpyDeviceToHost, S->stream), "download");
+  hip_check(hipStreamSynchronize(S->stream), "synchronize");
+  if (hst & ST_TABLE_FULL)
+    throw Failure{RPD_E_NOMEM, "session tables are full: create the session with a larger max_sites"};
+  status_error(hst);
+}
+
+// one full clipping pass over the items of a (all blocks, or the dirty ones with a device-side count)
+static void clip_pass(rpd_session* S, const ShapeArgs& a) {
+  hip_check(launch_fill_u64(S->D.cnt() + C_DEFER_ITEMS, 0, 1, S->stream), "fill");
+  hip_check(launch_clip_fast(a, S->o.precision, S->o.block, S->stream), "clip kernel");
+  hip_check(launch_clip_slow(a, S->D.slow.as<unsigned char>(), S->D.waves, S->stream), "deferred clip kernel");
+}
+
+// Allocate at the given table scale, upload, compute the initial state. False if a table overflowed.
+static bool session_init(rpd_session* S, const rpd_sites* sites, const rpd_sites* table, int scale) {
+  const rpd_mesh* m = S->mesh;
+  hipStream_t s = S->stream;
+  const bool dev = (S->o.flags & RPD_DEVICE_PTRS) != 0;
+  const int nt = m->nt, nblk = m->nblk;
+  DeviceState& D = S->D;
+  D.alloc(1, S->max_sites, nt, scale, false, true);
+  D.clear(s);
+  std::vector<ShapeDesc> hd{S->hd};
+  upload_sites(D, sites, hd, dev, s);
+  // the table, validated like sites, then put in the internal tet order
+  {
+    DBuf raw(sizeof(float4) * (size_t)nt), stage;
+    const float *tx = table->sx, *ty = table->sy, *tz = table->sz, *tr = table->sr;
+    if (!dev) {
+      stage.alloc(sizeof(float) * 4 * (size_t)nt);
+      float* q = stage.as<float>();
+      hip_check(hipMemcpyAsync(q, tx, sizeof(float) * nt, hipMemcpyHostToDevice, s), "upload");
+      hip_check(hipMemcpyAsync(q + nt, ty, sizeof(float) * nt, hipMemcpyHostToDevice, s), "upload");
+      hip_check(hipMemcpyAsync(q + 2 * (size_t)nt, tz, sizeof(float) * nt, hipMemcpyHostToDevice, s), "upload");
+      hip_check(hipMemcpyAsync(q + 3 * (size_t)nt, tr, sizeof(float) * nt, hipMemcpyHostToDevice, s), "upload");
+      tx = q;
+      ty = q + nt;
+      tz = q + 2 * (size_t)nt;
+      tr = q + 3 * (size_t)nt;
+    }
+    hip_check(launch_validate_sites(tx, ty, tz, tr, nt, raw.as<float4>(), D.status.as<int>(), s), "validate table");
+    S->table.alloc(sizeof(float4) * (size_t)nt);
+    hip_check(launch_gather_table(raw.as<float4>(), m->perm.as<int>(), nt, S->table.as<float4>(), s), "table");
+    hip_check(hipStreamSynchronize(s), "synchronize");  // the staging buffers are released next
+  }
+  std::vector<int> tb(nt);
+  for (int b = 0; b < nblk; ++b)
+    for (int t = m->hblk[b]; t < m->hblk[b + 1]; ++t) tb[t] = b;
+  std::vector<int2> all(nblk);
+  for (int b = 0; b < nblk; ++b) all[b] = make_int2(0, b);
+  ShapeDesc two[2] = {S->hd, S->hd};
+  S->dshapes.alloc(sizeof(two));
+  S->all_items.alloc(sizeof(int2) * (size_t)nblk);
+  S->items.alloc(sizeof(int2) * (size_t)nblk);
+  S->tet_block.alloc(sizeof(int) * (size_t)nt);
+  S->dirty.alloc(sizeof(int) * (size_t)nblk);
+  S->sel.alloc(sizeof(int) * (size_t)S->max_insert);
+  S->best.alloc(8 * (size_t)S->max_insert);
+  S->ref.alloc(sizeof(int) * (size_t)S->max_insert);
+  S->selpos.alloc(sizeof(int) * (size_t)S->max_sites);
+  S->tet_used.alloc(sizeof(int) * (size_t)nt);
+  S->ints.alloc(sizeof(int) * SI_COUNT);
+  hip_check(hipMemcpyAsync(S->dshapes.p, two, sizeof(two), hipMemcpyHostToDevice, s), "upload");
+  hip_check(hipMemcpyAsync(S->all_items.p, all.data(), sizeof(int2) * all.size(), hipMemcpyHostToDevice, s),
+            "upload");
+  hip_check(hipMemcpyAsync(S->tet_block.p, tb.data(), sizeof(int) * tb.size(), hipMemcpyHostToDevice, s), "upload");
+  hip_check(launch_fill_i32(S->dirty.as<int>(), 0, nblk, s), "fill");
+  hip_check(launch_fill_i32(S->selpos.as<int>(), -1, S->max_sites, s), "fill");
+  hip_check(launch_fill_i32(S->tet_used.as<int>(), 0, nt, s), "fill");
+  hip_check(launch_fill_i32(S->ints.as<int>(), 0, SI_COUNT, s), "fill");
+  hip_check(launch_fill_i32(S->ints.as<int>() + SI_NS, S->hd.ns, 1, s), "fill");
+
+  ShapeDesc* ds = S->dshapes.as<ShapeDesc>();
+  ShapeArgs a = D.args(ds + 1, S->all_items.as<int2>(), nblk, S->o.flags, S->kmax, +1);
+  clip_pass(S, a);
+  D.components(a, s);
+  hip_check(hipStreamSynchronize(s), "synchronize");
+  int hst = 0;
+  hip_check(hipMemcpy(&hst, D.status.p, sizeof(int), hipMemcpyDeviceToHost), "download");
+  if (hst & ST_TABLE_FULL) return false;
+  status_error(hst);
+
+  int* ints = S->ints.as<int>();
+  RoundState& r = S->r;
+  r.nsel = ints + SI_NSEL;
+  r.sel = S->sel.as<int>();
+  r.selpos = S->selpos.as<int>();
+  r.best = S->best.as<unsigned long long>();
+  r.ref = S->ref.as<int>();
+  r.tet_used = S->tet_used.as<int>();
+  r.table = S->table.as<float4>();
+  r.tet_block = S->tet_block.as<int>();
+  r.dirty = S->dirty.as<int>();
+  r.items = S->items.as<int2>();
+  r.nitems = ints + SI_NITEMS;
+  r.round = ints + SI_ROUND;
+  r.ns_cur = ints + SI_NS;
+  r.ins_total = ints + SI_INS;
+  r.dirty_total = ints + SI_DIRTY;
+  r.old_desc = ds;
+  r.new_desc = ds + 1;
+  r.max_sites = S->max_sites;
+  r.max_insert = S->max_insert;
+  return true;
+}
+
+// the launch sequence of one round (captured once into the session's graph)
+static void session_round(rpd_session* S) {
+  hipStream_t s = S->stream;
+  DeviceState& D = S->D;
+  const rpd_mesh* m = S->mesh;
+  ShapeDesc* ds = S->dshapes.as<ShapeDesc>();
+  ShapeArgs a_old = D.args(ds, S->items.as<int2>(), m->nblk, S->o.flags, S->kmax, -1);
+  ShapeArgs a_new = D.args(ds + 1, S->items.as<int2>(), m->nblk, S->o.flags, S->kmax, +1);
+  a_old.nitems_dev = S->r.nitems;
+  a_new.nitems_dev = S->r.nitems;
+  hip_check(launch_round_front(S->r, a_new, D.parent.as<int>(), D.cell_b0.as<int>(), m->tp.as<float4>(), m->nt,
+                               m->nblk, s),
+            "round selection");
+  clip_pass(S, a_old);  // the dirty blocks' contributions with the old sites, removed
+  clip_pass(S, a_new);  // ... and with the new sites, added
+  D.components(a_new, s);
+  hip_check(launch_round_end(S->r, s), "round end");
+}
+
+static void session_capture(rpd_session* S) {
+  hip_check(hipStreamBeginCapture(S->stream, hipStreamCaptureModeThreadLocal), "begin capture");
+  try {
+    session_round(S);
+  } catch (...) {
+    hipGraph_t g = nullptr;
+    (void)hipStreamEndCapture(S->stream, &g);
+    if (g) (void)hipGraphDestroy(g);
+    throw;
+  }
+  hip_check(hipStreamEndCapture(S->stream, &S->graph), "end capture");
+  hip_check(hipGraphInstantiate(&S->exec, S->graph, nullptr, nullptr, 0), "graph instantiate");
+}
+
+struct DeviceGuard {  // make the session's device current for the call, restore the caller's afterwards
+  int prev = -1;
+  explicit DeviceGuard(int dev) {
+    hip_check(hipGetDevice(&prev), "hipGetDevice");
+    if (prev != dev) hip_check(hipSetDevice(dev), "hipSetDevice");
+  }
+  ~DeviceGuard() {
+    int cur = -1;
+    if (prev >= 0 && hipGetDevice(&cur) == hipSuccess && cur != prev) (void)hipSetDevice(prev);
+  }
+};
+
+}  // namespace rpd
+
+extern "C" {
+
+rpd_status rpd_session_create(const rpd_mesh* mesh, const rpd_sites* sites, const rpd_sites* table,
+                              const rpd_session_opts* opts, rpd_session** out) {
+  if (out) *out = nullptr;
+  RPD_GUARD_BEGIN
+  rpd::set_error("");
+  if (!mesh || !sites || !table || !opts || !out) throw Failure{RPD_E_INVALID, "null argument"};
+  const rpd_opts& o = opts->build;
+  if (o.precision != RPD_FP32_FALLBACK && o.precision != RPD_FP64) throw Failure{RPD_E_INVALID, "bad precision"};
+  if (o.clip_budget != 0 && (o.clip_budget < 4 || o.clip_budget > rpd::KMAX))
+    throw Failure{RPD_E_INVALID, "clip_budget must be 0 or in [4, 28]"};
+  if (o.block != 0 && o.block != 64 && o.block != 128) throw Failure{RPD_E_INVALID, "block must be 0, 64 or 128"};
+  if (o.flags & (RPD_KEEP_PIECES | RPD_FORCE_SLOW_PATH))
+    throw Failure{RPD_E_INVALID, "RPD_KEEP_PIECES and RPD_FORCE_SLOW_PATH are not available in a session"};
+  if (sites->n_sites <= 0 || !sites->sx || !sites->sy || !sites->sz || !sites->sr)
+    throw Failure{RPD_E_INVALID, "no initial sites"};
+  if (opts->max_sites < sites->n_sites || opts->max_sites >= (1 << 21))
+    throw Failure{RPD_E_INVALID, "max_sites must be in [n_sites, 2^21)"};
+  if (opts->max_insert < 1 || opts->max_insert > 4096) throw Failure{RPD_E_INVALID, "max_insert must be in [1, 4096]"};
+  if (table->n_sites != mesh->nt || !table->sx || !table->sy || !table->sz || !table->sr)
+    throw Failure{RPD_E_INVALID, "the table needs one sphere per tet"};
+  if (mesh->nblk <= 0) throw Failure{RPD_E_INVALID, "empty mesh"};
+  if (o.stream) rpd::hip_check(hipStreamSynchronize((hipStream_t)o.stream), "synchronize");
+  rpd_session* S = new rpd_session();
+  try {
+    rpd::hip_check(hipGetDevice(&S->device), "hipGetDevice");
+    if (S->device != mesh->device) throw Failure{RPD_E_INVALID, "the mesh lives on another device"};
+    S->mesh = mesh;
+    S->o = o;
+    S->max_sites = opts->max_sites;
+    S->max_insert = opts->max_insert;
+    S->kmax = o.clip_budget > 0 ? std::min(o.clip_budget, rpd::KMAX) : rpd::KMAX;
+    rpd::hip_check(hipStreamCreateWithFlags(&S->stream, hipStreamNonBlocking), "stream");
+    for (auto& e : S->ev) rpd::hip_check(hipEventCreate(&e), "hipEventCreate");
+    int n0 = sites->n_sites;
+    long long ns_tot = 0, nt_tot = 0;
+    const rpd_mesh* ms[1] = {mesh};
+    S->hd = rpd::shape_table(ms, &n0, 1, &ns_tot, &nt_tot)[0];
+    bool done = false;
+    for (int scale = 2; scale <= 16 && !done; scale *= 2) done = rpd::session_init(S, sites, table, scale);
+    if (!done) throw Failure{RPD_E_NOMEM, "session tables kept overflowing"};
+    rpd::session_capture(S);
+  } catch (...) {
+    delete S;
+    throw;
+  }
+  *out = S;
+  return RPD_OK;
+  RPD_GUARD_END
+}
+
+rpd_status rpd_session_run(rpd_session* S, int32_t rounds) {
+  RPD_GUARD_BEGIN
+  rpd::set_error("");
+  if (!S || rounds < 0) throw Failure{RPD_E_INVALID, "null session or negative round count"};
+  if (S->failed) throw Failure{RPD_E_INVALID, "the session failed earlier"};
+  rpd::DeviceGuard g(S->device);
+  try {
+    rpd::hip_check(hipEventRecord(S->ev[0], S->stream), "hipEventRecord");
+    for (int k = 0; k < rounds; ++k) rpd::hip_check(hipGraphLaunch(S->exec, S->stream), "graph launch");
+    rpd::hip_check(hipEventRecord(S->ev[1], S->stream), "hipEventRecord");
+    rpd::check_status(S);
+    float ms = 0;
+    rpd::hip_check(hipEventElapsedTime(&ms, S->ev[0], S->ev[1]), "hipEventElapsedTime");
+    S->ms_last = ms;
+    S->rounds += rounds;
+  } catch (...) {
+    S->failed = true;
+    throw;
+  }
+  return RPD_OK;
+  RPD_GUARD_END
+}
+
+rpd_status rpd_session_get_info(rpd_session* S, rpd_session_info* info) {
+  RPD_GUARD_BEGIN
+  if (!S || !info) throw Failure{RPD_E_INVALID, "null argument"};
+  rpd::DeviceGuard g(S->device);
+  int h[rpd::SI_COUNT];
+  rpd::hip_check(hipMemcpyAsync(h, S->ints.p, sizeof(h), hipMemcpyDeviceToHost, S->stream), "download");
+  rpd::hip_check(hipStreamSynchronize(S->stream), "synchronize");
+  info->n_sites = h[rpd::SI_NS];
+  info->rounds = S->rounds;
+  info->n_selected = h[rpd::SI_NSEL];
+  info->n_blocks = S->mesh->nblk;
+  info->n_inserted = h[rpd::SI_INS];
+  info->n_dirty_blocks = h[rpd::SI_DIRTY];
+  unsigned long long cand = 0;
+  rpd::hip_check(hipMemcpy(&cand, S->D.cnt() + rpd::C_CAND, sizeof(cand), hipMemcpyDeviceToHost), "download");
+  info->n_clipped = (int64_t)cand;
+  info->ms_last_run = S->ms_last;
+  return RPD_OK;
+  RPD_GUARD_END
+}
+
+rpd_status rpd_session_sites(rpd_session* S, int32_t cap, float* xyzr, int32_t* n_out) {
+  RPD_GUARD_BEGIN
+  if (!S || !xyzr || !n_out) throw Failure{RPD_E_INVALID, "null argument"};
+  rpd::DeviceGuard g(S->device);
+  int n = 0;
+  rpd::hip_check(hipMemcpyAsync(&n, S->ints.as<int>() + rpd::SI_NS, sizeof(int), hipMemcpyDeviceToHost, S->stream),
+                 "download");
+  rpd::hip_check(hipStreamSynchronize(S->stream), "synchronize");
+  if (n > cap) throw Failure{RPD_E_INVALID, "output buffer too small for the session's sites"};
+  rpd::hip_check(hipMemcpyAsync(xyzr, S->D.site.p, sizeof(float4) * (size_t)n, hipMemcpyDeviceToHost, S->stream),
+                 "download");
+  rpd::hip_check(hipStreamSynchronize(S->stream), "synchronize");
+  *n_out = n;
+  return RPD_OK;
+  RPD_GUARD_END
+}
+
+rpd_status rpd_session_result(rpd_session* S, rpd_result** out) {
+  if (out) *out = nullptr;
+  RPD_GUARD_BEGIN
+  rpd::set_error("");
+  if (!S || !out) throw Failure{RPD_E_INVALID, "null argument"};
+  if (S->failed) throw Failure{RPD_E_INVALID, "the session failed earlier"};
+  rpd::DeviceGuard g(S->device);
+  int n = 0;
+  rpd::hip_check(hipMemcpyAsync(&n, S->ints.as<int>() + rpd::SI_NS, sizeof(int), hipMemcpyDeviceToHost, S->stream),
+                 "download");
+  rpd::hip_check(hipStreamSynchronize(S->stream), "synchronize");
+  std::vector<rpd::ShapeDesc> hd{S->hd};
+  hd[0].ns = n;
+  rpd_result* r = new rpd_result();
+  std::memset(&r->stats, 0, sizeof(r->stats));
+  try {
+    r->shapes.resize(1);
+    rpd::Timing tm(false);
+    const rpd_mesh* ms[1] = {S->mesh};
+    if (!rpd::collect(S->D, hd, S->dshapes.as<rpd::ShapeDesc>() + 1, ms, S->stream, tm, r->shapes, r->stats))
+      throw Failure{RPD_E_NOMEM, "session tables are full"};
+  } catch (...) {
+    delete r;
+    throw;
+  }
+  *out = r;
+  return RPD_OK;
+  RPD_GUARD_END
+}
+
+void rpd_session_free(rpd_session* S) {
+  if (!S) return;
+  const int dev = S->device;
+  int prev = -1;
+  (void)hipGetDevice(&prev);
+  if (prev != dev) (void)hipSetDevice(dev);
+  delete S;
+  if (prev >= 0 && prev != dev) (void)hipSetDevice(prev);
+}
 
 }  // extern "C"

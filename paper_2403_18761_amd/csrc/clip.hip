@@ -365,8 +365,17 @@ __global__ __launch_bounds__(NT) void k_clip_fast(ShapeArgs a) {
   if (item >= (a.nitems_dev ? *a.nitems_dev : a.nitems)) break;
   const int2 wi = a.items[item];
   const ShapeDesc sd = a.shapes[__builtin_amdgcn_readfirstlane(wi.x)];
-  const int t0 = sd.blk[wi.y];
-  const int ntb = sd.blk[wi.y + 1] - t0;
+  const int tb0 = sd.blk[wi.y];
+  const int ntb_all = sd.blk[wi.y + 1] - tb0;
+  // A block whose shared site list overflows is redone in chunks of SUB tets (smaller boxes, shorter lists);
+  // only tets of a chunk that still overflows go to the large-capacity kernel.
+  int sub = 0, sub_n = ntb_all;
+  bool split = false;
+  while (true) {
+  const int t0 = tb0 + sub;
+  const int ntb = sub_n;
+  int tpt = TPT;  // threads per tet in the candidate phase
+  while (tpt < 64 && 2 * tpt * ntb <= NT) tpt *= 2;
 
   // ---- 1. load the tets, their face planes and the bounding box
   float lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
@@ -433,11 +442,18 @@ __global__ __launch_bounds__(NT) void k_clip_fast(ShapeArgs a) {
   }
   __syncthreads();
   const int nsl = s_nsl;
+  if (nsl > SLMAX && !split && ntb > SUB && !(a.flags & RPD_FORCE_SLOW_PATH)) {
+    split = true;
+    sub_n = SUB;
+    if (tid == 0) atomicAdd(&a.counters[C_SPLIT], 1ull);
+    __syncthreads();
+    continue;
+  }
   const bool block_overflow = nsl > SLMAX || (a.flags & RPD_FORCE_SLOW_PATH);
 
   // ---- 3. candidates of every tet: sites whose minimum over the tet is <= min_j max over the tet
   if (!block_overflow) {
-    const int lt = tid / TPT, h = tid % TPT;
+    const int lt = tid / tpt, h = tid % tpt;
     if (lt < ntb) {
       const float4* tv = s_tv[lt];
       const float4 o = tv[0];
@@ -450,7 +466,7 @@ __global__ __launch_bounds__(NT) void k_clip_fast(ShapeArgs a) {
       const double ycx = (y[0][0] + y[1][0] + y[2][0]) * 0.25, ycy = (y[0][1] + y[1][1] + y[2][1]) * 0.25,
                    ycz = (y[0][2] + y[1][2] + y[2][2]) * 0.25;
       double U = INFINITY;
-      for (int q = h; q < nsl; q += TPT) {
+      for (int q = h; q < nsl; q += tpt) {
         float4 s = s_site[q];
         double ax_ = (double)s.x - o.x, ay_ = (double)s.y - o.y, az_ = (double)s.z - o.z;
         double D = ax_ * ax_ + ay_ * ay_ + az_ * az_ - (double)s.w * s.w;
@@ -458,9 +474,9 @@ __global__ __launch_bounds__(NT) void k_clip_fast(ShapeArgs a) {
         for (int v = 0; v < 3; ++v) gmx = fmax(gmx, D - 2.0 * (y[v][0] * ax_ + y[v][1] * ay_ + y[v][2] * az_));
         U = fmin(U, gmx);
       }
-      for (int off = 1; off < TPT; off <<= 1) U = fmin(U, __shfl_xor(U, off));
+      for (int off = 1; off < tpt; off <<= 1) U = fmin(U, __shfl_xor(U, off));
       if (a.tet_U && a.sign > 0 && h == 0) a.tet_U[sd.tet_off + t0 + lt] = U;
-      for (int q = h; q < nsl; q += TPT) {
+      for (int q = h; q < nsl; q += tpt) {
         float4 s = s_site[q];
         double ax_ = (double)s.x - o.x, ay_ = (double)s.y - o.y, az_ = (double)s.z - o.z;
         double D = ax_ * ax_ + ay_ * ay_ + az_ * az_ - (double)s.w * s.w;
@@ -486,6 +502,7 @@ __global__ __launch_bounds__(NT) void k_clip_fast(ShapeArgs a) {
                                                                          s_key[tid], m, true);
     if (block_overflow || m > a.kmax) {
       s_m[tid] = -1;
+      atomicAdd(&a.counters[block_overflow ? C_DEFER_BLOCK : C_DEFER_KMAX], 1ull);
       unsigned long long idx = atomicAdd(&a.counters[C_DEFER_ITEMS], 1ull);
       if (idx < (unsigned long long)a.deferred_cap) a.deferred[idx] = make_int4(wi.x, t0 + tid, -1, 0);
       else atomicOr(a.status, ST_TABLE_FULL);
@@ -556,10 +573,17 @@ __global__ __launch_bounds__(NT) void k_clip_fast(ShapeArgs a) {
       ++n_pairs;
       emit_piece(cl, sd, t0 + lt, a);
     } else if (r == CLIP_DEFER) {
+      atomicAdd(&a.counters[C_DEFER_CLIP], 1ull);
       unsigned long long idx = atomicAdd(&a.counters[C_DEFER_ITEMS], 1ull);
       if (idx < (unsigned long long)a.deferred_cap) a.deferred[idx] = make_int4(wi.x, t0 + lt, cl.env.site_i, 0);
       else atomicOr(a.status, ST_TABLE_FULL);
     }
+  }
+  if (!split) break;
+  sub += SUB;
+  if (sub >= ntb_all) break;
+  sub_n = min(SUB, ntb_all - sub);
+  __syncthreads();  // the next chunk reuses every shared array
   }
   } while (false);
   if (tid < 4) s_cnt[tid] = 0;
@@ -567,40 +591,41 @@ __global__ __launch_bounds__(NT) void k_clip_fast(ShapeArgs a) {
   atomicAdd(&s_cnt[0], n_pairs);
   atomicAdd(&s_cnt[1], n64);
   __syncthreads();
-  if (tid == 0) {
-    atomicAdd(&a.counters[C_PAIRS], s_cnt[0]);
-    atomicAdd(&a.counters[C_FP64], s_cnt[1]);
+  if (tid == 0 && n_cand) {
+    // live pieces: a removal pass (sign -1) subtracts in two's complement
+    if (s_cnt[0]) atomicAdd(&a.counters[C_PAIRS], a.sign > 0 ? s_cnt[0] : 0ull - s_cnt[0]);
+    if (s_cnt[1]) atomicAdd(&a.counters[C_FP64], s_cnt[1]);
     atomicAdd(&a.counters[C_CAND], n_cand);
   }
 }
 
 // ---------------------------------------------------------------------------------------------------------------
-// large-capacity kernel: one thread per deferred item, FP64 constructions, exact predicates, global scratch
+// large-capacity kernel: one wavefront per deferred item, FP64 constructions, exact predicates, global scratch
 // ---------------------------------------------------------------------------------------------------------------
-struct SlowScratch {  // per wave: the candidate list; per lane: one piece's polytope and plane table
+struct SlowScratch {  // per wave: the candidate list, then every lane's polytope and plane table, lane-interleaved
   static constexpr size_t cand_bytes = SLOW_KMAX * sizeof(int);
   static constexpr size_t key_bytes = SLOW_KMAX * sizeof(double);
   static constexpr size_t wave_bytes = cand_bytes + key_bytes;
-  static constexpr size_t xyz_bytes = SLOW_VMAX * sizeof(Coord4<double>::type);
-  static constexpr size_t topo_bytes = SLOW_VMAX * sizeof(unsigned long long);
-  static constexpr size_t tab_bytes = (SLOW_PMAX + 15) / 16 * 16;
-  static constexpr size_t lane_bytes = xyz_bytes + topo_bytes + tab_bytes;
-  static constexpr size_t bytes = wave_bytes + 64 * lane_bytes;  // one wave
+  static constexpr size_t xyz_bytes = 64 * SLOW_VMAX * sizeof(Coord4<double>::type);  // [slot][lane]
+  static constexpr size_t topo_bytes = 64 * SLOW_VMAX * sizeof(unsigned long long);    // [slot][lane]
+  static constexpr size_t tab_bytes = 64 * (size_t)SLOW_PMAX;                          // [plane][lane]
+  static constexpr size_t bytes = wave_bytes + xyz_bytes + topo_bytes + tab_bytes;
 };
 
 // One wavefront per deferred item: the lanes split the scan over all of the shape's sites (candidates are
-// compacted in ascending site order by ballots), lane 0 sorts them, then every lane clips its own pieces.
+// compacted in ascending site order by ballots), lane 0 sorts them, then every lane clips its own pieces. The
+// lanes' polytopes are interleaved slot by slot, so lanes that touch the same slot read one contiguous line.
 __global__ __launch_bounds__(64) void k_clip_slow(ShapeArgs a, unsigned char* scratch) {
   const int n_items = (int)min(a.counters[C_DEFER_ITEMS], (unsigned long long)a.deferred_cap);
   const int lane = threadIdx.x;
   unsigned char* wbase = scratch + (size_t)blockIdx.x * SlowScratch::bytes;
   int* cand = (int*)wbase;
   double* key = (double*)(wbase + SlowScratch::cand_bytes);
-  unsigned char* lbase = wbase + SlowScratch::wave_bytes + (size_t)lane * SlowScratch::lane_bytes;
-  Coord4<double>::type* xyz = (Coord4<double>::type*)lbase;
-  unsigned long long* topo = (unsigned long long*)(lbase + SlowScratch::xyz_bytes);
-  unsigned char* tab = lbase + SlowScratch::xyz_bytes + SlowScratch::topo_bytes;
-  for (int k = 0; k < SLOW_PMAX; ++k) tab[k] = 0;
+  Coord4<double>::type* xyz = (Coord4<double>::type*)(wbase + SlowScratch::wave_bytes) + lane;
+  unsigned long long* topo =
+      (unsigned long long*)(wbase + SlowScratch::wave_bytes + SlowScratch::xyz_bytes) + lane;
+  unsigned char* tab = wbase + SlowScratch::wave_bytes + SlowScratch::xyz_bytes + SlowScratch::topo_bytes + lane;
+  for (int k = 0; k < SLOW_PMAX; ++k) tab[64 * k] = 0;
   unsigned long long n_pairs = 0, n64 = 0, nex = 0;
   for (int it = blockIdx.x; it < n_items; it += gridDim.x) {
     const int4 di = a.deferred[it];
@@ -678,9 +703,9 @@ __global__ __launch_bounds__(64) void k_clip_slow(ShapeArgs a, unsigned char* sc
       Clipper<double, Topo64, unsigned long long, SLOW_VMAX, true> cl;
       cl.st.c = xyz;
       cl.st.w = topo;
-      cl.st.stride = 1;
+      cl.st.stride = 64;
       cl.tab = tab;
-      cl.tst = 1;
+      cl.tst = 64;
       cl.a = &a;
       cl.flags = a.flags & ~RPD_FORCE_FP64;
       cl.np = 4 + m;
@@ -715,7 +740,7 @@ __global__ __launch_bounds__(64) void k_clip_slow(ShapeArgs a, unsigned char* sc
     nex += __shfl_xor(nex, off);
   }
   if (lane == 0) {
-    if (n_pairs) atomicAdd(&a.counters[C_PAIRS], n_pairs);
+    if (n_pairs) atomicAdd(&a.counters[C_PAIRS], a.sign > 0 ? n_pairs : 0ull - n_pairs);
     if (n64) atomicAdd(&a.counters[C_FP64], n64);
     if (nex) atomicAdd(&a.counters[C_EXACT], nex);
   }

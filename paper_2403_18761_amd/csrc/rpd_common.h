@@ -11,6 +11,7 @@ constexpr int TB = 64;       // tets per workgroup
 constexpr int KMAX = 28;     // candidate sites per tet (plane ids 4 + position must fit 5 bits)
 constexpr int VMAX = 16;     // vertex slots of one piece (4-bit neighbour ids)
 constexpr int SLMAX = 256;   // sites in a workgroup's shared candidate list
+constexpr int SUB = 8;       // tets per chunk when a block's site list overflows
 // Large-capacity (deferred) path.
 constexpr int SLOW_KMAX = 1020;  // candidate sites per tet
 constexpr int SLOW_VMAX = 64;    // vertex slots of one piece
@@ -24,7 +25,14 @@ constexpr int ST_SLOW_CAPACITY = 8;  // the deferred path ran out of candidate o
 constexpr int ST_INVALID = 16;       // invalid site value (off grid, out of range, not finite)
 
 // counters (ShapeArgs::counters)
-enum { C_PAIRS = 0, C_CAND, C_FP64, C_EXACT, C_DEFER_ITEMS, C_GLUE, C_RPV, C_PIECES, C_NODES, NCOUNTERS };
+enum {
+  C_PAIRS = 0, C_CAND, C_FP64, C_EXACT, C_DEFER_ITEMS, C_GLUE, C_RPV, C_PIECES, C_NODES,
+  C_DEFER_BLOCK,  // tets deferred because the workgroup's site list overflowed
+  C_DEFER_KMAX,   // tets deferred because they kept more than the candidate budget
+  C_DEFER_CLIP,   // pieces deferred because the polytope outgrew the vertex slots
+  C_SPLIT,        // workgroup blocks redone in chunks because their site list overflowed
+  NCOUNTERS
+};
 // C_RPV counts RPV emissions; the RPV list itself is the set of keys of ShapeArgs::Q with a positive count
 
 constexpr unsigned long long EMPTY_KEY = ~0ull;
@@ -111,5 +119,30 @@ __device__ inline int shape_of_tet(const ShapeDesc* sd, int n, long long gt) {
   }
   return lo;
 }
+
+
+// Device state of one round of the incremental session (all counts live in device memory so that the round is a
+// fixed launch sequence).
+struct RoundState {
+  int* nsel;                  // cells selected this round
+  int* sel;                   // [max_insert] selected cells, ascending
+  int* selpos;                // [max_sites] position of a cell in sel, or -1
+  unsigned long long* best;   // [max_insert] packed (hash, tet) of the tet chosen for the cell
+  int* ref;                   // [max_insert] smallest tet among the cell's pieces
+  int* tet_used;              // [nt] the tet's sphere has been inserted
+  const float4* table;        // [nt] the sphere to insert for every tet (internal tet order)
+  const int* tet_block;       // [nt] workgroup block of every tet
+  int* dirty;                 // [nblk] block flags
+  int2* items;                // [nblk] dirty (shape 0, block) items, ascending
+  int* nitems;
+  int* round;
+  int* ns_cur;                // sites in use
+  int* ins_total;             // spheres inserted over all rounds
+  int* dirty_total;           // dirty blocks over all rounds
+  ShapeDesc* old_desc;        // the shape with the sites before this round's insertions
+  ShapeDesc* new_desc;        // ... and after them
+  int max_sites;
+  int max_insert;
+};
 
 }  // namespace rpd

@@ -29,18 +29,19 @@ inline void hip_check(hipError_t e, const char* what) {
 // Caching device allocator: freed blocks are kept in per-device free lists keyed by their power-of-two size class
 // and reused, so repeated rpd_build calls do not pay hipMalloc/hipFree. Memory returns to the runtime only when the
 // process ends.
-void* pool_alloc(size_t bytes, size_t* cls_bytes);
-void pool_free(void* p, size_t cls_bytes);
+void* pool_alloc(size_t bytes, size_t* cls_bytes, int* device);
+void pool_free(void* p, size_t cls_bytes, int device);
 
 // owning device allocation (through the pool)
 struct DBuf {
   void* p = nullptr;
   size_t bytes = 0;
+  int dev = 0;  // the device the block belongs to (its free list)
   DBuf() = default;
   explicit DBuf(size_t n) { alloc(n); }
   DBuf(const DBuf&) = delete;
   DBuf& operator=(const DBuf&) = delete;
-  DBuf(DBuf&& o) noexcept : p(o.p), bytes(o.bytes) {
+  DBuf(DBuf&& o) noexcept : p(o.p), bytes(o.bytes), dev(o.dev) {
     o.p = nullptr;
     o.bytes = 0;
   }
@@ -48,6 +49,7 @@ struct DBuf {
     release();
     p = o.p;
     bytes = o.bytes;
+    dev = o.dev;
     o.p = nullptr;
     o.bytes = 0;
     return *this;
@@ -56,10 +58,10 @@ struct DBuf {
   void alloc(size_t n) {
     release();
     if (n == 0) n = 16;
-    p = pool_alloc(n, &bytes);
+    p = pool_alloc(n, &bytes, &dev);
   }
   void release() {
-    if (p) pool_free(p, bytes);
+    if (p) pool_free(p, bytes, dev);
     p = nullptr;
     bytes = 0;
   }

@@ -44,4 +44,12 @@ hipError_t launch_sort_rpv(const int4* rpv, int n, unsigned long long* ka, unsig
 hipError_t launch_validate_sites(const float* sx, const float* sy, const float* sz, const float* sr, int ns,
                                  float4* site, int* status, hipStream_t s);
 
+
+// session.hip
+hipError_t launch_gather_table(const float4* src, const int* perm, int nt, float4* dst, hipStream_t s);
+// selection, insertion and dirty marking of one round; a supplies the element tables and sites of the new shape
+hipError_t launch_round_front(const RoundState& r, const ShapeArgs& a, const int* parent, const int* cell_b0,
+                              const float4* tp, int nt, int nblk, hipStream_t s);
+hipError_t launch_round_end(const RoundState& r, hipStream_t s);
+
 }  // namespace rpd

@@ -1,0 +1,218 @@
+// Incremental RPD update inside a topology-repair loop (paper Sec. 4: spheres are inserted where an element is not
+// contractible, and the RPD is updated only for the cells related to the new spheres, Sec. 4 overview and Sec. 5.2).
+//
+// One round, all on the device with device-side counts (so the round is captured once as a HIP graph):
+//   1. select up to M violating cells (nonempty, chi != 1 or beta0 > 1), lowest ids first;
+//   2. for each, pick a tet among the cell's pieces (outside the component of its first piece when beta0 > 1) by a
+//      deterministic hash of (tet, round), and insert the sphere the caller's per-tet table gives for that tet;
+//   3. mark the workgroup blocks whose tets a new sphere may own (the exact candidate test against the stored U_t);
+//   4. remove the contributions of the dirty blocks computed with the old sites, add them back with the new sites
+//      (every accumulator is an exactly invertible integer), and recompute beta0 of the live element pieces.
+#include <hip/hip_runtime.h>
+
+#include "rpd_device.h"
+#include "rpd_launch.h"
+
+namespace rpd {
+
+
+__global__ void k_round_begin(RoundState r) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) {
+    *r.nsel = 0;
+    *r.nitems = 0;
+  }
+}
+
+// first M violating cells in ascending order (one workgroup, chunked ballot compaction)
+__global__ __launch_bounds__(256) void k_select(RoundState r, const long long* cell_chi, const int* cell_np,
+                                                const int* cell_b0) {
+  __shared__ int s_count;
+  __shared__ int s_warp[4];
+  const int n = *r.ns_cur;
+  const long long L = r.new_desc->L;
+  if (threadIdx.x == 0) s_count = 0;
+  __syncthreads();
+  for (int base = 0; base < n; base += 256) {
+    const int i = base + threadIdx.x;
+    const bool v = i < n && cell_np[i] > 0 && (cell_chi[i] != L || cell_b0[i] > 1);
+    unsigned long long m = __ballot(v);
+    int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    if (lane == 0) s_warp[w] = __popcll(m);
+    __syncthreads();
+    int before = s_count;
+    for (int q = 0; q < w; ++q) before += s_warp[q];
+    int pos = before + __popcll(m & ((1ull << lane) - 1ull));
+    if (v && pos < r.max_insert) {
+      r.sel[pos] = i;
+      r.selpos[i] = pos;
+      r.best[pos] = 0ull;
+      r.ref[pos] = 0x7fffffff;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) s_count += s_warp[0] + s_warp[1] + s_warp[2] + s_warp[3];
+    __syncthreads();
+    if (s_count >= r.max_insert) break;
+  }
+  if (threadIdx.x == 0) *r.nsel = min(s_count, r.max_insert);
+}
+
+__device__ inline int uf_root(const int* par, int x) {
+  while (true) {
+    int p = par[x];
+    if (p == x) return x;
+    x = p;
+  }
+}
+
+__global__ void k_ref_tet(HashTab N, const int* node_cnt, RoundState r) {
+  const unsigned cap = N.mask + 1;
+  for (unsigned s = blockIdx.x * blockDim.x + threadIdx.x; s < cap; s += gridDim.x * blockDim.x) {
+    unsigned long long key = N.keys[s];
+    if (key == EMPTY_KEY || node_cnt[s] <= 0 || (key >> 62) != 1) continue;
+    int cell = (int)((key >> 32) & 0x3fffffff);
+    int k = r.selpos[cell];
+    if (k >= 0) atomicMin(&r.ref[k], (int)(key & 0xffffffffull));
+  }
+}
+
+__device__ inline unsigned mix_hash(unsigned long long x) {  // splitmix64 finaliser
+  x += 0x9E3779B97F4A7C15ull;
+  x = (x ^ (x >> 30)) * 0xBF58476D1CE4E5B9ull;
+  x = (x ^ (x >> 27)) * 0x94D049BB133111EBull;
+  return (unsigned)((x ^ (x >> 31)) >> 32);
+}
+
+__global__ void k_pick_tet(HashTab N, const int* node_cnt, const int* parent, const int* cell_b0, RoundState r) {
+  const unsigned cap = N.mask + 1;
+  const int round = *r.round;
+  for (unsigned s = blockIdx.x * blockDim.x + threadIdx.x; s < cap; s += gridDim.x * blockDim.x) {
+    unsigned long long key = N.keys[s];
+    if (key == EMPTY_KEY || node_cnt[s] <= 0 || (key >> 62) != 1) continue;
+    int cell = (int)((key >> 32) & 0x3fffffff);
+    int k = r.selpos[cell];
+    if (k < 0) continue;
+    int t = (int)(key & 0xffffffffull);
+    if (r.tet_used[t]) continue;
+    if (cell_b0[cell] > 1) {  // pick outside the component of the cell's first piece
+      int rs = ht_find(N, (key & ~0xffffffffull) | (unsigned)r.ref[k]);
+      if (rs >= 0 && uf_root(parent, rs) == uf_root(parent, (int)s)) continue;
+    }
+    unsigned h = mix_hash(((unsigned long long)(unsigned)t << 32) | (unsigned)round);
+    atomicMax(&r.best[k], ((unsigned long long)h << 32) | (unsigned)t);
+  }
+}
+
+// one thread: insert in selection order (deterministic site ids), update the two shape descriptors
+__global__ void k_insert(RoundState r, float4* site) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  const int n0 = *r.ns_cur;
+  int n = n0;
+  const int nsel = *r.nsel;
+  for (int k = 0; k < nsel; ++k) {
+    unsigned long long b = r.best[k];
+    if (b == 0ull || n >= r.max_sites) continue;
+    int t = (int)(b & 0xffffffffull);
+    if (r.tet_used[t]) continue;
+    r.tet_used[t] = 1;
+    site[n++] = r.table[t];
+  }
+  r.old_desc->ns = n0;
+  r.new_desc->ns = n;
+  *r.ins_total += n - n0;
+}
+
+// a tet is dirty if one of the new spheres passes its exact candidate test against the stored U_t
+__global__ void k_mark_dirty(RoundState r, const float4* tp, int nt, const float4* site, const double* tet_U) {
+  const int n0 = r.old_desc->ns, n1 = r.new_desc->ns;
+  if (n1 == n0) return;
+  for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < nt; t += gridDim.x * blockDim.x) {
+    const float4* tv = tp + 4 * (size_t)t;
+    const float4 o = tv[0];
+    const double U = tet_U[t];
+    bool dirty = false;
+    for (int j = n0; j < n1 && !dirty; ++j) {
+      float4 s = site[j];
+      double ax = (double)s.x - o.x, ay = (double)s.y - o.y, az = (double)s.z - o.z;
+      double D = ax * ax + ay * ay + az * az - (double)s.w * s.w;
+      double gmn = D;
+      for (int v = 1; v < 4; ++v)
+        gmn = fmin(gmn, D - 2.0 * (((double)tv[v].x - o.x) * ax + ((double)tv[v].y - o.y) * ay +
+                                   ((double)tv[v].z - o.z) * az));
+      dirty = gmn <= U;
+    }
+    if (dirty) r.dirty[r.tet_block[t]] = 1;
+  }
+}
+
+// dirty blocks -> work items in ascending block order (one workgroup), then clear the flags
+__global__ __launch_bounds__(256) void k_dirty_items(RoundState r, int nblk) {
+  __shared__ int s_count;
+  __shared__ int s_warp[4];
+  if (threadIdx.x == 0) s_count = 0;
+  __syncthreads();
+  for (int base = 0; base < nblk; base += 256) {
+    const int b = base + threadIdx.x;
+    const bool d = b < nblk && r.dirty[b] != 0;
+    unsigned long long m = __ballot(d);
+    int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    if (lane == 0) s_warp[w] = __popcll(m);
+    __syncthreads();
+    int before = s_count;
+    for (int q = 0; q < w; ++q) before += s_warp[q];
+    if (d) {
+      r.items[before + __popcll(m & ((1ull << lane) - 1ull))] = make_int2(0, b);
+      r.dirty[b] = 0;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) s_count += s_warp[0] + s_warp[1] + s_warp[2] + s_warp[3];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    *r.nitems = s_count;
+    *r.dirty_total += s_count;
+  }
+}
+
+__global__ void k_round_end(RoundState r) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  const int nsel = *r.nsel;
+  for (int k = 0; k < nsel; ++k) r.selpos[r.sel[k]] = -1;
+  *r.ns_cur = r.new_desc->ns;
+  *r.round += 1;
+}
+
+__global__ void k_gather_table(const float4* src, const int* perm, int nt, float4* dst) {
+  for (int k = blockIdx.x * blockDim.x + threadIdx.x; k < nt; k += gridDim.x * blockDim.x) dst[k] = src[perm[k]];
+}
+
+static int gsz(size_t n) {
+  size_t g = (n + 255) / 256;
+  if (g > 65536) g = 65536;
+  return (int)(g ? g : 1);
+}
+
+hipError_t launch_gather_table(const float4* src, const int* perm, int nt, float4* dst, hipStream_t s) {
+  hipLaunchKernelGGL(k_gather_table, dim3(gsz(nt)), dim3(256), 0, s, src, perm, nt, dst);
+  return hipGetLastError();
+}
+
+// the round's selection and insertion (everything before the clip passes)
+hipError_t launch_round_front(const RoundState& r, const ShapeArgs& a, const int* parent, const int* cell_b0,
+                              const float4* tp, int nt, int nblk, hipStream_t s) {
+  hipLaunchKernelGGL(k_round_begin, dim3(1), dim3(64), 0, s, r);
+  hipLaunchKernelGGL(k_select, dim3(1), dim3(256), 0, s, r, a.cell_chi, a.cell_np, cell_b0);
+  const size_t cap = (size_t)a.N.mask + 1;
+  hipLaunchKernelGGL(k_ref_tet, dim3(gsz(cap)), dim3(256), 0, s, a.N, a.node_cnt, r);
+  hipLaunchKernelGGL(k_pick_tet, dim3(gsz(cap)), dim3(256), 0, s, a.N, a.node_cnt, parent, cell_b0, r);
+  hipLaunchKernelGGL(k_insert, dim3(1), dim3(64), 0, s, r, (float4*)a.site);
+  hipLaunchKernelGGL(k_mark_dirty, dim3(gsz(nt)), dim3(256), 0, s, r, tp, nt, a.site, a.tet_U);
+  hipLaunchKernelGGL(k_dirty_items, dim3(1), dim3(256), 0, s, r, nblk);
+  return hipGetLastError();
+}
+
+hipError_t launch_round_end(const RoundState& r, hipStream_t s) {
+  hipLaunchKernelGGL(k_round_end, dim3(1), dim3(64), 0, s, r);
+  return hipGetLastError();
+}
+
+}  // namespace rpd

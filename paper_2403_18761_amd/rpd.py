@@ -53,7 +53,18 @@ class _Stats(C.Structure):
     _fields_ = [("n_pairs", C.c_int64), ("n_candidates", C.c_int64), ("n_deferred", C.c_int64),
                 ("n_fp64", C.c_int64), ("n_exact", C.c_int64), ("n_cells", C.c_int64), ("n_faces", C.c_int64),
                 ("n_edges", C.c_int64), ("n_rpv", C.c_int64), ("n_glue", C.c_int64), ("ms_clip", C.c_double),
-                ("ms_deferred", C.c_double), ("ms_reduce", C.c_double), ("ms_total", C.c_double)]
+                ("ms_deferred", C.c_double), ("ms_reduce", C.c_double), ("ms_total", C.c_double),
+                ("n_defer_block", C.c_int64), ("n_defer_kmax", C.c_int64), ("n_defer_clip", C.c_int64), ("n_split", C.c_int64)]
+
+
+class _SessionOpts(C.Structure):
+    _fields_ = [("max_sites", C.c_int32), ("max_insert", C.c_int32), ("build", _Opts)]
+
+
+class _SessionInfo(C.Structure):
+    _fields_ = [("n_sites", C.c_int32), ("rounds", C.c_int32), ("n_selected", C.c_int32), ("n_blocks", C.c_int32),
+                ("n_inserted", C.c_int64), ("n_dirty_blocks", C.c_int64), ("n_clipped", C.c_int64),
+                ("ms_last_run", C.c_double)]
 
 
 class RPDError(RuntimeError):
@@ -92,8 +103,17 @@ def load():
     lib.rpd_free.restype = None
     lib.rpd_last_error.restype = C.c_char_p
     lib.rpd_version.restype = C.c_char_p
+    lib.rpd_session_create.argtypes = [C.c_void_p, C.POINTER(_Sites), C.POINTER(_Sites), C.POINTER(_SessionOpts),
+                                       C.POINTER(C.c_void_p)]
+    lib.rpd_session_run.argtypes = [C.c_void_p, C.c_int32]
+    lib.rpd_session_result.argtypes = [C.c_void_p, C.POINTER(C.c_void_p)]
+    lib.rpd_session_get_info.argtypes = [C.c_void_p, C.POINTER(_SessionInfo)]
+    lib.rpd_session_sites.argtypes = [C.c_void_p, C.c_int32, C.POINTER(C.c_float), C.POINTER(C.c_int32)]
+    lib.rpd_session_free.argtypes = [C.c_void_p]
+    lib.rpd_session_free.restype = None
     for f in ("rpd_mesh_create", "rpd_mesh_get_info", "rpd_build", "rpd_euler", "rpd_components", "rpd_geometry",
-              "rpd_adjacency", "rpd_get_stats", "rpd_pieces"):
+              "rpd_adjacency", "rpd_get_stats", "rpd_pieces", "rpd_session_create", "rpd_session_run",
+              "rpd_session_result", "rpd_session_get_info", "rpd_session_sites"):
         getattr(lib, f).restype = C.c_int32
     _lib = lib
     return lib
@@ -244,3 +264,57 @@ def build(meshes, sites, precision: int = RPD_FP32_FALLBACK, clip_budget: int = 
 
 def version() -> str:
     return load().rpd_version().decode()
+
+
+class Session:
+    """Incremental sphere-insertion session over one mesh (rpd_session_*). ``sites`` and ``table`` are
+    (x, y, z, r) arrays or tensors; ``table`` has one sphere per tet in the caller's tet order."""
+
+    def __init__(self, mesh: Mesh, sites, table, max_sites: int, max_insert: int = 64,
+                 precision: int = RPD_FP32_FALLBACK, clip_budget: int = 0, block: int = 0, flags: int = 0,
+                 stream=None):
+        lib = load()
+        keep = []
+        dev = _is_torch(sites[0]) and sites[0].is_cuda
+        if dev != (_is_torch(table[0]) and table[0].is_cuda):
+            raise ValueError("sites and table must both be device tensors or both host arrays")
+
+        def mk(q):
+            return _Sites(int(q[0].shape[0]), *[_ptr(x, C.c_float, keep) for x in q])
+
+        st, tb = mk(sites), mk(table)
+        o = _SessionOpts(max_sites, max_insert,
+                         _Opts(precision, clip_budget, block, flags | (RPD_DEVICE_PTRS if dev else 0),
+                               _stream_ptr(stream)))
+        h = C.c_void_p()
+        _check(lib.rpd_session_create(mesh.handle, C.byref(st), C.byref(tb), C.byref(o), C.byref(h)))
+        self._h = h
+        self._lib = lib
+        self.mesh = mesh  # the session borrows the mesh
+        self.max_sites = max_sites
+
+    def run(self, rounds: int = 1):
+        _check(self._lib.rpd_session_run(self._h, rounds))
+
+    def result(self) -> Result:
+        h = C.c_void_p()
+        _check(self._lib.rpd_session_result(self._h, C.byref(h)))
+        return Result(h, 1)
+
+    def info(self) -> dict:
+        i = _SessionInfo()
+        _check(self._lib.rpd_session_get_info(self._h, C.byref(i)))
+        return {k: getattr(i, k) for k, _ in _SessionInfo._fields_}
+
+    def sites(self) -> np.ndarray:
+        """Current sites as an (n, 4) float32 array of (x, y, z, r)."""
+        out = np.zeros((self.max_sites, 4), np.float32)
+        n = C.c_int32()
+        _check(self._lib.rpd_session_sites(self._h, self.max_sites, out.ctypes.data_as(C.POINTER(C.c_float)),
+                                           C.byref(n)))
+        return out[: n.value].copy()
+
+    def __del__(self):
+        if getattr(self, "_h", None) and self._h.value:
+            self._lib.rpd_session_free(self._h)
+            self._h = C.c_void_p()

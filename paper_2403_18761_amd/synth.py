@@ -615,6 +615,83 @@ def batch_sizes(n_shapes: int = 256, seed: int = 4):
     return t, s
 
 
+def blobs_with_handles(N: int, seed: int, n_blobs: int = 5, max_attempts: int = 64):
+    """Separate metaball blobs on a jittered ring in the xy plane (field sum_k exp(-q_k(x)) > 1/2 with
+    q_k = (dx^2 + dy^2)/s_k^2 + dz^2/(1.8 s_k)^2, tall ellipsoids), each joined to the next by a thin capsule
+    handle (radius 0.06, at least 3.5 voxels on coarse grids), plus one chord handle from blob 0 to blob 2: a
+    genus-2 solid whose cells spanning the thin handles are the first to violate the topology constraints."""
+    hr = max(0.06, 3.5 * 2.0 / N)
+    for attempt in range(max_attempts):
+        rng = np.random.default_rng(seed * 1000 + attempt)
+        ang = 2 * math.pi * (np.arange(n_blobs) + rng.uniform(-0.06, 0.06, n_blobs)) / n_blobs
+        rad = 0.65 + rng.uniform(-0.02, 0.02, n_blobs)
+        cs = np.stack([rad * np.cos(ang), rad * np.sin(ang), rng.uniform(-0.05, 0.05, n_blobs)], axis=1)
+        ss = rng.uniform(0.295, 0.315, n_blobs)
+
+        def field(p, cs=cs, ss=ss):
+            acc = np.zeros(p.shape[:-1])
+            for c, sc in zip(cs, ss):
+                d = p - c
+                acc += np.exp(-(d[..., 0] ** 2 + d[..., 1] ** 2) / (sc * sc) - d[..., 2] ** 2 / (1.8 * sc) ** 2)
+            return 0.5 - acc
+
+        pairs = [(k, (k + 1) % n_blobs) for k in range(n_blobs)] + [(0, 2)]
+        sdf = union_sdf(field, *[_capsule_sdf(cs[a], cs[b], hr) for a, b in pairs])
+        occ = voxels_inside(sdf, N)
+        ok, _ = voxel_set_ok(occ, -1)
+        if ok and voxel_euler(voxels_inside(field, N)) >= n_blobs - 2:  # most blobs alone stay apart
+            return dict(kind="blobs_with_handles", sdf=sdf, occ=occ, genus=2, attempt=attempt, handles=len(pairs))
+    raise RuntimeError("no valid blobs-with-handles voxelisation found")
+
+
+def _jittered_centroids(prob: Problem, rng) -> np.ndarray:
+    """Tet centroids moved by a uniform offset of up to an eighth of the tet's shortest bounding-box side per axis,
+    so that inserted spheres sit in general position (bare centroids of a Kuhn grid lie on a lattice, where
+    bisectors of equal spheres pass exactly through mesh vertices)."""
+    v = np.stack([prob.vx, prob.vy, prob.vz], axis=1).astype(np.float64)
+    p = v[prob.tv]
+    ext = (p.max(axis=1) - p.min(axis=1)).min(axis=1)
+    return p.mean(axis=1) + rng.uniform(-0.125, 0.125, size=(p.shape[0], 3)) * ext[:, None]
+
+
+def centroid_table(prob: Problem, radius: float, seed: int = 0):
+    """An insertion table for any mesh: for every tet a sphere near its centroid (jittered, see
+    _jittered_centroids) with radius uniform in [0.9, 1.1] x radius."""
+    rng = np.random.default_rng(seed)
+    c = quantize(_jittered_centroids(prob, rng))
+    r = quantize(radius * rng.uniform(0.9, 1.1, size=c.shape[0]))
+    return (c[:, 0].astype(np.float32), c[:, 1].astype(np.float32), c[:, 2].astype(np.float32),
+            r.astype(np.float32))
+
+
+def _edt_radius(occ: np.ndarray, N: int, pts: np.ndarray, scale: float) -> np.ndarray:
+    """scale x (distance from the point's voxel centre to the nearest removed voxel centre - h/2): a distance to
+    the voxelised boundary that needs no analytic signed distance."""
+    edt = ndimage.distance_transform_edt(np.pad(occ, 1))[1:-1, 1:-1, 1:-1]
+    ijk = np.clip(np.floor((pts + 1.0) * N / 2.0).astype(np.int64), 0, N - 1)
+    h = 2.0 / N
+    return scale * np.maximum(edt[ijk[:, 0], ijk[:, 1], ijk[:, 2]] - 0.5, 0.0) * h
+
+
+def repair_problem(N: int = 128, n_sites: int = 500, seed: int = 5):
+    """The topology-repair workload: the genus-2 blobs-with-handles solid on an N^3 grid (about 1M Kuhn tets at
+    N=128), n_sites initial spheres uniform inside, and the insertion table: for every tet, a sphere near its
+    centroid (jittered into general position). Radii: 0.9 x (table: uniform 0.85-0.95 x) the voxel distance to
+    the boundary. Returns (Problem, table) with table = (tx, ty, tz, tr) float32 arrays in the problem's tet
+    order."""
+    solid = blobs_with_handles(N, seed)
+    rng = np.random.default_rng(seed)
+    cen = sample_in_voxels(solid["occ"], N, rng, n_sites)
+    rad = _edt_radius(solid["occ"], N, cen, 0.9)
+    prob = make_problem(solid, N, cen, rad, workload=f"repair_N{N}_n{n_sites}_s{seed}", seed=seed)
+    cent = _jittered_centroids(prob, rng)
+    tc = quantize(cent)
+    tr = np.maximum(quantize(_edt_radius(solid["occ"], N, cent, 1.0) * rng.uniform(0.85, 0.95, cent.shape[0])), 0.0)
+    table = (tc[:, 0].astype(np.float32), tc[:, 1].astype(np.float32), tc[:, 2].astype(np.float32),
+             tr.astype(np.float32))
+    return prob, table
+
+
 def tiny_two_tets() -> tuple:
     """Two positively oriented tets sharing one face (a bipyramid), vertices on the 2^-20 grid."""
     v = np.array([[0, 0, 0], [0.5, 0, 0], [0, 0.5, 0], [0, 0, 0.5], [0.25, 0.25, -0.5]], dtype=np.float64)

@@ -21,19 +21,31 @@ def run_gpu(prob, precision=0, clip_budget=0, block=0, flags=0, device_ptrs=True
         mesh = rpd.Mesh(prob.vx, prob.vy, prob.vz, prob.tv.reshape(-1))
         sites = (prob.sx, prob.sy, prob.sz, prob.sr)
     res = rpd.build([mesh], [sites], precision=precision, clip_budget=clip_budget, block=block, flags=flags)
-    out = {}
-    _, out["cell_chi"] = res.euler(0, rpd.RPD_CELL)
-    _, out["cell_beta0"] = res.components(0, rpd.RPD_CELL)
-    out["face_keys"], out["face_chi"] = res.euler(0, rpd.RPD_FACE)
-    _, out["face_beta0"] = res.components(0, rpd.RPD_FACE)
-    out["edge_keys"], out["edge_chi"] = res.euler(0, rpd.RPD_EDGE)
-    _, out["edge_beta0"] = res.components(0, rpd.RPD_EDGE)
-    out["rpv_keys"] = res.adjacency(0, rpd.RPD_VERTEX)
-    out["cell_vol"], out["cell_cen"] = res.geometry(0)
+    out = extract(res, 0)
     out["stats"] = res.stats()
     out["mesh_info"] = mesh.info()
     if flags & rpd.RPD_KEEP_PIECES:
         out["pieces"] = res.pieces(0)
+    return out
+
+
+ELEMENT_ARRAYS = ("cell_chi", "cell_beta0", "face_keys", "face_chi", "face_beta0", "edge_keys", "edge_chi",
+                  "edge_beta0", "rpv_keys", "cell_vol", "cell_cen")
+
+
+def extract(res, k):
+    """Every per-element array of shape k of a Result, as numpy arrays."""
+    from paper_2403_18761_amd import rpd
+
+    out = {}
+    _, out["cell_chi"] = res.euler(k, rpd.RPD_CELL)
+    _, out["cell_beta0"] = res.components(k, rpd.RPD_CELL)
+    out["face_keys"], out["face_chi"] = res.euler(k, rpd.RPD_FACE)
+    _, out["face_beta0"] = res.components(k, rpd.RPD_FACE)
+    out["edge_keys"], out["edge_chi"] = res.euler(k, rpd.RPD_EDGE)
+    _, out["edge_beta0"] = res.components(k, rpd.RPD_EDGE)
+    out["rpv_keys"] = res.adjacency(k, rpd.RPD_VERTEX)
+    out["cell_vol"], out["cell_cen"] = res.geometry(k)
     return out
 
 
@@ -54,10 +66,14 @@ def assert_parity(g, r, vol_rtol=1e-5, label=""):
                                err_msg=f"{label} volumes")
     ne = vr > 0
     np.testing.assert_array_equal(np.isnan(g["cell_cen"][:, 0]), ~ne, err_msg=f"{label} empty cells")
-    # centroid: absolute error on the [-1, 1]^3 domain; a piece's moment error is its volume error times its
-    # position (|x| <= sqrt 3), so the centroid error is bounded by about 2 sqrt(3) times the relative volume error
-    err = np.abs(g["cell_cen"][ne] - r["cell_cen"][ne])
-    assert err.max(initial=0.0) < 4 * vol_rtol, (label, err.max())
+    # centroid = moment / volume on the [-1, 1]^3 domain. A piece's moment error is its volume error times its
+    # position (|x| <= sqrt 3), so with volume error <= rtol vol + atol the centroid error is at most about
+    # 2 sqrt(3) (rtol + atol / vol): tiny cells, whose volume sits near the absolute floor (fixed-point sums with a
+    # 2^-56 quantum), have ill-conditioned centroids and get the second term.
+    atol = vol_rtol * 1e-6 * max(vr.max(), 1e-30)
+    err = np.abs(g["cell_cen"][ne] - r["cell_cen"][ne]).max(axis=1, initial=0.0)
+    bound = 4 * (vol_rtol + atol / vr[ne])
+    assert np.all(err < bound), (label, err.max(initial=0.0), (err / bound).max(initial=0.0))
 
 
 def log(*a):
@@ -81,15 +97,7 @@ def run_gpu_batch(probs, precision=0, flags=0):
     res = rpd.build(meshes, sites, precision=precision, flags=flags)
     outs = []
     for k in range(len(probs)):
-        out = {}
-        _, out["cell_chi"] = res.euler(k, rpd.RPD_CELL)
-        _, out["cell_beta0"] = res.components(k, rpd.RPD_CELL)
-        out["face_keys"], out["face_chi"] = res.euler(k, rpd.RPD_FACE)
-        _, out["face_beta0"] = res.components(k, rpd.RPD_FACE)
-        out["edge_keys"], out["edge_chi"] = res.euler(k, rpd.RPD_EDGE)
-        _, out["edge_beta0"] = res.components(k, rpd.RPD_EDGE)
-        out["rpv_keys"] = res.adjacency(k, rpd.RPD_VERTEX)
-        out["cell_vol"], out["cell_cen"] = res.geometry(k)
+        out = extract(res, k)
         out["mesh_info"] = meshes[k].info()
         outs.append(out)
     return outs, res.stats()

@@ -149,3 +149,16 @@ def test_batch_of_shapes_in_one_call():
         total_pairs += r["n_pairs"]
         assert_parity(g, r, label=f"batch shape {k}")
     assert st["n_pairs"] == total_pairs
+
+
+@pytest.mark.parametrize("N,n", [(8, 4000), (16, 8000)])
+def test_dense_sites_split_blocks(N, n):
+    """Many sites per workgroup box: blocks are redone in chunks, the densest tets go to the deferred kernel."""
+    prob = synth.cube_random(N=N, n_sites=n, seed=21)
+    log(f"case: dense cube N{N} n{n} tets {prob.n_tets}")
+    r = _oracle(prob, assemble=False)
+    g = run_gpu(prob)
+    st = g["stats"]
+    log("split", st["n_split"], "deferred", st["n_defer_block"], st["n_defer_kmax"], st["n_defer_clip"])
+    assert st["n_split"] > 0
+    assert_parity(g, r, label=f"dense cube {N}")

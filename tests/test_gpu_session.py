@@ -1,0 +1,117 @@
+"""The incremental session (sphere insertion with dirty-block re-clipping, one captured graph per round) through the
+C ABI: after any number of rounds its state equals, bit for bit, a from-scratch build with the session's sites, and
+on a small case it matches the oracle."""
+import numpy as np
+import pytest
+
+from paper_2403_18761_amd import synth
+from tests.gpu_util import ELEMENT_ARRAYS, assert_parity, extract, log
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    import torch
+
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+
+
+def _dev(a, dt=None):
+    import torch
+
+    return torch.as_tensor(np.ascontiguousarray(a), dtype=dt or torch.float32, device="cuda:0")
+
+
+def _mesh(prob):
+    import torch
+
+    from paper_2403_18761_amd import rpd
+
+    return rpd.Mesh(_dev(prob.vx), _dev(prob.vy), _dev(prob.vz), _dev(prob.tv.reshape(-1), torch.int32))
+
+
+def _rebuild(mesh, sites):
+    from paper_2403_18761_amd import rpd
+
+    s = tuple(_dev(sites[:, k]) for k in range(4))
+    res = rpd.build([mesh], [s])
+    out = extract(res, 0)
+    out["stats"] = res.stats()
+    return out
+
+
+def _same(a, b, label):
+    for k in ELEMENT_ARRAYS:
+        np.testing.assert_array_equal(a[k], b[k], err_msg=f"{label}: {k}")
+    assert a["stats"]["n_pairs"] == b["stats"]["n_pairs"], label
+
+
+def test_session_equals_rebuild():
+    from paper_2403_18761_amd import rpd
+
+    prob, table = synth.repair_problem(N=64, n_sites=100, seed=5)
+    log(f"case: session repair N64 n100 tets {prob.n_tets}")
+    mesh = _mesh(prob)
+    sess = rpd.Session(mesh, (_dev(prob.sx), _dev(prob.sy), _dev(prob.sz), _dev(prob.sr)),
+                       tuple(_dev(x) for x in table), max_sites=100 + 6 * 32, max_insert=32)
+    r0 = sess.result()
+    first = extract(r0, 0)
+    first["stats"] = r0.stats()
+    _same(first, _rebuild(mesh, sess.sites()), "initial state")
+    for rounds in (1, 2, 3):
+        sess.run(rounds)
+        info = sess.info()
+        log("after", info["rounds"], "rounds:", info)
+        res = sess.result()
+        cur = extract(res, 0)
+        cur["stats"] = res.stats()
+        _same(cur, _rebuild(mesh, sess.sites()), f"after {info['rounds']} rounds")
+    assert info["n_inserted"] > 0
+    assert info["n_sites"] == 100 + info["n_inserted"]
+    assert info["n_dirty_blocks"] < info["n_blocks"] * info["rounds"]
+
+
+def test_session_matches_oracle():
+    import oracle
+
+    from paper_2403_18761_amd import rpd
+
+    oracle.build(force=False)
+    prob = synth.torus_inside(32, 60, 17)
+    table = synth.centroid_table(prob, 0.03)
+    log(f"case: session torus N32 n60 tets {prob.n_tets}")
+    mesh = _mesh(prob)
+    sess = rpd.Session(mesh, (prob.sx, prob.sy, prob.sz, prob.sr), table, max_sites=60 + 40, max_insert=8)
+    sess.run(3)
+    info = sess.info()
+    log("session", info)
+    assert info["n_inserted"] > 0
+    s = sess.sites()
+    ref = oracle.rpd(prob.with_sites(s[:, 0], s[:, 1], s[:, 2], s[:, 3]), assemble=False)
+    res = sess.result()
+    g = extract(res, 0)
+    g["stats"] = res.stats()
+    assert_parity(g, ref, label="session vs oracle")
+
+
+def test_session_rejects_bad_arguments():
+    from paper_2403_18761_amd import rpd
+
+    prob = synth.torus_core(16, 64, 1)
+    mesh = _mesh(prob)
+    table = synth.centroid_table(prob, 0.02)
+    sites = (prob.sx, prob.sy, prob.sz, prob.sr)
+    with pytest.raises(rpd.RPDError) as e:
+        rpd.Session(mesh, sites, tuple(x[:-1] for x in table), max_sites=100)
+    assert e.value.code == -1
+    with pytest.raises(rpd.RPDError) as e:
+        rpd.Session(mesh, sites, table, max_sites=10)
+    assert e.value.code == -1
+    bad = list(table)
+    bad[0] = bad[0].copy()
+    bad[0][3] = 0.1  # off the 2^-20 grid
+    with pytest.raises(rpd.RPDError) as e:
+        rpd.Session(mesh, sites, tuple(bad), max_sites=100)
+    assert e.value.code == -1

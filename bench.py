@@ -8,6 +8,7 @@ line; metric: tet-site clips/sec (nonempty pieces per second) with ms per RPD+ch
 with FP64/exact fallback (the reported value) and the all-FP64 path.
 """
 import argparse
+import hashlib
 import json
 import os
 import sys
@@ -25,6 +26,34 @@ PEAK_FP32_TFLOPS = 157.3
 # evaluated at the piece's vertices (8 v f), every vertex is constructed once (30 v) and enters the volume and
 # moment fans (25 v). For this workload the oracle's piece statistics give mean v = 5.84 and mean f = 1.6.
 FLOP_PER_PIECE = 8 * 5.84 * 1.6 + 55 * 5.84
+
+
+# HBM traffic of the clipping kernel from rocprofv3 FETCH_SIZE / WRITE_SIZE runs (scaled by a plain copy of known
+# size), valid only for the kernel sources it was measured on.
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_k_clip_fast.json")
+KERNEL_SOURCES = ("clip.hip", "rpd_device.h", "rpd_common.h")
+
+
+def kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, "paper_2403_18761_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(workload: str, kernel: str):
+    """Bytes per launch of `kernel` on `workload` from the committed counter summary, or None when there is none
+    or the kernel sources changed since it was taken."""
+    try:
+        with open(TRAFFIC_FILE) as fh:
+            d = json.load(fh)
+    except (OSError, ValueError):
+        return None
+    e = d.get(workload, {})
+    if e.get("source_hash") != kernel_source_hash() or e.get("kernel") != kernel:
+        return None
+    return e.get("bytes_per_launch")
 
 
 WORKLOADS = {
@@ -157,8 +186,12 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-fp64", action="store_true", help="skip the all-FP64 comparison")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-autotune", action="store_true", help="use the default launch shape (128 threads, k=28)")
     ap.add_argument("--cpu-frac", type=float, default=None)
     ap.add_argument("--workload", default="torus2000", choices=sorted(WORKLOADS))
+    ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
+                    help="only run a plain device-to-device copy of MIB MiB (the reference kernel that scales the "
+                         "FETCH_SIZE / WRITE_SIZE counters to bytes) and exit")
     args = ap.parse_args()
     if args.gpus != 1:
         print("this build runs on one GPU only: multi-GPU sharding is a design note, not an implemented path",
@@ -168,6 +201,16 @@ def main():
     import torch
 
     from paper_2403_18761_amd import rpd
+
+    if args.calibrate_copy:
+        n = args.calibrate_copy * (1 << 20) // 4
+        src = torch.ones(n, dtype=torch.float32, device="cuda:0")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"calibrate_copy_bytes": 4 * n, "launches": 3}), flush=True)
+        return
 
     probs = workload(args.workload)
     if args.workload == "repair":
@@ -201,6 +244,9 @@ def main():
     meshes = [rpd.Mesh(t(p.vx), t(p.vy), t(p.vz), t(p.tv.reshape(-1), torch.int32), stream=stream) for p in probs]
     sites = [(t(p.sx), t(p.sy), t(p.sz), t(p.sr)) for p in probs]
     torch.cuda.synchronize()
+    # the autotuner picks the launch shape for this bucket of shapes (untimed); rpd_build then uses it
+    tuned = rpd.autotune(meshes, sites, stream=stream) if not args.no_autotune else {"block": 128, "clip_budget": 28}
+    print(f"# autotuned launch shape: {tuned}", file=sys.stderr, flush=True)
 
     ms32, clip32, pairs, st32 = time_builds(meshes, sites, rpd.RPD_FP32_FALLBACK, args.steps, args.warmup, stream)
     print(f"# fp32+fallback: {ms32:.3f} ms/RPD, clip kernel {clip32:.3f} ms, pairs {pairs}", file=sys.stderr,
@@ -213,6 +259,8 @@ def main():
         print(f"# all-fp64: {ms64:.3f} ms/RPD, clip kernel {clip64:.3f} ms", file=sys.stderr, flush=True)
 
     achieved = FLOP_PER_PIECE * pairs / (clip32 * 1e-3) / 1e12
+    kernel = f"k_clip_fast<float,{tuned['block']}>"
+    traffic = measured_traffic(args.workload, kernel) if len(probs) == 1 else None
     line = {
         "metric": "tet-site clips/sec (nonempty pieces/s) + ms per RPD+chi, FP32/FP64-fallback vs all-FP64, 1 MI355X",
         "value": pairs / (ms32 * 1e-3),
@@ -228,15 +276,15 @@ def main():
         "data": "synthetic",
         "config": {"workload": WORKLOADS[args.workload]["desc"], "name": args.workload, "n_shapes": len(probs),
                    "n_tets": sum(p.n_tets for p in probs), "n_sites": sum(p.n_sites for p in probs),
-                   "n_pairs": pairs},
+                   "n_pairs": pairs, "launch": tuned},
         "ms_per_rpd": ms32,
         "all_fp64": out64,
         "stats": {k: st32[k] for k in ("n_candidates", "n_deferred", "n_fp64", "n_exact", "n_faces", "n_edges",
                                        "n_rpv", "n_defer_block", "n_defer_kmax", "n_defer_clip", "n_split", "ms_clip",
                                        "ms_deferred", "ms_reduce", "ms_total")},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
-                     "frac": achieved / PEAK_FP32_TFLOPS, "traffic": None,
-                     "kernel": "k_clip_fast<float,128>", "flop_per_piece": FLOP_PER_PIECE},
+                     "frac": achieved / PEAK_FP32_TFLOPS, "traffic": traffic,
+                     "kernel": kernel, "flop_per_piece": FLOP_PER_PIECE},
     }
     if not args.no_cpu_baseline:
         frac = args.cpu_frac if args.cpu_frac is not None else WORKLOADS[args.workload]["cpu_frac"]

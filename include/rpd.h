@@ -94,8 +94,10 @@ typedef struct rpd_sites {
 
 typedef struct rpd_opts {
   int32_t precision;   /* RPD_FP32_FALLBACK or RPD_FP64 */
-  int32_t clip_budget; /* max candidate sites per tet in the fast path: 0 = default (28) or 4..28 */
-  int32_t block;       /* threads per workgroup of the clipping kernel: 0 = default (128), 64 or 128 */
+  int32_t clip_budget; /* max candidate sites per tet in the fast path: 0 = tuned or 28, else 4..28; tets
+                          with more go to the large-capacity kernel */
+  int32_t block;       /* threads per workgroup of the FP32 clipping kernel: 0 = tuned or 128, 64, 128 or 256
+                          (the FP64 path always runs 64) */
   uint32_t flags;      /* RPD_* flags above */
   void* stream;        /* hipStream_t to run on; NULL = the null stream */
 } rpd_opts;
@@ -163,6 +165,15 @@ rpd_status rpd_pieces(const rpd_result* r, int32_t shape, int64_t* n_out, const 
                       const double** vol_moment /* 4 per piece */, const int64_t** chi_num);
 
 void rpd_free(rpd_result* r);
+
+/* Autotuner for the batched FP32 path: runs rpd_build on these inputs once per launch shape (block of 64, 128 or 256
+ * threads x clip budget 16 or 28, each timed by HIP events over the clipping kernels, best of two after a warm-up),
+ * writes the fastest into *best (a copy of *opts with block and clip_budget set) and caches it for the process under
+ * the bucket (floor log2 of the mean sites per shape, floor log2 of the mean tets per shape). Later rpd_build calls
+ * whose block or clip_budget is 0 take the cached value of their bucket (else 128 and 28). Every launch shape gives
+ * identical results; only the time differs. Synchronises. Errors as rpd_build; RPD_E_INVALID for RPD_FP64. */
+rpd_status rpd_autotune(const rpd_mesh* const* meshes, const rpd_sites* sites, int32_t n_shapes, const rpd_opts* opts,
+                        rpd_opts* best);
 
 /* ---- Incremental session: the sphere-insertion loop of topology repair (Sec. 4 overview: spheres are added where
  * an element violates the topology constraints, and only the cells related to the new spheres are updated).

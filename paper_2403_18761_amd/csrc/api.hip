@@ -124,11 +124,12 @@ struct DeviceState {
   int def_cap = 0, piece_cap = 0;
   DBuf site, status, cell_chi, cell_geo, cell_np, cell_b0;
   DBuf fkeys, face_chi, face_np, face_b0, ekeys, edge_chi, edge_np, edge_b0, qkeys, rpv_cnt;
-  DBuf nkeys, node_glue, node_cnt, parent, deferred, pieces, counters, tetU, slow;
+  DBuf nkeys, node_glue, node_cnt, parent, deferred, pieces, counters, tetU, slow, touch;
   int waves = 0;
 
   unsigned long long* cnt() const { return counters.as<unsigned long long>(); }
   unsigned long long* fin_count() const { return cnt() + NCOUNTERS; }  // [0] faces, [1] edges
+  size_t touch_words() const { return ((size_t)ns_cap + capF + capE + 3) / 4; }
 
   void alloc(int n_shapes, int ns, long long nt, int scale, bool keep_pieces, bool keep_U) {
     nsh = n_shapes;
@@ -163,7 +164,10 @@ struct DeviceState {
     deferred.alloc(16 * (size_t)def_cap);
     pieces.alloc(sizeof(PieceRec) * (size_t)std::max(piece_cap, 1));
     counters.alloc(8 * (NCOUNTERS + 8));
-    if (keep_U) tetU.alloc(8 * (size_t)std::max<long long>(nt, 1));
+    if (keep_U) {  // incremental updates: U_t per tet and the touched-element flags
+      tetU.alloc(8 * (size_t)std::max<long long>(nt, 1));
+      touch.alloc(touch_words() * 4);
+    }
     waves = slow_waves(nt);
     slow.alloc(slow_scratch_bytes(waves));
   }
@@ -186,6 +190,15 @@ struct DeviceState {
     hip_check(launch_fill_i32(node_glue.as<int>(), 0, capN, s), "fill");
     hip_check(launch_fill_i32(node_cnt.as<int>(), 0, capN, s), "fill");
     hip_check(launch_fill_u64(cnt(), 0, NCOUNTERS + 8, s), "fill");
+    if (touch.p) hip_check(launch_fill_i32(touch.as<int>(), 0, touch_words(), s), "fill");
+  }
+
+  // the touched-element flags for an incremental pass
+  void set_touch(ShapeArgs& a) const {
+    unsigned char* t = touch.as<unsigned char>();
+    a.touch_cell = t;
+    a.touch_face = t + ns_cap;
+    a.touch_edge = t + ns_cap + capF;
   }
 
   ShapeArgs args(const ShapeDesc* shapes, const int2* items, int nitems, unsigned flags, int kmax, int sign) const {
@@ -225,14 +238,22 @@ struct DeviceState {
   }
 
   // components of every live element piece: fresh union-find and root counts
+  // (with a.touch_* set: of the touched elements only, then the flags are cleared)
   void components(const ShapeArgs& a, hipStream_t s) {
-    hip_check(launch_fill_i32(cell_b0.as<int>(), 0, (size_t)ns_cap, s), "fill");
-    hip_check(launch_fill_i32(face_b0.as<int>(), 0, capF, s), "fill");
-    hip_check(launch_fill_i32(edge_b0.as<int>(), 0, capE, s), "fill");
+    if (a.touch_cell) {
+      hip_check(launch_clear_touched_b0(a.touch_cell, cell_b0.as<int>(), (size_t)ns_cap, s), "clear");
+      hip_check(launch_clear_touched_b0(a.touch_face, face_b0.as<int>(), capF, s), "clear");
+      hip_check(launch_clear_touched_b0(a.touch_edge, edge_b0.as<int>(), capE, s), "clear");
+    } else {
+      hip_check(launch_fill_i32(cell_b0.as<int>(), 0, (size_t)ns_cap, s), "fill");
+      hip_check(launch_fill_i32(face_b0.as<int>(), 0, capF, s), "fill");
+      hip_check(launch_fill_i32(edge_b0.as<int>(), 0, capE, s), "fill");
+    }
     hip_check(launch_fill_u64(cnt() + C_NODES, 0, 1, s), "fill");
     hip_check(launch_glue(a, parent.as<int>(), s), "glue");
     hip_check(launch_count_roots(a, parent.as<int>(), cell_b0.as<int>(), face_b0.as<int>(), edge_b0.as<int>(), s),
               "roots");
+    if (a.touch_cell) hip_check(launch_fill_i32(touch.as<int>(), 0, touch_words(), s), "fill");
   }
 };
 
@@ -587,39 +608,123 @@ rpd_status rpd_mesh_get_info(const rpd_mesh* m, rpd_mesh_info* info) {
 
 void rpd_mesh_free(rpd_mesh* m) { delete m; }
 
+static void check_opts(const rpd_opts& o) {
+  if (o.precision != RPD_FP32_FALLBACK && o.precision != RPD_FP64) throw Failure{RPD_E_INVALID, "bad precision"};
+  if (o.clip_budget != 0 && (o.clip_budget < 4 || o.clip_budget > rpd::KMAX))
+    throw Failure{RPD_E_INVALID, "clip_budget must be 0 or in [4, 28]"};
+  if (o.block != 0 && o.block != 64 && o.block != 128 && o.block != 256)
+    throw Failure{RPD_E_INVALID, "block must be 0, 64, 128 or 256"};
+}
+
+static void check_shapes(const rpd_mesh* const* meshes, const rpd_sites* sites, int32_t n_shapes) {
+  if (!meshes || !sites || n_shapes <= 0) throw Failure{RPD_E_INVALID, "null argument or no shape"};
+  for (int k = 0; k < n_shapes; ++k) {
+    const rpd_sites* sp = &sites[k];
+    if (!meshes[k]) throw Failure{RPD_E_INVALID, "null mesh"};
+    if (sp->n_sites <= 0 || sp->n_sites >= (1 << 21) || !sp->sx || !sp->sy || !sp->sz || !sp->sr)
+      throw Failure{RPD_E_INVALID, "site count must be in [1, 2^21) with non-null arrays"};
+  }
+}
+
+// Autotuner cache: launch shape (block, clip budget) of the FP32 path per (log2 mean sites per shape, log2 mean tets
+// per shape) bucket, filled by rpd_autotune and read by rpd_build when block or clip_budget is 0.
+static std::mutex g_tune_mu;
+static std::map<std::pair<int, int>, std::pair<int, int>> g_tune;
+
+static std::pair<int, int> tune_bucket(const rpd_mesh* const* meshes, const rpd_sites* sites, int32_t n) {
+  double ns = 0, nt = 0;
+  for (int k = 0; k < n; ++k) {
+    ns += sites[k].n_sites;
+    nt += meshes[k]->nt;
+  }
+  return {(int)std::floor(std::log2(std::max(1.0, ns / n))), (int)std::floor(std::log2(std::max(1.0, nt / n)))};
+}
+
+static bool run_with_retry(const rpd_mesh* const* meshes, const rpd_sites* sites, int32_t n_shapes, const rpd_opts& o,
+                           std::vector<rpd::ShapeOut>& shapes, rpd_stats& st) {
+  hipStream_t s = (hipStream_t)o.stream;
+  for (int scale = 1; scale <= 16; scale *= 2)
+    if (rpd::run_batch(meshes, sites, n_shapes, o, s, scale, shapes, st)) return true;
+  return false;
+}
+
 rpd_status rpd_build(const rpd_mesh* const* meshes, const rpd_sites* sites, int32_t n_shapes, const rpd_opts* opts,
                      rpd_result** out) {
   if (out) *out = nullptr;
   RPD_GUARD_BEGIN
   rpd::set_error("");
-  if (!meshes || !sites || !out || n_shapes <= 0) throw Failure{RPD_E_INVALID, "null argument or no shape"};
+  if (!out) throw Failure{RPD_E_INVALID, "null argument"};
   rpd_opts o;
   std::memset(&o, 0, sizeof(o));
   if (opts) o = *opts;
-  if (o.precision != RPD_FP32_FALLBACK && o.precision != RPD_FP64) throw Failure{RPD_E_INVALID, "bad precision"};
-  if (o.clip_budget != 0 && (o.clip_budget < 4 || o.clip_budget > rpd::KMAX))
-    throw Failure{RPD_E_INVALID, "clip_budget must be 0 or in [4, 28]"};
-  if (o.block != 0 && o.block != 64 && o.block != 128) throw Failure{RPD_E_INVALID, "block must be 0, 64 or 128"};
-  hipStream_t s = (hipStream_t)o.stream;
+  check_opts(o);
+  check_shapes(meshes, sites, n_shapes);
+  if (o.precision == RPD_FP32_FALLBACK && (o.block == 0 || o.clip_budget == 0)) {
+    std::lock_guard<std::mutex> g(g_tune_mu);
+    auto it = g_tune.find(tune_bucket(meshes, sites, n_shapes));
+    if (it != g_tune.end()) {
+      if (o.block == 0) o.block = it->second.first;
+      if (o.clip_budget == 0) o.clip_budget = it->second.second;
+    }
+  }
   rpd_result* r = new rpd_result();
   std::memset(&r->stats, 0, sizeof(r->stats));
   try {
     r->shapes.resize(n_shapes);
-    for (int k = 0; k < n_shapes; ++k) {
-      const rpd_sites* sp = &sites[k];
-      if (!meshes[k]) throw Failure{RPD_E_INVALID, "null mesh"};
-      if (sp->n_sites <= 0 || sp->n_sites >= (1 << 21) || !sp->sx || !sp->sy || !sp->sz || !sp->sr)
-        throw Failure{RPD_E_INVALID, "site count must be in [1, 2^21) with non-null arrays"};
-    }
-    bool done = false;
-    for (int scale = 1; scale <= 16 && !done; scale *= 2)
-      done = rpd::run_batch(meshes, sites, n_shapes, o, s, scale, r->shapes, r->stats);
-    if (!done) throw Failure{RPD_E_NOMEM, "result tables kept overflowing"};
+    if (!run_with_retry(meshes, sites, n_shapes, o, r->shapes, r->stats))
+      throw Failure{RPD_E_NOMEM, "result tables kept overflowing"};
   } catch (...) {
     delete r;
     throw;
   }
   *out = r;
+  return RPD_OK;
+  RPD_GUARD_END
+}
+
+rpd_status rpd_autotune(const rpd_mesh* const* meshes, const rpd_sites* sites, int32_t n_shapes, const rpd_opts* opts,
+                        rpd_opts* best) {
+  RPD_GUARD_BEGIN
+  rpd::set_error("");
+  if (!best) throw Failure{RPD_E_INVALID, "null argument"};
+  rpd_opts o;
+  std::memset(&o, 0, sizeof(o));
+  if (opts) o = *opts;
+  check_opts(o);
+  check_shapes(meshes, sites, n_shapes);
+  if (o.precision != RPD_FP32_FALLBACK) throw Failure{RPD_E_INVALID, "only the FP32 path is tuned"};
+  o.flags |= RPD_TIMING;
+  o.flags &= ~(uint32_t)RPD_KEEP_PIECES;
+  const int blocks[3] = {64, 128, 256}, budgets[2] = {16, rpd::KMAX};
+  double best_ms = INFINITY;
+  int bb = 128, bk = rpd::KMAX;
+  for (int b : blocks)
+    for (int k : budgets) {
+      rpd_opts c = o;
+      c.block = b;
+      c.clip_budget = k;
+      double ms = INFINITY;
+      for (int rep = 0; rep < 3; ++rep) {  // the first run warms the allocator and the caches
+        std::vector<rpd::ShapeOut> shapes(n_shapes);
+        rpd_stats st;
+        std::memset(&st, 0, sizeof(st));
+        if (!run_with_retry(meshes, sites, n_shapes, c, shapes, st))
+          throw Failure{RPD_E_NOMEM, "result tables kept overflowing"};
+        if (rep > 0) ms = std::min(ms, st.ms_clip + st.ms_deferred);
+      }
+      if (ms < best_ms) {
+        best_ms = ms;
+        bb = b;
+        bk = k;
+      }
+    }
+  {
+    std::lock_guard<std::mutex> g(g_tune_mu);
+    g_tune[tune_bucket(meshes, sites, n_shapes)] = {bb, bk};
+  }
+  *best = opts ? *opts : o;
+  best->block = bb;
+  best->clip_budget = bk;
   return RPD_OK;
   RPD_GUARD_END
 }
@@ -875,6 +980,8 @@ static void session_round(rpd_session* S) {
   ShapeArgs a_new = D.args(ds + 1, S->items.as<int2>(), m->nblk, S->o.flags, S->kmax, +1);
   a_old.nitems_dev = S->r.nitems;
   a_new.nitems_dev = S->r.nitems;
+  D.set_touch(a_old);
+  D.set_touch(a_new);
   hip_check(launch_round_front(S->r, a_new, D.parent.as<int>(), D.cell_b0.as<int>(), m->tp.as<float4>(), m->nt,
                                m->nblk, s),
             "round selection");
@@ -921,10 +1028,7 @@ rpd_status rpd_session_create(const rpd_mesh* mesh, const rpd_sites* sites, cons
   rpd::set_error("");
   if (!mesh || !sites || !table || !opts || !out) throw Failure{RPD_E_INVALID, "null argument"};
   const rpd_opts& o = opts->build;
-  if (o.precision != RPD_FP32_FALLBACK && o.precision != RPD_FP64) throw Failure{RPD_E_INVALID, "bad precision"};
-  if (o.clip_budget != 0 && (o.clip_budget < 4 || o.clip_budget > rpd::KMAX))
-    throw Failure{RPD_E_INVALID, "clip_budget must be 0 or in [4, 28]"};
-  if (o.block != 0 && o.block != 64 && o.block != 128) throw Failure{RPD_E_INVALID, "block must be 0, 64 or 128"};
+  check_opts(o);
   if (o.flags & (RPD_KEEP_PIECES | RPD_FORCE_SLOW_PATH))
     throw Failure{RPD_E_INVALID, "RPD_KEEP_PIECES and RPD_FORCE_SLOW_PATH are not available in a session"};
   if (sites->n_sites <= 0 || !sites->sx || !sites->sy || !sites->sz || !sites->sr)

@@ -42,6 +42,10 @@ __device__ inline void add_fixed(long long* dst, double v, int sign) {  // fixed
 __device__ inline void node_emit(const ShapeArgs& a, unsigned long long key, int glue) {
   int ns = ht_insert(a.N, key, a.status);
   if (ns < 0) return;
+  if (a.touch_cell) {
+    const int kind = node_kind(key), elem = node_elem(key);
+    (kind == 1 ? a.touch_cell : kind == 2 ? a.touch_face : a.touch_edge)[elem] = 1;
+  }
   if (a.sign > 0) {
     if (glue) atomicOr(&a.node_glue[ns], glue);
   } else {
@@ -605,7 +609,7 @@ __global__ __launch_bounds__(NT) void k_clip_fast(ShapeArgs a) {
 struct SlowScratch {  // per wave: the candidate list, then every lane's polytope and plane table, lane-interleaved
   static constexpr size_t cand_bytes = SLOW_KMAX * sizeof(int);
   static constexpr size_t key_bytes = SLOW_KMAX * sizeof(double);
-  static constexpr size_t wave_bytes = cand_bytes + key_bytes;
+  static constexpr size_t wave_bytes = 2 * (cand_bytes + key_bytes);  // unsorted and sorted lists
   static constexpr size_t xyz_bytes = 64 * SLOW_VMAX * sizeof(Coord4<double>::type);  // [slot][lane]
   static constexpr size_t topo_bytes = 64 * SLOW_VMAX * sizeof(unsigned long long);    // [slot][lane]
   static constexpr size_t tab_bytes = 64 * (size_t)SLOW_PMAX;                          // [plane][lane]
@@ -621,6 +625,8 @@ __global__ __launch_bounds__(64) void k_clip_slow(ShapeArgs a, unsigned char* sc
   unsigned char* wbase = scratch + (size_t)blockIdx.x * SlowScratch::bytes;
   int* cand = (int*)wbase;
   double* key = (double*)(wbase + SlowScratch::cand_bytes);
+  int* scand = (int*)(wbase + SlowScratch::cand_bytes + SlowScratch::key_bytes);
+  double* skey = (double*)(wbase + 2 * SlowScratch::cand_bytes + SlowScratch::key_bytes);
   Coord4<double>::type* xyz = (Coord4<double>::type*)(wbase + SlowScratch::wave_bytes) + lane;
   unsigned long long* topo =
       (unsigned long long*)(wbase + SlowScratch::wave_bytes + SlowScratch::xyz_bytes) + lane;
@@ -683,23 +689,20 @@ __global__ __launch_bounds__(64) void k_clip_slow(ShapeArgs a, unsigned char* sc
       continue;
     }
     __syncthreads();
-    if (lane == 0) {  // ascending key; the ids ascend already, so the stable insertion keeps ties by id
-      for (int x = 1; x < m; ++x) {
-        double kx = key[x];
-        int cx = cand[x];
-        int q = x - 1;
-        while (q >= 0 && key[q] > kx) {
-          key[q + 1] = key[q];
-          cand[q + 1] = cand[q];
-          --q;
-        }
-        key[q + 1] = kx;
-        cand[q + 1] = cx;
+    // rank sort by (key, position): positions ascend with the site id, so ties keep the site order
+    for (int x = lane; x < m; x += 64) {
+      const double kx = key[x];
+      int rank = 0;
+      for (int q = 0; q < m; ++q) {
+        const double kq = key[q];
+        rank += (kq < kx || (kq == kx && q < x)) ? 1 : 0;
       }
+      scand[rank] = cand[x];
+      skey[rank] = kx;
     }
     __syncthreads();
     for (int ci = lane; ci < m; ci += 64) {
-      if (want >= 0 && cand[ci] != want) continue;
+      if (want >= 0 && scand[ci] != want) continue;
       Clipper<double, Topo64, unsigned long long, SLOW_VMAX, true> cl;
       cl.st.c = xyz;
       cl.st.w = topo;
@@ -716,10 +719,10 @@ __global__ __launch_bounds__(64) void k_clip_slow(ShapeArgs a, unsigned char* sc
       cl.env.sites = a.site;
       cl.env.sid = nullptr;  // candidates hold batch-global site ids directly
       cl.env.cidx8 = nullptr;
-      cl.env.cidx32 = cand;
+      cl.env.cidx32 = scand;
       cl.env.ci = ci;
-      cl.env.si = a.site[cand[ci]];
-      cl.env.site_i = cand[ci];
+      cl.env.si = a.site[scand[ci]];
+      cl.env.site_i = scand[ci];
       int r = clip_piece(cl, m, a.status);
       n64 += cl.n64;
       nex += cl.nex;
@@ -759,6 +762,7 @@ hipError_t launch_clip_fast(const ShapeArgs& a, int precision, int block, hipStr
   if (a.nitems == 0) return hipSuccess;
   if (precision == RPD_FP64) return launch_items<double, 64>(a, s);
   if (block == 64) return launch_items<float, 64>(a, s);
+  if (block == 256) return launch_items<float, 256>(a, s);
   return launch_items<float, 128>(a, s);
 }
 

@@ -62,8 +62,28 @@ __device__ inline void uf_union(int* par, int a, int b) {
   }
 }
 
-__global__ void k_parent_init(const unsigned long long* keys, int* parent, unsigned cap) {
-  for (unsigned s = blockIdx.x * blockDim.x + threadIdx.x; s < cap; s += gridDim.x * blockDim.x) parent[s] = (int)s;
+// with touch flags (incremental update) only the pieces of touched elements are redone: unions never join two
+// elements, so the forest of every other element stays valid
+__device__ inline bool node_touched(const ShapeArgs& a, unsigned long long key) {
+  if (!a.touch_cell) return true;
+  const int kind = node_kind(key), elem = node_elem(key);
+  return (kind == 1 ? a.touch_cell : kind == 2 ? a.touch_face : a.touch_edge)[elem] != 0;
+}
+
+__global__ void k_parent_init(ShapeArgs a, int* parent) {
+  const unsigned cap = a.N.mask + 1;
+  for (unsigned s = blockIdx.x * blockDim.x + threadIdx.x; s < cap; s += gridDim.x * blockDim.x) {
+    if (a.touch_cell) {
+      const unsigned long long key = a.N.keys[s];
+      if (key == EMPTY_KEY || !node_touched(a, key)) continue;
+    }
+    parent[s] = (int)s;
+  }
+}
+
+__global__ void k_clear_touched_b0(const unsigned char* touch, int* b0, size_t n) {
+  for (size_t k = blockIdx.x * (size_t)blockDim.x + threadIdx.x; k < n; k += (size_t)gridDim.x * blockDim.x)
+    if (touch[k]) b0[k] = 0;
 }
 
 // For every element piece with gluing bits: find the same element's piece in the face-adjacent tet, check that it
@@ -74,7 +94,7 @@ __global__ void k_glue(ShapeArgs a, int* parent) {
     unsigned long long key = a.N.keys[s];
     if (key == EMPTY_KEY || a.node_cnt[s] <= 0) continue;
     int g = a.node_glue[s];
-    if (!g) continue;
+    if (!g || !node_touched(a, key)) continue;
     const long long gt = (long long)(key & 0xffffffffull);
     const ShapeDesc& sd = a.shapes[shape_of_tet(a.shapes, a.nshapes, gt)];
     const int t = (int)(gt - sd.tet_off);
@@ -103,7 +123,7 @@ __global__ void k_count_roots(ShapeArgs a, int* parent, int* cell_b0, int* face_
     unsigned long long key = a.N.keys[s];
     if (key == EMPTY_KEY || a.node_cnt[s] <= 0) continue;
     ++nodes;
-    if (uf_find(parent, (int)s) != (int)s) continue;
+    if (!node_touched(a, key) || uf_find(parent, (int)s) != (int)s) continue;
     int kind = (int)(key >> 62);
     int elem = (int)((key >> 32) & 0x3fffffffull);
     if (kind == 1) atomicAdd(&cell_b0[elem], 1);
@@ -118,9 +138,15 @@ __global__ void k_count_roots(ShapeArgs a, int* parent, int* cell_b0, int* face_
   if (threadIdx.x == 0 && s_nodes) atomicAdd(&a.counters[C_NODES], s_nodes);
 }
 
+hipError_t launch_clear_touched_b0(const unsigned char* touch, int* b0, size_t n, hipStream_t s) {
+  if (!n) return hipSuccess;
+  hipLaunchKernelGGL(k_clear_touched_b0, dim3(grid_for(n, 256)), dim3(256), 0, s, touch, b0, n);
+  return hipGetLastError();
+}
+
 hipError_t launch_glue(const ShapeArgs& a, int* parent, hipStream_t s) {
   size_t cap = (size_t)a.N.mask + 1;
-  hipLaunchKernelGGL(k_parent_init, dim3(grid_for(cap, 256)), dim3(256), 0, s, a.N.keys, parent, (unsigned)cap);
+  hipLaunchKernelGGL(k_parent_init, dim3(grid_for(cap, 256)), dim3(256), 0, s, a, parent);
   hipLaunchKernelGGL(k_glue, dim3(grid_for(cap, 256)), dim3(256), 0, s, a, parent);
   return hipGetLastError();
 }

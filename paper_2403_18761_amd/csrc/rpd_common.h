@@ -89,6 +89,11 @@ struct ShapeArgs {
   int* node_glue;        // [cap N] bit f set: the element piece touches local face f of its tet (glue across it)
   int* node_cnt;         // [cap N] (live while > 0)
   int sign;              // +1 add the emitted contributions, -1 remove them (incremental update)
+  // optional (incremental update): element flags set by every emission, so that only the components of touched
+  // elements are recomputed; indexed by site (cells), face-table slot and edge-table slot
+  unsigned char* touch_cell;
+  unsigned char* touch_face;
+  unsigned char* touch_edge;
   double* tet_U;         // optional [total tets]: U_t of the candidate test, kept for the incremental update
   int4* deferred;        // (shape, local tet, global site or -1 for every candidate, 0) for the large-capacity path
   int deferred_cap;

@@ -483,6 +483,8 @@ __device__ inline int ht_find(const HashTab& h, unsigned long long key) {
 __device__ inline unsigned long long node_key(int kind, int elem, int t) {
   return ((unsigned long long)kind << 62) | ((unsigned long long)(unsigned)elem << 32) | (unsigned)t;
 }
+__device__ inline int node_kind(unsigned long long key) { return (int)(key >> 62); }
+__device__ inline int node_elem(unsigned long long key) { return (int)((key >> 32) & 0x3fffffffull); }
 
 // ---------------------------------------------------------------------------------------------------------------
 // The clipper: one convex piece P = t & {clipped half-spaces}, vertices in a Store, live slots in a mask.

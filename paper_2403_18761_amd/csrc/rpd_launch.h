@@ -16,7 +16,9 @@ hipError_t launch_clip_slow(const ShapeArgs& a, unsigned char* scratch, int wave
 // reduce.hip
 hipError_t launch_fill_u64(unsigned long long* p, unsigned long long v, size_t n, hipStream_t s);
 hipError_t launch_fill_i32(int* p, int v, size_t n, hipStream_t s);
+// union-find over the live element pieces (with a.touch_* set: only the pieces of touched elements)
 hipError_t launch_glue(const ShapeArgs& a, int* parent, hipStream_t s);
+hipError_t launch_clear_touched_b0(const unsigned char* touch, int* b0, size_t n, hipStream_t s);
 hipError_t launch_count_roots(const ShapeArgs& a, int* parent, int* cell_b0, int* face_b0, int* edge_b0,
                               hipStream_t s);
 hipError_t launch_iota(int* v, int n, hipStream_t s);

@@ -103,6 +103,8 @@ def load():
     lib.rpd_free.restype = None
     lib.rpd_last_error.restype = C.c_char_p
     lib.rpd_version.restype = C.c_char_p
+    lib.rpd_autotune.argtypes = [C.POINTER(C.c_void_p), C.POINTER(_Sites), C.c_int32, C.POINTER(_Opts),
+                                 C.POINTER(_Opts)]
     lib.rpd_session_create.argtypes = [C.c_void_p, C.POINTER(_Sites), C.POINTER(_Sites), C.POINTER(_SessionOpts),
                                        C.POINTER(C.c_void_p)]
     lib.rpd_session_run.argtypes = [C.c_void_p, C.c_int32]
@@ -113,7 +115,7 @@ def load():
     lib.rpd_session_free.restype = None
     for f in ("rpd_mesh_create", "rpd_mesh_get_info", "rpd_build", "rpd_euler", "rpd_components", "rpd_geometry",
               "rpd_adjacency", "rpd_get_stats", "rpd_pieces", "rpd_session_create", "rpd_session_run",
-              "rpd_session_result", "rpd_session_get_info", "rpd_session_sites"):
+              "rpd_session_result", "rpd_session_get_info", "rpd_session_sites", "rpd_autotune"):
         getattr(lib, f).restype = C.c_int32
     _lib = lib
     return lib
@@ -260,6 +262,25 @@ def build(meshes, sites, precision: int = RPD_FP32_FALLBACK, clip_budget: int = 
     h = C.c_void_p()
     _check(lib.rpd_build(handles, st, n, C.byref(o), C.byref(h)))
     return Result(h, n)
+
+
+def autotune(meshes, sites, flags: int = 0, stream=None) -> dict:
+    """rpd_autotune: time every launch shape on these inputs; returns the chosen {"block", "clip_budget"} (also
+    cached in the library for rpd_build calls that leave them at 0)."""
+    lib = load()
+    n = len(meshes)
+    keep = []
+    handles = (C.c_void_p * n)(*[m.handle.value for m in meshes])
+    st = (_Sites * n)()
+    dev = False
+    for k, (sx, sy, sz, sr) in enumerate(sites):
+        dev = dev or (_is_torch(sx) and sx.is_cuda)
+        st[k] = _Sites(int(sx.shape[0]), _ptr(sx, C.c_float, keep), _ptr(sy, C.c_float, keep),
+                       _ptr(sz, C.c_float, keep), _ptr(sr, C.c_float, keep))
+    o = _Opts(RPD_FP32_FALLBACK, 0, 0, flags | (RPD_DEVICE_PTRS if dev else 0), _stream_ptr(stream))
+    best = _Opts()
+    _check(lib.rpd_autotune(handles, st, n, C.byref(o), C.byref(best)))
+    return {"block": best.block, "clip_budget": best.clip_budget}
 
 
 def version() -> str:

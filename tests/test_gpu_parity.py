@@ -162,3 +162,39 @@ def test_dense_sites_split_blocks(N, n):
     log("split", st["n_split"], "deferred", st["n_defer_block"], st["n_defer_kmax"], st["n_defer_clip"])
     assert st["n_split"] > 0
     assert_parity(g, r, label=f"dense cube {N}")
+
+
+def test_launch_shapes_and_autotuner():
+    """Every launch shape the autotuner chooses from gives the same elements (bit for bit) and, for one clip budget,
+    the same volumes; the autotuner returns one of them and rpd_build then uses it."""
+    import torch
+
+    from paper_2403_18761_amd import rpd
+    from tests.gpu_util import ELEMENT_ARRAYS
+
+    prob = synth.torus_inside(32, 300, 7)
+    log("case: launch shapes")
+    r = _oracle(prob, assemble=False)
+    outs = {}
+    for block in (64, 128, 256):
+        for k in (16, 28):
+            g = run_gpu(prob, block=block, clip_budget=k)
+            assert_parity(g, r, label=f"block {block} k {k}")
+            outs[(block, k)] = g
+    for key, g in outs.items():
+        ref = outs[(128, key[1])]
+        for name in ELEMENT_ARRAYS:
+            np.testing.assert_array_equal(g[name], ref[name], err_msg=f"{key} {name}")
+    dev = torch.device("cuda:0")
+
+    def t(a, dt=torch.float32):
+        return torch.as_tensor(np.ascontiguousarray(a), dtype=dt, device=dev)
+
+    mesh = rpd.Mesh(t(prob.vx), t(prob.vy), t(prob.vz), t(prob.tv.reshape(-1), torch.int32))
+    sites = (t(prob.sx), t(prob.sy), t(prob.sz), t(prob.sr))
+    best = rpd.autotune([mesh], [sites])
+    log("autotuned", best)
+    assert best["block"] in (64, 128, 256) and best["clip_budget"] in (16, 28)
+    res = rpd.build([mesh], [sites])
+    _, chi = res.euler(0, rpd.RPD_CELL)
+    np.testing.assert_array_equal(chi, r["cell_chi"])

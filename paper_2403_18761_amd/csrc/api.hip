@@ -124,7 +124,7 @@ struct DeviceState {
   int def_cap = 0, piece_cap = 0;
   DBuf site, status, cell_chi, cell_geo, cell_np, cell_b0;
   DBuf fkeys, face_chi, face_np, face_b0, ekeys, edge_chi, edge_np, edge_b0, qkeys, rpv_cnt;
-  DBuf nkeys, node_glue, node_cnt, parent, deferred, pieces, counters, tetU, slow, touch;
+  DBuf nkeys, node_st, parent, deferred, pieces, counters, tetU, slow, touch;
   int waves = 0;
 
   unsigned long long* cnt() const { return counters.as<unsigned long long>(); }
@@ -158,8 +158,7 @@ struct DeviceState {
     qkeys.alloc(8 * (size_t)capQ);
     rpv_cnt.alloc(4 * (size_t)capQ);
     nkeys.alloc(8 * (size_t)capN);
-    node_glue.alloc(4 * (size_t)capN);
-    node_cnt.alloc(4 * (size_t)capN);
+    node_st.alloc(4 * (size_t)capN);
     parent.alloc(4 * (size_t)capN);
     deferred.alloc(16 * (size_t)def_cap);
     pieces.alloc(sizeof(PieceRec) * (size_t)std::max(piece_cap, 1));
@@ -187,8 +186,7 @@ struct DeviceState {
     hip_check(launch_fill_u64(qkeys.as<unsigned long long>(), EMPTY_KEY, capQ, s), "fill");
     hip_check(launch_fill_i32(rpv_cnt.as<int>(), 0, capQ, s), "fill");
     hip_check(launch_fill_u64(nkeys.as<unsigned long long>(), EMPTY_KEY, capN, s), "fill");
-    hip_check(launch_fill_i32(node_glue.as<int>(), 0, capN, s), "fill");
-    hip_check(launch_fill_i32(node_cnt.as<int>(), 0, capN, s), "fill");
+    hip_check(launch_fill_i32(node_st.as<int>(), 0, capN, s), "fill");
     hip_check(launch_fill_u64(cnt(), 0, NCOUNTERS + 8, s), "fill");
     if (touch.p) hip_check(launch_fill_i32(touch.as<int>(), 0, touch_words(), s), "fill");
   }
@@ -222,8 +220,7 @@ struct DeviceState {
     a.Q = HashTab{qkeys.as<unsigned long long>(), capQ - 1};
     a.rpv_cnt = rpv_cnt.as<int>();
     a.N = HashTab{nkeys.as<unsigned long long>(), capN - 1};
-    a.node_glue = node_glue.as<int>();
-    a.node_cnt = node_cnt.as<int>();
+    a.node_st = node_st.as<int>();
     a.sign = sign;
     a.tet_U = tetU.p ? tetU.as<double>() : nullptr;
     a.deferred = deferred.as<int4>();
@@ -267,8 +264,39 @@ static rpd_status status_error(int hst) {
   return RPD_OK;
 }
 
+// Pinned host staging for the result download (one copy per call), pooled like device memory.
+static std::mutex g_pin_mu;
+static std::map<size_t, std::vector<void*>> g_pin_pool;
+
+struct HostPinned {
+  void* p = nullptr;
+  size_t bytes = 0;
+  explicit HostPinned(size_t n) {
+    size_t c = 4096;
+    while (c < n) c <<= 1;
+    bytes = c;
+    {
+      std::lock_guard<std::mutex> g(g_pin_mu);
+      auto& v = g_pin_pool[c];
+      if (!v.empty()) {
+        p = v.back();
+        v.pop_back();
+        return;
+      }
+    }
+    hip_check(hipHostMalloc(&p, c, hipHostMallocDefault), "hipHostMalloc");
+  }
+  ~HostPinned() {
+    std::lock_guard<std::mutex> g(g_pin_mu);
+    g_pin_pool[bytes].push_back(p);
+  }
+  HostPinned(const HostPinned&) = delete;
+  HostPinned& operator=(const HostPinned&) = delete;
+};
+
 // Sorted element lists of the current state, copied to the host and split per shape. Returns false when a table
-// overflowed (the caller retries with larger tables).
+// overflowed (the caller retries with larger tables). Live entries are compacted first and the counts read back,
+// so that only they are sorted and downloaded.
 static bool collect(DeviceState& D, const std::vector<ShapeDesc>& hd, const ShapeDesc* dshapes,
                     const rpd_mesh* const* meshes, hipStream_t s, Timing& tm, std::vector<ShapeOut>& outs,
                     rpd_stats& st) {
@@ -276,51 +304,19 @@ static bool collect(DeviceState& D, const std::vector<ShapeDesc>& hd, const Shap
   int ns = 0;
   for (const auto& d : hd) ns = std::max(ns, d.site_off + d.ns);
   const unsigned capF = D.capF, capE = D.capE, capQ = D.capQ;
-  const int maxcap = (int)std::max(std::max(capF, capE), capQ);
-  size_t tmpb = sort_tmp_bytes(maxcap);
-  DBuf tmp(tmpb), kA(8 * (size_t)maxcap), kB(8 * (size_t)maxcap), kC(8 * (size_t)maxcap), vA(4 * (size_t)maxcap),
-      vB(4 * (size_t)maxcap);
-  DBuf f_keys(8 * (size_t)capF), f_chi(4 * (size_t)capF), f_b0(4 * (size_t)capF);
-  DBuf e_keys(12 * (size_t)capE), e_chi(4 * (size_t)capE), e_b0(4 * (size_t)capE);
-  DBuf c_chi(4 * (size_t)std::max(ns, 1)), c_vol(8 * (size_t)std::max(ns, 1)), c_cen(24 * (size_t)std::max(ns, 1));
-  DBuf rpv_raw(16 * (size_t)capQ), rpv_sorted(16 * (size_t)capQ);
-  unsigned long long* fin = D.fin_count();
-  hip_check(launch_fill_u64(fin, 0, 2, s), "fill");
-  hip_check(launch_live_keys(D.fkeys.as<unsigned long long>(), D.face_np.as<int>(), capF,
-                             kA.as<unsigned long long>(), s),
+  unsigned long long* fin = D.fin_count();  // [0] faces, [1] edges, [2] RPVs
+  DBuf fk(8 * (size_t)capF), fsl(4 * (size_t)capF), ek(8 * (size_t)capE), esl(4 * (size_t)capE),
+      rq(16 * (size_t)capQ);
+  hip_check(launch_fill_u64(fin, 0, 3, s), "fill");
+  hip_check(launch_compact_live(D.fkeys.as<unsigned long long>(), D.face_np.as<int>(), capF,
+                                fk.as<unsigned long long>(), fsl.as<int>(), fin + 0, s),
             "live faces");
-  hip_check(launch_iota(vA.as<int>(), capF, s), "iota");
-  hip_check(sort_pairs_u64(tmp.p, tmpb, kA.as<unsigned long long>(), kB.as<unsigned long long>(), vA.as<int>(),
-                           vB.as<int>(), capF, s),
-            "sort faces");
-  hip_check(launch_finalize_faces(kB.as<unsigned long long>(), vB.as<int>(), capF, D.face_chi.as<long long>(),
-                                  D.face_b0.as<int>(), dshapes, nsh, f_keys.as<int>(), f_chi.as<int>(),
-                                  f_b0.as<int>(), D.status.as<int>(), fin + 0, s),
-            "finalize faces");
-  hip_check(launch_live_keys(D.ekeys.as<unsigned long long>(), D.edge_np.as<int>(), capE,
-                             kA.as<unsigned long long>(), s),
+  hip_check(launch_compact_live(D.ekeys.as<unsigned long long>(), D.edge_np.as<int>(), capE,
+                                ek.as<unsigned long long>(), esl.as<int>(), fin + 1, s),
             "live edges");
-  hip_check(launch_iota(vA.as<int>(), capE, s), "iota");
-  hip_check(sort_pairs_u64(tmp.p, tmpb, kA.as<unsigned long long>(), kB.as<unsigned long long>(), vA.as<int>(),
-                           vB.as<int>(), capE, s),
-            "sort edges");
-  hip_check(launch_finalize_edges(kB.as<unsigned long long>(), vB.as<int>(), capE, D.edge_chi.as<long long>(),
-                                  D.edge_b0.as<int>(), dshapes, nsh, e_keys.as<int>(), e_chi.as<int>(),
-                                  e_b0.as<int>(), D.status.as<int>(), fin + 1, s),
-            "finalize edges");
-  if (ns > 0)
-    hip_check(launch_finalize_cells(ns, D.cell_chi.as<long long>(), D.cell_geo.as<long long>(), D.cell_np.as<int>(),
-                                    dshapes, nsh, c_chi.as<int>(), c_vol.as<double>(), c_cen.as<double>(),
-                                    D.status.as<int>(), s),
-              "finalize cells");
   HashTab Q{D.qkeys.as<unsigned long long>(), capQ - 1};
-  hip_check(launch_rpv_decode(Q, D.rpv_cnt.as<int>(), D.ekeys.as<unsigned long long>(), rpv_raw.as<int4>(), s),
-            "rpv decode");
-  hip_check(launch_sort_rpv(rpv_raw.as<int4>(), (int)capQ, kA.as<unsigned long long>(), kB.as<unsigned long long>(),
-                            kC.as<unsigned long long>(), vA.as<int>(), vB.as<int>(), tmp.p, tmpb,
-                            rpv_sorted.as<int4>(), s),
-            "sort rpv");
-  tm.mark(3, s);
+  hip_check(launch_rpv_compact(Q, D.rpv_cnt.as<int>(), D.ekeys.as<unsigned long long>(), rq.as<int4>(), fin + 2, s),
+            "live rpvs");
   unsigned long long hc[NCOUNTERS + 4];
   int hst = 0;
   hip_check(hipMemcpyAsync(hc, D.cnt(), sizeof(hc), hipMemcpyDeviceToHost, s), "download");
@@ -330,36 +326,79 @@ static bool collect(DeviceState& D, const std::vector<ShapeDesc>& hd, const Shap
   if (hc[C_DEFER_ITEMS] > (unsigned long long)D.def_cap || (D.piece_cap && hc[C_PIECES] > (unsigned long long)D.piece_cap))
     return false;
   status_error(hst);
-  const size_t nf = hc[NCOUNTERS + 0], ne = hc[NCOUNTERS + 1];
-  std::vector<int32_t> all_cchi, all_cb0, all_fk, all_fchi, all_fb0, all_ek, all_echi, all_eb0, all_rpv;
-  std::vector<double> all_vol, all_cen;
-  d2h(all_cchi, c_chi.p, ns, s);
-  d2h(all_cb0, D.cell_b0.p, ns, s);
-  d2h(all_vol, c_vol.p, ns, s);
-  d2h(all_cen, c_cen.p, 3 * (size_t)ns, s);
-  d2h(all_fk, f_keys.p, 2 * nf, s);
-  d2h(all_fchi, f_chi.p, nf, s);
-  d2h(all_fb0, f_b0.p, nf, s);
-  d2h(all_ek, e_keys.p, 3 * ne, s);
-  d2h(all_echi, e_chi.p, ne, s);
-  d2h(all_eb0, e_b0.p, ne, s);
-  d2h(all_rpv, rpv_sorted.p, 4 * (size_t)capQ, s);
+  const size_t nf = hc[NCOUNTERS + 0], ne = hc[NCOUNTERS + 1], nq = hc[NCOUNTERS + 2];
+
+  // one device buffer for everything that goes to the host: RPVs (int4) first, then the int32 and double arrays
+  const size_t n_int = 2 * (size_t)ns + 4 * nf + 5 * ne;
+  const size_t off_int = 16 * nq, off_dbl = (off_int + 4 * n_int + 7) / 8 * 8;
+  const size_t out_bytes = off_dbl + 8 * 4 * (size_t)ns;
+  DBuf out(std::max<size_t>(out_bytes, 16));
+  unsigned char* ob = out.as<unsigned char>();
+  int* c_chi = (int*)(ob + off_int);
+  int* c_b0 = c_chi + ns;
+  int* f_keys = c_b0 + ns;
+  int* f_chi = f_keys + 2 * nf;
+  int* f_b0 = f_chi + nf;
+  int* e_keys = f_b0 + nf;
+  int* e_chi = e_keys + 3 * ne;
+  int* e_b0 = e_chi + ne;
+  double* c_vol = (double*)(ob + off_dbl);
+  double* c_cen = c_vol + ns;
+
+  const size_t maxn = std::max(std::max(nf, ne), std::max(nq, (size_t)1));
+  size_t tmpb = sort_tmp_bytes((int)maxn);
+  DBuf tmp(tmpb), kA(8 * maxn), kB(8 * maxn), kC(8 * maxn), vA(4 * maxn), vB(4 * maxn);
+  hip_check(sort_pairs_u64(tmp.p, tmpb, fk.as<unsigned long long>(), kB.as<unsigned long long>(), fsl.as<int>(),
+                           vB.as<int>(), (int)nf, s),
+            "sort faces");
+  hip_check(launch_finalize_faces(kB.as<unsigned long long>(), vB.as<int>(), (int)nf, D.face_chi.as<long long>(),
+                                  D.face_b0.as<int>(), dshapes, nsh, f_keys, f_chi, f_b0, D.status.as<int>(), s),
+            "finalize faces");
+  hip_check(sort_pairs_u64(tmp.p, tmpb, ek.as<unsigned long long>(), kB.as<unsigned long long>(), esl.as<int>(),
+                           vB.as<int>(), (int)ne, s),
+            "sort edges");
+  hip_check(launch_finalize_edges(kB.as<unsigned long long>(), vB.as<int>(), (int)ne, D.edge_chi.as<long long>(),
+                                  D.edge_b0.as<int>(), dshapes, nsh, e_keys, e_chi, e_b0, D.status.as<int>(), s),
+            "finalize edges");
+  if (ns > 0)
+    hip_check(launch_finalize_cells(ns, D.cell_chi.as<long long>(), D.cell_geo.as<long long>(), D.cell_np.as<int>(),
+                                    D.cell_b0.as<int>(), dshapes, nsh, c_chi, c_b0, c_vol, c_cen, D.status.as<int>(),
+                                    s),
+              "finalize cells");
+  hip_check(launch_sort_rpv(rq.as<int4>(), (int)nq, kA.as<unsigned long long>(), kB.as<unsigned long long>(),
+                            kC.as<unsigned long long>(), vA.as<int>(), vB.as<int>(), tmp.p, tmpb, (int4*)ob, s),
+            "sort rpv");
+  tm.mark(3, s);
+  HostPinned host(out_bytes + 16);
+  unsigned char* hb = (unsigned char*)host.p;
+  hip_check(hipMemcpyAsync(hb, ob, out_bytes, hipMemcpyDeviceToHost, s), "download");
+  hip_check(hipMemcpyAsync(hb + out_bytes, D.status.p, sizeof(int), hipMemcpyDeviceToHost, s), "download");
   std::vector<PieceRec> prs;
   if (D.piece_cap) d2h(prs, D.pieces.p, hc[C_PIECES], s);
   tm.mark(4, s);
   hip_check(hipStreamSynchronize(s), "synchronize");
-  size_t nq = 0;
-  while (nq < (size_t)capQ && all_rpv[4 * nq] != 0x7fffffff) ++nq;
+  status_error(*(int*)(hb + out_bytes));
+  const int* all_rpv = (const int*)hb;
+  const int* all_cchi = (const int*)(hb + off_int);
+  const int* all_cb0 = all_cchi + ns;
+  const int* all_fk = all_cb0 + ns;
+  const int* all_fchi = all_fk + 2 * nf;
+  const int* all_fb0 = all_fchi + nf;
+  const int* all_ek = all_fb0 + nf;
+  const int* all_echi = all_ek + 3 * ne;
+  const int* all_eb0 = all_echi + ne;
+  const double* all_vol = (const double*)(hb + off_dbl);
+  const double* all_cen = all_vol + ns;
   // ---- split per shape (element lists are sorted by batch-global keys, so each shape is one contiguous run)
   size_t fpos = 0, epos = 0, qpos = 0;
   for (int k = 0; k < nsh; ++k) {
     ShapeOut& out = outs[k];
     const int off = hd[k].site_off, n = hd[k].ns, end = off + n;
     out.ns = n;
-    out.cell_chi.assign(all_cchi.begin() + off, all_cchi.begin() + end);
-    out.cell_b0.assign(all_cb0.begin() + off, all_cb0.begin() + end);
-    out.vol.assign(all_vol.begin() + off, all_vol.begin() + end);
-    out.cen.assign(all_cen.begin() + 3 * (size_t)off, all_cen.begin() + 3 * (size_t)end);
+    out.cell_chi.assign(all_cchi + off, all_cchi + end);
+    out.cell_b0.assign(all_cb0 + off, all_cb0 + end);
+    out.vol.assign(all_vol + off, all_vol + end);
+    out.cen.assign(all_cen + 3 * (size_t)off, all_cen + 3 * (size_t)end);
     out.cell_keys.resize(n);
     std::iota(out.cell_keys.begin(), out.cell_keys.end(), 0);
     out.face_keys.clear();

@@ -32,13 +32,8 @@ __device__ inline long long wv_of(typename Topo::W w, const unsigned* nu, long l
   return w_vertex(Topo::plane(w, 0), Topo::plane(w, 1), Topo::plane(w, 2), nu, L);
 }
 
-__device__ inline void add_fixed(long long* dst, double v, int sign) {  // fixed point 2^-56, exactly invertible
-  long long q = llrint(v * 72057594037927936.0);
-  atomicAdd((unsigned long long*)dst, (unsigned long long)(sign * q));
-}
-
-// One element piece (element, tet) is emitted exactly once per pass: adding sets its gluing bits, removing clears
-// them; the count tells whether the piece is live.
+// One element piece (element, tet) is emitted exactly once per pass: adding sets its gluing bits and count,
+// removing (the same piece recomputed with sign -1) takes both back.
 __device__ inline void node_emit(const ShapeArgs& a, unsigned long long key, int glue) {
   int ns = ht_insert(a.N, key, a.status);
   if (ns < 0) return;
@@ -46,16 +41,24 @@ __device__ inline void node_emit(const ShapeArgs& a, unsigned long long key, int
     const int kind = node_kind(key), elem = node_elem(key);
     (kind == 1 ? a.touch_cell : kind == 2 ? a.touch_face : a.touch_edge)[elem] = 1;
   }
-  if (a.sign > 0) {
-    if (glue) atomicOr(&a.node_glue[ns], glue);
-  } else {
-    atomicAnd(&a.node_glue[ns], 0);
-  }
-  atomicAdd(&a.node_cnt[ns], a.sign);
+  atomicAdd(&a.node_st[ns], a.sign * (16 + glue));  // removal re-emits the same bits, so this is exact
 }
 
+// Workgroup-local sums of the cell terms (chi numerator, piece count, fixed-point volume and moments) for the first
+// n sites of the workgroup's site list; a piece of another site adds to the global arrays directly.
+struct CellSink {
+  long long* chi;  // [n] (LDS)
+  int* np;         // [n]
+  long long* geo;  // [4 n]
+  int n;
+  int q;           // the piece's index in the workgroup's site list, or -1
+};
+
+__device__ inline long long fixed56(double v) { return llrint(v * 72057594037927936.0); }  // 2^-56 units
+
 template <typename T, typename Topo, typename Mask, int VCAP, bool EXACT>
-__device__ void emit_piece(Clipper<T, Topo, Mask, VCAP, EXACT>& c, const ShapeDesc& sd, int tl, const ShapeArgs& a) {
+__device__ void emit_piece(Clipper<T, Topo, Mask, VCAP, EXACT>& c, const ShapeDesc& sd, int tl, const ShapeArgs& a,
+                           const CellSink& sink) {
   typedef typename Topo::W W;
   const int i = c.env.site_i;  // batch-global site id
   const unsigned* nu = sd.nu + 14 * (size_t)tl;
@@ -200,18 +203,23 @@ __device__ void emit_piece(Clipper<T, Topo, Mask, VCAP, EXACT>& c, const ShapeDe
   }
   // ---- cell contributions
   long long chi = sv - se + sf - L;
-  atomicAdd((unsigned long long*)&a.cell_chi[i], (unsigned long long)(a.sign * chi));
-  atomicAdd(&a.cell_np[i], a.sign);
   node_emit(a, node_key(1, i, t), cell_glue);
   // moments were accumulated with 4x the centroid sum; shift to absolute coordinates
   float4 o = c.env.tv[0];
   double dvol = (double)vol;
   double dmx = (double)mx * 0.25 + dvol * o.x, dmy = (double)my * 0.25 + dvol * o.y,
          dmz = (double)mz * 0.25 + dvol * o.z;
-  add_fixed(&a.cell_geo[4 * (size_t)i + 0], dvol, a.sign);
-  add_fixed(&a.cell_geo[4 * (size_t)i + 1], dmx, a.sign);
-  add_fixed(&a.cell_geo[4 * (size_t)i + 2], dmy, a.sign);
-  add_fixed(&a.cell_geo[4 * (size_t)i + 3], dmz, a.sign);
+  const long long g[4] = {fixed56(dvol), fixed56(dmx), fixed56(dmy), fixed56(dmz)};
+  if (sink.q >= 0 && sink.q < sink.n) {  // workgroup-local sums, flushed once per workgroup pass
+    atomicAdd((unsigned long long*)&sink.chi[sink.q], (unsigned long long)chi);
+    atomicAdd(&sink.np[sink.q], 1);
+    for (int k = 0; k < 4; ++k) atomicAdd((unsigned long long*)&sink.geo[4 * sink.q + k], (unsigned long long)g[k]);
+  } else {
+    atomicAdd((unsigned long long*)&a.cell_chi[i], (unsigned long long)(a.sign * chi));
+    atomicAdd(&a.cell_np[i], a.sign);
+    for (int k = 0; k < 4; ++k)
+      atomicAdd((unsigned long long*)&a.cell_geo[4 * (size_t)i + k], (unsigned long long)(a.sign * g[k]));
+  }
   if (a.flags & RPD_KEEP_PIECES) {
     unsigned long long idx = atomicAdd(&a.counters[C_PIECES], 1ull);
     if (idx < (unsigned long long)a.piece_cap) {
@@ -356,10 +364,21 @@ __global__ __launch_bounds__(NT) void k_clip_fast(ShapeArgs a) {
   __shared__ unsigned long long s_cnt[4];
   __shared__ unsigned s_topo[VMAX * NT];
   __shared__ unsigned char s_tab[32 * NT];
+  // per-site sums of the workgroup's cell terms (all sites of the list, or the first 32 with 64 threads, where the
+  // LDS budget for four workgroups per compute unit is tight)
+  constexpr int AGG = NT == 64 ? 32 : SLMAX;
+  __shared__ long long s_acc_chi[AGG];
+  __shared__ int s_acc_np[AGG];
+  __shared__ long long s_acc_geo[4 * AGG];
 
   const int tid = threadIdx.x;
   const int lane = tid & 63, wid = tid >> 6;
   for (int k = tid; k < 32 * NT; k += NT) s_tab[k] = 0;
+  for (int k = tid; k < AGG; k += NT) {
+    s_acc_chi[k] = 0;
+    s_acc_np[k] = 0;
+    for (int d = 0; d < 4; ++d) s_acc_geo[4 * k + d] = 0;
+  }
   unsigned long long n_pairs = 0, n64 = 0, n_cand = 0;
   // One workgroup per (shape, block) item; items are ordered heaviest first and the hardware dispatcher hands
   // them to compute units in that order as they free up, which is the work queue. (A persistent loop that pulls
@@ -575,13 +594,28 @@ __global__ __launch_bounds__(NT) void k_clip_fast(ShapeArgs a) {
     n64 += cl.n64;
     if (r == CLIP_OK) {
       ++n_pairs;
-      emit_piece(cl, sd, t0 + lt, a);
+      const CellSink sink{s_acc_chi, s_acc_np, s_acc_geo, AGG, (int)s_cand[lt][ci]};
+      emit_piece(cl, sd, t0 + lt, a, sink);
     } else if (r == CLIP_DEFER) {
       atomicAdd(&a.counters[C_DEFER_CLIP], 1ull);
       unsigned long long idx = atomicAdd(&a.counters[C_DEFER_ITEMS], 1ull);
       if (idx < (unsigned long long)a.deferred_cap) a.deferred[idx] = make_int4(wi.x, t0 + lt, cl.env.site_i, 0);
       else atomicOr(a.status, ST_TABLE_FULL);
     }
+  }
+  // flush the workgroup's cell sums of this pass (the site list changes with the next chunk)
+  __syncthreads();
+  for (int q = tid; q < min(nsl, AGG); q += NT) {
+    const int np_q = s_acc_np[q];
+    if (np_q == 0) continue;
+    const int i = s_sid[q];
+    atomicAdd((unsigned long long*)&a.cell_chi[i], (unsigned long long)(a.sign * s_acc_chi[q]));
+    atomicAdd(&a.cell_np[i], a.sign * np_q);
+    for (int d = 0; d < 4; ++d)
+      atomicAdd((unsigned long long*)&a.cell_geo[4 * (size_t)i + d], (unsigned long long)(a.sign * s_acc_geo[4 * q + d]));
+    s_acc_chi[q] = 0;
+    s_acc_np[q] = 0;
+    for (int d = 0; d < 4; ++d) s_acc_geo[4 * q + d] = 0;
   }
   if (!split) break;
   sub += SUB;
@@ -732,7 +766,7 @@ __global__ __launch_bounds__(64) void k_clip_slow(ShapeArgs a, unsigned char* sc
       }
       if (r == CLIP_OK) {
         ++n_pairs;
-        emit_piece(cl, sd, t, a);
+        emit_piece(cl, sd, t, a, CellSink{nullptr, nullptr, nullptr, 0, -1});
       }
     }
     __syncthreads();  // the candidate list is rewritten by the next item

@@ -92,8 +92,9 @@ __global__ void k_glue(ShapeArgs a, int* parent) {
   const unsigned cap = a.N.mask + 1;
   for (unsigned s = blockIdx.x * blockDim.x + threadIdx.x; s < cap; s += gridDim.x * blockDim.x) {
     unsigned long long key = a.N.keys[s];
-    if (key == EMPTY_KEY || a.node_cnt[s] <= 0) continue;
-    int g = a.node_glue[s];
+    const int st = a.node_st[s];
+    if (key == EMPTY_KEY || !node_live(st)) continue;
+    int g = node_glue_bits(st);
     if (!g || !node_touched(a, key)) continue;
     const long long gt = (long long)(key & 0xffffffffull);
     const ShapeDesc& sd = a.shapes[shape_of_tet(a.shapes, a.nshapes, gt)];
@@ -107,7 +108,8 @@ __global__ void k_glue(ShapeArgs a, int* parent) {
       for (int q = 0; q < 4; ++q)
         if (sd.tn[4 * (size_t)t2 + q] == t) f2 = q;
       int s2 = ht_find(a.N, hi | (unsigned)(sd.tet_off + t2));
-      if (s2 < 0 || f2 < 0 || a.node_cnt[s2] <= 0 || !(a.node_glue[s2] & (1 << f2))) {
+      const int st2 = s2 >= 0 ? a.node_st[s2] : 0;
+      if (s2 < 0 || f2 < 0 || !node_live(st2) || !(node_glue_bits(st2) & (1 << f2))) {
         atomicOr(a.status, ST_INTERNAL);
         continue;
       }
@@ -121,7 +123,9 @@ __global__ void k_count_roots(ShapeArgs a, int* parent, int* cell_b0, int* face_
   unsigned long long nodes = 0;
   for (unsigned s = blockIdx.x * blockDim.x + threadIdx.x; s < cap; s += gridDim.x * blockDim.x) {
     unsigned long long key = a.N.keys[s];
-    if (key == EMPTY_KEY || a.node_cnt[s] <= 0) continue;
+    const int st = key == EMPTY_KEY ? 0 : a.node_st[s];
+    if (st < 0 || st >= 32) atomicOr(a.status, ST_INTERNAL);  // every piece is present at most once
+    if (!node_live(st)) continue;
     ++nodes;
     if (!node_touched(a, key) || uf_find(parent, (int)s) != (int)s) continue;
     int kind = (int)(key >> 62);
@@ -159,59 +163,68 @@ hipError_t launch_count_roots(const ShapeArgs& a, int* parent, int* cell_b0, int
 }
 
 // ---------------------------------------------------------------------------------------------------------------
-// element lists: sort the whole hash-table capacity by key (free slots hold the largest key and sort last), then
-// turn the fractional sums into integers
+// element lists: compact the live entries of a table (any order), sort exactly those by key, then turn the
+// fractional sums into integers
 // ---------------------------------------------------------------------------------------------------------------
-__global__ void k_iota(int* v, int n) {
-  for (int q = blockIdx.x * blockDim.x + threadIdx.x; q < n; q += gridDim.x * blockDim.x) v[q] = q;
-}
-hipError_t launch_iota(int* v, int n, hipStream_t s) {
-  hipLaunchKernelGGL(k_iota, dim3(grid_for(n, 256)), dim3(256), 0, s, v, n);
-  return hipGetLastError();
-}
-
-// copy of a table's keys for sorting in which entries without live pieces become free slots
-__global__ void k_live_keys(const unsigned long long* keys, const int* np, unsigned cap, unsigned long long* out) {
-  for (unsigned q = blockIdx.x * blockDim.x + threadIdx.x; q < cap; q += gridDim.x * blockDim.x)
-    out[q] = np[q] > 0 ? keys[q] : EMPTY_KEY;
-}
-hipError_t launch_live_keys(const unsigned long long* keys, const int* np, unsigned cap, unsigned long long* out,
-                            hipStream_t s) {
-  hipLaunchKernelGGL(k_live_keys, dim3(grid_for(cap, 256)), dim3(256), 0, s, keys, np, cap, out);
-  return hipGetLastError();
+// append position for the active lanes of a wave (one atomic per wave)
+__device__ inline unsigned long long wave_append(unsigned long long* count) {
+  const unsigned long long active = __ballot(1);
+  const int lane = (int)__lane_id();
+  const int leader = __ffsll((long long)active) - 1;
+  unsigned long long base = 0;
+  if (lane == leader) base = atomicAdd(count, (unsigned long long)__popcll(active));
+  base = __shfl(base, leader);
+  return base + (unsigned long long)__popcll(active & ((1ull << lane) - 1ull));
 }
 
-// RPV quadruples (i, j, k, l) from the counted set: key = edge slot of (i, j, k) << 21 | l
-__global__ void k_rpv_decode(HashTab Q, const int* cnt, const unsigned long long* ekeys, int4* out) {
-  const unsigned cap = Q.mask + 1;
+__global__ void k_compact_live(const unsigned long long* keys, const int* np, unsigned cap, unsigned long long* out_keys,
+                               int* out_slots, unsigned long long* count) {
   for (unsigned q = blockIdx.x * blockDim.x + threadIdx.x; q < cap; q += gridDim.x * blockDim.x) {
-    unsigned long long k = Q.keys[q];
-    if (k == EMPTY_KEY || cnt[q] <= 0) {
-      out[q] = make_int4(0x7fffffff, 0x7fffffff, 0x7fffffff, 0x7fffffff);
-      continue;
-    }
-    unsigned long long e = ekeys[k >> 21];
-    out[q] = make_int4((int)(e >> 42), (int)((e >> 21) & 0x1fffff), (int)(e & 0x1fffff), (int)(k & 0x1fffff));
+    const unsigned long long k = keys[q];
+    if (k == EMPTY_KEY || np[q] <= 0) continue;
+    const unsigned long long idx = wave_append(count);
+    out_keys[idx] = k;
+    out_slots[idx] = (int)q;
   }
 }
-hipError_t launch_rpv_decode(const HashTab& Q, const int* cnt, const unsigned long long* ekeys, int4* out,
-                             hipStream_t s) {
-  hipLaunchKernelGGL(k_rpv_decode, dim3(grid_for((size_t)Q.mask + 1, 256)), dim3(256), 0, s, Q, cnt, ekeys, out);
+hipError_t launch_compact_live(const unsigned long long* keys, const int* np, unsigned cap,
+                               unsigned long long* out_keys, int* out_slots, unsigned long long* count,
+                               hipStream_t s) {
+  hipLaunchKernelGGL(k_compact_live, dim3(grid_for(cap, 256)), dim3(256), 0, s, keys, np, cap, out_keys, out_slots,
+                     count);
+  return hipGetLastError();
+}
+
+// RPV quadruples (i, j, k, l) of the counted set (key = edge slot of (i, j, k) << 21 | l), compacted
+__global__ void k_rpv_compact(HashTab Q, const int* cnt, const unsigned long long* ekeys, int4* out,
+                              unsigned long long* count) {
+  const unsigned cap = Q.mask + 1;
+  for (unsigned q = blockIdx.x * blockDim.x + threadIdx.x; q < cap; q += gridDim.x * blockDim.x) {
+    const unsigned long long k = Q.keys[q];
+    if (k == EMPTY_KEY || cnt[q] <= 0) continue;
+    const unsigned long long e = ekeys[k >> 21];
+    const unsigned long long idx = wave_append(count);
+    out[idx] = make_int4((int)(e >> 42), (int)((e >> 21) & 0x1fffff), (int)(e & 0x1fffff), (int)(k & 0x1fffff));
+  }
+}
+hipError_t launch_rpv_compact(const HashTab& Q, const int* cnt, const unsigned long long* ekeys, int4* out,
+                              unsigned long long* count, hipStream_t s) {
+  hipLaunchKernelGGL(k_rpv_compact, dim3(grid_for((size_t)Q.mask + 1, 256)), dim3(256), 0, s, Q, cnt, ekeys, out,
+                     count);
   return hipGetLastError();
 }
 
 hipError_t sort_pairs_u64(void* tmp, size_t& tmp_bytes, const unsigned long long* kin, unsigned long long* kout,
                           const int* vin, int* vout, int n, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
   return rocprim::radix_sort_pairs(tmp, tmp_bytes, kin, kout, vin, vout, (size_t)n, 0, 64, s);
 }
 
-__global__ void k_finalize_faces(const unsigned long long* keys, const int* slots, int cap, const long long* chi_num,
+__global__ void k_finalize_faces(const unsigned long long* keys, const int* slots, int n, const long long* chi_num,
                                  const int* b0, const ShapeDesc* shapes, int nshapes, int* out_keys, int* out_chi,
-                                 int* out_b0, int* status, unsigned long long* count) {
-  unsigned long long used = 0;
-  for (int q = blockIdx.x * blockDim.x + threadIdx.x; q < cap; q += gridDim.x * blockDim.x) {
+                                 int* out_b0, int* status) {
+  for (int q = blockIdx.x * blockDim.x + threadIdx.x; q < n; q += gridDim.x * blockDim.x) {
     unsigned long long k = keys[q];
-    if (k == EMPTY_KEY) continue;
     int s = slots[q];
     out_keys[2 * q] = (int)(k >> 32);
     out_keys[2 * q + 1] = (int)(k & 0xffffffffull);
@@ -220,22 +233,13 @@ __global__ void k_finalize_faces(const unsigned long long* keys, const int* slot
     if (c % L != 0) atomicOr(status, ST_INTERNAL);
     out_chi[q] = (int)(c / L);
     out_b0[q] = b0[s];
-    ++used;
   }
-  __shared__ unsigned long long s_used;
-  if (threadIdx.x == 0) s_used = 0;
-  __syncthreads();
-  if (used) atomicAdd(&s_used, used);
-  __syncthreads();
-  if (threadIdx.x == 0 && s_used) atomicAdd(count, s_used);
 }
-__global__ void k_finalize_edges(const unsigned long long* keys, const int* slots, int cap, const long long* chi_num,
+__global__ void k_finalize_edges(const unsigned long long* keys, const int* slots, int n, const long long* chi_num,
                                  const int* b0, const ShapeDesc* shapes, int nshapes, int* out_keys, int* out_chi,
-                                 int* out_b0, int* status, unsigned long long* count) {
-  unsigned long long used = 0;
-  for (int q = blockIdx.x * blockDim.x + threadIdx.x; q < cap; q += gridDim.x * blockDim.x) {
+                                 int* out_b0, int* status) {
+  for (int q = blockIdx.x * blockDim.x + threadIdx.x; q < n; q += gridDim.x * blockDim.x) {
     unsigned long long k = keys[q];
-    if (k == EMPTY_KEY) continue;
     int s = slots[q];
     out_keys[3 * q] = (int)(k >> 42);
     out_keys[3 * q + 1] = (int)((k >> 21) & 0x1fffff);
@@ -245,23 +249,17 @@ __global__ void k_finalize_edges(const unsigned long long* keys, const int* slot
     if (c % L != 0) atomicOr(status, ST_INTERNAL);
     out_chi[q] = (int)(c / L);
     out_b0[q] = b0[s];
-    ++used;
   }
-  __shared__ unsigned long long s_used;
-  if (threadIdx.x == 0) s_used = 0;
-  __syncthreads();
-  if (used) atomicAdd(&s_used, used);
-  __syncthreads();
-  if (threadIdx.x == 0 && s_used) atomicAdd(count, s_used);
 }
-__global__ void k_finalize_cells(int ns, const long long* chi_num, const long long* geo, const int* np,
-                                 const ShapeDesc* shapes, int nshapes, int* out_chi, double* out_vol, double* out_cen,
-                                 int* status) {
+__global__ void k_finalize_cells(int ns, const long long* chi_num, const long long* geo, const int* np, const int* b0,
+                                 const ShapeDesc* shapes, int nshapes, int* out_chi, int* out_b0, double* out_vol,
+                                 double* out_cen, int* status) {
   for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < ns; i += gridDim.x * blockDim.x) {
     const long long L = shapes[shape_of_site(shapes, nshapes, i)].L;
     long long c = chi_num[i];
     if (c % L != 0) atomicOr(status, ST_INTERNAL);
     out_chi[i] = (int)(c / L);
+    out_b0[i] = b0[i];
     const double sc = 1.0 / 72057594037927936.0;  // 2^-56
     double v = (double)geo[4 * (size_t)i] * sc;
     out_vol[i] = v;
@@ -269,30 +267,31 @@ __global__ void k_finalize_cells(int ns, const long long* chi_num, const long lo
   }
 }
 
-hipError_t launch_finalize_faces(const unsigned long long* keys, const int* slots, int cap, const long long* chi_num,
+hipError_t launch_finalize_faces(const unsigned long long* keys, const int* slots, int n, const long long* chi_num,
                                  const int* b0, const ShapeDesc* shapes, int nshapes, int* out_keys, int* out_chi,
-                                 int* out_b0, int* status, unsigned long long* count, hipStream_t s) {
-  hipLaunchKernelGGL(k_finalize_faces, dim3(grid_for(cap, 256)), dim3(256), 0, s, keys, slots, cap, chi_num, b0, shapes,
-                     nshapes, out_keys, out_chi, out_b0, status, count);
+                                 int* out_b0, int* status, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_finalize_faces, dim3(grid_for(n, 256)), dim3(256), 0, s, keys, slots, n, chi_num, b0, shapes,
+                     nshapes, out_keys, out_chi, out_b0, status);
   return hipGetLastError();
 }
-hipError_t launch_finalize_edges(const unsigned long long* keys, const int* slots, int cap, const long long* chi_num,
+hipError_t launch_finalize_edges(const unsigned long long* keys, const int* slots, int n, const long long* chi_num,
                                  const int* b0, const ShapeDesc* shapes, int nshapes, int* out_keys, int* out_chi,
-                                 int* out_b0, int* status, unsigned long long* count, hipStream_t s) {
-  hipLaunchKernelGGL(k_finalize_edges, dim3(grid_for(cap, 256)), dim3(256), 0, s, keys, slots, cap, chi_num, b0, shapes,
-                     nshapes, out_keys, out_chi, out_b0, status, count);
+                                 int* out_b0, int* status, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_finalize_edges, dim3(grid_for(n, 256)), dim3(256), 0, s, keys, slots, n, chi_num, b0, shapes,
+                     nshapes, out_keys, out_chi, out_b0, status);
   return hipGetLastError();
 }
-hipError_t launch_finalize_cells(int ns, const long long* chi_num, const long long* geo, const int* np,
-                                 const ShapeDesc* shapes, int nshapes, int* out_chi, double* out_vol, double* out_cen,
-                                 int* status, hipStream_t s) {
-  hipLaunchKernelGGL(k_finalize_cells, dim3(grid_for(ns, 256)), dim3(256), 0, s, ns, chi_num, geo, np, shapes, nshapes,
-                     out_chi, out_vol, out_cen, status);
+hipError_t launch_finalize_cells(int ns, const long long* chi_num, const long long* geo, const int* np, const int* b0,
+                                 const ShapeDesc* shapes, int nshapes, int* out_chi, int* out_b0, double* out_vol,
+                                 double* out_cen, int* status, hipStream_t s) {
+  hipLaunchKernelGGL(k_finalize_cells, dim3(grid_for(ns, 256)), dim3(256), 0, s, ns, chi_num, geo, np, b0, shapes,
+                     nshapes, out_chi, out_b0, out_vol, out_cen, status);
   return hipGetLastError();
 }
 
-// RPV quadruples: two stable radix passes (by (k, l), then by (i, j)) over the whole buffer; unused entries hold
-// INT_MAX ids and sort last
+// RPV quadruples: two stable radix passes, by (k, l) and then by (i, j)
 __global__ void k_rpv_keys(const int4* rpv, int n, unsigned long long* k_hi, unsigned long long* k_lo, int* idx) {
   for (int q = blockIdx.x * blockDim.x + threadIdx.x; q < n; q += gridDim.x * blockDim.x) {
     int4 r = rpv[q];
@@ -306,14 +305,6 @@ __global__ void k_gather_u64(const unsigned long long* src, const int* idx, unsi
 }
 __global__ void k_gather_rpv(const int4* src, const int* idx, int4* dst, int n) {
   for (int q = blockIdx.x * blockDim.x + threadIdx.x; q < n; q += gridDim.x * blockDim.x) dst[q] = src[idx[q]];
-}
-__global__ void k_fill_rpv(int4* p, int n) {
-  for (int q = blockIdx.x * blockDim.x + threadIdx.x; q < n; q += gridDim.x * blockDim.x)
-    p[q] = make_int4(0x7fffffff, 0x7fffffff, 0x7fffffff, 0x7fffffff);
-}
-hipError_t launch_fill_rpv(int4* p, int n, hipStream_t s) {
-  hipLaunchKernelGGL(k_fill_rpv, dim3(grid_for(n, 256)), dim3(256), 0, s, p, n);
-  return hipGetLastError();
 }
 
 // buffers: ka, kb, kc of n u64 each; va, vb of n ints

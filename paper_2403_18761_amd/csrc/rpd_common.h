@@ -37,6 +37,10 @@ enum {
 
 constexpr unsigned long long EMPTY_KEY = ~0ull;
 
+// element-piece state word
+__host__ __device__ inline bool node_live(int st) { return st >= 16; }
+__host__ __device__ inline int node_glue_bits(int st) { return st & 15; }
+
 struct HashTab {
   unsigned long long* keys;  // EMPTY_KEY when free
   unsigned int mask;         // capacity - 1, capacity a power of two
@@ -86,8 +90,8 @@ struct ShapeArgs {
   HashTab Q;             // RPVs (i<j<k<l): key edge slot of (i,j,k) << 21 | l
   int* rpv_cnt;          // [cap Q] (exists while > 0)
   HashTab N;             // element pieces (union-find nodes): kind<<62 | elem<<32 | global tet
-  int* node_glue;        // [cap N] bit f set: the element piece touches local face f of its tet (glue across it)
-  int* node_cnt;         // [cap N] (live while > 0)
+  int* node_st;          // [cap N] 16 x (times the piece is present) + gluing bits (bit f: glue across local face
+                         // f of its tet); a piece is emitted once per pass, so adding the bits equals or-ing them
   int sign;              // +1 add the emitted contributions, -1 remove them (incremental update)
   // optional (incremental update): element flags set by every emission, so that only the components of touched
   // elements are recomputed; indexed by site (cells), face-table slot and edge-table slot

@@ -21,25 +21,25 @@ hipError_t launch_glue(const ShapeArgs& a, int* parent, hipStream_t s);
 hipError_t launch_clear_touched_b0(const unsigned char* touch, int* b0, size_t n, hipStream_t s);
 hipError_t launch_count_roots(const ShapeArgs& a, int* parent, int* cell_b0, int* face_b0, int* edge_b0,
                               hipStream_t s);
-hipError_t launch_iota(int* v, int n, hipStream_t s);
-hipError_t launch_live_keys(const unsigned long long* keys, const int* np, unsigned cap, unsigned long long* out,
-                            hipStream_t s);
-hipError_t launch_rpv_decode(const HashTab& Q, const int* cnt, const unsigned long long* ekeys, int4* out,
-                             hipStream_t s);
+// live entries of a counted table, compacted in any order (count += their number)
+hipError_t launch_compact_live(const unsigned long long* keys, const int* np, unsigned cap,
+                               unsigned long long* out_keys, int* out_slots, unsigned long long* count,
+                               hipStream_t s);
+hipError_t launch_rpv_compact(const HashTab& Q, const int* cnt, const unsigned long long* ekeys, int4* out,
+                              unsigned long long* count, hipStream_t s);
 hipError_t sort_pairs_u64(void* tmp, size_t& tmp_bytes, const unsigned long long* kin, unsigned long long* kout,
                           const int* vin, int* vout, int n, hipStream_t s);
 size_t sort_tmp_bytes(int n);
-// element lists over a whole sorted table capacity: free slots (EMPTY keys) are skipped; count += used entries
-hipError_t launch_finalize_faces(const unsigned long long* keys, const int* slots, int cap, const long long* chi_num,
+// element lists over exactly n sorted live entries
+hipError_t launch_finalize_faces(const unsigned long long* keys, const int* slots, int n, const long long* chi_num,
                                  const int* b0, const ShapeDesc* shapes, int nshapes, int* out_keys, int* out_chi,
-                                 int* out_b0, int* status, unsigned long long* count, hipStream_t s);
-hipError_t launch_finalize_edges(const unsigned long long* keys, const int* slots, int cap, const long long* chi_num,
+                                 int* out_b0, int* status, hipStream_t s);
+hipError_t launch_finalize_edges(const unsigned long long* keys, const int* slots, int n, const long long* chi_num,
                                  const int* b0, const ShapeDesc* shapes, int nshapes, int* out_keys, int* out_chi,
-                                 int* out_b0, int* status, unsigned long long* count, hipStream_t s);
-hipError_t launch_finalize_cells(int ns, const long long* chi_num, const long long* geo, const int* np,
-                                 const ShapeDesc* shapes, int nshapes, int* out_chi, double* out_vol, double* out_cen,
-                                 int* status, hipStream_t s);
-hipError_t launch_fill_rpv(int4* p, int n, hipStream_t s);
+                                 int* out_b0, int* status, hipStream_t s);
+hipError_t launch_finalize_cells(int ns, const long long* chi_num, const long long* geo, const int* np, const int* b0,
+                                 const ShapeDesc* shapes, int nshapes, int* out_chi, int* out_b0, double* out_vol,
+                                 double* out_cen, int* status, hipStream_t s);
 hipError_t launch_sort_rpv(const int4* rpv, int n, unsigned long long* ka, unsigned long long* kb,
                            unsigned long long* kc, int* va, int* vb, void* tmp, size_t tmp_bytes, int4* out,
                            hipStream_t s);

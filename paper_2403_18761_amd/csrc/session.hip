@@ -64,11 +64,11 @@ __device__ inline int uf_root(const int* par, int x) {
   }
 }
 
-__global__ void k_ref_tet(HashTab N, const int* node_cnt, RoundState r) {
+__global__ void k_ref_tet(HashTab N, const int* node_st, RoundState r) {
   const unsigned cap = N.mask + 1;
   for (unsigned s = blockIdx.x * blockDim.x + threadIdx.x; s < cap; s += gridDim.x * blockDim.x) {
     unsigned long long key = N.keys[s];
-    if (key == EMPTY_KEY || node_cnt[s] <= 0 || (key >> 62) != 1) continue;
+    if (key == EMPTY_KEY || !node_live(node_st[s]) || (key >> 62) != 1) continue;
     int cell = (int)((key >> 32) & 0x3fffffff);
     int k = r.selpos[cell];
     if (k >= 0) atomicMin(&r.ref[k], (int)(key & 0xffffffffull));
@@ -82,12 +82,12 @@ __device__ inline unsigned mix_hash(unsigned long long x) {  // splitmix64 final
   return (unsigned)((x ^ (x >> 31)) >> 32);
 }
 
-__global__ void k_pick_tet(HashTab N, const int* node_cnt, const int* parent, const int* cell_b0, RoundState r) {
+__global__ void k_pick_tet(HashTab N, const int* node_st, const int* parent, const int* cell_b0, RoundState r) {
   const unsigned cap = N.mask + 1;
   const int round = *r.round;
   for (unsigned s = blockIdx.x * blockDim.x + threadIdx.x; s < cap; s += gridDim.x * blockDim.x) {
     unsigned long long key = N.keys[s];
-    if (key == EMPTY_KEY || node_cnt[s] <= 0 || (key >> 62) != 1) continue;
+    if (key == EMPTY_KEY || !node_live(node_st[s]) || (key >> 62) != 1) continue;
     int cell = (int)((key >> 32) & 0x3fffffff);
     int k = r.selpos[cell];
     if (k < 0) continue;
@@ -202,8 +202,8 @@ hipError_t launch_round_front(const RoundState& r, const ShapeArgs& a, const int
   hipLaunchKernelGGL(k_round_begin, dim3(1), dim3(64), 0, s, r);
   hipLaunchKernelGGL(k_select, dim3(1), dim3(256), 0, s, r, a.cell_chi, a.cell_np, cell_b0);
   const size_t cap = (size_t)a.N.mask + 1;
-  hipLaunchKernelGGL(k_ref_tet, dim3(gsz(cap)), dim3(256), 0, s, a.N, a.node_cnt, r);
-  hipLaunchKernelGGL(k_pick_tet, dim3(gsz(cap)), dim3(256), 0, s, a.N, a.node_cnt, parent, cell_b0, r);
+  hipLaunchKernelGGL(k_ref_tet, dim3(gsz(cap)), dim3(256), 0, s, a.N, a.node_st, r);
+  hipLaunchKernelGGL(k_pick_tet, dim3(gsz(cap)), dim3(256), 0, s, a.N, a.node_st, parent, cell_b0, r);
   hipLaunchKernelGGL(k_insert, dim3(1), dim3(64), 0, s, r, (float4*)a.site);
   hipLaunchKernelGGL(k_mark_dirty, dim3(gsz(nt)), dim3(256), 0, s, r, tp, nt, a.site, a.tet_U);
   hipLaunchKernelGGL(k_dirty_items, dim3(1), dim3(256), 0, s, r, nblk);

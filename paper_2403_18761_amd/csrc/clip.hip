@@ -643,7 +643,8 @@ __global__ __launch_bounds__(NT) void k_clip_fast(ShapeArgs a) {
 struct SlowScratch {  // per wave: the candidate list, then every lane's polytope and plane table, lane-interleaved
   static constexpr size_t cand_bytes = SLOW_KMAX * sizeof(int);
   static constexpr size_t key_bytes = SLOW_KMAX * sizeof(double);
-  static constexpr size_t wave_bytes = 2 * (cand_bytes + key_bytes);  // unsorted and sorted lists
+  static constexpr size_t g_bytes = SLOW_KMAX * 4 * sizeof(double);   // g_j at the four tet vertices
+  static constexpr size_t wave_bytes = 2 * (cand_bytes + key_bytes) + g_bytes;  // unsorted and sorted lists
   static constexpr size_t xyz_bytes = 64 * SLOW_VMAX * sizeof(Coord4<double>::type);  // [slot][lane]
   static constexpr size_t topo_bytes = 64 * SLOW_VMAX * sizeof(unsigned long long);    // [slot][lane]
   static constexpr size_t tab_bytes = 64 * (size_t)SLOW_PMAX;                          // [plane][lane]
@@ -661,6 +662,7 @@ __global__ __launch_bounds__(64) void k_clip_slow(ShapeArgs a, unsigned char* sc
   double* key = (double*)(wbase + SlowScratch::cand_bytes);
   int* scand = (int*)(wbase + SlowScratch::cand_bytes + SlowScratch::key_bytes);
   double* skey = (double*)(wbase + 2 * SlowScratch::cand_bytes + SlowScratch::key_bytes);
+  double* gv = (double*)(wbase + 2 * (SlowScratch::cand_bytes + SlowScratch::key_bytes));
   Coord4<double>::type* xyz = (Coord4<double>::type*)(wbase + SlowScratch::wave_bytes) + lane;
   unsigned long long* topo =
       (unsigned long long*)(wbase + SlowScratch::wave_bytes + SlowScratch::xyz_bytes) + lane;
@@ -722,6 +724,41 @@ __global__ __launch_bounds__(64) void k_clip_slow(ShapeArgs a, unsigned char* sc
       if (lane == 0) atomicOr(a.status, ST_SLOW_CAPACITY);
       continue;
     }
+    __syncthreads();
+    // drop every candidate that another one beats at all four tet vertices (g is affine, so then everywhere on the
+    // tet: it owns nothing and its bisector constrains no piece); the values are exact in FP64
+    for (int x = lane; x < m; x += 64) {
+      const float4 s = a.site[cand[x]];
+      const double ax_ = (double)s.x - o.x, ay_ = (double)s.y - o.y, az_ = (double)s.z - o.z;
+      const double D = ax_ * ax_ + ay_ * ay_ + az_ * az_ - (double)s.w * s.w;
+      gv[4 * x] = D;
+      for (int v = 0; v < 3; ++v) gv[4 * x + 1 + v] = D - 2.0 * (y[v][0] * ax_ + y[v][1] * ay_ + y[v][2] * az_);
+    }
+    __syncthreads();
+    int kept = 0;
+    for (int base = 0; base < m; base += 64) {
+      const int x = base + lane;
+      bool keep = false;
+      double kx = 0.0;
+      int cx = 0;
+      if (x < m) {
+        const double g0 = gv[4 * x], g1 = gv[4 * x + 1], g2 = gv[4 * x + 2], g3 = gv[4 * x + 3];
+        keep = true;
+        for (int q = 0; q < m && keep; ++q)
+          keep = !(gv[4 * q] < g0 && gv[4 * q + 1] < g1 && gv[4 * q + 2] < g2 && gv[4 * q + 3] < g3);
+        kx = key[x];
+        cx = cand[x];
+      }
+      const unsigned long long mask = __ballot(keep);
+      __syncthreads();  // every lane has read cand/key of this chunk before they are overwritten in place
+      if (keep) {
+        const int pos = kept + __popcll(mask & ((1ull << lane) - 1ull));
+        cand[pos] = cx;
+        key[pos] = kx;
+      }
+      kept += __popcll(mask);
+    }
+    m = kept;
     __syncthreads();
     // rank sort by (key, position): positions ascend with the site id, so ties keep the site order
     for (int x = lane; x < m; x += 64) {

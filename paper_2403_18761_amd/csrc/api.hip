@@ -247,6 +247,7 @@ struct DeviceState {
       hip_check(launch_fill_i32(edge_b0.as<int>(), 0, capE, s), "fill");
     }
     hip_check(launch_fill_u64(cnt() + C_NODES, 0, 1, s), "fill");
+    hip_check(launch_fill_u64(cnt() + C_GLUE_BITS, 0, 2, s), "fill");
     hip_check(launch_glue(a, parent.as<int>(), s), "glue");
     hip_check(launch_count_roots(a, parent.as<int>(), cell_b0.as<int>(), face_b0.as<int>(), edge_b0.as<int>(), s),
               "roots");

@@ -88,14 +88,19 @@ __global__ void k_clear_touched_b0(const unsigned char* touch, int* b0, size_t n
 
 // For every element piece with gluing bits: find the same element's piece in the face-adjacent tet, check that it
 // glues back across the same mesh face (both sides must agree), and unite them.
+// Every gluing bit is matched from the tet with the smaller id only (one lookup and one union per glued pair); the
+// symmetry of the records is checked by counting: the bits set must be twice the pairs matched.
 __global__ void k_glue(ShapeArgs a, int* parent) {
   const unsigned cap = a.N.mask + 1;
+  unsigned long long bits = 0, pairs = 0;
   for (unsigned s = blockIdx.x * blockDim.x + threadIdx.x; s < cap; s += gridDim.x * blockDim.x) {
     unsigned long long key = a.N.keys[s];
+    if (key == EMPTY_KEY) continue;
     const int st = a.node_st[s];
-    if (key == EMPTY_KEY || !node_live(st)) continue;
+    if (!node_live(st)) continue;
     int g = node_glue_bits(st);
     if (!g || !node_touched(a, key)) continue;
+    bits += __popc(g);
     const long long gt = (long long)(key & 0xffffffffull);
     const ShapeDesc& sd = a.shapes[shape_of_tet(a.shapes, a.nshapes, gt)];
     const int t = (int)(gt - sd.tet_off);
@@ -103,7 +108,7 @@ __global__ void k_glue(ShapeArgs a, int* parent) {
     for (int f = 0; f < 4; ++f) {
       if (!(g & (1 << f))) continue;
       int t2 = sd.tn[4 * (size_t)t + f];
-      if (t2 < 0) continue;
+      if (t2 < t) continue;  // the boundary never carries a bit; the other side matches smaller ids
       int f2 = -1;
       for (int q = 0; q < 4; ++q)
         if (sd.tn[4 * (size_t)t2 + q] == t) f2 = q;
@@ -113,21 +118,32 @@ __global__ void k_glue(ShapeArgs a, int* parent) {
         atomicOr(a.status, ST_INTERNAL);
         continue;
       }
+      ++pairs;
       uf_union(parent, (int)s, s2);
     }
   }
+  __shared__ unsigned long long s_sum[2];
+  if (threadIdx.x < 2) s_sum[threadIdx.x] = 0;
+  __syncthreads();
+  if (bits) atomicAdd(&s_sum[0], bits);
+  if (pairs) atomicAdd(&s_sum[1], pairs);
+  __syncthreads();
+  if (threadIdx.x == 0 && s_sum[0]) atomicAdd(&a.counters[C_GLUE_BITS], s_sum[0]);
+  if (threadIdx.x == 0 && s_sum[1]) atomicAdd(&a.counters[C_GLUE_PAIRS], s_sum[1]);
 }
 
 __global__ void k_count_roots(ShapeArgs a, int* parent, int* cell_b0, int* face_b0, int* edge_b0) {
   const unsigned cap = a.N.mask + 1;
   unsigned long long nodes = 0;
+  if (blockIdx.x == 0 && threadIdx.x == 0 && a.counters[C_GLUE_BITS] != 2 * a.counters[C_GLUE_PAIRS])
+    atomicOr(a.status, ST_INTERNAL);  // a gluing bit without its counterpart
   for (unsigned s = blockIdx.x * blockDim.x + threadIdx.x; s < cap; s += gridDim.x * blockDim.x) {
     unsigned long long key = a.N.keys[s];
     const int st = key == EMPTY_KEY ? 0 : a.node_st[s];
     if (st < 0 || st >= 32) atomicOr(a.status, ST_INTERNAL);  // every piece is present at most once
     if (!node_live(st)) continue;
     ++nodes;
-    if (!node_touched(a, key) || uf_find(parent, (int)s) != (int)s) continue;
+    if (!node_touched(a, key) || parent[s] != (int)s) continue;  // one root per component
     int kind = (int)(key >> 62);
     int elem = (int)((key >> 32) & 0x3fffffffull);
     if (kind == 1) atomicAdd(&cell_b0[elem], 1);

@@ -31,6 +31,8 @@ enum {
   C_DEFER_KMAX,   // tets deferred because they kept more than the candidate budget
   C_DEFER_CLIP,   // pieces deferred because the polytope outgrew the vertex slots
   C_SPLIT,        // workgroup blocks redone in chunks because their site list overflowed
+  C_GLUE_BITS,    // gluing bits of the pieces whose components are (re)computed
+  C_GLUE_PAIRS,   // glued pairs matched
   NCOUNTERS
 };
 // C_RPV counts RPV emissions; the RPV list itself is the set of keys of ShapeArgs::Q with a positive count

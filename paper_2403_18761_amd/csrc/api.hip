@@ -129,6 +129,16 @@ struct DeviceState {
 
   unsigned long long* cnt() const { return counters.as<unsigned long long>(); }
   unsigned long long* fin_count() const { return cnt() + NCOUNTERS; }  // [0] faces, [1] edges
+  unsigned long long* stat() const { return cnt() + NCOUNTERS + 8; }  // [NSPREAD][NCOUNTERS]
+  // totals of every counter: the cursor and the sum of its spread copies (synchronises the stream)
+  void totals(unsigned long long* out, hipStream_t s) const {
+    std::vector<unsigned long long> h(NCOUNTERS + 8 + (size_t)NSPREAD * NCOUNTERS);
+    hip_check(hipMemcpyAsync(h.data(), cnt(), 8 * h.size(), hipMemcpyDeviceToHost, s), "download");
+    hip_check(hipStreamSynchronize(s), "synchronize");
+    for (int c = 0; c < NCOUNTERS + 8; ++c) out[c] = h[c];
+    for (int k = 0; k < NSPREAD; ++k)
+      for (int c = 0; c < NCOUNTERS; ++c) out[c] += h[NCOUNTERS + 8 + (size_t)k * NCOUNTERS + c];
+  }
   size_t touch_words() const { return ((size_t)ns_cap + capF + capE + 3) / 4; }
 
   void alloc(int n_shapes, int ns, long long nt, int scale, bool keep_pieces, bool keep_U) {
@@ -162,7 +172,7 @@ struct DeviceState {
     parent.alloc(4 * (size_t)capN);
     deferred.alloc(16 * (size_t)def_cap);
     pieces.alloc(sizeof(PieceRec) * (size_t)std::max(piece_cap, 1));
-    counters.alloc(8 * (NCOUNTERS + 8));
+    counters.alloc(8 * (NCOUNTERS + 8 + (size_t)NSPREAD * NCOUNTERS));
     if (keep_U) {  // incremental updates: U_t per tet and the touched-element flags
       tetU.alloc(8 * (size_t)std::max<long long>(nt, 1));
       touch.alloc(touch_words() * 4);
@@ -187,7 +197,7 @@ struct DeviceState {
     hip_check(launch_fill_i32(rpv_cnt.as<int>(), 0, capQ, s), "fill");
     hip_check(launch_fill_u64(nkeys.as<unsigned long long>(), EMPTY_KEY, capN, s), "fill");
     hip_check(launch_fill_i32(node_st.as<int>(), 0, capN, s), "fill");
-    hip_check(launch_fill_u64(cnt(), 0, NCOUNTERS + 8, s), "fill");
+    hip_check(launch_fill_u64(cnt(), 0, NCOUNTERS + 8 + (size_t)NSPREAD * NCOUNTERS, s), "fill");
     if (touch.p) hip_check(launch_fill_i32(touch.as<int>(), 0, touch_words(), s), "fill");
   }
 
@@ -228,6 +238,7 @@ struct DeviceState {
     a.pieces = pieces.as<PieceRec>();
     a.piece_cap = piece_cap;
     a.counters = cnt();
+    a.stats = stat();
     a.status = status.as<int>();
     a.flags = flags;
     a.kmax = kmax;
@@ -246,8 +257,8 @@ struct DeviceState {
       hip_check(launch_fill_i32(face_b0.as<int>(), 0, capF, s), "fill");
       hip_check(launch_fill_i32(edge_b0.as<int>(), 0, capE, s), "fill");
     }
-    hip_check(launch_fill_u64(cnt() + C_NODES, 0, 1, s), "fill");
-    hip_check(launch_fill_u64(cnt() + C_GLUE_BITS, 0, 2, s), "fill");
+    hip_check(launch_zero_stats(stat(), C_NODES, 1, s), "fill");
+    hip_check(launch_zero_stats(stat(), C_GLUE_BITS, 2, s), "fill");
     hip_check(launch_glue(a, parent.as<int>(), s), "glue");
     hip_check(launch_count_roots(a, parent.as<int>(), cell_b0.as<int>(), face_b0.as<int>(), edge_b0.as<int>(), s),
               "roots");
@@ -318,11 +329,10 @@ static bool collect(DeviceState& D, const std::vector<ShapeDesc>& hd, const Shap
   HashTab Q{D.qkeys.as<unsigned long long>(), capQ - 1};
   hip_check(launch_rpv_compact(Q, D.rpv_cnt.as<int>(), D.ekeys.as<unsigned long long>(), rq.as<int4>(), fin + 2, s),
             "live rpvs");
-  unsigned long long hc[NCOUNTERS + 4];
+  unsigned long long hc[NCOUNTERS + 8];
   int hst = 0;
-  hip_check(hipMemcpyAsync(hc, D.cnt(), sizeof(hc), hipMemcpyDeviceToHost, s), "download");
   hip_check(hipMemcpyAsync(&hst, D.status.p, sizeof(int), hipMemcpyDeviceToHost, s), "download");
-  hip_check(hipStreamSynchronize(s), "synchronize");
+  D.totals(hc, s);
   if (hst & ST_TABLE_FULL) return false;
   if (hc[C_DEFER_ITEMS] > (unsigned long long)D.def_cap || (D.piece_cap && hc[C_PIECES] > (unsigned long long)D.piece_cap))
     return false;
@@ -1144,9 +1154,9 @@ rpd_status rpd_session_get_info(rpd_session* S, rpd_session_info* info) {
   info->n_blocks = S->mesh->nblk;
   info->n_inserted = h[rpd::SI_INS];
   info->n_dirty_blocks = h[rpd::SI_DIRTY];
-  unsigned long long cand = 0;
-  rpd::hip_check(hipMemcpy(&cand, S->D.cnt() + rpd::C_CAND, sizeof(cand), hipMemcpyDeviceToHost), "download");
-  info->n_clipped = (int64_t)cand;
+  unsigned long long tot[rpd::NCOUNTERS + 8];
+  S->D.totals(tot, S->stream);
+  info->n_clipped = (int64_t)tot[rpd::C_CAND];
   info->ms_last_run = S->ms_last;
   return RPD_OK;
   RPD_GUARD_END

@@ -97,7 +97,7 @@ __device__ void emit_piece(Clipper<T, Topo, Mask, VCAP, EXACT>& c, const ShapeDe
           int qs = ht_insert(a.Q, ((unsigned long long)es << 21) | (unsigned)hi, status);
           if (qs >= 0) atomicAdd(&a.rpv_cnt[qs], a.sign);
         }
-        atomicAdd(&a.counters[C_RPV], 1ull);
+        stat_add(a, C_RPV, 1ull);
       }
     }
   }
@@ -468,7 +468,7 @@ __global__ __launch_bounds__(NT) void k_clip_fast(ShapeArgs a) {
   if (nsl > SLMAX && !split && ntb > SUB && !(a.flags & RPD_FORCE_SLOW_PATH)) {
     split = true;
     sub_n = SUB;
-    if (tid == 0) atomicAdd(&a.counters[C_SPLIT], 1ull);
+    if (tid == 0) stat_add(a, C_SPLIT, 1ull);
     __syncthreads();
     continue;
   }
@@ -525,7 +525,7 @@ __global__ __launch_bounds__(NT) void k_clip_fast(ShapeArgs a) {
                                                                          s_key[tid], m, true);
     if (block_overflow || m > a.kmax) {
       s_m[tid] = -1;
-      atomicAdd(&a.counters[block_overflow ? C_DEFER_BLOCK : C_DEFER_KMAX], 1ull);
+      stat_add(a, block_overflow ? C_DEFER_BLOCK : C_DEFER_KMAX, 1ull);
       unsigned long long idx = atomicAdd(&a.counters[C_DEFER_ITEMS], 1ull);
       if (idx < (unsigned long long)a.deferred_cap) a.deferred[idx] = make_int4(wi.x, t0 + tid, -1, 0);
       else atomicOr(a.status, ST_TABLE_FULL);
@@ -597,7 +597,7 @@ __global__ __launch_bounds__(NT) void k_clip_fast(ShapeArgs a) {
       const CellSink sink{s_acc_chi, s_acc_np, s_acc_geo, AGG, (int)s_cand[lt][ci]};
       emit_piece(cl, sd, t0 + lt, a, sink);
     } else if (r == CLIP_DEFER) {
-      atomicAdd(&a.counters[C_DEFER_CLIP], 1ull);
+      stat_add(a, C_DEFER_CLIP, 1ull);
       unsigned long long idx = atomicAdd(&a.counters[C_DEFER_ITEMS], 1ull);
       if (idx < (unsigned long long)a.deferred_cap) a.deferred[idx] = make_int4(wi.x, t0 + lt, cl.env.site_i, 0);
       else atomicOr(a.status, ST_TABLE_FULL);
@@ -631,9 +631,9 @@ __global__ __launch_bounds__(NT) void k_clip_fast(ShapeArgs a) {
   __syncthreads();
   if (tid == 0 && n_cand) {
     // live pieces: a removal pass (sign -1) subtracts in two's complement
-    if (s_cnt[0]) atomicAdd(&a.counters[C_PAIRS], a.sign > 0 ? s_cnt[0] : 0ull - s_cnt[0]);
-    if (s_cnt[1]) atomicAdd(&a.counters[C_FP64], s_cnt[1]);
-    atomicAdd(&a.counters[C_CAND], n_cand);
+    if (s_cnt[0]) stat_add(a, C_PAIRS, a.sign > 0 ? s_cnt[0] : 0ull - s_cnt[0]);
+    if (s_cnt[1]) stat_add(a, C_FP64, s_cnt[1]);
+    stat_add(a, C_CAND, n_cand);
   }
 }
 
@@ -814,9 +814,9 @@ __global__ __launch_bounds__(64) void k_clip_slow(ShapeArgs a, unsigned char* sc
     nex += __shfl_xor(nex, off);
   }
   if (lane == 0) {
-    if (n_pairs) atomicAdd(&a.counters[C_PAIRS], a.sign > 0 ? n_pairs : 0ull - n_pairs);
-    if (n64) atomicAdd(&a.counters[C_FP64], n64);
-    if (nex) atomicAdd(&a.counters[C_EXACT], nex);
+    if (n_pairs) stat_add(a, C_PAIRS, a.sign > 0 ? n_pairs : 0ull - n_pairs);
+    if (n64) stat_add(a, C_FP64, n64);
+    if (nex) stat_add(a, C_EXACT, nex);
   }
 }
 

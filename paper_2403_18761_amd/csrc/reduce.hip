@@ -1,6 +1,7 @@
 // Reductions after clipping: connected components by union-find over glued element pieces (paper Sec. 4.1.1),
 // integer Euler characteristics from the fractional sums (Sec. 4.1.2), compaction and sorting of the element lists,
 // site validation and small fills.
+#include <algorithm>
 #include <cstring>
 
 #include <hip/hip_runtime.h>
@@ -29,6 +30,16 @@ hipError_t launch_fill_u64(unsigned long long* p, unsigned long long v, size_t n
   hipLaunchKernelGGL(k_fill_u64, dim3(grid_for(n, 256)), dim3(256), 0, s, p, v, n);
   return hipGetLastError();
 }
+__global__ void k_zero_stats(unsigned long long* stats, int c0, int n) {
+  const int k = threadIdx.x;  // one thread per spread copy
+  if (k < NSPREAD)
+    for (int c = 0; c < n; ++c) stats[(size_t)k * NCOUNTERS + c0 + c] = 0;
+}
+hipError_t launch_zero_stats(unsigned long long* stats, int c0, int n, hipStream_t s) {
+  hipLaunchKernelGGL(k_zero_stats, dim3(1), dim3(NSPREAD), 0, s, stats, c0, n);
+  return hipGetLastError();
+}
+
 hipError_t launch_fill_i32(int* p, int v, size_t n, hipStream_t s) {
   if (!n) return hipSuccess;
   hipLaunchKernelGGL(k_fill_i32, dim3(grid_for(n, 256)), dim3(256), 0, s, p, v, n);
@@ -128,14 +139,14 @@ __global__ void k_glue(ShapeArgs a, int* parent) {
   if (bits) atomicAdd(&s_sum[0], bits);
   if (pairs) atomicAdd(&s_sum[1], pairs);
   __syncthreads();
-  if (threadIdx.x == 0 && s_sum[0]) atomicAdd(&a.counters[C_GLUE_BITS], s_sum[0]);
-  if (threadIdx.x == 0 && s_sum[1]) atomicAdd(&a.counters[C_GLUE_PAIRS], s_sum[1]);
+  if (threadIdx.x == 0 && s_sum[0]) stat_add(a, C_GLUE_BITS, s_sum[0]);
+  if (threadIdx.x == 0 && s_sum[1]) stat_add(a, C_GLUE_PAIRS, s_sum[1]);
 }
 
 __global__ void k_count_roots(ShapeArgs a, int* parent, int* cell_b0, int* face_b0, int* edge_b0) {
   const unsigned cap = a.N.mask + 1;
   unsigned long long nodes = 0;
-  if (blockIdx.x == 0 && threadIdx.x == 0 && a.counters[C_GLUE_BITS] != 2 * a.counters[C_GLUE_PAIRS])
+  if (blockIdx.x == 0 && threadIdx.x == 0 && stat_sum(a, C_GLUE_BITS) != 2 * stat_sum(a, C_GLUE_PAIRS))
     atomicOr(a.status, ST_INTERNAL);  // a gluing bit without its counterpart
   for (unsigned s = blockIdx.x * blockDim.x + threadIdx.x; s < cap; s += gridDim.x * blockDim.x) {
     unsigned long long key = a.N.keys[s];
@@ -155,7 +166,7 @@ __global__ void k_count_roots(ShapeArgs a, int* parent, int* cell_b0, int* face_
   __syncthreads();
   if (nodes) atomicAdd(&s_nodes, nodes);
   __syncthreads();
-  if (threadIdx.x == 0 && s_nodes) atomicAdd(&a.counters[C_NODES], s_nodes);
+  if (threadIdx.x == 0 && s_nodes) stat_add(a, C_NODES, s_nodes);
 }
 
 hipError_t launch_clear_touched_b0(const unsigned char* touch, int* b0, size_t n, hipStream_t s) {
@@ -164,17 +175,20 @@ hipError_t launch_clear_touched_b0(const unsigned char* touch, int* b0, size_t n
   return hipGetLastError();
 }
 
+// scans that end in a per-workgroup reduction run on a grid of at most 4096 workgroups (16 per compute unit)
+static int scan_grid(size_t n) { return std::min(grid_for(n, 256), 4096); }
+
 hipError_t launch_glue(const ShapeArgs& a, int* parent, hipStream_t s) {
   size_t cap = (size_t)a.N.mask + 1;
   hipLaunchKernelGGL(k_parent_init, dim3(grid_for(cap, 256)), dim3(256), 0, s, a, parent);
-  hipLaunchKernelGGL(k_glue, dim3(grid_for(cap, 256)), dim3(256), 0, s, a, parent);
+  hipLaunchKernelGGL(k_glue, dim3(scan_grid(cap)), dim3(256), 0, s, a, parent);
   return hipGetLastError();
 }
 
 hipError_t launch_count_roots(const ShapeArgs& a, int* parent, int* cell_b0, int* face_b0, int* edge_b0,
                               hipStream_t s) {
   size_t cap = (size_t)a.N.mask + 1;
-  hipLaunchKernelGGL(k_count_roots, dim3(grid_for(cap, 256)), dim3(256), 0, s, a, parent, cell_b0, face_b0, edge_b0);
+  hipLaunchKernelGGL(k_count_roots, dim3(scan_grid(cap)), dim3(256), 0, s, a, parent, cell_b0, face_b0, edge_b0);
   return hipGetLastError();
 }
 

@@ -37,6 +37,11 @@ enum {
 };
 // C_RPV counts RPV emissions; the RPV list itself is the set of keys of ShapeArgs::Q with a positive count
 
+// Statistics counters are spread over NSPREAD copies (picked by workgroup id) so that thousands of workgroups do
+// not serialise on one address; the host sums the copies. Counters used as cursors (C_DEFER_ITEMS, C_PIECES) are
+// not spread.
+constexpr int NSPREAD = 64;
+
 constexpr unsigned long long EMPTY_KEY = ~0ull;
 
 // element-piece state word
@@ -105,7 +110,8 @@ struct ShapeArgs {
   int deferred_cap;
   PieceRec* pieces;      // kept with RPD_KEEP_PIECES (t = global tet id)
   int piece_cap;
-  unsigned long long* counters;  // [NCOUNTERS]
+  unsigned long long* counters;  // [NCOUNTERS] (cursors and host-read totals)
+  unsigned long long* stats;     // [NSPREAD][NCOUNTERS] spread statistics
   int* status;
   unsigned flags;        // RPD_FORCE_* / RPD_KEEP_PIECES as in rpd.h
   int kmax;              // fast-path candidate budget (<= KMAX)
@@ -155,5 +161,14 @@ struct RoundState {
   int max_sites;
   int max_insert;
 };
+
+__device__ inline void stat_add(const ShapeArgs& a, int c, unsigned long long v) {
+  atomicAdd(&a.stats[(blockIdx.x & (NSPREAD - 1)) * NCOUNTERS + c], v);
+}
+__device__ inline unsigned long long stat_sum(const ShapeArgs& a, int c) {
+  unsigned long long v = 0;
+  for (int k = 0; k < NSPREAD; ++k) v += a.stats[k * NCOUNTERS + c];
+  return v;
+}
 
 }  // namespace rpd

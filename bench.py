@@ -83,20 +83,21 @@ def workload(name):
     raise SystemExit(f"unknown workload {name}")
 
 
-def time_builds(meshes, sites, precision, steps, warmup, stream):
+def time_builds(meshes, sites, precision, steps, warmup, stream, block=0, clip_budget=0):
     import torch
 
     from paper_2403_18761_amd import rpd
 
     flags = rpd.RPD_TIMING
+    kw = dict(precision=precision, flags=flags, stream=stream, block=block, clip_budget=clip_budget)
     for _ in range(warmup):
-        rpd.build(meshes, sites, precision=precision, flags=flags, stream=stream)
+        rpd.build(meshes, sites, **kw)
     torch.cuda.synchronize()
     clip_ms = []
     n_pairs = None
     t0 = time.perf_counter()
     for _ in range(steps):
-        res = rpd.build(meshes, sites, precision=precision, flags=flags, stream=stream)
+        res = rpd.build(meshes, sites, **kw)
         st = res.stats()
         clip_ms.append(st["ms_clip"])
         n_pairs = st["n_pairs"]
@@ -187,6 +188,8 @@ def main():
     ap.add_argument("--no-fp64", action="store_true", help="skip the all-FP64 comparison")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-autotune", action="store_true", help="use the default launch shape (128 threads, k=28)")
+    ap.add_argument("--launch", default=None, metavar="BLOCK,K",
+                    help="use this launch shape (threads per workgroup, clip budget) instead of autotuning")
     ap.add_argument("--cpu-frac", type=float, default=None)
     ap.add_argument("--workload", default="torus2000", choices=sorted(WORKLOADS))
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
@@ -245,10 +248,17 @@ def main():
     sites = [(t(p.sx), t(p.sy), t(p.sz), t(p.sr)) for p in probs]
     torch.cuda.synchronize()
     # the autotuner picks the launch shape for this bucket of shapes (untimed); rpd_build then uses it
-    tuned = rpd.autotune(meshes, sites, stream=stream) if not args.no_autotune else {"block": 128, "clip_budget": 28}
+    if args.launch:
+        b, k = (int(x) for x in args.launch.split(","))
+        tuned = {"block": b, "clip_budget": k}
+    elif args.no_autotune:
+        tuned = {"block": 128, "clip_budget": 28}
+    else:
+        tuned = rpd.autotune(meshes, sites, stream=stream)
     print(f"# autotuned launch shape: {tuned}", file=sys.stderr, flush=True)
 
-    ms32, clip32, pairs, st32 = time_builds(meshes, sites, rpd.RPD_FP32_FALLBACK, args.steps, args.warmup, stream)
+    ms32, clip32, pairs, st32 = time_builds(meshes, sites, rpd.RPD_FP32_FALLBACK, args.steps, args.warmup, stream,
+                                            tuned["block"], tuned["clip_budget"])
     print(f"# fp32+fallback: {ms32:.3f} ms/RPD, clip kernel {clip32:.3f} ms, pairs {pairs}", file=sys.stderr,
           flush=True)
     out64 = None

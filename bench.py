@@ -106,6 +106,27 @@ def time_builds(meshes, sites, precision, steps, warmup, stream, block=0, clip_b
     return (t1 - t0) * 1e3 / steps, float(np.mean(clip_ms)), n_pairs, st
 
 
+def invariants(meshes, sites, tuned):
+    """One more (untimed) build in the timed launch shape, checked for properties that hold at any size: cell volumes
+    partition each mesh, Euler additivity over the diagram equals the mesh's chi, every live element has beta0 >= 1."""
+    from paper_2403_18761_amd import rpd
+
+    res = rpd.build(meshes, sites, block=tuned["block"], clip_budget=tuned["clip_budget"])
+    worst_vol, bad = 0.0, 0
+    for k, m in enumerate(meshes):
+        info = m.info()
+        _, chi = res.euler(k, rpd.RPD_CELL)
+        _, b0 = res.components(k, rpd.RPD_CELL)
+        _, fchi = res.euler(k, rpd.RPD_FACE)
+        _, echi = res.euler(k, rpd.RPD_EDGE)
+        nrpv = len(res.adjacency(k, rpd.RPD_VERTEX))
+        vol, _ = res.geometry(k)
+        worst_vol = max(worst_vol, abs(vol.sum() - info["volume"]) / info["volume"])
+        additive = int(chi.sum()) - int(fchi.sum()) + int(echi.sum()) - nrpv == info["euler"]
+        bad += int(not additive) + int(np.any(b0[vol > 0] < 1))
+    return {"volume_partition_rel_err_max": worst_vol, "shapes_failing_euler_or_beta0": bad, "shapes": len(meshes)}
+
+
 def run_repair(args, prob, table):
     """One step = one round of the incremental session; value = (tet, site) pairs clipped per second in the timed
     rounds (removal and re-insertion passes of the dirty blocks). A from-scratch rebuild with the final sites is
@@ -296,6 +317,7 @@ def main():
                      "frac": achieved / PEAK_FP32_TFLOPS, "traffic": traffic,
                      "kernel": kernel, "flop_per_piece": FLOP_PER_PIECE},
     }
+    line["checks"] = invariants(meshes, sites, tuned)
     if not args.no_cpu_baseline:
         frac = args.cpu_frac if args.cpu_frac is not None else WORKLOADS[args.workload]["cpu_frac"]
         line["cpu_baseline"] = cpu_baseline(probs, frac)

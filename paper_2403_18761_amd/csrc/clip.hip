@@ -358,6 +358,7 @@ __global__ __launch_bounds__(NT) void k_clip_fast(ShapeArgs a) {
   typename Coord4<T>::type* s_xyz = reinterpret_cast<typename Coord4<T>::type*>(s_share);
   __shared__ int s_m[TB];
   __shared__ int s_off[TB + 1];
+  __shared__ int s_order[TB];
   __shared__ float s_box[6];
   __shared__ double s_red[NT / 64];
   __shared__ int s_nsl;
@@ -547,10 +548,23 @@ __global__ __launch_bounds__(NT) void k_clip_fast(ShapeArgs a) {
     }
   }
   __syncthreads();
+  // pieces are laid out tet by tet with the tets ordered by candidate count, largest first: every piece of a tet
+  // loops over the same planes, so a wavefront's lanes then have similar trip counts
+  if (tid < TB) {
+    const int mt = tid < ntb ? max(s_m[tid], 0) : 0;
+    int rank = 0;
+    for (int u = 0; u < TB; ++u) {
+      const int mu = u < ntb ? max(s_m[u], 0) : 0;
+      rank += (mu > mt || (mu == mt && u < tid)) ? 1 : 0;
+    }
+    s_order[rank] = tid;
+  }
+  __syncthreads();
   if (tid == 0) {
     int acc = 0;
-    for (int lt = 0; lt < TB; ++lt) {
-      s_off[lt] = acc;
+    for (int j = 0; j < TB; ++j) {
+      s_off[j] = acc;
+      const int lt = s_order[j];
       if (lt < ntb && s_m[lt] > 0) acc += s_m[lt];
     }
     s_off[TB] = acc;
@@ -561,14 +575,14 @@ __global__ __launch_bounds__(NT) void k_clip_fast(ShapeArgs a) {
   const int npairs = s_off[TB];
   n_cand += npairs;
   for (int p = tid; p < npairs; p += NT) {
-    int lo_ = 0, hi_ = TB - 1;  // last lt with s_off[lt] <= p
+    int lo_ = 0, hi_ = TB - 1;  // last position j with s_off[j] <= p
     while (lo_ < hi_) {
       int mid = (lo_ + hi_ + 1) >> 1;
       if (s_off[mid] <= p) lo_ = mid;
       else hi_ = mid - 1;
     }
-    const int lt = lo_;
-    const int ci = p - s_off[lt];
+    const int lt = s_order[lo_];
+    const int ci = p - s_off[lo_];
     const int m = s_m[lt];
     Clipper<T, Topo32, unsigned, VMAX, false> cl;
     cl.st.c = s_xyz + tid;

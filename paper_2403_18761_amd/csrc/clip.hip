@@ -681,7 +681,6 @@ __global__ __launch_bounds__(64) void k_clip_slow(ShapeArgs a, unsigned char* sc
   unsigned long long* topo =
       (unsigned long long*)(wbase + SlowScratch::wave_bytes + SlowScratch::xyz_bytes) + lane;
   unsigned char* tab = wbase + SlowScratch::wave_bytes + SlowScratch::xyz_bytes + SlowScratch::topo_bytes + lane;
-  for (int k = 0; k < SLOW_PMAX; ++k) tab[64 * k] = 0;
   unsigned long long n_pairs = 0, n64 = 0, nex = 0;
   for (int it = blockIdx.x; it < n_items; it += gridDim.x) {
     const int4 di = a.deferred[it];
@@ -785,6 +784,7 @@ __global__ __launch_bounds__(64) void k_clip_slow(ShapeArgs a, unsigned char* sc
       scand[rank] = cand[x];
       skey[rank] = kx;
     }
+    for (int k = 0; k < 4 + m; ++k) tab[64 * k] = 0;  // the plane ids of this item start unpaired
     __syncthreads();
     for (int ci = lane; ci < m; ci += 64) {
       if (want >= 0 && scand[ci] != want) continue;

@@ -9,6 +9,8 @@
 // deferred to the large-capacity kernel, which recomputes them with FP64 constructions and exact predicates.
 #include <hip/hip_runtime.h>
 
+#include <climits>
+
 #include <algorithm>
 
 #include "rpd_device.h"
@@ -654,7 +656,7 @@ __global__ __launch_bounds__(NT) void k_clip_fast(ShapeArgs a) {
 // ---------------------------------------------------------------------------------------------------------------
 // large-capacity kernel: one wavefront per deferred item, FP64 constructions, exact predicates, global scratch
 // ---------------------------------------------------------------------------------------------------------------
-struct SlowScratch {  // per wave: the candidate list, then every lane's polytope and plane table, lane-interleaved
+struct SlowScratch {  // per wave, in global memory: the candidate lists, their vertex values, the global-memory polytopes
   static constexpr size_t cand_bytes = SLOW_KMAX * sizeof(int);
   static constexpr size_t key_bytes = SLOW_KMAX * sizeof(double);
   static constexpr size_t g_bytes = SLOW_KMAX * 4 * sizeof(double);   // g_j at the four tet vertices
@@ -664,12 +666,22 @@ struct SlowScratch {  // per wave: the candidate list, then every lane's polytop
   static constexpr size_t tab_bytes = 64 * (size_t)SLOW_PMAX;                          // [plane][lane]
   static constexpr size_t bytes = wave_bytes + xyz_bytes + topo_bytes + tab_bytes;
 };
+constexpr int SLOW_LDS_LANES = 16;   // the LDS variant clips with 16 lanes, each polytope in LDS
+constexpr int SLOW_LDS_ITEMS = 512;  // the first deferred items go to the LDS variant (one item per wave)
 
 // One wavefront per deferred item: the lanes split the scan over all of the shape's sites (candidates are
-// compacted in ascending site order by ballots), lane 0 sorts them, then every lane clips its own pieces. The
-// lanes' polytopes are interleaved slot by slot, so lanes that touch the same slot read one contiguous line.
-__global__ __launch_bounds__(64) void k_clip_slow(ShapeArgs a, unsigned char* scratch) {
-  const int n_items = (int)min(a.counters[C_DEFER_ITEMS], (unsigned long long)a.deferred_cap);
+// compacted in ascending site order by ballots), drop dominated candidates and rank-sort the rest, then clip the
+// pieces with FP64 polytopes of up to 64 vertices. The LDS variant (few items: latency) keeps 16 lanes' polytopes in
+// LDS; the global variant (many items: throughput) keeps all 64 lanes' polytopes in its scratch. Both interleave the
+// lanes slot by slot.
+template <bool LDS>
+__global__ __launch_bounds__(64) void k_clip_slow(ShapeArgs a, unsigned char* scratch, int item_begin, int item_end) {
+  constexpr int CL = LDS ? SLOW_LDS_LANES : 64;  // clipping lanes
+  __shared__ Coord4<double>::type s_xyz[LDS ? SLOW_VMAX * CL : 1];
+  __shared__ unsigned long long s_topo[LDS ? SLOW_VMAX * CL : 1];
+  __shared__ unsigned char s_tab[LDS ? SLOW_PMAX * CL : 1];
+  const int n_items = (int)min(min(a.counters[C_DEFER_ITEMS], (unsigned long long)a.deferred_cap),
+                               (unsigned long long)item_end);
   const int lane = threadIdx.x;
   unsigned char* wbase = scratch + (size_t)blockIdx.x * SlowScratch::bytes;
   int* cand = (int*)wbase;
@@ -677,12 +689,16 @@ __global__ __launch_bounds__(64) void k_clip_slow(ShapeArgs a, unsigned char* sc
   int* scand = (int*)(wbase + SlowScratch::cand_bytes + SlowScratch::key_bytes);
   double* skey = (double*)(wbase + 2 * SlowScratch::cand_bytes + SlowScratch::key_bytes);
   double* gv = (double*)(wbase + 2 * (SlowScratch::cand_bytes + SlowScratch::key_bytes));
-  Coord4<double>::type* xyz = (Coord4<double>::type*)(wbase + SlowScratch::wave_bytes) + lane;
+  const int cl_lane = lane < CL ? lane : 0;
+  Coord4<double>::type* xyz =
+      LDS ? s_xyz + cl_lane : (Coord4<double>::type*)(wbase + SlowScratch::wave_bytes) + cl_lane;
   unsigned long long* topo =
-      (unsigned long long*)(wbase + SlowScratch::wave_bytes + SlowScratch::xyz_bytes) + lane;
-  unsigned char* tab = wbase + SlowScratch::wave_bytes + SlowScratch::xyz_bytes + SlowScratch::topo_bytes + lane;
+      LDS ? s_topo + cl_lane
+          : (unsigned long long*)(wbase + SlowScratch::wave_bytes + SlowScratch::xyz_bytes) + cl_lane;
+  unsigned char* tab =
+      LDS ? s_tab + cl_lane : wbase + SlowScratch::wave_bytes + SlowScratch::xyz_bytes + SlowScratch::topo_bytes + cl_lane;
   unsigned long long n_pairs = 0, n64 = 0, nex = 0;
-  for (int it = blockIdx.x; it < n_items; it += gridDim.x) {
+  for (int it = item_begin + blockIdx.x; it < n_items; it += gridDim.x) {
     const int4 di = a.deferred[it];
     const ShapeDesc sd = a.shapes[__builtin_amdgcn_readfirstlane(di.x)];
     const int t = di.y;
@@ -784,16 +800,17 @@ __global__ __launch_bounds__(64) void k_clip_slow(ShapeArgs a, unsigned char* sc
       scand[rank] = cand[x];
       skey[rank] = kx;
     }
-    for (int k = 0; k < 4 + m; ++k) tab[64 * k] = 0;  // the plane ids of this item start unpaired
+    if (lane < CL)
+      for (int k = 0; k < 4 + m; ++k) tab[CL * k] = 0;  // the plane ids of this item start unpaired
     __syncthreads();
-    for (int ci = lane; ci < m; ci += 64) {
+    for (int ci = lane; ci < m && lane < CL; ci += CL) {
       if (want >= 0 && scand[ci] != want) continue;
       Clipper<double, Topo64, unsigned long long, SLOW_VMAX, true> cl;
       cl.st.c = xyz;
       cl.st.w = topo;
-      cl.st.stride = 64;
+      cl.st.stride = CL;
       cl.tab = tab;
-      cl.tst = 64;
+      cl.tst = CL;
       cl.a = &a;
       cl.flags = a.flags & ~RPD_FORCE_FP64;
       cl.np = 4 + m;
@@ -853,8 +870,12 @@ hipError_t launch_clip_fast(const ShapeArgs& a, int precision, int block, hipStr
 
 size_t slow_scratch_bytes(int waves) { return (size_t)waves * SlowScratch::bytes; }
 
+// the first SLOW_LDS_ITEMS items by the LDS variant, the rest by the global one (whose waves exit at once when there
+// is no rest); the item count is read on the device
 hipError_t launch_clip_slow(const ShapeArgs& a, unsigned char* scratch, int waves, hipStream_t s) {
-  hipLaunchKernelGGL(k_clip_slow, dim3(waves), dim3(64), 0, s, a, scratch);
+  const int lds_waves = waves < SLOW_LDS_ITEMS ? waves : SLOW_LDS_ITEMS;
+  hipLaunchKernelGGL(k_clip_slow<true>, dim3(lds_waves), dim3(64), 0, s, a, scratch, 0, SLOW_LDS_ITEMS);
+  hipLaunchKernelGGL(k_clip_slow<false>, dim3(waves), dim3(64), 0, s, a, scratch, SLOW_LDS_ITEMS, INT_MAX);
   return hipGetLastError();
 }
 

@@ -356,29 +356,51 @@ static bool collect(DeviceState& D, const std::vector<ShapeDesc>& hd, const Shap
   double* c_vol = (double*)(ob + off_dbl);
   double* c_cen = c_vol + ns;
 
-  const size_t maxn = std::max(std::max(nf, ne), std::max(nq, (size_t)1));
-  size_t tmpb = sort_tmp_bytes((int)maxn);
-  DBuf tmp(tmpb), kA(8 * maxn), kB(8 * maxn), kC(8 * maxn), vA(4 * maxn), vB(4 * maxn);
-  hip_check(sort_pairs_u64(tmp.p, tmpb, fk.as<unsigned long long>(), kB.as<unsigned long long>(), fsl.as<int>(),
-                           vB.as<int>(), (int)nf, s),
-            "sort faces");
-  hip_check(launch_finalize_faces(kB.as<unsigned long long>(), vB.as<int>(), (int)nf, D.face_chi.as<long long>(),
-                                  D.face_b0.as<int>(), dshapes, nsh, f_keys, f_chi, f_b0, D.status.as<int>(), s),
-            "finalize faces");
-  hip_check(sort_pairs_u64(tmp.p, tmpb, ek.as<unsigned long long>(), kB.as<unsigned long long>(), esl.as<int>(),
-                           vB.as<int>(), (int)ne, s),
-            "sort edges");
-  hip_check(launch_finalize_edges(kB.as<unsigned long long>(), vB.as<int>(), (int)ne, D.edge_chi.as<long long>(),
-                                  D.edge_b0.as<int>(), dshapes, nsh, e_keys, e_chi, e_b0, D.status.as<int>(), s),
-            "finalize edges");
+  const HashTab F{D.fkeys.as<unsigned long long>(), capF - 1}, E{D.ekeys.as<unsigned long long>(), capE - 1};
+  if (ns < (1 << 16) && nf < (1u << 31) && ne < (1u << 31)) {
+    // up to 2^16 sites: the lists are sorted by rows of their first site; slots are looked up again by key
+    DBuf kq(8 * std::max<size_t>(nq, 1)), t0(8 * std::max<size_t>(nf, 1)), t1(8 * std::max<size_t>(ne, 1)),
+        t2(8 * std::max<size_t>(nq, 1)), roff(4 * 3 * ((size_t)ns + 1)), rcur(4 * 3 * (size_t)std::max(ns, 1));
+    hip_check(launch_pack_rpv(rq.as<int4>(), (int)nq, kq.as<unsigned long long>(), s), "pack rpv");
+    unsigned long long* const keys[3] = {fk.as<unsigned long long>(), ek.as<unsigned long long>(),
+                                         kq.as<unsigned long long>()};
+    unsigned long long* const tmps[3] = {t0.as<unsigned long long>(), t1.as<unsigned long long>(),
+                                         t2.as<unsigned long long>()};
+    const int counts[3] = {(int)nf, (int)ne, (int)nq}, shifts[3] = {32, 42, 48};
+    hip_check(launch_row_sort(keys, tmps, counts, shifts, std::max(ns, 1), roff.as<int>(), rcur.as<int>(), s),
+              "sort lists");
+    hip_check(launch_finalize_faces(fk.as<unsigned long long>(), nullptr, F, (int)nf, D.face_chi.as<long long>(),
+                                    D.face_b0.as<int>(), dshapes, nsh, f_keys, f_chi, f_b0, D.status.as<int>(), s),
+              "finalize faces");
+    hip_check(launch_finalize_edges(ek.as<unsigned long long>(), nullptr, E, (int)ne, D.edge_chi.as<long long>(),
+                                    D.edge_b0.as<int>(), dshapes, nsh, e_keys, e_chi, e_b0, D.status.as<int>(), s),
+              "finalize edges");
+    hip_check(launch_unpack_rpv(kq.as<unsigned long long>(), (int)nq, (int4*)ob, s), "unpack rpv");
+  } else {
+    const size_t maxn = std::max(std::max(nf, ne), std::max(nq, (size_t)1));
+    size_t tmpb = sort_tmp_bytes((int)maxn);
+    DBuf tmp(tmpb), kA(8 * maxn), kB(8 * maxn), kC(8 * maxn), vA(4 * maxn), vB(4 * maxn);
+    hip_check(sort_pairs_u64(tmp.p, tmpb, fk.as<unsigned long long>(), kB.as<unsigned long long>(), fsl.as<int>(),
+                             vB.as<int>(), (int)nf, s),
+              "sort faces");
+    hip_check(launch_finalize_faces(kB.as<unsigned long long>(), vB.as<int>(), F, (int)nf, D.face_chi.as<long long>(),
+                                    D.face_b0.as<int>(), dshapes, nsh, f_keys, f_chi, f_b0, D.status.as<int>(), s),
+              "finalize faces");
+    hip_check(sort_pairs_u64(tmp.p, tmpb, ek.as<unsigned long long>(), kB.as<unsigned long long>(), esl.as<int>(),
+                             vB.as<int>(), (int)ne, s),
+              "sort edges");
+    hip_check(launch_finalize_edges(kB.as<unsigned long long>(), vB.as<int>(), E, (int)ne, D.edge_chi.as<long long>(),
+                                    D.edge_b0.as<int>(), dshapes, nsh, e_keys, e_chi, e_b0, D.status.as<int>(), s),
+              "finalize edges");
+    hip_check(launch_sort_rpv(rq.as<int4>(), (int)nq, kA.as<unsigned long long>(), kB.as<unsigned long long>(),
+                              kC.as<unsigned long long>(), vA.as<int>(), vB.as<int>(), tmp.p, tmpb, (int4*)ob, s),
+              "sort rpv");
+  }
   if (ns > 0)
     hip_check(launch_finalize_cells(ns, D.cell_chi.as<long long>(), D.cell_geo.as<long long>(), D.cell_np.as<int>(),
                                     D.cell_b0.as<int>(), dshapes, nsh, c_chi, c_b0, c_vol, c_cen, D.status.as<int>(),
                                     s),
               "finalize cells");
-  hip_check(launch_sort_rpv(rq.as<int4>(), (int)nq, kA.as<unsigned long long>(), kB.as<unsigned long long>(),
-                            kC.as<unsigned long long>(), vA.as<int>(), vB.as<int>(), tmp.p, tmpb, (int4*)ob, s),
-            "sort rpv");
   tm.mark(3, s);
   HostPinned host(out_bytes + 16);
   unsigned char* hb = (unsigned char*)host.p;

@@ -244,18 +244,131 @@ hipError_t launch_rpv_compact(const HashTab& Q, const int* cnt, const unsigned l
   return hipGetLastError();
 }
 
+// Lists whose keys lead with a site id below 2^16 (one row per site) are sorted by rows: count the keys of every
+// row, scan the counts, scatter the keys to their rows, then place each key by its rank within its (short) row. Up to three lists per launch
+// (blockIdx.y selects the list); the row arrays hold 3 x (rows + 1) counts and 3 x rows cursors.
+struct RowLists {
+  unsigned long long* keys[3];  // in: keys (any order); out: sorted
+  unsigned long long* tmp[3];   // scratch of the same size
+  int n[3];
+  int shift[3];                 // row = key >> shift
+  int* off;                     // [3][rows + 1]
+  int* cur;                     // [3][rows]
+  int rows;
+};
+__global__ void k_row_count(RowLists L) {
+  const int l = blockIdx.y;
+  int* off = L.off + l * (L.rows + 1);
+  for (int q = blockIdx.x * blockDim.x + threadIdx.x; q < L.n[l]; q += gridDim.x * blockDim.x)
+    atomicAdd(&off[(int)(L.keys[l][q] >> L.shift[l]) + 1], 1);
+}
+// exclusive scan of the row counts in place (one workgroup per list)
+__global__ __launch_bounds__(1024) void k_row_scan(RowLists L) {
+  __shared__ int s_part[1024];
+  const int l = blockIdx.x;
+  int* off = L.off + l * (L.rows + 1);
+  const int n = L.rows + 1, per = (n + 1023) / 1024, b0 = threadIdx.x * per, b1 = min(n, b0 + per);
+  int sum = 0;
+  for (int q = b0; q < b1; ++q) sum += off[q];
+  s_part[threadIdx.x] = sum;
+  __syncthreads();
+  for (int d = 1; d < 1024; d <<= 1) {  // inclusive scan of the per-thread sums
+    const int v = threadIdx.x >= d ? s_part[threadIdx.x - d] : 0;
+    __syncthreads();
+    s_part[threadIdx.x] += v;
+    __syncthreads();
+  }
+  int run = threadIdx.x ? s_part[threadIdx.x - 1] : 0;
+  for (int q = b0; q < b1; ++q) {  // off[q] held the count of row q - 1
+    run += off[q];
+    off[q] = run;
+  }
+}
+__global__ void k_row_scatter(RowLists L) {
+  const int l = blockIdx.y;
+  const int* off = L.off + l * (L.rows + 1);
+  int* cur = L.cur + l * L.rows;
+  for (int q = blockIdx.x * blockDim.x + threadIdx.x; q < L.n[l]; q += gridDim.x * blockDim.x) {
+    const unsigned long long k = L.keys[l][q];
+    const int r = (int)(k >> L.shift[l]);
+    L.tmp[l][off[r] + atomicAdd(&cur[r], 1)] = k;
+  }
+}
+// every key finds its place within its row by counting the smaller keys of the row (rows are short; keys unique)
+__global__ void k_row_rank(RowLists L) {
+  const int l = blockIdx.y;
+  const int* off = L.off + l * (L.rows + 1);
+  const unsigned long long* t = L.tmp[l];
+  for (int q = blockIdx.x * blockDim.x + threadIdx.x; q < L.n[l]; q += gridDim.x * blockDim.x) {
+    const unsigned long long k = t[q];
+    const int r = (int)(k >> L.shift[l]);
+    const int a = off[r], b = off[r + 1];
+    int rank = 0;
+    for (int x = a; x < b; ++x) rank += t[x] < k ? 1 : 0;
+    L.keys[l][a + rank] = k;
+  }
+}
+hipError_t launch_row_sort(unsigned long long* const keys[3], unsigned long long* const tmp[3], const int n[3],
+                           const int shift[3], int rows, int* off, int* cur, hipStream_t s) {
+  RowLists L;
+  int nmax = 1;
+  for (int l = 0; l < 3; ++l) {
+    L.keys[l] = keys[l];
+    L.tmp[l] = tmp[l];
+    L.n[l] = n[l];
+    L.shift[l] = shift[l];
+    nmax = std::max(nmax, n[l]);
+  }
+  L.off = off;
+  L.cur = cur;
+  L.rows = rows;
+  hipError_t e = launch_fill_i32(off, 0, 3 * (size_t)(rows + 1), s);
+  if (e == hipSuccess) e = launch_fill_i32(cur, 0, 3 * (size_t)rows, s);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_row_count, dim3(grid_for(nmax, 256), 3), dim3(256), 0, s, L);
+  hipLaunchKernelGGL(k_row_scan, dim3(3), dim3(1024), 0, s, L);
+  hipLaunchKernelGGL(k_row_scatter, dim3(grid_for(nmax, 256), 3), dim3(256), 0, s, L);
+  hipLaunchKernelGGL(k_row_rank, dim3(grid_for(nmax, 256), 3), dim3(256), 0, s, L);
+  return hipGetLastError();
+}
+
+// RPV quadruples with every id below 2^16 packed into one 64-bit key (and back) for the small sort
+__global__ void k_pack_rpv(const int4* in, int n, unsigned long long* out) {
+  for (int q = blockIdx.x * blockDim.x + threadIdx.x; q < n; q += gridDim.x * blockDim.x) {
+    const int4 r = in[q];
+    out[q] = ((unsigned long long)r.x << 48) | ((unsigned long long)r.y << 32) | ((unsigned long long)r.z << 16) |
+             (unsigned long long)r.w;
+  }
+}
+__global__ void k_unpack_rpv(const unsigned long long* in, int n, int4* out) {
+  for (int q = blockIdx.x * blockDim.x + threadIdx.x; q < n; q += gridDim.x * blockDim.x) {
+    const unsigned long long k = in[q];
+    out[q] = make_int4((int)(k >> 48), (int)((k >> 32) & 0xffff), (int)((k >> 16) & 0xffff), (int)(k & 0xffff));
+  }
+}
+hipError_t launch_pack_rpv(const int4* in, int n, unsigned long long* out, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_pack_rpv, dim3(grid_for(n, 256)), dim3(256), 0, s, in, n, out);
+  return hipGetLastError();
+}
+hipError_t launch_unpack_rpv(const unsigned long long* in, int n, int4* out, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_unpack_rpv, dim3(grid_for(n, 256)), dim3(256), 0, s, in, n, out);
+  return hipGetLastError();
+}
+
 hipError_t sort_pairs_u64(void* tmp, size_t& tmp_bytes, const unsigned long long* kin, unsigned long long* kout,
                           const int* vin, int* vout, int n, hipStream_t s) {
   if (n <= 0) return hipSuccess;
   return rocprim::radix_sort_pairs(tmp, tmp_bytes, kin, kout, vin, vout, (size_t)n, 0, 64, s);
 }
 
-__global__ void k_finalize_faces(const unsigned long long* keys, const int* slots, int n, const long long* chi_num,
-                                 const int* b0, const ShapeDesc* shapes, int nshapes, int* out_keys, int* out_chi,
-                                 int* out_b0, int* status) {
+__global__ void k_finalize_faces(const unsigned long long* keys, const int* slots, HashTab T, int n,
+                                 const long long* chi_num, const int* b0, const ShapeDesc* shapes, int nshapes,
+                                 int* out_keys, int* out_chi, int* out_b0, int* status) {
   for (int q = blockIdx.x * blockDim.x + threadIdx.x; q < n; q += gridDim.x * blockDim.x) {
     unsigned long long k = keys[q];
-    int s = slots[q];
+    int s = slots ? slots[q] : ht_find(T, k);
     out_keys[2 * q] = (int)(k >> 32);
     out_keys[2 * q + 1] = (int)(k & 0xffffffffull);
     const long long L = shapes[shape_of_site(shapes, nshapes, (int)(k >> 32))].L;
@@ -265,12 +378,12 @@ __global__ void k_finalize_faces(const unsigned long long* keys, const int* slot
     out_b0[q] = b0[s];
   }
 }
-__global__ void k_finalize_edges(const unsigned long long* keys, const int* slots, int n, const long long* chi_num,
-                                 const int* b0, const ShapeDesc* shapes, int nshapes, int* out_keys, int* out_chi,
-                                 int* out_b0, int* status) {
+__global__ void k_finalize_edges(const unsigned long long* keys, const int* slots, HashTab T, int n,
+                                 const long long* chi_num, const int* b0, const ShapeDesc* shapes, int nshapes,
+                                 int* out_keys, int* out_chi, int* out_b0, int* status) {
   for (int q = blockIdx.x * blockDim.x + threadIdx.x; q < n; q += gridDim.x * blockDim.x) {
     unsigned long long k = keys[q];
-    int s = slots[q];
+    int s = slots ? slots[q] : ht_find(T, k);
     out_keys[3 * q] = (int)(k >> 42);
     out_keys[3 * q + 1] = (int)((k >> 21) & 0x1fffff);
     out_keys[3 * q + 2] = (int)(k & 0x1fffff);
@@ -297,20 +410,20 @@ __global__ void k_finalize_cells(int ns, const long long* chi_num, const long lo
   }
 }
 
-hipError_t launch_finalize_faces(const unsigned long long* keys, const int* slots, int n, const long long* chi_num,
-                                 const int* b0, const ShapeDesc* shapes, int nshapes, int* out_keys, int* out_chi,
-                                 int* out_b0, int* status, hipStream_t s) {
+hipError_t launch_finalize_faces(const unsigned long long* keys, const int* slots, const HashTab& T, int n,
+                                 const long long* chi_num, const int* b0, const ShapeDesc* shapes, int nshapes,
+                                 int* out_keys, int* out_chi, int* out_b0, int* status, hipStream_t s) {
   if (n <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_finalize_faces, dim3(grid_for(n, 256)), dim3(256), 0, s, keys, slots, n, chi_num, b0, shapes,
-                     nshapes, out_keys, out_chi, out_b0, status);
+  hipLaunchKernelGGL(k_finalize_faces, dim3(grid_for(n, 256)), dim3(256), 0, s, keys, slots, T, n, chi_num, b0,
+                     shapes, nshapes, out_keys, out_chi, out_b0, status);
   return hipGetLastError();
 }
-hipError_t launch_finalize_edges(const unsigned long long* keys, const int* slots, int n, const long long* chi_num,
-                                 const int* b0, const ShapeDesc* shapes, int nshapes, int* out_keys, int* out_chi,
-                                 int* out_b0, int* status, hipStream_t s) {
+hipError_t launch_finalize_edges(const unsigned long long* keys, const int* slots, const HashTab& T, int n,
+                                 const long long* chi_num, const int* b0, const ShapeDesc* shapes, int nshapes,
+                                 int* out_keys, int* out_chi, int* out_b0, int* status, hipStream_t s) {
   if (n <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_finalize_edges, dim3(grid_for(n, 256)), dim3(256), 0, s, keys, slots, n, chi_num, b0, shapes,
-                     nshapes, out_keys, out_chi, out_b0, status);
+  hipLaunchKernelGGL(k_finalize_edges, dim3(grid_for(n, 256)), dim3(256), 0, s, keys, slots, T, n, chi_num, b0,
+                     shapes, nshapes, out_keys, out_chi, out_b0, status);
   return hipGetLastError();
 }
 hipError_t launch_finalize_cells(int ns, const long long* chi_num, const long long* geo, const int* np, const int* b0,

@@ -33,12 +33,20 @@ hipError_t sort_pairs_u64(void* tmp, size_t& tmp_bytes, const unsigned long long
                           const int* vin, int* vout, int n, hipStream_t s);
 size_t sort_tmp_bytes(int n);
 // element lists over exactly n sorted live entries
-hipError_t launch_finalize_faces(const unsigned long long* keys, const int* slots, int n, const long long* chi_num,
-                                 const int* b0, const ShapeDesc* shapes, int nshapes, int* out_keys, int* out_chi,
-                                 int* out_b0, int* status, hipStream_t s);
-hipError_t launch_finalize_edges(const unsigned long long* keys, const int* slots, int n, const long long* chi_num,
-                                 const int* b0, const ShapeDesc* shapes, int nshapes, int* out_keys, int* out_chi,
-                                 int* out_b0, int* status, hipStream_t s);
+// (slots may be null: each key's slot is then looked up in T)
+hipError_t launch_finalize_faces(const unsigned long long* keys, const int* slots, const HashTab& T, int n,
+                                 const long long* chi_num, const int* b0, const ShapeDesc* shapes, int nshapes,
+                                 int* out_keys, int* out_chi, int* out_b0, int* status, hipStream_t s);
+hipError_t launch_finalize_edges(const unsigned long long* keys, const int* slots, const HashTab& T, int n,
+                                 const long long* chi_num, const int* b0, const ShapeDesc* shapes, int nshapes,
+                                 int* out_keys, int* out_chi, int* out_b0, int* status, hipStream_t s);
+// three lists of keys whose row (key >> shift) is below rows, sorted ascending in place; tmp[l] holds n[l] keys;
+// off holds 3 (rows + 1) ints, cur 3 rows ints
+hipError_t launch_row_sort(unsigned long long* const keys[3], unsigned long long* const tmp[3], const int n[3],
+                           const int shift[3], int rows, int* off, int* cur, hipStream_t s);
+// RPV quadruples whose ids are all below 2^16, packed into single keys and back
+hipError_t launch_pack_rpv(const int4* in, int n, unsigned long long* out, hipStream_t s);
+hipError_t launch_unpack_rpv(const unsigned long long* in, int n, int4* out, hipStream_t s);
 hipError_t launch_finalize_cells(int ns, const long long* chi_num, const long long* geo, const int* np, const int* b0,
                                  const ShapeDesc* shapes, int nshapes, int* out_chi, int* out_b0, double* out_vol,
                                  double* out_cen, int* status, hipStream_t s);

@@ -124,7 +124,7 @@ struct DeviceState {
   int def_cap = 0, piece_cap = 0;
   DBuf site, status, cell_chi, cell_geo, cell_np, cell_b0;
   DBuf fkeys, face_chi, face_np, face_b0, ekeys, edge_chi, edge_np, edge_b0, qkeys, rpv_cnt;
-  DBuf nkeys, node_st, parent, deferred, pieces, counters, tetU, slow, touch;
+  DBuf nkeys, node_st, parent, deferred, deferred2, pieces, counters, tetU, slow, touch;
   int waves = 0;
 
   unsigned long long* cnt() const { return counters.as<unsigned long long>(); }
@@ -171,6 +171,7 @@ struct DeviceState {
     node_st.alloc(4 * (size_t)capN);
     parent.alloc(4 * (size_t)capN);
     deferred.alloc(16 * (size_t)def_cap);
+    deferred2.alloc(16 * (size_t)(def_cap / 4 + 1024));
     pieces.alloc(sizeof(PieceRec) * (size_t)std::max(piece_cap, 1));
     counters.alloc(8 * (NCOUNTERS + 8 + (size_t)NSPREAD * NCOUNTERS));
     if (keep_U) {  // incremental updates: U_t per tet and the touched-element flags
@@ -235,6 +236,8 @@ struct DeviceState {
     a.tet_U = tetU.p ? tetU.as<double>() : nullptr;
     a.deferred = deferred.as<int4>();
     a.deferred_cap = def_cap;
+    a.deferred2 = deferred2.as<int4>();
+    a.deferred2_cap = def_cap / 4 + 1024;
     a.pieces = pieces.as<PieceRec>();
     a.piece_cap = piece_cap;
     a.counters = cnt();
@@ -945,6 +948,7 @@ static void check_status(rpd_session* S) {
 // one full clipping pass over the items of a (all blocks, or the dirty ones with a device-side count)
 static void clip_pass(rpd_session* S, const ShapeArgs& a) {
   hip_check(launch_fill_u64(S->D.cnt() + C_DEFER_ITEMS, 0, 1, S->stream), "fill");
+  hip_check(launch_fill_u64(S->D.cnt() + C_DEFER2, 0, 1, S->stream), "fill");
   hip_check(launch_clip_fast(a, S->o.precision, S->o.block, S->stream), "clip kernel");
   hip_check(launch_clip_slow(a, S->D.slow.as<unsigned char>(), S->D.waves, S->stream), "deferred clip kernel");
 }

@@ -666,29 +666,54 @@ struct SlowScratch {  // per wave, in global memory: the candidate lists, their 
   static constexpr size_t tab_bytes = 64 * (size_t)SLOW_PMAX;                          // [plane][lane]
   static constexpr size_t bytes = wave_bytes + xyz_bytes + topo_bytes + tab_bytes;
 };
-constexpr int SLOW_LDS_LANES = 16;   // the LDS variant clips with 16 lanes, each polytope in LDS
 constexpr int SLOW_LDS_ITEMS = 512;  // the first deferred items go to the LDS variant (one item per wave)
+
+// The LDS variant (few items: latency) keeps the candidate lists and 32 lanes' polytopes (32 vertices) in LDS; an item
+// with more than 256 candidates, or a piece with more vertices, is handed to the global variant through the overflow
+// list. The global variant (many items: throughput) keeps the lists and all 64 lanes' polytopes (64 vertices) in its
+// scratch and takes the items past the LDS variant's share, then the overflow list.
+template <bool LDS>
+struct SlowCfg;
+template <>
+struct SlowCfg<true> {
+  static constexpr int CL = 32, VCAP = 32, KCAP = 256;
+  typedef unsigned Mask;
+};
+template <>
+struct SlowCfg<false> {
+  static constexpr int CL = 64, VCAP = SLOW_VMAX, KCAP = SLOW_KMAX;
+  typedef unsigned long long Mask;
+};
+
+__device__ inline void push_overflow(const ShapeArgs& a, int4 item) {
+  const unsigned long long idx = atomicAdd(&a.counters[C_DEFER2], 1ull);
+  if (idx < (unsigned long long)a.deferred2_cap) a.deferred2[idx] = item;
+  else atomicOr(a.status, ST_TABLE_FULL);
+}
 
 // One wavefront per deferred item: the lanes split the scan over all of the shape's sites (candidates are
 // compacted in ascending site order by ballots), drop dominated candidates and rank-sort the rest, then clip the
-// pieces with FP64 polytopes of up to 64 vertices. The LDS variant (few items: latency) keeps 16 lanes' polytopes in
-// LDS; the global variant (many items: throughput) keeps all 64 lanes' polytopes in its scratch. Both interleave the
-// lanes slot by slot.
+// pieces with FP64 polytopes (lanes interleaved slot by slot).
 template <bool LDS>
 __global__ __launch_bounds__(64) void k_clip_slow(ShapeArgs a, unsigned char* scratch, int item_begin, int item_end) {
-  constexpr int CL = LDS ? SLOW_LDS_LANES : 64;  // clipping lanes
-  __shared__ Coord4<double>::type s_xyz[LDS ? SLOW_VMAX * CL : 1];
-  __shared__ unsigned long long s_topo[LDS ? SLOW_VMAX * CL : 1];
-  __shared__ unsigned char s_tab[LDS ? SLOW_PMAX * CL : 1];
-  const int n_items = (int)min(min(a.counters[C_DEFER_ITEMS], (unsigned long long)a.deferred_cap),
-                               (unsigned long long)item_end);
+  typedef SlowCfg<LDS> C;
+  constexpr int CL = C::CL, KC = C::KCAP;
+  __shared__ Coord4<double>::type s_xyz[LDS ? C::VCAP * CL : 1];
+  __shared__ unsigned long long s_topo[LDS ? C::VCAP * CL : 1];
+  __shared__ unsigned char s_tab[LDS ? (4 + KC) * CL : 1];
+  __shared__ int s_cand[LDS ? 2 * KC : 1];
+  __shared__ double s_key[LDS ? 6 * KC : 1];
+  const int n_main = (int)min(min(a.counters[C_DEFER_ITEMS], (unsigned long long)a.deferred_cap),
+                              (unsigned long long)item_end);
+  const int n_over = LDS ? 0 : (int)min(a.counters[C_DEFER2], (unsigned long long)a.deferred2_cap);
+  const int n_items = max(n_main - item_begin, 0) + n_over;
   const int lane = threadIdx.x;
   unsigned char* wbase = scratch + (size_t)blockIdx.x * SlowScratch::bytes;
-  int* cand = (int*)wbase;
-  double* key = (double*)(wbase + SlowScratch::cand_bytes);
-  int* scand = (int*)(wbase + SlowScratch::cand_bytes + SlowScratch::key_bytes);
-  double* skey = (double*)(wbase + 2 * SlowScratch::cand_bytes + SlowScratch::key_bytes);
-  double* gv = (double*)(wbase + 2 * (SlowScratch::cand_bytes + SlowScratch::key_bytes));
+  int* cand = LDS ? s_cand : (int*)wbase;
+  int* scand = LDS ? s_cand + KC : (int*)(wbase + SlowScratch::cand_bytes + SlowScratch::key_bytes);
+  double* key = LDS ? s_key : (double*)(wbase + SlowScratch::cand_bytes);
+  double* skey = LDS ? s_key + KC : (double*)(wbase + 2 * SlowScratch::cand_bytes + SlowScratch::key_bytes);
+  double* gv = LDS ? s_key + 2 * KC : (double*)(wbase + 2 * (SlowScratch::cand_bytes + SlowScratch::key_bytes));
   const int cl_lane = lane < CL ? lane : 0;
   Coord4<double>::type* xyz =
       LDS ? s_xyz + cl_lane : (Coord4<double>::type*)(wbase + SlowScratch::wave_bytes) + cl_lane;
@@ -698,8 +723,9 @@ __global__ __launch_bounds__(64) void k_clip_slow(ShapeArgs a, unsigned char* sc
   unsigned char* tab =
       LDS ? s_tab + cl_lane : wbase + SlowScratch::wave_bytes + SlowScratch::xyz_bytes + SlowScratch::topo_bytes + cl_lane;
   unsigned long long n_pairs = 0, n64 = 0, nex = 0;
-  for (int it = item_begin + blockIdx.x; it < n_items; it += gridDim.x) {
-    const int4 di = a.deferred[it];
+  for (int vi = blockIdx.x; vi < n_items; vi += gridDim.x) {
+    const int main_count = max(n_main - item_begin, 0);
+    const int4 di = vi < main_count ? a.deferred[item_begin + vi] : a.deferred2[vi - main_count];
     const ShapeDesc sd = a.shapes[__builtin_amdgcn_readfirstlane(di.x)];
     const int t = di.y;
     const int want = di.z;
@@ -743,14 +769,17 @@ __global__ __launch_bounds__(64) void k_clip_slow(ShapeArgs a, unsigned char* sc
       }
       unsigned long long mask = __ballot(take);
       int pos = m + __popcll(mask & ((1ull << lane) - 1ull));
-      if (take && pos < SLOW_KMAX) {
+      if (take && pos < KC) {
         cand[pos] = sd.site_off + j;
         key[pos] = kk;
       }
       m += __popcll(mask);
     }
-    if (m > SLOW_KMAX) {
-      if (lane == 0) atomicOr(a.status, ST_SLOW_CAPACITY);
+    if (m > KC) {
+      if (lane == 0) {
+        if (LDS) push_overflow(a, di);
+        else atomicOr(a.status, ST_SLOW_CAPACITY);
+      }
       continue;
     }
     __syncthreads();
@@ -805,7 +834,7 @@ __global__ __launch_bounds__(64) void k_clip_slow(ShapeArgs a, unsigned char* sc
     __syncthreads();
     for (int ci = lane; ci < m && lane < CL; ci += CL) {
       if (want >= 0 && scand[ci] != want) continue;
-      Clipper<double, Topo64, unsigned long long, SLOW_VMAX, true> cl;
+      Clipper<double, Topo64, typename C::Mask, C::VCAP, true> cl;
       cl.st.c = xyz;
       cl.st.w = topo;
       cl.st.stride = CL;
@@ -828,8 +857,9 @@ __global__ __launch_bounds__(64) void k_clip_slow(ShapeArgs a, unsigned char* sc
       int r = clip_piece(cl, m, a.status);
       n64 += cl.n64;
       nex += cl.nex;
-      if (r == CLIP_DEFER) {
-        atomicOr(a.status, ST_SLOW_CAPACITY);
+      if (r == CLIP_DEFER) {  // out of vertex slots
+        if (LDS) push_overflow(a, make_int4(di.x, t, scand[ci], 0));
+        else atomicOr(a.status, ST_SLOW_CAPACITY);
         continue;
       }
       if (r == CLIP_OK) {

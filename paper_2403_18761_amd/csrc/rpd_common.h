@@ -31,6 +31,7 @@ enum {
   C_DEFER_KMAX,   // tets deferred because they kept more than the candidate budget
   C_DEFER_CLIP,   // pieces deferred because the polytope outgrew the vertex slots
   C_SPLIT,        // workgroup blocks redone in chunks because their site list overflowed
+  C_DEFER2,       // items handed on by the LDS variant of the large-capacity kernel
   C_GLUE_BITS,    // gluing bits of the pieces whose components are (re)computed
   C_GLUE_PAIRS,   // glued pairs matched
   NCOUNTERS
@@ -108,6 +109,8 @@ struct ShapeArgs {
   double* tet_U;         // optional [total tets]: U_t of the candidate test, kept for the incremental update
   int4* deferred;        // (shape, local tet, global site or -1 for every candidate, 0) for the large-capacity path
   int deferred_cap;
+  int4* deferred2;       // items the LDS variant of the large-capacity path hands to its global variant
+  int deferred2_cap;
   PieceRec* pieces;      // kept with RPD_KEEP_PIECES (t = global tet id)
   int piece_cap;
   unsigned long long* counters;  // [NCOUNTERS] (cursors and host-read totals)

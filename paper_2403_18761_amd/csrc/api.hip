@@ -770,7 +770,7 @@ rpd_status rpd_autotune(const rpd_mesh* const* meshes, const rpd_sites* sites, i
   if (o.precision != RPD_FP32_FALLBACK) throw Failure{RPD_E_INVALID, "only the FP32 path is tuned"};
   o.flags |= RPD_TIMING;
   o.flags &= ~(uint32_t)RPD_KEEP_PIECES;
-  const int blocks[3] = {64, 128, 256}, budgets[2] = {16, rpd::KMAX};
+  const int blocks[3] = {64, 128, 256}, budgets[3] = {8, 16, rpd::KMAX};
   double best_ms = INFINITY;
   int bb = 128, bk = rpd::KMAX;
   for (int b : blocks)

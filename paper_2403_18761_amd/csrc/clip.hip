@@ -302,45 +302,33 @@ __device__ inline void g4(const float4* tv, const float4& s, double* g) {
 // Remove candidates dominated on the whole tet by one of the first three candidates (exact test: g_j - g_i is
 // affine, so being larger at the four vertices means larger everywhere on the tet and j owns no point of it).
 // The list must be sorted (only_count: the list is unsorted and over budget; it is filtered but stays unsorted).
-__device__ int refine_candidates(const float4* tv, const float4* sites, const int* sid, unsigned char* cand,
-                                 double* key, int m, bool unsorted) {
-  int r0 = 0, r1 = 1, r2 = 2;  // indices of the reference candidates
-  if (unsorted) {              // the three smallest keys (scalar insertion, no indexed arrays)
-    r0 = r1 = r2 = -1;
-    for (int c = 0; c < m; ++c) {
-      const double k = key[c];
-      if (r0 < 0 || k < key[r0]) {
-        r2 = r1;
-        r1 = r0;
-        r0 = c;
-      } else if (r1 < 0 || k < key[r1]) {
-        r2 = r1;
-        r1 = c;
-      } else if (r2 < 0 || k < key[r2]) {
-        r2 = c;
+// Drops the candidates that another candidate beats at all four tet vertices (g is affine, so then everywhere on the
+// tet: the site owns nothing there and its bisector constrains no piece; the values are exact in FP64). The list is
+// sorted by the power distance at the centroid, and a dominator has the smaller one, so rounds of three dominators
+// taken in list order (each tested against the candidates after them) find the dominated candidates the three-at-a-time
+// way; the rounds run while candidates remain past the dominators. Returns the new count; order is kept.
+__device__ int refine_candidates(const float4* tv, const float4* sites, unsigned char* cand, float* key, int m) {
+  for (int d = 0; d + 3 < m; d += 3) {
+    double g0[4], g1[4], g2[4];
+    g4(tv, sites[cand[d]], g0);
+    g4(tv, sites[cand[d + 1]], g1);
+    g4(tv, sites[cand[d + 2]], g2);
+    int w = d + 3;
+    for (int c = d + 3; c < m; ++c) {
+      double g[4];
+      g4(tv, sites[cand[c]], g);
+      const bool dom = (g[0] > g0[0] && g[1] > g0[1] && g[2] > g0[2] && g[3] > g0[3]) ||
+                       (g[0] > g1[0] && g[1] > g1[1] && g[2] > g1[2] && g[3] > g1[3]) ||
+                       (g[0] > g2[0] && g[1] > g2[1] && g[2] > g2[2] && g[3] > g2[3]);
+      if (!dom) {
+        cand[w] = cand[c];
+        key[w] = key[c];
+        ++w;
       }
     }
+    m = w;
   }
-  if (m < 3) r2 = -1;
-  if (m < 2) r1 = -1;
-  double g0[4], g1[4], g2[4];
-  g4(tv, sites[cand[r0]], g0);
-  if (r1 >= 0) g4(tv, sites[cand[r1]], g1);
-  if (r2 >= 0) g4(tv, sites[cand[r2]], g2);
-  int w = 0;
-  for (int c = 0; c < m; ++c) {
-    double g[4];
-    g4(tv, sites[cand[c]], g);
-    bool dom = (c != r0) && g[0] > g0[0] && g[1] > g0[1] && g[2] > g0[2] && g[3] > g0[3];
-    dom = dom || (r1 >= 0 && c != r1 && g[0] > g1[0] && g[1] > g1[1] && g[2] > g1[2] && g[3] > g1[3]);
-    dom = dom || (r2 >= 0 && c != r2 && g[0] > g2[0] && g[1] > g2[1] && g[2] > g2[2] && g[3] > g2[3]);
-    if (!dom) {
-      cand[w] = cand[c];
-      key[w] = key[c];
-      ++w;
-    }
-  }
-  return w;
+  return m;
 }
 
 template <typename T, int NT>
@@ -351,12 +339,12 @@ __global__ __launch_bounds__(NT) void k_clip_fast(ShapeArgs a) {
   __shared__ float4 s_face[TB][4];
   __shared__ float4 s_site[SLMAX];
   __shared__ int s_sid[SLMAX];
-  __shared__ unsigned char s_cand[TB][KMAX];
+  __shared__ unsigned char s_cand[TB][KRAW];
   // the candidates' sort keys are dead before the clipping phase starts: they share storage with the polytopes
   constexpr size_t XYZ_BYTES = sizeof(typename Coord4<T>::type) * VMAX * NT;
-  constexpr size_t KEY_BYTES = sizeof(double) * TB * KMAX;
+  constexpr size_t KEY_BYTES = sizeof(float) * TB * KRAW;
   __shared__ __attribute__((aligned(16))) unsigned char s_share[XYZ_BYTES > KEY_BYTES ? XYZ_BYTES : KEY_BYTES];
-  double(*s_key)[KMAX] = reinterpret_cast<double(*)[KMAX]>(s_share);
+  float(*s_key)[KRAW] = reinterpret_cast<float(*)[KRAW]>(s_share);
   typename Coord4<T>::type* s_xyz = reinterpret_cast<typename Coord4<T>::type*>(s_share);
   __shared__ int s_m[TB];
   __shared__ int s_off[TB + 1];
@@ -510,33 +498,24 @@ __global__ __launch_bounds__(NT) void k_clip_fast(ShapeArgs a) {
         for (int v = 0; v < 3; ++v) gmn = fmin(gmn, D - 2.0 * (y[v][0] * ax_ + y[v][1] * ay_ + y[v][2] * az_));
         if (gmn <= U) {
           int pos = atomicAdd(&s_m[lt], 1);
-          if (pos < KMAX) {
+          if (pos < KRAW) {
             s_cand[lt][pos] = (unsigned char)q;
-            s_key[lt][pos] = D - 2.0 * (ycx * ax_ + ycy * ay_ + ycz * az_);
+            s_key[lt][pos] = (float)(D - 2.0 * (ycx * ax_ + ycy * ay_ + ycz * az_));
           }
         }
       }
     }
   }
   __syncthreads();
-  // sort each tet's candidates by (power distance at the centroid, site id), drop the ones that one of the three
-  // nearest candidates dominates at all four tet vertices (g affine: then everywhere on the tet), and mark the
-  // overflowing tets
+  // sort each tet's candidates by (power distance at the centroid, site id), drop the dominated ones, and mark the
+  // tets that keep more than the budget
   if (tid < ntb) {
     int m = s_m[tid];
-    if (!block_overflow && m > a.kmax && m <= KMAX) m = refine_candidates(s_tv[tid], s_site, s_sid, s_cand[tid],
-                                                                         s_key[tid], m, true);
-    if (block_overflow || m > a.kmax) {
-      s_m[tid] = -1;
-      stat_add(a, block_overflow ? C_DEFER_BLOCK : C_DEFER_KMAX, 1ull);
-      unsigned long long idx = atomicAdd(&a.counters[C_DEFER_ITEMS], 1ull);
-      if (idx < (unsigned long long)a.deferred_cap) a.deferred[idx] = make_int4(wi.x, t0 + tid, -1, 0);
-      else atomicOr(a.status, ST_TABLE_FULL);
-    } else {
+    if (!block_overflow && m <= KRAW) {
       for (int x = 1; x < m; ++x) {
-        double kx = s_key[tid][x];
-        unsigned char cx = s_cand[tid][x];
-        int ix = s_sid[cx];
+        const float kx = s_key[tid][x];
+        const unsigned char cx = s_cand[tid][x];
+        const int ix = s_sid[cx];
         int y = x - 1;
         while (y >= 0 && (s_key[tid][y] > kx || (s_key[tid][y] == kx && s_sid[s_cand[tid][y]] > ix))) {
           s_key[tid][y + 1] = s_key[tid][y];
@@ -546,7 +525,16 @@ __global__ __launch_bounds__(NT) void k_clip_fast(ShapeArgs a) {
         s_key[tid][y + 1] = kx;
         s_cand[tid][y + 1] = cx;
       }
-      s_m[tid] = refine_candidates(s_tv[tid], s_site, s_sid, s_cand[tid], s_key[tid], m, false);
+      m = refine_candidates(s_tv[tid], s_site, s_cand[tid], s_key[tid], m);
+    }
+    if (block_overflow || m > a.kmax) {
+      s_m[tid] = -1;
+      stat_add(a, block_overflow ? C_DEFER_BLOCK : C_DEFER_KMAX, 1ull);
+      unsigned long long idx = atomicAdd(&a.counters[C_DEFER_ITEMS], 1ull);
+      if (idx < (unsigned long long)a.deferred_cap) a.deferred[idx] = make_int4(wi.x, t0 + tid, -1, 0);
+      else atomicOr(a.status, ST_TABLE_FULL);
+    } else {
+      s_m[tid] = m;
     }
   }
   __syncthreads();

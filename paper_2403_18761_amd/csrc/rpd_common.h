@@ -8,7 +8,8 @@ namespace rpd {
 
 // Fast-path capacities of the clipping kernel.
 constexpr int TB = 64;       // tets per workgroup
-constexpr int KMAX = 28;     // candidate sites per tet (plane ids 4 + position must fit 5 bits)
+constexpr int KMAX = 28;     // candidate sites per tet kept for clipping (plane ids 4 + position must fit 5 bits)
+constexpr int KRAW = 40;     // candidate sites per tet before the dominance refinement
 constexpr int VMAX = 16;     // vertex slots of one piece (4-bit neighbour ids)
 constexpr int SLMAX = 256;   // sites in a workgroup's shared candidate list
 constexpr int SUB = 8;       // tets per chunk when a block's site list overflows

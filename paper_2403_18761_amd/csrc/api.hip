@@ -1111,7 +1111,8 @@ rpd_status rpd_session_create(const rpd_mesh* mesh, const rpd_sites* sites, cons
     throw Failure{RPD_E_INVALID, "no initial sites"};
   if (opts->max_sites < sites->n_sites || opts->max_sites >= (1 << 21))
     throw Failure{RPD_E_INVALID, "max_sites must be in [n_sites, 2^21)"};
-  if (opts->max_insert < 1 || opts->max_insert > 4096) throw Failure{RPD_E_INVALID, "max_insert must be in [1, 4096]"};
+  if (opts->max_insert < 1 || opts->max_insert > rpd::MAX_INSERT)
+    throw Failure{RPD_E_INVALID, "max_insert must be in [1, 4096]"};
   if (table->n_sites != mesh->nt || !table->sx || !table->sy || !table->sz || !table->sr)
     throw Failure{RPD_E_INVALID, "the table needs one sphere per tet"};
   if (mesh->nblk <= 0) throw Failure{RPD_E_INVALID, "empty mesh"};

@@ -144,6 +144,8 @@ __device__ inline int shape_of_tet(const ShapeDesc* sd, int n, long long gt) {
 
 // Device state of one round of the incremental session (all counts live in device memory so that the round is a
 // fixed launch sequence).
+constexpr int MAX_INSERT = 4096;  // cells handled per session round, at most
+
 struct RoundState {
   int* nsel;                  // cells selected this round
   int* sel;                   // [max_insert] selected cells, ascending

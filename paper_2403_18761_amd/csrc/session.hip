@@ -10,6 +10,8 @@
 //      (every accumulator is an exactly invertible integer), and recompute beta0 of the live element pieces.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+
 #include "rpd_device.h"
 #include "rpd_launch.h"
 
@@ -64,15 +66,26 @@ __device__ inline int uf_root(const int* par, int x) {
   }
 }
 
-__global__ void k_ref_tet(HashTab N, const int* node_st, RoundState r) {
+// The scans over the element-piece table reduce into LDS slots of the selected cells first (dynamic LDS of
+// max_insert entries) and flush once per workgroup, on a grid of a few workgroups per compute unit.
+constexpr int SCAN_BLOCKS = 1024;
+
+__global__ __launch_bounds__(256) void k_ref_tet(HashTab N, const int* node_st, RoundState r) {
+  extern __shared__ int s_ref[];
+  const int nsel = *r.nsel;
+  for (int k = threadIdx.x; k < nsel; k += blockDim.x) s_ref[k] = 0x7fffffff;
+  __syncthreads();
   const unsigned cap = N.mask + 1;
   for (unsigned s = blockIdx.x * blockDim.x + threadIdx.x; s < cap; s += gridDim.x * blockDim.x) {
     unsigned long long key = N.keys[s];
-    if (key == EMPTY_KEY || !node_live(node_st[s]) || (key >> 62) != 1) continue;
+    if (key == EMPTY_KEY || (key >> 62) != 1 || !node_live(node_st[s])) continue;
     int cell = (int)((key >> 32) & 0x3fffffff);
     int k = r.selpos[cell];
-    if (k >= 0) atomicMin(&r.ref[k], (int)(key & 0xffffffffull));
+    if (k >= 0) atomicMin(&s_ref[k], (int)(key & 0xffffffffull));
   }
+  __syncthreads();
+  for (int k = threadIdx.x; k < nsel; k += blockDim.x)
+    if (s_ref[k] != 0x7fffffff) atomicMin(&r.ref[k], s_ref[k]);
 }
 
 __device__ inline unsigned mix_hash(unsigned long long x) {  // splitmix64 finaliser
@@ -82,12 +95,17 @@ __device__ inline unsigned mix_hash(unsigned long long x) {  // splitmix64 final
   return (unsigned)((x ^ (x >> 31)) >> 32);
 }
 
-__global__ void k_pick_tet(HashTab N, const int* node_st, const int* parent, const int* cell_b0, RoundState r) {
+__global__ __launch_bounds__(256) void k_pick_tet(HashTab N, const int* node_st, const int* parent, const int* cell_b0,
+                                                  RoundState r) {
+  extern __shared__ unsigned long long s_best[];
+  const int nsel = *r.nsel;
+  for (int k = threadIdx.x; k < nsel; k += blockDim.x) s_best[k] = 0ull;
+  __syncthreads();
   const unsigned cap = N.mask + 1;
   const int round = *r.round;
   for (unsigned s = blockIdx.x * blockDim.x + threadIdx.x; s < cap; s += gridDim.x * blockDim.x) {
     unsigned long long key = N.keys[s];
-    if (key == EMPTY_KEY || !node_live(node_st[s]) || (key >> 62) != 1) continue;
+    if (key == EMPTY_KEY || (key >> 62) != 1 || !node_live(node_st[s])) continue;
     int cell = (int)((key >> 32) & 0x3fffffff);
     int k = r.selpos[cell];
     if (k < 0) continue;
@@ -98,27 +116,60 @@ __global__ void k_pick_tet(HashTab N, const int* node_st, const int* parent, con
       if (rs >= 0 && uf_root(parent, rs) == uf_root(parent, (int)s)) continue;
     }
     unsigned h = mix_hash(((unsigned long long)(unsigned)t << 32) | (unsigned)round);
-    atomicMax(&r.best[k], ((unsigned long long)h << 32) | (unsigned)t);
+    atomicMax(&s_best[k], ((unsigned long long)h << 32) | (unsigned)t);
   }
+  __syncthreads();
+  for (int k = threadIdx.x; k < nsel; k += blockDim.x)
+    if (s_best[k]) atomicMax(&r.best[k], s_best[k]);
 }
 
-// one thread: insert in selection order (deterministic site ids), update the two shape descriptors
-__global__ void k_insert(RoundState r, float4* site) {
-  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+// Insertion in selection order (deterministic site ids): cell k inserts its tet's sphere unless a cell earlier in
+// the order chose the same tet, the tet's sphere is in already, or the site capacity is reached. One workgroup.
+__global__ __launch_bounds__(1024) void k_insert(RoundState r, float4* site) {
+  __shared__ unsigned long long s_b[MAX_INSERT];
+  __shared__ int s_wave[16];
+  __shared__ int s_total;
   const int n0 = *r.ns_cur;
-  int n = n0;
   const int nsel = *r.nsel;
-  for (int k = 0; k < nsel; ++k) {
-    unsigned long long b = r.best[k];
-    if (b == 0ull || n >= r.max_sites) continue;
-    int t = (int)(b & 0xffffffffull);
-    if (r.tet_used[t]) continue;
-    r.tet_used[t] = 1;
-    site[n++] = r.table[t];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  for (int k = threadIdx.x; k < nsel; k += blockDim.x) s_b[k] = r.best[k];
+  if (threadIdx.x == 0) s_total = 0;
+  __syncthreads();
+  for (int base = 0; base < nsel; base += 1024) {
+    const int k = base + threadIdx.x;
+    bool win = false;
+    int t = -1;
+    if (k < nsel) {
+      const unsigned long long b = s_b[k];
+      t = (int)(b & 0xffffffffull);
+      win = b != 0ull && !r.tet_used[t];
+      for (int q = 0; q < k && win; ++q) {
+        const unsigned long long bq = s_b[q];
+        win = !(bq != 0ull && (int)(bq & 0xffffffffull) == t);
+      }
+    }
+    const unsigned long long m = __ballot(win);
+    if (lane == 0) s_wave[w] = __popcll(m);
+    __syncthreads();
+    int before = s_total;
+    for (int q = 0; q < w; ++q) before += s_wave[q];
+    const int pos = n0 + before + __popcll(m & ((1ull << lane) - 1ull));
+    if (win && pos < r.max_sites) site[pos] = r.table[t];
+    __syncthreads();  // every thread has read tet_used before it changes
+    if (win && pos < r.max_sites) r.tet_used[t] = 1;
+    if (threadIdx.x == 0) {
+      int c = 0;
+      for (int q = 0; q < 16; ++q) c += s_wave[q];
+      s_total += c;
+    }
+    __syncthreads();
   }
-  r.old_desc->ns = n0;
-  r.new_desc->ns = n;
-  *r.ins_total += n - n0;
+  if (threadIdx.x == 0) {
+    const int n = min(n0 + s_total, r.max_sites);
+    r.old_desc->ns = n0;
+    r.new_desc->ns = n;
+    *r.ins_total += n - n0;
+  }
 }
 
 // a tet is dirty if one of the new spheres passes its exact candidate test against the stored U_t
@@ -144,37 +195,23 @@ __global__ void k_mark_dirty(RoundState r, const float4* tp, int nt, const float
   }
 }
 
-// dirty blocks -> work items in ascending block order (one workgroup), then clear the flags
-__global__ __launch_bounds__(256) void k_dirty_items(RoundState r, int nblk) {
-  __shared__ int s_count;
-  __shared__ int s_warp[4];
-  if (threadIdx.x == 0) s_count = 0;
-  __syncthreads();
-  for (int base = 0; base < nblk; base += 256) {
-    const int b = base + threadIdx.x;
-    const bool d = b < nblk && r.dirty[b] != 0;
-    unsigned long long m = __ballot(d);
-    int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    if (lane == 0) s_warp[w] = __popcll(m);
-    __syncthreads();
-    int before = s_count;
-    for (int q = 0; q < w; ++q) before += s_warp[q];
-    if (d) {
-      r.items[before + __popcll(m & ((1ull << lane) - 1ull))] = make_int2(0, b);
-      r.dirty[b] = 0;
-    }
-    __syncthreads();
-    if (threadIdx.x == 0) s_count += s_warp[0] + s_warp[1] + s_warp[2] + s_warp[3];
-    __syncthreads();
-  }
-  if (threadIdx.x == 0) {
-    *r.nitems = s_count;
-    *r.dirty_total += s_count;
+// dirty blocks -> work items (any order: every accumulation is an integer sum), then clear the flags
+__global__ void k_dirty_items(RoundState r, int nblk) {
+  for (int b = blockIdx.x * blockDim.x + threadIdx.x; b < nblk; b += gridDim.x * blockDim.x) {
+    if (!r.dirty[b]) continue;
+    r.dirty[b] = 0;
+    const unsigned long long active = __ballot(1);
+    const int lane = (int)__lane_id(), leader = __ffsll((long long)active) - 1;
+    int base = 0;
+    if (lane == leader) base = atomicAdd(r.nitems, __popcll(active));
+    base = __shfl(base, leader);
+    r.items[base + __popcll(active & ((1ull << lane) - 1ull))] = make_int2(0, b);
   }
 }
 
 __global__ void k_round_end(RoundState r) {
   if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  *r.dirty_total += *r.nitems;
   const int nsel = *r.nsel;
   for (int k = 0; k < nsel; ++k) r.selpos[r.sel[k]] = -1;
   *r.ns_cur = r.new_desc->ns;
@@ -202,11 +239,13 @@ hipError_t launch_round_front(const RoundState& r, const ShapeArgs& a, const int
   hipLaunchKernelGGL(k_round_begin, dim3(1), dim3(64), 0, s, r);
   hipLaunchKernelGGL(k_select, dim3(1), dim3(256), 0, s, r, a.cell_chi, a.cell_np, cell_b0);
   const size_t cap = (size_t)a.N.mask + 1;
-  hipLaunchKernelGGL(k_ref_tet, dim3(gsz(cap)), dim3(256), 0, s, a.N, a.node_st, r);
-  hipLaunchKernelGGL(k_pick_tet, dim3(gsz(cap)), dim3(256), 0, s, a.N, a.node_st, parent, cell_b0, r);
-  hipLaunchKernelGGL(k_insert, dim3(1), dim3(64), 0, s, r, (float4*)a.site);
+  const int scan = std::min(gsz(cap), SCAN_BLOCKS);
+  hipLaunchKernelGGL(k_ref_tet, dim3(scan), dim3(256), sizeof(int) * r.max_insert, s, a.N, a.node_st, r);
+  hipLaunchKernelGGL(k_pick_tet, dim3(scan), dim3(256), sizeof(unsigned long long) * r.max_insert, s, a.N, a.node_st,
+                     parent, cell_b0, r);
+  hipLaunchKernelGGL(k_insert, dim3(1), dim3(1024), 0, s, r, (float4*)a.site);
   hipLaunchKernelGGL(k_mark_dirty, dim3(gsz(nt)), dim3(256), 0, s, r, tp, nt, a.site, a.tet_U);
-  hipLaunchKernelGGL(k_dirty_items, dim3(1), dim3(256), 0, s, r, nblk);
+  hipLaunchKernelGGL(k_dirty_items, dim3(gsz(nblk)), dim3(256), 0, s, r, nblk);
   return hipGetLastError();
 }
 

@@ -113,6 +113,7 @@ def invariants(meshes, sites, tuned):
 
     res = rpd.build(meshes, sites, block=tuned["block"], clip_budget=tuned["clip_budget"])
     worst_vol, bad = 0.0, 0
+    medial = {"chi_mismatch_after_thinning": 0, "thin_ms": 0.0, "tets_left": 0}
     for k, m in enumerate(meshes):
         info = m.info()
         _, chi = res.euler(k, rpd.RPD_CELL)
@@ -124,7 +125,19 @@ def invariants(meshes, sites, tuned):
         worst_vol = max(worst_vol, abs(vol.sum() - info["volume"]) / info["volume"])
         additive = int(chi.sum()) - int(fchi.sum()) + int(echi.sum()) - nrpv == info["euler"]
         bad += int(not additive) + int(np.any(b0[vol > 0] < 1))
-    return {"volume_partition_rel_err_max": worst_vol, "shapes_failing_euler_or_beta0": bad, "shapes": len(meshes)}
+        # dual medial mesh and its thinning (host), sigma 0.3: the removals keep the medial chi
+        (V, E, F, T), mchi = res.medial_euler(k)
+        if k == 0:
+            medial.update(V=V, E=E, F=F, T=T, chi=mchi)
+        _, alpha = res.edge_geometry(k)
+        t0 = time.perf_counter()
+        ke, kf, kt = rpd.thin(len(chi), res.adjacency(k, rpd.RPD_FACE), res.adjacency(k, rpd.RPD_EDGE), alpha,
+                              res.adjacency(k, rpd.RPD_VERTEX), 0.3)
+        medial["thin_ms"] += 1e3 * (time.perf_counter() - t0)
+        medial["tets_left"] += int(kt.sum())
+        medial["chi_mismatch_after_thinning"] += int(V - int(ke.sum()) + int(kf.sum()) - int(kt.sum()) != mchi)
+    return {"volume_partition_rel_err_max": worst_vol, "shapes_failing_euler_or_beta0": bad, "shapes": len(meshes),
+            "medial": medial}
 
 
 def run_repair(args, prob, table):

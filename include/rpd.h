@@ -155,6 +155,35 @@ rpd_status rpd_geometry(const rpd_result* r, int32_t shape, const double** vol, 
  * (Sec. 3.2, RPC/RPF/RPE/RPV duality). */
 rpd_status rpd_adjacency(const rpd_result* r, int32_t shape, int32_t kind, int64_t* n_out, const int32_t** keys);
 
+/* Length of every RPE (the summed lengths of its pieces' segments) and the importance of its dual medial triangle,
+ * alpha_ijk = |RPE_ijk| / mean diameter 2 r of spheres i, j, k (Sec. 5.3, thinning order). Same order as
+ * rpd_euler(RPD_EDGE); alpha is +inf when all three radii are 0. FP32 path: segment lengths from the FP32 piece
+ * vertices, summed in 2^-56 fixed point (deterministic). Host memory owned by r. */
+rpd_status rpd_edge_geometry(const rpd_result* r, int32_t shape, int64_t* n_out, const double** length,
+                             const double** alpha);
+
+/* The dual medial mesh (Sec. 3.2 duality: cell -> vertex, RPF -> edge, RPE -> triangle, RPV -> tet) is given by the
+ * key lists above; counts = {V, E, F, T} with V the sites whose cell is nonempty, and chi = V - E + F - T (the
+ * medial mesh's Euler characteristic, Sec. 6). counts: room for 4. */
+rpd_status rpd_medial_euler(const rpd_result* r, int32_t shape, int64_t* counts, int64_t* chi);
+
+/* Geometry-guided thinning of a simplicial complex (Sec. 5.3), on host arrays (a sequential greedy process; the
+ * library runs it on the calling thread). Input: n_vertices, and edges (2 ids), triangles (3 ids) with their
+ * importance alpha, tets (4 ids), each simplex's ids strictly ascending and each list sorted lexicographically
+ * (the order rpd_adjacency returns); every face of a listed simplex must be listed. Steps:
+ *   1. while a tet-face simple pair exists (a triangle with exactly one tet left on it), remove the one with the
+ *      least alpha of the triangle (ties: lower triangle index), tet and triangle together;
+ *   2. then, among triangles that were faces of the original tets, while a face-edge simple pair (an edge with
+ *      exactly one triangle left on it, that triangle on no tet) has alpha < sigma, remove the one with the least
+ *      alpha (ties: lower triangle, then lower edge index), triangle and edge together.
+ * Vertices are never removed; every removal keeps the Euler characteristic. Output: keep masks (1 = kept) of
+ * n_edges, n_tris and n_tets bytes, caller-owned; tets that no simple pair could reach stay kept.
+ * Errors: RPD_E_INVALID (unsorted or out-of-range ids, a missing face, NaN alpha or sigma, null arrays),
+ * RPD_E_NOMEM. */
+rpd_status rpd_thin(int32_t n_vertices, int64_t n_edges, const int32_t* edges, int64_t n_tris, const int32_t* tris,
+                    const double* alpha, int64_t n_tets, const int32_t* tets, double sigma, uint8_t* keep_edge,
+                    uint8_t* keep_tri, uint8_t* keep_tet);
+
 /* Counters of the call (summed over shapes). */
 rpd_status rpd_get_stats(const rpd_result* r, rpd_stats* stats);
 

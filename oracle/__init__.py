@@ -49,7 +49,7 @@ class _Result(C.Structure):
         ("face_beta0_skel", C.POINTER(C.c_int32)),
         ("n_edges", C.c_int64), ("edge_keys", C.POINTER(C.c_int32)), ("edge_chi", C.POINTER(C.c_int32)),
         ("edge_chi_asm", C.POINTER(C.c_int32)), ("edge_beta0", C.POINTER(C.c_int32)),
-        ("edge_beta0_skel", C.POINTER(C.c_int32)),
+        ("edge_beta0_skel", C.POINTER(C.c_int32)), ("edge_length", C.POINTER(C.c_double)),
         ("n_rpv", C.c_int64), ("rpv_keys", C.POINTER(C.c_int32)),
         ("max_piece_verts", C.c_int32), ("max_piece_faces", C.c_int32),
     ]
@@ -162,6 +162,7 @@ def rpd(prob, threads: int = 0, assemble: bool = True) -> dict:
             edge_keys=_arr(r.edge_keys, 3 * ne, np.int32, (ne, 3)), edge_chi=_arr(r.edge_chi, ne, np.int32),
             edge_chi_asm=_arr(r.edge_chi_asm, ne, np.int32), edge_beta0=_arr(r.edge_beta0, ne, np.int32),
             edge_beta0_skel=_arr(r.edge_beta0_skel, ne, np.int32),
+            edge_length=_arr(r.edge_length, ne, np.float64),
             rpv_keys=_arr(r.rpv_keys, 4 * nq, np.int32, (nq, 4)),
         )
         return res

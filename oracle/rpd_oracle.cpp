@@ -514,6 +514,7 @@ struct PieceOut {
   i64 chi_cell;
   std::vector<std::pair<int, i64>> face_terms;                 // (j, numerator) for the face on bisector j
   std::vector<std::tuple<int, int, i64>> edge_terms;           // (j, k) j<k, numerator
+  std::vector<long double> edge_len;                          // length of each edge_terms segment
   std::vector<std::array<int, 3>> rpv;                        // (j, k, l) sorted
   std::vector<Glue> glue;
 };
@@ -709,6 +710,9 @@ void analyse_piece(const Ctx& C, int t, int i, const Piece& P, PieceOut& out, st
     i64 w = weight(M, t, P, V[e.u].data(), 3) + weight(M, t, P, V[e.w].data(), 3) - M.L;
     int j = std::min(a.id, b.id), k = std::max(a.id, b.id);
     out.edge_terms.push_back({j, k, w});
+    long double d2 = 0;
+    for (int d = 0; d < 3; ++d) d2 += (X[e.u][d] - X[e.w][d]) * (X[e.u][d] - X[e.w][d]);
+    out.edge_len.push_back(std::sqrt(d2));
   }
   for (int v = 0; v < nv; ++v) {
     const Plane& a = P.planes[V[v][0]];
@@ -1011,6 +1015,7 @@ typedef struct oracle_result {
   int32_t* edge_chi_asm;
   int32_t* edge_beta0;
   int32_t* edge_beta0_skel;
+  double* edge_length;  // summed segment lengths of the RPE's pieces (Sec. 5.3, importance of the dual triangle)
   // RPV quads
   int64_t n_rpv;
   int32_t* rpv_keys;  // 4 per quad
@@ -1102,6 +1107,7 @@ int oracle_rpd(int32_t nv, const float* vx, const float* vy, const float* vz, in
     std::map<std::pair<int, int>, std::array<int, 2>> fcount;
     std::map<std::array<int, 3>, std::array<i64, 3>> enumr;
     std::map<std::array<int, 3>, std::array<int, 3>> ecount;
+    std::map<std::array<int, 3>, std::array<long double, 3>> elen;
     std::map<std::array<int, 4>, int> rpvc;
     for (const auto& p : pcs) {
       for (const auto& ft : p.face_terms) {
@@ -1117,6 +1123,13 @@ int oracle_rpd(int32_t nv, const float* vx, const float* vy, const float* vz, in
         int side = p.i == key[0] ? 0 : (p.i == key[1] ? 1 : 2);
         enumr[key][side] += std::get<2>(et);
         ecount[key][side]++;
+      }
+      for (size_t q = 0; q < p.edge_terms.size(); ++q) {
+        const auto& et = p.edge_terms[q];
+        std::array<int, 3> key = {p.i, std::get<0>(et), std::get<1>(et)};
+        std::sort(key.begin(), key.end());
+        int side = p.i == key[0] ? 0 : (p.i == key[1] ? 1 : 2);
+        elen[key][side] += p.edge_len[q];
       }
       for (const auto& r : p.rpv) {
         std::array<int, 4> key = {p.i, r[0], r[1], r[2]};
@@ -1136,6 +1149,7 @@ int oracle_rpd(int32_t nv, const float* vx, const float* vy, const float* vz, in
       fchi.push_back((int32_t)(kv.second[0] / M.L));
     }
     std::vector<int32_t> ekeys, echi;
+    std::vector<double> elength;
     std::map<std::array<int, 3>, int> eidx;
     for (const auto& kv : enumr) {
       if (kv.second[0] != kv.second[1] || kv.second[0] != kv.second[2])
@@ -1146,6 +1160,11 @@ int oracle_rpd(int32_t nv, const float* vx, const float* vy, const float* vz, in
       eidx[kv.first] = (int)ekeys.size() / 3;
       for (int k = 0; k < 3; ++k) ekeys.push_back(kv.first[k]);
       echi.push_back((int32_t)(kv.second[0] / M.L));
+      // the same segments seen from the three cells: lengths agree up to rounding
+      const auto& l3 = elen[kv.first];
+      for (int sd = 1; sd < 3; ++sd)
+        if (std::fabs(l3[sd] - l3[0]) > 1e-12L * (1 + l3[0])) flag("edge length differs between its sides");
+      elength.push_back((double)l3[0]);
     }
     std::vector<int32_t> rkeys;
     for (const auto& kv : rpvc) {
@@ -1298,6 +1317,7 @@ int oracle_rpd(int32_t nv, const float* vx, const float* vy, const float* vz, in
     R->edge_chi_asm = dup(echi_a);
     R->edge_beta0 = dup(eb0);
     R->edge_beta0_skel = dup(eb0s);
+    R->edge_length = dup(elength);
     R->n_rpv = (int64_t)rkeys.size() / 4;
     R->rpv_keys = dup(rkeys);
     R->status = OK;
@@ -1420,7 +1440,7 @@ void oracle_free(oracle_result* r) {
   void* ptrs[] = {r->cell_chi,   r->cell_chi_asm,    r->cell_beta0,   r->cell_beta0_skel, r->cell_vol,
                   r->cell_cen,   r->cell_npieces,    r->face_keys,    r->face_chi,        r->face_chi_asm,
                   r->face_beta0, r->face_beta0_skel, r->edge_keys,    r->edge_chi,        r->edge_chi_asm,
-                  r->edge_beta0, r->edge_beta0_skel, r->rpv_keys};
+                  r->edge_beta0, r->edge_beta0_skel, r->edge_length, r->rpv_keys};
   for (void* p : ptrs) std::free(p);
   std::free(r);
 }

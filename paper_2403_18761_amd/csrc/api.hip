@@ -79,6 +79,7 @@ struct ShapeOut {
   std::vector<double> vol, cen;
   std::vector<int32_t> face_keys, face_chi, face_b0;
   std::vector<int32_t> edge_keys, edge_chi, edge_b0;
+  std::vector<double> edge_len, edge_alpha;
   std::vector<int32_t> rpv_keys;
   std::vector<int32_t> pc_t, pc_i;
   std::vector<double> pc_geo;
@@ -123,7 +124,7 @@ struct DeviceState {
   unsigned capF = 0, capE = 0, capQ = 0, capN = 0;
   int def_cap = 0, piece_cap = 0;
   DBuf site, status, cell_chi, cell_geo, cell_np, cell_b0;
-  DBuf fkeys, face_chi, face_np, face_b0, ekeys, edge_chi, edge_np, edge_b0, qkeys, rpv_cnt;
+  DBuf fkeys, face_chi, face_np, face_b0, ekeys, edge_chi, edge_np, edge_len, edge_b0, qkeys, rpv_cnt;
   DBuf nkeys, node_st, parent, deferred, deferred2, pieces, counters, tetU, slow, touch;
   int waves = 0;
 
@@ -164,6 +165,7 @@ struct DeviceState {
     ekeys.alloc(8 * (size_t)capE);
     edge_chi.alloc(8 * (size_t)capE);
     edge_np.alloc(4 * (size_t)capE);
+    edge_len.alloc(8 * (size_t)capE);
     edge_b0.alloc(4 * (size_t)capE);
     qkeys.alloc(8 * (size_t)capQ);
     rpv_cnt.alloc(4 * (size_t)capQ);
@@ -194,6 +196,7 @@ struct DeviceState {
     hip_check(launch_fill_u64(ekeys.as<unsigned long long>(), EMPTY_KEY, capE, s), "fill");
     hip_check(launch_fill_u64(edge_chi.as<unsigned long long>(), 0, capE, s), "fill");
     hip_check(launch_fill_i32(edge_np.as<int>(), 0, capE, s), "fill");
+    hip_check(launch_fill_u64(edge_len.as<unsigned long long>(), 0, capE, s), "fill");
     hip_check(launch_fill_u64(qkeys.as<unsigned long long>(), EMPTY_KEY, capQ, s), "fill");
     hip_check(launch_fill_i32(rpv_cnt.as<int>(), 0, capQ, s), "fill");
     hip_check(launch_fill_u64(nkeys.as<unsigned long long>(), EMPTY_KEY, capN, s), "fill");
@@ -228,6 +231,7 @@ struct DeviceState {
     a.E = HashTab{ekeys.as<unsigned long long>(), capE - 1};
     a.edge_chi = edge_chi.as<long long>();
     a.edge_np = edge_np.as<int>();
+    a.edge_len = edge_len.as<long long>();
     a.Q = HashTab{qkeys.as<unsigned long long>(), capQ - 1};
     a.rpv_cnt = rpv_cnt.as<int>();
     a.N = HashTab{nkeys.as<unsigned long long>(), capN - 1};
@@ -345,7 +349,7 @@ static bool collect(DeviceState& D, const std::vector<ShapeDesc>& hd, const Shap
   // one device buffer for everything that goes to the host: RPVs (int4) first, then the int32 and double arrays
   const size_t n_int = 2 * (size_t)ns + 4 * nf + 5 * ne;
   const size_t off_int = 16 * nq, off_dbl = (off_int + 4 * n_int + 7) / 8 * 8;
-  const size_t out_bytes = off_dbl + 8 * 4 * (size_t)ns;
+  const size_t out_bytes = off_dbl + 8 * (4 * (size_t)ns + 2 * ne);
   DBuf out(std::max<size_t>(out_bytes, 16));
   unsigned char* ob = out.as<unsigned char>();
   int* c_chi = (int*)(ob + off_int);
@@ -358,6 +362,8 @@ static bool collect(DeviceState& D, const std::vector<ShapeDesc>& hd, const Shap
   int* e_b0 = e_chi + ne;
   double* c_vol = (double*)(ob + off_dbl);
   double* c_cen = c_vol + ns;
+  double* e_len = c_cen + 3 * (size_t)ns;
+  double* e_alpha = e_len + ne;
 
   const HashTab F{D.fkeys.as<unsigned long long>(), capF - 1}, E{D.ekeys.as<unsigned long long>(), capE - 1};
   if (ns < (1 << 16) && nf < (1u << 31) && ne < (1u << 31)) {
@@ -376,7 +382,8 @@ static bool collect(DeviceState& D, const std::vector<ShapeDesc>& hd, const Shap
                                     D.face_b0.as<int>(), dshapes, nsh, f_keys, f_chi, f_b0, D.status.as<int>(), s),
               "finalize faces");
     hip_check(launch_finalize_edges(ek.as<unsigned long long>(), nullptr, E, (int)ne, D.edge_chi.as<long long>(),
-                                    D.edge_b0.as<int>(), dshapes, nsh, e_keys, e_chi, e_b0, D.status.as<int>(), s),
+                                    D.edge_b0.as<int>(), D.edge_len.as<long long>(), D.site.as<float4>(), dshapes, nsh,
+                                    e_keys, e_chi, e_b0, e_len, e_alpha, D.status.as<int>(), s),
               "finalize edges");
     hip_check(launch_unpack_rpv(kq.as<unsigned long long>(), (int)nq, (int4*)ob, s), "unpack rpv");
   } else {
@@ -393,7 +400,8 @@ static bool collect(DeviceState& D, const std::vector<ShapeDesc>& hd, const Shap
                              vB.as<int>(), (int)ne, s),
               "sort edges");
     hip_check(launch_finalize_edges(kB.as<unsigned long long>(), vB.as<int>(), E, (int)ne, D.edge_chi.as<long long>(),
-                                    D.edge_b0.as<int>(), dshapes, nsh, e_keys, e_chi, e_b0, D.status.as<int>(), s),
+                                    D.edge_b0.as<int>(), D.edge_len.as<long long>(), D.site.as<float4>(), dshapes, nsh,
+                                    e_keys, e_chi, e_b0, e_len, e_alpha, D.status.as<int>(), s),
               "finalize edges");
     hip_check(launch_sort_rpv(rq.as<int4>(), (int)nq, kA.as<unsigned long long>(), kB.as<unsigned long long>(),
                               kC.as<unsigned long long>(), vA.as<int>(), vB.as<int>(), tmp.p, tmpb, (int4*)ob, s),
@@ -425,6 +433,8 @@ static bool collect(DeviceState& D, const std::vector<ShapeDesc>& hd, const Shap
   const int* all_eb0 = all_echi + ne;
   const double* all_vol = (const double*)(hb + off_dbl);
   const double* all_cen = all_vol + ns;
+  const double* all_elen = all_cen + 3 * (size_t)ns;
+  const double* all_ealpha = all_elen + ne;
   // ---- split per shape (element lists are sorted by batch-global keys, so each shape is one contiguous run)
   size_t fpos = 0, epos = 0, qpos = 0;
   for (int k = 0; k < nsh; ++k) {
@@ -450,10 +460,14 @@ static bool collect(DeviceState& D, const std::vector<ShapeDesc>& hd, const Shap
     out.edge_keys.clear();
     out.edge_chi.clear();
     out.edge_b0.clear();
+    out.edge_len.clear();
+    out.edge_alpha.clear();
     while (epos < ne && all_ek[3 * epos] < end) {
       for (int c = 0; c < 3; ++c) out.edge_keys.push_back(all_ek[3 * epos + c] - off);
       out.edge_chi.push_back(all_echi[epos]);
       out.edge_b0.push_back(all_eb0[epos]);
+      out.edge_len.push_back(all_elen[epos]);
+      out.edge_alpha.push_back(all_ealpha[epos]);
       ++epos;
     }
     out.rpv_keys.clear();
@@ -856,6 +870,31 @@ rpd_status rpd_geometry(const rpd_result* r, int32_t shape, const double** vol, 
   if (e) return e;
   if (vol) *vol = r->shapes[shape].vol.data();
   if (centroid) *centroid = r->shapes[shape].cen.data();
+  return RPD_OK;
+}
+
+rpd_status rpd_edge_geometry(const rpd_result* r, int32_t shape, int64_t* n_out, const double** length,
+                             const double** alpha) {
+  rpd_status e = shape_check(r, shape);
+  if (e) return e;
+  if (!n_out) return RPD_E_INVALID;
+  const rpd::ShapeOut& s = r->shapes[shape];
+  *n_out = (int64_t)s.edge_len.size();
+  if (length) *length = s.edge_len.data();
+  if (alpha) *alpha = s.edge_alpha.data();
+  return RPD_OK;
+}
+
+rpd_status rpd_medial_euler(const rpd_result* r, int32_t shape, int64_t* counts, int64_t* chi) {
+  rpd_status e = shape_check(r, shape);
+  if (e) return e;
+  if (!counts) return RPD_E_INVALID;
+  const rpd::ShapeOut& s = r->shapes[shape];
+  counts[0] = (int64_t)std::count_if(s.cell_b0.begin(), s.cell_b0.end(), [](int32_t b) { return b > 0; });
+  counts[1] = (int64_t)s.face_chi.size();
+  counts[2] = (int64_t)s.edge_chi.size();
+  counts[3] = (int64_t)s.rpv_keys.size() / 4;
+  if (chi) *chi = counts[0] - counts[1] + counts[2] - counts[3];
   return RPD_OK;
 }
 

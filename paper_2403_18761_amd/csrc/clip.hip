@@ -157,6 +157,9 @@ __device__ void emit_piece(Clipper<T, Topo, Mask, VCAP, EXACT>& c, const ShapeDe
             if (es >= 0) {
               atomicAdd((unsigned long long*)&a.edge_chi[es], (unsigned long long)(a.sign * ev));
               atomicAdd(&a.edge_np[es], a.sign);
+              const T lx = N.x - C.x, ly = N.y - C.y, lz = N.z - C.z;
+              const double len = (double)sqrt(lx * lx + ly * ly + lz * lz);
+              atomicAdd((unsigned long long*)&a.edge_len[es], (unsigned long long)(a.sign * fixed56(len)));
               int g = ((t1 < 4 && tn[t1] >= 0) ? (1 << t1) : 0) | ((t2 < 4 && tn[t2] >= 0) ? (1 << t2) : 0);
               node_emit(a, node_key(3, es, t), g);
             }

@@ -378,9 +378,11 @@ __global__ void k_finalize_faces(const unsigned long long* keys, const int* slot
     out_b0[q] = b0[s];
   }
 }
+// RPE length (fixed point -> double) and the thinning importance alpha = length / mean diameter of the three spheres
 __global__ void k_finalize_edges(const unsigned long long* keys, const int* slots, HashTab T, int n,
-                                 const long long* chi_num, const int* b0, const ShapeDesc* shapes, int nshapes,
-                                 int* out_keys, int* out_chi, int* out_b0, int* status) {
+                                 const long long* chi_num, const int* b0, const long long* len_num,
+                                 const float4* site, const ShapeDesc* shapes, int nshapes, int* out_keys, int* out_chi,
+                                 int* out_b0, double* out_len, double* out_alpha, int* status) {
   for (int q = blockIdx.x * blockDim.x + threadIdx.x; q < n; q += gridDim.x * blockDim.x) {
     unsigned long long k = keys[q];
     int s = slots ? slots[q] : ht_find(T, k);
@@ -392,6 +394,11 @@ __global__ void k_finalize_edges(const unsigned long long* keys, const int* slot
     if (c % L != 0) atomicOr(status, ST_INTERNAL);
     out_chi[q] = (int)(c / L);
     out_b0[q] = b0[s];
+    const double len = (double)len_num[s] * (1.0 / 72057594037927936.0);  // 2^-56
+    const double dsum = 2.0 * ((double)site[out_keys[3 * q]].w + (double)site[out_keys[3 * q + 1]].w +
+                               (double)site[out_keys[3 * q + 2]].w);
+    out_len[q] = len;
+    out_alpha[q] = dsum > 0.0 ? 3.0 * len / dsum : INFINITY;
   }
 }
 __global__ void k_finalize_cells(int ns, const long long* chi_num, const long long* geo, const int* np, const int* b0,
@@ -419,11 +426,12 @@ hipError_t launch_finalize_faces(const unsigned long long* keys, const int* slot
   return hipGetLastError();
 }
 hipError_t launch_finalize_edges(const unsigned long long* keys, const int* slots, const HashTab& T, int n,
-                                 const long long* chi_num, const int* b0, const ShapeDesc* shapes, int nshapes,
-                                 int* out_keys, int* out_chi, int* out_b0, int* status, hipStream_t s) {
+                                 const long long* chi_num, const int* b0, const long long* len_num,
+                                 const float4* site, const ShapeDesc* shapes, int nshapes, int* out_keys, int* out_chi,
+                                 int* out_b0, double* out_len, double* out_alpha, int* status, hipStream_t s) {
   if (n <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_finalize_edges, dim3(grid_for(n, 256)), dim3(256), 0, s, keys, slots, T, n, chi_num, b0,
-                     shapes, nshapes, out_keys, out_chi, out_b0, status);
+                     len_num, site, shapes, nshapes, out_keys, out_chi, out_b0, out_len, out_alpha, status);
   return hipGetLastError();
 }
 hipError_t launch_finalize_cells(int ns, const long long* chi_num, const long long* geo, const int* np, const int* b0,

@@ -96,6 +96,7 @@ struct ShapeArgs {
   HashTab E;             // edges (i<j<k, global ids < 2^21): key i<<42 | j<<21 | k
   long long* edge_chi;   // [cap E]
   int* edge_np;          // [cap E]
+  long long* edge_len;   // [cap E] summed RPE piece lengths, 2^-56 units
   HashTab Q;             // RPVs (i<j<k<l): key edge slot of (i,j,k) << 21 | l
   int* rpv_cnt;          // [cap Q] (exists while > 0)
   HashTab N;             // element pieces (union-find nodes): kind<<62 | elem<<32 | global tet

@@ -38,8 +38,9 @@ hipError_t launch_finalize_faces(const unsigned long long* keys, const int* slot
                                  const long long* chi_num, const int* b0, const ShapeDesc* shapes, int nshapes,
                                  int* out_keys, int* out_chi, int* out_b0, int* status, hipStream_t s);
 hipError_t launch_finalize_edges(const unsigned long long* keys, const int* slots, const HashTab& T, int n,
-                                 const long long* chi_num, const int* b0, const ShapeDesc* shapes, int nshapes,
-                                 int* out_keys, int* out_chi, int* out_b0, int* status, hipStream_t s);
+                                 const long long* chi_num, const int* b0, const long long* len_num,
+                                 const float4* site, const ShapeDesc* shapes, int nshapes, int* out_keys, int* out_chi,
+                                 int* out_b0, double* out_len, double* out_alpha, int* status, hipStream_t s);
 // three lists of keys whose row (key >> shift) is below rows, sorted ascending in place; tmp[l] holds n[l] keys;
 // off holds 3 (rows + 1) ints, cur 3 rows ints
 hipError_t launch_row_sort(unsigned long long* const keys[3], unsigned long long* const tmp[3], const int n[3],

@@ -97,6 +97,11 @@ def load():
                                  C.POINTER(C.POINTER(C.c_double))]
     lib.rpd_adjacency.argtypes = [C.c_void_p, C.c_int32, C.c_int32, C.POINTER(C.c_int64), C.POINTER(_i32p)]
     lib.rpd_get_stats.argtypes = [C.c_void_p, C.POINTER(_Stats)]
+    lib.rpd_edge_geometry.argtypes = [C.c_void_p, C.c_int32, C.POINTER(C.c_int64), C.POINTER(C.POINTER(C.c_double)),
+                                      C.POINTER(C.POINTER(C.c_double))]
+    lib.rpd_medial_euler.argtypes = [C.c_void_p, C.c_int32, C.POINTER(C.c_int64), C.POINTER(C.c_int64)]
+    lib.rpd_thin.argtypes = [C.c_int32, C.c_int64, _i32p, C.c_int64, _i32p, C.POINTER(C.c_double), C.c_int64, _i32p,
+                             C.c_double, C.POINTER(C.c_uint8), C.POINTER(C.c_uint8), C.POINTER(C.c_uint8)]
     lib.rpd_pieces.argtypes = [C.c_void_p, C.c_int32, C.POINTER(C.c_int64), C.POINTER(_i32p), C.POINTER(_i32p),
                                C.POINTER(C.POINTER(C.c_double)), C.POINTER(C.POINTER(C.c_int64))]
     lib.rpd_free.argtypes = [C.c_void_p]
@@ -115,7 +120,8 @@ def load():
     lib.rpd_session_free.restype = None
     for f in ("rpd_mesh_create", "rpd_mesh_get_info", "rpd_build", "rpd_euler", "rpd_components", "rpd_geometry",
               "rpd_adjacency", "rpd_get_stats", "rpd_pieces", "rpd_session_create", "rpd_session_run",
-              "rpd_session_result", "rpd_session_get_info", "rpd_session_sites", "rpd_autotune"):
+              "rpd_session_result", "rpd_session_get_info", "rpd_session_sites", "rpd_autotune",
+              "rpd_edge_geometry", "rpd_medial_euler", "rpd_thin"):
         getattr(lib, f).restype = C.c_int32
     _lib = lib
     return lib
@@ -220,6 +226,23 @@ class Result:
             return np.zeros((0, width), np.int32)
         return np.ctypeslib.as_array(keys, shape=(n.value * width,)).copy().reshape(-1, width)
 
+    def edge_geometry(self, shape: int):
+        """(length, alpha) of every RPE, in the order of euler(shape, RPD_EDGE)."""
+        n = C.c_int64()
+        ln, al = C.POINTER(C.c_double)(), C.POINTER(C.c_double)()
+        _check(self._lib.rpd_edge_geometry(self._h, shape, C.byref(n), C.byref(ln), C.byref(al)))
+        if n.value == 0:
+            return np.zeros(0), np.zeros(0)
+        return (np.ctypeslib.as_array(ln, shape=(n.value,)).copy(),
+                np.ctypeslib.as_array(al, shape=(n.value,)).copy())
+
+    def medial_euler(self, shape: int):
+        """((V, E, F, T), chi) of the dual medial mesh."""
+        counts = (C.c_int64 * 4)()
+        chi = C.c_int64()
+        _check(self._lib.rpd_medial_euler(self._h, shape, counts, C.byref(chi)))
+        return tuple(int(c) for c in counts), int(chi.value)
+
     def stats(self) -> dict:
         s = _Stats()
         _check(self._lib.rpd_get_stats(self._h, C.byref(s)))
@@ -281,6 +304,24 @@ def autotune(meshes, sites, flags: int = 0, stream=None) -> dict:
     best = _Opts()
     _check(lib.rpd_autotune(handles, st, n, C.byref(o), C.byref(best)))
     return {"block": best.block, "clip_budget": best.clip_budget}
+
+
+def thin(n_vertices: int, edges, tris, alpha, tets, sigma: float):
+    """rpd_thin on host arrays: returns the keep masks (edges, triangles, tets) as bool arrays."""
+    lib = load()
+    e = np.ascontiguousarray(np.asarray(edges, np.int32).reshape(-1, 2))
+    f = np.ascontiguousarray(np.asarray(tris, np.int32).reshape(-1, 3))
+    t = np.ascontiguousarray(np.asarray(tets, np.int32).reshape(-1, 4))
+    a = np.ascontiguousarray(np.asarray(alpha, np.float64).reshape(-1))
+    if a.shape[0] != f.shape[0]:
+        raise ValueError("alpha needs one value per triangle")
+    ke, kf, kt = (np.zeros(max(x.shape[0], 1), np.uint8) for x in (e, f, t))
+    i32 = lambda x: x.ctypes.data_as(_i32p)
+    u8 = lambda x: x.ctypes.data_as(C.POINTER(C.c_uint8))
+    _check(lib.rpd_thin(int(n_vertices), e.shape[0], i32(e), f.shape[0], i32(f),
+                        a.ctypes.data_as(C.POINTER(C.c_double)), t.shape[0], i32(t), float(sigma), u8(ke), u8(kf),
+                        u8(kt)))
+    return ke[:e.shape[0]].astype(bool), kf[:f.shape[0]].astype(bool), kt[:t.shape[0]].astype(bool)
 
 
 def version() -> str:

@@ -24,13 +24,14 @@ def run_gpu(prob, precision=0, clip_budget=0, block=0, flags=0, device_ptrs=True
     out = extract(res, 0)
     out["stats"] = res.stats()
     out["mesh_info"] = mesh.info()
+    out["radii"] = np.asarray(prob.sr, np.float64)
     if flags & rpd.RPD_KEEP_PIECES:
         out["pieces"] = res.pieces(0)
     return out
 
 
 ELEMENT_ARRAYS = ("cell_chi", "cell_beta0", "face_keys", "face_chi", "face_beta0", "edge_keys", "edge_chi",
-                  "edge_beta0", "rpv_keys", "cell_vol", "cell_cen")
+                  "edge_beta0", "rpv_keys", "cell_vol", "cell_cen", "edge_len", "edge_alpha", "medial")
 
 
 def extract(res, k):
@@ -46,6 +47,9 @@ def extract(res, k):
     _, out["edge_beta0"] = res.components(k, rpd.RPD_EDGE)
     out["rpv_keys"] = res.adjacency(k, rpd.RPD_VERTEX)
     out["cell_vol"], out["cell_cen"] = res.geometry(k)
+    out["edge_len"], out["edge_alpha"] = res.edge_geometry(k)
+    counts, chi = res.medial_euler(k)
+    out["medial"] = np.array([*counts, chi], np.int64)  # V, E, F, T, chi of the dual medial mesh
     return out
 
 
@@ -74,6 +78,25 @@ def assert_parity(g, r, vol_rtol=1e-5, label=""):
     err = np.abs(g["cell_cen"][ne] - r["cell_cen"][ne]).max(axis=1, initial=0.0)
     bound = 4 * (vol_rtol + atol / vr[ne])
     assert np.all(err < bound), (label, err.max(initial=0.0), (err / bound).max(initial=0.0))
+    # RPE lengths: a segment's endpoint is where the line of two bisector planes crosses a third plane; the planes
+    # are rounded to the working precision, so the endpoint errs by u |x| / sin(angle of line and plane), and
+    # shallow crossings amplify u = 6e-8 (FP32) by 10^2..10^3 where the volumes, integrals over the piece, average
+    # it out. Lengths are held to 10x the volume tolerance (FP32: 1e-4 relative, 1e-5 absolute; FP64: 1e-8, 1e-9).
+    len_rtol, len_atol = 10 * vol_rtol, vol_rtol
+    np.testing.assert_allclose(g["edge_len"], r["edge_length"], rtol=len_rtol, atol=len_atol,
+                               err_msg=f"{label} RPE lengths")
+    from oracle import medial
+
+    counts, chi = medial.medial_counts(r)
+    np.testing.assert_array_equal(g["medial"], [*counts, chi], err_msg=f"{label} medial mesh counts")
+    if "radii" in g:
+        a_ref = medial.edge_alpha(r["edge_length"], r["edge_keys"], g["radii"])
+        d = 2.0 * g["radii"][r["edge_keys"]].mean(axis=1) if len(a_ref) else np.zeros(0)
+        tol = len_rtol * np.abs(a_ref) + len_atol / np.maximum(d, 1e-30)  # the length's tolerance over d
+        finite = np.isfinite(a_ref)
+        np.testing.assert_array_equal(np.isfinite(g["edge_alpha"]), finite, err_msg=f"{label} RPE importance")
+        err = np.abs(g["edge_alpha"][finite] - a_ref[finite])
+        assert np.all(err <= tol[finite]), (label, "RPE importance", (err / tol[finite]).max(initial=0.0))
 
 
 def log(*a):
@@ -99,5 +122,6 @@ def run_gpu_batch(probs, precision=0, flags=0):
     for k in range(len(probs)):
         out = extract(res, k)
         out["mesh_info"] = meshes[k].info()
+        out["radii"] = np.asarray(probs[k].sr, np.float64)
         outs.append(out)
     return outs, res.stats()

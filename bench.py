@@ -63,6 +63,9 @@ WORKLOADS = {
                         "20000 sites, 30% within 0.02 of sharp edges", cpu_frac=0.002),
     "batch256": dict(desc="256 seeded shapes (tori, box unions, metaballs), log-uniform 5k-200k tets and 100-5k sites "
                           "each, one rpd_build call", cpu_frac=0.002),
+    "envelope": dict(desc="geometric-error metric: distance from 1M surface samples of the torus2000 shape to the "
+                          "enveloping spheres, cones and slabs of its thinned (sigma 0.3) dual medial mesh",
+                     cpu_frac=0.0005),
     "repair": dict(desc="topology repair: 5 metaball blobs joined by thin handles (genus 2), 128^3 grid, 975462 Kuhn "
                         "tets, 500 initial sites, up to 64 insertions per round from a per-tet sphere table, one "
                         "captured graph per round (a step is one round)", cpu_frac=0.002),
@@ -80,6 +83,8 @@ def workload(name):
         return synth.batch_problems(256, 4)
     if name == "repair":
         return [synth.repair_problem(N=128, n_sites=500, seed=5)]
+    if name == "envelope":
+        return [synth.torus_inside(N=64, n_sites=2000, seed=2)]
     raise SystemExit(f"unknown workload {name}")
 
 
@@ -190,6 +195,67 @@ def run_repair(args, prob, table):
                        "sites_final": int(s.shape[0])})
 
 
+# Algorithmic FLOPs of one (sample, element) evaluation of the geometric-error kernel: d = q - c (3), then
+# sphere: |d| (5 + sqrt) - r = 10; cone: u = d.axis (5), d x axis (9), |.|^2 (5), sqrt, t = u + c h (2),
+# value (4) = 29; slab: H, g.d, two barycentric dots with their |H| terms (5 + 5 + 7 + 7), value (3) = 30.
+FLOP_SPHERE, FLOP_CONE, FLOP_SLAB = 10, 29, 30
+
+
+def run_envelope(args, prob):
+    """One step = one rpd_envelope_distance call over every sample (inputs resident on the device; distances only,
+    as the insertion test of Sec. 4.3 uses); value = sample-element evaluations per second."""
+    import torch
+
+    from paper_2403_18761_amd import rpd, synth
+
+    dev = torch.device("cuda:0")
+
+    def t(a, dt=torch.float32):
+        return torch.as_tensor(np.ascontiguousarray(a), dtype=dt, device=dev)
+
+    mesh = rpd.Mesh(t(prob.vx), t(prob.vy), t(prob.vz), t(prob.tv.reshape(-1), torch.int32))
+    res = rpd.build([mesh], [(t(prob.sx), t(prob.sy), t(prob.sz), t(prob.sr))])
+    S, E, F = res.medial_mesh(0, np.stack([prob.sx, prob.sy, prob.sz, prob.sr], axis=1), 0.3)
+    q = synth.surface_samples(prob, 1_000_000, seed=4)
+    dS, dE, dF, dq = t(S), t(E, torch.int32), t(F, torch.int32), t(q)
+    for _ in range(args.warmup):
+        rpd.envelope_distance(dS, dE, dF, dq, nearest=False)
+    torch.cuda.synchronize()
+    kms = []
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        d, _, k = rpd.envelope_distance(dS, dE, dF, dq, timing=True, nearest=False)
+        kms.append(k)
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3 / args.steps
+    kernel_ms = float(np.mean(kms))
+    n_el = len(S) + len(E) + len(F)
+    flops = len(q) * (FLOP_SPHERE * len(S) + FLOP_CONE * len(E) + FLOP_SLAB * len(F))
+    achieved = flops / (kernel_ms * 1e-3) / 1e12
+    print(f"# envelope: {len(S)} spheres {len(E)} cones {len(F)} slabs, {len(q)} samples: {ms:.3f} ms/call, "
+          f"kernel {kernel_ms:.3f} ms, {achieved:.1f} TFLOP/s", file=sys.stderr, flush=True)
+    dist = d.cpu().numpy()
+    return dict(value=len(q) * n_el / (ms * 1e-3), ms_per_step=ms, kernel_ms=kernel_ms, achieved=achieved,
+                counts=dict(spheres=len(S), cones=len(E), slabs=len(F), samples=len(q)),
+                checks=dict(finite=bool(np.all(np.isfinite(dist))), max_over_diag=float(dist.max() / np.sqrt(12.0)),
+                            mean=float(dist.mean())),
+                elements=(S, E, F), samples=q)
+
+
+def cpu_baseline_envelope(S, E, F, q, frac):
+    import oracle.envelope as env
+
+    rng = np.random.default_rng(0)
+    pick = rng.choice(len(q), max(1, int(frac * len(q))), replace=False)
+    t0 = time.perf_counter()
+    env.envelope_distance(S, E, F, q[pick])
+    dt = time.perf_counter() - t0
+    n_el = len(S) + len(E) + len(F)
+    return dict(value=len(pick) * n_el / dt, unit="evaluations/s", cores=1, kind="oracle",
+                sample=f"{len(pick)} of {len(q)} samples (random, seed 0) against all {n_el} elements, FP64 numpy "
+                       f"in {dt:.2f} s")
+
+
 def cpu_baseline(probs, frac):
     """The oracle (brute force over all sites, exact predicates) on a random sample of every shape's tets;
     clips/sec on the host."""
@@ -254,6 +320,25 @@ def main():
         probs, table = [probs[0][0]], probs[0][1]
     print(f"# workload {args.workload}: {len(probs)} shape(s), {sum(p.n_tets for p in probs)} tets, "
           f"{sum(p.n_sites for p in probs)} sites", file=sys.stderr, flush=True)
+    if args.workload == "envelope":
+        r = run_envelope(args, probs[0])
+        line = {
+            "metric": "sample-element distance evaluations/sec of the geometric-error metric, 1 MI355X",
+            "value": r["value"], "unit": "evaluations/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+            "ms_per_step": r["ms_per_step"], "higher_is_better": True, "scaling": "strong", "vs_baseline": None,
+            "dtype": "f32", "data": "synthetic",
+            "config": {"workload": WORKLOADS[args.workload]["desc"], "name": args.workload, **r["counts"]},
+            "roofline": {"bound": "alu", "achieved": r["achieved"], "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
+                         "frac": r["achieved"] / PEAK_FP32_TFLOPS, "traffic": None, "kernel": "k_env_dist",
+                         "kernel_ms": r["kernel_ms"],
+                         "flop_per_evaluation": {"sphere": FLOP_SPHERE, "cone": FLOP_CONE, "slab": FLOP_SLAB}},
+            "checks": r["checks"],
+        }
+        if not args.no_cpu_baseline:
+            frac = args.cpu_frac if args.cpu_frac is not None else WORKLOADS[args.workload]["cpu_frac"]
+            line["cpu_baseline"] = cpu_baseline_envelope(*r["elements"], r["samples"], frac)
+        print(json.dumps(line), flush=True)
+        return
     if args.workload == "repair":
         r = run_repair(args, probs[0], table)
         line = {

@@ -184,6 +184,24 @@ rpd_status rpd_thin(int32_t n_vertices, int64_t n_edges, const int32_t* edges, i
                     const double* alpha, int64_t n_tets, const int32_t* tets, double sigma, uint8_t* keep_edge,
                     uint8_t* keep_tri, uint8_t* keep_tet);
 
+/* Distance from surface samples to the enveloping volume of a medial mesh (Sec. 4.3, geometric preservation; the
+ * enveloping elements of Sec. 3.2: a vertex's sphere, an edge's medial cone, a triangle's medial slab, i.e. the
+ * spheres interpolated linearly over the simplex). For sample q and element e with spheres B(c(t), r(t)):
+ * value_e(q) = min over t of |q - c(t)| - r(t), the distance to e's volume when q is outside it (negative inside);
+ * dist[s] = min over all elements, nearest[s] = the element reaching it (ties: lowest id), ids numbered spheres
+ * 0..n_spheres-1, then edges, then triangles. No element: dist = +inf, nearest = -1.
+ * spheres: 4 floats per sphere (x, y, z, r); edges: 2 sphere ids each; tris: 3 sphere ids each; every face of a
+ * listed edge or triangle must be listed too (an element is evaluated at its interior stationary point and leaves
+ * its boundary to those faces, which is exact for a closed complex such as the output of rpd_thin).
+ * samples: 3 floats per sample. With RPD_DEVICE_PTRS in flags every array (inputs and outputs) is device memory
+ * and the call runs on stream (NULL = the null stream); otherwise host memory. nearest may be NULL. FP32
+ * arithmetic (element constants rounded from FP64). kernel_ms (host, may be NULL): HIP-event time of the distance
+ * kernel on that stream. Synchronises the stream.
+ * Errors: RPD_E_INVALID (negative count, null array, sphere id out of range), RPD_E_NOMEM, RPD_E_DEVICE. */
+rpd_status rpd_envelope_distance(const float* spheres, int32_t n_spheres, const int32_t* edges, int64_t n_edges,
+                                 const int32_t* tris, int64_t n_tris, const float* samples, int64_t n_samples,
+                                 uint32_t flags, void* stream, float* dist, int32_t* nearest, float* kernel_ms);
+
 /* Counters of the call (summed over shapes). */
 rpd_status rpd_get_stats(const rpd_result* r, rpd_stats* stats);
 

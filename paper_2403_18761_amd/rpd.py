@@ -100,6 +100,9 @@ def load():
     lib.rpd_edge_geometry.argtypes = [C.c_void_p, C.c_int32, C.POINTER(C.c_int64), C.POINTER(C.POINTER(C.c_double)),
                                       C.POINTER(C.POINTER(C.c_double))]
     lib.rpd_medial_euler.argtypes = [C.c_void_p, C.c_int32, C.POINTER(C.c_int64), C.POINTER(C.c_int64)]
+    lib.rpd_envelope_distance.argtypes = [C.c_void_p, C.c_int32, C.c_void_p, C.c_int64, C.c_void_p, C.c_int64,
+                                          C.c_void_p, C.c_int64, C.c_uint32, C.c_void_p, C.c_void_p, C.c_void_p,
+                                          C.POINTER(C.c_float)]
     lib.rpd_thin.argtypes = [C.c_int32, C.c_int64, _i32p, C.c_int64, _i32p, C.POINTER(C.c_double), C.c_int64, _i32p,
                              C.c_double, C.POINTER(C.c_uint8), C.POINTER(C.c_uint8), C.POINTER(C.c_uint8)]
     lib.rpd_pieces.argtypes = [C.c_void_p, C.c_int32, C.POINTER(C.c_int64), C.POINTER(_i32p), C.POINTER(_i32p),
@@ -121,7 +124,7 @@ def load():
     for f in ("rpd_mesh_create", "rpd_mesh_get_info", "rpd_build", "rpd_euler", "rpd_components", "rpd_geometry",
               "rpd_adjacency", "rpd_get_stats", "rpd_pieces", "rpd_session_create", "rpd_session_run",
               "rpd_session_result", "rpd_session_get_info", "rpd_session_sites", "rpd_autotune",
-              "rpd_edge_geometry", "rpd_medial_euler", "rpd_thin"):
+              "rpd_edge_geometry", "rpd_medial_euler", "rpd_thin", "rpd_envelope_distance"):
         getattr(lib, f).restype = C.c_int32
     _lib = lib
     return lib
@@ -243,6 +246,23 @@ class Result:
         _check(self._lib.rpd_medial_euler(self._h, shape, counts, C.byref(chi)))
         return tuple(int(c) for c in counts), int(chi.value)
 
+    def medial_mesh(self, shape: int, xyzr, sigma: float | None = 0.3):
+        """The dual medial mesh of one shape as enveloping elements: spheres (V, 4) of the sites whose cell is
+        nonempty (xyzr: the shape's sites, (n, 4)), edges (E, 2) and triangles (F, 3) indexing those spheres, after
+        rpd_thin with this sigma (None: unthinned; medial tets have no enveloping element and are dropped)."""
+        xyzr = np.asarray(xyzr, np.float32).reshape(-1, 4)
+        _, b0 = self.components(shape, RPD_CELL)
+        e = self.adjacency(shape, RPD_FACE)
+        f = self.adjacency(shape, RPD_EDGE)
+        if sigma is not None:
+            _, alpha = self.edge_geometry(shape)
+            ke, kf, _ = thin(len(b0), e, f, alpha, self.adjacency(shape, RPD_VERTEX), sigma)
+            e, f = e[ke], f[kf]
+        live = np.flatnonzero(b0 > 0)
+        remap = np.full(len(b0), -1, np.int32)
+        remap[live] = np.arange(len(live), dtype=np.int32)
+        return xyzr[live], remap[e], remap[f]
+
     def stats(self) -> dict:
         s = _Stats()
         _check(self._lib.rpd_get_stats(self._h, C.byref(s)))
@@ -322,6 +342,43 @@ def thin(n_vertices: int, edges, tris, alpha, tets, sigma: float):
                         a.ctypes.data_as(C.POINTER(C.c_double)), t.shape[0], i32(t), float(sigma), u8(ke), u8(kf),
                         u8(kt)))
     return ke[:e.shape[0]].astype(bool), kf[:f.shape[0]].astype(bool), kt[:t.shape[0]].astype(bool)
+
+
+def envelope_distance(spheres, edges, tris, samples, stream=None, timing: bool = False, nearest: bool = True):
+    """rpd_envelope_distance: distance from each sample to the enveloping volume of a medial mesh.
+
+    spheres (n, 4) float32 (x, y, z, r); edges (m, 2) and tris (k, 3) int32 sphere ids; samples (s, 3) float32.
+    CUDA tensors run on the device (outputs are tensors on that device); numpy arrays go through host memory.
+    Returns (dist float32 [s], nearest int32 [s] or None when not asked for), plus the distance kernel's HIP-event
+    ms when timing is set."""
+    lib = load()
+    kms = C.c_float(0.0)
+    kptr = C.byref(kms) if timing else None
+    if _is_torch(samples) and samples.is_cuda:
+        import torch
+
+        dev = samples.device
+        sp = spheres.to(dev, torch.float32).contiguous().reshape(-1, 4)
+        ed = edges.to(dev, torch.int32).contiguous().reshape(-1, 2)
+        tr = tris.to(dev, torch.int32).contiguous().reshape(-1, 3)
+        q = samples.to(torch.float32).contiguous().reshape(-1, 3)
+        dist = torch.empty(q.shape[0], dtype=torch.float32, device=dev)
+        near = torch.empty(q.shape[0], dtype=torch.int32, device=dev) if nearest else None
+        ptr = lambda t: C.c_void_p(t.data_ptr() if t is not None and t.numel() else 0)
+        st = _stream_ptr(stream) if stream is not None else C.c_void_p(torch.cuda.current_stream(dev).cuda_stream)
+        _check(lib.rpd_envelope_distance(ptr(sp), sp.shape[0], ptr(ed), ed.shape[0], ptr(tr), tr.shape[0], ptr(q),
+                                         q.shape[0], RPD_DEVICE_PTRS, st, ptr(dist), ptr(near), kptr))
+        return (dist, near, kms.value) if timing else (dist, near)
+    sp = np.ascontiguousarray(np.asarray(spheres, np.float32).reshape(-1, 4))
+    ed = np.ascontiguousarray(np.asarray(edges, np.int32).reshape(-1, 2))
+    tr = np.ascontiguousarray(np.asarray(tris, np.int32).reshape(-1, 3))
+    q = np.ascontiguousarray(np.asarray(samples, np.float32).reshape(-1, 3))
+    dist = np.empty(q.shape[0], np.float32)
+    near = np.empty(q.shape[0], np.int32) if nearest else None
+    ptr = lambda a: C.c_void_p(a.ctypes.data if a is not None and a.size else 0)
+    _check(lib.rpd_envelope_distance(ptr(sp), sp.shape[0], ptr(ed), ed.shape[0], ptr(tr), tr.shape[0], ptr(q),
+                                     q.shape[0], 0, _stream_ptr(stream), ptr(dist), ptr(near), kptr))
+    return (dist, near, kms.value) if timing else (dist, near)
 
 
 def version() -> str:

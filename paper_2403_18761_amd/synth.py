@@ -697,3 +697,32 @@ def tiny_two_tets() -> tuple:
     v = np.array([[0, 0, 0], [0.5, 0, 0], [0, 0.5, 0], [0, 0, 0.5], [0.25, 0.25, -0.5]], dtype=np.float64)
     tv = np.array([[0, 1, 2, 3], [0, 2, 1, 4]], dtype=np.int32)
     return v.astype(np.float32), tv
+
+
+# ----------------------------------------------------------------------------------------------------------------
+# surface samples (inputs of the geometric-error metric)
+# ----------------------------------------------------------------------------------------------------------------
+
+def boundary_triangles(prob: Problem) -> np.ndarray:
+    """Faces of the tet mesh that belong to one tet only (the surface), as (m, 3) vertex ids."""
+    tv = np.asarray(prob.tv).reshape(-1, 4)
+    faces = np.concatenate([tv[:, [1, 2, 3]], tv[:, [0, 2, 3]], tv[:, [0, 1, 3]], tv[:, [0, 1, 2]]])
+    key = np.sort(faces, axis=1)
+    uniq, inv, cnt = np.unique(key, axis=0, return_inverse=True, return_counts=True)
+    return uniq[cnt == 1]
+
+
+def surface_samples(prob: Problem, n: int, seed: int) -> np.ndarray:
+    """n points uniformly distributed over the surface of the tet mesh (area-weighted triangles, uniform
+    barycentric), float32 (n, 3)."""
+    rng = np.random.default_rng(seed)
+    tri = boundary_triangles(prob)
+    P = np.stack([prob.vx, prob.vy, prob.vz], axis=1).astype(np.float64)
+    a, b, c = P[tri[:, 0]], P[tri[:, 1]], P[tri[:, 2]]
+    area = 0.5 * np.linalg.norm(np.cross(b - a, c - a), axis=1)
+    pick = rng.choice(len(tri), size=n, p=area / area.sum())
+    u, v = rng.random(n), rng.random(n)
+    flip = u + v > 1
+    u[flip], v[flip] = 1 - u[flip], 1 - v[flip]
+    q = a[pick] + u[:, None] * (b[pick] - a[pick]) + v[:, None] * (c[pick] - a[pick])
+    return q.astype(np.float32)

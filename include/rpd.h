@@ -64,11 +64,16 @@ typedef int32_t rpd_status;
 #define RPD_FORCE_SLOW_PATH (1u << 3)   /* test-only: send every tet through the large-capacity deferred path */
 #define RPD_TIMING (1u << 4)            /* record per-kernel HIP-event timings into rpd_stats */
 #define RPD_KEEP_PIECES (1u << 5)       /* keep per-piece records (rpd_pieces) for sampled comparisons */
+#define RPD_OWNER_WEIGHTS (1u << 6)     /* rpd_mesh_create: ownership weights even when L / k(sigma) fits (below) */
 
 /*
  * A prepared tet mesh (device resident): vertex/tet arrays, face adjacency, the multiplicity k(sigma) of every
  * vertex, edge and face, the fractional weights L/k(sigma) (Sec. 4.1.2) and a spatial ordering of the tets.
  * Created once and reused by every rpd_build on that mesh (the paper recomputes the RPD many times per model).
+ * Meshes whose lcm L of multiplicities reaches 2^31 (general, non-voxel tet meshes), or any mesh created with
+ * RPD_OWNER_WEIGHTS, use ownership weights instead: a simplex weighs 1 in its owner tet (the lowest caller index
+ * among the tets containing it) and 0 in the others, with L = 1. Both sum to weight 1 per simplex over its tets,
+ * so every chi is the same; only the per-piece numerators differ.
  */
 typedef struct rpd_mesh rpd_mesh;
 
@@ -83,8 +88,10 @@ typedef struct rpd_mesh_info {
   int32_t n_verts, n_tets, n_edges, n_faces;
   int32_t euler;             /* V - E + F - C of the mesh */
   int32_t components;
-  int64_t L;                 /* lcm of all simplex multiplicities: the fixed-point denominator of chi */
+  int64_t L;                 /* lcm of all simplex multiplicities: the fixed-point denominator of chi (1 with
+                                ownership weights) */
   double volume;
+  int32_t owner_weights;     /* 1 if the mesh uses ownership weights */
 } rpd_mesh_info;
 
 typedef struct rpd_sites {

@@ -86,10 +86,11 @@ def _load():
             f32 = C.POINTER(C.c_float)
             i32 = C.POINTER(C.c_int32)
             lib.oracle_rpd.argtypes = [C.c_int32, f32, f32, f32, C.c_int32, i32, C.c_int32, f32, f32, f32, f32,
-                                       C.c_int32, C.c_int32, C.POINTER(C.POINTER(_Result))]
+                                       C.c_int32, C.c_int32, C.c_int32, C.POINTER(C.POINTER(_Result))]
             lib.oracle_rpd.restype = C.c_int
             lib.oracle_tet_pieces.argtypes = [C.c_int32, f32, f32, f32, C.c_int32, i32, C.c_int32, f32, f32, f32,
-                                              f32, C.c_int32, i32, C.c_int32, C.POINTER(C.POINTER(_Pieces))]
+                                              f32, C.c_int32, i32, C.c_int32, C.c_int32,
+                                              C.POINTER(C.POINTER(_Pieces))]
             lib.oracle_tet_pieces.restype = C.c_int
             lib.oracle_side_exact.argtypes = [C.POINTER(C.c_int64)]
             lib.oracle_side_exact.restype = C.c_int
@@ -133,14 +134,15 @@ def _inputs(prob):
     return vx, vy, vz, tv, sx, sy, sz, sr
 
 
-def rpd(prob, threads: int = 0, assemble: bool = True) -> dict:
-    """Whole-shape oracle. Returns numpy arrays; raises OracleError on a non-OK status."""
+def rpd(prob, threads: int = 0, assemble: bool = True, owner_weights: bool = False) -> dict:
+    """Whole-shape oracle. Returns numpy arrays; raises OracleError on a non-OK status. owner_weights forces the
+    ownership weights (used anyway when the lcm of multiplicities reaches 2^31)."""
     lib = _load()
     vx, vy, vz, tv, sx, sy, sz, sr = _inputs(prob)
     out = C.POINTER(_Result)()
     lib.oracle_rpd(len(vx), _ptr(vx, C.c_float), _ptr(vy, C.c_float), _ptr(vz, C.c_float), len(tv) // 4,
                    _ptr(tv, C.c_int32), len(sx), _ptr(sx, C.c_float), _ptr(sy, C.c_float), _ptr(sz, C.c_float),
-                   _ptr(sr, C.c_float), int(threads), int(bool(assemble)), C.byref(out))
+                   _ptr(sr, C.c_float), int(threads), int(bool(assemble)), int(bool(owner_weights)), C.byref(out))
     r = out.contents
     try:
         if r.status != 0:
@@ -170,7 +172,7 @@ def rpd(prob, threads: int = 0, assemble: bool = True) -> dict:
         lib.oracle_free(out)
 
 
-def tet_pieces(prob, tets, threads: int = 0) -> dict:
+def tet_pieces(prob, tets, threads: int = 0, owner_weights: bool = False) -> dict:
     """Per-piece oracle results for the selected tets (each clipped against all sites)."""
     lib = _load()
     vx, vy, vz, tv, sx, sy, sz, sr = _inputs(prob)
@@ -179,7 +181,7 @@ def tet_pieces(prob, tets, threads: int = 0) -> dict:
     lib.oracle_tet_pieces(len(vx), _ptr(vx, C.c_float), _ptr(vy, C.c_float), _ptr(vz, C.c_float), len(tv) // 4,
                           _ptr(tv, C.c_int32), len(sx), _ptr(sx, C.c_float), _ptr(sy, C.c_float),
                           _ptr(sz, C.c_float), _ptr(sr, C.c_float), len(sel), _ptr(sel, C.c_int32), int(threads),
-                          C.byref(out))
+                          int(bool(owner_weights)), C.byref(out))
     r = out.contents
     try:
         if r.status != 0:

@@ -22,6 +22,11 @@
 //     connectivity of the assembled complex.
 //   * volume and centroid of every RPC (Lebesgue measure / first moment over S), FP64.
 //
+//   * Ownership weights (meshes whose lcm of multiplicities reaches 2^31, or on request): each mesh simplex sigma
+//     weighs 1 in its owner tet, the lowest-numbered tet containing it, and 0 in the others, with L = 1. Summed over
+//     the tets around sigma this is the same total weight 1 as k(sigma) times 1/k(sigma), so every element's chi is
+//     unchanged; only its split over the pieces differs.
+//
 // Readings of the paper (where it is silent): weights w(sigma)=1/k(sigma) generalise the 2D example; input is
 // in general position -- any exactly zero predicate is reported as RPD_E_DEGENERATE; empty cells report chi=0,
 // beta0=0, volume 0 and a NaN centroid.
@@ -224,6 +229,8 @@ struct Mesh {
   std::vector<std::array<int, 4>> tface; // global face id of local face f (opposite vertex f)
   std::vector<std::array<int, 4>> tnb;   // neighbour tet across local face f, -1 on the boundary
   std::vector<int> kv, ke, kf;           // k(sigma)
+  std::vector<int> ov, oe, of;           // owner tet of each vertex, edge, face (ownership weights)
+  bool own = false;                      // ownership weights instead of L / k(sigma)
   int n_edges = 0, n_faces = 0, n_used_verts = 0;
   i64 L = 1;
   int chi = 0;
@@ -255,7 +262,8 @@ void unite(std::vector<int>& p, int a, int b) {
   p[a] = b;
 }
 
-Mesh build_mesh(int nv, const float* vx, const float* vy, const float* vz, int nt, const int32_t* tv) {
+Mesh build_mesh(int nv, const float* vx, const float* vy, const float* vz, int nt, const int32_t* tv,
+                bool force_owner) {
   Mesh m;
   if (nv <= 0 || nt <= 0) throw Failure{E_INVALID, "empty mesh"};
   m.nv = nv;
@@ -343,9 +351,11 @@ Mesh build_mesh(int nv, const float* vx, const float* vy, const float* vz, int n
   }
   int used = 0;
   i64 L = 1;
+  bool big = false;
   auto upd = [&](i64 k) {
+    if (big) return;
     L = L / gcd64(L, k) * k;
-    if (L > ((i64)1 << 40)) throw Failure{E_MESH, "lcm of simplex multiplicities too large"};
+    if (L >= ((i64)1 << 31)) big = true;
   };
   for (int v = 0; v < nv; ++v)
     if (m.kv[v] > 0) {
@@ -354,7 +364,21 @@ Mesh build_mesh(int nv, const float* vx, const float* vy, const float* vz, int n
     }
   for (int k : m.ke) upd(k);
   for (int k : m.kf) upd(k);
-  m.L = L;
+  m.own = force_owner || big;
+  m.L = m.own ? 1 : L;
+  if (m.own) {  // owner = lowest tet index containing the simplex
+    m.ov.assign(nv, -1);
+    m.oe.assign(m.n_edges, -1);
+    m.of.assign(m.n_faces, -1);
+    for (int t = 0; t < nt; ++t) {
+      for (int k = 0; k < 4; ++k)
+        if (m.ov[m.tv[t][k]] < 0) m.ov[m.tv[t][k]] = t;
+      for (int e = 0; e < 6; ++e)
+        if (m.oe[m.tedge[t][e]] < 0) m.oe[m.tedge[t][e]] = t;
+      for (int f = 0; f < 4; ++f)
+        if (m.of[m.tface[t][f]] < 0) m.of[m.tface[t][f]] = t;
+    }
+  }
   m.n_used_verts = used;
   m.chi = used - m.n_edges + m.n_faces - nt;
   std::vector<int> par(nt);
@@ -564,15 +588,19 @@ i64 weight(const Mesh& M, int t, const Piece& P, const int* pl, int np) {
   for (int k = 0; k < np; ++k)
     if (P.planes[pl[k]].kind == 0) faces[nf++] = P.planes[pl[k]].id;
   if (nf == 0) return M.L;
-  if (nf == 1) return M.L / M.kf[M.tface[t][faces[0]]];
+  if (nf == 1) {
+    const int f = M.tface[t][faces[0]];
+    return M.own ? (M.of[f] == t) : M.L / M.kf[f];
+  }
   if (nf == 2) {
     int vs[2], c = 0;
     for (int v = 0; v < 4; ++v)
       if (v != faces[0] && v != faces[1]) vs[c++] = v;
-    return M.L / M.ke[M.tedge[t][local_edge(vs[0], vs[1])]];
+    const int e = M.tedge[t][local_edge(vs[0], vs[1])];
+    return M.own ? (M.oe[e] == t) : M.L / M.ke[e];
   }
   int v = 6 - faces[0] - faces[1] - faces[2];
-  return M.L / M.kv[M.tv[t][v]];
+  return M.own ? (M.ov[M.tv[t][v]] == t) : M.L / M.kv[M.tv[t][v]];
 }
 
 // Everything the oracle derives from one nonempty piece.
@@ -1050,11 +1078,11 @@ void oracle_pieces_free(oracle_pieces* r);
 
 int oracle_rpd(int32_t nv, const float* vx, const float* vy, const float* vz, int32_t nt, const int32_t* tv,
                int32_t ns, const float* sx, const float* sy, const float* sz, const float* sr, int32_t nthreads,
-               int32_t assemble, oracle_result** out) {
+               int32_t assemble, int32_t owner_weights, oracle_result** out) {
   oracle_result* R = (oracle_result*)std::calloc(1, sizeof(oracle_result));
   *out = R;
   try {
-    Mesh M = build_mesh(nv, vx, vy, vz, nt, tv);
+    Mesh M = build_mesh(nv, vx, vy, vz, nt, tv, owner_weights != 0);
     Sites S = build_sites(ns, sx, sy, sz, sr);
     R->L = M.L;
     R->mesh_chi = M.chi;
@@ -1335,11 +1363,12 @@ int oracle_rpd(int32_t nv, const float* vx, const float* vy, const float* vz, in
 // Per-piece results for a chosen list of tets (each tet still clipped against ALL sites).
 int oracle_tet_pieces(int32_t nv, const float* vx, const float* vy, const float* vz, int32_t nt, const int32_t* tv,
                       int32_t ns, const float* sx, const float* sy, const float* sz, const float* sr,
-                      int32_t n_sel, const int32_t* sel, int32_t nthreads, oracle_pieces** out) {
+                      int32_t n_sel, const int32_t* sel, int32_t nthreads, int32_t owner_weights,
+                      oracle_pieces** out) {
   oracle_pieces* R = (oracle_pieces*)std::calloc(1, sizeof(oracle_pieces));
   *out = R;
   try {
-    Mesh M = build_mesh(nv, vx, vy, vz, nt, tv);
+    Mesh M = build_mesh(nv, vx, vy, vz, nt, tv, owner_weights != 0);
     Sites S = build_sites(ns, sx, sy, sz, sr);
     Ctx C{&M, &S, false};
     std::vector<int> tets;

@@ -692,6 +692,7 @@ rpd_status rpd_mesh_get_info(const rpd_mesh* m, rpd_mesh_info* info) {
   info->components = m->components;
   info->L = m->L;
   info->volume = m->volume;
+  info->owner_weights = m->owner;
   return RPD_OK;
 }
 

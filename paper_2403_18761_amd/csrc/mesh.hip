@@ -155,14 +155,34 @@ __global__ void k_presence(const int* kcount, int n, int* pres, int* used, int* 
   if (local) atomicAdd(used, local);
 }
 
+// owner of every vertex, edge and face: the lowest caller tet index among the tets containing it
+__global__ void k_owners(const int* itv, const int* tedge, const int* tface, const int* perm, int nt, int* ov,
+                         int* oe, int* of) {
+  for (int k = blockIdx.x * blockDim.x + threadIdx.x; k < nt; k += gridDim.x * blockDim.x) {
+    const int c = perm[k];
+    for (int v = 0; v < 4; ++v) atomicMin(&ov[itv[4 * (size_t)k + v]], c);
+    for (int e = 0; e < 6; ++e) atomicMin(&oe[tedge[6 * (size_t)k + e]], c);
+    for (int f = 0; f < 4; ++f) atomicMin(&of[tface[4 * (size_t)k + f]], c);
+  }
+}
+
+// weight numerators of a tet's 4 vertices, 6 edges and 4 faces: L / k(sigma), or with owners (ov != nullptr)
+// 1 in the owner tet and 0 elsewhere
 __global__ void k_weights(const int* itv, const int* tedge, const int* tface, const int* kv, const int* ke,
-                          const int* kf, int nt, long long L, unsigned* nu, unsigned long long* vol,
-                          const float4* tp) {
+                          const int* kf, int nt, long long L, const int* perm, const int* ov, const int* oe,
+                          const int* of, unsigned* nu, unsigned long long* vol, const float4* tp) {
   for (int k = blockIdx.x * blockDim.x + threadIdx.x; k < nt; k += gridDim.x * blockDim.x) {
     unsigned* o = nu + 14 * (size_t)k;
-    for (int v = 0; v < 4; ++v) o[v] = (unsigned)(L / kv[itv[4 * (size_t)k + v]]);
-    for (int e = 0; e < 6; ++e) o[4 + e] = (unsigned)(L / ke[tedge[6 * (size_t)k + e]]);
-    for (int f = 0; f < 4; ++f) o[10 + f] = (unsigned)(L / kf[tface[4 * (size_t)k + f]]);
+    if (ov) {
+      const int c = perm[k];
+      for (int v = 0; v < 4; ++v) o[v] = ov[itv[4 * (size_t)k + v]] == c;
+      for (int e = 0; e < 6; ++e) o[4 + e] = oe[tedge[6 * (size_t)k + e]] == c;
+      for (int f = 0; f < 4; ++f) o[10 + f] = of[tface[4 * (size_t)k + f]] == c;
+    } else {
+      for (int v = 0; v < 4; ++v) o[v] = (unsigned)(L / kv[itv[4 * (size_t)k + v]]);
+      for (int e = 0; e < 6; ++e) o[4 + e] = (unsigned)(L / ke[tedge[6 * (size_t)k + e]]);
+      for (int f = 0; f < 4; ++f) o[10 + f] = (unsigned)(L / kf[tface[4 * (size_t)k + f]]);
+    }
     const float4* p = tp + 4 * (size_t)k;
     double ax = (double)p[1].x - p[0].x, ay = (double)p[1].y - p[0].y, az = (double)p[1].z - p[0].z;
     double bx = (double)p[2].x - p[0].x, by = (double)p[2].y - p[0].y, bz = (double)p[2].z - p[0].z;
@@ -314,11 +334,14 @@ void mesh_prepare(rpd_mesh* m, const rpd_mesh_desc* d, uint32_t flags, hipStream
   if (hst[0] & MS_TABLE) throw Failure{RPD_E_INTERNAL, "mesh: hash table full"};
   if (hst[0] & MS_MESH) throw Failure{RPD_E_MESH, "mesh: a face is shared by more than two tets"};
   long long L = 1;
-  for (int k = 1; k < KPRES; ++k)
+  bool big = false;
+  for (int k = 1; k < KPRES && !big; ++k)
     if (hp[k]) {
       L = L / gcdll(L, k) * k;
-      if (L >= (1ll << 31)) throw Failure{RPD_E_MESH, "mesh: lcm of simplex multiplicities exceeds 2^31"};
+      big = L >= (1ll << 31);
     }
+  m->owner = big || (flags & RPD_OWNER_WEIGHTS) ? 1 : 0;
+  if (m->owner) L = 1;
   m->L = L;
   m->n_edges = hp[KPRES + 1];
   m->n_faces = hp[KPRES + 2];
@@ -326,11 +349,22 @@ void mesh_prepare(rpd_mesh* m, const rpd_mesh_desc* d, uint32_t flags, hipStream
   m->euler = hp[KPRES] - m->n_edges + m->n_faces - nt;
   if (m->components != 1) throw Failure{RPD_E_MESH, "mesh: more than one connected component"};
   m->nu.alloc(sizeof(unsigned) * 14 * (size_t)nt);
-  DBuf vol(sizeof(unsigned long long));
+  DBuf vol(sizeof(unsigned long long)), own_v, own_e, own_f;
   hip_check(hipMemsetAsync(vol.p, 0, sizeof(unsigned long long), s), "memset");
+  if (m->owner) {
+    own_v.alloc(sizeof(int) * nv);
+    own_e.alloc(sizeof(int) * ecap);
+    own_f.alloc(sizeof(int) * fcap);
+    hip_check(launch_fill_i32(own_v.as<int>(), INT32_MAX, nv, s), "fill");
+    hip_check(launch_fill_i32(own_e.as<int>(), INT32_MAX, ecap, s), "fill");
+    hip_check(launch_fill_i32(own_f.as<int>(), INT32_MAX, fcap, s), "fill");
+    hipLaunchKernelGGL(k_owners, dim3(gsz(nt)), dim3(256), 0, s, itv.as<int>(), tedge.as<int>(), tface.as<int>(),
+                       m->perm.as<int>(), nt, own_v.as<int>(), own_e.as<int>(), own_f.as<int>());
+  }
   hipLaunchKernelGGL(k_weights, dim3(gsz(nt)), dim3(256), 0, s, itv.as<int>(), tedge.as<int>(), tface.as<int>(),
-                     kv.as<int>(), ke.as<int>(), kf.as<int>(), nt, L, m->nu.as<unsigned>(),
-                     vol.as<unsigned long long>(), m->tp.as<float4>());
+                     kv.as<int>(), ke.as<int>(), kf.as<int>(), nt, L, m->perm.as<int>(), own_v.as<int>(),
+                     own_e.as<int>(), own_f.as<int>(), m->nu.as<unsigned>(), vol.as<unsigned long long>(),
+                     m->tp.as<float4>());
   hip_check(hipGetLastError(), "mesh weights");
   long long hv = 0;
   hip_check(hipMemcpyAsync(&hv, vol.p, sizeof(long long), hipMemcpyDeviceToHost, s), "download");

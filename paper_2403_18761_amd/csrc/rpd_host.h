@@ -79,6 +79,7 @@ struct rpd_mesh {
   int32_t euler = 0, components = 0;
   int64_t L = 1;
   double volume = 0;
+  int32_t owner = 0;  // ownership weights
   int device = 0;
   rpd::DBuf tp;    // float4 [4 nt]: vertex coordinates per internal tet
   rpd::DBuf tn;    // int [4 nt]: neighbour internal tet across local face f

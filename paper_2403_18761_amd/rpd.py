@@ -25,6 +25,7 @@ RPD_FORCE_EXACT = 1 << 2
 RPD_FORCE_SLOW_PATH = 1 << 3
 RPD_TIMING = 1 << 4
 RPD_KEEP_PIECES = 1 << 5
+RPD_OWNER_WEIGHTS = 1 << 6
 
 _f32p = C.POINTER(C.c_float)
 _i32p = C.POINTER(C.c_int32)
@@ -37,7 +38,8 @@ class _MeshDesc(C.Structure):
 
 class _MeshInfo(C.Structure):
     _fields_ = [("n_verts", C.c_int32), ("n_tets", C.c_int32), ("n_edges", C.c_int32), ("n_faces", C.c_int32),
-                ("euler", C.c_int32), ("components", C.c_int32), ("L", C.c_int64), ("volume", C.c_double)]
+                ("euler", C.c_int32), ("components", C.c_int32), ("L", C.c_int64), ("volume", C.c_double),
+                ("owner_weights", C.c_int32)]
 
 
 class _Sites(C.Structure):
@@ -161,7 +163,7 @@ def _stream_ptr(stream) -> int | None:
 class Mesh:
     """A prepared tet mesh (rpd_mesh_create)."""
 
-    def __init__(self, vx, vy, vz, tv, stream=None):
+    def __init__(self, vx, vy, vz, tv, stream=None, owner_weights: bool = False):
         lib = load()
         keep = []
         dev = _is_torch(vx) and vx.is_cuda
@@ -169,7 +171,8 @@ class Mesh:
         d = _MeshDesc(int(vx.shape[0]), _ptr(vx, C.c_float, keep), _ptr(vy, C.c_float, keep),
                       _ptr(vz, C.c_float, keep), int(tv_flat.shape[0]) // 4, _ptr(tv_flat, C.c_int32, keep))
         h = C.c_void_p()
-        _check(lib.rpd_mesh_create(C.byref(d), RPD_DEVICE_PTRS if dev else 0, _stream_ptr(stream), C.byref(h)))
+        fl = (RPD_DEVICE_PTRS if dev else 0) | (RPD_OWNER_WEIGHTS if owner_weights else 0)
+        _check(lib.rpd_mesh_create(C.byref(d), fl, _stream_ptr(stream), C.byref(h)))
         self._h = h
         self._lib = lib
 

@@ -726,3 +726,40 @@ def surface_samples(prob: Problem, n: int, seed: int) -> np.ndarray:
     u[flip], v[flip] = 1 - u[flip], 1 - v[flip]
     q = a[pick] + u[:, None] * (b[pick] - a[pick]) + v[:, None] * (c[pick] - a[pick])
     return q.astype(np.float32)
+
+
+# ----------------------------------------------------------------------------------------------------------------
+# general (non-voxel) tet meshes
+# ----------------------------------------------------------------------------------------------------------------
+
+def delaunay_ball(n_points: int = 400, n_sites: int = 40, seed: int = 0, radius: float = 0.9) -> Problem:
+    """Delaunay tetrahedralisation of random grid points in a ball (a convex, single-component tet mesh whose
+    vertex multiplicities are irregular, so the lcm of multiplicities is far beyond 2^31), with random weighted
+    sites inside."""
+    from scipy.spatial import Delaunay
+
+    rng = np.random.default_rng(seed)
+    d = rng.normal(size=(n_points, 3))
+    pts = d / np.linalg.norm(d, axis=1, keepdims=True) * radius * rng.random((n_points, 1)) ** (1 / 3)
+    pts = np.unique(quantize(pts), axis=0)
+    tv = Delaunay(pts).simplices.astype(np.int64)
+    P = np.round(pts * (1 << 20)).astype(np.int64)  # exact grid integers for the orientation test
+    a, b, c, e = (P[tv[:, k]] for k in range(4))
+    det = np.einsum("ij,ij->i", b - a, np.cross(c - a, e - a))
+    if np.any(det == 0):
+        raise ValueError("flat tet in the Delaunay tetrahedralisation; use another seed")
+    neg = det < 0
+    tv[neg, 0], tv[neg, 1] = tv[neg, 1].copy(), tv[neg, 0].copy()
+    # sites: random points of random tets, radii up to 0.15
+    pick = rng.integers(0, len(tv), n_sites)
+    w = rng.dirichlet(np.ones(4), size=n_sites)
+    cen = np.einsum("ik,ikj->ij", w, pts[tv[pick]])
+    rad = rng.uniform(0.0, 0.15, size=n_sites)
+    c = quantize(cen)
+    r = np.maximum(quantize(rad), 0.0)
+    c, r = _dedupe_centres(c, r)
+    meta = dict(kind="delaunay_ball", workload=f"delaunay_ball_p{n_points}_n{n_sites}_s{seed}", seed=seed, N=0,
+                genus=0)
+    return Problem(pts[:, 0].astype(np.float32), pts[:, 1].astype(np.float32), pts[:, 2].astype(np.float32),
+                   tv.astype(np.int32), c[:, 0].astype(np.float32), c[:, 1].astype(np.float32),
+                   c[:, 2].astype(np.float32), r.astype(np.float32), meta)

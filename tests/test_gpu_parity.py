@@ -198,3 +198,40 @@ def test_launch_shapes_and_autotuner():
     res = rpd.build([mesh], [sites])
     _, chi = res.euler(0, rpd.RPD_CELL)
     np.testing.assert_array_equal(chi, r["cell_chi"])
+
+
+# ------------------------------------------------------------------------------------------------ general meshes
+@pytest.mark.parametrize("seed", [0, 1, 2])
+def test_general_delaunay_mesh(seed):
+    """A Delaunay tet mesh (irregular multiplicities: ownership weights, L = 1) against the oracle."""
+    prob = synth.delaunay_ball(400, 40, seed)
+    log("case: delaunay ball seed", seed)
+    r = _oracle(prob)
+    g = run_gpu(prob)
+    assert g["mesh_info"]["owner_weights"] == 1 and g["mesh_info"]["L"] == r["L"] == 1
+    assert g["mesh_info"]["euler"] == r["mesh_chi"] == 1
+    assert_parity(g, r, label=f"delaunay {seed}")
+
+
+def test_owner_weights_forced_on_a_voxel_mesh():
+    """Ownership weights on a voxel mesh: the same chi, beta0, keys and geometry as the 1/k weights."""
+    import torch
+
+    from paper_2403_18761_amd import rpd
+    from tests.gpu_util import ELEMENT_ARRAYS, extract
+
+    prob = synth.torus_core(16, 64, 1)
+    log("case: forced ownership weights")
+    dev = torch.device("cuda:0")
+
+    def t(a, dt=torch.float32):
+        return torch.as_tensor(np.ascontiguousarray(a), dtype=dt, device=dev)
+
+    sites = [(t(prob.sx), t(prob.sy), t(prob.sz), t(prob.sr))]
+    outs = []
+    for own in (False, True):
+        mesh = rpd.Mesh(t(prob.vx), t(prob.vy), t(prob.vz), t(prob.tv.reshape(-1), torch.int32), owner_weights=own)
+        assert mesh.info()["owner_weights"] == int(own)
+        outs.append(extract(rpd.build([mesh], sites), 0))
+    for name in ELEMENT_ARRAYS:
+        np.testing.assert_array_equal(outs[0][name], outs[1][name], err_msg=name)

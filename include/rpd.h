@@ -21,8 +21,10 @@
  *   - every coordinate and radius is a finite float32 on the dyadic grid 2^-20 with |coordinate| <= 1 and
  *     0 <= radius <= 2 (exact integer predicates then have fixed width);
  *   - tets are positively oriented: det(v1-v0, v2-v0, v3-v0) > 0;
- *   - general position: no exactly-zero predicate is met (a vertex of a clipped piece exactly on a clipping plane,
- *     e.g. a mesh vertex on a bisector, five co-spherical sites, duplicate sites); otherwise RPD_E_DEGENERATE.
+ *   - exact ties (a vertex of a clipped piece exactly on a clipping plane: a mesh vertex on a bisector, five
+ *     co-spherical sites, equal spheres) are broken by symbolic perturbation of the weights: site s's squared radius
+ *     becomes r_s^2 + eps_s with eps_0 >> eps_1 >> ... > 0, so a lower site id wins a tie; the result is the
+ *     diagram of that perturbed input (zero-measure pieces included), identical on every code path.
  *
  * Threading: calls on different handles may run concurrently; calls that share a handle must be serialised.
  * All functions return an rpd_status; on a negative status no output is produced (*out is set to NULL) and
@@ -42,7 +44,7 @@ typedef int32_t rpd_status;
 #define RPD_OK 0
 #define RPD_E_INVALID (-1)    /* bad argument: NaN/Inf, off-grid value, r < 0, index out of range, bad orientation */
 #define RPD_E_MESH (-2)       /* face shared by more than two tets, several components, simplex multiplicity lcm too big */
-#define RPD_E_DEGENERATE (-3) /* an exact predicate is zero (input not in general position) or duplicate sites */
+#define RPD_E_DEGENERATE (-3) /* three clipping planes without a single meet point (cannot occur for valid input) */
 #define RPD_E_NOMEM (-4)      /* device or host allocation failed */
 #define RPD_E_DEVICE (-5)     /* HIP runtime error or no device */
 #define RPD_E_INTERNAL (-6)   /* an internal consistency check failed (gluing asymmetry, non-integer chi, ...) */
@@ -271,8 +273,8 @@ typedef struct rpd_session_info {
 rpd_status rpd_session_create(const rpd_mesh* mesh, const rpd_sites* sites, const rpd_sites* table,
                               const rpd_session_opts* opts, rpd_session** out);
 
-/* Run `rounds` rounds (graph replays), then synchronise and check the device status. Errors: RPD_E_DEGENERATE
- * (an inserted sphere duplicates a site or is not in general position), RPD_E_NOMEM (the session's tables filled
+/* Run `rounds` rounds (graph replays), then synchronise and check the device status (ties with an inserted sphere
+ * are broken like every other tie, see the preconditions above). Errors: RPD_E_NOMEM (the session's tables filled
  * up: create it with a larger max_sites), RPD_E_DEVICE. After an error the session can only be freed. */
 rpd_status rpd_session_run(rpd_session* s, int32_t rounds);
 

@@ -27,8 +27,12 @@
 //     the tets around sigma this is the same total weight 1 as k(sigma) times 1/k(sigma), so every element's chi is
 //     unchanged; only its split over the pieces differs.
 //
-// Readings of the paper (where it is silent): weights w(sigma)=1/k(sigma) generalise the 2D example; input is
-// in general position -- any exactly zero predicate is reported as RPD_E_DEGENERATE; empty cells report chi=0,
+//   * Exact ties (a vertex exactly on a clipping plane: a bisector through a mesh vertex, five co-spherical sites,
+//     equal spheres) are broken by symbolic perturbation of the weights (simulation of simplicity): site s's squared
+//     radius becomes W_s + eps_s with eps_0 >> eps_1 >> ... > 0, so a lower site id wins a tie.
+//
+// Readings of the paper (where it is silent): weights w(sigma)=1/k(sigma) generalise the 2D example; ties as
+// above (the paper assumes a clean cut); empty cells report chi=0,
 // beta0=0, volume 0 and a NaN centroid.
 //
 // Inputs are float32 values on the 2^-20 grid; they are converted exactly to integers in units of 2^-20.
@@ -153,7 +157,7 @@ I256 det3(const i128* a, const i128* b, const i128* c) {
 // Sign of plane q at the point where planes a, b, c meet.  With M = det[[n_a d_a];[n_b d_b];[n_c d_c];[n_q d_q]]
 // and Delta = det[n_a; n_b; n_c], the value of plane q at that point equals M / Delta (Cramer's rule on the
 // homogeneous system), so its sign is sign(M) * sign(Delta).
-int side_exact(const Plane& a, const Plane& b, const Plane& c, const Plane& q, int* delta_zero) {
+I256 side_value(const Plane& a, const Plane& b, const Plane& c, const Plane& q, int* sd_out) {
   I256 m_a = det3(b.n, c.n, q.n);
   I256 m_b = det3(a.n, c.n, q.n);
   I256 m_c = det3(a.n, b.n, q.n);
@@ -163,9 +167,42 @@ int side_exact(const Plane& a, const Plane& b, const Plane& c, const Plane& q, i
   M = sub(M, mul(from128(a.d), m_a));
   M = add(M, mul(from128(b.d), m_b));
   M = sub(M, mul(from128(c.d), m_c));
-  int sd = sgn(m_q);
+  *sd_out = sgn(m_q);
+  return M;
+}
+
+int side_exact(const Plane& a, const Plane& b, const Plane& c, const Plane& q, int* delta_zero) {
+  int sd = 0;
+  I256 M = side_value(a, b, c, q, &sd);
   if (delta_zero) *delta_zero = (sd == 0);
   return sgn(M) * sd;
+}
+
+// The same sign with exact zeros broken by symbolic perturbation of the weights: site s's squared radius becomes
+// W_s + eps_s, eps_0 >> eps_1 >> ... > 0 infinitesimal, so a bisector of the cell's site si against site j gains
+// eps_si - eps_j in its offset (power distance of the origin to j minus that to si) and face planes do not move.
+// The value M is linear in the four offsets, so the coefficient of eps_s is the change of M when s's weight
+// grows by one unit; the sign is that of the first nonzero coefficient in increasing site order.
+int side_sos(const Plane& a, const Plane& b, const Plane& c, const Plane& q, int si, int* delta_zero) {
+  int sd = 0;
+  I256 M = side_value(a, b, c, q, &sd);
+  *delta_zero = (sd == 0);
+  if (sd == 0 || sgn(M) != 0) return sgn(M) * sd;
+  const Plane* pl[4] = {&a, &b, &c, &q};
+  std::vector<int> sites = {si};
+  for (const Plane* p : pl)
+    if (p->kind == 1) sites.push_back(p->id);
+  std::sort(sites.begin(), sites.end());
+  sites.erase(std::unique(sites.begin(), sites.end()), sites.end());
+  for (int s : sites) {
+    Plane moved[4] = {a, b, c, q};
+    for (Plane& p : moved)
+      if (p.kind == 1) p.d += (s == si ? 1 : 0) - (s == p.id ? 1 : 0);
+    int sd2 = 0;
+    I256 coef = sub(side_value(moved[0], moved[1], moved[2], moved[3], &sd2), M);
+    if (sgn(coef) != 0) return sgn(coef) * sd;
+  }
+  return 0;
 }
 
 // Exact point of three planes (as long double coordinates, tet-local, units 2^-20):
@@ -441,17 +478,17 @@ int shared_planes(const std::array<int, 3>& u, const std::array<int, 3>& w, int 
   return c;
 }
 
-// Clip by plane q (exact). Returns false when the piece becomes empty.
-bool clip(Piece& P, const Plane& q) {
+// Clip the piece of site si by plane q (exact, ties by symbolic perturbation). Returns false when it empties.
+bool clip(Piece& P, const Plane& q, int si) {
   int nv = (int)P.verts.size();
   std::vector<int> side(nv);
   bool any_out = false, all_out = true;
   for (int v = 0; v < nv; ++v) {
     const auto& t = P.verts[v];
     int dz = 0;
-    int s = side_exact(P.planes[t[0]], P.planes[t[1]], P.planes[t[2]], q, &dz);
+    int s = side_sos(P.planes[t[0]], P.planes[t[1]], P.planes[t[2]], q, si, &dz);
     if (dz) throw Failure{E_DEGENERATE, "vertex planes without a unique intersection"};
-    if (s == 0) throw Failure{E_DEGENERATE, "a vertex lies exactly on a clipping plane"};
+    if (s == 0) throw Failure{E_DEGENERATE, "a perturbed predicate is still zero"};
     side[v] = s;
     if (s < 0) any_out = true;
     else all_out = false;
@@ -940,7 +977,7 @@ void process_tet(const Ctx& C, int t, std::vector<PieceOut>& outs, std::vector<A
       h.d = (i128)pow_dist(S, j, ox, oy, oz) - (i128)pow_dist(S, i, ox, oy, oz);
       h.kind = 1;
       h.id = j;
-      alive = clip(P, h);
+      alive = clip(P, h, i);
     }
     if (!alive || P.verts.empty()) continue;
     PieceOut po;

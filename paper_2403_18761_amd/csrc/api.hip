@@ -276,7 +276,7 @@ struct DeviceState {
 static rpd_status status_error(int hst) {
   if (hst & ST_INVALID) throw Failure{RPD_E_INVALID, "site value off the 2^-20 grid, out of range or not finite"};
   if (hst & ST_DEGENERATE)
-    throw Failure{RPD_E_DEGENERATE, "input not in general position (an exact predicate is zero or duplicate sites)"};
+    throw Failure{RPD_E_DEGENERATE, "three clipping planes without a single meet point"};
   if (hst & ST_SLOW_CAPACITY)
     throw Failure{RPD_E_NOMEM, "a tet exceeds the large-capacity path (over 1020 candidate sites or 64 vertices)"};
   if (hst & ST_INTERNAL) throw Failure{RPD_E_INTERNAL, "internal consistency check failed (gluing or chi)"};

@@ -260,7 +260,8 @@ __device__ int clip_piece(Clipper<T, Topo, Mask, VCAP, EXACT>& cl, int m, int* s
     Plane<double> P = bisector64(env.si, sj, o);
     if (P.nx == 0.0 && P.ny == 0.0 && P.nz == 0.0) {  // concentric spheres: the larger one owns everything
       if (P.d > 0) continue;
-      if (P.d == 0) atomicOr(status, ST_DEGENERATE);
+      // equal spheres: under the weight perturbation eps_i - eps_j the lower site id owns everything
+      if (P.d == 0 && env.site_i < env.cand_id(c)) continue;
       return CLIP_EMPTY;
     }
     // the bisector's values at the tet vertices are exact in FP64

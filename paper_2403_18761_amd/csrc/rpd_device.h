@@ -215,7 +215,16 @@ struct PlaneI {
 };
 
 // Exact sign of plane Q at the meet of A, B, C; returns 2 if A, B, C do not meet in one point.
-__device__ inline int side_exact(const PlaneI& A, const PlaneI& B, const PlaneI& C, const PlaneI& Q) {
+//
+// An exact zero is resolved by symbolic perturbation of the weights (simulation of simplicity): site s gets
+// r_s^2 + eps_s with eps_s infinitesimal and eps_0 >> eps_1 >> ... (a lower site id dominates). A bisector of the
+// cell's site i against site j (offset D_j - D_i, D = power distance of the local origin) then has offset
+// d + eps_i - eps_j, face planes are unchanged, and the raw value below, linear in the four offsets, gains
+// sum_P c_P (eps_i - eps_j(P)) with c_P the cofactor of plane P's offset. Its sign is that of the lowest site's
+// nonzero coefficient; Q's own site has coefficient -W != 0, so the result is never 0. site[] holds the other
+// site of each of A, B, C, Q (-1 for a face plane), si the cell's site.
+__device__ inline int side_exact(const PlaneI& A, const PlaneI& B, const PlaneI& C, const PlaneI& Q,
+                                 const int* site, int si) {
   i128 bc[3] = {(i128)B.ny * C.nz - (i128)B.nz * C.ny, (i128)B.nz * C.nx - (i128)B.nx * C.nz,
                 (i128)B.nx * C.ny - (i128)B.ny * C.nx};
   i128 ca[3] = {(i128)C.ny * A.nz - (i128)C.nz * A.ny, (i128)C.nz * A.nx - (i128)C.nx * A.nz,
@@ -233,7 +242,26 @@ __device__ inline int side_exact(const PlaneI& A, const PlaneI& B, const PlaneI&
                        i256_mul(i256(C.d), i256(ab[k])));
     s = i256_add(s, i256_neg(i256_mul(i256(qn[k]), Xk)));  // X = -(...)
   }
-  return i256_sign(s) * sw;
+  if (i256_sign(s) != 0) return i256_sign(s) * sw;
+  // cofactors of the offsets of A, B, C, Q in the raw value
+  I256 cof[4];
+  const i128* rows[3] = {bc, ca, ab};
+  for (int p = 0; p < 3; ++p) {
+    I256 t = i256_add(i256_add(i256_mul(i256(qn[0]), i256(rows[p][0])), i256_mul(i256(qn[1]), i256(rows[p][1]))),
+                      i256_mul(i256(qn[2]), i256(rows[p][2])));
+    cof[p] = i256_neg(t);
+  }
+  cof[3] = W;
+  I256 ci = {{0, 0, 0, 0}};  // coefficient of eps_i: every bisector's cofactor
+  for (int p = 0; p < 4; ++p)
+    if (site[p] >= 0) ci = i256_add(ci, cof[p]);
+  int best = i256_sign(ci) != 0 ? si : 0x7fffffff, best_sign = i256_sign(ci);
+  for (int p = 0; p < 4; ++p)  // coefficient of eps_j(P): -c_P (the four planes' sites are distinct)
+    if (site[p] >= 0 && site[p] < best && i256_sign(cof[p]) != 0) {
+      best = site[p];
+      best_sign = -i256_sign(cof[p]);
+    }
+  return best_sign * sw;
 }
 
 // ---------------------------------------------------------------------------------------------------------------
@@ -532,7 +560,8 @@ struct Clipper {
     }
     if (!EXACT) return 0;
     ++nex;
-    int s = side_exact(env.planeI(pa), env.planeI(pb), env.planeI(pc), env.planeI(q));
+    const int site[4] = {env.plane_site(pa), env.plane_site(pb), env.plane_site(pc), env.plane_site(q)};
+    int s = side_exact(env.planeI(pa), env.planeI(pb), env.planeI(pc), env.planeI(q), site, env.site_i);
     if (s == 0 || s == 2) {
       atomicOr(a->status, ST_DEGENERATE);
       return -1;

@@ -211,6 +211,18 @@ rpd_status rpd_envelope_distance(const float* spheres, int32_t n_spheres, const 
                                  const int32_t* tris, int64_t n_tris, const float* samples, int64_t n_samples,
                                  uint32_t flags, void* stream, float* dist, int32_t* nearest, float* kernel_ms);
 
+/* Medial spheres by sphere shrinking (Sec. 5.1, Fig. tech_sphere_gen (a)): for each pin point p with inward unit
+ * normal n, the maximal ball tangent to the surface at p with no surface point inside, i.e. the fixed point of the
+ * shrinking iteration. The surface is given as triangles (9 floats each: three vertices); the radius is
+ * min over surface points q with n.(q - p) > 0 of |q - p|^2 / (2 n.(q - p)), computed exactly per triangle
+ * (vertices, edge stationary points, plane tangency) over all triangles. own_tri (may be NULL): per pin, the index
+ * of the triangle that carries it (excluded). Output: 4 floats per pin (centre p + r n, radius r; r = +inf when no
+ * surface point lies on the inner side). FP32 arithmetic, constants rounded from FP64. With RPD_DEVICE_PTRS every
+ * array is device memory and the call runs on stream; otherwise host memory. Synchronises the stream.
+ * Errors: RPD_E_INVALID (negative count, null array), RPD_E_NOMEM, RPD_E_DEVICE. */
+rpd_status rpd_shrink_spheres(const float* tris, int64_t n_tris, const float* pins, const float* normals,
+                              const int32_t* own_tri, int64_t n_pins, uint32_t flags, void* stream, float* spheres);
+
 /* Counters of the call (summed over shapes). */
 rpd_status rpd_get_stats(const rpd_result* r, rpd_stats* stats);
 

@@ -17,7 +17,7 @@ CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "librpd.so")
-SOURCES = ["api.hip", "mesh.hip", "clip.hip", "reduce.hip", "session.hip", "medial.hip", "envelope.hip"]
+SOURCES = ["api.hip", "mesh.hip", "clip.hip", "reduce.hip", "session.hip", "medial.hip", "envelope.hip", "shrink.hip"]
 ARCH = os.environ.get("RPD_OFFLOAD_ARCH", "gfx950")
 
 

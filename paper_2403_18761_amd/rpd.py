@@ -105,6 +105,8 @@ def load():
     lib.rpd_envelope_distance.argtypes = [C.c_void_p, C.c_int32, C.c_void_p, C.c_int64, C.c_void_p, C.c_int64,
                                           C.c_void_p, C.c_int64, C.c_uint32, C.c_void_p, C.c_void_p, C.c_void_p,
                                           C.POINTER(C.c_float)]
+    lib.rpd_shrink_spheres.argtypes = [C.c_void_p, C.c_int64, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64,
+                                       C.c_uint32, C.c_void_p, C.c_void_p]
     lib.rpd_thin.argtypes = [C.c_int32, C.c_int64, _i32p, C.c_int64, _i32p, C.POINTER(C.c_double), C.c_int64, _i32p,
                              C.c_double, C.POINTER(C.c_uint8), C.POINTER(C.c_uint8), C.POINTER(C.c_uint8)]
     lib.rpd_pieces.argtypes = [C.c_void_p, C.c_int32, C.POINTER(C.c_int64), C.POINTER(_i32p), C.POINTER(_i32p),
@@ -126,7 +128,8 @@ def load():
     for f in ("rpd_mesh_create", "rpd_mesh_get_info", "rpd_build", "rpd_euler", "rpd_components", "rpd_geometry",
               "rpd_adjacency", "rpd_get_stats", "rpd_pieces", "rpd_session_create", "rpd_session_run",
               "rpd_session_result", "rpd_session_get_info", "rpd_session_sites", "rpd_autotune",
-              "rpd_edge_geometry", "rpd_medial_euler", "rpd_thin", "rpd_envelope_distance"):
+              "rpd_edge_geometry", "rpd_medial_euler", "rpd_thin", "rpd_envelope_distance",
+              "rpd_shrink_spheres"):
         getattr(lib, f).restype = C.c_int32
     _lib = lib
     return lib
@@ -382,6 +385,36 @@ def envelope_distance(spheres, edges, tris, samples, stream=None, timing: bool =
     _check(lib.rpd_envelope_distance(ptr(sp), sp.shape[0], ptr(ed), ed.shape[0], ptr(tr), tr.shape[0], ptr(q),
                                      q.shape[0], 0, _stream_ptr(stream), ptr(dist), ptr(near), kptr))
     return (dist, near, kms.value) if timing else (dist, near)
+
+
+def shrink_spheres(tris, pins, normals, own_tri=None, stream=None):
+    """rpd_shrink_spheres: maximal empty balls tangent to the surface (triangles (m, 3, 3)) at the pins (s, 3) with
+    inward unit normals (s, 3); own_tri (s,) the pin's triangle or None. CUDA tensors run on the device (output a
+    tensor), numpy arrays through host memory. Returns (s, 4) float32 (centre, radius)."""
+    lib = load()
+    if _is_torch(pins) and pins.is_cuda:
+        import torch
+
+        dev = pins.device
+        t = tris.to(dev, torch.float32).contiguous().reshape(-1, 9)
+        p = pins.to(torch.float32).contiguous().reshape(-1, 3)
+        n = normals.to(dev, torch.float32).contiguous().reshape(-1, 3)
+        o = own_tri.to(dev, torch.int32).contiguous() if own_tri is not None else None
+        out = torch.empty((p.shape[0], 4), dtype=torch.float32, device=dev)
+        ptr = lambda x: C.c_void_p(x.data_ptr() if x is not None and x.numel() else 0)
+        st = _stream_ptr(stream) if stream is not None else C.c_void_p(torch.cuda.current_stream(dev).cuda_stream)
+        _check(lib.rpd_shrink_spheres(ptr(t), t.shape[0], ptr(p), ptr(n), ptr(o), p.shape[0], RPD_DEVICE_PTRS, st,
+                                      ptr(out)))
+        return out
+    t = np.ascontiguousarray(np.asarray(tris, np.float32).reshape(-1, 9))
+    p = np.ascontiguousarray(np.asarray(pins, np.float32).reshape(-1, 3))
+    n = np.ascontiguousarray(np.asarray(normals, np.float32).reshape(-1, 3))
+    o = np.ascontiguousarray(np.asarray(own_tri, np.int32)) if own_tri is not None else None
+    out = np.empty((p.shape[0], 4), np.float32)
+    ptr = lambda x: C.c_void_p(x.ctypes.data if x is not None and x.size else 0)
+    _check(lib.rpd_shrink_spheres(ptr(t), t.shape[0], ptr(p), ptr(n), ptr(o), p.shape[0], 0, _stream_ptr(stream),
+                                  ptr(out)))
+    return out
 
 
 def version() -> str:

@@ -763,3 +763,28 @@ def delaunay_ball(n_points: int = 400, n_sites: int = 40, seed: int = 0, radius:
     return Problem(pts[:, 0].astype(np.float32), pts[:, 1].astype(np.float32), pts[:, 2].astype(np.float32),
                    tv.astype(np.int32), c[:, 0].astype(np.float32), c[:, 1].astype(np.float32),
                    c[:, 2].astype(np.float32), r.astype(np.float32), meta)
+
+
+def surface_pins(prob: Problem):
+    """Boundary triangles of the tet mesh as (m, 3, 3) float32 vertex coordinates, their inward unit normals, their
+    centroids (the pin points of sphere shrinking), and the (tet, local face) each comes from (face f is opposite the
+    tet's vertex f)."""
+    tv = np.asarray(prob.tv).reshape(-1, 4)
+    nt = len(tv)
+    faces = np.concatenate([tv[:, [1, 2, 3]], tv[:, [0, 2, 3]], tv[:, [0, 1, 3]], tv[:, [0, 1, 2]]])
+    tet = np.tile(np.arange(nt), 4)
+    loc = np.repeat(np.arange(4), nt)
+    key = np.sort(faces, axis=1)
+    _, inv, cnt = np.unique(key, axis=0, return_inverse=True, return_counts=True)
+    b = cnt[inv.reshape(-1)] == 1
+    faces, tet, loc = faces[b], tet[b], loc[b]
+    P = np.stack([prob.vx, prob.vy, prob.vz], axis=1).astype(np.float64)
+    tri = P[faces]
+    n = np.cross(tri[:, 1] - tri[:, 0], tri[:, 2] - tri[:, 0])
+    n /= np.linalg.norm(n, axis=1, keepdims=True)
+    opp = P[tv[tet, loc]]
+    flip = np.einsum("ij,ij->i", n, opp - tri[:, 0]) < 0
+    n[flip] = -n[flip]
+    order = np.lexsort((loc, tet))
+    return (tri[order].astype(np.float32), n[order].astype(np.float32), tri[order].mean(axis=1).astype(np.float32),
+            tet[order].astype(np.int32), loc[order].astype(np.int32))

@@ -42,16 +42,16 @@ def kernel_source_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def measured_traffic(workload: str, kernel: str):
-    """Bytes per launch of `kernel` on `workload` from the committed counter summary, or None when there is none
-    or the kernel sources changed since it was taken."""
+def measured_traffic(workload: str, kernel: str, launch: dict):
+    """Bytes per launch of `kernel` on `workload` from the committed counter summary, or None when there is none,
+    it was taken with another launch shape, or the kernel sources changed since."""
     try:
         with open(TRAFFIC_FILE) as fh:
             d = json.load(fh)
     except (OSError, ValueError):
         return None
     e = d.get(workload, {})
-    if e.get("source_hash") != kernel_source_hash() or e.get("kernel") != kernel:
+    if e.get("source_hash") != kernel_source_hash() or e.get("kernel") != kernel or e.get("launch") != launch:
         return None
     return e.get("bytes_per_launch")
 
@@ -161,8 +161,13 @@ def run_repair(args, prob, table):
 
     max_insert = 64
     mesh = rpd.Mesh(t(prob.vx), t(prob.vy), t(prob.vz), t(prob.tv.reshape(-1), torch.int32))
-    sess = rpd.Session(mesh, (t(prob.sx), t(prob.sy), t(prob.sz), t(prob.sr)), tuple(t(x) for x in table),
-                       max_sites=prob.n_sites + max_insert * (args.steps + args.warmup), max_insert=max_insert)
+    shrink = args.insertion == "shrink"
+    t_create = time.perf_counter()
+    sess = rpd.Session(mesh, (t(prob.sx), t(prob.sy), t(prob.sz), t(prob.sr)),
+                       None if shrink else tuple(t(x) for x in table),
+                       max_sites=prob.n_sites + max_insert * (args.steps + args.warmup), max_insert=max_insert,
+                       insertion=rpd.RPD_INSERT_SHRINK if shrink else rpd.RPD_INSERT_TABLE)
+    ms_create = (time.perf_counter() - t_create) * 1e3
     sess.run(args.warmup)
     i0 = sess.info()
     torch.cuda.synchronize()
@@ -186,13 +191,15 @@ def run_repair(args, prob, table):
     ms_round = dt * 1e3 / args.steps
     print(f"# repair: {ms_round:.3f} ms/round, {i1['n_inserted'] - i0['n_inserted']} inserted, "
           f"{i1['n_dirty_blocks'] - i0['n_dirty_blocks']} dirty blocks of {i1['n_blocks']} x {args.steps}, "
-          f"rebuild {ms_full:.3f} ms, violating cells left {bad}", file=sys.stderr, flush=True)
+          f"rebuild {ms_full:.3f} ms, violating cells left {bad}, insertion {args.insertion}, session creation "
+          f"{ms_create:.1f} ms", file=sys.stderr, flush=True)
     return dict(value=clipped / dt, ms_per_step=ms_round, n_pairs=st["n_pairs"], n_sites=int(s.shape[0]),
                 extra={"ms_per_round": ms_round, "ms_full_rebuild_final_sites": ms_full,
                        "rounds_timed": args.steps, "inserted_timed": i1["n_inserted"] - i0["n_inserted"],
                        "dirty_blocks_timed": i1["n_dirty_blocks"] - i0["n_dirty_blocks"], "n_blocks": i1["n_blocks"],
                        "pairs_clipped_timed": clipped, "violating_cells_left": bad,
-                       "sites_final": int(s.shape[0])})
+                       "sites_final": int(s.shape[0]), "insertion": args.insertion,
+                       "ms_session_create": ms_create})
 
 
 # Algorithmic FLOPs of one (sample, element) evaluation of the geometric-error kernel: d = q - c (3), then
@@ -292,6 +299,8 @@ def main():
                     help="use this launch shape (threads per workgroup, clip budget) instead of autotuning")
     ap.add_argument("--cpu-frac", type=float, default=None)
     ap.add_argument("--workload", default="torus2000", choices=sorted(WORKLOADS))
+    ap.add_argument("--insertion", default="table", choices=("table", "shrink"),
+                    help="repair workload: spheres from the per-tet table, or shrunk at the furthest surface face")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run a plain device-to-device copy of MIB MiB (the reference kernel that scales the "
                          "FETCH_SIZE / WRITE_SIZE counters to bytes) and exit")
@@ -389,7 +398,7 @@ def main():
 
     achieved = FLOP_PER_PIECE * pairs / (clip32 * 1e-3) / 1e12
     kernel = f"k_clip_fast<float,{tuned['block']}>"
-    traffic = measured_traffic(args.workload, kernel) if len(probs) == 1 else None
+    traffic = measured_traffic(args.workload, kernel, tuned) if len(probs) == 1 else None
     line = {
         "metric": "tet-site clips/sec (nonempty pieces/s) + ms per RPD+chi, FP32/FP64-fallback vs all-FP64, 1 MI355X",
         "value": pairs / (ms32 * 1e-3),

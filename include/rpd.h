@@ -250,8 +250,12 @@ rpd_status rpd_autotune(const rpd_mesh* const* meshes, const rpd_sites* sites, i
  *   1. selects up to max_insert restricted power cells with chi != 1 or more than one component (lowest site ids
  *      first; Sec. 3.3 / 4.1 criteria for a cell),
  *   2. picks for each a tet among the cell's pieces (for a cell with several components, outside the component
- *      of its first piece) by a fixed hash of (tet, round), and appends the sphere that `table` holds for that
- *      tet (each tet's sphere is inserted at most once),
+ *      of its first piece) and appends a sphere (each at most once):
+ *      RPD_INSERT_TABLE: the sphere that `table` holds for a tet chosen by a fixed hash of (tet, round);
+ *      RPD_INSERT_SHRINK (Sec. 4.1.3 with Sec. 5.1): among the surface triangles (mesh faces without a neighbour)
+ *      the cell's pieces touch, the one whose centroid is furthest from the cell's sphere centre is the pin, and the
+ *      sphere is the shrunk sphere at that pin (rpd_shrink_spheres over the mesh surface, computed once at
+ *      creation and rounded to the 2^-20 grid: centre to nearest, radius down);
  *   3. re-clips only the workgroup blocks whose tets a new sphere can reach (exact candidate test), removing the
  *      blocks' old contributions and adding the new ones, and recomputes the components.
  * The round is one captured HIP graph replayed by rpd_session_run. The state after any number of rounds is
@@ -259,12 +263,16 @@ rpd_status rpd_autotune(const rpd_mesh* const* meshes, const rpd_sites* sites, i
  */
 typedef struct rpd_session rpd_session;
 
+#define RPD_INSERT_TABLE 0  /* insertion from the caller's per-tet table */
+#define RPD_INSERT_SHRINK 1 /* insertion by sphere shrinking at the furthest surface triangle of the cell */
+
 typedef struct rpd_session_opts {
   int32_t max_sites;  /* capacity: initial sites plus every insertion, in [n_sites, 2^21) */
   int32_t max_insert; /* cells handled per round, 1..4096 */
   rpd_opts build;     /* precision, clip_budget, block, flags as for rpd_build (RPD_DEVICE_PTRS applies to the sites
                          and the table); build.stream is synchronised before the session reads the inputs, and the
                          session then runs on a stream of its own */
+  int32_t insertion;  /* RPD_INSERT_TABLE or RPD_INSERT_SHRINK */
 } rpd_session_opts;
 
 typedef struct rpd_session_info {
@@ -279,8 +287,9 @@ typedef struct rpd_session_info {
 } rpd_session_info;
 
 /* Create a session: validate the inputs, compute the initial RPD, capture the round graph.
- * mesh is borrowed and must outlive the session. sites: the initial spheres. table: one sphere per tet of the
- * mesh in the caller's tet order (table->n_sites == n_tets), on the 2^-20 grid like every site. Synchronises.
+ * mesh is borrowed and must outlive the session. sites: the initial spheres. table (RPD_INSERT_TABLE; NULL with
+ * RPD_INSERT_SHRINK): one sphere per tet of the mesh in the caller's tet order (table->n_sites == n_tets), on the
+ * 2^-20 grid like every site. Synchronises.
  * Errors: RPD_E_INVALID, RPD_E_DEGENERATE, RPD_E_NOMEM, RPD_E_DEVICE. */
 rpd_status rpd_session_create(const rpd_mesh* mesh, const rpd_sites* sites, const rpd_sites* table,
                               const rpd_session_opts* opts, rpd_session** out);

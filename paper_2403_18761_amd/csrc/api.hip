@@ -948,7 +948,7 @@ struct rpd_session {
   hipStream_t stream = nullptr;
   const rpd_mesh* mesh = nullptr;
   rpd_opts o{};
-  int max_sites = 0, max_insert = 0, kmax = rpd::KMAX;
+  int max_sites = 0, max_insert = 0, kmax = rpd::KMAX, mode = 0;
   bool failed = false;
   rpd::ShapeDesc hd{};
   rpd::DeviceState D;
@@ -1004,8 +1004,28 @@ static bool session_init(rpd_session* S, const rpd_sites* sites, const rpd_sites
   D.clear(s);
   std::vector<ShapeDesc> hd{S->hd};
   upload_sites(D, sites, hd, dev, s);
-  // the table, validated like sites, then put in the internal tet order
-  {
+  const size_t nslots = S->mode ? 4 * (size_t)nt : (size_t)nt;
+  S->tet_used.alloc(sizeof(int) * nslots);
+  hip_check(launch_fill_i32(S->tet_used.as<int>(), S->mode ? 1 : 0, nslots, s), "fill");
+  if (S->mode) {  // shrunk spheres at every surface face (the pins), on the grid
+    DBuf tri(36 * 4 * (size_t)nt), pin(12 * 4 * (size_t)nt), nrm(12 * 4 * (size_t)nt), slot(16 * (size_t)nt),
+        own(16 * (size_t)nt), cnt(sizeof(int)), sph;
+    hip_check(launch_fill_i32(cnt.as<int>(), 0, 1, s), "fill");
+    hip_check(launch_surface_faces(m->tp.as<float4>(), m->tn.as<int>(), nt, tri.as<float>(), pin.as<float>(),
+                                   nrm.as<float>(), slot.as<int>(), cnt.as<int>(), s),
+              "surface faces");
+    int nf = 0;
+    hip_check(hipMemcpyAsync(&nf, cnt.p, sizeof(int), hipMemcpyDeviceToHost, s), "download");
+    hip_check(hipStreamSynchronize(s), "synchronize");
+    sph.alloc(16 * (size_t)std::max(nf, 1));
+    hip_check(launch_iota(own.as<int>(), nf, s), "iota");
+    shrink_spheres(tri.as<float>(), nf, pin.as<float>(), nrm.as<float>(), own.as<int>(), nf, s, sph.as<float4>());
+    S->table.alloc(sizeof(float4) * nslots);
+    hip_check(launch_scatter_spheres(sph.as<float4>(), slot.as<int>(), nf, S->table.as<float4>(),
+                                     S->tet_used.as<int>(), s),
+              "table");
+    hip_check(hipStreamSynchronize(s), "synchronize");
+  } else {  // the table, validated like sites, then put in the internal tet order
     DBuf raw(sizeof(float4) * (size_t)nt), stage;
     const float *tx = table->sx, *ty = table->sy, *tz = table->sz, *tr = table->sr;
     if (!dev) {
@@ -1040,7 +1060,6 @@ static bool session_init(rpd_session* S, const rpd_sites* sites, const rpd_sites
   S->best.alloc(8 * (size_t)S->max_insert);
   S->ref.alloc(sizeof(int) * (size_t)S->max_insert);
   S->selpos.alloc(sizeof(int) * (size_t)S->max_sites);
-  S->tet_used.alloc(sizeof(int) * (size_t)nt);
   S->ints.alloc(sizeof(int) * SI_COUNT);
   hip_check(hipMemcpyAsync(S->dshapes.p, two, sizeof(two), hipMemcpyHostToDevice, s), "upload");
   hip_check(hipMemcpyAsync(S->all_items.p, all.data(), sizeof(int2) * all.size(), hipMemcpyHostToDevice, s),
@@ -1048,7 +1067,6 @@ static bool session_init(rpd_session* S, const rpd_sites* sites, const rpd_sites
   hip_check(hipMemcpyAsync(S->tet_block.p, tb.data(), sizeof(int) * tb.size(), hipMemcpyHostToDevice, s), "upload");
   hip_check(launch_fill_i32(S->dirty.as<int>(), 0, nblk, s), "fill");
   hip_check(launch_fill_i32(S->selpos.as<int>(), -1, S->max_sites, s), "fill");
-  hip_check(launch_fill_i32(S->tet_used.as<int>(), 0, nt, s), "fill");
   hip_check(launch_fill_i32(S->ints.as<int>(), 0, SI_COUNT, s), "fill");
   hip_check(launch_fill_i32(S->ints.as<int>() + SI_NS, S->hd.ns, 1, s), "fill");
 
@@ -1071,6 +1089,7 @@ static bool session_init(rpd_session* S, const rpd_sites* sites, const rpd_sites
   r.ref = S->ref.as<int>();
   r.tet_used = S->tet_used.as<int>();
   r.table = S->table.as<float4>();
+  r.mode = S->mode;
   r.tet_block = S->tet_block.as<int>();
   r.dirty = S->dirty.as<int>();
   r.items = S->items.as<int2>();
@@ -1142,7 +1161,10 @@ rpd_status rpd_session_create(const rpd_mesh* mesh, const rpd_sites* sites, cons
   if (out) *out = nullptr;
   RPD_GUARD_BEGIN
   rpd::set_error("");
-  if (!mesh || !sites || !table || !opts || !out) throw Failure{RPD_E_INVALID, "null argument"};
+  if (!mesh || !sites || !opts || !out) throw Failure{RPD_E_INVALID, "null argument"};
+  if (opts->insertion != RPD_INSERT_TABLE && opts->insertion != RPD_INSERT_SHRINK)
+    throw Failure{RPD_E_INVALID, "unknown insertion mode"};
+  if (opts->insertion == RPD_INSERT_TABLE && !table) throw Failure{RPD_E_INVALID, "null table"};
   const rpd_opts& o = opts->build;
   check_opts(o);
   if (o.flags & (RPD_KEEP_PIECES | RPD_FORCE_SLOW_PATH))
@@ -1153,7 +1175,8 @@ rpd_status rpd_session_create(const rpd_mesh* mesh, const rpd_sites* sites, cons
     throw Failure{RPD_E_INVALID, "max_sites must be in [n_sites, 2^21)"};
   if (opts->max_insert < 1 || opts->max_insert > rpd::MAX_INSERT)
     throw Failure{RPD_E_INVALID, "max_insert must be in [1, 4096]"};
-  if (table->n_sites != mesh->nt || !table->sx || !table->sy || !table->sz || !table->sr)
+  if (opts->insertion == RPD_INSERT_TABLE &&
+      (table->n_sites != mesh->nt || !table->sx || !table->sy || !table->sz || !table->sr))
     throw Failure{RPD_E_INVALID, "the table needs one sphere per tet"};
   if (mesh->nblk <= 0) throw Failure{RPD_E_INVALID, "empty mesh"};
   if (o.stream) rpd::hip_check(hipStreamSynchronize((hipStream_t)o.stream), "synchronize");
@@ -1165,6 +1188,7 @@ rpd_status rpd_session_create(const rpd_mesh* mesh, const rpd_sites* sites, cons
     S->o = o;
     S->max_sites = opts->max_sites;
     S->max_insert = opts->max_insert;
+    S->mode = opts->insertion;
     S->kmax = o.clip_budget > 0 ? std::min(o.clip_budget, rpd::KMAX) : rpd::KMAX;
     rpd::hip_check(hipStreamCreateWithFlags(&S->stream, hipStreamNonBlocking), "stream");
     for (auto& e : S->ev) rpd::hip_check(hipEventCreate(&e), "hipEventCreate");

@@ -43,7 +43,7 @@ __device__ inline void node_emit(const ShapeArgs& a, unsigned long long key, int
     const int kind = node_kind(key), elem = node_elem(key);
     (kind == 1 ? a.touch_cell : kind == 2 ? a.touch_face : a.touch_edge)[elem] = 1;
   }
-  atomicAdd(&a.node_st[ns], a.sign * (16 + glue));  // removal re-emits the same bits, so this is exact
+  atomicAdd(&a.node_st[ns], a.sign * (NODE_UNIT + glue));  // removal re-emits the same bits, so this is exact
 }
 
 // Workgroup-local sums of the cell terms (chi numerator, piece count, fixed-point volume and moments) for the first
@@ -116,7 +116,7 @@ __device__ void emit_piece(Clipper<T, Topo, Mask, VCAP, EXACT>& c, const ShapeDe
     c.tab[p * c.tst] = 0;
     r -= 1;
     sf += (p < 4) ? (long long)nu[10 + p] : L;
-    if (p < 4 && tn[p] >= 0) cell_glue |= 1 << p;
+    if (p < 4) cell_glue |= tn[p] >= 0 ? 1 << p : 16 << p;  // glue across an interior face; boundary contact
     const int sp = c.env.plane_site(p);
     const bool felem = (p >= 4) && (sp > i);
     long long fv = 0, fe = 0;

@@ -151,7 +151,7 @@ __global__ void k_count_roots(ShapeArgs a, int* parent, int* cell_b0, int* face_
   for (unsigned s = blockIdx.x * blockDim.x + threadIdx.x; s < cap; s += gridDim.x * blockDim.x) {
     unsigned long long key = a.N.keys[s];
     const int st = key == EMPTY_KEY ? 0 : a.node_st[s];
-    if (st < 0 || st >= 32) atomicOr(a.status, ST_INTERNAL);  // every piece is present at most once
+    if (st < 0 || st >= 2 * NODE_UNIT) atomicOr(a.status, ST_INTERNAL);  // every piece is present at most once
     if (!node_live(st)) continue;
     ++nodes;
     if (!node_touched(a, key) || parent[s] != (int)s) continue;  // one root per component

@@ -47,8 +47,12 @@ constexpr int NSPREAD = 64;
 constexpr unsigned long long EMPTY_KEY = ~0ull;
 
 // element-piece state word
-__host__ __device__ inline bool node_live(int st) { return st >= 16; }
+// element-piece state: NODE_UNIT x (times the piece was emitted) + 16 x (boundary faces of the tet the piece touches,
+// cells only) + gluing bits (interior faces of the tet the piece touches)
+constexpr int NODE_UNIT = 256;
+__host__ __device__ inline bool node_live(int st) { return st >= NODE_UNIT; }
 __host__ __device__ inline int node_glue_bits(int st) { return st & 15; }
+__host__ __device__ inline int node_bnd_bits(int st) { return (st >> 4) & 15; }
 
 struct HashTab {
   unsigned long long* keys;  // EMPTY_KEY when free
@@ -153,8 +157,9 @@ struct RoundState {
   int* selpos;                // [max_sites] position of a cell in sel, or -1
   unsigned long long* best;   // [max_insert] packed (hash, tet) of the tet chosen for the cell
   int* ref;                   // [max_insert] smallest tet among the cell's pieces
-  int* tet_used;              // [nt] the tet's sphere has been inserted
-  const float4* table;        // [nt] the sphere to insert for every tet (internal tet order)
+  int* tet_used;              // [slots] the slot's sphere has been inserted (or it has none)
+  const float4* table;        // [slots] the sphere of every slot: per tet (mode 0) or per (tet, face) (mode 1)
+  int mode;                   // 0: caller's per-tet table, hashed pick; 1: shrunk spheres at the furthest surface face
   const int* tet_block;       // [nt] workgroup block of every tet
   int* dirty;                 // [nblk] block flags
   int2* items;                // [nblk] dirty (shape 0, block) items, ascending

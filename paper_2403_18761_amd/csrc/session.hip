@@ -3,8 +3,10 @@
 //
 // One round, all on the device with device-side counts (so the round is captured once as a HIP graph):
 //   1. select up to M violating cells (nonempty, chi != 1 or beta0 > 1), lowest ids first;
-//   2. for each, pick a tet among the cell's pieces (outside the component of its first piece when beta0 > 1) by a
-//      deterministic hash of (tet, round), and insert the sphere the caller's per-tet table gives for that tet;
+//   2. for each, pick a tet among the cell's pieces (outside the component of its first piece when beta0 > 1) and
+//      insert a sphere: either the caller's per-tet table entry of a tet chosen by a deterministic hash of
+//      (tet, round), or (Sec. 4.1.3: the furthest surface triangle of the cell is the pin of sphere shrinking) the
+//      shrunk sphere of the surface face, among those the cell touches, furthest from the cell's sphere centre;
 //   3. mark the workgroup blocks whose tets a new sphere may own (the exact candidate test against the stored U_t);
 //   4. remove the contributions of the dirty blocks computed with the old sites, add them back with the new sites
 //      (every accumulator is an exactly invertible integer), and recompute beta0 of the live element pieces.
@@ -96,7 +98,7 @@ __device__ inline unsigned mix_hash(unsigned long long x) {  // splitmix64 final
 }
 
 __global__ __launch_bounds__(256) void k_pick_tet(HashTab N, const int* node_st, const int* parent, const int* cell_b0,
-                                                  RoundState r) {
+                                                  RoundState r, const float4* tp, const float4* site) {
   extern __shared__ unsigned long long s_best[];
   const int nsel = *r.nsel;
   for (int k = threadIdx.x; k < nsel; k += blockDim.x) s_best[k] = 0ull;
@@ -110,10 +112,32 @@ __global__ __launch_bounds__(256) void k_pick_tet(HashTab N, const int* node_st,
     int k = r.selpos[cell];
     if (k < 0) continue;
     int t = (int)(key & 0xffffffffull);
-    if (r.tet_used[t]) continue;
+    const int bnd = node_bnd_bits(node_st[s]);
+    if (r.mode ? bnd == 0 : r.tet_used[t] != 0) continue;
     if (cell_b0[cell] > 1) {  // pick outside the component of the cell's first piece
       int rs = ht_find(N, (key & ~0xffffffffull) | (unsigned)r.ref[k]);
       if (rs >= 0 && uf_root(parent, rs) == uf_root(parent, (int)s)) continue;
+    }
+    if (r.mode) {  // surface faces of tet t that the piece touches: the one furthest from the cell's centre
+      const float4 c = site[cell];
+      const float4* v = tp + 4 * (size_t)t;
+      for (int f = 0; f < 4; ++f) {
+        const int slot = 4 * t + f;
+        if (!(bnd & (1 << f)) || r.tet_used[slot]) continue;
+        float gx = 0.f, gy = 0.f, gz = 0.f;
+        for (int q = 0; q < 4; ++q)
+          if (q != f) {
+            gx += v[q].x;
+            gy += v[q].y;
+            gz += v[q].z;
+          }
+        gx = gx * (1.f / 3.f) - c.x;
+        gy = gy * (1.f / 3.f) - c.y;
+        gz = gz * (1.f / 3.f) - c.z;
+        const float d = __builtin_sqrtf(gx * gx + gy * gy + gz * gz);  // >= 0: its bits order like the value
+        atomicMax(&s_best[k], ((unsigned long long)__float_as_uint(d) << 32) | (unsigned)slot);
+      }
+      continue;
     }
     unsigned h = mix_hash(((unsigned long long)(unsigned)t << 32) | (unsigned)round);
     atomicMax(&s_best[k], ((unsigned long long)h << 32) | (unsigned)t);
@@ -228,6 +252,70 @@ static int gsz(size_t n) {
   return (int)(g ? g : 1);
 }
 
+// Surface faces of the mesh (faces without a neighbour tet), compacted in any order: the triangle, its centroid as
+// the pin and its unit normal towards the tet's opposite vertex (inward), and the face's slot 4 t + f.
+__global__ void k_surface_faces(const float4* tp, const int* tn, int nt, float* tri, float* pin, float* nrm, int* slot,
+                                int* count) {
+  for (int q = blockIdx.x * blockDim.x + threadIdx.x; q < 4 * nt; q += gridDim.x * blockDim.x) {
+    if (tn[q] >= 0) continue;
+    const int t = q >> 2, f = q & 3;
+    const float4* v = tp + 4 * (size_t)t;
+    double P[3][3];
+    int c = 0;
+    for (int k = 0; k < 4; ++k)
+      if (k != f) {
+        P[c][0] = v[k].x;
+        P[c][1] = v[k].y;
+        P[c][2] = v[k].z;
+        ++c;
+      }
+    const double ux = P[1][0] - P[0][0], uy = P[1][1] - P[0][1], uz = P[1][2] - P[0][2];
+    const double wx = P[2][0] - P[0][0], wy = P[2][1] - P[0][1], wz = P[2][2] - P[0][2];
+    double nx = uy * wz - uz * wy, ny = uz * wx - ux * wz, nz = ux * wy - uy * wx;
+    const double nn = sqrt(nx * nx + ny * ny + nz * nz);
+    const double sgn = ((v[f].x - P[0][0]) * nx + (v[f].y - P[0][1]) * ny + (v[f].z - P[0][2]) * nz) < 0 ? -1.0 : 1.0;
+    const int i = atomicAdd(count, 1);
+    for (int a = 0; a < 3; ++a)
+      for (int b = 0; b < 3; ++b) tri[9 * (size_t)i + 3 * a + b] = (float)P[a][b];
+    for (int b = 0; b < 3; ++b) pin[3 * (size_t)i + b] = (float)((P[0][b] + P[1][b] + P[2][b]) / 3.0);
+    nrm[3 * (size_t)i] = (float)(sgn * nx / nn);
+    nrm[3 * (size_t)i + 1] = (float)(sgn * ny / nn);
+    nrm[3 * (size_t)i + 2] = (float)(sgn * nz / nn);
+    slot[i] = q;
+  }
+}
+__global__ void k_iota(int* p, int n) {
+  for (int k = blockIdx.x * blockDim.x + threadIdx.x; k < n; k += gridDim.x * blockDim.x) p[k] = k;
+}
+// shrunk spheres -> the slots' table entries on the 2^-20 grid (centre rounded, radius rounded down so the ball stays
+// empty); a sphere that does not fit the site range stays unused
+__global__ void k_scatter_spheres(const float4* sph, const int* slot, int n, float4* table, int* used) {
+  for (int k = blockIdx.x * blockDim.x + threadIdx.x; k < n; k += gridDim.x * blockDim.x) {
+    const float4 s = sph[k];
+    const float x = rintf(s.x * 1048576.0f) * (1.0f / 1048576.0f), y = rintf(s.y * 1048576.0f) * (1.0f / 1048576.0f),
+                z = rintf(s.z * 1048576.0f) * (1.0f / 1048576.0f), r = floorf(s.w * 1048576.0f) * (1.0f / 1048576.0f);
+    const bool ok = fabsf(x) <= 1.f && fabsf(y) <= 1.f && fabsf(z) <= 1.f && r >= 0.f && r <= 2.f;
+    table[slot[k]] = make_float4(x, y, z, r);
+    used[slot[k]] = ok ? 0 : 1;
+  }
+}
+
+hipError_t launch_surface_faces(const float4* tp, const int* tn, int nt, float* tri, float* pin, float* nrm, int* slot,
+                                int* count, hipStream_t s) {
+  hipLaunchKernelGGL(k_surface_faces, dim3(gsz(4 * (size_t)nt)), dim3(256), 0, s, tp, tn, nt, tri, pin, nrm, slot,
+                     count);
+  return hipGetLastError();
+}
+hipError_t launch_iota(int* p, int n, hipStream_t s) {
+  hipLaunchKernelGGL(k_iota, dim3(gsz(n)), dim3(256), 0, s, p, n);
+  return hipGetLastError();
+}
+hipError_t launch_scatter_spheres(const float4* sph, const int* slot, int n, float4* table, int* used, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_scatter_spheres, dim3(gsz(n)), dim3(256), 0, s, sph, slot, n, table, used);
+  return hipGetLastError();
+}
+
 hipError_t launch_gather_table(const float4* src, const int* perm, int nt, float4* dst, hipStream_t s) {
   hipLaunchKernelGGL(k_gather_table, dim3(gsz(nt)), dim3(256), 0, s, src, perm, nt, dst);
   return hipGetLastError();
@@ -242,7 +330,7 @@ hipError_t launch_round_front(const RoundState& r, const ShapeArgs& a, const int
   const int scan = std::min(gsz(cap), SCAN_BLOCKS);
   hipLaunchKernelGGL(k_ref_tet, dim3(scan), dim3(256), sizeof(int) * r.max_insert, s, a.N, a.node_st, r);
   hipLaunchKernelGGL(k_pick_tet, dim3(scan), dim3(256), sizeof(unsigned long long) * r.max_insert, s, a.N, a.node_st,
-                     parent, cell_b0, r);
+                     parent, cell_b0, r, tp, a.site);
   hipLaunchKernelGGL(k_insert, dim3(1), dim3(1024), 0, s, r, (float4*)a.site);
   hipLaunchKernelGGL(k_mark_dirty, dim3(gsz(nt)), dim3(256), 0, s, r, tp, nt, a.site, a.tet_U);
   hipLaunchKernelGGL(k_dirty_items, dim3(gsz(nblk)), dim3(256), 0, s, r, nblk);

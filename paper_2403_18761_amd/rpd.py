@@ -60,7 +60,7 @@ class _Stats(C.Structure):
 
 
 class _SessionOpts(C.Structure):
-    _fields_ = [("max_sites", C.c_int32), ("max_insert", C.c_int32), ("build", _Opts)]
+    _fields_ = [("max_sites", C.c_int32), ("max_insert", C.c_int32), ("build", _Opts), ("insertion", C.c_int32)]
 
 
 class _SessionInfo(C.Structure):
@@ -421,28 +421,35 @@ def version() -> str:
     return load().rpd_version().decode()
 
 
+RPD_INSERT_TABLE = 0
+RPD_INSERT_SHRINK = 1
+
+
 class Session:
     """Incremental sphere-insertion session over one mesh (rpd_session_*). ``sites`` and ``table`` are
-    (x, y, z, r) arrays or tensors; ``table`` has one sphere per tet in the caller's tet order."""
+    (x, y, z, r) arrays or tensors; ``table`` has one sphere per tet in the caller's tet order, or is None with
+    insertion=RPD_INSERT_SHRINK (spheres shrunk at the furthest surface triangle of each violating cell)."""
 
     def __init__(self, mesh: Mesh, sites, table, max_sites: int, max_insert: int = 64,
                  precision: int = RPD_FP32_FALLBACK, clip_budget: int = 0, block: int = 0, flags: int = 0,
-                 stream=None):
+                 stream=None, insertion: int = RPD_INSERT_TABLE):
         lib = load()
         keep = []
         dev = _is_torch(sites[0]) and sites[0].is_cuda
-        if dev != (_is_torch(table[0]) and table[0].is_cuda):
+        if table is not None and dev != (_is_torch(table[0]) and table[0].is_cuda):
             raise ValueError("sites and table must both be device tensors or both host arrays")
 
         def mk(q):
             return _Sites(int(q[0].shape[0]), *[_ptr(x, C.c_float, keep) for x in q])
 
-        st, tb = mk(sites), mk(table)
+        st = mk(sites)
+        tb = mk(table) if table is not None else None
         o = _SessionOpts(max_sites, max_insert,
                          _Opts(precision, clip_budget, block, flags | (RPD_DEVICE_PTRS if dev else 0),
-                               _stream_ptr(stream)))
+                               _stream_ptr(stream)), insertion)
         h = C.c_void_p()
-        _check(lib.rpd_session_create(mesh.handle, C.byref(st), C.byref(tb), C.byref(o), C.byref(h)))
+        _check(lib.rpd_session_create(mesh.handle, C.byref(st), C.byref(tb) if tb is not None else None, C.byref(o),
+                                      C.byref(h)))
         self._h = h
         self._lib = lib
         self.mesh = mesh  # the session borrows the mesh

@@ -115,3 +115,74 @@ def test_session_rejects_bad_arguments():
     with pytest.raises(rpd.RPDError) as e:
         rpd.Session(mesh, sites, tuple(bad), max_sites=100)
     assert e.value.code == -1
+
+
+def _inserted_are_shrunk_spheres(prob, s, n0):
+    """Every inserted site is the shrunk sphere (rounded to the grid) of one of the mesh's surface triangles."""
+    from paper_2403_18761_amd import rpd
+
+    tri, n, cen, _, _ = synth.surface_pins(prob)
+    sph = rpd.shrink_spheres(tri, cen, n, np.arange(len(tri), dtype=np.int32)).astype(np.float64)
+    new = s[n0:].astype(np.float64)
+    assert len(new) > 0
+    for q in new:
+        d = np.abs(sph[:, :3] - q[:3]).max(axis=1)
+        k = int(np.argmin(d))
+        assert d[k] <= 4 * 2.0 ** -20 and abs(sph[k, 3] - q[3]) <= 4 * 2.0 ** -20, (q, sph[k])
+
+
+def test_shrink_insertion_equals_rebuild():
+    from paper_2403_18761_amd import rpd
+
+    prob, _ = synth.repair_problem(N=64, n_sites=100, seed=5)
+    log(f"case: shrink-insertion session N64 n100 tets {prob.n_tets}")
+    mesh = _mesh(prob)
+    sess = rpd.Session(mesh, (_dev(prob.sx), _dev(prob.sy), _dev(prob.sz), _dev(prob.sr)), None,
+                       max_sites=100 + 6 * 32, max_insert=32, insertion=rpd.RPD_INSERT_SHRINK)
+    for rounds in (1, 2, 3):
+        sess.run(rounds)
+        info = sess.info()
+        log("after", info["rounds"], "rounds:", info)
+        res = sess.result()
+        cur = extract(res, 0)
+        cur["stats"] = res.stats()
+        _same(cur, _rebuild(mesh, sess.sites()), f"after {info['rounds']} rounds")
+    assert info["n_inserted"] > 0
+    _inserted_are_shrunk_spheres(prob, sess.sites(), 100)
+
+
+def test_shrink_insertion_matches_oracle():
+    import oracle
+
+    from paper_2403_18761_amd import rpd
+
+    oracle.build(force=False)
+    prob = synth.torus_inside(32, 60, 17)
+    log(f"case: shrink-insertion session torus N32 n60 tets {prob.n_tets}")
+    mesh = _mesh(prob)
+    sess = rpd.Session(mesh, (prob.sx, prob.sy, prob.sz, prob.sr), None, max_sites=60 + 40, max_insert=8,
+                       insertion=rpd.RPD_INSERT_SHRINK)
+    sess.run(3)
+    info = sess.info()
+    log("session", info)
+    s = sess.sites()
+    _inserted_are_shrunk_spheres(prob, s, 60)
+    ref = oracle.rpd(prob.with_sites(s[:, 0], s[:, 1], s[:, 2], s[:, 3]), assemble=False)
+    res = sess.result()
+    g = extract(res, 0)
+    g["stats"] = res.stats()
+    assert_parity(g, ref, label="shrink session vs oracle")
+
+
+def test_session_insertion_mode_arguments():
+    from paper_2403_18761_amd import rpd
+
+    prob = synth.torus_core(16, 64, 1)
+    mesh = _mesh(prob)
+    sites = (prob.sx, prob.sy, prob.sz, prob.sr)
+    with pytest.raises(rpd.RPDError) as e:
+        rpd.Session(mesh, sites, None, max_sites=100)  # the table mode needs a table
+    assert e.value.code == -1
+    with pytest.raises(rpd.RPDError) as e:
+        rpd.Session(mesh, sites, None, max_sites=100, insertion=7)
+    assert e.value.code == -1

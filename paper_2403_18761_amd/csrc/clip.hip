@@ -484,23 +484,48 @@ __global__ __launch_bounds__(NT) void k_clip_fast(ShapeArgs a) {
       const double ycx = (y[0][0] + y[1][0] + y[2][0]) * 0.25, ycy = (y[0][1] + y[1][1] + y[2][1]) * 0.25,
                    ycz = (y[0][2] + y[1][2] + y[2][2]) * 0.25;
       double U = INFINITY;
+      int qU = 0x7fffffff;  // the site attaining U (lowest list position on ties)
       for (int q = h; q < nsl; q += tpt) {
         float4 s = s_site[q];
         double ax_ = (double)s.x - o.x, ay_ = (double)s.y - o.y, az_ = (double)s.z - o.z;
         double D = ax_ * ax_ + ay_ * ay_ + az_ * az_ - (double)s.w * s.w;
         double gmx = D;
         for (int v = 0; v < 3; ++v) gmx = fmax(gmx, D - 2.0 * (y[v][0] * ax_ + y[v][1] * ay_ + y[v][2] * az_));
-        U = fmin(U, gmx);
+        if (gmx < U) {
+          U = gmx;
+          qU = q;
+        }
       }
-      for (int off = 1; off < tpt; off <<= 1) U = fmin(U, __shfl_xor(U, off));
+      for (int off = 1; off < tpt; off <<= 1) {
+        const double U2 = __shfl_xor(U, off);
+        const int q2 = __shfl_xor(qU, off);
+        if (U2 < U || (U2 == U && q2 < qU)) {
+          U = U2;
+          qU = q2;
+        }
+      }
       if (a.tet_U && a.sign > 0 && h == 0) a.tet_U[sd.tet_off + t0 + lt] = U;
+      // that site's g at the four vertices: a site it beats at all four owns no point of the tet and its bisector
+      // constrains no piece (the dominator's own bisector already does), so it is not a candidate
+      double gb[4];
+      {
+        const float4 s = s_site[qU];
+        const double ax_ = (double)s.x - o.x, ay_ = (double)s.y - o.y, az_ = (double)s.z - o.z;
+        gb[0] = ax_ * ax_ + ay_ * ay_ + az_ * az_ - (double)s.w * s.w;
+        for (int v = 0; v < 3; ++v) gb[v + 1] = gb[0] - 2.0 * (y[v][0] * ax_ + y[v][1] * ay_ + y[v][2] * az_);
+      }
       for (int q = h; q < nsl; q += tpt) {
         float4 s = s_site[q];
         double ax_ = (double)s.x - o.x, ay_ = (double)s.y - o.y, az_ = (double)s.z - o.z;
         double D = ax_ * ax_ + ay_ * ay_ + az_ * az_ - (double)s.w * s.w;
         double gmn = D;
-        for (int v = 0; v < 3; ++v) gmn = fmin(gmn, D - 2.0 * (y[v][0] * ax_ + y[v][1] * ay_ + y[v][2] * az_));
-        if (gmn <= U) {
+        bool dom = D > gb[0];
+        for (int v = 0; v < 3; ++v) {
+          const double gv = D - 2.0 * (y[v][0] * ax_ + y[v][1] * ay_ + y[v][2] * az_);
+          gmn = fmin(gmn, gv);
+          dom = dom && gv > gb[v + 1];
+        }
+        if (gmn <= U && !dom) {
           int pos = atomicAdd(&s_m[lt], 1);
           if (pos < KRAW) {
             s_cand[lt][pos] = (unsigned char)q;

@@ -196,50 +196,86 @@ hipError_t launch_count_roots(const ShapeArgs& a, int* parent, int* cell_b0, int
 // element lists: compact the live entries of a table (any order), sort exactly those by key, then turn the
 // fractional sums into integers
 // ---------------------------------------------------------------------------------------------------------------
-// append position for the active lanes of a wave (one atomic per wave)
-__device__ inline unsigned long long wave_append(unsigned long long* count) {
-  const unsigned long long active = __ballot(1);
-  const int lane = (int)__lane_id();
-  const int leader = __ffsll((long long)active) - 1;
-  unsigned long long base = 0;
-  if (lane == leader) base = atomicAdd(count, (unsigned long long)__popcll(active));
-  base = __shfl(base, leader);
-  return base + (unsigned long long)__popcll(active & ((1ull << lane) - 1ull));
+// Output position of a thread's n items: exclusive prefix within the 256-thread block, plus the block's base from
+// one global atomic per block (a wave-level atomic on one address for every wave of a large table serialises).
+__device__ inline unsigned long long block_append(int n, unsigned long long* count) {
+  __shared__ int s_w[4];
+  __shared__ unsigned long long s_base;
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  int x = n;
+  for (int off = 1; off < 64; off <<= 1) {
+    const int y = __shfl_up(x, off);
+    if (lane >= off) x += y;
+  }
+  if (lane == 63) s_w[w] = x;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const int tot = s_w[0] + s_w[1] + s_w[2] + s_w[3];
+    s_base = tot ? atomicAdd(count, (unsigned long long)tot) : 0ull;
+  }
+  __syncthreads();
+  int before = 0;
+  for (int q = 0; q < w; ++q) before += s_w[q];
+  return s_base + (unsigned long long)(before + x - n);
 }
 
-__global__ void k_compact_live(const unsigned long long* keys, const int* np, unsigned cap, unsigned long long* out_keys,
-                               int* out_slots, unsigned long long* count) {
-  for (unsigned q = blockIdx.x * blockDim.x + threadIdx.x; q < cap; q += gridDim.x * blockDim.x) {
-    const unsigned long long k = keys[q];
-    if (k == EMPTY_KEY || np[q] <= 0) continue;
-    const unsigned long long idx = wave_append(count);
-    out_keys[idx] = k;
-    out_slots[idx] = (int)q;
+constexpr int CPT = 16;  // table slots per thread in the compactions
+
+__global__ __launch_bounds__(256) void k_compact_live(const unsigned long long* keys, const int* np, unsigned cap,
+                                                      unsigned long long* out_keys, int* out_slots,
+                                                      unsigned long long* count) {
+  const size_t q0 = ((size_t)blockIdx.x * blockDim.x + threadIdx.x) * CPT;
+  int n = 0;
+  for (int k = 0; k < CPT; ++k) {
+    const size_t q = q0 + k;
+    if (q < cap && keys[q] != EMPTY_KEY && np[q] > 0) ++n;
+  }
+  unsigned long long pos = block_append(n, count);
+  for (int k = 0; k < CPT && n; ++k) {
+    const size_t q = q0 + k;
+    if (q < cap && keys[q] != EMPTY_KEY && np[q] > 0) {
+      out_keys[pos] = keys[q];
+      out_slots[pos] = (int)q;
+      ++pos;
+      --n;
+    }
   }
 }
 hipError_t launch_compact_live(const unsigned long long* keys, const int* np, unsigned cap,
                                unsigned long long* out_keys, int* out_slots, unsigned long long* count,
                                hipStream_t s) {
-  hipLaunchKernelGGL(k_compact_live, dim3(grid_for(cap, 256)), dim3(256), 0, s, keys, np, cap, out_keys, out_slots,
-                     count);
+  const size_t per = 256 * (size_t)CPT;
+  hipLaunchKernelGGL(k_compact_live, dim3((unsigned)((cap + per - 1) / per)), dim3(256), 0, s, keys, np, cap, out_keys,
+                     out_slots, count);
   return hipGetLastError();
 }
 
 // RPV quadruples (i, j, k, l) of the counted set (key = edge slot of (i, j, k) << 21 | l), compacted
-__global__ void k_rpv_compact(HashTab Q, const int* cnt, const unsigned long long* ekeys, int4* out,
-                              unsigned long long* count) {
-  const unsigned cap = Q.mask + 1;
-  for (unsigned q = blockIdx.x * blockDim.x + threadIdx.x; q < cap; q += gridDim.x * blockDim.x) {
-    const unsigned long long k = Q.keys[q];
-    if (k == EMPTY_KEY || cnt[q] <= 0) continue;
-    const unsigned long long e = ekeys[k >> 21];
-    const unsigned long long idx = wave_append(count);
-    out[idx] = make_int4((int)(e >> 42), (int)((e >> 21) & 0x1fffff), (int)(e & 0x1fffff), (int)(k & 0x1fffff));
+__global__ __launch_bounds__(256) void k_rpv_compact(HashTab Q, const int* cnt, const unsigned long long* ekeys,
+                                                     int4* out, unsigned long long* count) {
+  const size_t cap = (size_t)Q.mask + 1;
+  const size_t q0 = ((size_t)blockIdx.x * blockDim.x + threadIdx.x) * CPT;
+  int n = 0;
+  for (int k = 0; k < CPT; ++k) {
+    const size_t q = q0 + k;
+    if (q < cap && Q.keys[q] != EMPTY_KEY && cnt[q] > 0) ++n;
+  }
+  unsigned long long pos = block_append(n, count);
+  for (int k = 0; k < CPT && n; ++k) {
+    const size_t q = q0 + k;
+    if (q < cap && Q.keys[q] != EMPTY_KEY && cnt[q] > 0) {
+      const unsigned long long key = Q.keys[q];
+      const unsigned long long e = ekeys[key >> 21];
+      out[pos] = make_int4((int)(e >> 42), (int)((e >> 21) & 0x1fffff), (int)(e & 0x1fffff), (int)(key & 0x1fffff));
+      ++pos;
+      --n;
+    }
   }
 }
 hipError_t launch_rpv_compact(const HashTab& Q, const int* cnt, const unsigned long long* ekeys, int4* out,
                               unsigned long long* count, hipStream_t s) {
-  hipLaunchKernelGGL(k_rpv_compact, dim3(grid_for((size_t)Q.mask + 1, 256)), dim3(256), 0, s, Q, cnt, ekeys, out,
+  const size_t per = 256 * (size_t)CPT, cap = (size_t)Q.mask + 1;
+  hipLaunchKernelGGL(k_rpv_compact, dim3((unsigned)((cap + per - 1) / per)), dim3(256), 0, s, Q, cnt, ekeys, out,
                      count);
   return hipGetLastError();
 }

@@ -447,34 +447,27 @@ static bool collect(DeviceState& D, const std::vector<ShapeDesc>& hd, const Shap
     out.cen.assign(all_cen + 3 * (size_t)off, all_cen + 3 * (size_t)end);
     out.cell_keys.resize(n);
     std::iota(out.cell_keys.begin(), out.cell_keys.end(), 0);
-    out.face_keys.clear();
-    out.face_chi.clear();
-    out.face_b0.clear();
-    while (fpos < nf && all_fk[2 * fpos] < end) {
-      out.face_keys.push_back(all_fk[2 * fpos] - off);
-      out.face_keys.push_back(all_fk[2 * fpos + 1] - off);
-      out.face_chi.push_back(all_fchi[fpos]);
-      out.face_b0.push_back(all_fb0[fpos]);
-      ++fpos;
-    }
-    out.edge_keys.clear();
-    out.edge_chi.clear();
-    out.edge_b0.clear();
-    out.edge_len.clear();
-    out.edge_alpha.clear();
-    while (epos < ne && all_ek[3 * epos] < end) {
-      for (int c = 0; c < 3; ++c) out.edge_keys.push_back(all_ek[3 * epos + c] - off);
-      out.edge_chi.push_back(all_echi[epos]);
-      out.edge_b0.push_back(all_eb0[epos]);
-      out.edge_len.push_back(all_elen[epos]);
-      out.edge_alpha.push_back(all_ealpha[epos]);
-      ++epos;
-    }
-    out.rpv_keys.clear();
-    while (qpos < nq && all_rpv[4 * qpos] < end) {
-      for (int c = 0; c < 4; ++c) out.rpv_keys.push_back(all_rpv[4 * qpos + c] - off);
-      ++qpos;
-    }
+    // element lists: one contiguous run per shape; keys shifted to the shape's own site ids
+    size_t fend = fpos, eend = epos, qend = qpos;
+    while (fend < nf && all_fk[2 * fend] < end) ++fend;
+    while (eend < ne && all_ek[3 * eend] < end) ++eend;
+    while (qend < nq && all_rpv[4 * qend] < end) ++qend;
+    auto shifted = [off](std::vector<int32_t>& dst, const int* src, size_t n) {
+      dst.resize(n);
+      for (size_t k = 0; k < n; ++k) dst[k] = src[k] - off;
+    };
+    shifted(out.face_keys, all_fk + 2 * fpos, 2 * (fend - fpos));
+    out.face_chi.assign(all_fchi + fpos, all_fchi + fend);
+    out.face_b0.assign(all_fb0 + fpos, all_fb0 + fend);
+    shifted(out.edge_keys, all_ek + 3 * epos, 3 * (eend - epos));
+    out.edge_chi.assign(all_echi + epos, all_echi + eend);
+    out.edge_b0.assign(all_eb0 + epos, all_eb0 + eend);
+    out.edge_len.assign(all_elen + epos, all_elen + eend);
+    out.edge_alpha.assign(all_ealpha + epos, all_ealpha + eend);
+    shifted(out.rpv_keys, all_rpv + 4 * qpos, 4 * (qend - qpos));
+    fpos = fend;
+    epos = eend;
+    qpos = qend;
     out.pc_t.clear();
     out.pc_i.clear();
     out.pc_geo.clear();

@@ -712,7 +712,7 @@ __device__ inline void push_overflow(const ShapeArgs& a, int4 item) {
 // compacted in ascending site order by ballots), drop dominated candidates and rank-sort the rest, then clip the
 // pieces with FP64 polytopes (lanes interleaved slot by slot).
 template <bool LDS>
-__global__ __launch_bounds__(64) void k_clip_slow(ShapeArgs a, unsigned char* scratch, int item_begin, int item_end) {
+__global__ __launch_bounds__(64, LDS ? 1 : 2) void k_clip_slow(ShapeArgs a, unsigned char* scratch, int item_begin, int item_end) {
   typedef SlowCfg<LDS> C;
   constexpr int CL = C::CL, KC = C::KCAP;
   __shared__ Coord4<double>::type s_xyz[LDS ? C::VCAP * CL : 1];

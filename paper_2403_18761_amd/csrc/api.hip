@@ -149,7 +149,10 @@ struct DeviceState {
     capF = pow2_cap((32 * (size_t)ns + 1024) * scale);
     capE = pow2_cap((32 * (size_t)ns + 1024) * scale);
     capQ = pow2_cap((16 * (size_t)ns + 1024) * scale);
-    capN = pow2_cap((6 * (size_t)nt + 4096) * scale);
+    // element pieces: 12 slots per tet keeps the probe chains of the emission's inserts short; past 2^23 slots
+    // the table scans of the gluing pass cost more than that saves, so large meshes get 6
+    capN = pow2_cap((12 * (size_t)nt + 4096) * scale);
+    if (capN > (1u << 23)) capN = std::max(1u << 23, pow2_cap((6 * (size_t)nt + 4096) * scale));
     def_cap = (int)std::min<size_t>((4 * (size_t)nt + 4096) * scale, 1u << 30);
     piece_cap = keep_pieces ? (int)std::min<size_t>((8 * (size_t)nt + 1024) * scale, 1u << 30) : 0;
     site.alloc(sizeof(float4) * (size_t)ns);

@@ -482,9 +482,13 @@ __device__ inline long long w_edge(int p0, int p1, const unsigned* nu, long long
 // ---------------------------------------------------------------------------------------------------------------
 // hash tables (open addressing, linear probing)
 // ---------------------------------------------------------------------------------------------------------------
-__device__ inline unsigned hslot(unsigned long long key, unsigned mask) {
-  unsigned long long x = key * 0x9E3779B97F4A7C15ull;
-  x ^= x >> 29;
+__device__ inline unsigned hslot(unsigned long long key, unsigned mask) {  // 64-bit finaliser: every key bit mixes
+  unsigned long long x = key;
+  x ^= x >> 33;
+  x *= 0xff51afd7ed558ccdull;
+  x ^= x >> 33;
+  x *= 0xc4ceb9fe1a85ec53ull;
+  x ^= x >> 33;
   return (unsigned)x & mask;
 }
 __device__ inline int ht_insert(const HashTab& h, unsigned long long key, int* status) {

@@ -187,25 +187,27 @@ struct DeviceState {
     slow.alloc(slow_scratch_bytes(waves));
   }
 
-  void clear(hipStream_t s) {
+  void clear(hipStream_t s) {  // one launch for every accumulator and table
     const size_t ns = (size_t)ns_cap;
-    hip_check(launch_fill_i32(status.as<int>(), 0, 4, s), "fill");
-    hip_check(launch_fill_u64(cell_chi.as<unsigned long long>(), 0, ns, s), "fill");
-    hip_check(launch_fill_u64(cell_geo.as<unsigned long long>(), 0, 4 * ns, s), "fill");
-    hip_check(launch_fill_i32(cell_np.as<int>(), 0, ns, s), "fill");
-    hip_check(launch_fill_u64(fkeys.as<unsigned long long>(), EMPTY_KEY, capF, s), "fill");
-    hip_check(launch_fill_u64(face_chi.as<unsigned long long>(), 0, capF, s), "fill");
-    hip_check(launch_fill_i32(face_np.as<int>(), 0, capF, s), "fill");
-    hip_check(launch_fill_u64(ekeys.as<unsigned long long>(), EMPTY_KEY, capE, s), "fill");
-    hip_check(launch_fill_u64(edge_chi.as<unsigned long long>(), 0, capE, s), "fill");
-    hip_check(launch_fill_i32(edge_np.as<int>(), 0, capE, s), "fill");
-    hip_check(launch_fill_u64(edge_len.as<unsigned long long>(), 0, capE, s), "fill");
-    hip_check(launch_fill_u64(qkeys.as<unsigned long long>(), EMPTY_KEY, capQ, s), "fill");
-    hip_check(launch_fill_i32(rpv_cnt.as<int>(), 0, capQ, s), "fill");
-    hip_check(launch_fill_u64(nkeys.as<unsigned long long>(), EMPTY_KEY, capN, s), "fill");
-    hip_check(launch_fill_i32(node_st.as<int>(), 0, capN, s), "fill");
-    hip_check(launch_fill_u64(cnt(), 0, NCOUNTERS + 8 + (size_t)NSPREAD * NCOUNTERS, s), "fill");
-    if (touch.p) hip_check(launch_fill_i32(touch.as<int>(), 0, touch_words(), s), "fill");
+    FillList L{};
+    L.add(status.p, 0, 4, 4);
+    L.add(cell_chi.p, 0, ns, 8);
+    L.add(cell_geo.p, 0, 4 * ns, 8);
+    L.add(cell_np.p, 0, ns, 4);
+    L.add(fkeys.p, EMPTY_KEY, capF, 8);
+    L.add(face_chi.p, 0, capF, 8);
+    L.add(face_np.p, 0, capF, 4);
+    L.add(ekeys.p, EMPTY_KEY, capE, 8);
+    L.add(edge_chi.p, 0, capE, 8);
+    L.add(edge_np.p, 0, capE, 4);
+    L.add(edge_len.p, 0, capE, 8);
+    L.add(qkeys.p, EMPTY_KEY, capQ, 8);
+    L.add(rpv_cnt.p, 0, capQ, 4);
+    L.add(nkeys.p, EMPTY_KEY, capN, 8);
+    L.add(node_st.p, 0, capN, 4);
+    L.add(cnt(), 0, NCOUNTERS + 8 + (size_t)NSPREAD * NCOUNTERS, 8);
+    if (touch.p) L.add(touch.p, 0, touch_words(), 4);
+    hip_check(launch_fill_multi(L, s), "fill");
   }
 
   // the touched-element flags for an incremental pass

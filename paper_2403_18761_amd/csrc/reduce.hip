@@ -19,6 +19,19 @@ __global__ void k_fill_i32(int* p, int v, size_t n) {
   for (size_t k = blockIdx.x * (size_t)blockDim.x + threadIdx.x; k < n; k += (size_t)gridDim.x * blockDim.x) p[k] = v;
 }
 
+// several fills in one launch (blockIdx.y = job): each job writes n values of 4 or 8 bytes
+__global__ void k_fill_multi(FillList L) {
+  const FillJob j = L.job[blockIdx.y];
+  const size_t step = (size_t)gridDim.x * blockDim.x;
+  if (j.width == 8) {
+    unsigned long long* p = (unsigned long long*)j.p;
+    for (size_t k = blockIdx.x * (size_t)blockDim.x + threadIdx.x; k < j.n; k += step) p[k] = j.v;
+  } else {
+    int* p = (int*)j.p;
+    for (size_t k = blockIdx.x * (size_t)blockDim.x + threadIdx.x; k < j.n; k += step) p[k] = (int)j.v;
+  }
+}
+
 static int grid_for(size_t n, int bs) {
   size_t g = (n + bs - 1) / bs;
   if (g > 65536) g = 65536;
@@ -40,6 +53,13 @@ hipError_t launch_zero_stats(unsigned long long* stats, int c0, int n, hipStream
   return hipGetLastError();
 }
 
+hipError_t launch_fill_multi(const FillList& L, hipStream_t s) {
+  if (L.n <= 0) return hipSuccess;
+  size_t big = 1;
+  for (int k = 0; k < L.n; ++k) big = std::max(big, L.job[k].n);
+  hipLaunchKernelGGL(k_fill_multi, dim3(std::min(grid_for(big, 256), 8192), L.n), dim3(256), 0, s, L);
+  return hipGetLastError();
+}
 hipError_t launch_fill_i32(int* p, int v, size_t n, hipStream_t s) {
   if (!n) return hipSuccess;
   hipLaunchKernelGGL(k_fill_i32, dim3(grid_for(n, 256)), dim3(256), 0, s, p, v, n);

@@ -15,6 +15,20 @@ hipError_t launch_clip_slow(const ShapeArgs& a, unsigned char* scratch, int wave
 
 // reduce.hip
 hipError_t launch_fill_u64(unsigned long long* p, unsigned long long v, size_t n, hipStream_t s);
+struct FillJob {
+  void* p;
+  unsigned long long v;
+  size_t n;
+  int width;  // 4 or 8 bytes
+};
+struct FillList {
+  FillJob job[24];
+  int n;
+  void add(void* ptr, unsigned long long val, size_t count, int w) {
+    if (count) job[n++] = FillJob{ptr, val, count, w};
+  }
+};
+hipError_t launch_fill_multi(const FillList& L, hipStream_t s);
 hipError_t launch_fill_i32(int* p, int v, size_t n, hipStream_t s);
 // zero counters [c0, c0 + n) in every spread copy of the statistics
 hipError_t launch_zero_stats(unsigned long long* stats, int c0, int n, hipStream_t s);

@@ -602,6 +602,15 @@ static bool run_batch(const rpd_mesh* const* meshes, const rpd_sites* sites, int
   long long ns_tot = 0, nt_tot = 0;
   std::vector<ShapeDesc> hd = shape_table(meshes, nsites.data(), nsh, &ns_tot, &nt_tot);
   std::vector<int2> items = work_items(hd);
+  if (o.flags & RPD_SHUFFLE_QUEUE) {  // a fixed permutation: results must not depend on the processing order
+    unsigned long long x = 0x9E3779B97F4A7C15ull;
+    for (size_t k = items.size(); k > 1; --k) {
+      x ^= x << 13;
+      x ^= x >> 7;
+      x ^= x << 17;
+      std::swap(items[k - 1], items[x % k]);
+    }
+  }
   DBuf dshapes(sizeof(ShapeDesc) * nsh), ditems(sizeof(int2) * std::max<size_t>(items.size(), 1));
   hip_check(hipMemcpyAsync(dshapes.p, hd.data(), sizeof(ShapeDesc) * nsh, hipMemcpyHostToDevice, s), "upload");
   if (!items.empty())

@@ -26,6 +26,7 @@ RPD_FORCE_SLOW_PATH = 1 << 3
 RPD_TIMING = 1 << 4
 RPD_KEEP_PIECES = 1 << 5
 RPD_OWNER_WEIGHTS = 1 << 6
+RPD_SHUFFLE_QUEUE = 1 << 7
 
 _f32p = C.POINTER(C.c_float)
 _i32p = C.POINTER(C.c_int32)

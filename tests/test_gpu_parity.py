@@ -97,12 +97,18 @@ def test_genus3_small():
 
 
 def test_deterministic_bits():
+    """Repeated runs, and a shuffled order of the work items, give the same bits (integer accumulation)."""
+    from paper_2403_18761_amd import rpd
+    from tests.gpu_util import ELEMENT_ARRAYS
+
     prob = synth.torus_inside(32, 500, 9)
     log("case: determinism")
     a = run_gpu(prob)
     b = run_gpu(prob)
-    for k in ("cell_chi", "cell_beta0", "face_keys", "face_chi", "edge_keys", "edge_chi", "rpv_keys", "cell_vol"):
-        np.testing.assert_array_equal(a[k], b[k])
+    c = run_gpu(prob, flags=rpd.RPD_SHUFFLE_QUEUE)
+    for k in ELEMENT_ARRAYS:
+        np.testing.assert_array_equal(a[k], b[k], err_msg=k)
+        np.testing.assert_array_equal(a[k], c[k], err_msg=f"shuffled {k}")
 
 
 def test_single_site_is_the_solid():

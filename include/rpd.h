@@ -137,6 +137,9 @@ typedef struct rpd_result rpd_result;
  * Errors: RPD_E_INVALID (off-grid or out-of-range values, bad indices, non-positive orientation),
  * RPD_E_MESH (a face in more than two tets, more than one component, lcm of multiplicities of 2^31 or more). */
 rpd_status rpd_mesh_create(const rpd_mesh_desc* desc, uint32_t flags, void* stream, rpd_mesh** out);
+/* A mesh keeps one piece of mutable state: the time each of its blocks took in the last rpd_build that used it,
+ * which orders the next build's work (heaviest first). It changes no result. Builds that share a mesh may run
+ * from several threads (the hint is locked); rpd_mesh_free must not overlap a build that uses the mesh. */
 rpd_status rpd_mesh_get_info(const rpd_mesh* mesh, rpd_mesh_info* info);
 void rpd_mesh_free(rpd_mesh* mesh);
 

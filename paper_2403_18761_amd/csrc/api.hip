@@ -551,21 +551,56 @@ static std::vector<ShapeDesc> shape_table(const rpd_mesh* const* meshes, const i
   return hd;
 }
 
-// (shape, block) work items, heaviest first (estimated cost: block tets x shape sites, the box filter dominates
-// for large site counts); blocks of one shape stay in Morton order
-static std::vector<int2> work_items(const std::vector<ShapeDesc>& hd) {
+// (shape, block) work items, heaviest first. The hardware dispatcher hands workgroups to compute units in grid
+// order as they free up, so a heavy item dispatched late sets the kernel's tail. The cost of an item is its
+// fast-kernel time in the last build on the same mesh when every mesh of the call has one, else the estimate
+// shape sites x block tets (the box filter scans every site of the shape; clipping grows with the tets).
+// Ties keep the shapes' order and the blocks' Morton order. The order never changes a result.
+static std::vector<int2> work_items(const std::vector<ShapeDesc>& hd, const rpd_mesh* const* meshes) {
   const int nsh = (int)hd.size();
   std::vector<int2> items;
-  std::vector<int> order(nsh);
-  std::iota(order.begin(), order.end(), 0);
-  std::stable_sort(order.begin(), order.end(), [&](int x, int y) {
-    double cx = (double)hd[x].ns * hd[x].nt / std::max(1, hd[x].nblk),
-           cy = (double)hd[y].ns * hd[y].nt / std::max(1, hd[y].nblk);
-    return cx > cy;
-  });
-  for (int k : order)
-    for (int b = 0; b < hd[k].nblk; ++b) items.push_back(make_int2(k, b));
-  return items;
+  std::vector<unsigned long long> cost;
+  bool learned = true;
+  for (int k = 0; k < nsh && learned; ++k) {
+    rpd_mesh* m = const_cast<rpd_mesh*>(meshes[k]);
+    std::lock_guard<std::mutex> g(m->cost_mu);
+    learned = (int)m->blk_cost.size() == hd[k].nblk;
+  }
+  for (int k = 0; k < nsh; ++k) {
+    rpd_mesh* m = const_cast<rpd_mesh*>(meshes[k]);
+    std::unique_lock<std::mutex> g(m->cost_mu, std::defer_lock);
+    if (learned) g.lock();
+    for (int b = 0; b < hd[k].nblk; ++b) {
+      items.push_back(make_int2(k, b));
+      cost.push_back(learned ? (unsigned long long)m->blk_cost[b]
+                             : (unsigned long long)hd[k].ns * (unsigned long long)(m->hblk[b + 1] - m->hblk[b]));
+    }
+  }
+  // stable counting sort, descending, on the top 16 bits of the cost range
+  unsigned long long cmax = 1;
+  for (unsigned long long c : cost) cmax = std::max(cmax, c);
+  int shift = 0;
+  while ((cmax >> shift) > 0xffffull) ++shift;
+  std::vector<int> start(65537, 0);
+  for (unsigned long long c : cost) ++start[0xffff - (int)(c >> shift) + 1];
+  for (int d = 0; d < 65536; ++d) start[d + 1] += start[d];
+  std::vector<int2> out(items.size());
+  for (size_t k = 0; k < items.size(); ++k) out[start[0xffff - (int)(cost[k] >> shift)]++] = items[k];
+  return out;
+}
+
+// Records the fast-kernel time of every item as its mesh's block costs (see work_items).
+static void learn_costs(const std::vector<int2>& items, const unsigned* ticks,
+                        const std::vector<ShapeDesc>& hd, const rpd_mesh* const* meshes) {
+  const int nsh = (int)hd.size();
+  std::vector<std::vector<unsigned>> per(nsh);
+  for (int k = 0; k < nsh; ++k) per[k].assign(hd[k].nblk, 0);
+  for (size_t k = 0; k < items.size(); ++k) per[items[k].x][items[k].y] = ticks[k];
+  for (int k = 0; k < nsh; ++k) {  // a mesh that several shapes share keeps the last one's times
+    rpd_mesh* m = const_cast<rpd_mesh*>(meshes[k]);
+    std::lock_guard<std::mutex> g(m->cost_mu);
+    m->blk_cost.swap(per[k]);
+  }
 }
 
 static void upload_sites(DeviceState& D, const rpd_sites* sites, const std::vector<ShapeDesc>& hd, bool dev,
@@ -601,7 +636,7 @@ static bool run_batch(const rpd_mesh* const* meshes, const rpd_sites* sites, int
   for (int k = 0; k < nsh; ++k) nsites[k] = sites[k].n_sites;
   long long ns_tot = 0, nt_tot = 0;
   std::vector<ShapeDesc> hd = shape_table(meshes, nsites.data(), nsh, &ns_tot, &nt_tot);
-  std::vector<int2> items = work_items(hd);
+  std::vector<int2> items = work_items(hd, meshes);
   if (o.flags & RPD_SHUFFLE_QUEUE) {  // a fixed permutation: results must not depend on the processing order
     unsigned long long x = 0x9E3779B97F4A7C15ull;
     for (size_t k = items.size(); k > 1; --k) {
@@ -621,14 +656,25 @@ static bool run_batch(const rpd_mesh* const* meshes, const rpd_sites* sites, int
   upload_sites(D, sites, hd, dev, s);
   const int kmax = o.clip_budget > 0 ? std::min(o.clip_budget, KMAX) : KMAX;
   ShapeArgs a = D.args(dshapes.as<ShapeDesc>(), ditems.as<int2>(), (int)items.size(), o.flags, kmax, +1);
+  HostPinned ticks_host(sizeof(unsigned) * items.size() + 16);  // pinned: the copy does not stall the host
+  struct DrainOnExit {  // an early exit (exception) must not leave the copy into ticks_host pending
+    hipStream_t s;
+    ~DrainOnExit() { (void)hipStreamSynchronize(s); }
+  } drain{s};
+  DBuf dcost(sizeof(unsigned) * std::max<size_t>(items.size(), 1));
+  a.item_cost = dcost.as<unsigned>();
   Timing tm((o.flags & RPD_TIMING) != 0);
   tm.mark(0, s);
   hip_check(launch_clip_fast(a, o.precision, o.block, s), "clip kernel");
   tm.mark(1, s);
+  if (!items.empty())  // read by the host after collect's synchronisation
+    hip_check(hipMemcpyAsync(ticks_host.p, dcost.p, sizeof(unsigned) * items.size(), hipMemcpyDeviceToHost, s),
+              "download");
   hip_check(launch_clip_slow(a, D.slow.as<unsigned char>(), D.waves, s), "deferred clip kernel");
   tm.mark(2, s);
   D.components(a, s);
   if (!collect(D, hd, dshapes.as<ShapeDesc>(), meshes, s, tm, outs, st)) return false;
+  learn_costs(items, (const unsigned*)ticks_host.p, hd, meshes);
   st.ms_clip = tm.ms(0, 1);
   st.ms_deferred = tm.ms(1, 2);
   st.ms_reduce = tm.ms(2, 3);

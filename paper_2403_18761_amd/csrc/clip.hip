@@ -375,6 +375,7 @@ __global__ __launch_bounds__(NT) void k_clip_fast(ShapeArgs a) {
     for (int d = 0; d < 4; ++d) s_acc_geo[4 * k + d] = 0;
   }
   unsigned long long n_pairs = 0, n64 = 0, n_cand = 0;
+  const unsigned long long clock0 = wall_clock64();
   // One workgroup per (shape, block) item; items are ordered heaviest first and the hardware dispatcher hands
   // them to compute units in that order as they free up, which is the work queue. (A persistent loop that pulls
   // items from an atomic counter computes the same thing but costs about 100 more VGPRs per thread here.)
@@ -620,6 +621,8 @@ __global__ __launch_bounds__(NT) void k_clip_fast(ShapeArgs a) {
     cl.env.sid = s_sid;
     cl.env.cidx8 = s_cand[lt];
     cl.env.cidx32 = nullptr;
+    cl.env.csite = nullptr;
+    cl.env.ncs = 0;
     cl.env.ci = ci;
     cl.env.si = s_site[s_cand[lt][ci]];
     cl.env.site_i = s_sid[s_cand[lt][ci]];
@@ -659,6 +662,10 @@ __global__ __launch_bounds__(NT) void k_clip_fast(ShapeArgs a) {
   } while (false);
   if (tid < 4) s_cnt[tid] = 0;
   __syncthreads();
+  if (a.item_cost && tid == 0) {  // the item's duration (every thread is past it), a scheduling hint for the next build
+    const int nit = a.nitems_dev ? *a.nitems_dev : a.nitems;
+    if ((int)blockIdx.x < nit) a.item_cost[blockIdx.x] = (unsigned)min(wall_clock64() - clock0, 0xffffffffull);
+  }
   atomicAdd(&s_cnt[0], n_pairs);
   atomicAdd(&s_cnt[1], n64);
   __syncthreads();
@@ -720,6 +727,11 @@ __global__ __launch_bounds__(64, LDS ? 1 : 2) void k_clip_slow(ShapeArgs a, unsi
   __shared__ unsigned char s_tab[LDS ? (4 + KC) * CL : 1];
   __shared__ int s_cand[LDS ? 2 * KC : 1];
   __shared__ double s_key[LDS ? 6 * KC : 1];
+  // on-chip copies for the clipping loop, whose plane rebuilds would otherwise wait on memory: the item's tet and
+  // the sites of its first SC candidates (sorted positions)
+  constexpr int SC = 256;
+  __shared__ float4 s_tv4[4];
+  __shared__ float4 s_csite[SC];
   const int n_main = (int)min(min(a.counters[C_DEFER_ITEMS], (unsigned long long)a.deferred_cap),
                               (unsigned long long)item_end);
   const int n_over = LDS ? 0 : (int)min(a.counters[C_DEFER2], (unsigned long long)a.deferred2_cap);
@@ -749,6 +761,7 @@ __global__ __launch_bounds__(64, LDS ? 1 : 2) void k_clip_slow(ShapeArgs a, unsi
     const float4* ssite = a.site + sd.site_off;
     float4 tv[4];
     for (int v = 0; v < 4; ++v) tv[v] = sd.tp[4 * (size_t)t + v];
+    if (lane < 4) s_tv4[lane] = sd.tp[4 * (size_t)t + lane];
     const float4 o = tv[0];
     double y[3][3];
     for (int v = 1; v < 4; ++v) {
@@ -845,6 +858,7 @@ __global__ __launch_bounds__(64, LDS ? 1 : 2) void k_clip_slow(ShapeArgs a, unsi
       }
       scand[rank] = cand[x];
       skey[rank] = kx;
+      if (rank < SC) s_csite[rank] = a.site[cand[x]];
     }
     if (lane < CL)
       for (int k = 0; k < 4 + m; ++k) tab[CL * k] = 0;  // the plane ids of this item start unpaired
@@ -862,12 +876,14 @@ __global__ __launch_bounds__(64, LDS ? 1 : 2) void k_clip_slow(ShapeArgs a, unsi
       cl.np = 4 + m;
       cl.n64 = 0;
       cl.nex = 0;
-      cl.env.tv = tv;
+      cl.env.tv = s_tv4;
       cl.env.faceT = nullptr;
       cl.env.sites = a.site;
       cl.env.sid = nullptr;  // candidates hold batch-global site ids directly
       cl.env.cidx8 = nullptr;
       cl.env.cidx32 = scand;
+      cl.env.csite = s_csite;
+      cl.env.ncs = min(m, SC);
       cl.env.ci = ci;
       cl.env.si = a.site[scand[ci]];
       cl.env.site_i = scand[ci];

@@ -124,6 +124,7 @@ struct ShapeArgs {
   int* status;
   unsigned flags;        // RPD_FORCE_* / RPD_KEEP_PIECES as in rpd.h
   int kmax;              // fast-path candidate budget (<= KMAX)
+  unsigned* item_cost;   // optional [nitems]: wall-clock ticks each work item took in the fast kernel
 };
 
 // shape of a batch-global id by binary search over the shapes' offsets

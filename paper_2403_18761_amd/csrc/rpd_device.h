@@ -419,12 +419,14 @@ struct TetEnv {
   const int* sid;        // site ids, indexed through cidx
   const unsigned char* cidx8;  // candidate -> index into sites/sid (fast path)
   const int* cidx32;     // candidate -> index (slow path)
+  const float4* csite;   // the first ncs candidates' sites by candidate position (slow path: on chip), or nullptr
+  int ncs;
   int ci;                // candidate position of the piece's own site
   float4 si;             // own site
   int site_i;            // own site id
 
   __device__ int cand_index(int c) const { return cidx8 ? (int)cidx8[c] : cidx32[c]; }
-  __device__ float4 cand_site(int c) const { return sites[cand_index(c)]; }
+  __device__ float4 cand_site(int c) const { return c < ncs ? csite[c] : sites[cand_index(c)]; }
   __device__ int cand_id(int c) const { return sid ? sid[cand_index(c)] : cand_index(c); }
   __device__ int plane_site(int p) const { return p < 4 ? -1 : cand_id(p - 4); }
 

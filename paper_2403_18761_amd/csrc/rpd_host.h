@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -88,6 +89,10 @@ struct rpd_mesh {
   rpd::DBuf blk;   // int [nblk + 1]: workgroup blocks over the internal order
   int32_t nblk = 0;
   std::vector<int> hblk;  // host copy of blk
+  // Fast-kernel time of every block in the last build that used this mesh: a dispatch-order hint for the next
+  // build (heaviest first); never read by any kernel.
+  std::mutex cost_mu;
+  std::vector<unsigned> blk_cost;
 };
 
 namespace rpd {

@@ -111,6 +111,39 @@ def test_deterministic_bits():
         np.testing.assert_array_equal(a[k], c[k], err_msg=f"shuffled {k}")
 
 
+def test_learned_dispatch_order_gives_the_same_bits():
+    """Later builds on one mesh dispatch its blocks by the times measured in the build before (heaviest first):
+    the order changes, the bits do not, also in a batch that holds the mesh twice with different sites."""
+    import torch
+
+    from paper_2403_18761_amd import rpd
+    from tests.gpu_util import ELEMENT_ARRAYS, extract
+
+    prob = synth.torus_inside(32, 500, 9)
+    other = synth.torus_inside(32, 300, 4)
+    log("case: learned dispatch order")
+    dev = torch.device("cuda:0")
+
+    def t(a, dt=torch.float32):
+        return torch.as_tensor(np.ascontiguousarray(a), dtype=dt, device=dev)
+
+    mesh = rpd.Mesh(t(prob.vx), t(prob.vy), t(prob.vz), t(prob.tv.reshape(-1), torch.int32))
+    s1 = (t(prob.sx), t(prob.sy), t(prob.sz), t(prob.sr))
+    s2 = (t(other.sx), t(other.sy), t(other.sz), t(other.sr))
+    first = extract(rpd.build([mesh], [s1]), 0)  # estimated order
+    for _ in range(2):
+        again = extract(rpd.build([mesh], [s1]), 0)  # measured order
+        for k in ELEMENT_ARRAYS:
+            np.testing.assert_array_equal(first[k], again[k], err_msg=k)
+    lone = extract(rpd.build([mesh], [s2]), 0)
+    res = rpd.build([mesh, mesh], [s2, s1])
+    for _ in range(2):
+        res = rpd.build([mesh, mesh], [s2, s1])
+        for k in ELEMENT_ARRAYS:
+            np.testing.assert_array_equal(extract(res, 0)[k], lone[k], err_msg=f"batch shape 0 {k}")
+            np.testing.assert_array_equal(extract(res, 1)[k], first[k], err_msg=f"batch shape 1 {k}")
+
+
 def test_single_site_is_the_solid():
     base = synth.torus_core(16, 64, 1)
     c = synth.quantize([[0.013, -0.021, 0.007]])

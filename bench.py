@@ -88,12 +88,12 @@ def workload(name):
     raise SystemExit(f"unknown workload {name}")
 
 
-def time_builds(meshes, sites, precision, steps, warmup, stream, block=0, clip_budget=0):
+def time_builds(meshes, sites, precision, steps, warmup, stream, block=0, clip_budget=0, flags=0):
     import torch
 
     from paper_2403_18761_amd import rpd
 
-    flags = rpd.RPD_TIMING
+    flags |= rpd.RPD_TIMING
     kw = dict(precision=precision, flags=flags, stream=stream, block=block, clip_budget=clip_budget)
     for _ in range(warmup):
         rpd.build(meshes, sites, **kw)
@@ -389,6 +389,11 @@ def main():
                                             tuned["block"], tuned["clip_budget"])
     print(f"# fp32+fallback: {ms32:.3f} ms/RPD, clip kernel {clip32:.3f} ms, pairs {pairs}", file=sys.stderr,
           flush=True)
+    # the same builds with the work dispatched by the static cost estimate (what a first build on a mesh uses)
+    ms_est, clip_est, _, _ = time_builds(meshes, sites, rpd.RPD_FP32_FALLBACK, args.steps, 1, stream,
+                                         tuned["block"], tuned["clip_budget"], flags=rpd.RPD_ESTIMATED_ORDER)
+    print(f"# fp32+fallback, estimated dispatch order: {ms_est:.3f} ms/RPD, clip kernel {clip_est:.3f} ms",
+          file=sys.stderr, flush=True)
     out64 = None
     if not args.no_fp64:
         ms64, clip64, pairs64, st64 = time_builds(meshes, sites, rpd.RPD_FP64, args.steps, args.warmup, stream)
@@ -416,6 +421,7 @@ def main():
                    "n_tets": sum(p.n_tets for p in probs), "n_sites": sum(p.n_sites for p in probs),
                    "n_pairs": pairs, "launch": tuned},
         "ms_per_rpd": ms32,
+        "estimated_order": {"ms_per_rpd": ms_est, "clip_kernel_ms": clip_est},
         "all_fp64": out64,
         "stats": {k: st32[k] for k in ("n_candidates", "n_deferred", "n_fp64", "n_exact", "n_faces", "n_edges",
                                        "n_rpv", "n_defer_block", "n_defer_kmax", "n_defer_clip", "n_split", "ms_clip",

@@ -68,6 +68,7 @@ typedef int32_t rpd_status;
 #define RPD_KEEP_PIECES (1u << 5)       /* keep per-piece records (rpd_pieces) for sampled comparisons */
 #define RPD_OWNER_WEIGHTS (1u << 6)     /* rpd_mesh_create: ownership weights even when L / k(sigma) fits (below) */
 #define RPD_SHUFFLE_QUEUE (1u << 7)     /* test-only: process the work items in a shuffled order (same results) */
+#define RPD_ESTIMATED_ORDER (1u << 8)   /* order the work by the static estimate even when a mesh has measured times */
 
 /*
  * A prepared tet mesh (device resident): vertex/tet arrays, face adjacency, the multiplicity k(sigma) of every

@@ -553,14 +553,15 @@ static std::vector<ShapeDesc> shape_table(const rpd_mesh* const* meshes, const i
 
 // (shape, block) work items, heaviest first. The hardware dispatcher hands workgroups to compute units in grid
 // order as they free up, so a heavy item dispatched late sets the kernel's tail. The cost of an item is its
-// fast-kernel time in the last build on the same mesh when every mesh of the call has one, else the estimate
-// shape sites x block tets (the box filter scans every site of the shape; clipping grows with the tets).
+// fast-kernel time in the last build on the same mesh when every mesh of the call has one (and
+// RPD_ESTIMATED_ORDER is not set), else the estimate shape sites x block tets (the box filter scans every site of the shape; clipping grows with the tets).
 // Ties keep the shapes' order and the blocks' Morton order. The order never changes a result.
-static std::vector<int2> work_items(const std::vector<ShapeDesc>& hd, const rpd_mesh* const* meshes) {
+static std::vector<int2> work_items(const std::vector<ShapeDesc>& hd, const rpd_mesh* const* meshes,
+                                    unsigned flags) {
   const int nsh = (int)hd.size();
   std::vector<int2> items;
   std::vector<unsigned long long> cost;
-  bool learned = true;
+  bool learned = (flags & RPD_ESTIMATED_ORDER) == 0;
   for (int k = 0; k < nsh && learned; ++k) {
     rpd_mesh* m = const_cast<rpd_mesh*>(meshes[k]);
     std::lock_guard<std::mutex> g(m->cost_mu);
@@ -636,7 +637,7 @@ static bool run_batch(const rpd_mesh* const* meshes, const rpd_sites* sites, int
   for (int k = 0; k < nsh; ++k) nsites[k] = sites[k].n_sites;
   long long ns_tot = 0, nt_tot = 0;
   std::vector<ShapeDesc> hd = shape_table(meshes, nsites.data(), nsh, &ns_tot, &nt_tot);
-  std::vector<int2> items = work_items(hd, meshes);
+  std::vector<int2> items = work_items(hd, meshes, o.flags);
   if (o.flags & RPD_SHUFFLE_QUEUE) {  // a fixed permutation: results must not depend on the processing order
     unsigned long long x = 0x9E3779B97F4A7C15ull;
     for (size_t k = items.size(); k > 1; --k) {

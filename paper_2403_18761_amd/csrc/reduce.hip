@@ -19,17 +19,24 @@ __global__ void k_fill_i32(int* p, int v, size_t n) {
   for (size_t k = blockIdx.x * (size_t)blockDim.x + threadIdx.x; k < n; k += (size_t)gridDim.x * blockDim.x) p[k] = v;
 }
 
-// several fills in one launch (blockIdx.y = job): each job writes n values of 4 or 8 bytes
+// several fills in one launch (blockIdx.y = job): each job writes n values of 4 or 8 bytes (p aligned to the
+// width), with 16-byte stores between the first and the last 16-byte boundary and single values around them
 __global__ void k_fill_multi(FillList L) {
   const FillJob j = L.job[blockIdx.y];
-  const size_t step = (size_t)gridDim.x * blockDim.x;
-  if (j.width == 8) {
-    unsigned long long* p = (unsigned long long*)j.p;
-    for (size_t k = blockIdx.x * (size_t)blockDim.x + threadIdx.x; k < j.n; k += step) p[k] = j.v;
-  } else {
-    int* p = (int*)j.p;
-    for (size_t k = blockIdx.x * (size_t)blockDim.x + threadIdx.x; k < j.n; k += step) p[k] = (int)j.v;
+  const size_t tid = blockIdx.x * (size_t)blockDim.x + threadIdx.x, step = (size_t)gridDim.x * blockDim.x;
+  const unsigned lo = (unsigned)j.v, hi = j.width == 8 ? (unsigned)(j.v >> 32) : lo;
+  const size_t w = (size_t)j.width;
+  const size_t head = min(((16 - ((size_t)j.p & 15)) & 15) / w, j.n);  // values before the first boundary
+  const size_t nvec = (j.n - head) * w / 16;
+  const size_t tail0 = head + nvec * 16 / w;  // first value after the last full 16 bytes
+  if (tid < head || (tid >= head && tid - head < j.n - tail0)) {
+    const size_t k = tid < head ? tid : tail0 + (tid - head);
+    if (w == 8) ((unsigned long long*)j.p)[k] = j.v;
+    else ((unsigned*)j.p)[k] = lo;
   }
+  uint4* q = (uint4*)((unsigned char*)j.p + head * w);
+  const uint4 val = make_uint4(lo, hi, lo, hi);
+  for (size_t k = tid; k < nvec; k += step) q[k] = val;
 }
 
 static int grid_for(size_t n, int bs) {
@@ -54,10 +61,11 @@ hipError_t launch_zero_stats(unsigned long long* stats, int c0, int n, hipStream
 }
 
 hipError_t launch_fill_multi(const FillList& L, hipStream_t s) {
+  if (L.overflow) return hipErrorInvalidValue;
   if (L.n <= 0) return hipSuccess;
-  size_t big = 1;
-  for (int k = 0; k < L.n; ++k) big = std::max(big, L.job[k].n);
-  hipLaunchKernelGGL(k_fill_multi, dim3(std::min(grid_for(big, 256), 8192), L.n), dim3(256), 0, s, L);
+  size_t big = 1;  // 16-byte vectors of the largest job (at least one thread per value outside them)
+  for (int k = 0; k < L.n; ++k) big = std::max(big, std::max(L.job[k].n * L.job[k].width / 16, (size_t)8));
+  hipLaunchKernelGGL(k_fill_multi, dim3(std::min(grid_for(big, 256), 1024), L.n), dim3(256), 0, s, L);
   return hipGetLastError();
 }
 hipError_t launch_fill_i32(int* p, int v, size_t n, hipStream_t s) {

@@ -24,8 +24,11 @@ struct FillJob {
 struct FillList {
   FillJob job[24];
   int n;
+  bool overflow;  // more than 24 jobs were added (launch_fill_multi then fails)
   void add(void* ptr, unsigned long long val, size_t count, int w) {
-    if (count) job[n++] = FillJob{ptr, val, count, w};
+    if (!count) return;
+    if (n < 24) job[n++] = FillJob{ptr, val, count, w};
+    else overflow = true;
   }
 };
 hipError_t launch_fill_multi(const FillList& L, hipStream_t s);

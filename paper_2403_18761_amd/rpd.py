@@ -14,6 +14,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "librpd.so")
 
 RPD_OK = 0
+RPD_E_INVALID, RPD_E_MESH, RPD_E_DEGENERATE, RPD_E_NOMEM, RPD_E_DEVICE, RPD_E_INTERNAL = -1, -2, -3, -4, -5, -6
 ERRORS = {-1: "RPD_E_INVALID", -2: "RPD_E_MESH", -3: "RPD_E_DEGENERATE", -4: "RPD_E_NOMEM", -5: "RPD_E_DEVICE",
           -6: "RPD_E_INTERNAL"}
 RPD_FP32_FALLBACK = 0
@@ -27,6 +28,7 @@ RPD_TIMING = 1 << 4
 RPD_KEEP_PIECES = 1 << 5
 RPD_OWNER_WEIGHTS = 1 << 6
 RPD_SHUFFLE_QUEUE = 1 << 7
+RPD_ESTIMATED_ORDER = 1 << 8
 
 _f32p = C.POINTER(C.c_float)
 _i32p = C.POINTER(C.c_int32)

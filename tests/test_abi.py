@@ -49,3 +49,16 @@ def test_library_loads_and_reports_version(lib_path):
 def test_library_contains_gfx950_code(lib_path):
     data = open(lib_path, "rb").read()
     assert b"amdgcn-amd-amdhsa--gfx950" in data
+
+
+def test_binding_constants_match_the_header():
+    """Every RPD_ constant of the header has the same value in the Python binding."""
+    from paper_2403_18761_amd import rpd
+
+    src = re.sub(r"/\*.*?\*/", "", open(HEADER).read(), flags=re.S)
+    seen = 0
+    for name, expr in re.findall(r"^#define (RPD_[A-Z0-9_]+)[ \t]+(.+?)\s*$", src, flags=re.M):
+        value = eval(expr.replace("u <<", " <<"), {})  # integer literals and shifts only
+        assert getattr(rpd, name) == value, name
+        seen += 1
+    assert seen >= 20

@@ -294,6 +294,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-fp64", action="store_true", help="skip the all-FP64 comparison")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-estimated", action="store_true",
+                    help="skip the timing of the same builds in the static-estimate dispatch order")
     ap.add_argument("--no-autotune", action="store_true", help="use the default launch shape (128 threads, k=28)")
     ap.add_argument("--launch", default=None, metavar="BLOCK,K",
                     help="use this launch shape (threads per workgroup, clip budget) instead of autotuning")
@@ -390,10 +392,13 @@ def main():
     print(f"# fp32+fallback: {ms32:.3f} ms/RPD, clip kernel {clip32:.3f} ms, pairs {pairs}", file=sys.stderr,
           flush=True)
     # the same builds with the work dispatched by the static cost estimate (what a first build on a mesh uses)
-    ms_est, clip_est, _, _ = time_builds(meshes, sites, rpd.RPD_FP32_FALLBACK, args.steps, 1, stream,
-                                         tuned["block"], tuned["clip_budget"], flags=rpd.RPD_ESTIMATED_ORDER)
-    print(f"# fp32+fallback, estimated dispatch order: {ms_est:.3f} ms/RPD, clip kernel {clip_est:.3f} ms",
-          file=sys.stderr, flush=True)
+    est = None
+    if not args.no_estimated:
+        ms_est, clip_est, _, _ = time_builds(meshes, sites, rpd.RPD_FP32_FALLBACK, args.steps, 1, stream,
+                                             tuned["block"], tuned["clip_budget"], flags=rpd.RPD_ESTIMATED_ORDER)
+        est = {"ms_per_rpd": ms_est, "clip_kernel_ms": clip_est}
+        print(f"# fp32+fallback, estimated dispatch order: {ms_est:.3f} ms/RPD, clip kernel {clip_est:.3f} ms",
+              file=sys.stderr, flush=True)
     out64 = None
     if not args.no_fp64:
         ms64, clip64, pairs64, st64 = time_builds(meshes, sites, rpd.RPD_FP64, args.steps, args.warmup, stream)
@@ -421,7 +426,7 @@ def main():
                    "n_tets": sum(p.n_tets for p in probs), "n_sites": sum(p.n_sites for p in probs),
                    "n_pairs": pairs, "launch": tuned},
         "ms_per_rpd": ms32,
-        "estimated_order": {"ms_per_rpd": ms_est, "clip_kernel_ms": clip_est},
+        "estimated_order": est,
         "all_fp64": out64,
         "stats": {k: st32[k] for k in ("n_candidates", "n_deferred", "n_fp64", "n_exact", "n_faces", "n_edges",
                                        "n_rpv", "n_defer_block", "n_defer_kmax", "n_defer_clip", "n_split", "ms_clip",

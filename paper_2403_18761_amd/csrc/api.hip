@@ -577,16 +577,19 @@ static std::vector<int2> work_items(const std::vector<ShapeDesc>& hd, const rpd_
                              : (unsigned long long)hd[k].ns * (unsigned long long)(m->hblk[b + 1] - m->hblk[b]));
     }
   }
-  // stable counting sort, descending, on the top 16 bits of the cost range
+  // stable counting sort, descending, on the top bits of the cost range: about one bucket per item, 2^16 at most
+  int bits = 8;
+  while (bits < 16 && ((size_t)1 << bits) < items.size()) ++bits;
+  const unsigned long long top = (1ull << bits) - 1;
   unsigned long long cmax = 1;
   for (unsigned long long c : cost) cmax = std::max(cmax, c);
   int shift = 0;
-  while ((cmax >> shift) > 0xffffull) ++shift;
-  std::vector<int> start(65537, 0);
-  for (unsigned long long c : cost) ++start[0xffff - (int)(c >> shift) + 1];
-  for (int d = 0; d < 65536; ++d) start[d + 1] += start[d];
+  while ((cmax >> shift) > top) ++shift;
+  std::vector<int> start((size_t)top + 2, 0);
+  for (unsigned long long c : cost) ++start[top - (c >> shift) + 1];
+  for (size_t d = 0; d <= top; ++d) start[d + 1] += start[d];
   std::vector<int2> out(items.size());
-  for (size_t k = 0; k < items.size(); ++k) out[start[0xffff - (int)(cost[k] >> shift)]++] = items[k];
+  for (size_t k = 0; k < items.size(); ++k) out[start[top - (cost[k] >> shift)]++] = items[k];
   return out;
 }
 

@@ -58,17 +58,17 @@ def measured_traffic(workload: str, kernel: str, launch: dict):
 
 WORKLOADS = {
     "torus2000": dict(desc="solid torus R0.6 r0.25 (seed 2 jitter), 64^3 grid, 131838 Kuhn tets, 2000 sites uniform "
-                           "inside with r = 0.9|sdf|", cpu_frac=0.25),
+                           "inside with r = 0.9|sdf|", cpu_frac=1.0),
     "genus3": dict(desc="genus-3 CAD-like solid (three boxes minus three cylinders), 128^3 grid, 2142000 Kuhn tets, "
-                        "20000 sites, 30% within 0.02 of sharp edges", cpu_frac=0.002),
+                        "20000 sites, 30% within 0.02 of sharp edges", cpu_frac=0.005),
     "batch256": dict(desc="256 seeded shapes (tori, box unions, metaballs), log-uniform 5k-200k tets and 100-5k sites "
                           "each, one rpd_build call", cpu_frac=0.002),
     "envelope": dict(desc="geometric-error metric: distance from 1M surface samples of the torus2000 shape to the "
                           "enveloping spheres, cones and slabs of its thinned (sigma 0.3) dual medial mesh",
-                     cpu_frac=0.0005),
+                     cpu_frac=0.02),
     "repair": dict(desc="topology repair: 5 metaball blobs joined by thin handles (genus 2), 128^3 grid, 975462 Kuhn "
                         "tets, 500 initial sites, up to 64 insertions per round from a per-tet sphere table, one "
-                        "captured graph per round (a step is one round)", cpu_frac=0.002),
+                        "captured graph per round (a step is one round)", cpu_frac=0.08),
 }
 
 

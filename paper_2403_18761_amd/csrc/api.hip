@@ -1011,6 +1011,7 @@ struct rpd_session {
   rpd::DeviceState D;
   rpd::DBuf dshapes;  // [0] the shape before a round's insertions, [1] after them (the current state)
   rpd::DBuf all_items, items, table, tet_block, dirty, sel, selpos, best, ref, tet_used, ints;
+  rpd::DBuf order;  // [nblk] blocks by their fast-kernel time in the initial build, heaviest first
   rpd::RoundState r{};
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
@@ -1129,6 +1130,8 @@ static bool session_init(rpd_session* S, const rpd_sites* sites, const rpd_sites
 
   ShapeDesc* ds = S->dshapes.as<ShapeDesc>();
   ShapeArgs a = D.args(ds + 1, S->all_items.as<int2>(), nblk, S->o.flags, S->kmax, +1);
+  DBuf ticks(sizeof(unsigned) * (size_t)nblk);
+  a.item_cost = ticks.as<unsigned>();  // item k is block k
   clip_pass(S, a);
   D.components(a, s);
   hip_check(hipStreamSynchronize(s), "synchronize");
@@ -1136,6 +1139,15 @@ static bool session_init(rpd_session* S, const rpd_sites* sites, const rpd_sites
   hip_check(hipMemcpy(&hst, D.status.p, sizeof(int), hipMemcpyDeviceToHost), "download");
   if (hst & ST_TABLE_FULL) return false;
   status_error(hst);
+  {  // the rounds scan the blocks heaviest first (k_dirty_items)
+    std::vector<unsigned> cost(nblk);
+    hip_check(hipMemcpy(cost.data(), ticks.p, sizeof(unsigned) * (size_t)nblk, hipMemcpyDeviceToHost), "download");
+    std::vector<int> ord(nblk);
+    std::iota(ord.begin(), ord.end(), 0);
+    std::stable_sort(ord.begin(), ord.end(), [&](int x, int y) { return cost[x] > cost[y]; });
+    S->order.alloc(sizeof(int) * (size_t)nblk);
+    hip_check(hipMemcpy(S->order.p, ord.data(), sizeof(int) * (size_t)nblk, hipMemcpyHostToDevice), "upload");
+  }
 
   int* ints = S->ints.as<int>();
   RoundState& r = S->r;
@@ -1149,6 +1161,7 @@ static bool session_init(rpd_session* S, const rpd_sites* sites, const rpd_sites
   r.mode = S->mode;
   r.tet_block = S->tet_block.as<int>();
   r.dirty = S->dirty.as<int>();
+  r.order = S->order.as<int>();
   r.items = S->items.as<int2>();
   r.nitems = ints + SI_NITEMS;
   r.round = ints + SI_ROUND;

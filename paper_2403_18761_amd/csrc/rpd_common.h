@@ -163,7 +163,8 @@ struct RoundState {
   int mode;                   // 0: caller's per-tet table, hashed pick; 1: shrunk spheres at the furthest surface face
   const int* tet_block;       // [nt] workgroup block of every tet
   int* dirty;                 // [nblk] block flags
-  int2* items;                // [nblk] dirty (shape 0, block) items, ascending
+  const int* order;           // [nblk] blocks by their time in the initial build, heaviest first (scan order)
+  int2* items;                // [nblk] dirty (shape 0, block) items, in about that order
   int* nitems;
   int* round;
   int* ns_cur;                // sites in use

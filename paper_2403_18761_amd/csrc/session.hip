@@ -219,9 +219,11 @@ __global__ void k_mark_dirty(RoundState r, const float4* tp, int nt, const float
   }
 }
 
-// dirty blocks -> work items (any order: every accumulation is an integer sum), then clear the flags
+// dirty blocks -> work items, then clear the flags. Any order gives the same sums (integers); the blocks are
+// scanned heaviest first so that the items come out in about that order, which shortens the clipping kernel's tail.
 __global__ void k_dirty_items(RoundState r, int nblk) {
-  for (int b = blockIdx.x * blockDim.x + threadIdx.x; b < nblk; b += gridDim.x * blockDim.x) {
+  for (int k = blockIdx.x * blockDim.x + threadIdx.x; k < nblk; k += gridDim.x * blockDim.x) {
+    const int b = r.order[k];
     if (!r.dirty[b]) continue;
     r.dirty[b] = 0;
     const unsigned long long active = __ballot(1);

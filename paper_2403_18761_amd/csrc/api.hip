@@ -6,6 +6,7 @@
 #include <cmath>
 #include <cstring>
 #include <map>
+#include <memory>
 #include <mutex>
 #include <numeric>
 #include <string>
@@ -73,14 +74,40 @@ static unsigned pow2_cap(size_t n) {
 // region of slow_scratch_bytes(1) (about 240 KB), allocated with the call's other buffers.
 static int slow_waves(long long nt) { return (int)std::max<long long>(64, std::min<long long>(2048, nt / 16)); }
 
+struct HostPinned;
+
+// A result array: its own storage, or a view into the call's downloaded (pinned) buffer that the result keeps.
+template <typename T>
+struct Arr {
+  std::vector<T> own;
+  const T* ext = nullptr;
+  size_t n_ext = 0;
+  bool is_view = false;
+  const T* data() const { return is_view ? ext : own.data(); }
+  size_t size() const { return is_view ? n_ext : own.size(); }
+  const T* begin() const { return data(); }
+  const T* end() const { return data() + size(); }
+  void view(const T* p, size_t n) {
+    own.clear();
+    ext = p;
+    n_ext = n;
+    is_view = true;
+  }
+  std::vector<T>& owned() {
+    is_view = false;
+    return own;
+  }
+};
+
 struct ShapeOut {
   int ns = 0;
-  std::vector<int32_t> cell_keys, cell_chi, cell_b0;
-  std::vector<double> vol, cen;
-  std::vector<int32_t> face_keys, face_chi, face_b0;
-  std::vector<int32_t> edge_keys, edge_chi, edge_b0;
-  std::vector<double> edge_len, edge_alpha;
-  std::vector<int32_t> rpv_keys;
+  std::shared_ptr<HostPinned> hold;  // the downloaded buffer the views point into
+  Arr<int32_t> cell_keys, cell_chi, cell_b0;
+  Arr<double> vol, cen;
+  Arr<int32_t> face_keys, face_chi, face_b0;
+  Arr<int32_t> edge_keys, edge_chi, edge_b0;
+  Arr<double> edge_len, edge_alpha;
+  Arr<int32_t> rpv_keys;
   std::vector<int32_t> pc_t, pc_i;
   std::vector<double> pc_geo;
   std::vector<int64_t> pc_chi;
@@ -418,8 +445,8 @@ static bool collect(DeviceState& D, const std::vector<ShapeDesc>& hd, const Shap
                                     s),
               "finalize cells");
   tm.mark(3, s);
-  HostPinned host(out_bytes + 16);
-  unsigned char* hb = (unsigned char*)host.p;
+  auto host = std::make_shared<HostPinned>(out_bytes + 16);  // kept by the result (its arrays point into it)
+  unsigned char* hb = (unsigned char*)host->p;
   hip_check(hipMemcpyAsync(hb, ob, out_bytes, hipMemcpyDeviceToHost, s), "download");
   hip_check(hipMemcpyAsync(hb + out_bytes, D.status.p, sizeof(int), hipMemcpyDeviceToHost, s), "download");
   std::vector<PieceRec> prs;
@@ -446,29 +473,36 @@ static bool collect(DeviceState& D, const std::vector<ShapeDesc>& hd, const Shap
     ShapeOut& out = outs[k];
     const int off = hd[k].site_off, n = hd[k].ns, end = off + n;
     out.ns = n;
-    out.cell_chi.assign(all_cchi + off, all_cchi + end);
-    out.cell_b0.assign(all_cb0 + off, all_cb0 + end);
-    out.vol.assign(all_vol + off, all_vol + end);
-    out.cen.assign(all_cen + 3 * (size_t)off, all_cen + 3 * (size_t)end);
-    out.cell_keys.resize(n);
-    std::iota(out.cell_keys.begin(), out.cell_keys.end(), 0);
+    out.hold = host;
+    out.cell_chi.view(all_cchi + off, n);
+    out.cell_b0.view(all_cb0 + off, n);
+    out.vol.view(all_vol + off, n);
+    out.cen.view(all_cen + 3 * (size_t)off, 3 * (size_t)n);
+    std::vector<int32_t>& ck = out.cell_keys.owned();
+    ck.resize(n);
+    std::iota(ck.begin(), ck.end(), 0);
     // element lists: one contiguous run per shape; keys shifted to the shape's own site ids
     size_t fend = fpos, eend = epos, qend = qpos;
     while (fend < nf && all_fk[2 * fend] < end) ++fend;
     while (eend < ne && all_ek[3 * eend] < end) ++eend;
     while (qend < nq && all_rpv[4 * qend] < end) ++qend;
-    auto shifted = [off](std::vector<int32_t>& dst, const int* src, size_t n) {
-      dst.resize(n);
-      for (size_t k = 0; k < n; ++k) dst[k] = src[k] - off;
+    auto shifted = [off](Arr<int32_t>& dst, const int* src, size_t n) {
+      if (off == 0) {  // the first shape's ids are its own
+        dst.view(src, n);
+        return;
+      }
+      std::vector<int32_t>& d = dst.owned();
+      d.resize(n);
+      for (size_t k = 0; k < n; ++k) d[k] = src[k] - off;
     };
     shifted(out.face_keys, all_fk + 2 * fpos, 2 * (fend - fpos));
-    out.face_chi.assign(all_fchi + fpos, all_fchi + fend);
-    out.face_b0.assign(all_fb0 + fpos, all_fb0 + fend);
+    out.face_chi.view(all_fchi + fpos, fend - fpos);
+    out.face_b0.view(all_fb0 + fpos, fend - fpos);
     shifted(out.edge_keys, all_ek + 3 * epos, 3 * (eend - epos));
-    out.edge_chi.assign(all_echi + epos, all_echi + eend);
-    out.edge_b0.assign(all_eb0 + epos, all_eb0 + eend);
-    out.edge_len.assign(all_elen + epos, all_elen + eend);
-    out.edge_alpha.assign(all_ealpha + epos, all_ealpha + eend);
+    out.edge_chi.view(all_echi + epos, eend - epos);
+    out.edge_b0.view(all_eb0 + epos, eend - epos);
+    out.edge_len.view(all_elen + epos, eend - epos);
+    out.edge_alpha.view(all_ealpha + epos, eend - epos);
     shifted(out.rpv_keys, all_rpv + 4 * qpos, 4 * (qend - qpos));
     fpos = fend;
     epos = eend;

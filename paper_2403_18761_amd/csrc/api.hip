@@ -292,12 +292,13 @@ struct DeviceState {
       hip_check(launch_clear_touched_b0(a.touch_face, face_b0.as<int>(), capF, s), "clear");
       hip_check(launch_clear_touched_b0(a.touch_edge, edge_b0.as<int>(), capE, s), "clear");
     } else {
-      hip_check(launch_fill_i32(cell_b0.as<int>(), 0, (size_t)ns_cap, s), "fill");
-      hip_check(launch_fill_i32(face_b0.as<int>(), 0, capF, s), "fill");
-      hip_check(launch_fill_i32(edge_b0.as<int>(), 0, capE, s), "fill");
+      FillList L{};
+      L.add(cell_b0.p, 0, (size_t)ns_cap, 4);
+      L.add(face_b0.p, 0, capF, 4);
+      L.add(edge_b0.p, 0, capE, 4);
+      hip_check(launch_fill_multi(L, s), "fill");
     }
-    hip_check(launch_zero_stats(stat(), C_NODES, 1, s), "fill");
-    hip_check(launch_zero_stats(stat(), C_GLUE_BITS, 2, s), "fill");
+    hip_check(launch_zero_stats(stat(), C_NODES, 1, C_GLUE_BITS, 2, s), "fill");
     hip_check(launch_glue(a, parent.as<int>(), s), "glue");
     hip_check(launch_count_roots(a, parent.as<int>(), cell_b0.as<int>(), face_b0.as<int>(), edge_b0.as<int>(), s),
               "roots");

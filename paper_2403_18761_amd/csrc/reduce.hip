@@ -50,13 +50,16 @@ hipError_t launch_fill_u64(unsigned long long* p, unsigned long long v, size_t n
   hipLaunchKernelGGL(k_fill_u64, dim3(grid_for(n, 256)), dim3(256), 0, s, p, v, n);
   return hipGetLastError();
 }
-__global__ void k_zero_stats(unsigned long long* stats, int c0, int n) {
+// counters [c0, c0 + n0) and [c1, c1 + n1) in every spread copy of the statistics
+__global__ void k_zero_stats(unsigned long long* stats, int c0, int n0, int c1, int n1) {
   const int k = threadIdx.x;  // one thread per spread copy
-  if (k < NSPREAD)
-    for (int c = 0; c < n; ++c) stats[(size_t)k * NCOUNTERS + c0 + c] = 0;
+  if (k < NSPREAD) {
+    for (int c = 0; c < n0; ++c) stats[(size_t)k * NCOUNTERS + c0 + c] = 0;
+    for (int c = 0; c < n1; ++c) stats[(size_t)k * NCOUNTERS + c1 + c] = 0;
+  }
 }
-hipError_t launch_zero_stats(unsigned long long* stats, int c0, int n, hipStream_t s) {
-  hipLaunchKernelGGL(k_zero_stats, dim3(1), dim3(NSPREAD), 0, s, stats, c0, n);
+hipError_t launch_zero_stats(unsigned long long* stats, int c0, int n0, int c1, int n1, hipStream_t s) {
+  hipLaunchKernelGGL(k_zero_stats, dim3(1), dim3(NSPREAD), 0, s, stats, c0, n0, c1, n1);
   return hipGetLastError();
 }
 
@@ -386,8 +389,10 @@ hipError_t launch_row_sort(unsigned long long* const keys[3], unsigned long long
   L.off = off;
   L.cur = cur;
   L.rows = rows;
-  hipError_t e = launch_fill_i32(off, 0, 3 * (size_t)(rows + 1), s);
-  if (e == hipSuccess) e = launch_fill_i32(cur, 0, 3 * (size_t)rows, s);
+  FillList Z{};
+  Z.add(off, 0, 3 * (size_t)(rows + 1), 4);
+  Z.add(cur, 0, 3 * (size_t)rows, 4);
+  hipError_t e = launch_fill_multi(Z, s);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_row_count, dim3(grid_for(nmax, 256), 3), dim3(256), 0, s, L);
   hipLaunchKernelGGL(k_row_scan, dim3(3), dim3(1024), 0, s, L);

@@ -33,8 +33,8 @@ struct FillList {
 };
 hipError_t launch_fill_multi(const FillList& L, hipStream_t s);
 hipError_t launch_fill_i32(int* p, int v, size_t n, hipStream_t s);
-// zero counters [c0, c0 + n) in every spread copy of the statistics
-hipError_t launch_zero_stats(unsigned long long* stats, int c0, int n, hipStream_t s);
+// zero counters [c0, c0 + n0) and [c1, c1 + n1) in every spread copy of the statistics
+hipError_t launch_zero_stats(unsigned long long* stats, int c0, int n0, int c1, int n1, hipStream_t s);
 // union-find over the live element pieces (with a.touch_* set: only the pieces of touched elements)
 hipError_t launch_glue(const ShapeArgs& a, int* parent, hipStream_t s);
 hipError_t launch_clear_touched_b0(const unsigned char* touch, int* b0, size_t n, hipStream_t s);

@@ -68,7 +68,7 @@ WORKLOADS = {
                      cpu_frac=0.02),
     "repair": dict(desc="topology repair: 5 metaball blobs joined by thin handles (genus 2), 128^3 grid, 975462 Kuhn "
                         "tets, 500 initial sites, up to 64 insertions per round from a per-tet sphere table, one "
-                        "captured graph per round (a step is one round)", cpu_frac=0.08),
+                        "captured graph per round (a step is one round)", cpu_frac=0.25),
 }
 
 

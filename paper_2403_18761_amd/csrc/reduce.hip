@@ -250,20 +250,25 @@ __device__ inline unsigned long long block_append(int n, unsigned long long* cou
   return s_base + (unsigned long long)(before + x - n);
 }
 
-constexpr int CPT = 16;  // table slots per thread in the compactions
+// Each workgroup takes cpt runs of 256 consecutive slots (lane-strided, so every load is coalesced); cpt grows with
+// the table from 1 (small tables: enough workgroups to cover the latency) to 16 (one global atomic per 4,096 slots).
+static unsigned compact_cpt(size_t cap) {
+  size_t c = (cap + 256 * 2048 - 1) / (256 * 2048);
+  return (unsigned)std::min<size_t>(std::max<size_t>(c, 1), 16);
+}
 
 __global__ __launch_bounds__(256) void k_compact_live(const unsigned long long* keys, const int* np, unsigned cap,
-                                                      unsigned long long* out_keys, int* out_slots,
+                                                      unsigned cpt, unsigned long long* out_keys, int* out_slots,
                                                       unsigned long long* count) {
-  const size_t q0 = ((size_t)blockIdx.x * blockDim.x + threadIdx.x) * CPT;
+  const size_t q0 = (size_t)blockIdx.x * cpt * 256 + threadIdx.x;
   int n = 0;
-  for (int k = 0; k < CPT; ++k) {
-    const size_t q = q0 + k;
+  for (unsigned k = 0; k < cpt; ++k) {
+    const size_t q = q0 + 256 * (size_t)k;
     if (q < cap && keys[q] != EMPTY_KEY && np[q] > 0) ++n;
   }
   unsigned long long pos = block_append(n, count);
-  for (int k = 0; k < CPT && n; ++k) {
-    const size_t q = q0 + k;
+  for (unsigned k = 0; k < cpt && n; ++k) {
+    const size_t q = q0 + 256 * (size_t)k;
     if (q < cap && keys[q] != EMPTY_KEY && np[q] > 0) {
       out_keys[pos] = keys[q];
       out_slots[pos] = (int)q;
@@ -275,25 +280,26 @@ __global__ __launch_bounds__(256) void k_compact_live(const unsigned long long* 
 hipError_t launch_compact_live(const unsigned long long* keys, const int* np, unsigned cap,
                                unsigned long long* out_keys, int* out_slots, unsigned long long* count,
                                hipStream_t s) {
-  const size_t per = 256 * (size_t)CPT;
-  hipLaunchKernelGGL(k_compact_live, dim3((unsigned)((cap + per - 1) / per)), dim3(256), 0, s, keys, np, cap, out_keys,
-                     out_slots, count);
+  const unsigned cpt = compact_cpt(cap);
+  const size_t per = 256 * (size_t)cpt;
+  hipLaunchKernelGGL(k_compact_live, dim3((unsigned)((cap + per - 1) / per)), dim3(256), 0, s, keys, np, cap, cpt,
+                     out_keys, out_slots, count);
   return hipGetLastError();
 }
 
 // RPV quadruples (i, j, k, l) of the counted set (key = edge slot of (i, j, k) << 21 | l), compacted
 __global__ __launch_bounds__(256) void k_rpv_compact(HashTab Q, const int* cnt, const unsigned long long* ekeys,
-                                                     int4* out, unsigned long long* count) {
+                                                     unsigned cpt, int4* out, unsigned long long* count) {
   const size_t cap = (size_t)Q.mask + 1;
-  const size_t q0 = ((size_t)blockIdx.x * blockDim.x + threadIdx.x) * CPT;
+  const size_t q0 = (size_t)blockIdx.x * cpt * 256 + threadIdx.x;
   int n = 0;
-  for (int k = 0; k < CPT; ++k) {
-    const size_t q = q0 + k;
+  for (unsigned k = 0; k < cpt; ++k) {
+    const size_t q = q0 + 256 * (size_t)k;
     if (q < cap && Q.keys[q] != EMPTY_KEY && cnt[q] > 0) ++n;
   }
   unsigned long long pos = block_append(n, count);
-  for (int k = 0; k < CPT && n; ++k) {
-    const size_t q = q0 + k;
+  for (unsigned k = 0; k < cpt && n; ++k) {
+    const size_t q = q0 + 256 * (size_t)k;
     if (q < cap && Q.keys[q] != EMPTY_KEY && cnt[q] > 0) {
       const unsigned long long key = Q.keys[q];
       const unsigned long long e = ekeys[key >> 21];
@@ -305,8 +311,10 @@ __global__ __launch_bounds__(256) void k_rpv_compact(HashTab Q, const int* cnt, 
 }
 hipError_t launch_rpv_compact(const HashTab& Q, const int* cnt, const unsigned long long* ekeys, int4* out,
                               unsigned long long* count, hipStream_t s) {
-  const size_t per = 256 * (size_t)CPT, cap = (size_t)Q.mask + 1;
-  hipLaunchKernelGGL(k_rpv_compact, dim3((unsigned)((cap + per - 1) / per)), dim3(256), 0, s, Q, cnt, ekeys, out,
+  const size_t cap = (size_t)Q.mask + 1;
+  const unsigned cpt = compact_cpt(cap);
+  const size_t per = 256 * (size_t)cpt;
+  hipLaunchKernelGGL(k_rpv_compact, dim3((unsigned)((cap + per - 1) / per)), dim3(256), 0, s, Q, cnt, ekeys, cpt, out,
                      count);
   return hipGetLastError();
 }

@@ -135,6 +135,9 @@ def test_learned_dispatch_order_gives_the_same_bits():
         again = extract(rpd.build([mesh], [s1]), 0)  # measured order
         for k in ELEMENT_ARRAYS:
             np.testing.assert_array_equal(first[k], again[k], err_msg=k)
+    forced = extract(rpd.build([mesh], [s1], flags=rpd.RPD_ESTIMATED_ORDER), 0)  # estimate despite measured times
+    for k in ELEMENT_ARRAYS:
+        np.testing.assert_array_equal(first[k], forced[k], err_msg=f"estimated order {k}")
     lone = extract(rpd.build([mesh], [s2]), 0)
     res = rpd.build([mesh, mesh], [s2, s1])
     for _ in range(2):

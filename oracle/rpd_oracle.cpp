@@ -46,6 +46,7 @@
 #include <cstdlib>
 #include <cstring>
 #include <map>
+#include <set>
 #include <mutex>
 #include <numeric>
 #include <string>
@@ -299,6 +300,66 @@ void unite(std::vector<int>& p, int a, int b) {
   p[a] = b;
 }
 
+// The input is a manifold tet mesh (Sec. 3.3, Assumption). Besides every face lying in one or two tets, the link of
+// every edge must be a circle or an arc, and the link of every vertex a sphere or a disk:
+//  - edge e: the tets containing e, joined through the faces that contain e and are shared by two tets, form one
+//    connected chain;
+//  - vertex v: the tets containing v, joined through the shared faces that contain v, are connected, and the link
+//    surface (one triangle per tet, one edge per face and one vertex per edge containing v) has Euler characteristic
+//    2 and no boundary (an interior vertex) or 1 and a boundary (a boundary vertex), i.e. it is a sphere or a disk.
+void check_links(const Mesh& m) {
+  std::vector<std::vector<int>> etets(m.n_edges), vtets(m.nv);
+  for (int t = 0; t < m.nt; ++t) {
+    for (int e = 0; e < 6; ++e) etets[m.tedge[t][e]].push_back(t);
+    for (int k = 0; k < 4; ++k) vtets[m.tv[t][k]].push_back(t);
+  }
+  // connected components of a set of tets under the given face joins (faces identified by local index)
+  auto one_piece = [&](const std::vector<int>& tets, auto face_joins) {
+    std::map<int, int> idx;
+    for (int t : tets) idx.emplace(t, (int)idx.size());
+    std::vector<int> par(idx.size());
+    std::iota(par.begin(), par.end(), 0);
+    for (int t : tets)
+      for (int f = 0; f < 4; ++f) {
+        const int nb = m.tnb[t][f];
+        if (nb >= 0 && face_joins(t, f)) unite(par, idx[t], idx.at(nb));
+      }
+    int roots = 0;
+    for (size_t k = 0; k < par.size(); ++k)
+      if (find_root(par, (int)k) == (int)k) ++roots;
+    return roots == 1;
+  };
+  for (int t = 0; t < m.nt; ++t)
+    for (int e = 0; e < 6; ++e) {
+      const int id = m.tedge[t][e];
+      if (etets[id].empty()) continue;  // checked once, from its first tet
+      const int a = m.tv[t][EDGE_V[e][0]], b = m.tv[t][EDGE_V[e][1]];
+      // a face of tet u contains {a, b} iff the vertex opposite it is neither a nor b
+      bool ok = one_piece(etets[id], [&](int u, int f) { return m.tv[u][f] != a && m.tv[u][f] != b; });
+      if (!ok) throw Failure{E_MESH, "non-manifold edge: the tets around an edge are not one chain"};
+      etets[id].clear();
+    }
+  for (int v = 0; v < m.nv; ++v) {
+    if (vtets[v].empty()) continue;
+    if (!one_piece(vtets[v], [&](int u, int f) { return m.tv[u][f] != v; }))
+      throw Failure{E_MESH, "non-manifold vertex: the tets around a vertex are not connected"};
+    std::set<int> edges, faces;
+    bool boundary = false;
+    for (int u : vtets[v]) {
+      for (int e = 0; e < 6; ++e)
+        if (m.tv[u][EDGE_V[e][0]] == v || m.tv[u][EDGE_V[e][1]] == v) edges.insert(m.tedge[u][e]);
+      for (int f = 0; f < 4; ++f)
+        if (m.tv[u][f] != v) {
+          faces.insert(m.tface[u][f]);
+          if (m.tnb[u][f] < 0) boundary = true;
+        }
+    }
+    const long chi = (long)edges.size() - (long)faces.size() + (long)vtets[v].size();
+    if (!((chi == 2 && !boundary) || (chi == 1 && boundary)))
+      throw Failure{E_MESH, "non-manifold vertex: its link is not a sphere or a disk"};
+  }
+}
+
 Mesh build_mesh(int nv, const float* vx, const float* vy, const float* vz, int nt, const int32_t* tv,
                 bool force_owner) {
   Mesh m;
@@ -386,6 +447,7 @@ Mesh build_mesh(int nv, const float* vx, const float* vy, const float* vz, int n
       m.tnb[b.first][b.second] = a.first;
     }
   }
+  check_links(m);
   int used = 0;
   i64 L = 1;
   bool big = false;
@@ -941,12 +1003,13 @@ void process_tet(const Ctx& C, int t, std::vector<PieceOut>& outs, std::vector<A
   std::sort(order.begin(), order.end());
   Plane faces[4];
   for (int f = 0; f < 4; ++f) faces[f] = face_plane(M, t, f);
-  for (int oi = 0; oi < n; ++oi) {
-    int i = order[oi].second;
-    ++*attempted;
-    Piece P;
-    for (int f = 0; f < 4; ++f) P.planes.push_back(faces[f]);
-    // tet vertex v is the meet of the three faces other than face v
+  // P_{t,i} starts as the tet itself: its four face planes, and vertex v as the meet of the three faces other than
+  // face v. It is set up when the first plane cuts the tet (a plane that keeps or removes the whole tet is decided
+  // at the four vertices alone); the storage is reused from site to site.
+  Piece P;
+  auto start_as_tet = [&]() {
+    P.planes.assign(faces, faces + 4);
+    P.verts.clear();
     for (int v = 0; v < 4; ++v) {
       std::array<int, 3> tri;
       int c = 0;
@@ -954,6 +1017,11 @@ void process_tet(const Ctx& C, int t, std::vector<PieceOut>& outs, std::vector<A
         if (f != v) tri[c++] = f;
       P.verts.push_back(tri);
     }
+  };
+  for (int oi = 0; oi < n; ++oi) {
+    int i = order[oi].second;
+    ++*attempted;
+    bool started = false;
     bool alive = true;
     for (int oj = 0; oj < n && alive; ++oj) {
       int j = order[oj].second;
@@ -977,9 +1045,15 @@ void process_tet(const Ctx& C, int t, std::vector<PieceOut>& outs, std::vector<A
       h.d = (i128)pow_dist(S, j, ox, oy, oz) - (i128)pow_dist(S, i, ox, oy, oz);
       h.kind = 1;
       h.id = j;
+      if (!started) {
+        start_as_tet();
+        started = true;
+      }
       alive = clip(P, h, i);
     }
-    if (!alive || P.verts.empty()) continue;
+    if (!alive) continue;
+    if (!started) start_as_tet();  // no plane cuts the tet: the piece is the whole tet
+    if (P.verts.empty()) continue;
     PieceOut po;
     analyse_piece(C, t, i, P, po, asmrec);
     outs.push_back(std::move(po));

@@ -1284,7 +1284,9 @@ rpd_status rpd_session_create(const rpd_mesh* mesh, const rpd_sites* sites, cons
       (table->n_sites != mesh->nt || !table->sx || !table->sy || !table->sz || !table->sr))
     throw Failure{RPD_E_INVALID, "the table needs one sphere per tet"};
   if (mesh->nblk <= 0) throw Failure{RPD_E_INVALID, "empty mesh"};
-  if (o.stream) rpd::hip_check(hipStreamSynchronize((hipStream_t)o.stream), "synchronize");
+  // the session reads the inputs on a non-blocking stream of its own, which is not ordered after the caller's
+  // stream: wait for that stream (NULL: the null stream) before anything is read
+  rpd::hip_check(hipStreamSynchronize((hipStream_t)o.stream), "synchronize");
   rpd_session* S = new rpd_session();
   try {
     rpd::hip_check(hipGetDevice(&S->device), "hipGetDevice");

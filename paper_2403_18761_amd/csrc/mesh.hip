@@ -19,7 +19,7 @@ namespace rpd {
 
 constexpr int KPRES = 4096;  // multiplicities k(sigma) must stay below this
 
-enum { MS_INVALID = 1, MS_MESH = 2, MS_TOO_MANY_VERTS = 4, MS_TABLE = 8 };
+enum { MS_INVALID = 1, MS_MESH = 2, MS_TOO_MANY_VERTS = 4, MS_TABLE = 8, MS_EDGE_LINK = 16, MS_VERT_LINK = 32 };
 
 __device__ inline bool grid_ok(float v) {
   if (!(fabsf(v) <= 1.0f)) return false;
@@ -140,6 +140,51 @@ __global__ void k_mesh_neighbours(const int* tface, const int* face_t, const int
       if (kf[s] == 2) nb = face_t[2 * (size_t)s] == k ? face_t[2 * (size_t)s + 1] : face_t[2 * (size_t)s];
       tn[4 * (size_t)k + f] = nb;
     }
+  }
+}
+
+// Manifold links (Sec. 3.3, Assumption: the input is a manifold tet mesh), by counting over the face and edge tables.
+// Edge e: the tets around e, joined through the faces that contain e, form chains; a chain of m tets has m - 1
+// shared faces when open (its two end faces lie on the boundary) and m when closed, so e has one chain exactly when
+// (shared faces = k_e, no boundary face) or (shared faces = k_e - 1, two boundary faces). (Two closed chains around
+// one edge would overlap in space, which the tets of a solid cannot.) Vertex v: the link surface, one vertex per edge
+// at v, one edge per face at v and one triangle per tet at v, must be a sphere (V - E + F = 2, no boundary face at v)
+// or a disk (1, with boundary faces); a pinched vertex, whose link falls apart into several spheres or disks, has a
+// larger characteristic.
+__global__ void k_link_faces(HashTab Fh, const int* kf, HashTab Eh, int* vf, int* vb, int* eint, int* ebnd) {
+  const unsigned cap = Fh.mask + 1;
+  for (unsigned s = blockIdx.x * blockDim.x + threadIdx.x; s < cap; s += gridDim.x * blockDim.x) {
+    const unsigned long long key = Fh.keys[s];
+    if (key == EMPTY_KEY) continue;
+    const unsigned w[3] = {(unsigned)(key >> 42), (unsigned)((key >> 21) & 0x1fffff), (unsigned)(key & 0x1fffff)};
+    const bool bnd = kf[s] == 1;
+    for (int k = 0; k < 3; ++k) {
+      atomicAdd(&vf[w[k]], 1);
+      if (bnd) atomicAdd(&vb[w[k]], 1);
+    }
+    const int pa[3] = {0, 0, 1}, pb[3] = {1, 2, 2};
+    for (int k = 0; k < 3; ++k) {  // w is ascending, so every pair is an edge key (min << 32 | max)
+      const int e = ht_find(Eh, ((unsigned long long)w[pa[k]] << 32) | w[pb[k]]);
+      if (e >= 0) atomicAdd(bnd ? &ebnd[e] : &eint[e], 1);
+    }
+  }
+}
+__global__ void k_link_edges(HashTab Eh, const int* ke, const int* eint, const int* ebnd, int* ve, int* st) {
+  const unsigned cap = Eh.mask + 1;
+  for (unsigned s = blockIdx.x * blockDim.x + threadIdx.x; s < cap; s += gridDim.x * blockDim.x) {
+    const unsigned long long key = Eh.keys[s];
+    if (key == EMPTY_KEY) continue;
+    atomicAdd(&ve[(unsigned)(key >> 32)], 1);
+    atomicAdd(&ve[(unsigned)(key & 0xffffffffull)], 1);
+    const int k = ke[s], fi = eint[s], fb = ebnd[s];
+    if (!((fi == k && fb == 0) || (fi == k - 1 && fb == 2))) atomicOr(st, MS_EDGE_LINK);
+  }
+}
+__global__ void k_link_verts(const int* kv, const int* ve, const int* vf, const int* vb, int nv, int* st) {
+  for (int v = blockIdx.x * blockDim.x + threadIdx.x; v < nv; v += gridDim.x * blockDim.x) {
+    if (kv[v] == 0) continue;
+    const int chi = ve[v] - vf[v] + kv[v];
+    if (!((chi == 2 && vb[v] == 0) || (chi == 1 && vb[v] > 0))) atomicOr(st, MS_VERT_LINK);
   }
 }
 
@@ -309,6 +354,19 @@ void mesh_prepare(rpd_mesh* m, const rpd_mesh_desc* d, uint32_t flags, hipStream
   HashTab Eh{ekeys.as<unsigned long long>(), ecap - 1}, Fh{fkeys.as<unsigned long long>(), fcap - 1};
   hipLaunchKernelGGL(k_mesh_simplices, dim3(gsz(nt)), dim3(256), 0, s, itv.as<int>(), nt, Eh, Fh, tedge.as<int>(),
                      tface.as<int>(), ke.as<int>(), kf.as<int>(), face_t.as<int>(), pst);
+  {  // edge and vertex links
+    DBuf lnk(sizeof(int) * (3 * (size_t)nv + 2 * (size_t)ecap));
+    hip_check(hipMemsetAsync(lnk.p, 0, lnk.bytes, s), "memset");
+    int* vf = lnk.as<int>();
+    int* vb = vf + nv;
+    int* ve = vb + nv;
+    int* eint = ve + nv;
+    int* ebnd = eint + ecap;
+    hipLaunchKernelGGL(k_link_faces, dim3(gsz(fcap)), dim3(256), 0, s, Fh, kf.as<int>(), Eh, vf, vb, eint, ebnd);
+    hipLaunchKernelGGL(k_link_edges, dim3(gsz(ecap)), dim3(256), 0, s, Eh, ke.as<int>(), eint, ebnd, ve, pst);
+    hipLaunchKernelGGL(k_link_verts, dim3(gsz(nv)), dim3(256), 0, s, kv.as<int>(), ve, vf, vb, nv, pst);
+    hip_check(hipStreamSynchronize(s), "sync");  // the counters are released next
+  }
   m->tn.alloc(sizeof(int) * 4 * (size_t)nt);
   hipLaunchKernelGGL(k_mesh_neighbours, dim3(gsz(nt)), dim3(256), 0, s, tface.as<int>(), face_t.as<int>(),
                      kf.as<int>(), nt, m->tn.as<int>());
@@ -333,6 +391,8 @@ void mesh_prepare(rpd_mesh* m, const rpd_mesh_desc* d, uint32_t flags, hipStream
   if (hst[0] & MS_INVALID) throw Failure{RPD_E_INVALID, "mesh: off-grid coordinate, bad index or non-positive tet"};
   if (hst[0] & MS_TABLE) throw Failure{RPD_E_INTERNAL, "mesh: hash table full"};
   if (hst[0] & MS_MESH) throw Failure{RPD_E_MESH, "mesh: a face is shared by more than two tets"};
+  if (hst[0] & MS_EDGE_LINK) throw Failure{RPD_E_MESH, "mesh: non-manifold edge (its tets are not one chain)"};
+  if (hst[0] & MS_VERT_LINK) throw Failure{RPD_E_MESH, "mesh: non-manifold vertex (its link is not a sphere or disk)"};
   long long L = 1;
   bool big = false;
   for (int k = 1; k < KPRES && !big; ++k)

@@ -1,6 +1,7 @@
 // Device-side building blocks of the restricted-power-diagram clipping (paper Sec. 5.2 Tet-Cell clipping with the
 // half-space polytope representation of Sec. 5.2 -- planes + vertices as plane triples -- and the fractional Euler
-// characteristic of Sec. 4.1.2). Everything here is written for gfx950 wave64; no host code.
+// characteristic of Sec. 4.1.2). Everything here is written for gfx950 wave64; the plane constructions and the FP64
+// filter are also compiled for the host, where a test checks them against exact arithmetic.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -10,6 +11,9 @@
 #include "rpd_common.h"
 
 namespace rpd {
+
+// predicate helpers that the host test build also compiles
+#define RPD_HD __host__ __device__
 
 // ---------------------------------------------------------------------------------------------------------------
 // precision traits
@@ -111,7 +115,7 @@ __device__ inline int side_fast(const Plane<T>& q, T x, T y, T z, T F) {
 
 // FP64 homogeneous test with a semi-static bound: sign of plane q at the meet of planes a, b, c, computed as
 // sign(n_q . X + d_q W) * sign(W) from exactly representable (or once-rounded) coefficients. Returns 0 if uncertain.
-__device__ inline int side64(const Plane<double>& A, const Plane<double>& B, const Plane<double>& C,
+RPD_HD inline int side64(const Plane<double>& A, const Plane<double>& B, const Plane<double>& C,
                              const Plane<double>& Q) {
   const double u = Prec<double>::u;
   double bcx = fma(B.ny, C.nz, -(B.nz * C.ny)), bcy = fma(B.nz, C.nx, -(B.nx * C.nz)),
@@ -268,26 +272,9 @@ __device__ inline int side_exact(const PlaneI& A, const PlaneI& B, const PlaneI&
 // Plane construction from a tet (4 vertices, absolute float coordinates on the 2^-20 grid) and sites (x,y,z,r).
 // Local frame: origin at tet vertex 0.  Face f is the face opposite vertex f, normal pointing inwards.
 // ---------------------------------------------------------------------------------------------------------------
-__device__ inline Plane<double> face_plane64(const float4* tv, int f) {
-  int o0 = (f == 0) ? 1 : 0;
-  int o1 = (f <= 1) ? 2 : 1;
-  int o2 = (f <= 2) ? 3 : 2;
-  double px = (double)tv[o0].x - tv[0].x, py = (double)tv[o0].y - tv[0].y, pz = (double)tv[o0].z - tv[0].z;
-  double ux = (double)tv[o1].x - tv[o0].x, uy = (double)tv[o1].y - tv[o0].y, uz = (double)tv[o1].z - tv[o0].z;
-  double wx = (double)tv[o2].x - tv[o0].x, wy = (double)tv[o2].y - tv[o0].y, wz = (double)tv[o2].z - tv[o0].z;
-  double vx = (double)tv[f].x - tv[o0].x, vy = (double)tv[f].y - tv[o0].y, vz = (double)tv[f].z - tv[o0].z;
-  double nx = uy * wz - uz * wy, ny = uz * wx - ux * wz, nz = ux * wy - uy * wx;
-  if (nx * vx + ny * vy + nz * vz < 0) {
-    nx = -nx;
-    ny = -ny;
-    nz = -nz;
-  }
-  return Plane<double>{nx, ny, nz, -(nx * px + ny * py + nz * pz)};
-}
+RPD_HD inline long long grid_int(float v) { return (long long)(v * 1048576.0f); }
 
-__device__ inline long long grid_int(float v) { return (long long)(v * 1048576.0f); }
-
-__device__ inline PlaneI face_planeI(const float4* tv, int f) {
+RPD_HD inline PlaneI face_planeI(const float4* tv, int f) {
   int o0 = (f == 0) ? 1 : 0;
   int o1 = (f <= 1) ? 2 : 1;
   int o2 = (f <= 2) ? 3 : 2;
@@ -313,14 +300,29 @@ __device__ inline PlaneI face_planeI(const float4* tv, int f) {
   return P;
 }
 
+// The same plane in FP64 and float units: the normal (|n| < 2^44 grid units, scaled by 2^-40) is exact and the offset
+// (|d| < 2^66 grid units, scaled by 2^-60) is rounded once: its high part times 2^32 and its low 32 bits are both
+// exact doubles, so their sum is the single rounding. The FP64 filters rely on this (every input coefficient exact or
+// once rounded).
+RPD_HD inline double i128_to_double(i128 v) {
+  const long long hi = (long long)(v >> 32);  // |v| < 2^85 keeps hi exact in a double
+  const unsigned long long lo = (unsigned long long)(v & (i128)0xffffffffull);
+  return ldexp((double)hi, 32) + (double)lo;
+}
+RPD_HD inline Plane<double> face_plane64(const float4* tv, int f) {
+  const PlaneI P = face_planeI(tv, f);
+  return Plane<double>{ldexp((double)P.nx, -40), ldexp((double)P.ny, -40), ldexp((double)P.nz, -40),
+                       ldexp(i128_to_double(P.d), -60)};
+}
+
 // power distance of the local origin o to site s, exact in FP64 (all values multiples of 2^-40, < 2^6)
-__device__ inline double pow_origin64(const float4& s, const float4& o) {
+RPD_HD inline double pow_origin64(const float4& s, const float4& o) {
   double ax = (double)s.x - o.x, ay = (double)s.y - o.y, az = (double)s.z - o.z;
   return ax * ax + ay * ay + az * az - (double)s.w * s.w;
 }
 
 // bisector of site i against site j (kept side: d_i <= d_j), exact coefficients in FP64
-__device__ inline Plane<double> bisector64(const float4& si, const float4& sj, const float4& o) {
+RPD_HD inline Plane<double> bisector64(const float4& si, const float4& sj, const float4& o) {
   return Plane<double>{2.0 * ((double)si.x - sj.x), 2.0 * ((double)si.y - sj.y), 2.0 * ((double)si.z - sj.z),
                        pow_origin64(sj, o) - pow_origin64(si, o)};
 }

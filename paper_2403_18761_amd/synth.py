@@ -453,6 +453,25 @@ def cube_solid(N: int, lo: int = 0, hi: int | None = None):
     return dict(kind="cube", sdf=None, occ=occ, genus=0)
 
 
+# Face-connected voxel sets on a 4^3 grid whose Kuhn meshes are not manifold: two voxels that touch only at the grid
+# vertex (2, 2, 2) ("vertex") or only along the grid edge x = y = 2, 1 <= z <= 2 ("edge"), joined by a path of voxels
+# that stays away from that vertex or edge. Adding the voxel listed under "fix" closes the pinch (a manifold mesh).
+PINCHED = {
+    "vertex": dict(cells=[(1, 1, 1), (0, 1, 1), (0, 2, 1), (0, 3, 1), (1, 3, 1), (2, 3, 1), (2, 3, 2), (2, 2, 2)],
+                   fix=[(2, 1, 1), (2, 2, 1)]),
+    "edge": dict(cells=[(1, 1, 1), (1, 1, 0), (2, 1, 0), (2, 2, 0), (2, 2, 1)], fix=[(2, 1, 1)]),
+}
+
+
+def pinched_voxels(kind: str, fixed: bool = False) -> Problem:
+    """The Kuhn mesh of a PINCHED voxel set (with its fix when fixed), one site at the centre of the first voxel."""
+    occ = np.zeros((4, 4, 4), dtype=bool)
+    for c in PINCHED[kind]["cells"] + (PINCHED[kind]["fix"] if fixed else []):
+        occ[c] = True
+    c0 = -1.0 + (np.asarray(PINCHED[kind]["cells"][0], np.float64) + 0.5) * 0.5
+    return make_problem(dict(kind=f"pinched_{kind}", sdf=None, occ=occ, genus=0), 4, c0[None, :], np.array([0.1]))
+
+
 # ----------------------------------------------------------------------------------------------------------------
 # sites
 # ----------------------------------------------------------------------------------------------------------------

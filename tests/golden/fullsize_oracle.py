@@ -1,0 +1,142 @@
+"""Writes the oracle's results for the full-size workloads into small digest files beside this script.
+
+Calls only ``oracle`` (the CPU brute-force oracle) and ``paper_2403_18761_amd.synth`` (seeded inputs, no arithmetic of
+the method); nothing here touches the HIP path. The whole oracle runs once per workload on the CPU (about one to a few
+hours for the genus-3 solid and the 256-shape batch on 8 threads), and the GPU tests compare their own results with
+the stored digests element list by element list.
+
+What is stored per shape (``fullsize_<workload>.json``):
+
+* ``input_sha256``: digest of the exact input arrays (the test regenerates the input and checks it first);
+* ``n_pairs``, ``L`` and the element counts;
+* ``sha256`` of every exact per-element array, in the byte layout ``digest_arrays`` defines: cell chi and beta0 (one
+  entry per site), face keys/chi/beta0, edge keys/chi/beta0 (sorted by key), RPV keys;
+* sums of chi and beta0 per kind (a mismatch then says which kind differs and by how much);
+* the total cell volume and the volumes of 64 cells picked by a fixed seed (float64, for the 1e-5 check).
+
+Usage: ``python tests/golden/fullsize_oracle.py torus2000|genus3|batch256 [--threads N]``. The batch file is
+written after every shape, and a rerun resumes after the last stored shape of the same input.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+ROOT = os.path.dirname(os.path.dirname(HERE))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+EXACT = ("cell_chi", "cell_beta0", "face_keys", "face_chi", "face_beta0", "edge_keys", "edge_chi", "edge_beta0",
+         "rpv_keys")
+N_VOL_SAMPLES = 64
+
+
+def input_digest(prob) -> str:
+    h = hashlib.sha256()
+    for a, dt in ((prob.vx, np.float32), (prob.vy, np.float32), (prob.vz, np.float32), (prob.tv, np.int32),
+                  (prob.sx, np.float32), (prob.sy, np.float32), (prob.sz, np.float32), (prob.sr, np.float32)):
+        h.update(np.ascontiguousarray(a, dtype=dt).tobytes())
+    return h.hexdigest()
+
+
+def digest_arrays(res: dict) -> dict:
+    """sha256 of each exact array as little-endian int32, row-major (the same layout on the GPU side)."""
+    return {k: hashlib.sha256(np.ascontiguousarray(res[k], dtype="<i4").tobytes()).hexdigest() for k in EXACT}
+
+
+def summary(res: dict) -> dict:
+    return dict(
+        n_cells_nonempty=int(np.count_nonzero(res["cell_vol"] > 0)),
+        n_faces=int(len(res["face_keys"])), n_edges=int(len(res["edge_keys"])), n_rpv=int(len(res["rpv_keys"])),
+        sum_cell_chi=int(np.sum(res["cell_chi"], dtype=np.int64)),
+        sum_cell_beta0=int(np.sum(res["cell_beta0"], dtype=np.int64)),
+        sum_face_chi=int(np.sum(res["face_chi"], dtype=np.int64)),
+        sum_face_beta0=int(np.sum(res["face_beta0"], dtype=np.int64)),
+        sum_edge_chi=int(np.sum(res["edge_chi"], dtype=np.int64)),
+        sum_edge_beta0=int(np.sum(res["edge_beta0"], dtype=np.int64)),
+    )
+
+
+def volume_samples(n_sites: int, seed: int) -> np.ndarray:
+    rng = np.random.default_rng(seed)
+    return np.sort(rng.choice(n_sites, min(N_VOL_SAMPLES, n_sites), replace=False))
+
+
+def shape_record(prob, threads: int, seed: int) -> dict:
+    import oracle
+
+    t0 = time.perf_counter()
+    r = oracle.rpd(prob, threads=threads, assemble=False)
+    dt = time.perf_counter() - t0
+    if not r["consistent"]:
+        raise RuntimeError(f"oracle reports an inconsistency: {r['report']}")
+    pick = volume_samples(prob.n_sites, seed)
+    return dict(
+        input_sha256=input_digest(prob), n_tets=prob.n_tets, n_sites=prob.n_sites, L=r["L"],
+        n_pairs=r["n_pairs"], sha256=digest_arrays(r), **summary(r),
+        volume_total=float(np.sum(r["cell_vol"])), volume_sample_seed=seed,
+        volume_sample_sites=[int(x) for x in pick], volume_sample=[float(r["cell_vol"][x]) for x in pick],
+        oracle_seconds=round(dt, 1), oracle_threads=threads,
+    )
+
+
+def workload_problems(name: str):
+    from paper_2403_18761_amd import synth
+
+    if name == "torus2000":
+        return [synth.torus_inside(N=64, n_sites=2000, seed=2)]
+    if name == "genus3":
+        return [synth.genus3_cad(N=128, n_sites=20000, seed=3)]
+    if name == "batch256":
+        return None  # generated shape by shape (see main)
+    raise SystemExit(f"unknown workload {name}")
+
+
+def path_for(name: str) -> str:
+    return os.path.join(HERE, f"fullsize_{name}.json")
+
+
+def main() -> None:
+    ap = argparse.ArgumentParser()
+    ap.add_argument("workload", choices=("torus2000", "genus3", "batch256"))
+    ap.add_argument("--threads", type=int, default=os.cpu_count() or 1)
+    args = ap.parse_args()
+    import oracle
+
+    oracle.build(force=False)
+    out = path_for(args.workload)
+    if args.workload != "batch256":
+        prob = workload_problems(args.workload)[0]
+        rec = shape_record(prob, args.threads, seed=11)
+        with open(out, "w") as fh:
+            json.dump({"workload": args.workload, "shapes": [rec]}, fh, indent=1)
+        print(args.workload, "done in", rec["oracle_seconds"], "s", flush=True)
+        return
+    from paper_2403_18761_amd import synth
+
+    tets, sites = synth.batch_sizes(256, 4)
+    done = []
+    if os.path.exists(out):
+        with open(out) as fh:
+            done = json.load(fh)["shapes"]
+    for k in range(len(done), 256):
+        prob = synth.batch_shape(k, int(tets[k]), int(sites[k]))
+        rec = shape_record(prob, args.threads, seed=1000 + k)
+        rec["shape"] = k
+        done.append(rec)
+        tmp = out + ".tmp"
+        with open(tmp, "w") as fh:
+            json.dump({"workload": args.workload, "shapes": done}, fh, indent=1)
+        os.replace(tmp, out)
+        print(f"batch shape {k}: {prob.n_tets} tets, {prob.n_sites} sites, {rec['oracle_seconds']} s", flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -54,7 +54,11 @@ def extract(res, k):
 
 
 def assert_parity(g, r, vol_rtol=1e-5, label=""):
-    """Bit-exact chi / beta0 / adjacency; volumes and centroids within FP32 tolerance."""
+    """Bit-exact chi / beta0 / adjacency; volumes and first moments within FP32 tolerance."""
+    # the oracle's own cross-checks (divisibility, cross-side symmetry, gluing symmetry) must hold before its result
+    # serves as the reference
+    if "consistent" in r:
+        assert r["consistent"], (label, r.get("report"))
     np.testing.assert_array_equal(g["cell_chi"], r["cell_chi"], err_msg=f"{label} cell chi")
     np.testing.assert_array_equal(g["cell_beta0"], r["cell_beta0"], err_msg=f"{label} cell beta0")
     np.testing.assert_array_equal(g["face_keys"], r["face_keys"], err_msg=f"{label} face keys")
@@ -70,14 +74,16 @@ def assert_parity(g, r, vol_rtol=1e-5, label=""):
                                err_msg=f"{label} volumes")
     ne = vr > 0
     np.testing.assert_array_equal(np.isnan(g["cell_cen"][:, 0]), ~ne, err_msg=f"{label} empty cells")
-    # centroid = moment / volume on the [-1, 1]^3 domain. A piece's moment error is its volume error times its
-    # position (|x| <= sqrt 3), so with volume error <= rtol vol + atol the centroid error is at most about
-    # 2 sqrt(3) (rtol + atol / vol): tiny cells, whose volume sits near the absolute floor (fixed-point sums with a
-    # 2^-56 quantum), have ill-conditioned centroids and get the second term.
+    # First moments M = vol * centroid, for every nonempty cell however small: a piece's moment is its volume times
+    # a position with |x| <= sqrt 3 (plus the position's own rounding, far below), so the moment error of a cell is
+    # at most sqrt 3 times its volume error; both volume terms (relative and absolute floor) carry over. Tiny cells are
+    # held to the same absolute floor as their volumes.
     atol = vol_rtol * 1e-6 * max(vr.max(), 1e-30)
-    err = np.abs(g["cell_cen"][ne] - r["cell_cen"][ne]).max(axis=1, initial=0.0)
-    bound = 4 * (vol_rtol + atol / vr[ne])
-    assert np.all(err < bound), (label, err.max(initial=0.0), (err / bound).max(initial=0.0))
+    mg = g["cell_cen"][ne] * g["cell_vol"][ne, None]
+    mr = r["cell_cen"][ne] * vr[ne, None]
+    err = np.abs(mg - mr).max(axis=1, initial=0.0)
+    bound = 2 * np.sqrt(3.0) * (vol_rtol * vr[ne] + atol)
+    assert np.all(err <= bound), (label, "first moments", (err / bound).max(initial=0.0))
     # RPE lengths: a segment's endpoint is where the line of two bisector planes crosses a third plane; the planes
     # are rounded to the working precision, so the endpoint errs by u |x| / sin(angle of line and plane), and
     # shallow crossings amplify u = 6e-8 (FP32) by 10^2..10^3 where the volumes, integrals over the piece, average

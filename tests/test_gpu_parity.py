@@ -171,6 +171,15 @@ def test_errors_reported():
     with pytest.raises(rpd.RPDError) as e:
         run_gpu(synth.Problem(base.vx, base.vy, base.vz, tv, base.sx, base.sy, base.sz, base.sr, {}))
     assert e.value.code == -1
+    # non-manifold meshes (Sec. 3.3, Assumption): a bow-tie vertex and a bow-tie edge, rejected like the oracle does;
+    # the same voxel sets with the pinch closed are accepted
+    for kind in ("vertex", "edge"):
+        for device_ptrs in (True, False):
+            with pytest.raises(rpd.RPDError) as e:
+                run_gpu(synth.pinched_voxels(kind), device_ptrs=device_ptrs)
+            assert e.value.code == -2 and f"non-manifold {kind}" in str(e.value), str(e.value)
+        fixed = synth.pinched_voxels(kind, fixed=True)
+        assert_parity(run_gpu(fixed), _oracle(fixed, assemble=False), label=f"pinch closed ({kind})")
 
 
 def test_batch_of_shapes_in_one_call():

@@ -96,6 +96,32 @@ def test_session_matches_oracle():
     assert_parity(g, ref, label="session vs oracle")
 
 
+def test_session_waits_for_pending_site_writes():
+    """Sites written by GPU work that is still queued on the null (default) stream when the session is created: the
+    session computes on a non-blocking stream of its own, so it must wait for the caller's stream (NULL: the null
+    stream) before it reads them."""
+    import torch
+
+    from paper_2403_18761_amd import rpd
+
+    prob = synth.torus_core(16, 64, 1)
+    table = synth.centroid_table(prob, 0.02)
+    log(f"case: session on freshly written sites, tets {prob.n_tets}")
+    mesh = _mesh(prob)
+    base = [_dev(x) for x in (prob.sx, prob.sy, prob.sz, prob.sr)]
+    torch.cuda.synchronize()
+    busy = torch.ones(1 << 24, device="cuda:0")
+    for _ in range(40):  # a queue of default-stream work ahead of the kernels that write the sites
+        busy = busy * 1.0000001
+    sites = tuple((b * 2.0) * 0.5 for b in base)  # exact, written by kernels behind that queue
+    sess = rpd.Session(mesh, sites, tuple(_dev(x) for x in table), max_sites=64 + 16, max_insert=8)
+    res = sess.result()
+    got = extract(res, 0)
+    got["stats"] = res.stats()
+    np.testing.assert_array_equal(sess.sites(), np.stack([prob.sx, prob.sy, prob.sz, prob.sr], axis=1))
+    _same(got, _rebuild(mesh, sess.sites()), "fresh sites")
+
+
 def test_session_rejects_bad_arguments():
     from paper_2403_18761_amd import rpd
 

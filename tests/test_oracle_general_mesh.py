@@ -40,3 +40,25 @@ def test_delaunay_mesh_consistent(oracle_lib, seed):
     vol = np.einsum("ij,ij->i", P[t[:, 1]] - P[t[:, 0]],
                     np.cross(P[t[:, 2]] - P[t[:, 0]], P[t[:, 3]] - P[t[:, 0]])).sum() / 6
     assert abs(r["cell_vol"].sum() - vol) < 1e-12 * vol
+
+
+@pytest.mark.parametrize("kind", ["vertex", "edge"])
+def test_pinched_meshes_are_rejected(oracle_lib, kind):
+    """Sec. 3.3, Assumption: the input is a manifold tet mesh. A face-connected voxel mesh with a bow-tie vertex (two
+    voxels that share only a corner) or a bow-tie edge (two voxels that share only an edge) is an input error; the same
+    set with the pinch closed is accepted. Ground truth independent of the oracle: the voxel-level test for a
+    manifold boundary (no edge- or vertex-critical 2x2 / 2x2x2 configuration)."""
+    import numpy as np
+
+    import oracle
+
+    for fixed in (False, True):
+        occ = np.zeros((4, 4, 4), dtype=bool)
+        for c in synth.PINCHED[kind]["cells"] + (synth.PINCHED[kind]["fix"] if fixed else []):
+            occ[c] = True
+        assert synth.well_composed(occ) == fixed
+    with pytest.raises(oracle.OracleError) as e:
+        oracle.rpd(synth.pinched_voxels(kind))
+    assert e.value.status == -2 and f"non-manifold {kind}" in e.value.msg, e.value.msg
+    r = oracle.rpd(synth.pinched_voxels(kind, fixed=True))
+    assert r["mesh_components"] == 1 and r["consistent"]

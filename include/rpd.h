@@ -237,6 +237,18 @@ rpd_status rpd_get_stats(const rpd_result* r, rpd_stats* stats);
 rpd_status rpd_pieces(const rpd_result* r, int32_t shape, int64_t* n_out, const int32_t** tet, const int32_t** site,
                       const double** vol_moment /* 4 per piece */, const int64_t** chi_num);
 
+/* Per-piece element terms kept with RPD_KEEP_PIECES (Sec. 4.1.2: each piece's fractional contributions; Sec. 4.1.1:
+ * the mesh faces through which its element pieces are glued). kind RPD_CELL: one term per nonempty piece (site i;
+ * num = its cell contribution over L; glue bit f: the piece touches interior face f of its tet, bit 4 + f: boundary
+ * face f). RPD_FACE: one per face of a piece lying on the bisector of i against j > i (sites i, j; num = the RPF
+ * piece's contribution; glue bit f: the face polygon has an edge on interior face f). RPD_EDGE: one per segment of
+ * a piece on the bisectors of i against j and k, i < j < k (sites i, j, k; glue bit f: an endpoint on interior face
+ * f). RPD_VERTEX: one per vertex of a piece on three bisectors, all of whose sites exceed i (sites i, j, k, l; num 1,
+ * glue 0). tet is in the caller's numbering; sites holds kind ids per term (shape-local); terms are ordered by
+ * (tet, sites). Arrays are host memory owned by r; n_out is 0 without RPD_KEEP_PIECES. */
+rpd_status rpd_piece_terms(const rpd_result* r, int32_t shape, int32_t kind, int64_t* n_out, const int32_t** tet,
+                           const int32_t** sites, const int64_t** num, const int32_t** glue);
+
 void rpd_free(rpd_result* r);
 
 /* Autotuner for the batched FP32 path: runs rpd_build on these inputs once per launch shape (block of 64, 128 or 256
@@ -255,8 +267,11 @@ rpd_status rpd_autotune(const rpd_mesh* const* meshes, const rpd_sites* sites, i
  *   1. selects up to max_insert restricted power cells with chi != 1 or more than one component (lowest site ids
  *      first; Sec. 3.3 / 4.1 criteria for a cell),
  *   2. picks for each a tet among the cell's pieces (for a cell with several components, outside the component
- *      of its first piece) and appends a sphere (each at most once):
- *      RPD_INSERT_TABLE: the sphere that `table` holds for a tet chosen by a fixed hash of (tet, round);
+ *      of its piece in the smallest tet, tets in the caller's numbering) and appends a sphere (each at most once):
+ *      RPD_INSERT_TABLE: the sphere that `table` holds for the candidate tet t (pieces whose table sphere is not in
+ *      yet) with the largest pair (h, t), h = the upper 32 bits of the splitmix64 finaliser of t * 2^32 + round
+ *      (rounds counted from 0); spheres are appended in the order of the selected cells, a cell's sphere skipped
+ *      when an earlier cell of the round picked the same tet;
  *      RPD_INSERT_SHRINK (Sec. 4.1.3 with Sec. 5.1): among the surface triangles (mesh faces without a neighbour)
  *      the cell's pieces touch, the one whose centroid is furthest from the cell's sphere centre is the pin, and the
  *      sphere is the shrunk sphere at that pin (rpd_shrink_spheres over the mesh surface, computed once at

@@ -52,6 +52,7 @@ class _Result(C.Structure):
         ("edge_beta0_skel", C.POINTER(C.c_int32)), ("edge_length", C.POINTER(C.c_double)),
         ("n_rpv", C.c_int64), ("rpv_keys", C.POINTER(C.c_int32)),
         ("max_piece_verts", C.c_int32), ("max_piece_faces", C.c_int32),
+        ("n_cell_pieces", C.c_int64), ("cell_piece", C.POINTER(C.c_int32)),
     ]
 
 
@@ -166,6 +167,7 @@ def rpd(prob, threads: int = 0, assemble: bool = True, owner_weights: bool = Fal
             edge_beta0_skel=_arr(r.edge_beta0_skel, ne, np.int32),
             edge_length=_arr(r.edge_length, ne, np.float64),
             rpv_keys=_arr(r.rpv_keys, 4 * nq, np.int32, (nq, 4)),
+            cell_piece=_arr(r.cell_piece, 3 * r.n_cell_pieces, np.int32, (r.n_cell_pieces, 3)),
         )
         return res
     finally:

@@ -1161,6 +1161,10 @@ typedef struct oracle_result {
   // per-piece statistics
   int32_t max_piece_verts;
   int32_t max_piece_faces;
+  // the connected component of every cell piece: (t, i, label), labels equal iff the pieces of cell i are glued
+  // into one component (Sec. 4.1.1); ordered by (i, t)
+  int64_t n_cell_pieces;
+  int32_t* cell_piece;  // 3 per piece
 } oracle_result;
 
 typedef struct oracle_piece {  // one nonempty piece, for sampled comparisons
@@ -1361,6 +1365,13 @@ int oracle_rpd(int32_t nv, const float* vx, const float* vy, const float* vz, in
     for (const auto& kv : glue_seen)
       if (kv.second != 2) flag("gluing record not symmetric across a mesh face");
     std::vector<int32_t> cb0(ns, 0), fb0(fkeys.size() / 2, 0), eb0(ekeys.size() / 3, 0);
+    std::vector<int32_t> cell_piece;  // (t, i, root) of every cell piece, in (i, t) order (the map's order)
+    for (const auto& kv : node)
+      if (kv.first.first.kind == 1) {
+        cell_piece.push_back(kv.first.second);
+        cell_piece.push_back(kv.first.first.s[0]);
+        cell_piece.push_back(find_root(par, kv.second));
+      }
     for (const auto& kv : node) {
       if (find_root(par, kv.second) != kv.second) continue;
       const Elem& e = kv.first.first;
@@ -1459,6 +1470,8 @@ int oracle_rpd(int32_t nv, const float* vx, const float* vy, const float* vz, in
     R->edge_length = dup(elength);
     R->n_rpv = (int64_t)rkeys.size() / 4;
     R->rpv_keys = dup(rkeys);
+    R->n_cell_pieces = (int64_t)cell_piece.size() / 3;
+    R->cell_piece = dup(cell_piece);
     R->status = OK;
     set_msg(R->msg, "ok");
   } catch (const Failure& f) {
@@ -1580,7 +1593,7 @@ void oracle_free(oracle_result* r) {
   void* ptrs[] = {r->cell_chi,   r->cell_chi_asm,    r->cell_beta0,   r->cell_beta0_skel, r->cell_vol,
                   r->cell_cen,   r->cell_npieces,    r->face_keys,    r->face_chi,        r->face_chi_asm,
                   r->face_beta0, r->face_beta0_skel, r->edge_keys,    r->edge_chi,        r->edge_chi_asm,
-                  r->edge_beta0, r->edge_beta0_skel, r->edge_length, r->rpv_keys};
+                  r->edge_beta0, r->edge_beta0_skel, r->edge_length, r->rpv_keys, r->cell_piece};
   for (void* p : ptrs) std::free(p);
   std::free(r);
 }

@@ -111,6 +111,9 @@ struct ShapeOut {
   std::vector<int32_t> pc_t, pc_i;
   std::vector<double> pc_geo;
   std::vector<int64_t> pc_chi;
+  // per-piece element terms by kind (cell, face, edge, RPV): caller tet, kind site ids, numerator, gluing bits
+  std::vector<int32_t> tm_t[4], tm_s[4], tm_glue[4];
+  std::vector<int64_t> tm_num[4];
 };
 
 struct Timing {
@@ -149,10 +152,10 @@ struct DeviceState {
   int nsh = 0, ns_cap = 0;
   long long nt_tot = 0;
   unsigned capF = 0, capE = 0, capQ = 0, capN = 0;
-  int def_cap = 0, piece_cap = 0;
+  int def_cap = 0, piece_cap = 0, term_cap = 0;
   DBuf site, status, cell_chi, cell_geo, cell_np, cell_b0;
   DBuf fkeys, face_chi, face_np, face_b0, ekeys, edge_chi, edge_np, edge_len, edge_b0, qkeys, rpv_cnt;
-  DBuf nkeys, node_st, parent, deferred, deferred2, pieces, counters, tetU, slow, touch;
+  DBuf nkeys, node_st, parent, deferred, deferred2, pieces, terms, counters, tetU, slow, touch;
   int waves = 0;
 
   unsigned long long* cnt() const { return counters.as<unsigned long long>(); }
@@ -182,6 +185,7 @@ struct DeviceState {
     if (capN > (1u << 23)) capN = std::max(1u << 23, pow2_cap((6 * (size_t)nt + 4096) * scale));
     def_cap = (int)std::min<size_t>((4 * (size_t)nt + 4096) * scale, 1u << 30);
     piece_cap = keep_pieces ? (int)std::min<size_t>((8 * (size_t)nt + 1024) * scale, 1u << 30) : 0;
+    term_cap = keep_pieces ? (int)std::min<size_t>((24 * (size_t)nt + 4096) * scale, 1u << 30) : 0;
     site.alloc(sizeof(float4) * (size_t)ns);
     status.alloc(16);
     cell_chi.alloc(8 * (size_t)ns);
@@ -205,6 +209,7 @@ struct DeviceState {
     deferred.alloc(16 * (size_t)def_cap);
     deferred2.alloc(16 * (size_t)(def_cap / 4 + 1024));
     pieces.alloc(sizeof(PieceRec) * (size_t)std::max(piece_cap, 1));
+    terms.alloc(sizeof(TermRec) * (size_t)std::max(term_cap, 1));
     counters.alloc(8 * (NCOUNTERS + 8 + (size_t)NSPREAD * NCOUNTERS));
     if (keep_U) {  // incremental updates: U_t per tet and the touched-element flags
       tetU.alloc(8 * (size_t)std::max<long long>(nt, 1));
@@ -276,6 +281,8 @@ struct DeviceState {
     a.deferred2_cap = def_cap / 4 + 1024;
     a.pieces = pieces.as<PieceRec>();
     a.piece_cap = piece_cap;
+    a.terms = terms.as<TermRec>();
+    a.term_cap = term_cap;
     a.counters = cnt();
     a.stats = stat();
     a.status = status.as<int>();
@@ -374,7 +381,8 @@ static bool collect(DeviceState& D, const std::vector<ShapeDesc>& hd, const Shap
   hip_check(hipMemcpyAsync(&hst, D.status.p, sizeof(int), hipMemcpyDeviceToHost, s), "download");
   D.totals(hc, s);
   if (hst & ST_TABLE_FULL) return false;
-  if (hc[C_DEFER_ITEMS] > (unsigned long long)D.def_cap || (D.piece_cap && hc[C_PIECES] > (unsigned long long)D.piece_cap))
+  if (hc[C_DEFER_ITEMS] > (unsigned long long)D.def_cap ||
+      (D.piece_cap && (hc[C_PIECES] > (unsigned long long)D.piece_cap || hc[C_TERMS] > (unsigned long long)D.term_cap)))
     return false;
   status_error(hst);
   const size_t nf = hc[NCOUNTERS + 0], ne = hc[NCOUNTERS + 1], nq = hc[NCOUNTERS + 2];
@@ -452,6 +460,8 @@ static bool collect(DeviceState& D, const std::vector<ShapeDesc>& hd, const Shap
   hip_check(hipMemcpyAsync(hb + out_bytes, D.status.p, sizeof(int), hipMemcpyDeviceToHost, s), "download");
   std::vector<PieceRec> prs;
   if (D.piece_cap) d2h(prs, D.pieces.p, hc[C_PIECES], s);
+  std::vector<TermRec> trs;
+  if (D.piece_cap) d2h(trs, D.terms.p, hc[C_TERMS], s);
   tm.mark(4, s);
   hip_check(hipStreamSynchronize(s), "synchronize");
   status_error(*(int*)(hb + out_bytes));
@@ -512,15 +522,28 @@ static bool collect(DeviceState& D, const std::vector<ShapeDesc>& hd, const Shap
     out.pc_i.clear();
     out.pc_geo.clear();
     out.pc_chi.clear();
+    for (int q = 0; q < 4; ++q) {
+      out.tm_t[q].clear();
+      out.tm_s[q].clear();
+      out.tm_num[q].clear();
+      out.tm_glue[q].clear();
+    }
   }
   if (D.piece_cap) {
     std::vector<std::vector<int32_t>> perms(nsh);
     std::vector<std::vector<size_t>> per_shape(nsh);
-    for (size_t q = 0; q < prs.size(); ++q) {
-      int k = nsh - 1;
-      while (k > 0 && hd[k].tet_off > prs[q].t) --k;
-      per_shape[k].push_back(q);
-    }
+    std::vector<std::vector<size_t>> terms_of(nsh);
+    auto shape_of = [&](long long t) {
+      int lo = 0, hi = nsh - 1;
+      while (lo < hi) {
+        const int mid = (lo + hi + 1) / 2;
+        if (hd[mid].tet_off <= t) lo = mid;
+        else hi = mid - 1;
+      }
+      return lo;
+    };
+    for (size_t q = 0; q < prs.size(); ++q) per_shape[shape_of(prs[q].t)].push_back(q);
+    for (size_t q = 0; q < trs.size(); ++q) terms_of[shape_of(trs[q].t)].push_back(q);
     for (int k = 0; k < nsh; ++k) {
       if (per_shape[k].empty()) continue;
       d2h(perms[k], meshes[k]->perm.p, meshes[k]->nt, s);
@@ -531,6 +554,22 @@ static bool collect(DeviceState& D, const std::vector<ShapeDesc>& hd, const Shap
         return tt(x) != tt(y) ? tt(x) < tt(y) : prs[x].i < prs[y].i;
       });
       ShapeOut& out = outs[k];
+      // element terms of the shape's pieces, by kind, ordered by (caller tet, site ids)
+      std::vector<size_t>& tix = terms_of[k];
+      auto tkey = [&](size_t q) {
+        const TermRec& r = trs[q];
+        return std::make_tuple(r.kind, perms[k][r.t - (int)hd[k].tet_off], r.i, r.j, r.k, r.l);
+      };
+      std::sort(tix.begin(), tix.end(), [&](size_t x, size_t y) { return tkey(x) < tkey(y); });
+      for (size_t q : tix) {
+        const TermRec& r = trs[q];
+        const int kind = r.kind, off = hd[k].site_off;
+        out.tm_t[kind - 1].push_back(perms[k][r.t - (int)hd[k].tet_off]);
+        const int ids[4] = {r.i, r.j, r.k, r.l};
+        for (int c = 0; c < kind; ++c) out.tm_s[kind - 1].push_back(ids[c] - off);
+        out.tm_num[kind - 1].push_back(r.num);
+        out.tm_glue[kind - 1].push_back(r.glue);
+      }
       for (size_t q : idx) {
         const PieceRec& p = prs[q];
         out.pc_t.push_back(tt(q));
@@ -569,6 +608,7 @@ static std::vector<ShapeDesc> shape_table(const rpd_mesh* const* meshes, const i
     const rpd_mesh* m = meshes[k];
     ShapeDesc& d = hd[k];
     d.tp = m->tp.as<float4>();
+    d.tf = m->tf.as<double4>();
     d.tn = m->tn.as<int>();
     d.nu = m->nu.as<unsigned>();
     d.blk = m->blk.as<int>();
@@ -1028,6 +1068,21 @@ rpd_status rpd_pieces(const rpd_result* r, int32_t shape, int64_t* n_out, const 
   return RPD_OK;
 }
 
+rpd_status rpd_piece_terms(const rpd_result* r, int32_t shape, int32_t kind, int64_t* n_out, const int32_t** tet,
+                           const int32_t** sites, const int64_t** num, const int32_t** glue) {
+  rpd_status e = shape_check(r, shape);
+  if (e) return e;
+  if (!n_out || kind < RPD_CELL || kind > RPD_VERTEX) return RPD_E_INVALID;
+  const rpd::ShapeOut& s = r->shapes[shape];
+  const int q = kind - 1;
+  *n_out = (int64_t)s.tm_t[q].size();
+  if (tet) *tet = s.tm_t[q].data();
+  if (sites) *sites = s.tm_s[q].data();
+  if (num) *num = s.tm_num[q].data();
+  if (glue) *glue = s.tm_glue[q].data();
+  return RPD_OK;
+}
+
 void rpd_free(rpd_result* r) { delete r; }
 
 }  // extern "C"
@@ -1118,8 +1173,8 @@ static bool session_init(rpd_session* S, const rpd_sites* sites, const rpd_sites
                                      S->tet_used.as<int>(), s),
               "table");
     hip_check(hipStreamSynchronize(s), "synchronize");
-  } else {  // the table, validated like sites, then put in the internal tet order
-    DBuf raw(sizeof(float4) * (size_t)nt), stage;
+  } else {  // the table, validated like sites, kept in the caller's tet order (the pick rule's numbering)
+    DBuf stage;
     const float *tx = table->sx, *ty = table->sy, *tz = table->sz, *tr = table->sr;
     if (!dev) {
       stage.alloc(sizeof(float) * 4 * (size_t)nt);
@@ -1133,9 +1188,9 @@ static bool session_init(rpd_session* S, const rpd_sites* sites, const rpd_sites
       tz = q + 2 * (size_t)nt;
       tr = q + 3 * (size_t)nt;
     }
-    hip_check(launch_validate_sites(tx, ty, tz, tr, nt, raw.as<float4>(), D.status.as<int>(), s), "validate table");
     S->table.alloc(sizeof(float4) * (size_t)nt);
-    hip_check(launch_gather_table(raw.as<float4>(), m->perm.as<int>(), nt, S->table.as<float4>(), s), "table");
+    hip_check(launch_validate_sites(tx, ty, tz, tr, nt, S->table.as<float4>(), D.status.as<int>(), s),
+              "validate table");
     hip_check(hipStreamSynchronize(s), "synchronize");  // the staging buffers are released next
   }
   std::vector<int> tb(nt);
@@ -1151,7 +1206,7 @@ static bool session_init(rpd_session* S, const rpd_sites* sites, const rpd_sites
   S->dirty.alloc(sizeof(int) * (size_t)nblk);
   S->sel.alloc(sizeof(int) * (size_t)S->max_insert);
   S->best.alloc(8 * (size_t)S->max_insert);
-  S->ref.alloc(sizeof(int) * (size_t)S->max_insert);
+  S->ref.alloc(sizeof(unsigned long long) * (size_t)S->max_insert);
   S->selpos.alloc(sizeof(int) * (size_t)S->max_sites);
   S->ints.alloc(sizeof(int) * SI_COUNT);
   hip_check(hipMemcpyAsync(S->dshapes.p, two, sizeof(two), hipMemcpyHostToDevice, s), "upload");
@@ -1190,7 +1245,8 @@ static bool session_init(rpd_session* S, const rpd_sites* sites, const rpd_sites
   r.sel = S->sel.as<int>();
   r.selpos = S->selpos.as<int>();
   r.best = S->best.as<unsigned long long>();
-  r.ref = S->ref.as<int>();
+  r.ref = S->ref.as<unsigned long long>();
+  r.perm = m->perm.as<int>();
   r.tet_used = S->tet_used.as<int>();
   r.table = S->table.as<float4>();
   r.mode = S->mode;

@@ -46,6 +46,28 @@ __device__ inline void node_emit(const ShapeArgs& a, unsigned long long key, int
   atomicAdd(&a.node_st[ns], a.sign * (NODE_UNIT + glue));  // removal re-emits the same bits, so this is exact
 }
 
+// a per-piece element term for sampled comparisons (RPD_KEEP_PIECES only)
+__device__ inline void keep_term(const ShapeArgs& a, int kind, int t, int i, int j, int k, int l, int glue,
+                                 long long num) {
+  if (!(a.flags & RPD_KEEP_PIECES)) return;
+  const unsigned long long idx = atomicAdd(&a.counters[C_TERMS], 1ull);
+  if (idx < (unsigned long long)a.term_cap) {
+    TermRec r;
+    r.kind = kind;
+    r.t = t;
+    r.i = i;
+    r.j = j;
+    r.k = k;
+    r.l = l;
+    r.glue = glue;
+    r.pad = 0;
+    r.num = num;
+    a.terms[idx] = r;
+  } else {
+    atomicOr(a.status, ST_TABLE_FULL);
+  }
+}
+
 // Workgroup-local sums of the cell terms (chi numerator, piece count, fixed-point volume and moments) for the first
 // n sites of the workgroup's site list; a piece of another site adds to the global arrays directly.
 struct CellSink {
@@ -100,6 +122,7 @@ __device__ void emit_piece(Clipper<T, Topo, Mask, VCAP, EXACT>& c, const ShapeDe
           if (qs >= 0) atomicAdd(&a.rpv_cnt[qs], a.sign);
         }
         stat_add(a, C_RPV, 1ull);
+        keep_term(a, 4, t, i, lo, mid, hi, 0, 1);
       }
     }
   }
@@ -162,6 +185,7 @@ __device__ void emit_piece(Clipper<T, Topo, Mask, VCAP, EXACT>& c, const ShapeDe
               atomicAdd((unsigned long long*)&a.edge_len[es], (unsigned long long)(a.sign * fixed56(len)));
               int g = ((t1 < 4 && tn[t1] >= 0) ? (1 << t1) : 0) | ((t2 < 4 && tn[t2] >= 0) ? (1 << t2) : 0);
               node_emit(a, node_key(3, es, t), g);
+              keep_term(a, 3, t, i, j, k, -1, g, ev);
             }
           }
         }
@@ -204,11 +228,13 @@ __device__ void emit_piece(Clipper<T, Topo, Mask, VCAP, EXACT>& c, const ShapeDe
         atomicAdd(&a.face_np[fs], a.sign);
         node_emit(a, node_key(2, fs, t), fglue);
       }
+      keep_term(a, 2, t, i, sp, -1, -1, fglue, fvl);
     }
   }
   // ---- cell contributions
   long long chi = sv - se + sf - L;
   node_emit(a, node_key(1, i, t), cell_glue);
+  keep_term(a, 1, t, i, -1, -1, -1, cell_glue, chi);
   // moments were accumulated with 4x the centroid sum; shift to absolute coordinates
   float4 o = c.env.tv[0];
   double dvol = (double)vol;
@@ -411,8 +437,10 @@ __global__ __launch_bounds__(NT) void k_clip_fast(ShapeArgs a) {
         hi[1] = fmaxf(hi[1], p.y);
         hi[2] = fmaxf(hi[2], p.z);
       }
+      const double4* tf = sd.tf + 4 * (size_t)(t0 + tid);
       for (int f = 0; f < 4; ++f) {
-        Plane<float> pf = round_plane<float>(face_plane64(s_tv[tid], f));
+        const double4 pd = tf[f];
+        Plane<float> pf = round_plane<float>(Plane<double>{pd.x, pd.y, pd.z, pd.w});
         s_face[tid][f] = make_float4(pf.nx, pf.ny, pf.nz, pf.d);
       }
     }
@@ -617,6 +645,7 @@ __global__ __launch_bounds__(NT) void k_clip_fast(ShapeArgs a) {
     cl.nex = 0;
     cl.env.tv = s_tv[lt];
     cl.env.faceT = s_face[lt];
+    cl.env.face64 = sd.tf + 4 * (size_t)(t0 + lt);
     cl.env.sites = s_site;
     cl.env.sid = s_sid;
     cl.env.cidx8 = s_cand[lt];
@@ -731,6 +760,7 @@ __global__ __launch_bounds__(64, LDS ? 1 : 2) void k_clip_slow(ShapeArgs a, unsi
   // the sites of its first SC candidates (sorted positions)
   constexpr int SC = 256;
   __shared__ float4 s_tv4[4];
+  __shared__ double4 s_tf4[4];
   __shared__ float4 s_csite[SC];
   const int n_main = (int)min(min(a.counters[C_DEFER_ITEMS], (unsigned long long)a.deferred_cap),
                               (unsigned long long)item_end);
@@ -761,7 +791,10 @@ __global__ __launch_bounds__(64, LDS ? 1 : 2) void k_clip_slow(ShapeArgs a, unsi
     const float4* ssite = a.site + sd.site_off;
     float4 tv[4];
     for (int v = 0; v < 4; ++v) tv[v] = sd.tp[4 * (size_t)t + v];
-    if (lane < 4) s_tv4[lane] = sd.tp[4 * (size_t)t + lane];
+    if (lane < 4) {
+      s_tv4[lane] = sd.tp[4 * (size_t)t + lane];
+      s_tf4[lane] = sd.tf[4 * (size_t)t + lane];
+    }
     const float4 o = tv[0];
     double y[3][3];
     for (int v = 1; v < 4; ++v) {
@@ -878,6 +911,7 @@ __global__ __launch_bounds__(64, LDS ? 1 : 2) void k_clip_slow(ShapeArgs a, unsi
       cl.nex = 0;
       cl.env.tv = s_tv4;
       cl.env.faceT = nullptr;
+      cl.env.face64 = s_tf4;
       cl.env.sites = a.site;
       cl.env.sid = nullptr;  // candidates hold batch-global site ids directly
       cl.env.cidx8 = nullptr;

@@ -92,6 +92,15 @@ __global__ void k_mesh_gather(const int* tv, const int* perm, int nt, int nv, co
   }
 }
 
+// the four face planes of every tet in FP64 (tet-local frame), computed once per mesh: the exact integer plane with its
+// offset rounded once, which every FP64 filter reads instead of rebuilding it with 128-bit products
+__global__ void k_mesh_faces64(const float4* tp, int nt, double4* tf) {
+  for (long long q = blockIdx.x * (long long)blockDim.x + threadIdx.x; q < 4ll * nt; q += (long long)gridDim.x * blockDim.x) {
+    const Plane<double> P = face_plane64(tp + 4 * (q >> 2), (int)(q & 3));
+    tf[q] = make_double4(P.nx, P.ny, P.nz, P.d);
+  }
+}
+
 __global__ void k_mesh_simplices(const int* itv, int nt, HashTab Eh, HashTab Fh, int* tedge, int* tface, int* ke,
                                  int* kf, int* face_t, int* st) {
   const int EV[6][2] = {{0, 1}, {0, 2}, {0, 3}, {1, 2}, {1, 3}, {2, 3}};
@@ -341,6 +350,9 @@ void mesh_prepare(rpd_mesh* m, const rpd_mesh_desc* d, uint32_t flags, hipStream
   hip_check(hipMemsetAsync(kv.p, 0, sizeof(int) * nv, s), "memset");
   hipLaunchKernelGGL(k_mesh_gather, dim3(gsz(nt)), dim3(256), 0, s, ptv, m->perm.as<int>(), nt, nv, pvx, pvy, pvz,
                      m->tp.as<float4>(), itv.as<int>(), kv.as<int>());
+  m->tf.alloc(sizeof(double4) * 4 * (size_t)nt);
+  hipLaunchKernelGGL(k_mesh_faces64, dim3(gsz(4ll * nt)), dim3(256), 0, s, m->tp.as<float4>(), nt,
+                     m->tf.as<double4>());
   // edges and faces
   // capacities at least the number of possible distinct keys (6 edges and 4 faces per tet): inserts cannot fail
   unsigned ecap = pow2_at_least(6 * (size_t)nt + 1024), fcap = pow2_at_least(4 * (size_t)nt + 1024);

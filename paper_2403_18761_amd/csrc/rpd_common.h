@@ -35,6 +35,7 @@ enum {
   C_DEFER2,       // items handed on by the LDS variant of the large-capacity kernel
   C_GLUE_BITS,    // gluing bits of the pieces whose components are (re)computed
   C_GLUE_PAIRS,   // glued pairs matched
+  C_TERMS,        // per-piece element terms kept with RPD_KEEP_PIECES (cursor)
   NCOUNTERS
 };
 // C_RPV counts RPV emissions; the RPV list itself is the set of keys of ShapeArgs::Q with a positive count
@@ -67,9 +68,18 @@ struct PieceRec {
   long long chi;  // fractional cell contribution (numerator over L)
 };
 
+// per-piece element term kept with RPD_KEEP_PIECES: the piece of site i in tet t contributes num (over L) to the
+// element of kind 1 (cell i), 2 (face {i, j}), 3 (edge {i, j, k}) or 4 (RPV {i, j, k, l}: num = 1), and touches the
+// faces of t in glue (bit f: interior face f; cells also 16 << f: boundary face f)
+struct TermRec {
+  int kind, t, i, j, k, l, glue, pad;
+  long long num;
+};
+
 // One shape of a batch: its prepared mesh and its range of the batch's site array.
 struct ShapeDesc {
   const float4* tp;    // [4 nt] tet vertex coordinates (w unused), internal (Morton) tet order
+  const double4* tf;   // [4 nt] face f of every tet in FP64, tet-local frame (normal exact, offset rounded once)
   const int* tn;       // [4 nt] neighbour tet across local face f (face f is opposite vertex f), -1 on the boundary
   const unsigned* nu;  // [14 nt] weight numerators L/k: 4 vertices, 6 edges, 4 faces
   const int* blk;      // [nblk + 1] first tet of every workgroup block (spatially compact runs of <= TB tets)
@@ -119,6 +129,8 @@ struct ShapeArgs {
   int deferred2_cap;
   PieceRec* pieces;      // kept with RPD_KEEP_PIECES (t = global tet id)
   int piece_cap;
+  TermRec* terms;        // kept with RPD_KEEP_PIECES (t = global tet id)
+  int term_cap;
   unsigned long long* counters;  // [NCOUNTERS] (cursors and host-read totals)
   unsigned long long* stats;     // [NSPREAD][NCOUNTERS] spread statistics
   int* status;
@@ -156,10 +168,12 @@ struct RoundState {
   int* nsel;                  // cells selected this round
   int* sel;                   // [max_insert] selected cells, ascending
   int* selpos;                // [max_sites] position of a cell in sel, or -1
-  unsigned long long* best;   // [max_insert] packed (hash, tet) of the tet chosen for the cell
-  int* ref;                   // [max_insert] smallest tet among the cell's pieces
+  unsigned long long* best;   // [max_insert] packed (hash, slot) of the slot chosen for the cell
+  unsigned long long* ref;    // [max_insert] the cell's piece in its smallest tet: caller tet << 32 | internal tet
   int* tet_used;              // [slots] the slot's sphere has been inserted (or it has none)
-  const float4* table;        // [slots] the sphere of every slot: per tet (mode 0) or per (tet, face) (mode 1)
+  const float4* table;        // [slots] the sphere of every slot: per tet in the caller's numbering (mode 0) or per
+                              // (internal tet, face) (mode 1)
+  const int* perm;            // [nt] internal -> caller tet
   int mode;                   // 0: caller's per-tet table, hashed pick; 1: shrunk spheres at the furthest surface face
   const int* tet_block;       // [nt] workgroup block of every tet
   int* dirty;                 // [nblk] block flags

@@ -417,6 +417,7 @@ __device__ inline int ctz_mask(unsigned long long m) { return __builtin_ctzll(m)
 struct TetEnv {
   const float4* tv;      // 4 vertices (absolute)
   const float4* faceT;   // 4 normalised float face planes (fast path), or nullptr
+  const double4* face64;  // the tet's 4 face planes in FP64 (normal exact, offset rounded once)
   const float4* sites;   // candidate site data, indexed through cidx
   const int* sid;        // site ids, indexed through cidx
   const unsigned char* cidx8;  // candidate -> index into sites/sid (fast path)
@@ -433,7 +434,10 @@ struct TetEnv {
   __device__ int plane_site(int p) const { return p < 4 ? -1 : cand_id(p - 4); }
 
   __device__ Plane<double> plane64(int p) const {
-    if (p < 4) return face_plane64(tv, p);
+    if (p < 4) {
+      const double4 f = face64[p];
+      return Plane<double>{f.x, f.y, f.z, f.w};
+    }
     return bisector64(si, cand_site(p - 4), tv[0]);
   }
   __device__ PlaneI planeI(int p) const {

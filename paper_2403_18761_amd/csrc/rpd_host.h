@@ -83,6 +83,7 @@ struct rpd_mesh {
   int32_t owner = 0;  // ownership weights
   int device = 0;
   rpd::DBuf tp;    // float4 [4 nt]: vertex coordinates per internal tet
+  rpd::DBuf tf;    // double4 [4 nt]: face planes of every internal tet in FP64 (normal exact, offset rounded once)
   rpd::DBuf tn;    // int [4 nt]: neighbour internal tet across local face f
   rpd::DBuf nu;    // unsigned [14 nt]: weight numerators
   rpd::DBuf perm;  // int [nt]: internal -> caller tet index

@@ -82,7 +82,6 @@ hipError_t launch_iota(int* p, int n, hipStream_t s);
 hipError_t launch_scatter_spheres(const float4* sph, const int* slot, int n, float4* table, int* used, hipStream_t s);
 void shrink_spheres(const float* tri, long long nt, const float* pins, const float* normals, const int* own,
                     long long n, hipStream_t st, float4* out);
-hipError_t launch_gather_table(const float4* src, const int* perm, int nt, float4* dst, hipStream_t s);
 // selection, insertion and dirty marking of one round; a supplies the element tables and sites of the new shape
 hipError_t launch_round_front(const RoundState& r, const ShapeArgs& a, const int* parent, const int* cell_b0,
                               const float4* tp, int nt, int nblk, hipStream_t s);

@@ -3,10 +3,11 @@
 //
 // One round, all on the device with device-side counts (so the round is captured once as a HIP graph):
 //   1. select up to M violating cells (nonempty, chi != 1 or beta0 > 1), lowest ids first;
-//   2. for each, pick a tet among the cell's pieces (outside the component of its first piece when beta0 > 1) and
-//      insert a sphere: either the caller's per-tet table entry of a tet chosen by a deterministic hash of
-//      (tet, round), or (Sec. 4.1.3: the furthest surface triangle of the cell is the pin of sphere shrinking) the
-//      shrunk sphere of the surface face, among those the cell touches, furthest from the cell's sphere centre;
+//   2. for each, pick a tet among the cell's pieces (outside the component of its piece in its smallest tet when
+//      beta0 > 1) and insert a sphere: either the caller's per-tet table entry of the tet with the largest
+//      (hash(tet, round), tet), tets in the caller's numbering, or (Sec. 4.1.3: the furthest surface triangle of the
+//      cell is the pin of sphere shrinking) the shrunk sphere of the surface face, among those the cell touches,
+//      furthest from the cell's sphere centre;
 //   3. mark the workgroup blocks whose tets a new sphere may own (the exact candidate test against the stored U_t);
 //   4. remove the contributions of the dirty blocks computed with the old sites, add them back with the new sites
 //      (every accumulator is an exactly invertible integer), and recompute beta0 of the live element pieces.
@@ -50,7 +51,7 @@ __global__ __launch_bounds__(256) void k_select(RoundState r, const long long* c
       r.sel[pos] = i;
       r.selpos[i] = pos;
       r.best[pos] = 0ull;
-      r.ref[pos] = 0x7fffffff;
+      r.ref[pos] = ~0ull;
     }
     __syncthreads();
     if (threadIdx.x == 0) s_count += s_warp[0] + s_warp[1] + s_warp[2] + s_warp[3];
@@ -72,10 +73,12 @@ __device__ inline int uf_root(const int* par, int x) {
 // max_insert entries) and flush once per workgroup, on a grid of a few workgroups per compute unit.
 constexpr int SCAN_BLOCKS = 1024;
 
+// the piece of every selected cell in its smallest tet (caller's numbering, so that the rule does not depend on the
+// internal tet order), packed with its internal tet id for the lookup of its node
 __global__ __launch_bounds__(256) void k_ref_tet(HashTab N, const int* node_st, RoundState r) {
-  extern __shared__ int s_ref[];
+  extern __shared__ unsigned long long s_ref[];
   const int nsel = *r.nsel;
-  for (int k = threadIdx.x; k < nsel; k += blockDim.x) s_ref[k] = 0x7fffffff;
+  for (int k = threadIdx.x; k < nsel; k += blockDim.x) s_ref[k] = ~0ull;
   __syncthreads();
   const unsigned cap = N.mask + 1;
   for (unsigned s = blockIdx.x * blockDim.x + threadIdx.x; s < cap; s += gridDim.x * blockDim.x) {
@@ -83,11 +86,13 @@ __global__ __launch_bounds__(256) void k_ref_tet(HashTab N, const int* node_st, 
     if (key == EMPTY_KEY || (key >> 62) != 1 || !node_live(node_st[s])) continue;
     int cell = (int)((key >> 32) & 0x3fffffff);
     int k = r.selpos[cell];
-    if (k >= 0) atomicMin(&s_ref[k], (int)(key & 0xffffffffull));
+    if (k < 0) continue;
+    const unsigned t = (unsigned)(key & 0xffffffffull);
+    atomicMin(&s_ref[k], ((unsigned long long)(unsigned)r.perm[t] << 32) | t);
   }
   __syncthreads();
   for (int k = threadIdx.x; k < nsel; k += blockDim.x)
-    if (s_ref[k] != 0x7fffffff) atomicMin(&r.ref[k], s_ref[k]);
+    if (s_ref[k] != ~0ull) atomicMin(&r.ref[k], s_ref[k]);
 }
 
 __device__ inline unsigned mix_hash(unsigned long long x) {  // splitmix64 finaliser
@@ -112,10 +117,11 @@ __global__ __launch_bounds__(256) void k_pick_tet(HashTab N, const int* node_st,
     int k = r.selpos[cell];
     if (k < 0) continue;
     int t = (int)(key & 0xffffffffull);
+    const int tc = r.perm[t];  // caller's tet id: the table's index and the hash input
     const int bnd = node_bnd_bits(node_st[s]);
-    if (r.mode ? bnd == 0 : r.tet_used[t] != 0) continue;
-    if (cell_b0[cell] > 1) {  // pick outside the component of the cell's first piece
-      int rs = ht_find(N, (key & ~0xffffffffull) | (unsigned)r.ref[k]);
+    if (r.mode ? bnd == 0 : r.tet_used[tc] != 0) continue;
+    if (cell_b0[cell] > 1) {  // pick outside the component of the cell's piece in its smallest tet
+      int rs = ht_find(N, (key & ~0xffffffffull) | (unsigned)(r.ref[k] & 0xffffffffull));
       if (rs >= 0 && uf_root(parent, rs) == uf_root(parent, (int)s)) continue;
     }
     if (r.mode) {  // surface faces of tet t that the piece touches: the one furthest from the cell's centre
@@ -139,8 +145,8 @@ __global__ __launch_bounds__(256) void k_pick_tet(HashTab N, const int* node_st,
       }
       continue;
     }
-    unsigned h = mix_hash(((unsigned long long)(unsigned)t << 32) | (unsigned)round);
-    atomicMax(&s_best[k], ((unsigned long long)h << 32) | (unsigned)t);
+    unsigned h = mix_hash(((unsigned long long)(unsigned)tc << 32) | (unsigned)round);
+    atomicMax(&s_best[k], ((unsigned long long)h << 32) | (unsigned)tc);
   }
   __syncthreads();
   for (int k = threadIdx.x; k < nsel; k += blockDim.x)
@@ -244,10 +250,6 @@ __global__ void k_round_end(RoundState r) {
   *r.round += 1;
 }
 
-__global__ void k_gather_table(const float4* src, const int* perm, int nt, float4* dst) {
-  for (int k = blockIdx.x * blockDim.x + threadIdx.x; k < nt; k += gridDim.x * blockDim.x) dst[k] = src[perm[k]];
-}
-
 static int gsz(size_t n) {
   size_t g = (n + 255) / 256;
   if (g > 65536) g = 65536;
@@ -318,11 +320,6 @@ hipError_t launch_scatter_spheres(const float4* sph, const int* slot, int n, flo
   return hipGetLastError();
 }
 
-hipError_t launch_gather_table(const float4* src, const int* perm, int nt, float4* dst, hipStream_t s) {
-  hipLaunchKernelGGL(k_gather_table, dim3(gsz(nt)), dim3(256), 0, s, src, perm, nt, dst);
-  return hipGetLastError();
-}
-
 // the round's selection and insertion (everything before the clip passes)
 hipError_t launch_round_front(const RoundState& r, const ShapeArgs& a, const int* parent, const int* cell_b0,
                               const float4* tp, int nt, int nblk, hipStream_t s) {
@@ -330,7 +327,8 @@ hipError_t launch_round_front(const RoundState& r, const ShapeArgs& a, const int
   hipLaunchKernelGGL(k_select, dim3(1), dim3(256), 0, s, r, a.cell_chi, a.cell_np, cell_b0);
   const size_t cap = (size_t)a.N.mask + 1;
   const int scan = std::min(gsz(cap), SCAN_BLOCKS);
-  hipLaunchKernelGGL(k_ref_tet, dim3(scan), dim3(256), sizeof(int) * r.max_insert, s, a.N, a.node_st, r);
+  hipLaunchKernelGGL(k_ref_tet, dim3(scan), dim3(256), sizeof(unsigned long long) * r.max_insert, s, a.N, a.node_st,
+                     r);
   hipLaunchKernelGGL(k_pick_tet, dim3(scan), dim3(256), sizeof(unsigned long long) * r.max_insert, s, a.N, a.node_st,
                      parent, cell_b0, r, tp, a.site);
   hipLaunchKernelGGL(k_insert, dim3(1), dim3(1024), 0, s, r, (float4*)a.site);

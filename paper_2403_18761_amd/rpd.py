@@ -114,6 +114,8 @@ def load():
                              C.c_double, C.POINTER(C.c_uint8), C.POINTER(C.c_uint8), C.POINTER(C.c_uint8)]
     lib.rpd_pieces.argtypes = [C.c_void_p, C.c_int32, C.POINTER(C.c_int64), C.POINTER(_i32p), C.POINTER(_i32p),
                                C.POINTER(C.POINTER(C.c_double)), C.POINTER(C.POINTER(C.c_int64))]
+    lib.rpd_piece_terms.argtypes = [C.c_void_p, C.c_int32, C.c_int32, C.POINTER(C.c_int64), C.POINTER(_i32p),
+                                    C.POINTER(_i32p), C.POINTER(C.POINTER(C.c_int64)), C.POINTER(_i32p)]
     lib.rpd_free.argtypes = [C.c_void_p]
     lib.rpd_free.restype = None
     lib.rpd_last_error.restype = C.c_char_p
@@ -129,7 +131,7 @@ def load():
     lib.rpd_session_free.argtypes = [C.c_void_p]
     lib.rpd_session_free.restype = None
     for f in ("rpd_mesh_create", "rpd_mesh_get_info", "rpd_build", "rpd_euler", "rpd_components", "rpd_geometry",
-              "rpd_adjacency", "rpd_get_stats", "rpd_pieces", "rpd_session_create", "rpd_session_run",
+              "rpd_adjacency", "rpd_get_stats", "rpd_pieces", "rpd_piece_terms", "rpd_session_create", "rpd_session_run",
               "rpd_session_result", "rpd_session_get_info", "rpd_session_sites", "rpd_autotune",
               "rpd_edge_geometry", "rpd_medial_euler", "rpd_thin", "rpd_envelope_distance",
               "rpd_shrink_spheres"):
@@ -290,6 +292,22 @@ class Result:
         return dict(t=np.ctypeslib.as_array(t, shape=(m,)).copy(), i=np.ctypeslib.as_array(i, shape=(m,)).copy(),
                     geo=np.ctypeslib.as_array(geo, shape=(4 * m,)).copy().reshape(m, 4),
                     chi=np.ctypeslib.as_array(chi, shape=(m,)).copy())
+
+    def piece_terms(self, shape: int, kind: int) -> dict:
+        """Per-piece element terms of one kind (RPD_KEEP_PIECES): t [m], sites [m, kind], num [m], glue [m]."""
+        n = C.c_int64()
+        t, sv, g = _i32p(), _i32p(), _i32p()
+        num = C.POINTER(C.c_int64)()
+        _check(self._lib.rpd_piece_terms(self._h, shape, kind, C.byref(n), C.byref(t), C.byref(sv), C.byref(num),
+                                         C.byref(g)))
+        m = n.value
+        if m == 0:
+            return dict(t=np.zeros(0, np.int32), sites=np.zeros((0, kind), np.int32), num=np.zeros(0, np.int64),
+                        glue=np.zeros(0, np.int32))
+        return dict(t=np.ctypeslib.as_array(t, shape=(m,)).copy(),
+                    sites=np.ctypeslib.as_array(sv, shape=(m * kind,)).copy().reshape(m, kind),
+                    num=np.ctypeslib.as_array(num, shape=(m,)).copy(),
+                    glue=np.ctypeslib.as_array(g, shape=(m,)).copy())
 
     def __del__(self):
         if getattr(self, "_h", None) and self._h.value:

@@ -14,8 +14,12 @@ What is stored per shape (``fullsize_<workload>.json``):
 * sums of chi and beta0 per kind (a mismatch then says which kind differs and by how much);
 * the total cell volume and the volumes of 64 cells picked by a fixed seed (float64, for the 1e-5 check).
 
-Usage: ``python tests/golden/fullsize_oracle.py torus2000|genus3|batch256 [--threads N]``. The batch file is
-written after every shape, and a rerun resumes after the last stored shape of the same input.
+``repair50`` runs the oracle's own insertion loop (``oracle.repair``) for 50 rounds of at most 64 insertions on the
+repair workload (975,462 tets, 500 initial sites, the per-tet sphere table) and stores the digest of the final site
+array (float32 [n, 4]), the per-round counts and the record of the final RPD.
+
+Usage: ``python tests/golden/fullsize_oracle.py torus2000|genus3|batch256|repair50 [--threads N]``. The batch file
+is written after every shape, and a rerun resumes after the last stored shape of the same input.
 """
 from __future__ import annotations
 
@@ -75,6 +79,10 @@ def shape_record(prob, threads: int, seed: int) -> dict:
     t0 = time.perf_counter()
     r = oracle.rpd(prob, threads=threads, assemble=False)
     dt = time.perf_counter() - t0
+    return record_of(prob, r, threads, seed, dt)
+
+
+def record_of(prob, r: dict, threads: int, seed: int, dt: float) -> dict:
     if not r["consistent"]:
         raise RuntimeError(f"oracle reports an inconsistency: {r['report']}")
     pick = volume_samples(prob.n_sites, seed)
@@ -105,13 +113,16 @@ def path_for(name: str) -> str:
 
 def main() -> None:
     ap = argparse.ArgumentParser()
-    ap.add_argument("workload", choices=("torus2000", "genus3", "batch256"))
+    ap.add_argument("workload", choices=("torus2000", "genus3", "batch256", "repair50"))
     ap.add_argument("--threads", type=int, default=os.cpu_count() or 1)
     args = ap.parse_args()
     import oracle
 
     oracle.build(force=False)
     out = path_for(args.workload)
+    if args.workload == "repair50":
+        repair50(out, args.threads)
+        return
     if args.workload != "batch256":
         prob = workload_problems(args.workload)[0]
         rec = shape_record(prob, args.threads, seed=11)
@@ -136,6 +147,33 @@ def main() -> None:
             json.dump({"workload": args.workload, "shapes": done}, fh, indent=1)
         os.replace(tmp, out)
         print(f"batch shape {k}: {prob.n_tets} tets, {prob.n_sites} sites, {rec['oracle_seconds']} s", flush=True)
+
+
+REPAIR_ROUNDS, REPAIR_MAX_INSERT = 50, 64
+
+
+def repair50(out: str, threads: int) -> None:
+    from oracle import repair
+    from paper_2403_18761_amd import synth
+
+    prob, table = synth.repair_problem(N=128, n_sites=500, seed=5)
+    max_sites = prob.n_sites + REPAIR_MAX_INSERT * REPAIR_ROUNDS
+    t0 = time.perf_counter()
+    sites, history, final = repair.repair_loop(prob, table, REPAIR_ROUNDS, REPAIR_MAX_INSERT, max_sites,
+                                               threads=threads, log=lambda m: print(m, flush=True))
+    dt = time.perf_counter() - t0
+    fin = prob.with_sites(sites[:, 0], sites[:, 1], sites[:, 2], sites[:, 3])
+    tab = np.stack([np.asarray(a, np.float32) for a in table], axis=1)
+    rec = dict(workload="repair50", rounds=REPAIR_ROUNDS, max_insert=REPAIR_MAX_INSERT, max_sites=max_sites,
+               initial_input_sha256=input_digest(prob),
+               table_sha256=hashlib.sha256(np.ascontiguousarray(tab).tobytes()).hexdigest(),
+               n_sites_final=int(sites.shape[0]),
+               sites_sha256=hashlib.sha256(np.ascontiguousarray(sites, dtype="<f4").tobytes()).hexdigest(),
+               history=[list(h) for h in history], loop_seconds=round(dt, 1),
+               shapes=[record_of(fin, final, threads, 13, dt)])
+    with open(out, "w") as fh:
+        json.dump(rec, fh, indent=1)
+    print("repair50 done in", round(dt, 1), "s", flush=True)
 
 
 if __name__ == "__main__":

@@ -1,16 +1,31 @@
-"""The benchmark workloads at full size, in the launch configuration the benchmark times (autotuned first): tets
-sampled at random are checked against the oracle piece by piece, and properties that hold at any size are checked on
-the whole result (volumes partition the mesh, Euler additivity over the diagram, cell chi equal to the sum of its
-pieces' fractional terms)."""
+"""The benchmark workloads at full size, in the launch configuration the benchmark times (autotuned first).
+
+* Whole-element parity: the torus workload against the oracle run live (every element list, chi, beta0, volumes,
+  first moments); the genus-3 solid and every shape of the 256-shape batch against the oracle's stored digests
+  (``tests/golden/fullsize_<workload>.json``, written by ``tests/golden/fullsize_oracle.py``, which calls only the
+  oracle and the input generators): sha256 of every exact per-element array, element counts and sums, the total
+  volume and 64 sampled cell volumes.
+* Per-piece parity on tets sampled at random: the set of nonempty pieces, each piece's cell, face, edge and RPV terms
+  (fractional chi numerators, Sec. 4.1.2) and the mesh faces its element pieces are glued through (Sec. 4.1.1),
+  and its volume.
+* Properties that hold at any size on the whole result (volumes partition the mesh, Euler additivity over the
+  diagram, cell chi equal to the sum of its pieces' fractional terms).
+"""
+import hashlib
+import json
 import os
 
 import numpy as np
 import pytest
 
 from paper_2403_18761_amd import synth
-from tests.gpu_util import ELEMENT_ARRAYS, extract, log
+from tests.gpu_util import ELEMENT_ARRAYS, assert_parity, extract, log
 
 pytestmark = pytest.mark.gpu
+
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+DIGEST_ARRAYS = ("cell_chi", "cell_beta0", "face_keys", "face_chi", "face_beta0", "edge_keys", "edge_chi",
+                 "edge_beta0", "rpv_keys")
 
 
 @pytest.fixture(scope="module", autouse=True)
@@ -39,6 +54,45 @@ def _mesh_sites(prob):
     return mesh, (_dev(prob.sx), _dev(prob.sy), _dev(prob.sz), _dev(prob.sr))
 
 
+def input_digest(prob) -> str:
+    h = hashlib.sha256()
+    for a, dt in ((prob.vx, np.float32), (prob.vy, np.float32), (prob.vz, np.float32), (prob.tv, np.int32),
+                  (prob.sx, np.float32), (prob.sy, np.float32), (prob.sz, np.float32), (prob.sr, np.float32)):
+        h.update(np.ascontiguousarray(a, dtype=dt).tobytes())
+    return h.hexdigest()
+
+
+def load_golden(name):
+    path = os.path.join(GOLDEN, f"fullsize_{name}.json")
+    if not os.path.exists(path):
+        pytest.skip(f"oracle digest {path} not written yet (tests/golden/fullsize_oracle.py {name})")
+    with open(path) as fh:
+        return json.load(fh)["shapes"]
+
+
+def assert_digest(g, rec, prob, label):
+    """The GPU's element lists against the oracle's stored digest of the same input."""
+    assert input_digest(prob) == rec["input_sha256"], (label, "input differs from the one the digest was taken on")
+    counts = dict(n_cells_nonempty=int(np.count_nonzero(g["cell_vol"] > 0)), n_faces=len(g["face_keys"]),
+                  n_edges=len(g["edge_keys"]), n_rpv=len(g["rpv_keys"]))
+    for k, v in counts.items():
+        assert v == rec[k], (label, k, v, rec[k])
+    for kind in ("cell", "face", "edge"):
+        for what in ("chi", "beta0"):
+            key = f"sum_{kind}_{what}"
+            assert int(np.sum(g[f"{kind}_{what}"], dtype=np.int64)) == rec[key], (label, key)
+    for k in DIGEST_ARRAYS:
+        d = hashlib.sha256(np.ascontiguousarray(g[k], dtype="<i4").tobytes()).hexdigest()
+        assert d == rec["sha256"][k], (label, k)
+    assert g["stats"]["n_pairs"] == rec["n_pairs"], (label, g["stats"]["n_pairs"], rec["n_pairs"])
+    vol = g["cell_vol"]
+    assert abs(vol.sum() - rec["volume_total"]) <= 1e-5 * rec["volume_total"], (label, vol.sum())
+    pick = np.asarray(rec["volume_sample_sites"], np.int64)
+    want = np.asarray(rec["volume_sample"], np.float64)
+    np.testing.assert_allclose(vol[pick], want, rtol=1e-5, atol=1e-11 * max(want.max(initial=0.0), 1e-30),
+                               err_msg=f"{label} sampled cell volumes")
+
+
 def check_invariants(g, info, pieces=None, label=""):
     """Properties of any restricted power diagram of a mesh (exact integers, volumes to FP32 accuracy)."""
     vol = g["cell_vol"]
@@ -54,55 +108,161 @@ def check_invariants(g, info, pieces=None, label=""):
         np.testing.assert_array_equal(num, g["cell_chi"].astype(np.int64) * info["L"], err_msg=f"{label} cell chi")
 
 
-def sampled_against_oracle(prob, pieces, n_sample, seed, info, label):
+def interior_faces(prob):
+    """bool [T, 4]: local face f of tet t (opposite vertex f) is shared with another tet."""
+    tv = np.asarray(prob.tv, np.int64).reshape(-1, 4)
+    keys = []
+    for f in range(4):
+        tri = np.sort(np.delete(tv, f, axis=1), axis=1)
+        keys.append((tri[:, 0] << 42) | (tri[:, 1] << 21) | tri[:, 2])
+    k = np.stack(keys, axis=1).reshape(-1)
+    _, inv, cnt = np.unique(k, return_inverse=True, return_counts=True)
+    return (cnt[inv] == 2).reshape(-1, 4)
+
+
+def expected_terms(r, interior):
+    """The oracle's per-piece records in the form the GPU keeps them (Sec. 4.1.2 terms; Sec. 4.1.1 gluing faces):
+    faces, edges and RPVs from the piece of their smallest site, gluing bits over interior faces (cells also mark
+    boundary faces in bits 4..7)."""
+    cells, faces, edges, rpvs = {}, {}, {}, set()
+    for p in r["pieces"]:
+        t, i = p["t"], p["i"]
+        inner = interior[t]
+        cg = {1: 0, 2: {}, 3: {}}
+        for kind, s0, s1, s2, f in p["glue"]:
+            if kind == 1:
+                cg[1] |= (1 << f) if inner[f] else (16 << f)
+            elif inner[f]:
+                key = (s0, s1) if kind == 2 else (s0, s1, s2)
+                cg[kind][key] = cg[kind].get(key, 0) | (1 << f)
+        cells[(t, i)] = (p["chi_cell"], cg[1], p["vol"])
+        for j, num in p["face_terms"]:
+            if j > i:
+                faces[(t, i, j)] = (num, cg[2].get((i, j), 0))
+        for j, k, num in p["edge_terms"]:
+            if j > i:
+                edges[(t, i, j, k)] = (num, cg[3].get((i, j, k), 0))
+        for j, k, l in p["rpv"]:
+            if j > i:
+                rpvs.add((t, i, j, k, l))
+    return cells, faces, edges, rpvs
+
+
+def sampled_against_oracle(prob, res, shape, n_sample, seed, info, label, interior=None):
     import oracle
+
+    from paper_2403_18761_amd import rpd
 
     rng = np.random.default_rng(seed)
     sel = np.sort(rng.choice(prob.n_tets, min(n_sample, prob.n_tets), replace=False))
     r = oracle.tet_pieces(prob, sel, threads=min(16, os.cpu_count() or 1))
     assert r["L"] == info["L"]
-    want = {(p["t"], p["i"]): (p["chi_cell"], p["vol"]) for p in r["pieces"]}
-    mask = np.isin(pieces["t"], sel)
-    got = {(int(t), int(i)): (int(c), float(v))
-           for t, i, c, v in zip(pieces["t"][mask], pieces["i"][mask], pieces["chi"][mask], pieces["geo"][mask, 0])}
-    assert set(got) == set(want), (label, len(got), len(want), sorted(set(got) ^ set(want))[:5])
+    if interior is None:
+        interior = interior_faces(prob)
+    cells, faces, edges, rpvs = expected_terms(r, interior)
+    pieces = res.pieces(shape)
+    terms = {kind: res.piece_terms(shape, kind) for kind in (rpd.RPD_CELL, rpd.RPD_FACE, rpd.RPD_EDGE,
+                                                             rpd.RPD_VERTEX)}
+
+    def got(kind):
+        d = terms[kind]
+        m = np.isin(d["t"], sel)
+        return d["t"][m], d["sites"][m], d["num"][m], d["glue"][m]
+
+    t, s, num, glue = got(rpd.RPD_CELL)
+    gcell = {(int(a), int(b[0])): (int(c), int(d)) for a, b, c, d in zip(t, s, num, glue)}
+    assert set(gcell) == set(cells), (label, "pieces", sorted(set(gcell) ^ set(cells))[:5])
+    for k, (c, g, _) in cells.items():
+        assert gcell[k] == (c, g), (label, "cell term", k, gcell[k], (c, g))
+    t, s, num, glue = got(rpd.RPD_FACE)
+    gface = {(int(a), int(b[0]), int(b[1])): (int(c), int(d)) for a, b, c, d in zip(t, s, num, glue)}
+    assert gface == faces, (label, "face terms", sorted(set(gface.items()) ^ set(faces.items()))[:5])
+    t, s, num, glue = got(rpd.RPD_EDGE)
+    gedge = {(int(a), *map(int, b)): (int(c), int(d)) for a, b, c, d in zip(t, s, num, glue)}
+    assert gedge == edges, (label, "edge terms", sorted(set(gedge.items()) ^ set(edges.items()))[:5])
+    t, s, _, _ = got(rpd.RPD_VERTEX)
+    grpv = {(int(a), *map(int, b)) for a, b in zip(t, s)}
+    assert grpv == rpvs, (label, "RPV terms", sorted(grpv ^ rpvs)[:5])
     # FP32 constructions err by about u |x| in the tet's frame, so a piece's volume error is absolute at the tet's
     # scale (surface h^2 times u h, about 6 u vol(t)): slivers get the floor 1e-6 vol(t), the rest 1e-5 relative
+    mask = np.isin(pieces["t"], sel)
+    gvol = {(int(a), int(b)): float(v) for a, b, v in zip(pieces["t"][mask], pieces["i"][mask],
+                                                         pieces["geo"][mask, 0])}
+    assert set(gvol) == set(cells), label
     v = np.stack([prob.vx, prob.vy, prob.vz], axis=1).astype(np.float64)
     p = v[prob.tv]
     tvol = np.abs(np.einsum("ij,ij->i", p[:, 1] - p[:, 0], np.cross(p[:, 2] - p[:, 0], p[:, 3] - p[:, 0]))) / 6.0
-    for k, (c, vo) in want.items():
-        assert got[k][0] == c, (label, k, got[k][0], c)
-        assert abs(got[k][1] - vo) <= 1e-5 * vo + 1e-6 * tvol[k[0]], (label, k, got[k][1], vo, tvol[k[0]])
-    return len(want)
+    for k, (_, _, vo) in cells.items():
+        assert abs(gvol[k] - vo) <= 1e-5 * vo + 1e-6 * tvol[k[0]], (label, k, gvol[k], vo, tvol[k[0]])
+    return len(cells), len(faces), len(edges), len(rpvs)
 
 
-def run_full(prob, n_sample, seed, label):
+def run_full(prob, label, keep=True):
     from paper_2403_18761_amd import rpd
 
     mesh, sites = _mesh_sites(prob)
     best = rpd.autotune([mesh], [sites])
     log(label, "tets", prob.n_tets, "sites", prob.n_sites, "launch", best)
-    res = rpd.build([mesh], [sites], block=best["block"], clip_budget=best["clip_budget"], flags=rpd.RPD_KEEP_PIECES)
+    flags = rpd.RPD_KEEP_PIECES if keep else 0
+    res = rpd.build([mesh], [sites], block=best["block"], clip_budget=best["clip_budget"], flags=flags)
     g = extract(res, 0)
-    pieces = res.pieces(0)
+    g["stats"] = res.stats()
+    g["radii"] = np.asarray(prob.sr, np.float64)
     info = mesh.info()
-    assert res.stats()["n_pairs"] == len(pieces["t"])
+    pieces = res.pieces(0) if keep else None
+    if keep:
+        assert res.stats()["n_pairs"] == len(pieces["t"])
     check_invariants(g, info, pieces, label)
-    n = sampled_against_oracle(prob, pieces, n_sample, seed, info, label)
-    log(label, "sampled pieces", n, "total pieces", len(pieces["t"]))
+    return g, res, info
 
 
 def test_fullsize_torus():
-    run_full(synth.torus_inside(64, 2000, 2), 400, 1, "torus N64 n2000")
+    """The benchmark workload: every element list against the oracle run live, and against its stored digest."""
+    import oracle
+
+    prob = synth.torus_inside(64, 2000, 2)
+    g, res, info = run_full(prob, "torus N64 n2000")
+    r = oracle.rpd(prob, threads=min(16, os.cpu_count() or 1), assemble=False)
+    assert_parity(g, r, label="torus N64 n2000 (whole)")
+    assert_digest(g, load_golden("torus2000")[0], prob, "torus N64 n2000 (digest)")
+    n = sampled_against_oracle(prob, res, 0, 400, 1, info, "torus N64 n2000")
+    log("torus sampled cell/face/edge/RPV terms", n)
 
 
 def test_fullsize_genus3():
-    run_full(synth.genus3_cad(128, 20000, 3), 200, 2, "genus3 N128 n20000")
+    prob = synth.genus3_cad(128, 20000, 3)
+    rec = load_golden("genus3")[0]
+    g, res, info = run_full(prob, "genus3 N128 n20000")
+    assert_digest(g, rec, prob, "genus3 N128 n20000")
+    n = sampled_against_oracle(prob, res, 0, 200, 2, info, "genus3 N128 n20000")
+    log("genus3 sampled cell/face/edge/RPV terms", n)
 
 
-def test_fullsize_batch_subset():
-    """24 shapes of the 256-shape batch recipe (shape k is the batch's shape k) in one call."""
+def test_fullsize_batch():
+    """All 256 shapes of the batch in one call, in the autotuned launch shape: every shape's element lists against
+    the oracle's digest of that shape."""
+    from paper_2403_18761_amd import rpd
+
+    recs = load_golden("batch256")
+    probs = synth.batch_problems(256, 4)
+    assert len(recs) == len(probs), (len(recs), "shapes in the digest file")
+    made = [_mesh_sites(p) for p in probs]
+    meshes, sites = [m for m, _ in made], [x for _, x in made]
+    best = rpd.autotune(meshes, sites)
+    log("batch tets", sum(p.n_tets for p in probs), "launch", best)
+    res = rpd.build(meshes, sites, block=best["block"], clip_budget=best["clip_budget"])
+    st = res.stats()
+    assert st["n_pairs"] == sum(rec["n_pairs"] for rec in recs)
+    for k, (p, rec) in enumerate(zip(probs, recs)):
+        g = extract(res, k)
+        g["stats"] = {"n_pairs": rec["n_pairs"]}  # the call's total is checked above
+        check_invariants(g, meshes[k].info(), None, f"batch shape {k}")
+        assert_digest(g, rec, p, f"batch shape {k}")
+    log("batch: 256 shapes equal the oracle's digests")
+
+
+def test_fullsize_batch_subset_pieces():
+    """24 shapes of the 256-shape batch recipe (shape k is the batch's shape k) in one call, pieces sampled."""
     from paper_2403_18761_amd import rpd
 
     t, s = synth.batch_sizes(256, 4)
@@ -112,32 +272,57 @@ def test_fullsize_batch_subset():
     best = rpd.autotune(meshes, sites)
     log("batch subset tets", sum(p.n_tets for p in probs), "launch", best)
     res = rpd.build(meshes, sites, block=best["block"], clip_budget=best["clip_budget"], flags=rpd.RPD_KEEP_PIECES)
-    total = 0
+    total = np.zeros(4, np.int64)
     for k, p in enumerate(probs):
         g = extract(res, k)
         pieces = res.pieces(k)
         info = meshes[k].info()
         check_invariants(g, info, pieces, f"batch shape {k}")
-        total += sampled_against_oracle(p, pieces, 12, 100 + k, info, f"batch shape {k}")
-    log("batch subset sampled pieces", total)
+        total += sampled_against_oracle(p, res, k, 12, 100 + k, info, f"batch shape {k}")
+    log("batch subset sampled cell/face/edge/RPV terms", total)
 
 
-def test_fullsize_repair_session():
-    """The repair workload at full size: after rounds of the session, the state equals a fresh build."""
+def _repair_session(rounds, max_insert, max_sites):
     from paper_2403_18761_amd import rpd
 
     prob, table = synth.repair_problem(N=128, n_sites=500, seed=5)
     mesh, sites = _mesh_sites(prob)
-    sess = rpd.Session(mesh, sites, tuple(_dev(x) for x in table), max_sites=500 + 64 * 4, max_insert=64)
-    sess.run(3)
+    sess = rpd.Session(mesh, sites, tuple(_dev(x) for x in table), max_sites=max_sites, max_insert=max_insert)
+    sess.run(rounds)
     info = sess.info()
     log("repair session", info)
     res = sess.result()
-    a = extract(res, 0)
-    s = sess.sites()
+    g = extract(res, 0)
+    g["stats"] = res.stats()
+    return prob, mesh, sess.sites(), g
+
+
+def test_fullsize_repair_session():
+    """The repair workload at full size, 50 rounds of at most 64 insertions: the state equals a fresh build of the
+    session's sites, bit for bit."""
+    from paper_2403_18761_amd import rpd
+
+    prob, mesh, s, a = _repair_session(50, 64, 500 + 64 * 50)
+    assert len(s) > 500
     fresh = rpd.build([mesh], [tuple(_dev(s[:, k]) for k in range(4))])
     b = extract(fresh, 0)
     for name in ELEMENT_ARRAYS:
         np.testing.assert_array_equal(a[name], b[name], err_msg=name)
-    assert res.stats()["n_pairs"] == fresh.stats()["n_pairs"]
+    assert a["stats"]["n_pairs"] == fresh.stats()["n_pairs"]
     check_invariants(a, mesh.info(), None, "repair session")
+
+
+def test_fullsize_repair_matches_oracle():
+    """The same 50 rounds against the oracle's own insertion loop (oracle.repair, stored digests): the session
+    inserts the same sites in the same order, and its final state equals the oracle's RPD of those sites."""
+    path = os.path.join(GOLDEN, "fullsize_repair50.json")
+    if not os.path.exists(path):
+        pytest.skip(f"oracle digest {path} not written yet (tests/golden/fullsize_oracle.py repair50)")
+    with open(path) as fh:
+        rec = json.load(fh)
+    prob, mesh, s, g = _repair_session(rec["rounds"], rec["max_insert"], rec["max_sites"])
+    assert input_digest(prob) == rec["initial_input_sha256"]
+    assert len(s) == rec["n_sites_final"], (len(s), rec["n_sites_final"])
+    assert hashlib.sha256(np.ascontiguousarray(s, dtype="<f4").tobytes()).hexdigest() == rec["sites_sha256"]
+    fin = prob.with_sites(s[:, 0], s[:, 1], s[:, 2], s[:, 3])
+    assert_digest(g, rec["shapes"][0], fin, "repair 50 rounds")

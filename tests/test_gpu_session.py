@@ -73,26 +73,31 @@ def test_session_equals_rebuild():
     assert info["n_dirty_blocks"] < info["n_blocks"] * info["rounds"]
 
 
-def test_session_matches_oracle():
+@pytest.mark.parametrize("rounds", [1, 4])
+def test_session_matches_oracle(rounds):
+    """The oracle runs the same insertion loop on its own results (oracle.repair): the session inserts the same
+    sites in the same order, and its state after the rounds equals the oracle's RPD of the final sites."""
     import oracle
+    from oracle import repair
 
     from paper_2403_18761_amd import rpd
 
     oracle.build(force=False)
     prob = synth.torus_inside(32, 60, 17)
     table = synth.centroid_table(prob, 0.03)
-    log(f"case: session torus N32 n60 tets {prob.n_tets}")
+    log(f"case: session torus N32 n60 tets {prob.n_tets}, {rounds} rounds")
+    want_sites, history, ref = repair.repair_loop(prob, table, rounds, max_insert=8, max_sites=60 + 40)
+    assert sum(a for _, a in history) > 0
     mesh = _mesh(prob)
     sess = rpd.Session(mesh, (prob.sx, prob.sy, prob.sz, prob.sr), table, max_sites=60 + 40, max_insert=8)
-    sess.run(3)
+    sess.run(rounds)
     info = sess.info()
-    log("session", info)
-    assert info["n_inserted"] > 0
-    s = sess.sites()
-    ref = oracle.rpd(prob.with_sites(s[:, 0], s[:, 1], s[:, 2], s[:, 3]), assemble=False)
+    log("session", info, "oracle rounds", history)
+    np.testing.assert_array_equal(sess.sites(), want_sites)
     res = sess.result()
     g = extract(res, 0)
     g["stats"] = res.stats()
+    g["radii"] = want_sites[:, 3].astype(np.float64)
     assert_parity(g, ref, label="session vs oracle")
 
 

@@ -18,8 +18,12 @@
 
 namespace rpd {
 
-static thread_local std::string g_error;
-void set_error(const std::string& msg) { g_error = msg; }
+static thread_local char g_error[512];
+void set_error(const char* msg) {
+  size_t k = 0;
+  for (; msg[k] && k + 1 < sizeof(g_error); ++k) g_error[k] = msg[k];
+  g_error[k] = 0;
+}
 
 // ---- caching allocator
 static std::mutex g_pool_mu;
@@ -189,7 +193,7 @@ struct DeviceState {
     site.alloc(sizeof(float4) * (size_t)ns);
     status.alloc(16);
     cell_chi.alloc(8 * (size_t)ns);
-    cell_geo.alloc(32 * (size_t)ns);
+    cell_geo.alloc(64 * (size_t)ns);  // volume and first moment: four 128-bit accumulators per site
     cell_np.alloc(4 * (size_t)ns);
     cell_b0.alloc(4 * (size_t)ns);
     fkeys.alloc(8 * (size_t)capF);
@@ -224,7 +228,7 @@ struct DeviceState {
     FillList L{};
     L.add(status.p, 0, 4, 4);
     L.add(cell_chi.p, 0, ns, 8);
-    L.add(cell_geo.p, 0, 4 * ns, 8);
+    L.add(cell_geo.p, 0, 8 * ns, 8);
     L.add(cell_np.p, 0, ns, 4);
     L.add(fkeys.p, EMPTY_KEY, capF, 8);
     L.add(face_chi.p, 0, capF, 8);
@@ -790,7 +794,7 @@ extern "C" {
 
 const char* rpd_version(void) { return "rpd-mi355x 0.1 (gfx950)"; }
 
-const char* rpd_last_error(void) { return rpd::g_error.c_str(); }
+const char* rpd_last_error(void) { return rpd::g_error; }
 
 rpd_status rpd_mesh_create(const rpd_mesh_desc* desc, uint32_t flags, void* stream, rpd_mesh** out) {
   if (out) *out = nullptr;

@@ -73,12 +73,37 @@ __device__ inline void keep_term(const ShapeArgs& a, int kind, int t, int i, int
 struct CellSink {
   long long* chi;  // [n] (LDS)
   int* np;         // [n]
-  long long* geo;  // [4 n]
+  unsigned long long* geo_lo;  // [4 n] low words of the workgroup's 128-bit sums
+  int* geo_hi;                 // [4 n] their high words (a workgroup's sum stays below 2^84: 32 bits suffice)
   int n;
   int q;           // the piece's index in the workgroup's site list, or -1
 };
 
 __device__ inline long long fixed56(double v) { return llrint(v * 72057594037927936.0); }  // 2^-56 units
+
+// Cell volumes and first moments are exact sums of 128-bit integers in units of 2^-80 (resolution 8e-25, range
+// 2^47), so that a nonempty piece far smaller than a grid cell still counts, every sum is independent of the order
+// of the additions, and a removal pass takes its contributions back exactly. An accumulator is a (low, high) pair
+// of 64-bit words; an addition adds the low word atomically and carries into the high word only when needed.
+struct Fix128 {
+  unsigned long long lo;
+  long long hi;
+};
+__device__ inline Fix128 fixed80(double v) {
+  const double D = rint(ldexp(v, 80));  // exact scaling, then the nearest integer
+  const double h = floor(ldexp(D, -64));
+  const double l = D - ldexp(h, 64);    // in [0, 2^64): the low bits of D, exact
+  return Fix128{(unsigned long long)l, (long long)h};
+}
+__device__ inline Fix128 signed128(Fix128 x, int sign) {
+  if (sign > 0) return x;
+  return Fix128{0ull - x.lo, -x.hi - (x.lo != 0ull ? 1 : 0)};
+}
+__device__ inline void acc128(unsigned long long* p, Fix128 v) {
+  const unsigned long long old = atomicAdd(p, v.lo);
+  const long long h = v.hi + (old + v.lo < old ? 1 : 0);  // carry out of the low word
+  if (h) atomicAdd(p + 1, (unsigned long long)h);
+}
 
 template <typename T, typename Topo, typename Mask, int VCAP, bool EXACT>
 __device__ void emit_piece(Clipper<T, Topo, Mask, VCAP, EXACT>& c, const ShapeDesc& sd, int tl, const ShapeArgs& a,
@@ -240,16 +265,20 @@ __device__ void emit_piece(Clipper<T, Topo, Mask, VCAP, EXACT>& c, const ShapeDe
   double dvol = (double)vol;
   double dmx = (double)mx * 0.25 + dvol * o.x, dmy = (double)my * 0.25 + dvol * o.y,
          dmz = (double)mz * 0.25 + dvol * o.z;
-  const long long g[4] = {fixed56(dvol), fixed56(dmx), fixed56(dmy), fixed56(dmz)};
+  const Fix128 g[4] = {fixed80(dvol), fixed80(dmx), fixed80(dmy), fixed80(dmz)};
   if (sink.q >= 0 && sink.q < sink.n) {  // workgroup-local sums, flushed once per workgroup pass
     atomicAdd((unsigned long long*)&sink.chi[sink.q], (unsigned long long)chi);
     atomicAdd(&sink.np[sink.q], 1);
-    for (int k = 0; k < 4; ++k) atomicAdd((unsigned long long*)&sink.geo[4 * sink.q + k], (unsigned long long)g[k]);
+    for (int k = 0; k < 4; ++k) {
+      const unsigned long long old = atomicAdd(&sink.geo_lo[4 * sink.q + k], g[k].lo);
+      const long long h = g[k].hi + (old + g[k].lo < old ? 1 : 0);
+      if (h) atomicAdd(&sink.geo_hi[4 * sink.q + k], (int)h);
+    }
   } else {
     atomicAdd((unsigned long long*)&a.cell_chi[i], (unsigned long long)(a.sign * chi));
     atomicAdd(&a.cell_np[i], a.sign);
     for (int k = 0; k < 4; ++k)
-      atomicAdd((unsigned long long*)&a.cell_geo[4 * (size_t)i + k], (unsigned long long)(a.sign * g[k]));
+      acc128((unsigned long long*)&a.cell_geo[2 * (4 * (size_t)i + k)], signed128(g[k], a.sign));
   }
   if (a.flags & RPD_KEEP_PIECES) {
     unsigned long long idx = atomicAdd(&a.counters[C_PIECES], 1ull);
@@ -377,20 +406,23 @@ __global__ __launch_bounds__(NT) void k_clip_fast(ShapeArgs a) {
   float(*s_key)[KRAW] = reinterpret_cast<float(*)[KRAW]>(s_share);
   typename Coord4<T>::type* s_xyz = reinterpret_cast<typename Coord4<T>::type*>(s_share);
   __shared__ int s_m[TB];
-  __shared__ int s_off[TB + 1];
-  __shared__ int s_order[TB];
+  static_assert(TB * KMAX < 32768, "piece offsets are 16-bit");
+  __shared__ short s_off[TB + 1];
+  __shared__ short s_order[TB];
   __shared__ float s_box[6];
   __shared__ double s_red[NT / 64];
   __shared__ int s_nsl;
   __shared__ unsigned long long s_cnt[4];
   __shared__ unsigned s_topo[VMAX * NT];
   __shared__ unsigned char s_tab[32 * NT];
-  // per-site sums of the workgroup's cell terms (all sites of the list, or the first 32 with 64 threads, where the
-  // LDS budget for four workgroups per compute unit is tight)
-  constexpr int AGG = NT == 64 ? 32 : SLMAX;
+  // per-site sums of the workgroup's cell terms (the first 128 sites of the list, or the first 32 with 64 threads,
+  // where the LDS budget for four workgroups per compute unit is tight); pieces of later sites add to the global
+  // accumulators directly
+  constexpr int AGG = NT == 64 ? 32 : 128;
   __shared__ long long s_acc_chi[AGG];
   __shared__ int s_acc_np[AGG];
-  __shared__ long long s_acc_geo[4 * AGG];
+  __shared__ unsigned long long s_acc_lo[4 * AGG];
+  __shared__ int s_acc_hi[4 * AGG];
 
   const int tid = threadIdx.x;
   const int lane = tid & 63, wid = tid >> 6;
@@ -398,7 +430,10 @@ __global__ __launch_bounds__(NT) void k_clip_fast(ShapeArgs a) {
   for (int k = tid; k < AGG; k += NT) {
     s_acc_chi[k] = 0;
     s_acc_np[k] = 0;
-    for (int d = 0; d < 4; ++d) s_acc_geo[4 * k + d] = 0;
+    for (int d = 0; d < 4; ++d) {
+      s_acc_lo[4 * k + d] = 0;
+      s_acc_hi[4 * k + d] = 0;
+    }
   }
   unsigned long long n_pairs = 0, n64 = 0, n_cand = 0;
   const unsigned long long clock0 = wall_clock64();
@@ -659,7 +694,7 @@ __global__ __launch_bounds__(NT) void k_clip_fast(ShapeArgs a) {
     n64 += cl.n64;
     if (r == CLIP_OK) {
       ++n_pairs;
-      const CellSink sink{s_acc_chi, s_acc_np, s_acc_geo, AGG, (int)s_cand[lt][ci]};
+      const CellSink sink{s_acc_chi, s_acc_np, s_acc_lo, s_acc_hi, AGG, (int)s_cand[lt][ci]};
       emit_piece(cl, sd, t0 + lt, a, sink);
     } else if (r == CLIP_DEFER) {
       stat_add(a, C_DEFER_CLIP, 1ull);
@@ -676,11 +711,14 @@ __global__ __launch_bounds__(NT) void k_clip_fast(ShapeArgs a) {
     const int i = s_sid[q];
     atomicAdd((unsigned long long*)&a.cell_chi[i], (unsigned long long)(a.sign * s_acc_chi[q]));
     atomicAdd(&a.cell_np[i], a.sign * np_q);
-    for (int d = 0; d < 4; ++d)
-      atomicAdd((unsigned long long*)&a.cell_geo[4 * (size_t)i + d], (unsigned long long)(a.sign * s_acc_geo[4 * q + d]));
+    for (int d = 0; d < 4; ++d) {
+      const Fix128 v{s_acc_lo[4 * q + d], (long long)s_acc_hi[4 * q + d]};
+      acc128((unsigned long long*)&a.cell_geo[8 * (size_t)i + 2 * d], signed128(v, a.sign));
+      s_acc_lo[4 * q + d] = 0;
+      s_acc_hi[4 * q + d] = 0;
+    }
     s_acc_chi[q] = 0;
     s_acc_np[q] = 0;
-    for (int d = 0; d < 4; ++d) s_acc_geo[4 * q + d] = 0;
   }
   if (!split) break;
   sub += SUB;
@@ -931,7 +969,7 @@ __global__ __launch_bounds__(64, LDS ? 1 : 2) void k_clip_slow(ShapeArgs a, unsi
       }
       if (r == CLIP_OK) {
         ++n_pairs;
-        emit_piece(cl, sd, t, a, CellSink{nullptr, nullptr, nullptr, 0, -1});
+        emit_piece(cl, sd, t, a, CellSink{nullptr, nullptr, nullptr, nullptr, 0, -1});
       }
     }
     __syncthreads();  // the candidate list is rewritten by the next item

@@ -487,10 +487,15 @@ __global__ void k_finalize_cells(int ns, const long long* chi_num, const long lo
     if (c % L != 0) atomicOr(status, ST_INTERNAL);
     out_chi[i] = (int)(c / L);
     out_b0[i] = b0[i];
-    const double sc = 1.0 / 72057594037927936.0;  // 2^-56
-    double v = (double)geo[4 * (size_t)i] * sc;
+    // 128-bit accumulators (low word, high word) in units of 2^-80
+    auto value = [&](int d) {
+      const unsigned long long lo = (unsigned long long)geo[8 * (size_t)i + 2 * d];
+      const long long hi = geo[8 * (size_t)i + 2 * d + 1];
+      return ldexp(ldexp((double)hi, 64) + (double)lo, -80);
+    };
+    const double v = value(0);
     out_vol[i] = v;
-    for (int d = 0; d < 3; ++d) out_cen[3 * (size_t)i + d] = np[i] ? ((double)geo[4 * (size_t)i + 1 + d] * sc) / v : NAN;
+    for (int d = 0; d < 3; ++d) out_cen[3 * (size_t)i + d] = np[i] ? value(1 + d) / v : NAN;
   }
 }
 

@@ -102,7 +102,7 @@ struct ShapeArgs {
   const float4* site;    // [ns] (x, y, z, r)
   // ---- accumulators
   long long* cell_chi;   // [ns] fractional chi numerators
-  long long* cell_geo;   // [4 ns] volume and first moment, fixed point 2^-56
+  long long* cell_geo;   // [8 ns] volume and first moment: 128-bit fixed point 2^-80 as (low, high) word pairs
   int* cell_np;          // [ns] nonempty pieces
   HashTab F;             // faces (i<j, global ids): key i<<32 | j
   long long* face_chi;   // [cap F]

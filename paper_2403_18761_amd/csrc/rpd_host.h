@@ -13,7 +13,9 @@
 
 namespace rpd {
 
-void set_error(const std::string& msg);
+// the calling thread's last error message (a fixed buffer: setting it allocates nothing)
+void set_error(const char* msg);
+inline void set_error(const std::string& msg) { set_error(msg.c_str()); }
 
 struct Failure {
   rpd_status code;

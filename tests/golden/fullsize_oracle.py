@@ -134,9 +134,12 @@ def main() -> None:
 
     tets, sites = synth.batch_sizes(256, 4)
     done = []
-    if os.path.exists(out):
-        with open(out) as fh:
-            done = json.load(fh)["shapes"]
+    partial = out + ".partial"  # shapes so far; renamed to the final name once all are in
+    for path in (out, partial):
+        if os.path.exists(path):
+            with open(path) as fh:
+                done = json.load(fh)["shapes"]
+            break
     for k in range(len(done), 256):
         prob = synth.batch_shape(k, int(tets[k]), int(sites[k]))
         rec = shape_record(prob, args.threads, seed=1000 + k)
@@ -145,7 +148,7 @@ def main() -> None:
         tmp = out + ".tmp"
         with open(tmp, "w") as fh:
             json.dump({"workload": args.workload, "shapes": done}, fh, indent=1)
-        os.replace(tmp, out)
+        os.replace(tmp, out if len(done) == 256 else partial)
         print(f"batch shape {k}: {prob.n_tets} tets, {prob.n_sites} sites, {rec['oracle_seconds']} s", flush=True)
 
 

@@ -89,8 +89,21 @@ def assert_digest(g, rec, prob, label):
     assert abs(vol.sum() - rec["volume_total"]) <= 1e-5 * rec["volume_total"], (label, vol.sum())
     pick = np.asarray(rec["volume_sample_sites"], np.int64)
     want = np.asarray(rec["volume_sample"], np.float64)
-    np.testing.assert_allclose(vol[pick], want, rtol=1e-5, atol=1e-11 * max(want.max(initial=0.0), 1e-30),
-                               err_msg=f"{label} sampled cell volumes")
+    # FP32 vertices err by about u |x| in their tet's frame, so a piece's volume error is absolute at the scale of
+    # its tet (about 6 u vol(t), the per-piece bound 1e-6 vol(t) of the sampled piece checks); a cell far smaller
+    # than its tets (a sliver or a cut-off corner) is held to that floor, larger cells to 1e-5 relative
+    atol = 1e-6 * max_tet_volume(prob)
+    np.testing.assert_allclose(vol[pick], want, rtol=1e-5, atol=atol, err_msg=f"{label} sampled cell volumes")
+
+
+def tet_volumes(prob):
+    v = np.stack([prob.vx, prob.vy, prob.vz], axis=1).astype(np.float64)
+    p = v[prob.tv]
+    return np.abs(np.einsum("ij,ij->i", p[:, 1] - p[:, 0], np.cross(p[:, 2] - p[:, 0], p[:, 3] - p[:, 0]))) / 6.0
+
+
+def max_tet_volume(prob):
+    return float(tet_volumes(prob).max())
 
 
 def check_invariants(g, info, pieces=None, label=""):
@@ -189,9 +202,7 @@ def sampled_against_oracle(prob, res, shape, n_sample, seed, info, label, interi
     gvol = {(int(a), int(b)): float(v) for a, b, v in zip(pieces["t"][mask], pieces["i"][mask],
                                                          pieces["geo"][mask, 0])}
     assert set(gvol) == set(cells), label
-    v = np.stack([prob.vx, prob.vy, prob.vz], axis=1).astype(np.float64)
-    p = v[prob.tv]
-    tvol = np.abs(np.einsum("ij,ij->i", p[:, 1] - p[:, 0], np.cross(p[:, 2] - p[:, 0], p[:, 3] - p[:, 0]))) / 6.0
+    tvol = tet_volumes(prob)
     for k, (_, _, vo) in cells.items():
         assert abs(gvol[k] - vo) <= 1e-5 * vo + 1e-6 * tvol[k[0]], (label, k, gvol[k], vo, tvol[k[0]])
     return len(cells), len(faces), len(edges), len(rpvs)
@@ -245,20 +256,22 @@ def test_fullsize_batch():
 
     recs = load_golden("batch256")
     probs = synth.batch_problems(256, 4)
-    assert len(recs) == len(probs), (len(recs), "shapes in the digest file")
+    complete = len(recs) == len(probs)  # the digest file is written shape by shape
     made = [_mesh_sites(p) for p in probs]
     meshes, sites = [m for m, _ in made], [x for _, x in made]
     best = rpd.autotune(meshes, sites)
     log("batch tets", sum(p.n_tets for p in probs), "launch", best)
     res = rpd.build(meshes, sites, block=best["block"], clip_budget=best["clip_budget"])
     st = res.stats()
-    assert st["n_pairs"] == sum(rec["n_pairs"] for rec in recs)
+    if complete:
+        assert st["n_pairs"] == sum(rec["n_pairs"] for rec in recs)
     for k, (p, rec) in enumerate(zip(probs, recs)):
         g = extract(res, k)
         g["stats"] = {"n_pairs": rec["n_pairs"]}  # the call's total is checked above
         check_invariants(g, meshes[k].info(), None, f"batch shape {k}")
         assert_digest(g, rec, p, f"batch shape {k}")
-    log("batch: 256 shapes equal the oracle's digests")
+    log(f"batch: {len(recs)} of {len(probs)} shapes equal the oracle's digests")
+    assert complete, f"the oracle digest holds {len(recs)} of {len(probs)} shapes"
 
 
 def test_fullsize_batch_subset_pieces():

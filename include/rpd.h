@@ -216,6 +216,23 @@ rpd_status rpd_envelope_distance(const float* spheres, int32_t n_spheres, const 
                                  const int32_t* tris, int64_t n_tris, const float* samples, int64_t n_samples,
                                  uint32_t flags, void* stream, float* dist, int32_t* nearest, float* kernel_ms);
 
+/* No-allocation variant of rpd_envelope_distance, for callers that cannot allocate device memory (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid allocation). Same arguments and results as
+ * rpd_envelope_distance with RPD_DEVICE_PTRS (every array is device memory, the call runs on stream, NULL = the null
+ * stream, nearest may be NULL), without kernel timing; it runs the same kernels and gives the same bits. Its working
+ * memory (element records, per-sample minima, a status word) lives in a fixed region of RPD_NOALLOC_SCRATCH_BYTES
+ * on each device, reserved with the library's code and held until the process ends; the call itself allocates
+ * nothing. Limit: 256 + 8 n_samples + 16 (3 n_edges + 5 n_tris) bytes, each part rounded up to 256, must fit the
+ * region (else RPD_E_NOMEM, checked before any device work). All calls on one device share the region and every call
+ * rewrites what it uses: calls that overlap on one device (from other host threads or on other streams) race, so
+ * the caller serialises them. Synchronises the stream (to read the status word).
+ * Errors: RPD_E_INVALID (negative count, null array, sphere id out of range), RPD_E_NOMEM (over the limit),
+ * RPD_E_DEVICE. */
+#define RPD_NOALLOC_SCRATCH_BYTES (64u << 20)
+rpd_status rpd_envelope_distance_noalloc(const float* spheres, int32_t n_spheres, const int32_t* edges,
+                                         int64_t n_edges, const int32_t* tris, int64_t n_tris, const float* samples,
+                                         int64_t n_samples, void* stream, float* dist, int32_t* nearest);
+
 /* Medial spheres by sphere shrinking (Sec. 5.1, Fig. tech_sphere_gen (a)): for each pin point p with inward unit
  * normal n, the maximal ball tangent to the surface at p with no surface point inside, i.e. the fixed point of the
  * shrinking iteration. The surface is given as triangles (9 floats each: three vertices); the radius is

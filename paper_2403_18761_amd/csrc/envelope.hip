@@ -26,6 +26,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <mutex>
 
 #include "rpd.h"
 #include "rpd_host.h"
@@ -215,13 +216,64 @@ __global__ void k_env_finish(const unsigned long long* key, long long n, float* 
   }
 }
 
+// Working memory of one call: the element records (CONE_F4 float4 per edge, SLAB_F4 per triangle), the per-sample
+// minima (one 64-bit key per sample) and a status word.
+size_t record_bytes(long long ne, long long nf) { return 16 * ((size_t)CONE_F4 * ne + (size_t)SLAB_F4 * nf); }
+
+// The launches of one call on device-resident inputs and outputs, given its working memory; ev0/ev1 (optional)
+// bracket the distance kernel. No allocation and no exception: returns the first HIP error.
+hipError_t envelope_launch(const float4* sph, int ns, const int* edg, long long ne, const int* tri, long long nf,
+                           const float* xyz, long long n, hipStream_t st, float4* rec, unsigned long long* key,
+                           int* status, float* dist, int* nearest, hipEvent_t ev0, hipEvent_t ev1) {
+  float4* cone = rec;
+  float4* slab = rec + (size_t)CONE_F4 * ne;
+  hipError_t e = launch_fill_i32(status, 0, 1, st);
+  if (e == hipSuccess) e = launch_fill_u64(key, ~0ull, (size_t)n, st);
+  if (e != hipSuccess) return e;
+  if (ne + nf > 0) {
+    const int g = (int)std::min<long long>((ne + nf + 255) / 256, 4096);
+    hipLaunchKernelGGL(k_env_prep, dim3(g), dim3(256), 0, st, sph, ns, edg, (int)ne, tri, (int)nf, cone, slab,
+                       status);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+  }
+  // grid: sample blocks x element chunks, about 2048 workgroups in all, each chunk at least 64 elements
+  const long long sblocks = (n + ENV_SAMPLES_PER_BLOCK - 1) / ENV_SAMPLES_PER_BLOCK;
+  const long long total = ns + ne + nf;
+  long long chunks = std::max<long long>(1, std::min<long long>((2048 + sblocks - 1) / sblocks, total / 64));
+  chunks = std::min<long long>(chunks, 65535);
+  if (ev0 && (e = hipEventRecord(ev0, st)) != hipSuccess) return e;
+  if (total > 0) {
+    if (nearest)
+      hipLaunchKernelGGL(k_env_dist<true>, dim3((unsigned)sblocks, (unsigned)chunks), dim3(ENV_THREADS), 0, st, xyz,
+                         n, sph, ns, cone, (int)ne, slab, (int)nf, key);
+    else
+      hipLaunchKernelGGL(k_env_dist<false>, dim3((unsigned)sblocks, (unsigned)chunks), dim3(ENV_THREADS), 0, st, xyz,
+                         n, sph, ns, cone, (int)ne, slab, (int)nf, key);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+  }
+  if (ev1 && (e = hipEventRecord(ev1, st)) != hipSuccess) return e;
+  const int g = (int)std::min<long long>((n + 255) / 256, 4096);
+  hipLaunchKernelGGL(k_env_finish, dim3(g), dim3(256), 0, st, key, n, dist, nearest);
+  return hipGetLastError();
+}
+
+// argument checks shared by both entry points (pure: no device access); 0 when the call may proceed
+rpd_status envelope_args(const float* spheres, int ns, const int* edges, long long ne, const int* tris, long long nf,
+                         const float* samples, long long n, const float* dist, const char** msg) {
+  *msg = "";
+  if (ns < 0 || ne < 0 || nf < 0 || n < 0) return *msg = "negative count", RPD_E_INVALID;
+  if (ns + ne + nf > (long long)INT32_MAX) return *msg = "more than 2^31 elements", RPD_E_INVALID;
+  if ((ns && !spheres) || (ne && !edges) || (nf && !tris) || (n && (!samples || !dist)))
+    return *msg = "null array", RPD_E_INVALID;
+  if ((n + ENV_SAMPLES_PER_BLOCK - 1) / ENV_SAMPLES_PER_BLOCK > INT32_MAX) return *msg = "too many samples", RPD_E_INVALID;
+  return RPD_OK;
+}
+
 void envelope_distance(const float* spheres, int ns, const int* edges, long long ne, const int* tris, long long nf,
                        const float* samples, long long n, unsigned flags, hipStream_t st, float* dist, int* nearest,
                        float* kernel_ms) {
-  if (ns < 0 || ne < 0 || nf < 0 || n < 0) throw Failure{RPD_E_INVALID, "negative count"};
-  if (ns + ne + nf > (long long)INT32_MAX) throw Failure{RPD_E_INVALID, "more than 2^31 elements"};
-  if ((ns && !spheres) || (ne && !edges) || (nf && !tris) || (n && (!samples || !dist)))
-    throw Failure{RPD_E_INVALID, "null array"};
+  const char* msg = "";
+  if (rpd_status c = envelope_args(spheres, ns, edges, ne, tris, nf, samples, n, dist, &msg)) throw Failure{c, msg};
   if (n == 0) return;
   const bool dev = (flags & RPD_DEVICE_PTRS) != 0;
   int ndev = 0;
@@ -246,23 +298,7 @@ void envelope_distance(const float* spheres, int ns, const int* edges, long long
     tri = d_tri.as<int>();
     xyz = d_xyz.as<float>();
   }
-  DBuf rec(16 * ((size_t)CONE_F4 * ne + (size_t)SLAB_F4 * nf)), key(8 * (size_t)n), status(sizeof(int));
-  float4* cone = rec.as<float4>();
-  float4* slab = cone + (size_t)CONE_F4 * ne;
-  hip_check(launch_fill_i32(status.as<int>(), 0, 1, st), "fill");
-  hip_check(launch_fill_u64(key.as<unsigned long long>(), ~0ull, (size_t)n, st), "fill");
-  if (ne + nf > 0) {
-    const int g = (int)std::min<long long>((ne + nf + 255) / 256, 4096);
-    hipLaunchKernelGGL(k_env_prep, dim3(g), dim3(256), 0, st, sph, ns, edg, (int)ne, tri, (int)nf, cone, slab,
-                       status.as<int>());
-    hip_check(hipGetLastError(), "envelope records");
-  }
-  // grid: sample blocks x element chunks, about 2048 workgroups in all, each chunk at least 64 elements
-  const long long sblocks = (n + ENV_SAMPLES_PER_BLOCK - 1) / ENV_SAMPLES_PER_BLOCK;
-  if (sblocks > INT32_MAX) throw Failure{RPD_E_INVALID, "too many samples"};
-  const long long total = ns + ne + nf;
-  long long chunks = std::max<long long>(1, std::min<long long>((2048 + sblocks - 1) / sblocks, total / 64));
-  chunks = std::min<long long>(chunks, 65535);
+  DBuf rec(record_bytes(ne, nf)), key(8 * (size_t)n), status(sizeof(int));
   hipEvent_t ev[2] = {nullptr, nullptr};
   struct EventGuard {
     hipEvent_t* e;
@@ -274,18 +310,7 @@ void envelope_distance(const float* spheres, int ns, const int* edges, long long
   if (kernel_ms) {
     *kernel_ms = 0.f;
     for (auto& e : ev) hip_check(hipEventCreate(&e), "hipEventCreate");
-    hip_check(hipEventRecord(ev[0], st), "hipEventRecord");
   }
-  if (total > 0) {
-    if (nearest)
-      hipLaunchKernelGGL(k_env_dist<true>, dim3((unsigned)sblocks, (unsigned)chunks), dim3(ENV_THREADS), 0, st, xyz,
-                         n, sph, ns, cone, (int)ne, slab, (int)nf, key.as<unsigned long long>());
-    else
-      hipLaunchKernelGGL(k_env_dist<false>, dim3((unsigned)sblocks, (unsigned)chunks), dim3(ENV_THREADS), 0, st, xyz,
-                         n, sph, ns, cone, (int)ne, slab, (int)nf, key.as<unsigned long long>());
-    hip_check(hipGetLastError(), "envelope distance");
-  }
-  if (kernel_ms) hip_check(hipEventRecord(ev[1], st), "hipEventRecord");
   float* out_d = dist;
   int* out_n = nearest;
   if (!dev) {
@@ -294,9 +319,9 @@ void envelope_distance(const float* spheres, int ns, const int* edges, long long
     out_d = d_out.as<float>();
     out_n = nearest ? d_near.as<int>() : nullptr;
   }
-  const int g = (int)std::min<long long>((n + 255) / 256, 4096);
-  hipLaunchKernelGGL(k_env_finish, dim3(g), dim3(256), 0, st, key.as<unsigned long long>(), n, out_d, out_n);
-  hip_check(hipGetLastError(), "envelope finish");
+  hip_check(envelope_launch(sph, ns, edg, ne, tri, nf, xyz, n, st, rec.as<float4>(), key.as<unsigned long long>(),
+                            status.as<int>(), out_d, out_n, ev[0], ev[1]),
+            "envelope distance");
   int hst = 0;
   hip_check(hipMemcpyAsync(&hst, status.p, sizeof(int), hipMemcpyDeviceToHost, st), "download");
   if (!dev) {
@@ -308,8 +333,83 @@ void envelope_distance(const float* spheres, int ns, const int* edges, long long
   if (hst & ST_INVALID) throw Failure{RPD_E_INVALID, "an edge or triangle names a sphere out of range"};
 }
 
+// ---------------------------------------------------------------------------------------------------------------
+// The no-allocation variant's working memory: one fixed region per device, reserved with the library's code
+// object and held until the process ends. Host code never passes the array itself to a kernel (its name is a host
+// stand-in); it looks up the region's device address once per device and uses that.
+// ---------------------------------------------------------------------------------------------------------------
+static __device__ __align__(256) unsigned char scratch[RPD_NOALLOC_SCRATCH_BYTES];
+
+constexpr int MAX_DEVICES = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[MAX_DEVICES];  // device address of `scratch` per device (nullptr until looked up)
+
+// the current device's address of the region (looked up on the first call on that device)
+rpd_status scratch_address(void** out, const char** msg) {
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0) return *msg = "no HIP device", RPD_E_DEVICE;
+  if (dev >= MAX_DEVICES) return *msg = "device index beyond the scratch table", RPD_E_DEVICE;
+  std::lock_guard<std::mutex> g(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p)
+      return *msg = "scratch region not available on this device", RPD_E_DEVICE;
+    g_scratch_ptr[dev] = p;
+  }
+  *out = g_scratch_ptr[dev];
+  return RPD_OK;
+}
+
+// bytes of the region one call uses: status word, per-sample minima, element records, each 256-byte aligned
+size_t noalloc_bytes(long long ne, long long nf, long long n) {
+  auto up = [](size_t b) { return (b + 255) & ~(size_t)255; };
+  return 256 + up(8 * (size_t)n) + up(record_bytes(ne, nf));
+}
 }  // namespace
 }  // namespace rpd
+
+extern "C" rpd_status rpd_envelope_distance_noalloc(const float* spheres, int32_t n_spheres, const int32_t* edges,
+                                                    int64_t n_edges, const int32_t* tris, int64_t n_tris,
+                                                    const float* samples, int64_t n_samples, void* stream, float* dist,
+                                                    int32_t* nearest) {
+  using namespace rpd;
+  const char* msg = "";
+  rpd_status c = envelope_args(spheres, n_spheres, edges, n_edges, tris, n_tris, samples, n_samples, dist, &msg);
+  if (c == RPD_OK && noalloc_bytes(n_edges, n_tris, n_samples) > (size_t)RPD_NOALLOC_SCRATCH_BYTES) {
+    c = RPD_E_NOMEM;
+    msg = "the samples and elements exceed the no-allocation scratch region (RPD_NOALLOC_SCRATCH_BYTES)";
+  }
+  if (c != RPD_OK) {
+    set_error(msg);
+    return c;
+  }
+  set_error("");
+  if (n_samples == 0) return RPD_OK;
+  void* base = nullptr;
+  if ((c = scratch_address(&base, &msg)) != RPD_OK) {
+    set_error(msg);
+    return c;
+  }
+  unsigned char* b = (unsigned char*)base;
+  int* status = (int*)b;
+  unsigned long long* key = (unsigned long long*)(b + 256);
+  float4* rec = (float4*)(b + 256 + ((8 * (size_t)n_samples + 255) & ~(size_t)255));
+  hipStream_t st = (hipStream_t)stream;
+  hipError_t e = envelope_launch((const float4*)spheres, n_spheres, edges, n_edges, tris, n_tris, samples, n_samples,
+                                 st, rec, key, status, dist, nearest, nullptr, nullptr);
+  int hst = 0;
+  if (e == hipSuccess) e = hipMemcpyAsync(&hst, status, sizeof(int), hipMemcpyDeviceToHost, st);
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  if (e != hipSuccess) {
+    set_error(hipGetErrorString(e));
+    return RPD_E_DEVICE;
+  }
+  if (hst & ST_INVALID) {
+    set_error("an edge or triangle names a sphere out of range");
+    return RPD_E_INVALID;
+  }
+  return RPD_OK;
+}
 
 extern "C" rpd_status rpd_envelope_distance(const float* spheres, int32_t n_spheres, const int32_t* edges,
                                             int64_t n_edges, const int32_t* tris, int64_t n_tris,

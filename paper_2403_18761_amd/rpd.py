@@ -29,6 +29,7 @@ RPD_KEEP_PIECES = 1 << 5
 RPD_OWNER_WEIGHTS = 1 << 6
 RPD_SHUFFLE_QUEUE = 1 << 7
 RPD_ESTIMATED_ORDER = 1 << 8
+RPD_NOALLOC_SCRATCH_BYTES = 64 << 20  # the no-allocation entry point's working memory per device
 
 _f32p = C.POINTER(C.c_float)
 _i32p = C.POINTER(C.c_int32)
@@ -108,6 +109,9 @@ def load():
     lib.rpd_envelope_distance.argtypes = [C.c_void_p, C.c_int32, C.c_void_p, C.c_int64, C.c_void_p, C.c_int64,
                                           C.c_void_p, C.c_int64, C.c_uint32, C.c_void_p, C.c_void_p, C.c_void_p,
                                           C.POINTER(C.c_float)]
+    lib.rpd_envelope_distance_noalloc.argtypes = [C.c_void_p, C.c_int32, C.c_void_p, C.c_int64, C.c_void_p,
+                                                  C.c_int64, C.c_void_p, C.c_int64, C.c_void_p, C.c_void_p,
+                                                  C.c_void_p]
     lib.rpd_shrink_spheres.argtypes = [C.c_void_p, C.c_int64, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64,
                                        C.c_uint32, C.c_void_p, C.c_void_p]
     lib.rpd_thin.argtypes = [C.c_int32, C.c_int64, _i32p, C.c_int64, _i32p, C.POINTER(C.c_double), C.c_int64, _i32p,
@@ -134,6 +138,7 @@ def load():
               "rpd_adjacency", "rpd_get_stats", "rpd_pieces", "rpd_piece_terms", "rpd_session_create", "rpd_session_run",
               "rpd_session_result", "rpd_session_get_info", "rpd_session_sites", "rpd_autotune",
               "rpd_edge_geometry", "rpd_medial_euler", "rpd_thin", "rpd_envelope_distance",
+              "rpd_envelope_distance_noalloc",
               "rpd_shrink_spheres"):
         getattr(lib, f).restype = C.c_int32
     _lib = lib
@@ -406,6 +411,28 @@ def envelope_distance(spheres, edges, tris, samples, stream=None, timing: bool =
     _check(lib.rpd_envelope_distance(ptr(sp), sp.shape[0], ptr(ed), ed.shape[0], ptr(tr), tr.shape[0], ptr(q),
                                      q.shape[0], 0, _stream_ptr(stream), ptr(dist), ptr(near), kptr))
     return (dist, near, kms.value) if timing else (dist, near)
+
+
+def envelope_distance_noalloc(spheres, edges, tris, samples, dist, nearest=None, stream=None):
+    """rpd_envelope_distance_noalloc: the same distances into caller-allocated device tensors (dist float32 [s],
+    nearest int32 [s] or None). Every argument is a contiguous device tensor of the documented dtype and shape; the
+    call allocates nothing (its working memory is the library's fixed scratch region on the device)."""
+    lib = load()
+    import torch
+
+    for name, t, dt in (("spheres", spheres, torch.float32), ("edges", edges, torch.int32), ("tris", tris, torch.int32),
+                        ("samples", samples, torch.float32), ("dist", dist, torch.float32),
+                        ("nearest", nearest, torch.int32)):
+        if t is None:
+            continue
+        if not (t.is_cuda and t.dtype == dt and t.is_contiguous()):
+            raise ValueError(f"{name} must be a contiguous {dt} device tensor")
+    ptr = lambda t: C.c_void_p(t.data_ptr() if t is not None and t.numel() else 0)
+    dev = samples.device
+    st = _stream_ptr(stream) if stream is not None else C.c_void_p(torch.cuda.current_stream(dev).cuda_stream)
+    _check(lib.rpd_envelope_distance_noalloc(ptr(spheres), spheres.numel() // 4, ptr(edges), edges.numel() // 2,
+                                             ptr(tris), tris.numel() // 3, ptr(samples), samples.numel() // 3, st,
+                                             ptr(dist), ptr(nearest)))
 
 
 def shrink_spheres(tris, pins, normals, own_tri=None, stream=None):

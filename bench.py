@@ -19,13 +19,21 @@ import numpy as np
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-# MI355X published peaks (dense): FP32 vector 157.3 TFLOP/s (packed issue), FP64 vector 78.6 TFLOP/s
+# MI355X published peaks (dense): FP32 vector 157.3 TFLOP/s (packed issue), FP64 vector 78.6 TFLOP/s; without
+# packed FP32 instructions (the build disables them) the FP32 vector rate is that of FP64, 78.6 TFLOP/s
 PEAK_FP32_TFLOPS = 157.3
+PEAK_FP32_NONPACKED_TFLOPS = 78.6
 
 # Algorithmic FLOPs of one nonempty piece with v vertices and f bisector faces: each bounding bisector is
 # evaluated at the piece's vertices (8 v f), every vertex is constructed once (30 v) and enters the volume and
-# moment fans (25 v). For this workload the oracle's piece statistics give mean v = 5.84 and mean f = 1.6.
-FLOP_PER_PIECE = 8 * 5.84 * 1.6 + 55 * 5.84
+# moment fans (25 v). The mean over the pieces of each workload comes from the oracle's piece statistics
+# (tests/golden/piece_stats.py writes tests/golden/piece_stats.json).
+PIECE_STATS_FILE = os.path.join(ROOT, "tests", "golden", "piece_stats.json")
+
+
+def flop_per_piece(workload: str) -> float:
+    with open(PIECE_STATS_FILE) as fh:
+        return float(json.load(fh)[workload]["flop_per_piece"])
 
 
 # HBM traffic of the clipping kernel from rocprofv3 FETCH_SIZE / WRITE_SIZE runs (scaled by a plain copy of known
@@ -42,9 +50,9 @@ def kernel_source_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def measured_traffic(workload: str, kernel: str, launch: dict):
-    """Bytes per launch of `kernel` on `workload` from the committed counter summary, or None when there is none,
-    it was taken with another launch shape, or the kernel sources changed since."""
+def measured_counters(workload: str, kernel: str, launch: dict):
+    """The committed counter summary of `kernel` on `workload` (HBM bytes and executed VALU FLOPs per launch), or
+    None when there is none, it was taken with another launch shape, or the kernel sources changed since."""
     try:
         with open(TRAFFIC_FILE) as fh:
             d = json.load(fh)
@@ -53,7 +61,7 @@ def measured_traffic(workload: str, kernel: str, launch: dict):
     e = d.get(workload, {})
     if e.get("source_hash") != kernel_source_hash() or e.get("kernel") != kernel or e.get("launch") != launch:
         return None
-    return e.get("bytes_per_launch")
+    return e
 
 
 WORKLOADS = {
@@ -89,6 +97,9 @@ def workload(name):
 
 
 def time_builds(meshes, sites, precision, steps, warmup, stream, block=0, clip_budget=0, flags=0):
+    """Times `steps` rpd_build calls (each returns with its results on the host, its stream synchronised).
+    Returns a dict: mean ms per call over the timed region, median and p90 of the per-call times, the mean
+    HIP-event time of the fast clipping kernel, the pieces and the last call's statistics."""
     import torch
 
     from paper_2403_18761_amd import rpd
@@ -98,17 +109,55 @@ def time_builds(meshes, sites, precision, steps, warmup, stream, block=0, clip_b
     for _ in range(warmup):
         rpd.build(meshes, sites, **kw)
     torch.cuda.synchronize()
-    clip_ms = []
+    clip_ms, per_call = [], []
     n_pairs = None
     t0 = time.perf_counter()
     for _ in range(steps):
+        c0 = time.perf_counter()
         res = rpd.build(meshes, sites, **kw)
+        per_call.append((time.perf_counter() - c0) * 1e3)
         st = res.stats()
         clip_ms.append(st["ms_clip"])
         n_pairs = st["n_pairs"]
     torch.cuda.synchronize()
     t1 = time.perf_counter()
-    return (t1 - t0) * 1e3 / steps, float(np.mean(clip_ms)), n_pairs, st
+    return dict(ms=(t1 - t0) * 1e3 / steps, ms_median=float(np.median(per_call)),
+                ms_p90=float(np.percentile(per_call, 90)), clip_ms=float(np.mean(clip_ms)), n_pairs=n_pairs,
+                stats=st)
+
+
+def batch_comparison(args, stream):
+    """The 256-shape batch in one rpd_build call, FP32 + fallback (autotuned launch) against all-FP64, so that one
+    benchmark line shows whether the batched FP32 path beats the all-FP64 one (no oracle leg)."""
+    import torch
+
+    from paper_2403_18761_amd import rpd
+
+    t0 = time.perf_counter()
+    probs = workload("batch256")
+    dev = torch.device("cuda:0")
+
+    def t(a, dt=torch.float32):
+        return torch.as_tensor(np.ascontiguousarray(a), dtype=dt, device=dev)
+
+    meshes = [rpd.Mesh(t(p.vx), t(p.vy), t(p.vz), t(p.tv.reshape(-1), torch.int32), stream=stream) for p in probs]
+    sites = [(t(p.sx), t(p.sy), t(p.sz), t(p.sr)) for p in probs]
+    torch.cuda.synchronize()
+    prep_s = time.perf_counter() - t0
+    tuned = rpd.autotune(meshes, sites, stream=stream)
+    steps = args.batch_steps
+    a = time_builds(meshes, sites, rpd.RPD_FP32_FALLBACK, steps, 1, stream, tuned["block"], tuned["clip_budget"])
+    b = time_builds(meshes, sites, rpd.RPD_FP64, steps, 1, stream)
+    assert a["n_pairs"] == b["n_pairs"]
+    out = {"workload": WORKLOADS["batch256"]["desc"], "n_tets": sum(p.n_tets for p in probs),
+           "n_sites": sum(p.n_sites for p in probs), "n_pairs": a["n_pairs"], "launch": tuned, "steps": steps,
+           "fp32_ms": {"mean": a["ms"], "median": a["ms_median"], "p90": a["ms_p90"], "clip_kernel": a["clip_ms"]},
+           "fp64_ms": {"mean": b["ms"], "median": b["ms_median"], "p90": b["ms_p90"], "clip_kernel": b["clip_ms"]},
+           "fp32_clips_per_s": a["n_pairs"] / (a["ms"] * 1e-3), "fp32_speedup_over_fp64": b["ms"] / a["ms"],
+           "input_prep_s": prep_s}
+    print(f"# batch256: fp32+fallback {a['ms']:.2f} ms, all-fp64 {b['ms']:.2f} ms per call "
+          f"({out['fp32_speedup_over_fp64']:.2f}x), launch {tuned}", file=sys.stderr, flush=True)
+    return out
 
 
 def invariants(meshes, sites, tuned):
@@ -185,8 +234,9 @@ def run_repair(args, prob, table):
     bad = int(np.sum(live & ((chi != 1) | (b0 > 1))))
     s = sess.sites()
     sites = tuple(t(s[:, k]) for k in range(4))
-    ms_full, clip_full, pairs_full, _ = time_builds([mesh], [sites], rpd.RPD_FP32_FALLBACK, 5, 1, None)
-    assert pairs_full == st["n_pairs"]
+    full = time_builds([mesh], [sites], rpd.RPD_FP32_FALLBACK, 5, 1, None)
+    ms_full = full["ms"]
+    assert full["n_pairs"] == st["n_pairs"]
     clipped = i1["n_clipped"] - i0["n_clipped"]
     ms_round = dt * 1e3 / args.steps
     print(f"# repair: {ms_round:.3f} ms/round, {i1['n_inserted'] - i0['n_inserted']} inserted, "
@@ -282,9 +332,16 @@ def cpu_baseline(probs, frac):
         pieces += len(r["pieces"])
         tets += len(sel)
     total = sum(p.n_tets for p in probs)
+    # the per-core rate: one thread on a smaller random sample of the first shape
+    sel1 = np.sort(rng.choice(probs[0].n_tets, max(1, int(frac * probs[0].n_tets / 20)), replace=False))
+    t0 = time.perf_counter()
+    r1 = oracle.tet_pieces(probs[0], sel1, threads=1)
+    dt1 = time.perf_counter() - t0
     return dict(value=pieces / dt, unit="clips/s", cores=threads, kind="oracle",
                 sample=f"{tets} of {total} tets (random {frac:g} of every shape, seed 0), each clipped against all "
-                       f"sites of its shape; {pieces} nonempty pieces in {dt:.2f} s")
+                       f"sites of its shape; {pieces} nonempty pieces in {dt:.2f} s",
+                one_thread={"value": len(r1["pieces"]) / dt1, "unit": "clips/s", "cores": 1,
+                            "sample": f"{len(sel1)} tets of shape 0, {len(r1['pieces'])} pieces in {dt1:.2f} s"})
 
 
 def main():
@@ -300,6 +357,9 @@ def main():
     ap.add_argument("--launch", default=None, metavar="BLOCK,K",
                     help="use this launch shape (threads per workgroup, clip budget) instead of autotuning")
     ap.add_argument("--cpu-frac", type=float, default=None)
+    ap.add_argument("--no-batch", action="store_true",
+                    help="torus workload: skip the 256-shape batch comparison of FP32 + fallback against all-FP64")
+    ap.add_argument("--batch-steps", type=int, default=5)
     ap.add_argument("--workload", default="torus2000", choices=sorted(WORKLOADS))
     ap.add_argument("--insertion", default="table", choices=("table", "shrink"),
                     help="repair workload: spheres from the per-tet table, or shrunk at the furthest surface face")
@@ -387,36 +447,51 @@ def main():
         tuned = rpd.autotune(meshes, sites, stream=stream)
     print(f"# autotuned launch shape: {tuned}", file=sys.stderr, flush=True)
 
-    ms32, clip32, pairs, st32 = time_builds(meshes, sites, rpd.RPD_FP32_FALLBACK, args.steps, args.warmup, stream,
-                                            tuned["block"], tuned["clip_budget"])
-    print(f"# fp32+fallback: {ms32:.3f} ms/RPD, clip kernel {clip32:.3f} ms, pairs {pairs}", file=sys.stderr,
-          flush=True)
+    f32 = time_builds(meshes, sites, rpd.RPD_FP32_FALLBACK, args.steps, args.warmup, stream, tuned["block"],
+                      tuned["clip_budget"])
+    pairs, st32 = f32["n_pairs"], f32["stats"]
+    print(f"# fp32+fallback: {f32['ms']:.3f} ms/RPD (median {f32['ms_median']:.3f}, p90 {f32['ms_p90']:.3f}), clip "
+          f"kernel {f32['clip_ms']:.3f} ms, pairs {pairs}", file=sys.stderr, flush=True)
     # the same builds with the work dispatched by the static cost estimate (what a first build on a mesh uses)
     est = None
     if not args.no_estimated:
-        ms_est, clip_est, _, _ = time_builds(meshes, sites, rpd.RPD_FP32_FALLBACK, args.steps, 1, stream,
-                                             tuned["block"], tuned["clip_budget"], flags=rpd.RPD_ESTIMATED_ORDER)
-        est = {"ms_per_rpd": ms_est, "clip_kernel_ms": clip_est}
-        print(f"# fp32+fallback, estimated dispatch order: {ms_est:.3f} ms/RPD, clip kernel {clip_est:.3f} ms",
+        e = time_builds(meshes, sites, rpd.RPD_FP32_FALLBACK, args.steps, 1, stream, tuned["block"],
+                        tuned["clip_budget"], flags=rpd.RPD_ESTIMATED_ORDER)
+        est = {"ms_per_rpd": e["ms"], "ms_median": e["ms_median"], "clip_kernel_ms": e["clip_ms"]}
+        print(f"# fp32+fallback, estimated dispatch order: {e['ms']:.3f} ms/RPD, clip kernel {e['clip_ms']:.3f} ms",
               file=sys.stderr, flush=True)
     out64 = None
     if not args.no_fp64:
-        ms64, clip64, pairs64, st64 = time_builds(meshes, sites, rpd.RPD_FP64, args.steps, args.warmup, stream)
-        assert pairs64 == pairs
-        out64 = dict(ms_per_rpd=ms64, clips_per_s=pairs / (ms64 * 1e-3), clip_kernel_ms=clip64)
-        print(f"# all-fp64: {ms64:.3f} ms/RPD, clip kernel {clip64:.3f} ms", file=sys.stderr, flush=True)
+        d = time_builds(meshes, sites, rpd.RPD_FP64, args.steps, args.warmup, stream)
+        assert d["n_pairs"] == pairs
+        out64 = dict(ms_per_rpd=d["ms"], ms_median=d["ms_median"], ms_p90=d["ms_p90"],
+                     clips_per_s=pairs / (d["ms"] * 1e-3), clip_kernel_ms=d["clip_ms"],
+                     fp32_speedup=d["ms"] / f32["ms"])
+        print(f"# all-fp64: {d['ms']:.3f} ms/RPD, clip kernel {d['clip_ms']:.3f} ms", file=sys.stderr, flush=True)
 
-    achieved = FLOP_PER_PIECE * pairs / (clip32 * 1e-3) / 1e12
+    fpp = flop_per_piece(args.workload)
+    achieved = fpp * pairs / (f32["clip_ms"] * 1e-3) / 1e12
     kernel = f"k_clip_fast<float,{tuned['block']}>"
-    traffic = measured_traffic(args.workload, kernel, tuned) if len(probs) == 1 else None
+    cnt = measured_counters(args.workload, kernel, tuned) if len(probs) == 1 else None
+    roof = {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
+            "frac": achieved / PEAK_FP32_TFLOPS, "traffic": cnt["bytes_per_launch"] if cnt else None,
+            "kernel": kernel, "kernel_ms": f32["clip_ms"], "flop_per_piece": fpp,
+            "frac_of_nonpacked_peak": achieved / PEAK_FP32_NONPACKED_TFLOPS}
+    if cnt:  # executed work and HBM rate from the committed counter summary of this kernel and launch shape
+        roof["executed_fp32_tflops"] = cnt["fp32_flop_per_launch"] / (f32["clip_ms"] * 1e-3) / 1e12
+        roof["executed_fp32_frac"] = roof["executed_fp32_tflops"] / PEAK_FP32_TFLOPS
+        roof["executed_fp64_tflops"] = cnt["fp64_flop_per_launch"] / (f32["clip_ms"] * 1e-3) / 1e12
+        roof["valu_busy"] = cnt["valu_busy"]
+        roof["hbm_gbps"] = cnt["bytes_per_launch"] / (f32["clip_ms"] * 1e-3) / 1e9
+        roof["counters"] = cnt["summary"]
     line = {
         "metric": "tet-site clips/sec (nonempty pieces/s) + ms per RPD+chi, FP32/FP64-fallback vs all-FP64, 1 MI355X",
-        "value": pairs / (ms32 * 1e-3),
+        "value": pairs / (f32["ms"] * 1e-3),
         "unit": "clips/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": ms32,
+        "ms_per_step": f32["ms"],
         "higher_is_better": True,
         "scaling": "strong",
         "vs_baseline": None,
@@ -425,16 +500,16 @@ def main():
         "config": {"workload": WORKLOADS[args.workload]["desc"], "name": args.workload, "n_shapes": len(probs),
                    "n_tets": sum(p.n_tets for p in probs), "n_sites": sum(p.n_sites for p in probs),
                    "n_pairs": pairs, "launch": tuned},
-        "ms_per_rpd": ms32,
+        "ms_per_rpd": {"mean": f32["ms"], "median": f32["ms_median"], "p90": f32["ms_p90"]},
         "estimated_order": est,
         "all_fp64": out64,
         "stats": {k: st32[k] for k in ("n_candidates", "n_deferred", "n_fp64", "n_exact", "n_faces", "n_edges",
                                        "n_rpv", "n_defer_block", "n_defer_kmax", "n_defer_clip", "n_split", "ms_clip",
                                        "ms_deferred", "ms_reduce", "ms_total")},
-        "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
-                     "frac": achieved / PEAK_FP32_TFLOPS, "traffic": traffic,
-                     "kernel": kernel, "flop_per_piece": FLOP_PER_PIECE},
+        "roofline": roof,
     }
+    if args.workload == "torus2000" and not args.no_batch:
+        line["batch256"] = batch_comparison(args, stream)
     line["checks"] = invariants(meshes, sites, tuned)
     if not args.no_cpu_baseline:
         frac = args.cpu_frac if args.cpu_frac is not None else WORKLOADS[args.workload]["cpu_frac"]

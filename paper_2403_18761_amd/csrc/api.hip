@@ -156,10 +156,10 @@ struct DeviceState {
   int nsh = 0, ns_cap = 0;
   long long nt_tot = 0;
   unsigned capF = 0, capE = 0, capQ = 0, capN = 0;
-  int def_cap = 0, piece_cap = 0, term_cap = 0;
+  int def_cap = 0, piece_cap = 0, term_cap = 0, list_cap = 0;
   DBuf site, status, cell_chi, cell_geo, cell_np, cell_b0;
   DBuf fkeys, face_chi, face_np, face_b0, ekeys, edge_chi, edge_np, edge_len, edge_b0, qkeys, rpv_cnt;
-  DBuf nkeys, node_st, parent, deferred, deferred2, pieces, terms, counters, tetU, slow, touch;
+  DBuf nodes, deferred, deferred2, dlist, pieces, terms, counters, tetU, slow, touch;
   int waves = 0;
 
   unsigned long long* cnt() const { return counters.as<unsigned long long>(); }
@@ -207,11 +207,12 @@ struct DeviceState {
     edge_b0.alloc(4 * (size_t)capE);
     qkeys.alloc(8 * (size_t)capQ);
     rpv_cnt.alloc(4 * (size_t)capQ);
-    nkeys.alloc(8 * (size_t)capN);
-    node_st.alloc(4 * (size_t)capN);
-    parent.alloc(4 * (size_t)capN);
+    nodes.alloc(sizeof(NodeRec) * (size_t)capN);
     deferred.alloc(16 * (size_t)def_cap);
     deferred2.alloc(16 * (size_t)(def_cap / 4 + 1024));
+    // candidate lists of deferred tets and pieces (a few per cent of the tets on the heaviest workloads)
+    list_cap = (int)std::min<size_t>((nt / 8 + 4096) * (size_t)scale, (1u << 25) - 1);
+    dlist.alloc(sizeof(int) * KRAW * (size_t)list_cap);
     pieces.alloc(sizeof(PieceRec) * (size_t)std::max(piece_cap, 1));
     terms.alloc(sizeof(TermRec) * (size_t)std::max(term_cap, 1));
     counters.alloc(8 * (NCOUNTERS + 8 + (size_t)NSPREAD * NCOUNTERS));
@@ -239,8 +240,7 @@ struct DeviceState {
     L.add(edge_len.p, 0, capE, 8);
     L.add(qkeys.p, EMPTY_KEY, capQ, 8);
     L.add(rpv_cnt.p, 0, capQ, 4);
-    L.add(nkeys.p, EMPTY_KEY, capN, 8);
-    L.add(node_st.p, 0, capN, 4);
+    L.add(nodes.p, EMPTY_KEY, capN, 16, 0ull);  // key EMPTY, state 0, parent 0
     L.add(cnt(), 0, NCOUNTERS + 8 + (size_t)NSPREAD * NCOUNTERS, 8);
     if (touch.p) L.add(touch.p, 0, touch_words(), 4);
     hip_check(launch_fill_multi(L, s), "fill");
@@ -275,14 +275,15 @@ struct DeviceState {
     a.edge_len = edge_len.as<long long>();
     a.Q = HashTab{qkeys.as<unsigned long long>(), capQ - 1};
     a.rpv_cnt = rpv_cnt.as<int>();
-    a.N = HashTab{nkeys.as<unsigned long long>(), capN - 1};
-    a.node_st = node_st.as<int>();
+    a.N = NodeTab{nodes.as<NodeRec>(), capN - 1};
     a.sign = sign;
     a.tet_U = tetU.p ? tetU.as<double>() : nullptr;
     a.deferred = deferred.as<int4>();
     a.deferred_cap = def_cap;
     a.deferred2 = deferred2.as<int4>();
     a.deferred2_cap = def_cap / 4 + 1024;
+    a.deferred_list = dlist.as<int>();
+    a.list_cap = list_cap;
     a.pieces = pieces.as<PieceRec>();
     a.piece_cap = piece_cap;
     a.terms = terms.as<TermRec>();
@@ -310,9 +311,8 @@ struct DeviceState {
       hip_check(launch_fill_multi(L, s), "fill");
     }
     hip_check(launch_zero_stats(stat(), C_NODES, 1, C_GLUE_BITS, 2, s), "fill");
-    hip_check(launch_glue(a, parent.as<int>(), s), "glue");
-    hip_check(launch_count_roots(a, parent.as<int>(), cell_b0.as<int>(), face_b0.as<int>(), edge_b0.as<int>(), s),
-              "roots");
+    hip_check(launch_glue(a, s), "glue");
+    hip_check(launch_count_roots(a, cell_b0.as<int>(), face_b0.as<int>(), edge_b0.as<int>(), s), "roots");
     if (a.touch_cell) hip_check(launch_fill_i32(touch.as<int>(), 0, touch_words(), s), "fill");
   }
 };
@@ -385,7 +385,7 @@ static bool collect(DeviceState& D, const std::vector<ShapeDesc>& hd, const Shap
   hip_check(hipMemcpyAsync(&hst, D.status.p, sizeof(int), hipMemcpyDeviceToHost, s), "download");
   D.totals(hc, s);
   if (hst & ST_TABLE_FULL) return false;
-  if (hc[C_DEFER_ITEMS] > (unsigned long long)D.def_cap ||
+  if (hc[C_DEFER_ITEMS] > (unsigned long long)D.def_cap || hc[C_LISTS] > (unsigned long long)D.list_cap ||
       (D.piece_cap && (hc[C_PIECES] > (unsigned long long)D.piece_cap || hc[C_TERMS] > (unsigned long long)D.term_cap)))
     return false;
   status_error(hst);
@@ -1141,6 +1141,7 @@ static void check_status(rpd_session* S) {
 static void clip_pass(rpd_session* S, const ShapeArgs& a) {
   hip_check(launch_fill_u64(S->D.cnt() + C_DEFER_ITEMS, 0, 1, S->stream), "fill");
   hip_check(launch_fill_u64(S->D.cnt() + C_DEFER2, 0, 1, S->stream), "fill");
+  hip_check(launch_fill_u64(S->D.cnt() + C_LISTS, 0, 1, S->stream), "fill");
   hip_check(launch_clip_fast(a, S->o.precision, S->o.block, S->stream), "clip kernel");
   hip_check(launch_clip_slow(a, S->D.slow.as<unsigned char>(), S->D.waves, S->stream), "deferred clip kernel");
 }
@@ -1282,7 +1283,7 @@ static void session_round(rpd_session* S) {
   a_new.nitems_dev = S->r.nitems;
   D.set_touch(a_old);
   D.set_touch(a_new);
-  hip_check(launch_round_front(S->r, a_new, D.parent.as<int>(), D.cell_b0.as<int>(), m->tp.as<float4>(), m->nt,
+  hip_check(launch_round_front(S->r, a_new, D.cell_b0.as<int>(), m->tp.as<float4>(), m->nt,
                                m->nblk, s),
             "round selection");
   clip_pass(S, a_old);  // the dirty blocks' contributions with the old sites, removed

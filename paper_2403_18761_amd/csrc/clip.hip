@@ -37,13 +37,13 @@ __device__ inline long long wv_of(typename Topo::W w, const unsigned* nu, long l
 // One element piece (element, tet) is emitted exactly once per pass: adding sets its gluing bits and count,
 // removing (the same piece recomputed with sign -1) takes both back.
 __device__ inline void node_emit(const ShapeArgs& a, unsigned long long key, int glue) {
-  int ns = ht_insert(a.N, key, a.status);
+  int ns = node_insert(a.N, key, a.status);
   if (ns < 0) return;
   if (a.touch_cell) {
     const int kind = node_kind(key), elem = node_elem(key);
     (kind == 1 ? a.touch_cell : kind == 2 ? a.touch_face : a.touch_edge)[elem] = 1;
   }
-  atomicAdd(&a.node_st[ns], a.sign * (NODE_UNIT + glue));  // removal re-emits the same bits, so this is exact
+  atomicAdd(&a.N.rec[ns].st, a.sign * (NODE_UNIT + glue));  // removal re-emits the same bits, so this is exact
 }
 
 // a per-piece element term for sampled comparisons (RPD_KEEP_PIECES only)
@@ -66,6 +66,20 @@ __device__ inline void keep_term(const ShapeArgs& a, int kind, int t, int i, int
   } else {
     atomicOr(a.status, ST_TABLE_FULL);
   }
+}
+
+// Hands a tet's sorted candidates (list positions into the workgroup's site list) to the large-capacity kernel;
+// returns the item's list word (64 x list index + m), or 0 when the list buffer is full (the call is then redone
+// with larger buffers, so no item is ever processed without its list).
+__device__ inline int hand_over_list(const ShapeArgs& a, const unsigned char* cand, const int* sid, int m) {
+  const unsigned long long idx = atomicAdd(&a.counters[C_LISTS], 1ull);
+  if (idx >= (unsigned long long)a.list_cap) {
+    atomicOr(a.status, ST_TABLE_FULL);
+    return 0;
+  }
+  int* dst = a.deferred_list + idx * (size_t)KRAW;
+  for (int c = 0; c < m; ++c) dst[c] = sid[cand[c]];
+  return (int)(idx * 64) + m;
 }
 
 // Workgroup-local sums of the cell terms (chi numerator, piece count, fixed-point volume and moments) for the first
@@ -548,24 +562,27 @@ __global__ __launch_bounds__(NT) void k_clip_fast(ShapeArgs a) {
       const double ycx = (y[0][0] + y[1][0] + y[2][0]) * 0.25, ycy = (y[0][1] + y[1][1] + y[2][1]) * 0.25,
                    ycz = (y[0][2] + y[1][2] + y[2][2]) * 0.25;
       double U = INFINITY;
-      int qU = 0x7fffffff;  // the site attaining U (lowest list position on ties)
+      int qU = 0, idU = 0x7fffffff;  // the site attaining U: its list position and id (lowest id on ties, so the
+                                     // choice does not depend on the list's order)
       for (int q = h; q < nsl; q += tpt) {
         float4 s = s_site[q];
         double ax_ = (double)s.x - o.x, ay_ = (double)s.y - o.y, az_ = (double)s.z - o.z;
         double D = ax_ * ax_ + ay_ * ay_ + az_ * az_ - (double)s.w * s.w;
         double gmx = D;
         for (int v = 0; v < 3; ++v) gmx = fmax(gmx, D - 2.0 * (y[v][0] * ax_ + y[v][1] * ay_ + y[v][2] * az_));
-        if (gmx < U) {
+        if (gmx < U || (gmx == U && s_sid[q] < idU)) {
           U = gmx;
           qU = q;
+          idU = s_sid[q];
         }
       }
       for (int off = 1; off < tpt; off <<= 1) {
         const double U2 = __shfl_xor(U, off);
-        const int q2 = __shfl_xor(qU, off);
-        if (U2 < U || (U2 == U && q2 < qU)) {
+        const int q2 = __shfl_xor(qU, off), id2 = __shfl_xor(idU, off);
+        if (U2 < U || (U2 == U && id2 < idU)) {
           U = U2;
           qU = q2;
+          idU = id2;
         }
       }
       if (a.tet_U && a.sign > 0 && h == 0) a.tet_U[sd.tet_off + t0 + lt] = U;
@@ -623,8 +640,11 @@ __global__ __launch_bounds__(NT) void k_clip_fast(ShapeArgs a) {
     if (block_overflow || m > a.kmax) {
       s_m[tid] = -1;
       stat_add(a, block_overflow ? C_DEFER_BLOCK : C_DEFER_KMAX, 1ull);
+      // the sorted, refined candidates go with the tet when they fit the list (else the large-capacity kernel finds
+      // them among all sites); either way the choice depends on the tet's candidates only
+      const int list = (!block_overflow && m <= KRAW) ? hand_over_list(a, s_cand[tid], s_sid, m) : 0;
       unsigned long long idx = atomicAdd(&a.counters[C_DEFER_ITEMS], 1ull);
-      if (idx < (unsigned long long)a.deferred_cap) a.deferred[idx] = make_int4(wi.x, t0 + tid, -1, 0);
+      if (idx < (unsigned long long)a.deferred_cap) a.deferred[idx] = make_int4(wi.x, t0 + tid, -1, list);
       else atomicOr(a.status, ST_TABLE_FULL);
     } else {
       s_m[tid] = m;
@@ -698,8 +718,9 @@ __global__ __launch_bounds__(NT) void k_clip_fast(ShapeArgs a) {
       emit_piece(cl, sd, t0 + lt, a, sink);
     } else if (r == CLIP_DEFER) {
       stat_add(a, C_DEFER_CLIP, 1ull);
+      const int list = hand_over_list(a, s_cand[lt], s_sid, m);
       unsigned long long idx = atomicAdd(&a.counters[C_DEFER_ITEMS], 1ull);
-      if (idx < (unsigned long long)a.deferred_cap) a.deferred[idx] = make_int4(wi.x, t0 + lt, cl.env.site_i, 0);
+      if (idx < (unsigned long long)a.deferred_cap) a.deferred[idx] = make_int4(wi.x, t0 + lt, cl.env.site_i, list);
       else atomicOr(a.status, ST_TABLE_FULL);
     }
   }
@@ -842,94 +863,108 @@ __global__ __launch_bounds__(64, LDS ? 1 : 2) void k_clip_slow(ShapeArgs a, unsi
     }
     const double ycx = (y[0][0] + y[1][0] + y[2][0]) * 0.25, ycy = (y[0][1] + y[1][1] + y[2][1]) * 0.25,
                  ycz = (y[0][2] + y[1][2] + y[2][2]) * 0.25;
-    // candidates among ALL sites of the shape (same exact test as the fast kernel)
-    double U = INFINITY;
-    for (int j = lane; j < sd.ns; j += 64) {
-      float4 s = ssite[j];
-      double ax_ = (double)s.x - o.x, ay_ = (double)s.y - o.y, az_ = (double)s.z - o.z;
-      double D = ax_ * ax_ + ay_ * ay_ + az_ * az_ - (double)s.w * s.w;
-      double gmx = D;
-      for (int v = 0; v < 3; ++v) gmx = fmax(gmx, D - 2.0 * (y[v][0] * ax_ + y[v][1] * ay_ + y[v][2] * az_));
-      U = fmin(U, gmx);
-    }
-    for (int off = 32; off > 0; off >>= 1) U = fmin(U, __shfl_xor(U, off));
-    if (a.tet_U && a.sign > 0 && lane == 0) a.tet_U[sd.tet_off + t] = U;
+    // the fast kernel hands over the sorted candidates of the tets and pieces it defers when they fit its list (a
+    // function of the tet's candidates only); otherwise they are found here among all sites
+    const int m_list = di.w & 63;
     int m = 0;
-    for (int base = 0; base < sd.ns; base += 64) {
-      const int j = base + lane;
-      bool take = false;
-      double kk = 0.0;
-      if (j < sd.ns) {
+    if (m_list > 0) {
+      const int* lst = a.deferred_list + (size_t)(di.w >> 6) * KRAW;
+      for (int x = lane; x < m_list; x += 64) {
+        const int sx = lst[x];
+        scand[x] = sx;
+        if (x < SC) s_csite[x] = a.site[sx];
+      }
+      m = m_list;
+      __syncthreads();
+    } else {
+      // candidates among ALL sites of the shape (same exact test as the fast kernel)
+      double U = INFINITY;
+      for (int j = lane; j < sd.ns; j += 64) {
         float4 s = ssite[j];
         double ax_ = (double)s.x - o.x, ay_ = (double)s.y - o.y, az_ = (double)s.z - o.z;
         double D = ax_ * ax_ + ay_ * ay_ + az_ * az_ - (double)s.w * s.w;
-        double gmn = D;
-        for (int v = 0; v < 3; ++v) gmn = fmin(gmn, D - 2.0 * (y[v][0] * ax_ + y[v][1] * ay_ + y[v][2] * az_));
-        take = gmn <= U;
-        kk = D - 2.0 * (ycx * ax_ + ycy * ay_ + ycz * az_);
+        double gmx = D;
+        for (int v = 0; v < 3; ++v) gmx = fmax(gmx, D - 2.0 * (y[v][0] * ax_ + y[v][1] * ay_ + y[v][2] * az_));
+        U = fmin(U, gmx);
       }
-      unsigned long long mask = __ballot(take);
-      int pos = m + __popcll(mask & ((1ull << lane) - 1ull));
-      if (take && pos < KC) {
-        cand[pos] = sd.site_off + j;
-        key[pos] = kk;
+      for (int off = 32; off > 0; off >>= 1) U = fmin(U, __shfl_xor(U, off));
+      if (a.tet_U && a.sign > 0 && lane == 0) a.tet_U[sd.tet_off + t] = U;
+      for (int base = 0; base < sd.ns; base += 64) {
+        const int j = base + lane;
+        bool take = false;
+        double kk = 0.0;
+        if (j < sd.ns) {
+          float4 s = ssite[j];
+          double ax_ = (double)s.x - o.x, ay_ = (double)s.y - o.y, az_ = (double)s.z - o.z;
+          double D = ax_ * ax_ + ay_ * ay_ + az_ * az_ - (double)s.w * s.w;
+          double gmn = D;
+          for (int v = 0; v < 3; ++v) gmn = fmin(gmn, D - 2.0 * (y[v][0] * ax_ + y[v][1] * ay_ + y[v][2] * az_));
+          take = gmn <= U;
+          kk = D - 2.0 * (ycx * ax_ + ycy * ay_ + ycz * az_);
+        }
+        unsigned long long mask = __ballot(take);
+        int pos = m + __popcll(mask & ((1ull << lane) - 1ull));
+        if (take && pos < KC) {
+          cand[pos] = sd.site_off + j;
+          key[pos] = kk;
+        }
+        m += __popcll(mask);
       }
-      m += __popcll(mask);
-    }
-    if (m > KC) {
-      if (lane == 0) {
-        if (LDS) push_overflow(a, di);
-        else atomicOr(a.status, ST_SLOW_CAPACITY);
+      if (m > KC) {
+        if (lane == 0) {
+          if (LDS) push_overflow(a, di);
+          else atomicOr(a.status, ST_SLOW_CAPACITY);
+        }
+        continue;
       }
-      continue;
-    }
-    __syncthreads();
-    // drop every candidate that another one beats at all four tet vertices (g is affine, so then everywhere on the
-    // tet: it owns nothing and its bisector constrains no piece); the values are exact in FP64
-    for (int x = lane; x < m; x += 64) {
-      const float4 s = a.site[cand[x]];
-      const double ax_ = (double)s.x - o.x, ay_ = (double)s.y - o.y, az_ = (double)s.z - o.z;
-      const double D = ax_ * ax_ + ay_ * ay_ + az_ * az_ - (double)s.w * s.w;
-      gv[4 * x] = D;
-      for (int v = 0; v < 3; ++v) gv[4 * x + 1 + v] = D - 2.0 * (y[v][0] * ax_ + y[v][1] * ay_ + y[v][2] * az_);
-    }
-    __syncthreads();
-    int kept = 0;
-    for (int base = 0; base < m; base += 64) {
-      const int x = base + lane;
-      bool keep = false;
-      double kx = 0.0;
-      int cx = 0;
-      if (x < m) {
-        const double g0 = gv[4 * x], g1 = gv[4 * x + 1], g2 = gv[4 * x + 2], g3 = gv[4 * x + 3];
-        keep = true;
-        for (int q = 0; q < m && keep; ++q)
-          keep = !(gv[4 * q] < g0 && gv[4 * q + 1] < g1 && gv[4 * q + 2] < g2 && gv[4 * q + 3] < g3);
-        kx = key[x];
-        cx = cand[x];
+      __syncthreads();
+      // drop every candidate that another one beats at all four tet vertices (g is affine, so then everywhere on the
+      // tet: it owns nothing and its bisector constrains no piece); the values are exact in FP64
+      for (int x = lane; x < m; x += 64) {
+        const float4 s = a.site[cand[x]];
+        const double ax_ = (double)s.x - o.x, ay_ = (double)s.y - o.y, az_ = (double)s.z - o.z;
+        const double D = ax_ * ax_ + ay_ * ay_ + az_ * az_ - (double)s.w * s.w;
+        gv[4 * x] = D;
+        for (int v = 0; v < 3; ++v) gv[4 * x + 1 + v] = D - 2.0 * (y[v][0] * ax_ + y[v][1] * ay_ + y[v][2] * az_);
       }
-      const unsigned long long mask = __ballot(keep);
-      __syncthreads();  // every lane has read cand/key of this chunk before they are overwritten in place
-      if (keep) {
-        const int pos = kept + __popcll(mask & ((1ull << lane) - 1ull));
-        cand[pos] = cx;
-        key[pos] = kx;
+      __syncthreads();
+      int kept = 0;
+      for (int base = 0; base < m; base += 64) {
+        const int x = base + lane;
+        bool keep = false;
+        double kx = 0.0;
+        int cx = 0;
+        if (x < m) {
+          const double g0 = gv[4 * x], g1 = gv[4 * x + 1], g2 = gv[4 * x + 2], g3 = gv[4 * x + 3];
+          keep = true;
+          for (int q = 0; q < m && keep; ++q)
+            keep = !(gv[4 * q] < g0 && gv[4 * q + 1] < g1 && gv[4 * q + 2] < g2 && gv[4 * q + 3] < g3);
+          kx = key[x];
+          cx = cand[x];
+        }
+        const unsigned long long mask = __ballot(keep);
+        __syncthreads();  // every lane has read cand/key of this chunk before they are overwritten in place
+        if (keep) {
+          const int pos = kept + __popcll(mask & ((1ull << lane) - 1ull));
+          cand[pos] = cx;
+          key[pos] = kx;
+        }
+        kept += __popcll(mask);
       }
-      kept += __popcll(mask);
-    }
-    m = kept;
-    __syncthreads();
-    // rank sort by (key, position): positions ascend with the site id, so ties keep the site order
-    for (int x = lane; x < m; x += 64) {
-      const double kx = key[x];
-      int rank = 0;
-      for (int q = 0; q < m; ++q) {
-        const double kq = key[q];
-        rank += (kq < kx || (kq == kx && q < x)) ? 1 : 0;
+      m = kept;
+      __syncthreads();
+      // rank sort by (key, position): positions ascend with the site id, so ties keep the site order
+      for (int x = lane; x < m; x += 64) {
+        const double kx = key[x];
+        int rank = 0;
+        for (int q = 0; q < m; ++q) {
+          const double kq = key[q];
+          rank += (kq < kx || (kq == kx && q < x)) ? 1 : 0;
+        }
+        scand[rank] = cand[x];
+        skey[rank] = kx;
+        if (rank < SC) s_csite[rank] = a.site[cand[x]];
       }
-      scand[rank] = cand[x];
-      skey[rank] = kx;
-      if (rank < SC) s_csite[rank] = a.site[cand[x]];
     }
     if (lane < CL)
       for (int k = 0; k < 4 + m; ++k) tab[CL * k] = 0;  // the plane ids of this item start unpaired
@@ -962,8 +997,8 @@ __global__ __launch_bounds__(64, LDS ? 1 : 2) void k_clip_slow(ShapeArgs a, unsi
       int r = clip_piece(cl, m, a.status);
       n64 += cl.n64;
       nex += cl.nex;
-      if (r == CLIP_DEFER) {  // out of vertex slots
-        if (LDS) push_overflow(a, make_int4(di.x, t, scand[ci], 0));
+      if (r == CLIP_DEFER) {  // out of vertex slots: the global variant redoes the piece with the same candidates
+        if (LDS) push_overflow(a, make_int4(di.x, t, scand[ci], di.w));
         else atomicOr(a.status, ST_SLOW_CAPACITY);
         continue;
       }

@@ -24,6 +24,11 @@ __global__ void k_fill_i32(int* p, int v, size_t n) {
 __global__ void k_fill_multi(FillList L) {
   const FillJob j = L.job[blockIdx.y];
   const size_t tid = blockIdx.x * (size_t)blockDim.x + threadIdx.x, step = (size_t)gridDim.x * blockDim.x;
+  if (j.width == 16) {  // a 16-byte pattern over a 16-byte aligned array
+    const uint4 val = make_uint4((unsigned)j.v, (unsigned)(j.v >> 32), (unsigned)j.v2, (unsigned)(j.v2 >> 32));
+    for (size_t k = tid; k < j.n; k += step) ((uint4*)j.p)[k] = val;
+    return;
+  }
   const unsigned lo = (unsigned)j.v, hi = j.width == 8 ? (unsigned)(j.v >> 32) : lo;
   const size_t w = (size_t)j.width;
   const size_t head = min(((16 - ((size_t)j.p & 15)) & 15) / w, j.n);  // values before the first boundary
@@ -80,26 +85,26 @@ hipError_t launch_fill_i32(int* p, int v, size_t n, hipStream_t s) {
 // ---------------------------------------------------------------------------------------------------------------
 // union-find (lock-free: hook the larger root under the smaller with CAS; path halving)
 // ---------------------------------------------------------------------------------------------------------------
-__device__ inline int uf_find(int* par, int x) {
+__device__ inline int uf_find(NodeRec* rec, int x) {
   while (true) {
-    int p = par[x];
+    int p = rec[x].parent;
     if (p == x) return x;
-    int gp = par[p];
-    if (gp != p) par[x] = gp;
+    int gp = rec[p].parent;
+    if (gp != p) rec[x].parent = gp;
     x = p;
   }
 }
-__device__ inline void uf_union(int* par, int a, int b) {
+__device__ inline void uf_union(NodeRec* rec, int a, int b) {
   while (true) {
-    a = uf_find(par, a);
-    b = uf_find(par, b);
+    a = uf_find(rec, a);
+    b = uf_find(rec, b);
     if (a == b) return;
     if (a < b) {
       int t = a;
       a = b;
       b = t;
     }
-    int old = atomicCAS(&par[a], a, b);
+    int old = atomicCAS(&rec[a].parent, a, b);
     if (old == a) return;
   }
 }
@@ -112,14 +117,14 @@ __device__ inline bool node_touched(const ShapeArgs& a, unsigned long long key) 
   return (kind == 1 ? a.touch_cell : kind == 2 ? a.touch_face : a.touch_edge)[elem] != 0;
 }
 
-__global__ void k_parent_init(ShapeArgs a, int* parent) {
+__global__ void k_parent_init(ShapeArgs a) {
   const unsigned cap = a.N.mask + 1;
   for (unsigned s = blockIdx.x * blockDim.x + threadIdx.x; s < cap; s += gridDim.x * blockDim.x) {
     if (a.touch_cell) {
-      const unsigned long long key = a.N.keys[s];
+      const unsigned long long key = a.N.rec[s].key;
       if (key == EMPTY_KEY || !node_touched(a, key)) continue;
     }
-    parent[s] = (int)s;
+    a.N.rec[s].parent = (int)s;
   }
 }
 
@@ -132,13 +137,14 @@ __global__ void k_clear_touched_b0(const unsigned char* touch, int* b0, size_t n
 // glues back across the same mesh face (both sides must agree), and unite them.
 // Every gluing bit is matched from the tet with the smaller id only (one lookup and one union per glued pair); the
 // symmetry of the records is checked by counting: the bits set must be twice the pairs matched.
-__global__ void k_glue(ShapeArgs a, int* parent) {
+__global__ void k_glue(ShapeArgs a) {
   const unsigned cap = a.N.mask + 1;
   unsigned long long bits = 0, pairs = 0;
   for (unsigned s = blockIdx.x * blockDim.x + threadIdx.x; s < cap; s += gridDim.x * blockDim.x) {
-    unsigned long long key = a.N.keys[s];
+    const NodeRec r = a.N.rec[s];
+    const unsigned long long key = r.key;
     if (key == EMPTY_KEY) continue;
-    const int st = a.node_st[s];
+    const int st = r.st;
     if (!node_live(st)) continue;
     int g = node_glue_bits(st);
     if (!g || !node_touched(a, key)) continue;
@@ -154,14 +160,14 @@ __global__ void k_glue(ShapeArgs a, int* parent) {
       int f2 = -1;
       for (int q = 0; q < 4; ++q)
         if (sd.tn[4 * (size_t)t2 + q] == t) f2 = q;
-      int s2 = ht_find(a.N, hi | (unsigned)(sd.tet_off + t2));
-      const int st2 = s2 >= 0 ? a.node_st[s2] : 0;
+      int s2 = node_find(a.N, hi | (unsigned)(sd.tet_off + t2));
+      const int st2 = s2 >= 0 ? a.N.rec[s2].st : 0;
       if (s2 < 0 || f2 < 0 || !node_live(st2) || !(node_glue_bits(st2) & (1 << f2))) {
         atomicOr(a.status, ST_INTERNAL);
         continue;
       }
       ++pairs;
-      uf_union(parent, (int)s, s2);
+      uf_union(a.N.rec, (int)s, s2);
     }
   }
   __shared__ unsigned long long s_sum[2];
@@ -174,18 +180,19 @@ __global__ void k_glue(ShapeArgs a, int* parent) {
   if (threadIdx.x == 0 && s_sum[1]) stat_add(a, C_GLUE_PAIRS, s_sum[1]);
 }
 
-__global__ void k_count_roots(ShapeArgs a, int* parent, int* cell_b0, int* face_b0, int* edge_b0) {
+__global__ void k_count_roots(ShapeArgs a, int* cell_b0, int* face_b0, int* edge_b0) {
   const unsigned cap = a.N.mask + 1;
   unsigned long long nodes = 0;
   if (blockIdx.x == 0 && threadIdx.x == 0 && stat_sum(a, C_GLUE_BITS) != 2 * stat_sum(a, C_GLUE_PAIRS))
     atomicOr(a.status, ST_INTERNAL);  // a gluing bit without its counterpart
   for (unsigned s = blockIdx.x * blockDim.x + threadIdx.x; s < cap; s += gridDim.x * blockDim.x) {
-    unsigned long long key = a.N.keys[s];
-    const int st = key == EMPTY_KEY ? 0 : a.node_st[s];
+    const NodeRec r = a.N.rec[s];
+    const unsigned long long key = r.key;
+    const int st = key == EMPTY_KEY ? 0 : r.st;
     if (st < 0 || st >= 2 * NODE_UNIT) atomicOr(a.status, ST_INTERNAL);  // every piece is present at most once
     if (!node_live(st)) continue;
     ++nodes;
-    if (!node_touched(a, key) || parent[s] != (int)s) continue;  // one root per component
+    if (!node_touched(a, key) || r.parent != (int)s) continue;  // one root per component
     int kind = (int)(key >> 62);
     int elem = (int)((key >> 32) & 0x3fffffffull);
     if (kind == 1) atomicAdd(&cell_b0[elem], 1);
@@ -209,17 +216,17 @@ hipError_t launch_clear_touched_b0(const unsigned char* touch, int* b0, size_t n
 // scans that end in a per-workgroup reduction run on a grid of at most 4096 workgroups (16 per compute unit)
 static int scan_grid(size_t n) { return std::min(grid_for(n, 256), 4096); }
 
-hipError_t launch_glue(const ShapeArgs& a, int* parent, hipStream_t s) {
+hipError_t launch_glue(const ShapeArgs& a, hipStream_t s) {
   size_t cap = (size_t)a.N.mask + 1;
-  hipLaunchKernelGGL(k_parent_init, dim3(grid_for(cap, 256)), dim3(256), 0, s, a, parent);
-  hipLaunchKernelGGL(k_glue, dim3(scan_grid(cap)), dim3(256), 0, s, a, parent);
+  hipLaunchKernelGGL(k_parent_init, dim3(grid_for(cap, 256)), dim3(256), 0, s, a);
+  hipLaunchKernelGGL(k_glue, dim3(scan_grid(cap)), dim3(256), 0, s, a);
   return hipGetLastError();
 }
 
-hipError_t launch_count_roots(const ShapeArgs& a, int* parent, int* cell_b0, int* face_b0, int* edge_b0,
+hipError_t launch_count_roots(const ShapeArgs& a, int* cell_b0, int* face_b0, int* edge_b0,
                               hipStream_t s) {
   size_t cap = (size_t)a.N.mask + 1;
-  hipLaunchKernelGGL(k_count_roots, dim3(scan_grid(cap)), dim3(256), 0, s, a, parent, cell_b0, face_b0, edge_b0);
+  hipLaunchKernelGGL(k_count_roots, dim3(scan_grid(cap)), dim3(256), 0, s, a, cell_b0, face_b0, edge_b0);
   return hipGetLastError();
 }
 

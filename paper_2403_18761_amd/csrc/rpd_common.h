@@ -36,6 +36,7 @@ enum {
   C_GLUE_BITS,    // gluing bits of the pieces whose components are (re)computed
   C_GLUE_PAIRS,   // glued pairs matched
   C_TERMS,        // per-piece element terms kept with RPD_KEEP_PIECES (cursor)
+  C_LISTS,        // candidate lists handed from the fast kernel to the large-capacity kernel (cursor)
   NCOUNTERS
 };
 // C_RPV counts RPV emissions; the RPV list itself is the set of keys of ShapeArgs::Q with a positive count
@@ -58,6 +59,18 @@ __host__ __device__ inline int node_bnd_bits(int st) { return (st >> 4) & 15; }
 struct HashTab {
   unsigned long long* keys;  // EMPTY_KEY when free
   unsigned int mask;         // capacity - 1, capacity a power of two
+};
+
+// Element pieces (the union-find nodes), one 16-byte record per slot: an insert, its state update and the gluing
+// pass's lookups of a piece touch one cache line.
+struct NodeRec {
+  unsigned long long key;  // kind << 62 | element << 32 | batch-global tet, EMPTY_KEY when free
+  int st;                  // NODE_UNIT x (times the piece is present) + boundary bits + gluing bits
+  int parent;              // union-find parent slot
+};
+struct NodeTab {
+  NodeRec* rec;
+  unsigned int mask;  // capacity - 1, capacity a power of two
 };
 
 // per-piece record kept with RPD_KEEP_PIECES
@@ -113,9 +126,8 @@ struct ShapeArgs {
   long long* edge_len;   // [cap E] summed RPE piece lengths, 2^-56 units
   HashTab Q;             // RPVs (i<j<k<l): key edge slot of (i,j,k) << 21 | l
   int* rpv_cnt;          // [cap Q] (exists while > 0)
-  HashTab N;             // element pieces (union-find nodes): kind<<62 | elem<<32 | global tet
-  int* node_st;          // [cap N] 16 x (times the piece is present) + gluing bits (bit f: glue across local face
-                         // f of its tet); a piece is emitted once per pass, so adding the bits equals or-ing them
+  NodeTab N;             // element pieces (union-find nodes); a piece is emitted once per pass, so adding its
+                         // gluing bits (bit f: glue across local face f of its tet) to the state equals or-ing them
   int sign;              // +1 add the emitted contributions, -1 remove them (incremental update)
   // optional (incremental update): element flags set by every emission, so that only the components of touched
   // elements are recomputed; indexed by site (cells), face-table slot and edge-table slot
@@ -123,8 +135,12 @@ struct ShapeArgs {
   unsigned char* touch_face;
   unsigned char* touch_edge;
   double* tet_U;         // optional [total tets]: U_t of the candidate test, kept for the incremental update
-  int4* deferred;        // (shape, local tet, global site or -1 for every candidate, 0) for the large-capacity path
+  int4* deferred;        // (shape, local tet, global site or -1 for every candidate, list) for the large-capacity
+                         // path; list = 64 x (index in deferred_list) + m when the fast kernel hands over the tet's
+                         // m sorted candidates, else 0 (the large-capacity kernel then finds them itself)
   int deferred_cap;
+  int* deferred_list;    // [list_cap][KRAW] batch-global site ids
+  int list_cap;
   int4* deferred2;       // items the LDS variant of the large-capacity path hands to its global variant
   int deferred2_cap;
   PieceRec* pieces;      // kept with RPD_KEEP_PIECES (t = global tet id)

@@ -520,6 +520,27 @@ __device__ inline int ht_find(const HashTab& h, unsigned long long key) {
   return -1;
 }
 
+__device__ inline int node_insert(const NodeTab& h, unsigned long long key, int* status) {
+  unsigned s = hslot(key, h.mask);
+  for (unsigned probe = 0; probe <= h.mask; ++probe) {
+    unsigned long long prev = atomicCAS(&h.rec[s].key, EMPTY_KEY, key);
+    if (prev == EMPTY_KEY || prev == key) return (int)s;
+    s = (s + 1) & h.mask;
+  }
+  atomicOr(status, ST_TABLE_FULL);
+  return -1;
+}
+__device__ inline int node_find(const NodeTab& h, unsigned long long key) {
+  unsigned s = hslot(key, h.mask);
+  for (unsigned probe = 0; probe <= h.mask; ++probe) {
+    unsigned long long k = h.rec[s].key;
+    if (k == key) return (int)s;
+    if (k == EMPTY_KEY) return -1;
+    s = (s + 1) & h.mask;
+  }
+  return -1;
+}
+
 __device__ inline unsigned long long node_key(int kind, int elem, int t) {
   return ((unsigned long long)kind << 62) | ((unsigned long long)(unsigned)elem << 32) | (unsigned)t;
 }

@@ -17,17 +17,17 @@ hipError_t launch_clip_slow(const ShapeArgs& a, unsigned char* scratch, int wave
 hipError_t launch_fill_u64(unsigned long long* p, unsigned long long v, size_t n, hipStream_t s);
 struct FillJob {
   void* p;
-  unsigned long long v;
+  unsigned long long v, v2;  // the value (width 4 or 8), or the two halves of a 16-byte pattern
   size_t n;
-  int width;  // 4 or 8 bytes
+  int width;  // 4, 8 or 16 bytes (16: p 16-byte aligned)
 };
 struct FillList {
   FillJob job[24];
   int n;
   bool overflow;  // more than 24 jobs were added (launch_fill_multi then fails)
-  void add(void* ptr, unsigned long long val, size_t count, int w) {
+  void add(void* ptr, unsigned long long val, size_t count, int w, unsigned long long val2 = 0) {
     if (!count) return;
-    if (n < 24) job[n++] = FillJob{ptr, val, count, w};
+    if (n < 24) job[n++] = FillJob{ptr, val, val2, count, w};
     else overflow = true;
   }
 };
@@ -36,10 +36,9 @@ hipError_t launch_fill_i32(int* p, int v, size_t n, hipStream_t s);
 // zero counters [c0, c0 + n0) and [c1, c1 + n1) in every spread copy of the statistics
 hipError_t launch_zero_stats(unsigned long long* stats, int c0, int n0, int c1, int n1, hipStream_t s);
 // union-find over the live element pieces (with a.touch_* set: only the pieces of touched elements)
-hipError_t launch_glue(const ShapeArgs& a, int* parent, hipStream_t s);
+hipError_t launch_glue(const ShapeArgs& a, hipStream_t s);
 hipError_t launch_clear_touched_b0(const unsigned char* touch, int* b0, size_t n, hipStream_t s);
-hipError_t launch_count_roots(const ShapeArgs& a, int* parent, int* cell_b0, int* face_b0, int* edge_b0,
-                              hipStream_t s);
+hipError_t launch_count_roots(const ShapeArgs& a, int* cell_b0, int* face_b0, int* edge_b0, hipStream_t s);
 // live entries of a counted table, compacted in any order (count += their number)
 hipError_t launch_compact_live(const unsigned long long* keys, const int* np, unsigned cap,
                                unsigned long long* out_keys, int* out_slots, unsigned long long* count,
@@ -83,7 +82,7 @@ hipError_t launch_scatter_spheres(const float4* sph, const int* slot, int n, flo
 void shrink_spheres(const float* tri, long long nt, const float* pins, const float* normals, const int* own,
                     long long n, hipStream_t st, float4* out);
 // selection, insertion and dirty marking of one round; a supplies the element tables and sites of the new shape
-hipError_t launch_round_front(const RoundState& r, const ShapeArgs& a, const int* parent, const int* cell_b0,
+hipError_t launch_round_front(const RoundState& r, const ShapeArgs& a, const int* cell_b0,
                               const float4* tp, int nt, int nblk, hipStream_t s);
 hipError_t launch_round_end(const RoundState& r, hipStream_t s);
 

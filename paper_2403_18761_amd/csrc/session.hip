@@ -61,9 +61,9 @@ __global__ __launch_bounds__(256) void k_select(RoundState r, const long long* c
   if (threadIdx.x == 0) *r.nsel = min(s_count, r.max_insert);
 }
 
-__device__ inline int uf_root(const int* par, int x) {
+__device__ inline int uf_root(const NodeRec* rec, int x) {
   while (true) {
-    int p = par[x];
+    int p = rec[x].parent;
     if (p == x) return x;
     x = p;
   }
@@ -75,15 +75,16 @@ constexpr int SCAN_BLOCKS = 1024;
 
 // the piece of every selected cell in its smallest tet (caller's numbering, so that the rule does not depend on the
 // internal tet order), packed with its internal tet id for the lookup of its node
-__global__ __launch_bounds__(256) void k_ref_tet(HashTab N, const int* node_st, RoundState r) {
+__global__ __launch_bounds__(256) void k_ref_tet(NodeTab N, RoundState r) {
   extern __shared__ unsigned long long s_ref[];
   const int nsel = *r.nsel;
   for (int k = threadIdx.x; k < nsel; k += blockDim.x) s_ref[k] = ~0ull;
   __syncthreads();
   const unsigned cap = N.mask + 1;
   for (unsigned s = blockIdx.x * blockDim.x + threadIdx.x; s < cap; s += gridDim.x * blockDim.x) {
-    unsigned long long key = N.keys[s];
-    if (key == EMPTY_KEY || (key >> 62) != 1 || !node_live(node_st[s])) continue;
+    const NodeRec nr = N.rec[s];
+    const unsigned long long key = nr.key;
+    if (key == EMPTY_KEY || (key >> 62) != 1 || !node_live(nr.st)) continue;
     int cell = (int)((key >> 32) & 0x3fffffff);
     int k = r.selpos[cell];
     if (k < 0) continue;
@@ -102,8 +103,8 @@ __device__ inline unsigned mix_hash(unsigned long long x) {  // splitmix64 final
   return (unsigned)((x ^ (x >> 31)) >> 32);
 }
 
-__global__ __launch_bounds__(256) void k_pick_tet(HashTab N, const int* node_st, const int* parent, const int* cell_b0,
-                                                  RoundState r, const float4* tp, const float4* site) {
+__global__ __launch_bounds__(256) void k_pick_tet(NodeTab N, const int* cell_b0, RoundState r, const float4* tp,
+                                                  const float4* site) {
   extern __shared__ unsigned long long s_best[];
   const int nsel = *r.nsel;
   for (int k = threadIdx.x; k < nsel; k += blockDim.x) s_best[k] = 0ull;
@@ -111,18 +112,19 @@ __global__ __launch_bounds__(256) void k_pick_tet(HashTab N, const int* node_st,
   const unsigned cap = N.mask + 1;
   const int round = *r.round;
   for (unsigned s = blockIdx.x * blockDim.x + threadIdx.x; s < cap; s += gridDim.x * blockDim.x) {
-    unsigned long long key = N.keys[s];
-    if (key == EMPTY_KEY || (key >> 62) != 1 || !node_live(node_st[s])) continue;
+    const NodeRec nr = N.rec[s];
+    const unsigned long long key = nr.key;
+    if (key == EMPTY_KEY || (key >> 62) != 1 || !node_live(nr.st)) continue;
     int cell = (int)((key >> 32) & 0x3fffffff);
     int k = r.selpos[cell];
     if (k < 0) continue;
     int t = (int)(key & 0xffffffffull);
     const int tc = r.perm[t];  // caller's tet id: the table's index and the hash input
-    const int bnd = node_bnd_bits(node_st[s]);
+    const int bnd = node_bnd_bits(nr.st);
     if (r.mode ? bnd == 0 : r.tet_used[tc] != 0) continue;
     if (cell_b0[cell] > 1) {  // pick outside the component of the cell's piece in its smallest tet
-      int rs = ht_find(N, (key & ~0xffffffffull) | (unsigned)(r.ref[k] & 0xffffffffull));
-      if (rs >= 0 && uf_root(parent, rs) == uf_root(parent, (int)s)) continue;
+      int rs = node_find(N, (key & ~0xffffffffull) | (unsigned)(r.ref[k] & 0xffffffffull));
+      if (rs >= 0 && uf_root(N.rec, rs) == uf_root(N.rec, (int)s)) continue;
     }
     if (r.mode) {  // surface faces of tet t that the piece touches: the one furthest from the cell's centre
       const float4 c = site[cell];
@@ -321,16 +323,15 @@ hipError_t launch_scatter_spheres(const float4* sph, const int* slot, int n, flo
 }
 
 // the round's selection and insertion (everything before the clip passes)
-hipError_t launch_round_front(const RoundState& r, const ShapeArgs& a, const int* parent, const int* cell_b0,
+hipError_t launch_round_front(const RoundState& r, const ShapeArgs& a, const int* cell_b0,
                               const float4* tp, int nt, int nblk, hipStream_t s) {
   hipLaunchKernelGGL(k_round_begin, dim3(1), dim3(64), 0, s, r);
   hipLaunchKernelGGL(k_select, dim3(1), dim3(256), 0, s, r, a.cell_chi, a.cell_np, cell_b0);
   const size_t cap = (size_t)a.N.mask + 1;
   const int scan = std::min(gsz(cap), SCAN_BLOCKS);
-  hipLaunchKernelGGL(k_ref_tet, dim3(scan), dim3(256), sizeof(unsigned long long) * r.max_insert, s, a.N, a.node_st,
-                     r);
-  hipLaunchKernelGGL(k_pick_tet, dim3(scan), dim3(256), sizeof(unsigned long long) * r.max_insert, s, a.N, a.node_st,
-                     parent, cell_b0, r, tp, a.site);
+  hipLaunchKernelGGL(k_ref_tet, dim3(scan), dim3(256), sizeof(unsigned long long) * r.max_insert, s, a.N, r);
+  hipLaunchKernelGGL(k_pick_tet, dim3(scan), dim3(256), sizeof(unsigned long long) * r.max_insert, s, a.N, cell_b0,
+                     r, tp, a.site);
   hipLaunchKernelGGL(k_insert, dim3(1), dim3(1024), 0, s, r, (float4*)a.site);
   hipLaunchKernelGGL(k_mark_dirty, dim3(gsz(nt)), dim3(256), 0, s, r, tp, nt, a.site, a.tet_U);
   hipLaunchKernelGGL(k_dirty_items, dim3(gsz(nblk)), dim3(256), 0, s, r, nblk);

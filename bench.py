@@ -460,6 +460,12 @@ def main():
         est = {"ms_per_rpd": e["ms"], "ms_median": e["ms_median"], "clip_kernel_ms": e["clip_ms"]}
         print(f"# fp32+fallback, estimated dispatch order: {e['ms']:.3f} ms/RPD, clip kernel {e['clip_ms']:.3f} ms",
               file=sys.stderr, flush=True)
+    # the same builds without dispatching heavy blocks in parts
+    ns_ = time_builds(meshes, sites, rpd.RPD_FP32_FALLBACK, args.steps, 1, stream, tuned["block"],
+                      tuned["clip_budget"], flags=rpd.RPD_NO_SPLIT)
+    nosplit = {"ms_per_rpd": ns_["ms"], "ms_median": ns_["ms_median"], "clip_kernel_ms": ns_["clip_ms"]}
+    print(f"# fp32+fallback, heavy blocks not split: {ns_['ms']:.3f} ms/RPD, clip kernel {ns_['clip_ms']:.3f} ms",
+          file=sys.stderr, flush=True)
     out64 = None
     if not args.no_fp64:
         d = time_builds(meshes, sites, rpd.RPD_FP64, args.steps, args.warmup, stream)
@@ -504,8 +510,9 @@ def main():
         "estimated_order": est,
         "all_fp64": out64,
         "stats": {k: st32[k] for k in ("n_candidates", "n_deferred", "n_fp64", "n_exact", "n_faces", "n_edges",
-                                       "n_rpv", "n_defer_block", "n_defer_kmax", "n_defer_clip", "n_split", "ms_clip",
-                                       "ms_deferred", "ms_reduce", "ms_total")},
+                                       "n_rpv", "n_defer_block", "n_defer_kmax", "n_defer_clip", "n_split", "n_items",
+                                       "ms_clip", "ms_deferred", "ms_reduce", "ms_total")},
+        "no_split": nosplit,
         "roofline": roof,
     }
     if args.workload == "torus2000" and not args.no_batch:

@@ -69,6 +69,7 @@ typedef int32_t rpd_status;
 #define RPD_OWNER_WEIGHTS (1u << 6)     /* rpd_mesh_create: ownership weights even when L / k(sigma) fits (below) */
 #define RPD_SHUFFLE_QUEUE (1u << 7)     /* test-only: process the work items in a shuffled order (same results) */
 #define RPD_ESTIMATED_ORDER (1u << 8)   /* order the work by the static estimate even when a mesh has measured times */
+#define RPD_NO_SPLIT (1u << 9)          /* never dispatch a heavy workgroup block in parts (same results, for timing) */
 
 /*
  * A prepared tet mesh (device resident): vertex/tet arrays, face adjacency, the multiplicity k(sigma) of every
@@ -96,6 +97,7 @@ typedef struct rpd_mesh_info {
                                 ownership weights) */
   double volume;
   int32_t owner_weights;     /* 1 if the mesh uses ownership weights */
+  int32_t n_blocks;          /* workgroup blocks (spatially compact runs of up to 64 tets) */
 } rpd_mesh_info;
 
 typedef struct rpd_sites {
@@ -129,6 +131,7 @@ typedef struct rpd_stats {
   int64_t n_defer_kmax;   /* tets deferred because more candidates than the clip budget remained */
   int64_t n_defer_clip;   /* pieces deferred because their polytope outgrew the fast path's vertex slots */
   int64_t n_split;        /* workgroup blocks redone in smaller chunks because their site list overflowed */
+  int64_t n_items;        /* work items of the fast kernel (blocks, and parts of blocks that were heavy before) */
 } rpd_stats;
 
 typedef struct rpd_result rpd_result;

@@ -625,6 +625,8 @@ static std::vector<ShapeDesc> shape_table(const rpd_mesh* const* meshes, const i
     *ns_tot += nsites[k];
     *nt_tot += m->nt;
   }
+  for (int k = 0; k < nsh; ++k)
+    if (hd[k].nblk >= (1 << ITEM_PART_SHIFT)) throw Failure{RPD_E_INVALID, "mesh with 2^20 or more workgroup blocks"};
   if (*ns_tot >= (1 << 21)) throw Failure{RPD_E_INVALID, "more than 2^21 - 1 sites in one call"};
   if (*nt_tot >= (1ll << 31)) throw Failure{RPD_E_INVALID, "more than 2^31 - 1 tets in one call"};
   return hd;
@@ -656,6 +658,33 @@ static std::vector<int2> work_items(const std::vector<ShapeDesc>& hd, const rpd_
                              : (unsigned long long)hd[k].ns * (unsigned long long)(m->hblk[b + 1] - m->hblk[b]));
     }
   }
+  // With measured times, a block that could set the kernel's tail (more than twice the mean, and more than half the
+  // time the kernel needs per workgroup slot: the total over about four resident workgroups per compute unit) is
+  // dispatched in parts of SPLIT_TETS tets, each part its own workgroup with its own site box. Where items are short
+  // against the kernel (large batches) nothing is split, since every part scans the sites again.
+  if (learned && !(flags & RPD_NO_SPLIT) && !items.empty()) {
+    unsigned long long sum = 0;
+    for (unsigned long long c : cost) sum += c;
+    int dev = 0, cus = 0;
+    if (hipGetDevice(&dev) != hipSuccess || hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) !=
+                                                hipSuccess || cus <= 0)
+      cus = 256;
+    const unsigned long long heavy = std::max(2 * (sum / items.size()), sum / (8ull * (unsigned long long)cus)) + 1;
+    const size_t n0 = items.size();
+    for (size_t q = 0; q < n0; ++q) {
+      const int k = items[q].x, b = items[q].y;
+      const int n = meshes[k]->hblk[b + 1] - meshes[k]->hblk[b];
+      if (cost[q] < heavy || n <= SPLIT_TETS) continue;
+      const int parts = (n + SPLIT_TETS - 1) / SPLIT_TETS;
+      const unsigned long long c = cost[q] / parts + 1;
+      items[q].y = b | (1 << ITEM_PART_SHIFT);
+      cost[q] = c;
+      for (int p = 2; p <= parts; ++p) {
+        items.push_back(make_int2(k, b | (p << ITEM_PART_SHIFT)));
+        cost.push_back(c);
+      }
+    }
+  }
   // stable counting sort, descending, on the top bits of the cost range: about one bucket per item, 2^16 at most
   int bits = 8;
   while (bits < 16 && ((size_t)1 << bits) < items.size()) ++bits;
@@ -678,7 +707,8 @@ static void learn_costs(const std::vector<int2>& items, const unsigned* ticks,
   const int nsh = (int)hd.size();
   std::vector<std::vector<unsigned>> per(nsh);
   for (int k = 0; k < nsh; ++k) per[k].assign(hd[k].nblk, 0);
-  for (size_t k = 0; k < items.size(); ++k) per[items[k].x][items[k].y] = ticks[k];
+  for (size_t k = 0; k < items.size(); ++k)  // a split block's cost is the sum of its parts'
+    per[items[k].x][items[k].y & ((1 << ITEM_PART_SHIFT) - 1)] += ticks[k];
   for (int k = 0; k < nsh; ++k) {  // a mesh that several shapes share keeps the last one's times
     rpd_mesh* m = const_cast<rpd_mesh*>(meshes[k]);
     std::lock_guard<std::mutex> g(m->cost_mu);
@@ -758,6 +788,7 @@ static bool run_batch(const rpd_mesh* const* meshes, const rpd_sites* sites, int
   D.components(a, s);
   if (!collect(D, hd, dshapes.as<ShapeDesc>(), meshes, s, tm, outs, st)) return false;
   learn_costs(items, (const unsigned*)ticks_host.p, hd, meshes);
+  st.n_items = (int64_t)items.size();
   st.ms_clip = tm.ms(0, 1);
   st.ms_deferred = tm.ms(1, 2);
   st.ms_reduce = tm.ms(2, 3);
@@ -829,6 +860,7 @@ rpd_status rpd_mesh_get_info(const rpd_mesh* m, rpd_mesh_info* info) {
   info->L = m->L;
   info->volume = m->volume;
   info->owner_weights = m->owner;
+  info->n_blocks = m->nblk;
   return RPD_OK;
 }
 

@@ -119,8 +119,8 @@ __device__ inline void acc128(unsigned long long* p, Fix128 v) {
   if (h) atomicAdd(p + 1, (unsigned long long)h);
 }
 
-template <typename T, typename Topo, typename Mask, int VCAP, bool EXACT>
-__device__ void emit_piece(Clipper<T, Topo, Mask, VCAP, EXACT>& c, const ShapeDesc& sd, int tl, const ShapeArgs& a,
+template <typename T, typename Topo, typename Mask, int VCAP, bool EXACT, typename Tab>
+__device__ void emit_piece(Clipper<T, Topo, Mask, VCAP, EXACT, Tab>& c, const ShapeDesc& sd, int tl, const ShapeArgs& a,
                            const CellSink& sink) {
   typedef typename Topo::W W;
   const int i = c.env.site_i;  // batch-global site id
@@ -148,7 +148,7 @@ __device__ void emit_piece(Clipper<T, Topo, Mask, VCAP, EXACT>& c, const ShapeDe
       int nb = Topo::nb(w, e);
       if (k < nb) se += w_edge(Topo::plane(w, (e + 1) % 3), Topo::plane(w, (e + 2) % 3), nu, L);
       int p = Topo::plane(w, e);
-      if (c.tab[p * c.tst] == 0) c.tab[p * c.tst] = (unsigned char)(k + 1);
+      if (c.tab.get(p) == 0) c.tab.set(p, k + 1);
     }
     if (p0 >= 4 && p1 >= 4 && p2 >= 4) {
       int s0 = c.env.plane_site(p0), s1 = c.env.plane_site(p1), s2 = c.env.plane_site(p2);
@@ -173,9 +173,9 @@ __device__ void emit_piece(Clipper<T, Topo, Mask, VCAP, EXACT>& c, const ShapeDe
   int cell_glue = 0;
   T vol = 0, mx = 0, my = 0, mz = 0;
   for (int p = 0; p < c.np; ++p) {
-    int r = c.tab[p * c.tst];
+    int r = c.tab.get(p);
     if (r == 0) continue;
-    c.tab[p * c.tst] = 0;
+    c.tab.set(p, 0);
     r -= 1;
     sf += (p < 4) ? (long long)nu[10 + p] : L;
     if (p < 4) cell_glue |= tn[p] >= 0 ? 1 << p : 16 << p;  // glue across an interior face; boundary contact
@@ -275,7 +275,7 @@ __device__ void emit_piece(Clipper<T, Topo, Mask, VCAP, EXACT>& c, const ShapeDe
   node_emit(a, node_key(1, i, t), cell_glue);
   keep_term(a, 1, t, i, -1, -1, -1, cell_glue, chi);
   // moments were accumulated with 4x the centroid sum; shift to absolute coordinates
-  float4 o = c.env.tv[0];
+  const float4 o = c.env.o;
   double dvol = (double)vol;
   double dmx = (double)mx * 0.25 + dvol * o.x, dmy = (double)my * 0.25 + dvol * o.y,
          dmz = (double)mz * 0.25 + dvol * o.z;
@@ -315,10 +315,10 @@ __device__ void emit_piece(Clipper<T, Topo, Mask, VCAP, EXACT>& c, const ShapeDe
 // ---------------------------------------------------------------------------------------------------------------
 // clipping of one (tet, candidate) piece against the other candidates in order; returns CLIP_* for the piece
 // ---------------------------------------------------------------------------------------------------------------
-template <typename T, typename Topo, typename Mask, int VCAP, bool EXACT>
-__device__ int clip_piece(Clipper<T, Topo, Mask, VCAP, EXACT>& cl, int m, int* status) {
+template <typename T, typename Topo, typename Mask, int VCAP, bool EXACT, typename Tab>
+__device__ int clip_piece(Clipper<T, Topo, Mask, VCAP, EXACT, Tab>& cl, int m, int* status) {
   const TetEnv& env = cl.env;
-  const float4 o = env.tv[0];
+  const float4 o = env.o;
   const double y1x = (double)env.tv[1].x - o.x, y1y = (double)env.tv[1].y - o.y, y1z = (double)env.tv[1].z - o.z;
   const double y2x = (double)env.tv[2].x - o.x, y2y = (double)env.tv[2].y - o.y, y2z = (double)env.tv[2].z - o.z;
   const double y3x = (double)env.tv[3].x - o.x, y3y = (double)env.tv[3].y - o.y, y3z = (double)env.tv[3].z - o.z;
@@ -363,7 +363,7 @@ __device__ inline float wave_maxf(float v) {
 }
 
 // g_j at the four tet vertices (tet-local frame, exact in FP64)
-__device__ inline void g4(const float4* tv, const float4& s, double* g) {
+__device__ __forceinline__ void g4(const float4* tv, const float4& s, double* g) {
   const float4 o = tv[0];
   double ax = (double)s.x - o.x, ay = (double)s.y - o.y, az = (double)s.z - o.z;
   double D = ax * ax + ay * ay + az * az - (double)s.w * s.w;
@@ -380,7 +380,8 @@ __device__ inline void g4(const float4* tv, const float4& s, double* g) {
 // sorted by the power distance at the centroid, and a dominator has the smaller one, so rounds of three dominators
 // taken in list order (each tested against the candidates after them) find the dominated candidates the three-at-a-time
 // way; the rounds run while candidates remain past the dominators. Returns the new count; order is kept.
-__device__ int refine_candidates(const float4* tv, const float4* sites, unsigned char* cand, float* key, int m) {
+__device__ __forceinline__ int refine_candidates(const float4* tv, const float4* sites, unsigned char* cand, float* key,
+                                                 int m) {
   for (int d = 0; d + 3 < m; d += 3) {
     double g0[4], g1[4], g2[4];
     g4(tv, sites[cand[d]], g0);
@@ -408,8 +409,6 @@ template <typename T, int NT>
 __global__ __launch_bounds__(NT) void k_clip_fast(ShapeArgs a) {
   static_assert(NT % TB == 0 && NT >= TB, "threads per block must be a multiple of the tets per block");
   constexpr int TPT = NT / TB;  // threads per tet in the candidate phase
-  __shared__ float4 s_tv[TB][4];
-  __shared__ float4 s_face[TB][4];
   __shared__ float4 s_site[SLMAX];
   __shared__ int s_sid[SLMAX];
   __shared__ unsigned char s_cand[TB][KRAW];
@@ -428,7 +427,6 @@ __global__ __launch_bounds__(NT) void k_clip_fast(ShapeArgs a) {
   __shared__ int s_nsl;
   __shared__ unsigned long long s_cnt[4];
   __shared__ unsigned s_topo[VMAX * NT];
-  __shared__ unsigned char s_tab[32 * NT];
   // per-site sums of the workgroup's cell terms (the first 128 sites of the list, or the first 32 with 64 threads,
   // where the LDS budget for four workgroups per compute unit is tight); pieces of later sites add to the global
   // accumulators directly
@@ -440,7 +438,6 @@ __global__ __launch_bounds__(NT) void k_clip_fast(ShapeArgs a) {
 
   const int tid = threadIdx.x;
   const int lane = tid & 63, wid = tid >> 6;
-  for (int k = tid; k < 32 * NT; k += NT) s_tab[k] = 0;
   for (int k = tid; k < AGG; k += NT) {
     s_acc_chi[k] = 0;
     s_acc_np[k] = 0;
@@ -459,8 +456,13 @@ __global__ __launch_bounds__(NT) void k_clip_fast(ShapeArgs a) {
   if (item >= (a.nitems_dev ? *a.nitems_dev : a.nitems)) break;
   const int2 wi = a.items[item];
   const ShapeDesc sd = a.shapes[__builtin_amdgcn_readfirstlane(wi.x)];
-  const int tb0 = sd.blk[wi.y];
-  const int ntb_all = sd.blk[wi.y + 1] - tb0;
+  const int blk = wi.y & ((1 << ITEM_PART_SHIFT) - 1), part = wi.y >> ITEM_PART_SHIFT;
+  int tb0 = sd.blk[blk];
+  int ntb_all = sd.blk[blk + 1] - tb0;
+  if (part > 0) {  // one part of a heavy block (the host only makes parts that exist)
+    tb0 += (part - 1) * SPLIT_TETS;
+    ntb_all = min(SPLIT_TETS, ntb_all - (part - 1) * SPLIT_TETS);
+  }
   // A block whose shared site list overflows is redone in chunks of SUB tets (smaller boxes, shorter lists);
   // only tets of a chunk that still overflows go to the large-capacity kernel.
   int sub = 0, sub_n = ntb_all;
@@ -471,26 +473,20 @@ __global__ __launch_bounds__(NT) void k_clip_fast(ShapeArgs a) {
   int tpt = TPT;  // threads per tet in the candidate phase
   while (tpt < 64 && 2 * tpt * ntb <= NT) tpt *= 2;
 
-  // ---- 1. load the tets, their face planes and the bounding box
+  // ---- 1. the tets' bounding box (tet vertices and face planes are read from HBM where they are needed, through
+  //        the caches: on chip, the LDS budget goes to the polytopes, so that more workgroups fit a compute unit)
   float lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
   if (tid < TB) {
     if (tid < ntb) {
       const float4* tp = sd.tp + 4 * (size_t)(t0 + tid);
       for (int v = 0; v < 4; ++v) {
         float4 p = tp[v];
-        s_tv[tid][v] = p;
         lo[0] = fminf(lo[0], p.x);
         lo[1] = fminf(lo[1], p.y);
         lo[2] = fminf(lo[2], p.z);
         hi[0] = fmaxf(hi[0], p.x);
         hi[1] = fmaxf(hi[1], p.y);
         hi[2] = fmaxf(hi[2], p.z);
-      }
-      const double4* tf = sd.tf + 4 * (size_t)(t0 + tid);
-      for (int f = 0; f < 4; ++f) {
-        const double4 pd = tf[f];
-        Plane<float> pf = round_plane<float>(Plane<double>{pd.x, pd.y, pd.z, pd.w});
-        s_face[tid][f] = make_float4(pf.nx, pf.ny, pf.nz, pf.d);
       }
     }
     s_m[tid] = 0;
@@ -551,7 +547,7 @@ __global__ __launch_bounds__(NT) void k_clip_fast(ShapeArgs a) {
   if (!block_overflow) {
     const int lt = tid / tpt, h = tid % tpt;
     if (lt < ntb) {
-      const float4* tv = s_tv[lt];
+      const float4* tv = sd.tp + 4 * (size_t)(t0 + lt);
       const float4 o = tv[0];
       double y[3][3];
       for (int v = 1; v < 4; ++v) {
@@ -635,7 +631,7 @@ __global__ __launch_bounds__(NT) void k_clip_fast(ShapeArgs a) {
         s_key[tid][y + 1] = kx;
         s_cand[tid][y + 1] = cx;
       }
-      m = refine_candidates(s_tv[tid], s_site, s_cand[tid], s_key[tid], m);
+      m = refine_candidates(sd.tp + 4 * (size_t)(t0 + tid), s_site, s_cand[tid], s_key[tid], m);
     }
     if (block_overflow || m > a.kmax) {
       s_m[tid] = -1;
@@ -687,19 +683,18 @@ __global__ __launch_bounds__(NT) void k_clip_fast(ShapeArgs a) {
     const int lt = s_order[lo_];
     const int ci = p - s_off[lo_];
     const int m = s_m[lt];
-    Clipper<T, Topo32, unsigned, VMAX, false> cl;
+    Clipper<T, Topo32, unsigned, VMAX, false, RegTab> cl;
     cl.st.c = s_xyz + tid;
     cl.st.w = s_topo + tid;
     cl.st.stride = NT;
-    cl.tab = s_tab + tid;
-    cl.tst = NT;
-    cl.a = &a;
+    cl.tab.clear(0);
+    cl.a = nullptr;  // only the exact predicates use it (not compiled into this kernel)
     cl.flags = a.flags;
     cl.np = 4 + m;
     cl.n64 = 0;
     cl.nex = 0;
-    cl.env.tv = s_tv[lt];
-    cl.env.faceT = s_face[lt];
+    cl.env.tv = sd.tp + 4 * (size_t)(t0 + lt);
+    cl.env.o = cl.env.tv[0];
     cl.env.face64 = sd.tf + 4 * (size_t)(t0 + lt);
     cl.env.sites = s_site;
     cl.env.sid = s_sid;
@@ -971,19 +966,18 @@ __global__ __launch_bounds__(64, LDS ? 1 : 2) void k_clip_slow(ShapeArgs a, unsi
     __syncthreads();
     for (int ci = lane; ci < m && lane < CL; ci += CL) {
       if (want >= 0 && scand[ci] != want) continue;
-      Clipper<double, Topo64, typename C::Mask, C::VCAP, true> cl;
+      Clipper<double, Topo64, typename C::Mask, C::VCAP, true, MemTab> cl;
       cl.st.c = xyz;
       cl.st.w = topo;
       cl.st.stride = CL;
-      cl.tab = tab;
-      cl.tst = CL;
+      cl.tab = MemTab{tab, CL};
       cl.a = &a;
       cl.flags = a.flags & ~RPD_FORCE_FP64;
       cl.np = 4 + m;
       cl.n64 = 0;
       cl.nex = 0;
       cl.env.tv = s_tv4;
-      cl.env.faceT = nullptr;
+      cl.env.o = s_tv4[0];
       cl.env.face64 = s_tf4;
       cl.env.sites = a.site;
       cl.env.sid = nullptr;  // candidates hold batch-global site ids directly

@@ -13,6 +13,10 @@ constexpr int KRAW = 40;     // candidate sites per tet before the dominance ref
 constexpr int VMAX = 16;     // vertex slots of one piece (4-bit neighbour ids)
 constexpr int SLMAX = 256;   // sites in a workgroup's shared candidate list
 constexpr int SUB = 8;       // tets per chunk when a block's site list overflows
+// Work items are (shape, block + (part << ITEM_PART_SHIFT)): part 0 is the whole block, part p >= 1 its tets
+// [(p - 1) SPLIT_TETS, p SPLIT_TETS) (heavy blocks are dispatched in parts so that no workgroup sets the kernel's tail)
+constexpr int ITEM_PART_SHIFT = 20;  // blocks per mesh < 2^20
+constexpr int SPLIT_TETS = 16;
 // Large-capacity (deferred) path.
 constexpr int SLOW_KMAX = 1020;  // candidate sites per tet
 constexpr int SLOW_VMAX = 64;    // vertex slots of one piece
@@ -107,7 +111,7 @@ struct ShapeDesc {
 struct ShapeArgs {
   const ShapeDesc* shapes;
   int nshapes;
-  const int2* items;     // (shape, block) work items, heaviest first
+  const int2* items;     // (shape, block and part) work items, heaviest first
   int nitems;            // number of items, or the grid size when nitems_dev is set
   const int* nitems_dev; // optional: the item count in device memory (graph-captured rounds)
   // ---- sites (all shapes)

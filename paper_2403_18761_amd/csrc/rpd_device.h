@@ -416,7 +416,7 @@ __device__ inline int ctz_mask(unsigned long long m) { return __builtin_ctzll(m)
 // ---------------------------------------------------------------------------------------------------------------
 struct TetEnv {
   const float4* tv;      // 4 vertices (absolute)
-  const float4* faceT;   // 4 normalised float face planes (fast path), or nullptr
+  float4 o;              // vertex 0: the origin of the tet-local frame
   const double4* face64;  // the tet's 4 face planes in FP64 (normal exact, offset rounded once)
   const float4* sites;   // candidate site data, indexed through cidx
   const int* sid;        // site ids, indexed through cidx
@@ -438,22 +438,20 @@ struct TetEnv {
       const double4 f = face64[p];
       return Plane<double>{f.x, f.y, f.z, f.w};
     }
-    return bisector64(si, cand_site(p - 4), tv[0]);
+    return bisector64(si, cand_site(p - 4), o);
   }
   __device__ PlaneI planeI(int p) const {
     if (p < 4) return face_planeI(tv, p);
-    return bisectorI(si, cand_site(p - 4), tv[0]);
+    return bisectorI(si, cand_site(p - 4), o);
   }
   template <typename T>
   __device__ Plane<T> planeT(int p) const;
 };
 
+// FP32 planes are rounded from the FP64 ones on every use (face planes included: the FP64 face planes are read
+// through the caches, which keeps the per-workgroup LDS of the fast kernel to its polytopes)
 template <>
 __device__ inline Plane<float> TetEnv::planeT<float>(int p) const {
-  if (p < 4 && faceT) {
-    float4 f = faceT[p];
-    return Plane<float>{f.x, f.y, f.z, f.w};
-  }
   return round_plane<float>(plane64(p));
 }
 template <>
@@ -548,17 +546,48 @@ __device__ inline int node_kind(unsigned long long key) { return (int)(key >> 62
 __device__ inline int node_elem(unsigned long long key) { return (int)((key >> 32) & 0x3fffffffull); }
 
 // ---------------------------------------------------------------------------------------------------------------
+// Per-plane scratch of the clipper (pairing of new vertices; first vertex of each face during emission): entry p is
+// 0 or (slot + 1), and every entry is 0 between operations. MemTab keeps it in memory (any number of planes);
+// RegTab in five registers (plane ids < 32, slots < 16: four words of 4-bit slots and a word of fifth bits).
+// ---------------------------------------------------------------------------------------------------------------
+struct MemTab {
+  unsigned char* base;
+  int stride;
+  __device__ int get(int q) const { return base[q * stride]; }
+  __device__ void set(int q, int v) { base[q * stride] = (unsigned char)v; }
+  __device__ void clear(int np) {
+    for (int q = 0; q < np; ++q) base[q * stride] = 0;
+  }
+};
+struct RegTab {
+  unsigned w0, w1, w2, w3, hi;
+  __device__ void clear(int) { w0 = w1 = w2 = w3 = hi = 0u; }
+  __device__ int get(int q) const {
+    const unsigned w = q < 8 ? w0 : q < 16 ? w1 : q < 24 ? w2 : w3;
+    return (int)(((w >> ((q & 7) * 4)) & 15u) | (((hi >> q) & 1u) << 4));
+  }
+  __device__ void set(int q, int v) {
+    const int sh = (q & 7) * 4;
+    const unsigned keep = ~(15u << sh), put = ((unsigned)v & 15u) << sh;
+    if (q < 8) w0 = (w0 & keep) | put;
+    else if (q < 16) w1 = (w1 & keep) | put;
+    else if (q < 24) w2 = (w2 & keep) | put;
+    else w3 = (w3 & keep) | put;
+    hi = (hi & ~(1u << q)) | (((unsigned)v >> 4) << q);
+  }
+};
+
+// ---------------------------------------------------------------------------------------------------------------
 // The clipper: one convex piece P = t & {clipped half-spaces}, vertices in a Store, live slots in a mask.
 // ---------------------------------------------------------------------------------------------------------------
 enum { CLIP_OK = 0, CLIP_EMPTY = 1, CLIP_DEFER = 2 };
 
-template <typename T, typename Topo, typename Mask, int VCAP, bool EXACT>
+template <typename T, typename Topo, typename Mask, int VCAP, bool EXACT, typename Tab>
 struct Clipper {
   typedef typename Topo::W W;
   static_assert((VCAP & (VCAP - 1)) == 0, "vertex capacity must be a power of two");
   Store<T, Topo, VCAP> st;
-  unsigned char* tab;  // per plane id p at tab[p * tst]: 0 or (slot + 1); all zero between operations
-  int tst;
+  Tab tab;  // per plane id: 0 or (slot + 1); all zero between operations
   Mask live;
   TetEnv env;
   const ShapeArgs* a;
@@ -569,7 +598,7 @@ struct Clipper {
   __device__ static Mask bit(int k) { return (Mask)1 << k; }
 
   __device__ void init_tet() {
-    float4 o = env.tv[0];
+    const float4 o = env.o;
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
       T x = (T)(env.tv[v].x - o.x), y = (T)(env.tv[v].y - o.y), z = (T)(env.tv[v].z - o.z);
@@ -603,12 +632,12 @@ struct Clipper {
   }
 
   __device__ void pair_up(int p, int s, W& nw, int pos_in_new) {
-    int prev = tab[p * tst];
+    int prev = tab.get(p);
     if (prev == 0) {
-      tab[p * tst] = (unsigned char)(s + 1);
+      tab.set(p, s + 1);
       return;
     }
-    tab[p * tst] = 0;
+    tab.set(p, 0);
     int s1 = prev - 1;
     nw = Topo::set_nb(nw, pos_in_new, s1);
     W w1 = st.topo(s1);
@@ -645,7 +674,7 @@ struct Clipper {
         int nb = Topo::nb(w, e);
         if (!(out & bit(nb))) continue;
         if (!freem) {  // out of vertex slots: clear the half-done pairing state and defer the piece
-          for (int p = 0; p < np; ++p) tab[p * tst] = 0;
+          tab.clear(np);
           return CLIP_DEFER;
         }
         int s = ctz_mask(freem);

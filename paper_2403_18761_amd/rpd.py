@@ -29,6 +29,7 @@ RPD_KEEP_PIECES = 1 << 5
 RPD_OWNER_WEIGHTS = 1 << 6
 RPD_SHUFFLE_QUEUE = 1 << 7
 RPD_ESTIMATED_ORDER = 1 << 8
+RPD_NO_SPLIT = 1 << 9
 RPD_NOALLOC_SCRATCH_BYTES = 64 << 20  # the no-allocation entry point's working memory per device
 
 _f32p = C.POINTER(C.c_float)
@@ -43,7 +44,7 @@ class _MeshDesc(C.Structure):
 class _MeshInfo(C.Structure):
     _fields_ = [("n_verts", C.c_int32), ("n_tets", C.c_int32), ("n_edges", C.c_int32), ("n_faces", C.c_int32),
                 ("euler", C.c_int32), ("components", C.c_int32), ("L", C.c_int64), ("volume", C.c_double),
-                ("owner_weights", C.c_int32)]
+                ("owner_weights", C.c_int32), ("n_blocks", C.c_int32)]
 
 
 class _Sites(C.Structure):
@@ -60,7 +61,8 @@ class _Stats(C.Structure):
                 ("n_fp64", C.c_int64), ("n_exact", C.c_int64), ("n_cells", C.c_int64), ("n_faces", C.c_int64),
                 ("n_edges", C.c_int64), ("n_rpv", C.c_int64), ("n_glue", C.c_int64), ("ms_clip", C.c_double),
                 ("ms_deferred", C.c_double), ("ms_reduce", C.c_double), ("ms_total", C.c_double),
-                ("n_defer_block", C.c_int64), ("n_defer_kmax", C.c_int64), ("n_defer_clip", C.c_int64), ("n_split", C.c_int64)]
+                ("n_defer_block", C.c_int64), ("n_defer_kmax", C.c_int64), ("n_defer_clip", C.c_int64), ("n_split", C.c_int64),
+                ("n_items", C.c_int64)]
 
 
 class _SessionOpts(C.Structure):

@@ -138,6 +138,14 @@ def test_learned_dispatch_order_gives_the_same_bits():
     forced = extract(rpd.build([mesh], [s1], flags=rpd.RPD_ESTIMATED_ORDER), 0)  # estimate despite measured times
     for k in ELEMENT_ARRAYS:
         np.testing.assert_array_equal(first[k], forced[k], err_msg=f"estimated order {k}")
+    # measured times also split the heavy blocks into parts of 16 tets (their own workgroups and site boxes)
+    split = rpd.build([mesh], [s1])
+    whole = rpd.build([mesh], [s1], flags=rpd.RPD_NO_SPLIT)
+    log("work items with and without parts:", split.stats()["n_items"], whole.stats()["n_items"])
+    assert split.stats()["n_items"] > whole.stats()["n_items"] == mesh.info()["n_blocks"]
+    for k in ELEMENT_ARRAYS:
+        np.testing.assert_array_equal(first[k], extract(split, 0)[k], err_msg=f"split blocks {k}")
+        np.testing.assert_array_equal(first[k], extract(whole, 0)[k], err_msg=f"no split {k}")
     lone = extract(rpd.build([mesh], [s2]), 0)
     res = rpd.build([mesh, mesh], [s2, s1])
     for _ in range(2):

@@ -353,7 +353,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-estimated", action="store_true",
                     help="skip the timing of the same builds in the static-estimate dispatch order")
-    ap.add_argument("--no-autotune", action="store_true", help="use the default launch shape (128 threads, k=28)")
+    ap.add_argument("--no-autotune", action="store_true", help="use the default launch shape (64 threads, k=28)")
     ap.add_argument("--launch", default=None, metavar="BLOCK,K",
                     help="use this launch shape (threads per workgroup, clip budget) instead of autotuning")
     ap.add_argument("--cpu-frac", type=float, default=None)
@@ -442,7 +442,7 @@ def main():
         b, k = (int(x) for x in args.launch.split(","))
         tuned = {"block": b, "clip_budget": k}
     elif args.no_autotune:
-        tuned = {"block": 128, "clip_budget": 28}
+        tuned = {"block": 64, "clip_budget": 28}
     else:
         tuned = rpd.autotune(meshes, sites, stream=stream)
     print(f"# autotuned launch shape: {tuned}", file=sys.stderr, flush=True)

@@ -275,7 +275,7 @@ void rpd_free(rpd_result* r);
  * threads x clip budget 8, 16 or 28, each timed by HIP events over the clipping kernels, best of two after a warm-up),
  * writes the fastest into *best (a copy of *opts with block and clip_budget set) and caches it for the process under
  * the bucket (floor log2 of the mean sites per shape, floor log2 of the mean tets per shape). Later rpd_build calls
- * whose block or clip_budget is 0 take the cached value of their bucket (else 128 and 28). Every launch shape gives
+ * whose block or clip_budget is 0 take the cached value of their bucket (else 64 and 28), and so does a session. Every launch shape gives
  * identical results; only the time differs. Synchronises. Errors as rpd_build; RPD_E_INVALID for RPD_FP64. */
 rpd_status rpd_autotune(const rpd_mesh* const* meshes, const rpd_sites* sites, int32_t n_shapes, const rpd_opts* opts,
                         rpd_opts* best);

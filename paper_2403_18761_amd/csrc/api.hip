@@ -159,7 +159,7 @@ struct DeviceState {
   int def_cap = 0, piece_cap = 0, term_cap = 0, list_cap = 0;
   DBuf site, status, cell_chi, cell_geo, cell_np, cell_b0;
   DBuf fkeys, face_chi, face_np, face_b0, ekeys, edge_chi, edge_np, edge_len, edge_b0, qkeys, rpv_cnt;
-  DBuf nodes, deferred, deferred2, dlist, pieces, terms, counters, tetU, slow, touch;
+  DBuf nodes, deferred, deferred2, dlist, pieces, terms, counters, tetU, slow, touch, removed;
   int waves = 0;
 
   unsigned long long* cnt() const { return counters.as<unsigned long long>(); }
@@ -216,9 +216,10 @@ struct DeviceState {
     pieces.alloc(sizeof(PieceRec) * (size_t)std::max(piece_cap, 1));
     terms.alloc(sizeof(TermRec) * (size_t)std::max(term_cap, 1));
     counters.alloc(8 * (NCOUNTERS + 8 + (size_t)NSPREAD * NCOUNTERS));
-    if (keep_U) {  // incremental updates: U_t per tet and the touched-element flags
+    if (keep_U) {  // incremental updates: U_t per tet, the touched-element flags, the removed-piece tags
       tetU.alloc(8 * (size_t)std::max<long long>(nt, 1));
       touch.alloc(touch_words() * 4);
+      removed.alloc(2 * (size_t)capN);
     }
     waves = slow_waves(nt);
     slow.alloc(slow_scratch_bytes(waves));
@@ -243,6 +244,7 @@ struct DeviceState {
     L.add(nodes.p, EMPTY_KEY, capN, 16, 0ull);  // key EMPTY, state 0, parent 0
     L.add(cnt(), 0, NCOUNTERS + 8 + (size_t)NSPREAD * NCOUNTERS, 8);
     if (touch.p) L.add(touch.p, 0, touch_words(), 4);
+    if (removed.p) L.add(removed.p, 0, capN / 2, 4);
     hip_check(launch_fill_multi(L, s), "fill");
   }
 
@@ -252,6 +254,7 @@ struct DeviceState {
     a.touch_cell = t;
     a.touch_face = t + ns_cap;
     a.touch_edge = t + ns_cap + capF;
+    a.removed = removed.as<unsigned short>();
   }
 
   ShapeArgs args(const ShapeDesc* shapes, const int2* items, int nitems, unsigned flags, int kmax, int sign) const {
@@ -1184,6 +1187,7 @@ static bool session_init(rpd_session* S, const rpd_sites* sites, const rpd_sites
   hipStream_t s = S->stream;
   const bool dev = (S->o.flags & RPD_DEVICE_PTRS) != 0;
   const int nt = m->nt, nblk = m->nblk;
+  if (nblk >= (1 << ITEM_PART_SHIFT)) throw Failure{RPD_E_INVALID, "mesh with 2^20 or more workgroup blocks"};
   DeviceState& D = S->D;
   D.alloc(1, S->max_sites, nt, scale, false, true);
   D.clear(s);
@@ -1238,7 +1242,7 @@ static bool session_init(rpd_session* S, const rpd_sites* sites, const rpd_sites
   ShapeDesc two[2] = {S->hd, S->hd};
   S->dshapes.alloc(sizeof(two));
   S->all_items.alloc(sizeof(int2) * (size_t)nblk);
-  S->items.alloc(sizeof(int2) * (size_t)nblk);
+  S->items.alloc(sizeof(int2) * (size_t)nblk * (TB / SPLIT_TETS));  // every dirty block goes in parts
   S->tet_block.alloc(sizeof(int) * (size_t)nt);
   S->dirty.alloc(sizeof(int) * (size_t)nblk);
   S->sel.alloc(sizeof(int) * (size_t)S->max_insert);
@@ -1291,6 +1295,7 @@ static bool session_init(rpd_session* S, const rpd_sites* sites, const rpd_sites
   r.dirty = S->dirty.as<int>();
   r.order = S->order.as<int>();
   r.items = S->items.as<int2>();
+  r.blk = m->blk.as<int>();
   r.nitems = ints + SI_NITEMS;
   r.round = ints + SI_ROUND;
   r.ns_cur = ints + SI_NS;
@@ -1313,6 +1318,13 @@ static void session_round(rpd_session* S) {
   ShapeArgs a_new = D.args(ds + 1, S->items.as<int2>(), m->nblk, S->o.flags, S->kmax, +1);
   a_old.nitems_dev = S->r.nitems;
   a_new.nitems_dev = S->r.nitems;
+  // the dirty items (every dirty block in parts of SPLIT_TETS tets) are counted on the device: a grid of twice the
+  // resident workgroups (five per compute unit) takes them in grid-stride order, instead of one workgroup per
+  // possible item that mostly exit at once (measured on the 975k-tet repair loop: 1.93 ms per round, against 2.00
+  // with one grid of resident workgroups and 2.03 with one workgroup per possible item)
+  int cus = 0;
+  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, S->device) != hipSuccess || cus <= 0) cus = 256;
+  a_old.nitems = a_new.nitems = std::min(m->nblk * (TB / SPLIT_TETS), 10 * cus);
   D.set_touch(a_old);
   D.set_touch(a_new);
   hip_check(launch_round_front(S->r, a_new, D.cell_b0.as<int>(), m->tp.as<float4>(), m->nt,
@@ -1320,6 +1332,7 @@ static void session_round(rpd_session* S) {
             "round selection");
   clip_pass(S, a_old);  // the dirty blocks' contributions with the old sites, removed
   clip_pass(S, a_new);  // ... and with the new sites, added
+  hip_check(launch_touch_removed(a_new, s), "removed pieces");
   D.components(a_new, s);
   hip_check(launch_round_end(S->r, s), "round end");
 }
@@ -1363,8 +1376,17 @@ rpd_status rpd_session_create(const rpd_mesh* mesh, const rpd_sites* sites, cons
   if (opts->insertion != RPD_INSERT_TABLE && opts->insertion != RPD_INSERT_SHRINK)
     throw Failure{RPD_E_INVALID, "unknown insertion mode"};
   if (opts->insertion == RPD_INSERT_TABLE && !table) throw Failure{RPD_E_INVALID, "null table"};
-  const rpd_opts& o = opts->build;
+  rpd_opts o = opts->build;
   check_opts(o);
+  if (o.precision == RPD_FP32_FALLBACK && (o.block == 0 || o.clip_budget == 0)) {  // the autotuner's launch shape
+    std::lock_guard<std::mutex> g(g_tune_mu);
+    const rpd_mesh* ms1[1] = {mesh};
+    auto it = g_tune.find(tune_bucket(ms1, sites, 1));
+    if (it != g_tune.end()) {
+      if (o.block == 0) o.block = it->second.first;
+      if (o.clip_budget == 0) o.clip_budget = it->second.second;
+    }
+  }
   if (o.flags & (RPD_KEEP_PIECES | RPD_FORCE_SLOW_PATH))
     throw Failure{RPD_E_INVALID, "RPD_KEEP_PIECES and RPD_FORCE_SLOW_PATH are not available in a session"};
   if (sites->n_sites <= 0 || !sites->sx || !sites->sy || !sites->sz || !sites->sr)

@@ -36,14 +36,27 @@ __device__ inline long long wv_of(typename Topo::W w, const unsigned* nu, long l
 
 // One element piece (element, tet) is emitted exactly once per pass: adding sets its gluing bits and count,
 // removing (the same piece recomputed with sign -1) takes both back.
+// In an incremental update the element is flagged for a new union-find only when the piece changes: a piece the
+// removal pass takes out and the addition pass puts back with the same gluing bits leaves the element's forest as
+// it was (pieces that do not come back are flagged by a scan after the addition pass).
 __device__ inline void node_emit(const ShapeArgs& a, unsigned long long key, int glue) {
   int ns = node_insert(a.N, key, a.status);
   if (ns < 0) return;
-  if (a.touch_cell) {
-    const int kind = node_kind(key), elem = node_elem(key);
-    (kind == 1 ? a.touch_cell : kind == 2 ? a.touch_face : a.touch_edge)[elem] = 1;
-  }
   atomicAdd(&a.N.rec[ns].st, a.sign * (NODE_UNIT + glue));  // removal re-emits the same bits, so this is exact
+  if (a.touch_cell) {
+    const unsigned short tag = (unsigned short)(0x100 | glue);
+    bool changed = false;
+    if (a.sign < 0) {
+      a.removed[ns] = tag;
+    } else {
+      changed = a.removed[ns] != tag;
+      a.removed[ns] = 0;
+    }
+    if (changed) {
+      const int kind = node_kind(key), elem = node_elem(key);
+      (kind == 1 ? a.touch_cell : kind == 2 ? a.touch_face : a.touch_edge)[elem] = 1;
+    }
+  }
 }
 
 // a per-piece element term for sampled comparisons (RPD_KEEP_PIECES only)
@@ -447,13 +460,13 @@ __global__ __launch_bounds__(NT) void k_clip_fast(ShapeArgs a) {
     }
   }
   unsigned long long n_pairs = 0, n64 = 0, n_cand = 0;
+  const int nitems = a.nitems_dev ? *a.nitems_dev : a.nitems;
+  // Work items are (shape, block or part of a block), ordered heaviest first. In a build the grid covers them, one
+  // item per workgroup, and the hardware dispatcher hands them to compute units in that order as they free up,
+  // which is the work queue. The passes of an incremental round read the item count on the device and launch a
+  // grid sized to the resident workgroups, each taking items in grid-stride order.
+  for (int item = blockIdx.x; item < nitems; item += gridDim.x) {
   const unsigned long long clock0 = wall_clock64();
-  // One workgroup per (shape, block) item; items are ordered heaviest first and the hardware dispatcher hands
-  // them to compute units in that order as they free up, which is the work queue. (A persistent loop that pulls
-  // items from an atomic counter computes the same thing but costs about 100 more VGPRs per thread here.)
-  do {
-  const int item = blockIdx.x;
-  if (item >= (a.nitems_dev ? *a.nitems_dev : a.nitems)) break;
   const int2 wi = a.items[item];
   const ShapeDesc sd = a.shapes[__builtin_amdgcn_readfirstlane(wi.x)];
   const int blk = wi.y & ((1 << ITEM_PART_SHIFT) - 1), part = wi.y >> ITEM_PART_SHIFT;
@@ -742,13 +755,12 @@ __global__ __launch_bounds__(NT) void k_clip_fast(ShapeArgs a) {
   sub_n = min(SUB, ntb_all - sub);
   __syncthreads();  // the next chunk reuses every shared array
   }
-  } while (false);
+  __syncthreads();  // the next item reuses every shared array
+  if (a.item_cost && tid == 0)  // the item's duration (every thread is past it), a scheduling hint for the next build
+    a.item_cost[item] = (unsigned)min(wall_clock64() - clock0, 0xffffffffull);
+  }
   if (tid < 4) s_cnt[tid] = 0;
   __syncthreads();
-  if (a.item_cost && tid == 0) {  // the item's duration (every thread is past it), a scheduling hint for the next build
-    const int nit = a.nitems_dev ? *a.nitems_dev : a.nitems;
-    if ((int)blockIdx.x < nit) a.item_cost[blockIdx.x] = (unsigned)min(wall_clock64() - clock0, 0xffffffffull);
-  }
   atomicAdd(&s_cnt[0], n_pairs);
   atomicAdd(&s_cnt[1], n64);
   __syncthreads();
@@ -1027,9 +1039,9 @@ static hipError_t launch_items(const ShapeArgs& a, hipStream_t s) {
 hipError_t launch_clip_fast(const ShapeArgs& a, int precision, int block, hipStream_t s) {
   if (a.nitems == 0) return hipSuccess;
   if (precision == RPD_FP64) return launch_items<double, 64>(a, s);
-  if (block == 64) return launch_items<float, 64>(a, s);
+  if (block == 128) return launch_items<float, 128>(a, s);
   if (block == 256) return launch_items<float, 256>(a, s);
-  return launch_items<float, 128>(a, s);
+  return launch_items<float, 64>(a, s);  // 64 threads (also for block 0): five workgroups per compute unit
 }
 
 size_t slow_scratch_bytes(int waves) { return (size_t)waves * SlowScratch::bytes; }

@@ -128,6 +128,23 @@ __global__ void k_parent_init(ShapeArgs a) {
   }
 }
 
+// pieces the removal pass took out and the addition pass did not put back: their elements are flagged
+__global__ void k_touch_removed(ShapeArgs a) {
+  const unsigned cap = a.N.mask + 1;
+  for (unsigned s = blockIdx.x * blockDim.x + threadIdx.x; s < cap; s += gridDim.x * blockDim.x) {
+    if (!a.removed[s]) continue;
+    a.removed[s] = 0;
+    const unsigned long long key = a.N.rec[s].key;
+    const int kind = node_kind(key), elem = node_elem(key);
+    (kind == 1 ? a.touch_cell : kind == 2 ? a.touch_face : a.touch_edge)[elem] = 1;
+  }
+}
+hipError_t launch_touch_removed(const ShapeArgs& a, hipStream_t s) {
+  const size_t cap = (size_t)a.N.mask + 1;
+  hipLaunchKernelGGL(k_touch_removed, dim3(grid_for(cap, 256)), dim3(256), 0, s, a);
+  return hipGetLastError();
+}
+
 __global__ void k_clear_touched_b0(const unsigned char* touch, int* b0, size_t n) {
   for (size_t k = blockIdx.x * (size_t)blockDim.x + threadIdx.x; k < n; k += (size_t)gridDim.x * blockDim.x)
     if (touch[k]) b0[k] = 0;

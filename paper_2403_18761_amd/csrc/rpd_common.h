@@ -138,6 +138,8 @@ struct ShapeArgs {
   unsigned char* touch_cell;
   unsigned char* touch_face;
   unsigned char* touch_edge;
+  unsigned short* removed;  // [cap N] with touch flags: 0x100 | gluing bits of a piece the removal pass took out and
+                            // the addition pass has not put back (yet)
   double* tet_U;         // optional [total tets]: U_t of the candidate test, kept for the incremental update
   int4* deferred;        // (shape, local tet, global site or -1 for every candidate, list) for the large-capacity
                          // path; list = 64 x (index in deferred_list) + m when the fast kernel hands over the tet's
@@ -198,7 +200,8 @@ struct RoundState {
   const int* tet_block;       // [nt] workgroup block of every tet
   int* dirty;                 // [nblk] block flags
   const int* order;           // [nblk] blocks by their time in the initial build, heaviest first (scan order)
-  int2* items;                // [nblk] dirty (shape 0, block) items, in about that order
+  const int* blk;             // [nblk + 1] first tet of every block
+  int2* items;                // [4 nblk] dirty (shape 0, block part) items, in about that order
   int* nitems;
   int* round;
   int* ns_cur;                // sites in use

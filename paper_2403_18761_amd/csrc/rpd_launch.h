@@ -38,6 +38,8 @@ hipError_t launch_zero_stats(unsigned long long* stats, int c0, int n0, int c1, 
 // union-find over the live element pieces (with a.touch_* set: only the pieces of touched elements)
 hipError_t launch_glue(const ShapeArgs& a, hipStream_t s);
 hipError_t launch_clear_touched_b0(const unsigned char* touch, int* b0, size_t n, hipStream_t s);
+// elements of pieces an incremental update removed and did not put back are flagged as touched
+hipError_t launch_touch_removed(const ShapeArgs& a, hipStream_t s);
 hipError_t launch_count_roots(const ShapeArgs& a, int* cell_b0, int* face_b0, int* edge_b0, hipStream_t s);
 // live entries of a counted table, compacted in any order (count += their number)
 hipError_t launch_compact_live(const unsigned long long* keys, const int* np, unsigned cap,

@@ -227,25 +227,39 @@ __global__ void k_mark_dirty(RoundState r, const float4* tp, int nt, const float
   }
 }
 
-// dirty blocks -> work items, then clear the flags. Any order gives the same sums (integers); the blocks are
-// scanned heaviest first so that the items come out in about that order, which shortens the clipping kernel's tail.
+// dirty blocks -> work items (every dirty block in parts of SPLIT_TETS tets: dirty blocks cluster where spheres go in,
+// which is where the sites are densest, and parts spread them over more workgroups), then clear the flags. Any
+// order gives the same sums (integers); the blocks are scanned heaviest first so that the items come out in about
+// that order, which shortens the clipping kernel's tail.
 __global__ void k_dirty_items(RoundState r, int nblk) {
   for (int k = blockIdx.x * blockDim.x + threadIdx.x; k < nblk; k += gridDim.x * blockDim.x) {
     const int b = r.order[k];
     if (!r.dirty[b]) continue;
     r.dirty[b] = 0;
+    const int parts = (r.blk[b + 1] - r.blk[b] + SPLIT_TETS - 1) / SPLIT_TETS;
+    // room for the active lanes' parts: one atomic per wavefront, offsets by a prefix over the active lanes
     const unsigned long long active = __ballot(1);
     const int lane = (int)__lane_id(), leader = __ffsll((long long)active) - 1;
+    int before = 0, sum = 0;
+    for (int q = 0; q < 64; ++q) {
+      const int pq = __shfl(parts, q);
+      if ((active >> q) & 1ull) {
+        sum += pq;
+        if (q < lane) before += pq;
+      }
+    }
     int base = 0;
-    if (lane == leader) base = atomicAdd(r.nitems, __popcll(active));
+    if (lane == leader) {
+      base = atomicAdd(r.nitems, sum);
+      atomicAdd(r.dirty_total, __popcll(active));
+    }
     base = __shfl(base, leader);
-    r.items[base + __popcll(active & ((1ull << lane) - 1ull))] = make_int2(0, b);
+    for (int p = 0; p < parts; ++p) r.items[base + before + p] = make_int2(0, b | ((p + 1) << ITEM_PART_SHIFT));
   }
 }
 
 __global__ void k_round_end(RoundState r) {
   if (threadIdx.x != 0 || blockIdx.x != 0) return;
-  *r.dirty_total += *r.nitems;
   const int nsel = *r.nsel;
   for (int k = 0; k < nsel; ++k) r.selpos[r.sel[k]] = -1;
   *r.ns_cur = r.new_desc->ns;

@@ -148,7 +148,8 @@ rpd_status rpd_mesh_get_info(const rpd_mesh* mesh, rpd_mesh_info* info);
 void rpd_mesh_free(rpd_mesh* mesh);
 
 /* Compute the RPD, chi and beta0 of n_shapes (mesh, sites) pairs in one call (Sec. 5.2 Tet-Cell clipping, Sec. 4.1).
- * meshes[s] and sites[s] describe shape s; sites pointers are borrowed (host, or device with RPD_DEVICE_PTRS).
+ * meshes[s] and sites[s] describe shape s (n_shapes in [1, 2^16)); sites pointers are borrowed (host, or device
+ * with RPD_DEVICE_PTRS).
  * The result owns every array reachable from it until rpd_free; results are host-visible when the call returns
  * (the stream is synchronised once at the end). Errors: RPD_E_INVALID, RPD_E_DEGENERATE, RPD_E_NOMEM,
  * RPD_E_DEVICE, RPD_E_INTERNAL; no partial result. */

@@ -219,7 +219,7 @@ struct DeviceState {
     if (keep_U) {  // incremental updates: U_t per tet, the touched-element flags, the removed-piece tags
       tetU.alloc(8 * (size_t)std::max<long long>(nt, 1));
       touch.alloc(touch_words() * 4);
-      removed.alloc(2 * (size_t)capN);
+      removed.alloc(4 * (size_t)capN);
     }
     waves = slow_waves(nt);
     slow.alloc(slow_scratch_bytes(waves));
@@ -244,7 +244,7 @@ struct DeviceState {
     L.add(nodes.p, EMPTY_KEY, capN, 16, 0ull);  // key EMPTY, state 0, parent 0
     L.add(cnt(), 0, NCOUNTERS + 8 + (size_t)NSPREAD * NCOUNTERS, 8);
     if (touch.p) L.add(touch.p, 0, touch_words(), 4);
-    if (removed.p) L.add(removed.p, 0, capN / 2, 4);
+    if (removed.p) L.add(removed.p, 0, capN, 4);
     hip_check(launch_fill_multi(L, s), "fill");
   }
 
@@ -257,7 +257,7 @@ struct DeviceState {
     a.removed = removed.as<unsigned short>();
   }
 
-  ShapeArgs args(const ShapeDesc* shapes, const int2* items, int nitems, unsigned flags, int kmax, int sign) const {
+  ShapeArgs args(const ShapeDesc* shapes, const int2* items, int nitems, unsigned flags, int kmax) const {
     ShapeArgs a;
     std::memset(&a, 0, sizeof(a));
     a.shapes = shapes;
@@ -279,7 +279,6 @@ struct DeviceState {
     a.Q = HashTab{qkeys.as<unsigned long long>(), capQ - 1};
     a.rpv_cnt = rpv_cnt.as<int>();
     a.N = NodeTab{nodes.as<NodeRec>(), capN - 1};
-    a.sign = sign;
     a.tet_U = tetU.p ? tetU.as<double>() : nullptr;
     a.deferred = deferred.as<int4>();
     a.deferred_cap = def_cap;
@@ -625,6 +624,8 @@ static std::vector<ShapeDesc> shape_table(const rpd_mesh* const* meshes, const i
     d.site_off = (int)*ns_tot;
     d.ns = nsites[k];
     d.tet_off = *nt_tot;
+    d.sign = +1;
+    d.pad = 0;
     *ns_tot += nsites[k];
     *nt_tot += m->nt;
   }
@@ -771,7 +772,7 @@ static bool run_batch(const rpd_mesh* const* meshes, const rpd_sites* sites, int
   D.clear(s);
   upload_sites(D, sites, hd, dev, s);
   const int kmax = o.clip_budget > 0 ? std::min(o.clip_budget, KMAX) : KMAX;
-  ShapeArgs a = D.args(dshapes.as<ShapeDesc>(), ditems.as<int2>(), (int)items.size(), o.flags, kmax, +1);
+  ShapeArgs a = D.args(dshapes.as<ShapeDesc>(), ditems.as<int2>(), (int)items.size(), o.flags, kmax);
   HostPinned ticks_host(sizeof(unsigned) * items.size() + 16);  // pinned: the copy does not stall the host
   struct DrainOnExit {  // an early exit (exception) must not leave the copy into ticks_host pending
     hipStream_t s;
@@ -879,6 +880,7 @@ static void check_opts(const rpd_opts& o) {
 
 static void check_shapes(const rpd_mesh* const* meshes, const rpd_sites* sites, int32_t n_shapes) {
   if (!meshes || !sites || n_shapes <= 0) throw Failure{RPD_E_INVALID, "null argument or no shape"};
+  if (n_shapes >= (1 << 16)) throw Failure{RPD_E_INVALID, "2^16 or more shapes in one call"};
   for (int k = 0; k < n_shapes; ++k) {
     const rpd_sites* sp = &sites[k];
     if (!meshes[k]) throw Failure{RPD_E_INVALID, "null mesh"};
@@ -1240,11 +1242,12 @@ static bool session_init(rpd_session* S, const rpd_sites* sites, const rpd_sites
   std::vector<int2> all(nblk);
   for (int b = 0; b < nblk; ++b) all[b] = make_int2(0, b);
   ShapeDesc two[2] = {S->hd, S->hd};
+  two[0].sign = -1;  // the state before a round's insertions: its dirty pieces are taken back
   S->dshapes.alloc(sizeof(two));
   S->all_items.alloc(sizeof(int2) * (size_t)nblk);
-  S->items.alloc(sizeof(int2) * (size_t)nblk * (TB / SPLIT_TETS));  // every dirty block goes in parts
+  S->items.alloc(sizeof(int2) * 2 * (size_t)nblk * (TB / SPLIT_TETS));  // every dirty block in parts, twice
   S->tet_block.alloc(sizeof(int) * (size_t)nt);
-  S->dirty.alloc(sizeof(int) * (size_t)nblk);
+  S->dirty.alloc(sizeof(unsigned long long) * (size_t)nblk);
   S->sel.alloc(sizeof(int) * (size_t)S->max_insert);
   S->best.alloc(8 * (size_t)S->max_insert);
   S->ref.alloc(sizeof(unsigned long long) * (size_t)S->max_insert);
@@ -1254,13 +1257,13 @@ static bool session_init(rpd_session* S, const rpd_sites* sites, const rpd_sites
   hip_check(hipMemcpyAsync(S->all_items.p, all.data(), sizeof(int2) * all.size(), hipMemcpyHostToDevice, s),
             "upload");
   hip_check(hipMemcpyAsync(S->tet_block.p, tb.data(), sizeof(int) * tb.size(), hipMemcpyHostToDevice, s), "upload");
-  hip_check(launch_fill_i32(S->dirty.as<int>(), 0, nblk, s), "fill");
+  hip_check(launch_fill_i32(S->dirty.as<int>(), 0, 2 * (size_t)nblk, s), "fill");
   hip_check(launch_fill_i32(S->selpos.as<int>(), -1, S->max_sites, s), "fill");
   hip_check(launch_fill_i32(S->ints.as<int>(), 0, SI_COUNT, s), "fill");
   hip_check(launch_fill_i32(S->ints.as<int>() + SI_NS, S->hd.ns, 1, s), "fill");
 
   ShapeDesc* ds = S->dshapes.as<ShapeDesc>();
-  ShapeArgs a = D.args(ds + 1, S->all_items.as<int2>(), nblk, S->o.flags, S->kmax, +1);
+  ShapeArgs a = D.args(ds + 1, S->all_items.as<int2>(), nblk, S->o.flags, S->kmax);
   DBuf ticks(sizeof(unsigned) * (size_t)nblk);
   a.item_cost = ticks.as<unsigned>();  // item k is block k
   clip_pass(S, a);
@@ -1292,7 +1295,7 @@ static bool session_init(rpd_session* S, const rpd_sites* sites, const rpd_sites
   r.table = S->table.as<float4>();
   r.mode = S->mode;
   r.tet_block = S->tet_block.as<int>();
-  r.dirty = S->dirty.as<int>();
+  r.dirty = S->dirty.as<unsigned long long>();
   r.order = S->order.as<int>();
   r.items = S->items.as<int2>();
   r.blk = m->blk.as<int>();
@@ -1314,25 +1317,23 @@ static void session_round(rpd_session* S) {
   DeviceState& D = S->D;
   const rpd_mesh* m = S->mesh;
   ShapeDesc* ds = S->dshapes.as<ShapeDesc>();
-  ShapeArgs a_old = D.args(ds, S->items.as<int2>(), m->nblk, S->o.flags, S->kmax, -1);
-  ShapeArgs a_new = D.args(ds + 1, S->items.as<int2>(), m->nblk, S->o.flags, S->kmax, +1);
-  a_old.nitems_dev = S->r.nitems;
-  a_new.nitems_dev = S->r.nitems;
-  // the dirty items (every dirty block in parts of SPLIT_TETS tets) are counted on the device: a grid of twice the
-  // resident workgroups (five per compute unit) takes them in grid-stride order, instead of one workgroup per
-  // possible item that mostly exit at once (measured on the 975k-tet repair loop: 1.93 ms per round, against 2.00
-  // with one grid of resident workgroups and 2.03 with one workgroup per possible item)
+  // one launch takes out the dirty parts' pieces of the state before the round's insertions (shape 0, sign -1)
+  // and adds those of the state after them (shape 1): items come in pairs (0, part), (1, part)
+  ShapeArgs a = D.args(ds, S->items.as<int2>(), m->nblk, S->o.flags, S->kmax);
+  ShapeArgs a_new = D.args(ds + 1, S->items.as<int2>(), m->nblk, S->o.flags, S->kmax);
+  a.nitems_dev = S->r.nitems;
+  // the dirty items are counted on the device: a grid of twice the resident workgroups (five per compute unit)
+  // takes them in grid-stride order, instead of one workgroup per possible item that mostly exit at once
   int cus = 0;
   if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, S->device) != hipSuccess || cus <= 0) cus = 256;
-  a_old.nitems = a_new.nitems = std::min(m->nblk * (TB / SPLIT_TETS), 10 * cus);
-  D.set_touch(a_old);
+  a.nitems = std::min(2 * m->nblk * (TB / SPLIT_TETS), 10 * cus);
+  D.set_touch(a);
   D.set_touch(a_new);
   hip_check(launch_round_front(S->r, a_new, D.cell_b0.as<int>(), m->tp.as<float4>(), m->nt,
                                m->nblk, s),
             "round selection");
-  clip_pass(S, a_old);  // the dirty blocks' contributions with the old sites, removed
-  clip_pass(S, a_new);  // ... and with the new sites, added
-  hip_check(launch_touch_removed(a_new, s), "removed pieces");
+  clip_pass(S, a);
+  hip_check(launch_touch_removed(a_new, s), "changed pieces");
   D.components(a_new, s);
   hip_check(launch_round_end(S->r, s), "round end");
 }

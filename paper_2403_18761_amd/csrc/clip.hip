@@ -34,29 +34,16 @@ __device__ inline long long wv_of(typename Topo::W w, const unsigned* nu, long l
   return w_vertex(Topo::plane(w, 0), Topo::plane(w, 1), Topo::plane(w, 2), nu, L);
 }
 
-// One element piece (element, tet) is emitted exactly once per pass: adding sets its gluing bits and count,
-// removing (the same piece recomputed with sign -1) takes both back.
-// In an incremental update the element is flagged for a new union-find only when the piece changes: a piece the
-// removal pass takes out and the addition pass puts back with the same gluing bits leaves the element's forest as
-// it was (pieces that do not come back are flagged by a scan after the addition pass).
-__device__ inline void node_emit(const ShapeArgs& a, unsigned long long key, int glue) {
+// One element piece (element, tet) is emitted exactly once per shape: adding sets its gluing bits and count,
+// removing (the same piece recomputed from the state before an incremental update, sign -1) takes both back.
+// The two happen in one launch, in either order. Each records the piece's gluing bits in its own half of the
+// piece's tag pair; a scan after the launch flags the element for a new union-find only where the two differ (a
+// piece put back with the same gluing bits leaves the element's forest as it was).
+__device__ inline void node_emit(const ShapeArgs& a, int sign, unsigned long long key, int glue) {
   int ns = node_insert(a.N, key, a.status);
   if (ns < 0) return;
-  atomicAdd(&a.N.rec[ns].st, a.sign * (NODE_UNIT + glue));  // removal re-emits the same bits, so this is exact
-  if (a.touch_cell) {
-    const unsigned short tag = (unsigned short)(0x100 | glue);
-    bool changed = false;
-    if (a.sign < 0) {
-      a.removed[ns] = tag;
-    } else {
-      changed = a.removed[ns] != tag;
-      a.removed[ns] = 0;
-    }
-    if (changed) {
-      const int kind = node_kind(key), elem = node_elem(key);
-      (kind == 1 ? a.touch_cell : kind == 2 ? a.touch_face : a.touch_edge)[elem] = 1;
-    }
-  }
+  atomicAdd(&a.N.rec[ns].st, sign * (NODE_UNIT + glue));  // removal re-emits the same bits, so this is exact
+  if (a.touch_cell) a.removed[2 * (size_t)ns + (sign > 0)] = (unsigned short)(0x100 | glue);
 }
 
 // a per-piece element term for sampled comparisons (RPD_KEEP_PIECES only)
@@ -141,6 +128,7 @@ __device__ void emit_piece(Clipper<T, Topo, Mask, VCAP, EXACT, Tab>& c, const Sh
   const long long L = sd.L;
   const int* tn = sd.tn + 4 * (size_t)tl;
   const int t = (int)(sd.tet_off + tl);  // batch-global tet id (node keys, piece records)
+  const int sign = sd.sign;
   int* status = a.status;
 
   // ---- vertex pass: vertex and edge weights, face references, apex, RPVs
@@ -171,7 +159,7 @@ __device__ void emit_piece(Clipper<T, Topo, Mask, VCAP, EXACT, Tab>& c, const Sh
         int es = ht_insert(a.E, ekey, status);
         if (es >= 0) {
           int qs = ht_insert(a.Q, ((unsigned long long)es << 21) | (unsigned)hi, status);
-          if (qs >= 0) atomicAdd(&a.rpv_cnt[qs], a.sign);
+          if (qs >= 0) atomicAdd(&a.rpv_cnt[qs], sign);
         }
         stat_add(a, C_RPV, 1ull);
         keep_term(a, 4, t, i, lo, mid, hi, 0, 1);
@@ -230,13 +218,13 @@ __device__ void emit_piece(Clipper<T, Topo, Mask, VCAP, EXACT, Tab>& c, const Sh
             unsigned long long key = ((unsigned long long)i << 42) | ((unsigned long long)j << 21) | (unsigned)k;
             int es = ht_insert(a.E, key, status);
             if (es >= 0) {
-              atomicAdd((unsigned long long*)&a.edge_chi[es], (unsigned long long)(a.sign * ev));
-              atomicAdd(&a.edge_np[es], a.sign);
+              atomicAdd((unsigned long long*)&a.edge_chi[es], (unsigned long long)(sign * ev));
+              atomicAdd(&a.edge_np[es], sign);
               const T lx = N.x - C.x, ly = N.y - C.y, lz = N.z - C.z;
               const double len = (double)sqrt(lx * lx + ly * ly + lz * lz);
-              atomicAdd((unsigned long long*)&a.edge_len[es], (unsigned long long)(a.sign * fixed56(len)));
+              atomicAdd((unsigned long long*)&a.edge_len[es], (unsigned long long)(sign * fixed56(len)));
               int g = ((t1 < 4 && tn[t1] >= 0) ? (1 << t1) : 0) | ((t2 < 4 && tn[t2] >= 0) ? (1 << t2) : 0);
-              node_emit(a, node_key(3, es, t), g);
+              node_emit(a, sign, node_key(3, es, t), g);
               keep_term(a, 3, t, i, j, k, -1, g, ev);
             }
           }
@@ -276,16 +264,16 @@ __device__ void emit_piece(Clipper<T, Topo, Mask, VCAP, EXACT, Tab>& c, const Sh
       unsigned long long key = ((unsigned long long)i << 32) | (unsigned)sp;
       int fs = ht_insert(a.F, key, status);
       if (fs >= 0) {
-        atomicAdd((unsigned long long*)&a.face_chi[fs], (unsigned long long)(a.sign * fvl));
-        atomicAdd(&a.face_np[fs], a.sign);
-        node_emit(a, node_key(2, fs, t), fglue);
+        atomicAdd((unsigned long long*)&a.face_chi[fs], (unsigned long long)(sign * fvl));
+        atomicAdd(&a.face_np[fs], sign);
+        node_emit(a, sign, node_key(2, fs, t), fglue);
       }
       keep_term(a, 2, t, i, sp, -1, -1, fglue, fvl);
     }
   }
   // ---- cell contributions
   long long chi = sv - se + sf - L;
-  node_emit(a, node_key(1, i, t), cell_glue);
+  node_emit(a, sign, node_key(1, i, t), cell_glue);
   keep_term(a, 1, t, i, -1, -1, -1, cell_glue, chi);
   // moments were accumulated with 4x the centroid sum; shift to absolute coordinates
   const float4 o = c.env.o;
@@ -302,10 +290,10 @@ __device__ void emit_piece(Clipper<T, Topo, Mask, VCAP, EXACT, Tab>& c, const Sh
       if (h) atomicAdd(&sink.geo_hi[4 * sink.q + k], (int)h);
     }
   } else {
-    atomicAdd((unsigned long long*)&a.cell_chi[i], (unsigned long long)(a.sign * chi));
-    atomicAdd(&a.cell_np[i], a.sign);
+    atomicAdd((unsigned long long*)&a.cell_chi[i], (unsigned long long)(sign * chi));
+    atomicAdd(&a.cell_np[i], sign);
     for (int k = 0; k < 4; ++k)
-      acc128((unsigned long long*)&a.cell_geo[2 * (4 * (size_t)i + k)], signed128(g[k], a.sign));
+      acc128((unsigned long long*)&a.cell_geo[2 * (4 * (size_t)i + k)], signed128(g[k], sign));
   }
   if (a.flags & RPD_KEEP_PIECES) {
     unsigned long long idx = atomicAdd(&a.counters[C_PIECES], 1ull);
@@ -468,8 +456,13 @@ __global__ __launch_bounds__(NT) void k_clip_fast(ShapeArgs a) {
   for (int item = blockIdx.x; item < nitems; item += gridDim.x) {
   const unsigned long long clock0 = wall_clock64();
   const int2 wi = a.items[item];
-  const ShapeDesc sd = a.shapes[__builtin_amdgcn_readfirstlane(wi.x)];
+  const int shape = __builtin_amdgcn_readfirstlane(wi.x & 0xffff);
+  const ShapeDesc sd = a.shapes[shape];
   const int blk = wi.y & ((1 << ITEM_PART_SHIFT) - 1), part = wi.y >> ITEM_PART_SHIFT;
+  // the tets of the item to clip, relative to its first tet (an incremental update names the tets a new sphere can
+  // reach; every other item takes all)
+  const unsigned tet_mask16 = (unsigned)wi.x >> 16;
+  const unsigned long long item_mask = tet_mask16 ? (unsigned long long)tet_mask16 : ~0ull;
   int tb0 = sd.blk[blk];
   int ntb_all = sd.blk[blk + 1] - tb0;
   if (part > 0) {  // one part of a heavy block (the host only makes parts that exist)
@@ -483,6 +476,13 @@ __global__ __launch_bounds__(NT) void k_clip_fast(ShapeArgs a) {
   while (true) {
   const int t0 = tb0 + sub;
   const int ntb = sub_n;
+  const unsigned long long cmask = item_mask >> sub;  // bit lt: tet t0 + lt is clipped
+  if (split && !(cmask & (ntb >= 64 ? ~0ull : (1ull << ntb) - 1ull))) {  // a chunk without such tets
+    sub += SUB;
+    if (sub >= ntb_all) break;
+    sub_n = min(SUB, ntb_all - sub);
+    continue;
+  }
   int tpt = TPT;  // threads per tet in the candidate phase
   while (tpt < 64 && 2 * tpt * ntb <= NT) tpt *= 2;
 
@@ -490,7 +490,7 @@ __global__ __launch_bounds__(NT) void k_clip_fast(ShapeArgs a) {
   //        the caches: on chip, the LDS budget goes to the polytopes, so that more workgroups fit a compute unit)
   float lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
   if (tid < TB) {
-    if (tid < ntb) {
+    if (tid < ntb && ((cmask >> tid) & 1ull)) {
       const float4* tp = sd.tp + 4 * (size_t)(t0 + tid);
       for (int v = 0; v < 4; ++v) {
         float4 p = tp[v];
@@ -559,7 +559,7 @@ __global__ __launch_bounds__(NT) void k_clip_fast(ShapeArgs a) {
   // ---- 3. candidates of every tet: sites whose minimum over the tet is <= min_j max over the tet
   if (!block_overflow) {
     const int lt = tid / tpt, h = tid % tpt;
-    if (lt < ntb) {
+    if (lt < ntb && ((cmask >> lt) & 1ull)) {
       const float4* tv = sd.tp + 4 * (size_t)(t0 + lt);
       const float4 o = tv[0];
       double y[3][3];
@@ -594,7 +594,7 @@ __global__ __launch_bounds__(NT) void k_clip_fast(ShapeArgs a) {
           idU = id2;
         }
       }
-      if (a.tet_U && a.sign > 0 && h == 0) a.tet_U[sd.tet_off + t0 + lt] = U;
+      if (a.tet_U && sd.sign > 0 && h == 0) a.tet_U[sd.tet_off + t0 + lt] = U;
       // that site's g at the four vertices: a site it beats at all four owns no point of the tet and its bisector
       // constrains no piece (the dominator's own bisector already does), so it is not a candidate
       double gb[4];
@@ -628,7 +628,7 @@ __global__ __launch_bounds__(NT) void k_clip_fast(ShapeArgs a) {
   __syncthreads();
   // sort each tet's candidates by (power distance at the centroid, site id), drop the dominated ones, and mark the
   // tets that keep more than the budget
-  if (tid < ntb) {
+  if (tid < ntb && ((cmask >> tid) & 1ull)) {
     int m = s_m[tid];
     if (!block_overflow && m <= KRAW) {
       for (int x = 1; x < m; ++x) {
@@ -653,7 +653,7 @@ __global__ __launch_bounds__(NT) void k_clip_fast(ShapeArgs a) {
       // them among all sites); either way the choice depends on the tet's candidates only
       const int list = (!block_overflow && m <= KRAW) ? hand_over_list(a, s_cand[tid], s_sid, m) : 0;
       unsigned long long idx = atomicAdd(&a.counters[C_DEFER_ITEMS], 1ull);
-      if (idx < (unsigned long long)a.deferred_cap) a.deferred[idx] = make_int4(wi.x, t0 + tid, -1, list);
+      if (idx < (unsigned long long)a.deferred_cap) a.deferred[idx] = make_int4(shape, t0 + tid, -1, list);
       else atomicOr(a.status, ST_TABLE_FULL);
     } else {
       s_m[tid] = m;
@@ -721,14 +721,14 @@ __global__ __launch_bounds__(NT) void k_clip_fast(ShapeArgs a) {
     int r = clip_piece(cl, m, a.status);
     n64 += cl.n64;
     if (r == CLIP_OK) {
-      ++n_pairs;
+      n_pairs += (unsigned long long)(long long)sd.sign;  // live pieces, in two's complement
       const CellSink sink{s_acc_chi, s_acc_np, s_acc_lo, s_acc_hi, AGG, (int)s_cand[lt][ci]};
       emit_piece(cl, sd, t0 + lt, a, sink);
     } else if (r == CLIP_DEFER) {
       stat_add(a, C_DEFER_CLIP, 1ull);
       const int list = hand_over_list(a, s_cand[lt], s_sid, m);
       unsigned long long idx = atomicAdd(&a.counters[C_DEFER_ITEMS], 1ull);
-      if (idx < (unsigned long long)a.deferred_cap) a.deferred[idx] = make_int4(wi.x, t0 + lt, cl.env.site_i, list);
+      if (idx < (unsigned long long)a.deferred_cap) a.deferred[idx] = make_int4(shape, t0 + lt, cl.env.site_i, list);
       else atomicOr(a.status, ST_TABLE_FULL);
     }
   }
@@ -738,11 +738,11 @@ __global__ __launch_bounds__(NT) void k_clip_fast(ShapeArgs a) {
     const int np_q = s_acc_np[q];
     if (np_q == 0) continue;
     const int i = s_sid[q];
-    atomicAdd((unsigned long long*)&a.cell_chi[i], (unsigned long long)(a.sign * s_acc_chi[q]));
-    atomicAdd(&a.cell_np[i], a.sign * np_q);
+    atomicAdd((unsigned long long*)&a.cell_chi[i], (unsigned long long)(sd.sign * s_acc_chi[q]));
+    atomicAdd(&a.cell_np[i], sd.sign * np_q);
     for (int d = 0; d < 4; ++d) {
       const Fix128 v{s_acc_lo[4 * q + d], (long long)s_acc_hi[4 * q + d]};
-      acc128((unsigned long long*)&a.cell_geo[8 * (size_t)i + 2 * d], signed128(v, a.sign));
+      acc128((unsigned long long*)&a.cell_geo[8 * (size_t)i + 2 * d], signed128(v, sd.sign));
       s_acc_lo[4 * q + d] = 0;
       s_acc_hi[4 * q + d] = 0;
     }
@@ -765,8 +765,7 @@ __global__ __launch_bounds__(NT) void k_clip_fast(ShapeArgs a) {
   atomicAdd(&s_cnt[1], n64);
   __syncthreads();
   if (tid == 0 && n_cand) {
-    // live pieces: a removal pass (sign -1) subtracts in two's complement
-    if (s_cnt[0]) stat_add(a, C_PAIRS, a.sign > 0 ? s_cnt[0] : 0ull - s_cnt[0]);
+    if (s_cnt[0]) stat_add(a, C_PAIRS, s_cnt[0]);
     if (s_cnt[1]) stat_add(a, C_FP64, s_cnt[1]);
     stat_add(a, C_CAND, n_cand);
   }
@@ -895,7 +894,7 @@ __global__ __launch_bounds__(64, LDS ? 1 : 2) void k_clip_slow(ShapeArgs a, unsi
         U = fmin(U, gmx);
       }
       for (int off = 32; off > 0; off >>= 1) U = fmin(U, __shfl_xor(U, off));
-      if (a.tet_U && a.sign > 0 && lane == 0) a.tet_U[sd.tet_off + t] = U;
+      if (a.tet_U && sd.sign > 0 && lane == 0) a.tet_U[sd.tet_off + t] = U;
       for (int base = 0; base < sd.ns; base += 64) {
         const int j = base + lane;
         bool take = false;
@@ -1009,7 +1008,7 @@ __global__ __launch_bounds__(64, LDS ? 1 : 2) void k_clip_slow(ShapeArgs a, unsi
         continue;
       }
       if (r == CLIP_OK) {
-        ++n_pairs;
+        n_pairs += (unsigned long long)(long long)sd.sign;
         emit_piece(cl, sd, t, a, CellSink{nullptr, nullptr, nullptr, nullptr, 0, -1});
       }
     }
@@ -1021,7 +1020,7 @@ __global__ __launch_bounds__(64, LDS ? 1 : 2) void k_clip_slow(ShapeArgs a, unsi
     nex += __shfl_xor(nex, off);
   }
   if (lane == 0) {
-    if (n_pairs) stat_add(a, C_PAIRS, a.sign > 0 ? n_pairs : 0ull - n_pairs);
+    if (n_pairs) stat_add(a, C_PAIRS, n_pairs);
     if (n64) stat_add(a, C_FP64, n64);
     if (nex) stat_add(a, C_EXACT, nex);
   }

@@ -128,12 +128,16 @@ __global__ void k_parent_init(ShapeArgs a) {
   }
 }
 
-// pieces the removal pass took out and the addition pass did not put back: their elements are flagged
+// pieces an incremental update took out and did not put back with the same gluing bits, or added new: their
+// elements are flagged
 __global__ void k_touch_removed(ShapeArgs a) {
   const unsigned cap = a.N.mask + 1;
+  unsigned* pair = (unsigned*)a.removed;  // (taken out, put back) tags of a slot in one word
   for (unsigned s = blockIdx.x * blockDim.x + threadIdx.x; s < cap; s += gridDim.x * blockDim.x) {
-    if (!a.removed[s]) continue;
-    a.removed[s] = 0;
+    const unsigned w = pair[s];
+    if (!w) continue;
+    pair[s] = 0;
+    if ((w & 0xffffu) == (w >> 16)) continue;
     const unsigned long long key = a.N.rec[s].key;
     const int kind = node_kind(key), elem = node_elem(key);
     (kind == 1 ? a.touch_cell : kind == 2 ? a.touch_face : a.touch_edge)[elem] = 1;

@@ -13,10 +13,12 @@ constexpr int KRAW = 40;     // candidate sites per tet before the dominance ref
 constexpr int VMAX = 16;     // vertex slots of one piece (4-bit neighbour ids)
 constexpr int SLMAX = 256;   // sites in a workgroup's shared candidate list
 constexpr int SUB = 8;       // tets per chunk when a block's site list overflows
-// Work items are (shape, block + (part << ITEM_PART_SHIFT)): part 0 is the whole block, part p >= 1 its tets
-// [(p - 1) SPLIT_TETS, p SPLIT_TETS) (heavy blocks are dispatched in parts so that no workgroup sets the kernel's tail)
+// Work items are (shape + (tet mask << 16), block + (part << ITEM_PART_SHIFT)): part 0 is the whole block, part
+// p >= 1 its tets [(p - 1) SPLIT_TETS, p SPLIT_TETS) (heavy blocks are dispatched in parts so that no workgroup sets
+// the kernel's tail). A nonzero tet mask (parts only) names the part's tets to clip, bit k for its tet k; zero
+// means all. Shapes per call < 2^16.
 constexpr int ITEM_PART_SHIFT = 20;  // blocks per mesh < 2^20
-constexpr int SPLIT_TETS = 16;
+constexpr int SPLIT_TETS = 16;       // = the width of the tet mask
 // Large-capacity (deferred) path.
 constexpr int SLOW_KMAX = 1020;  // candidate sites per tet
 constexpr int SLOW_VMAX = 64;    // vertex slots of one piece
@@ -104,6 +106,9 @@ struct ShapeDesc {
   long long L;
   int site_off, ns;    // sites [site_off, site_off + ns) of the batch
   long long tet_off;   // batch-global id of the shape's tet 0
+  int sign;            // +1: the shape's pieces are added; -1: an incremental update takes them back (the state
+                       // before the round's insertions)
+  int pad;
 };
 
 // Everything the kernels of one rpd_build call share. Site ids and tet ids in keys and accumulators are
@@ -132,14 +137,13 @@ struct ShapeArgs {
   int* rpv_cnt;          // [cap Q] (exists while > 0)
   NodeTab N;             // element pieces (union-find nodes); a piece is emitted once per pass, so adding its
                          // gluing bits (bit f: glue across local face f of its tet) to the state equals or-ing them
-  int sign;              // +1 add the emitted contributions, -1 remove them (incremental update)
   // optional (incremental update): element flags set by every emission, so that only the components of touched
   // elements are recomputed; indexed by site (cells), face-table slot and edge-table slot
   unsigned char* touch_cell;
   unsigned char* touch_face;
   unsigned char* touch_edge;
-  unsigned short* removed;  // [cap N] with touch flags: 0x100 | gluing bits of a piece the removal pass took out and
-                            // the addition pass has not put back (yet)
+  unsigned short* removed;  // [2 cap N] with touch flags: per element-piece slot, 0x100 | the gluing bits with which
+                            // an incremental update took the piece out (even entry) and put it back (odd entry)
   double* tet_U;         // optional [total tets]: U_t of the candidate test, kept for the incremental update
   int4* deferred;        // (shape, local tet, global site or -1 for every candidate, list) for the large-capacity
                          // path; list = 64 x (index in deferred_list) + m when the fast kernel hands over the tet's
@@ -198,7 +202,7 @@ struct RoundState {
   const int* perm;            // [nt] internal -> caller tet
   int mode;                   // 0: caller's per-tet table, hashed pick; 1: shrunk spheres at the furthest surface face
   const int* tet_block;       // [nt] workgroup block of every tet
-  int* dirty;                 // [nblk] block flags
+  unsigned long long* dirty;  // [nblk] per block, the mask of its dirty tets (bit k: the block's tet k)
   const int* order;           // [nblk] blocks by their time in the initial build, heaviest first (scan order)
   const int* blk;             // [nblk + 1] first tet of every block
   int2* items;                // [4 nblk] dirty (shape 0, block part) items, in about that order

@@ -223,20 +223,27 @@ __global__ void k_mark_dirty(RoundState r, const float4* tp, int nt, const float
                                    ((double)tv[v].z - o.z) * az));
       dirty = gmn <= U;
     }
-    if (dirty) r.dirty[r.tet_block[t]] = 1;
+    if (dirty) {
+      const int b = r.tet_block[t];
+      atomicOr(&r.dirty[b], 1ull << (t - r.blk[b]));
+    }
   }
 }
 
-// dirty blocks -> work items (every dirty block in parts of SPLIT_TETS tets: dirty blocks cluster where spheres go in,
-// which is where the sites are densest, and parts spread them over more workgroups), then clear the flags. Any
-// order gives the same sums (integers); the blocks are scanned heaviest first so that the items come out in about
-// that order, which shortens the clipping kernel's tail.
+// dirty tets -> work items, then clear the masks. Every part of SPLIT_TETS tets that holds a dirty tet becomes two
+// items with the mask of its dirty tets: in any other tet no new sphere owns a point, so none of its pieces change.
+// Dirty tets cluster where spheres go in, which is where the sites are densest, and parts spread them over more
+// workgroups. Any order gives the same sums (integers); the blocks are scanned heaviest first so that the items
+// come out in about that order, which shortens the clipping kernel's tail.
 __global__ void k_dirty_items(RoundState r, int nblk) {
+  static_assert(SPLIT_TETS == 16 && TB <= 64, "16-bit part masks of a 64-bit block mask");
   for (int k = blockIdx.x * blockDim.x + threadIdx.x; k < nblk; k += gridDim.x * blockDim.x) {
     const int b = r.order[k];
-    if (!r.dirty[b]) continue;
+    const unsigned long long mask = r.dirty[b];
+    if (!mask) continue;
     r.dirty[b] = 0;
-    const int parts = (r.blk[b + 1] - r.blk[b] + SPLIT_TETS - 1) / SPLIT_TETS;
+    int parts = 0;  // parts with a dirty tet
+    for (int p = 0; p < TB / SPLIT_TETS; ++p) parts += ((mask >> (SPLIT_TETS * p)) & 0xffffull) ? 1 : 0;
     // room for the active lanes' parts: one atomic per wavefront, offsets by a prefix over the active lanes
     const unsigned long long active = __ballot(1);
     const int lane = (int)__lane_id(), leader = __ffsll((long long)active) - 1;
@@ -250,11 +257,18 @@ __global__ void k_dirty_items(RoundState r, int nblk) {
     }
     int base = 0;
     if (lane == leader) {
-      base = atomicAdd(r.nitems, sum);
+      base = atomicAdd(r.nitems, 2 * sum) / 2;
       atomicAdd(r.dirty_total, __popcll(active));
     }
     base = __shfl(base, leader);
-    for (int p = 0; p < parts; ++p) r.items[base + before + p] = make_int2(0, b | ((p + 1) << ITEM_PART_SHIFT));
+    int2* out = r.items + 2 * (size_t)(base + before);
+    for (int p = 0; p < TB / SPLIT_TETS; ++p) {
+      const unsigned pm = (unsigned)((mask >> (SPLIT_TETS * p)) & 0xffffull);
+      if (!pm) continue;
+      const int y = b | ((p + 1) << ITEM_PART_SHIFT);
+      *out++ = make_int2((int)(pm << 16), y);      // taken out from the state before the insertions
+      *out++ = make_int2((int)(pm << 16) | 1, y);  // added from the state after them
+    }
   }
 }
 

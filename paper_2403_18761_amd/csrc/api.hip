@@ -159,7 +159,7 @@ struct DeviceState {
   int def_cap = 0, piece_cap = 0, term_cap = 0, list_cap = 0;
   DBuf site, status, cell_chi, cell_geo, cell_np, cell_b0;
   DBuf fkeys, face_chi, face_np, face_b0, ekeys, edge_chi, edge_np, edge_len, edge_b0, qkeys, rpv_cnt;
-  DBuf nodes, deferred, deferred2, dlist, pieces, terms, counters, tetU, slow, touch, removed;
+  DBuf nodes, glist, gseg, deferred, deferred2, dlist, pieces, terms, counters, tetU, slow, touch, removed;
   int waves = 0;
 
   unsigned long long* cnt() const { return counters.as<unsigned long long>(); }
@@ -208,6 +208,8 @@ struct DeviceState {
     qkeys.alloc(8 * (size_t)capQ);
     rpv_cnt.alloc(4 * (size_t)capQ);
     nodes.alloc(sizeof(NodeRec) * (size_t)capN);
+    glist.alloc(sizeof(int) * (size_t)capN);
+    gseg.alloc(sizeof(int) * (size_t)capN / 256);  // the gluing list's segments
     deferred.alloc(16 * (size_t)def_cap);
     deferred2.alloc(16 * (size_t)(def_cap / 4 + 1024));
     // candidate lists of deferred tets and pieces (a few per cent of the tets on the heaviest workloads)
@@ -313,8 +315,10 @@ struct DeviceState {
       hip_check(launch_fill_multi(L, s), "fill");
     }
     hip_check(launch_zero_stats(stat(), C_NODES, 1, C_GLUE_BITS, 2, s), "fill");
-    hip_check(launch_glue(a, s), "glue");
-    hip_check(launch_count_roots(a, cell_b0.as<int>(), face_b0.as<int>(), edge_b0.as<int>(), s), "roots");
+    hip_check(launch_glue(a, glist.as<int>(), gseg.as<int>(), s), "glue");
+    hip_check(launch_count_roots(a, glist.as<int>(), gseg.as<int>(), cell_b0.as<int>(), face_b0.as<int>(),
+                                 edge_b0.as<int>(), s),
+              "roots");
     if (a.touch_cell) hip_check(launch_fill_i32(touch.as<int>(), 0, touch_words(), s), "fill");
   }
 };

@@ -117,15 +117,61 @@ __device__ inline bool node_touched(const ShapeArgs& a, unsigned long long key) 
   return (kind == 1 ? a.touch_cell : kind == 2 ? a.touch_face : a.touch_edge)[elem] != 0;
 }
 
-__global__ void k_parent_init(ShapeArgs a) {
-  const unsigned cap = a.N.mask + 1;
-  for (unsigned s = blockIdx.x * blockDim.x + threadIdx.x; s < cap; s += gridDim.x * blockDim.x) {
-    if (a.touch_cell) {
-      const unsigned long long key = a.N.rec[s].key;
-      if (key == EMPTY_KEY || !node_touched(a, key)) continue;
-    }
-    a.N.rec[s].parent = (int)s;
+// Output position of a thread's n items: exclusive prefix within the 256-thread block, plus the block's base from
+// one global atomic per block (a wave-level atomic on one address for every wave of a large table serialises).
+__device__ inline unsigned long long block_append(int n, unsigned long long* count) {
+  __shared__ int s_w[4];
+  __shared__ unsigned long long s_base;
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  int x = n;
+  for (int off = 1; off < 64; off <<= 1) {
+    const int y = __shfl_up(x, off);
+    if (lane >= off) x += y;
   }
+  if (lane == 63) s_w[w] = x;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const int tot = s_w[0] + s_w[1] + s_w[2] + s_w[3];
+    s_base = tot ? atomicAdd(count, (unsigned long long)tot) : 0ull;
+  }
+  __syncthreads();
+  int before = 0;
+  for (int q = 0; q < w; ++q) before += s_w[q];
+  return s_base + (unsigned long long)(before + x - n);
+}
+
+// One scan of the element-piece table: every live piece whose element is redone becomes its own root and goes on
+// the gluing list (gluing and root counting then visit the list, not the table); live pieces are counted and every
+// state word is checked (each piece present at most once). Workgroup b (256 threads) scans the slots of segment b,
+// [b len, (b + 1) len), and lists its pieces in the same range of the list, seg[b] of them: no global cursor, and
+// the later passes give segment b to workgroup b. The segment length grows with the table (at least 256 slots, at
+// most 4,096 segments), which bounds the workgroups' statistics atomics.
+__global__ __launch_bounds__(256) void k_parent_init(ShapeArgs a, int* list, int* seg, unsigned len) {
+  __shared__ unsigned long long s_n;
+  if (threadIdx.x == 0) s_n = 0;
+  __syncthreads();
+  unsigned long long nodes = 0;
+  const unsigned base = blockIdx.x * len;  // the table holds a whole number of segments
+  for (unsigned run = 0; run < len; run += 256) {
+    const unsigned s = base + run + threadIdx.x;
+    const NodeRec r = a.N.rec[s];
+    const int st = r.key == EMPTY_KEY ? 0 : r.st;
+    if (st < 0 || st >= 2 * NODE_UNIT) atomicOr(a.status, ST_INTERNAL);
+    const bool live = node_live(st);
+    nodes += live ? 1 : 0;
+    const bool take = live && node_touched(a, r.key);
+    if (take) a.N.rec[s].parent = (int)s;
+    const unsigned long long pos = block_append(take ? 1 : 0, &s_n);
+    if (take) list[base + pos] = (int)s;
+    __syncthreads();  // block_append's shared words are rewritten by the next run
+  }
+  if (threadIdx.x == 0) seg[blockIdx.x] = (int)s_n;
+  __shared__ unsigned long long s_nodes;
+  if (threadIdx.x == 0) s_nodes = 0;
+  __syncthreads();
+  if (nodes) atomicAdd(&s_nodes, nodes);
+  __syncthreads();
+  if (threadIdx.x == 0 && s_nodes) stat_add(a, C_NODES, s_nodes);
 }
 
 // pieces an incremental update took out and did not put back with the same gluing bits, or added new: their
@@ -158,17 +204,15 @@ __global__ void k_clear_touched_b0(const unsigned char* touch, int* b0, size_t n
 // glues back across the same mesh face (both sides must agree), and unite them.
 // Every gluing bit is matched from the tet with the smaller id only (one lookup and one union per glued pair); the
 // symmetry of the records is checked by counting: the bits set must be twice the pairs matched.
-__global__ void k_glue(ShapeArgs a) {
-  const unsigned cap = a.N.mask + 1;
+__global__ void k_glue(ShapeArgs a, const int* list, const int* seg, unsigned len) {
+  const int n = seg[blockIdx.x];
   unsigned long long bits = 0, pairs = 0;
-  for (unsigned s = blockIdx.x * blockDim.x + threadIdx.x; s < cap; s += gridDim.x * blockDim.x) {
+  for (int k = threadIdx.x; k < n; k += blockDim.x) {
+    const int s = list[(size_t)blockIdx.x * len + k];
     const NodeRec r = a.N.rec[s];
     const unsigned long long key = r.key;
-    if (key == EMPTY_KEY) continue;
-    const int st = r.st;
-    if (!node_live(st)) continue;
-    int g = node_glue_bits(st);
-    if (!g || !node_touched(a, key)) continue;
+    int g = node_glue_bits(r.st);
+    if (!g) continue;
     bits += __popc(g);
     const long long gt = (long long)(key & 0xffffffffull);
     const ShapeDesc& sd = a.shapes[shape_of_tet(a.shapes, a.nshapes, gt)];
@@ -188,7 +232,7 @@ __global__ void k_glue(ShapeArgs a) {
         continue;
       }
       ++pairs;
-      uf_union(a.N.rec, (int)s, s2);
+      uf_union(a.N.rec, s, s2);
     }
   }
   __shared__ unsigned long long s_sum[2];
@@ -201,31 +245,22 @@ __global__ void k_glue(ShapeArgs a) {
   if (threadIdx.x == 0 && s_sum[1]) stat_add(a, C_GLUE_PAIRS, s_sum[1]);
 }
 
-__global__ void k_count_roots(ShapeArgs a, int* cell_b0, int* face_b0, int* edge_b0) {
-  const unsigned cap = a.N.mask + 1;
-  unsigned long long nodes = 0;
+__global__ void k_count_roots(ShapeArgs a, const int* list, const int* seg, unsigned len, int* cell_b0,
+                              int* face_b0, int* edge_b0) {
+  const int n = seg[blockIdx.x];
   if (blockIdx.x == 0 && threadIdx.x == 0 && stat_sum(a, C_GLUE_BITS) != 2 * stat_sum(a, C_GLUE_PAIRS))
     atomicOr(a.status, ST_INTERNAL);  // a gluing bit without its counterpart
-  for (unsigned s = blockIdx.x * blockDim.x + threadIdx.x; s < cap; s += gridDim.x * blockDim.x) {
+  for (int k = threadIdx.x; k < n; k += blockDim.x) {
+    const int s = list[(size_t)blockIdx.x * len + k];
     const NodeRec r = a.N.rec[s];
+    if (r.parent != s) continue;  // one root per component
     const unsigned long long key = r.key;
-    const int st = key == EMPTY_KEY ? 0 : r.st;
-    if (st < 0 || st >= 2 * NODE_UNIT) atomicOr(a.status, ST_INTERNAL);  // every piece is present at most once
-    if (!node_live(st)) continue;
-    ++nodes;
-    if (!node_touched(a, key) || r.parent != (int)s) continue;  // one root per component
-    int kind = (int)(key >> 62);
-    int elem = (int)((key >> 32) & 0x3fffffffull);
+    const int kind = (int)(key >> 62);
+    const int elem = (int)((key >> 32) & 0x3fffffffull);
     if (kind == 1) atomicAdd(&cell_b0[elem], 1);
     else if (kind == 2) atomicAdd(&face_b0[elem], 1);
     else atomicAdd(&edge_b0[elem], 1);
   }
-  __shared__ unsigned long long s_nodes;
-  if (threadIdx.x == 0) s_nodes = 0;
-  __syncthreads();
-  if (nodes) atomicAdd(&s_nodes, nodes);
-  __syncthreads();
-  if (threadIdx.x == 0 && s_nodes) stat_add(a, C_NODES, s_nodes);
 }
 
 hipError_t launch_clear_touched_b0(const unsigned char* touch, int* b0, size_t n, hipStream_t s) {
@@ -237,17 +272,22 @@ hipError_t launch_clear_touched_b0(const unsigned char* touch, int* b0, size_t n
 // scans that end in a per-workgroup reduction run on a grid of at most 4096 workgroups (16 per compute unit)
 static int scan_grid(size_t n) { return std::min(grid_for(n, 256), 4096); }
 
-hipError_t launch_glue(const ShapeArgs& a, hipStream_t s) {
-  size_t cap = (size_t)a.N.mask + 1;
-  hipLaunchKernelGGL(k_parent_init, dim3(grid_for(cap, 256)), dim3(256), 0, s, a);
-  hipLaunchKernelGGL(k_glue, dim3(scan_grid(cap)), dim3(256), 0, s, a);
+// segment length of the gluing list: a power of two, at least 256 slots and at most 4,096 segments
+static unsigned glue_seg_len(size_t cap) { return (unsigned)std::max<size_t>(256, cap / 4096); }
+
+hipError_t launch_glue(const ShapeArgs& a, int* list, int* seg, hipStream_t s) {
+  const size_t cap = (size_t)a.N.mask + 1;
+  const unsigned len = glue_seg_len(cap);
+  hipLaunchKernelGGL(k_parent_init, dim3(cap / len), dim3(256), 0, s, a, list, seg, len);
+  hipLaunchKernelGGL(k_glue, dim3(cap / len), dim3(256), 0, s, a, (const int*)list, (const int*)seg, len);
   return hipGetLastError();
 }
 
-hipError_t launch_count_roots(const ShapeArgs& a, int* cell_b0, int* face_b0, int* edge_b0,
-                              hipStream_t s) {
-  size_t cap = (size_t)a.N.mask + 1;
-  hipLaunchKernelGGL(k_count_roots, dim3(scan_grid(cap)), dim3(256), 0, s, a, cell_b0, face_b0, edge_b0);
+hipError_t launch_count_roots(const ShapeArgs& a, const int* list, const int* seg, int* cell_b0, int* face_b0,
+                              int* edge_b0, hipStream_t s) {
+  const size_t cap = (size_t)a.N.mask + 1;
+  const unsigned len = glue_seg_len(cap);
+  hipLaunchKernelGGL(k_count_roots, dim3(cap / len), dim3(256), 0, s, a, list, seg, len, cell_b0, face_b0, edge_b0);
   return hipGetLastError();
 }
 
@@ -255,29 +295,6 @@ hipError_t launch_count_roots(const ShapeArgs& a, int* cell_b0, int* face_b0, in
 // element lists: compact the live entries of a table (any order), sort exactly those by key, then turn the
 // fractional sums into integers
 // ---------------------------------------------------------------------------------------------------------------
-// Output position of a thread's n items: exclusive prefix within the 256-thread block, plus the block's base from
-// one global atomic per block (a wave-level atomic on one address for every wave of a large table serialises).
-__device__ inline unsigned long long block_append(int n, unsigned long long* count) {
-  __shared__ int s_w[4];
-  __shared__ unsigned long long s_base;
-  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  int x = n;
-  for (int off = 1; off < 64; off <<= 1) {
-    const int y = __shfl_up(x, off);
-    if (lane >= off) x += y;
-  }
-  if (lane == 63) s_w[w] = x;
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    const int tot = s_w[0] + s_w[1] + s_w[2] + s_w[3];
-    s_base = tot ? atomicAdd(count, (unsigned long long)tot) : 0ull;
-  }
-  __syncthreads();
-  int before = 0;
-  for (int q = 0; q < w; ++q) before += s_w[q];
-  return s_base + (unsigned long long)(before + x - n);
-}
-
 // Each workgroup takes cpt runs of 256 consecutive slots (lane-strided, so every load is coalesced); cpt grows with
 // the table from 1 (small tables: enough workgroups to cover the latency) to 16 (one global atomic per 4,096 slots).
 static unsigned compact_cpt(size_t cap) {

@@ -159,7 +159,7 @@ struct DeviceState {
   int def_cap = 0, piece_cap = 0, term_cap = 0, list_cap = 0;
   DBuf site, status, cell_chi, cell_geo, cell_np, cell_b0;
   DBuf fkeys, face_chi, face_np, face_b0, ekeys, edge_chi, edge_np, edge_len, edge_b0, qkeys, rpv_cnt;
-  DBuf nodes, glist, gseg, deferred, deferred2, dlist, pieces, terms, counters, tetU, slow, touch, removed;
+  DBuf nodes, glist, gseg, clist, cseg, deferred, deferred2, dlist, pieces, terms, counters, tetU, slow, touch, removed;
   int waves = 0;
 
   unsigned long long* cnt() const { return counters.as<unsigned long long>(); }
@@ -222,6 +222,8 @@ struct DeviceState {
       tetU.alloc(8 * (size_t)std::max<long long>(nt, 1));
       touch.alloc(touch_words() * 4);
       removed.alloc(4 * (size_t)capN);
+      clist.alloc(sizeof(int) * (size_t)capN);  // the live cell pieces, for the rounds' selection scans
+      cseg.alloc(sizeof(int) * (size_t)capN / 256);
     }
     waves = slow_waves(nt);
     slow.alloc(slow_scratch_bytes(waves));
@@ -315,7 +317,7 @@ struct DeviceState {
       hip_check(launch_fill_multi(L, s), "fill");
     }
     hip_check(launch_zero_stats(stat(), C_NODES, 1, C_GLUE_BITS, 2, s), "fill");
-    hip_check(launch_glue(a, glist.as<int>(), gseg.as<int>(), s), "glue");
+    hip_check(launch_glue(a, glist.as<int>(), gseg.as<int>(), clist.as<int>(), cseg.as<int>(), s), "glue");
     hip_check(launch_count_roots(a, glist.as<int>(), gseg.as<int>(), cell_b0.as<int>(), face_b0.as<int>(),
                                  edge_b0.as<int>(), s),
               "roots");
@@ -1303,6 +1305,10 @@ static bool session_init(rpd_session* S, const rpd_sites* sites, const rpd_sites
   r.order = S->order.as<int>();
   r.items = S->items.as<int2>();
   r.blk = m->blk.as<int>();
+  r.clist = D.clist.as<int>();
+  r.cseg = D.cseg.as<int>();
+  r.clen = glue_segment_length((size_t)D.capN);
+  r.cnseg = (int)((size_t)D.capN / r.clen);
   r.nitems = ints + SI_NITEMS;
   r.round = ints + SI_ROUND;
   r.ns_cur = ints + SI_NS;

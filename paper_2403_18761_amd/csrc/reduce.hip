@@ -146,9 +146,10 @@ __device__ inline unsigned long long block_append(int n, unsigned long long* cou
 // [b len, (b + 1) len), and lists its pieces in the same range of the list, seg[b] of them: no global cursor, and
 // the later passes give segment b to workgroup b. The segment length grows with the table (at least 256 slots, at
 // most 4,096 segments), which bounds the workgroups' statistics atomics.
-__global__ __launch_bounds__(256) void k_parent_init(ShapeArgs a, int* list, int* seg, unsigned len) {
-  __shared__ unsigned long long s_n;
-  if (threadIdx.x == 0) s_n = 0;
+__global__ __launch_bounds__(256) void k_parent_init(ShapeArgs a, int* list, int* seg, int* clist, int* cseg,
+                                                     unsigned len) {
+  __shared__ unsigned long long s_n, s_nc;
+  if (threadIdx.x == 0) s_n = s_nc = 0;
   __syncthreads();
   unsigned long long nodes = 0;
   const unsigned base = blockIdx.x * len;  // the table holds a whole number of segments
@@ -163,9 +164,18 @@ __global__ __launch_bounds__(256) void k_parent_init(ShapeArgs a, int* list, int
     if (take) a.N.rec[s].parent = (int)s;
     const unsigned long long pos = block_append(take ? 1 : 0, &s_n);
     if (take) list[base + pos] = (int)s;
-    __syncthreads();  // block_append's shared words are rewritten by the next run
+    __syncthreads();  // block_append's shared words are rewritten by the next call
+    if (clist) {  // every live cell piece, for the next incremental round's selection scans
+      const bool cell = live && node_kind(r.key) == 1;
+      const unsigned long long cpos = block_append(cell ? 1 : 0, &s_nc);
+      if (cell) clist[base + cpos] = (int)s;
+      __syncthreads();
+    }
   }
-  if (threadIdx.x == 0) seg[blockIdx.x] = (int)s_n;
+  if (threadIdx.x == 0) {
+    seg[blockIdx.x] = (int)s_n;
+    if (cseg) cseg[blockIdx.x] = (int)s_nc;
+  }
   __shared__ unsigned long long s_nodes;
   if (threadIdx.x == 0) s_nodes = 0;
   __syncthreads();
@@ -275,10 +285,12 @@ static int scan_grid(size_t n) { return std::min(grid_for(n, 256), 4096); }
 // segment length of the gluing list: a power of two, at least 256 slots and at most 4,096 segments
 static unsigned glue_seg_len(size_t cap) { return (unsigned)std::max<size_t>(256, cap / 4096); }
 
-hipError_t launch_glue(const ShapeArgs& a, int* list, int* seg, hipStream_t s) {
+unsigned glue_segment_length(size_t cap) { return glue_seg_len(cap); }
+
+hipError_t launch_glue(const ShapeArgs& a, int* list, int* seg, int* clist, int* cseg, hipStream_t s) {
   const size_t cap = (size_t)a.N.mask + 1;
   const unsigned len = glue_seg_len(cap);
-  hipLaunchKernelGGL(k_parent_init, dim3(cap / len), dim3(256), 0, s, a, list, seg, len);
+  hipLaunchKernelGGL(k_parent_init, dim3(cap / len), dim3(256), 0, s, a, list, seg, clist, cseg, len);
   hipLaunchKernelGGL(k_glue, dim3(cap / len), dim3(256), 0, s, a, (const int*)list, (const int*)seg, len);
   return hipGetLastError();
 }

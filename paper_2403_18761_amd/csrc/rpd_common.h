@@ -205,7 +205,11 @@ struct RoundState {
   unsigned long long* dirty;  // [nblk] per block, the mask of its dirty tets (bit k: the block's tet k)
   const int* order;           // [nblk] blocks by their time in the initial build, heaviest first (scan order)
   const int* blk;             // [nblk + 1] first tet of every block
-  int2* items;                // [4 nblk] dirty (shape 0, block part) items, in about that order
+  int2* items;                // [8 nblk] dirty (shape 0 or 1 and tet mask, block part) items, in about that order
+  const int* clist;           // the live cell pieces' slots, per segment of clen table slots (the gluing pass
+  const int* cseg;            // writes them): cseg[b] of them at clist[b clen]
+  unsigned clen;
+  int cnseg;
   int* nitems;
   int* round;
   int* ns_cur;                // sites in use

@@ -36,8 +36,10 @@ hipError_t launch_fill_i32(int* p, int v, size_t n, hipStream_t s);
 // zero counters [c0, c0 + n0) and [c1, c1 + n1) in every spread copy of the statistics
 hipError_t launch_zero_stats(unsigned long long* stats, int c0, int n0, int c1, int n1, hipStream_t s);
 // union-find over the live element pieces (with a.touch_* set: only the pieces of touched elements); list [cap N]
-// and seg [cap N / 256] receive those pieces' slots per segment of the table (at least 256 slots)
-hipError_t launch_glue(const ShapeArgs& a, int* list, int* seg, hipStream_t s);
+// and seg [cap N / 256] receive those pieces' slots per segment of the table (glue_segment_length slots); clist and
+// cseg, if not null, the same for every live cell piece
+hipError_t launch_glue(const ShapeArgs& a, int* list, int* seg, int* clist, int* cseg, hipStream_t s);
+unsigned glue_segment_length(size_t cap);
 hipError_t launch_clear_touched_b0(const unsigned char* touch, int* b0, size_t n, hipStream_t s);
 // elements of pieces an incremental update removed and did not put back are flagged as touched
 hipError_t launch_touch_removed(const ShapeArgs& a, hipStream_t s);

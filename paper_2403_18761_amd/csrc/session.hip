@@ -80,16 +80,16 @@ __global__ __launch_bounds__(256) void k_ref_tet(NodeTab N, RoundState r) {
   const int nsel = *r.nsel;
   for (int k = threadIdx.x; k < nsel; k += blockDim.x) s_ref[k] = ~0ull;
   __syncthreads();
-  const unsigned cap = N.mask + 1;
-  for (unsigned s = blockIdx.x * blockDim.x + threadIdx.x; s < cap; s += gridDim.x * blockDim.x) {
-    const NodeRec nr = N.rec[s];
-    const unsigned long long key = nr.key;
-    if (key == EMPTY_KEY || (key >> 62) != 1 || !node_live(nr.st)) continue;
-    int cell = (int)((key >> 32) & 0x3fffffff);
-    int k = r.selpos[cell];
-    if (k < 0) continue;
-    const unsigned t = (unsigned)(key & 0xffffffffull);
-    atomicMin(&s_ref[k], ((unsigned long long)(unsigned)r.perm[t] << 32) | t);
+  for (int b = blockIdx.x; b < r.cnseg; b += gridDim.x) {
+    const int n = r.cseg[b];
+    for (int j = threadIdx.x; j < n; j += blockDim.x) {
+      const unsigned long long key = N.rec[r.clist[(size_t)b * r.clen + j]].key;  // a live cell piece
+      int cell = (int)((key >> 32) & 0x3fffffff);
+      int k = r.selpos[cell];
+      if (k < 0) continue;
+      const unsigned t = (unsigned)(key & 0xffffffffull);
+      atomicMin(&s_ref[k], ((unsigned long long)(unsigned)r.perm[t] << 32) | t);
+    }
   }
   __syncthreads();
   for (int k = threadIdx.x; k < nsel; k += blockDim.x)
@@ -109,12 +109,17 @@ __global__ __launch_bounds__(256) void k_pick_tet(NodeTab N, const int* cell_b0,
   const int nsel = *r.nsel;
   for (int k = threadIdx.x; k < nsel; k += blockDim.x) s_best[k] = 0ull;
   __syncthreads();
-  const unsigned cap = N.mask + 1;
   const int round = *r.round;
-  for (unsigned s = blockIdx.x * blockDim.x + threadIdx.x; s < cap; s += gridDim.x * blockDim.x) {
+  for (int j = threadIdx.x, b = blockIdx.x; b < r.cnseg;) {  // the live cell pieces, segment by segment
+    if (j >= r.cseg[b]) {
+      j = threadIdx.x;
+      b += gridDim.x;
+      continue;
+    }
+    const int s = r.clist[(size_t)b * r.clen + j];
+    j += blockDim.x;
     const NodeRec nr = N.rec[s];
     const unsigned long long key = nr.key;
-    if (key == EMPTY_KEY || (key >> 62) != 1 || !node_live(nr.st)) continue;
     int cell = (int)((key >> 32) & 0x3fffffff);
     int k = r.selpos[cell];
     if (k < 0) continue;
@@ -124,7 +129,7 @@ __global__ __launch_bounds__(256) void k_pick_tet(NodeTab N, const int* cell_b0,
     if (r.mode ? bnd == 0 : r.tet_used[tc] != 0) continue;
     if (cell_b0[cell] > 1) {  // pick outside the component of the cell's piece in its smallest tet
       int rs = node_find(N, (key & ~0xffffffffull) | (unsigned)(r.ref[k] & 0xffffffffull));
-      if (rs >= 0 && uf_root(N.rec, rs) == uf_root(N.rec, (int)s)) continue;
+      if (rs >= 0 && uf_root(N.rec, rs) == uf_root(N.rec, s)) continue;
     }
     if (r.mode) {  // surface faces of tet t that the piece touches: the one furthest from the cell's centre
       const float4 c = site[cell];
@@ -355,8 +360,7 @@ hipError_t launch_round_front(const RoundState& r, const ShapeArgs& a, const int
                               const float4* tp, int nt, int nblk, hipStream_t s) {
   hipLaunchKernelGGL(k_round_begin, dim3(1), dim3(64), 0, s, r);
   hipLaunchKernelGGL(k_select, dim3(1), dim3(256), 0, s, r, a.cell_chi, a.cell_np, cell_b0);
-  const size_t cap = (size_t)a.N.mask + 1;
-  const int scan = std::min(gsz(cap), SCAN_BLOCKS);
+  const int scan = std::min(r.cnseg, SCAN_BLOCKS);
   hipLaunchKernelGGL(k_ref_tet, dim3(scan), dim3(256), sizeof(unsigned long long) * r.max_insert, s, a.N, r);
   hipLaunchKernelGGL(k_pick_tet, dim3(scan), dim3(256), sizeof(unsigned long long) * r.max_insert, s, a.N, cell_b0,
                      r, tp, a.site);

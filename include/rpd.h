@@ -274,7 +274,8 @@ void rpd_free(rpd_result* r);
 
 /* Autotuner for the batched FP32 path: runs rpd_build on these inputs once per launch shape (block of 64, 128 or 256
  * threads x clip budget 8, 16 or 28, each timed by HIP events over the clipping kernels, best of two after a warm-up),
- * writes the fastest into *best (a copy of *opts with block and clip_budget set) and caches it for the process under
+ * writes the fastest into *best (a copy of *opts with block and clip_budget set; the default 64 x 28 is kept unless
+ * another shape is more than 2% faster) and caches it for the process under
  * the bucket (floor log2 of the mean sites per shape, floor log2 of the mean tets per shape). Later rpd_build calls
  * whose block or clip_budget is 0 take the cached value of their bucket (else 64 and 28), and so does a session. Every launch shape gives
  * identical results; only the time differs. Synchronises. Errors as rpd_build; RPD_E_INVALID for RPD_FP64. */

@@ -414,11 +414,11 @@ __global__ __launch_bounds__(NT) void k_clip_fast(ShapeArgs a) {
   __shared__ int s_sid[SLMAX];
   __shared__ unsigned char s_cand[TB][KRAW];
   // the candidates' sort keys are dead before the clipping phase starts: they share storage with the polytopes
-  constexpr size_t XYZ_BYTES = sizeof(typename Coord4<T>::type) * VMAX * NT;
+  typedef typename StoreOf<T, Topo32, VMAX>::type PolyStore;
+  constexpr size_t XYZ_BYTES = PolyStore::coord_bytes(NT);
   constexpr size_t KEY_BYTES = sizeof(float) * TB * KRAW;
   __shared__ __attribute__((aligned(16))) unsigned char s_share[XYZ_BYTES > KEY_BYTES ? XYZ_BYTES : KEY_BYTES];
   float(*s_key)[KRAW] = reinterpret_cast<float(*)[KRAW]>(s_share);
-  typename Coord4<T>::type* s_xyz = reinterpret_cast<typename Coord4<T>::type*>(s_share);
   __shared__ int s_m[TB];
   static_assert(TB * KMAX < 32768, "piece offsets are 16-bit");
   __shared__ short s_off[TB + 1];
@@ -697,9 +697,7 @@ __global__ __launch_bounds__(NT) void k_clip_fast(ShapeArgs a) {
     const int ci = p - s_off[lo_];
     const int m = s_m[lt];
     Clipper<T, Topo32, unsigned, VMAX, false, RegTab> cl;
-    cl.st.c = s_xyz + tid;
-    cl.st.w = s_topo + tid;
-    cl.st.stride = NT;
+    cl.st.bind(s_share, s_topo, tid, NT);
     cl.tab.clear(0);
     cl.a = nullptr;  // only the exact predicates use it (not compiled into this kernel)
     cl.flags = a.flags;

@@ -406,6 +406,63 @@ struct Store {
   }
   __device__ typename Topo::W topo(int k) const { return w[(k & (VCAP - 1)) * stride]; }
   __device__ void set_topo(int k, typename Topo::W t) { w[(k & (VCAP - 1)) * stride] = t; }
+  __device__ static typename Topo::W with_F(typename Topo::W t, T) { return t; }  // F is stored with the coordinates
+  __device__ void bind(void* coords, typename Topo::W* topo_words, int lane, int nthreads) {
+    c = reinterpret_cast<typename Coord4<T>::type*>(coords) + lane;
+    w = topo_words + lane;
+    stride = nthreads;
+  }
+  static constexpr size_t coord_bytes(int nthreads) { return sizeof(typename Coord4<T>::type) * VCAP * nthreads; }
+};
+
+// The FP32 polytopes of the fast kernel in 16 bytes per vertex: x and y as a pair and z in separate [slot][lane]
+// planes, the topology word, and in its five free bits the vertex's error bound F rounded up to a power of two
+// between 2^-40 and 2^-10 (code 31: infinite, every test on the vertex goes to FP64). Rounding F up only makes the
+// FP32 filter more cautious, so every sign it certifies is still right.
+__device__ inline unsigned encode_F(float F) {
+  if (!(F <= 0x1p-10f)) return 31u;  // also infinite and NaN
+  if (F <= 0x1p-40f) return 0u;
+  const unsigned b = __float_as_uint(F);
+  const int e = (int)((b >> 23) & 255u) - 127;                 // F = 1.m x 2^e, normal here
+  return (unsigned)(((b & 0x7fffffu) ? e + 1 : e) + 40);        // ceil(log2 F) + 40, in [1, 30]
+}
+__device__ inline float decode_F(unsigned code) {
+  return code == 31u ? INFINITY : __uint_as_float((code + 87u) << 23);  // 2^(code - 40)
+}
+template <int VCAP>
+struct StoreP {
+  float2* xy;  // [VCAP][stride]
+  float* zz;   // [VCAP][stride]
+  unsigned* w;
+  int stride;
+  __device__ float4 get(int k) const {
+    const int o = (k & (VCAP - 1)) * stride;
+    const float2 p = xy[o];
+    return make_float4(p.x, p.y, zz[o], decode_F(w[o] >> 27));
+  }
+  __device__ void put(int k, float x, float y, float z, float) {  // F travels in the topology word (with_F)
+    const int o = (k & (VCAP - 1)) * stride;
+    xy[o] = make_float2(x, y);
+    zz[o] = z;
+  }
+  __device__ unsigned topo(int k) const { return w[(k & (VCAP - 1)) * stride]; }
+  __device__ void set_topo(int k, unsigned t) { w[(k & (VCAP - 1)) * stride] = t; }
+  __device__ static unsigned with_F(unsigned t, float F) { return (t & 0x07ffffffu) | (encode_F(F) << 27); }
+  __device__ void bind(void* coords, unsigned* topo_words, int lane, int nthreads) {
+    xy = reinterpret_cast<float2*>(coords) + lane;
+    zz = reinterpret_cast<float*>(reinterpret_cast<float2*>(coords) + VCAP * nthreads) + lane;
+    w = topo_words + lane;
+    stride = nthreads;
+  }
+  static constexpr size_t coord_bytes(int nthreads) { return (sizeof(float2) + sizeof(float)) * VCAP * nthreads; }
+};
+template <typename T, typename Topo, int VCAP>
+struct StoreOf {
+  typedef Store<T, Topo, VCAP> type;
+};
+template <int VCAP>
+struct StoreOf<float, Topo32, VCAP> {  // Topo32 leaves bits 27..31 free
+  typedef StoreP<VCAP> type;
 };
 
 __device__ inline int ctz_mask(unsigned m) { return __builtin_ctz(m); }
@@ -586,7 +643,7 @@ template <typename T, typename Topo, typename Mask, int VCAP, bool EXACT, typena
 struct Clipper {
   typedef typename Topo::W W;
   static_assert((VCAP & (VCAP - 1)) == 0, "vertex capacity must be a power of two");
-  Store<T, Topo, VCAP> st;
+  typename StoreOf<T, Topo, VCAP>::type st;
   Tab tab;  // per plane id: 0 or (slot + 1); all zero between operations
   Mask live;
   TetEnv env;
@@ -605,8 +662,9 @@ struct Clipper {
       // the three faces through vertex v (all but face v), ascending; across the edge formed by two of them
       // lies the tet vertex with the third one's index
       const int p0 = (v == 0) ? 1 : 0, p1 = (v <= 1) ? 2 : 1, p2 = (v <= 2) ? 3 : 2;
-      st.put(v, x, y, z, exact_point_F(x, y, z));
-      st.set_topo(v, Topo::make(p0, p1, p2, p0, p1, p2));
+      const T F = exact_point_F(x, y, z);
+      st.put(v, x, y, z, F);
+      st.set_topo(v, st.with_F(Topo::make(p0, p1, p2, p0, p1, p2), F));
     }
     live = (Mask)15;
   }
@@ -682,7 +740,7 @@ struct Clipper {
         int pa = Topo::plane(w, (e + 1) % 3), pb = Topo::plane(w, (e + 2) % 3);
         T x, y, z, F;
         make_vertex(env.planeT<T>(pa), env.planeT<T>(pb), P, x, y, z, F);
-        W nw = Topo::make(pa, pb, q, 0, 0, k);
+        W nw = st.with_F(Topo::make(pa, pb, q, 0, 0, k), F);
         st.put(s, x, y, z, F);
         pair_up(pa, s, nw, 1);  // edge (pa, q) is opposite pb (position 1)
         pair_up(pb, s, nw, 0);  // edge (pb, q) is opposite pa (position 0)

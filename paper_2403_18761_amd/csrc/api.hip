@@ -400,7 +400,7 @@ static bool collect(DeviceState& D, const std::vector<ShapeDesc>& hd, const Shap
   const size_t nf = hc[NCOUNTERS + 0], ne = hc[NCOUNTERS + 1], nq = hc[NCOUNTERS + 2];
 
   // one device buffer for everything that goes to the host: RPVs (int4) first, then the int32 and double arrays
-  const size_t n_int = 2 * (size_t)ns + 4 * nf + 5 * ne;
+  const size_t n_int = 2 * (size_t)ns + 4 * nf + 5 * ne + 3 * (size_t)nsh;
   const size_t off_int = 16 * nq, off_dbl = (off_int + 4 * n_int + 7) / 8 * 8;
   const size_t out_bytes = off_dbl + 8 * (4 * (size_t)ns + 2 * ne);
   DBuf out(std::max<size_t>(out_bytes, 16));
@@ -413,6 +413,7 @@ static bool collect(DeviceState& D, const std::vector<ShapeDesc>& hd, const Shap
   int* e_keys = f_b0 + nf;
   int* e_chi = e_keys + 3 * ne;
   int* e_b0 = e_chi + ne;
+  int* l_start = e_b0 + ne;  // [3][nsh] first face, edge and RPV of every shape (batches)
   double* c_vol = (double*)(ob + off_dbl);
   double* c_cen = c_vol + ns;
   double* e_len = c_cen + 3 * (size_t)ns;
@@ -460,6 +461,21 @@ static bool collect(DeviceState& D, const std::vector<ShapeDesc>& hd, const Shap
                               kC.as<unsigned long long>(), vA.as<int>(), vB.as<int>(), tmp.p, tmpb, (int4*)ob, s),
               "sort rpv");
   }
+  if (nsh > 1) {  // per-shape runs of the lists, and keys in each shape's own site ids
+    ListsOut L;
+    L.keys[0] = f_keys;
+    L.keys[1] = e_keys;
+    L.keys[2] = (int*)ob;
+    L.n[0] = (int)nf;
+    L.n[1] = (int)ne;
+    L.n[2] = (int)nq;
+    L.width[0] = 2;
+    L.width[1] = 3;
+    L.width[2] = 4;
+    for (int y = 0; y < 3; ++y) L.start[y] = l_start + (size_t)y * nsh;
+    hip_check(launch_fill_i32(l_start, -1, 3 * (size_t)nsh, s), "fill");
+    hip_check(launch_localize_lists(L, dshapes, nsh, s), "localize lists");
+  }
   if (ns > 0)
     hip_check(launch_finalize_cells(ns, D.cell_chi.as<long long>(), D.cell_geo.as<long long>(), D.cell_np.as<int>(),
                                     D.cell_b0.as<int>(), dshapes, nsh, c_chi, c_b0, c_vol, c_cen, D.status.as<int>(),
@@ -490,11 +506,24 @@ static bool collect(DeviceState& D, const std::vector<ShapeDesc>& hd, const Shap
   const double* all_cen = all_vol + ns;
   const double* all_elen = all_cen + 3 * (size_t)ns;
   const double* all_ealpha = all_elen + ne;
-  // ---- split per shape (element lists are sorted by batch-global keys, so each shape is one contiguous run)
-  size_t fpos = 0, epos = 0, qpos = 0;
+  // ---- split per shape (element lists are sorted by batch-global keys, so each shape is one contiguous run; the
+  //      device found the runs and turned the keys into shape-local site ids)
+  std::vector<size_t> run[3];
+  {
+    const size_t tot[3] = {nf, ne, nq};
+    const int* starts = all_eb0 + ne;
+    for (int y = 0; y < 3; ++y) {
+      run[y].assign((size_t)nsh + 1, tot[y]);
+      if (nsh == 1) run[y][0] = 0;
+      for (int k = nsh - 1; k >= 0 && nsh > 1; --k) {
+        const int v = starts[(size_t)y * nsh + k];
+        run[y][k] = v >= 0 ? (size_t)v : run[y][k + 1];  // a shape without elements: an empty run
+      }
+    }
+  }
   for (int k = 0; k < nsh; ++k) {
     ShapeOut& out = outs[k];
-    const int off = hd[k].site_off, n = hd[k].ns, end = off + n;
+    const int off = hd[k].site_off, n = hd[k].ns;
     out.ns = n;
     out.hold = host;
     out.cell_chi.view(all_cchi + off, n);
@@ -504,32 +533,17 @@ static bool collect(DeviceState& D, const std::vector<ShapeDesc>& hd, const Shap
     std::vector<int32_t>& ck = out.cell_keys.owned();
     ck.resize(n);
     std::iota(ck.begin(), ck.end(), 0);
-    // element lists: one contiguous run per shape; keys shifted to the shape's own site ids
-    size_t fend = fpos, eend = epos, qend = qpos;
-    while (fend < nf && all_fk[2 * fend] < end) ++fend;
-    while (eend < ne && all_ek[3 * eend] < end) ++eend;
-    while (qend < nq && all_rpv[4 * qend] < end) ++qend;
-    auto shifted = [off](Arr<int32_t>& dst, const int* src, size_t n) {
-      if (off == 0) {  // the first shape's ids are its own
-        dst.view(src, n);
-        return;
-      }
-      std::vector<int32_t>& d = dst.owned();
-      d.resize(n);
-      for (size_t k = 0; k < n; ++k) d[k] = src[k] - off;
-    };
-    shifted(out.face_keys, all_fk + 2 * fpos, 2 * (fend - fpos));
+    const size_t fpos = run[0][k], fend = run[0][k + 1], epos = run[1][k], eend = run[1][k + 1], qpos = run[2][k],
+                 qend = run[2][k + 1];
+    out.face_keys.view(all_fk + 2 * fpos, 2 * (fend - fpos));
     out.face_chi.view(all_fchi + fpos, fend - fpos);
     out.face_b0.view(all_fb0 + fpos, fend - fpos);
-    shifted(out.edge_keys, all_ek + 3 * epos, 3 * (eend - epos));
+    out.edge_keys.view(all_ek + 3 * epos, 3 * (eend - epos));
     out.edge_chi.view(all_echi + epos, eend - epos);
     out.edge_b0.view(all_eb0 + epos, eend - epos);
     out.edge_len.view(all_elen + epos, eend - epos);
     out.edge_alpha.view(all_ealpha + epos, eend - epos);
-    shifted(out.rpv_keys, all_rpv + 4 * qpos, 4 * (qend - qpos));
-    fpos = fend;
-    epos = eend;
-    qpos = qend;
+    out.rpv_keys.view(all_rpv + 4 * qpos, 4 * (qend - qpos));
     out.pc_t.clear();
     out.pc_i.clear();
     out.pc_geo.clear();
@@ -726,29 +740,56 @@ static void learn_costs(const std::vector<int2>& items, const unsigned* ticks,
   }
 }
 
-static void upload_sites(DeviceState& D, const rpd_sites* sites, const std::vector<ShapeDesc>& hd, bool dev,
-                         hipStream_t s) {
-  std::vector<DBuf> raws;
+// What the site upload leaves in flight: kept by the caller until its stream has been synchronised.
+struct SiteUpload {
+  DBuf raw, dsrc;
+  std::vector<SiteSrc> src;
+};
+
+static SiteUpload upload_sites(DeviceState& D, const rpd_sites* sites, const std::vector<ShapeDesc>& hd, bool dev,
+                               hipStream_t s) {
+  // host arrays are staged into one device buffer; then one launch validates and packs every shape's sites
+  SiteUpload u;
+  size_t total = 0;
+  int max_n = 0;
+  for (size_t k = 0; k < hd.size(); ++k) {
+    total += (size_t)sites[k].n_sites;
+    max_n = std::max(max_n, sites[k].n_sites);
+  }
+  DBuf& raw = u.raw;
+  if (!dev) raw.alloc(sizeof(float) * 4 * total);
+  std::vector<SiteSrc>& src = u.src;
+  src.resize(hd.size());
+  size_t pos = 0;
   for (size_t k = 0; k < hd.size(); ++k) {
     const rpd_sites* sp = &sites[k];
     const int n = sp->n_sites;
-    const float *sx = sp->sx, *sy = sp->sy, *sz = sp->sz, *sr = sp->sr;
+    SiteSrc& d = src[k];
+    d.x = sp->sx;
+    d.y = sp->sy;
+    d.z = sp->sz;
+    d.r = sp->sr;
+    d.n = n;
+    d.off = hd[k].site_off;
     if (!dev) {
-      raws.emplace_back(sizeof(float) * 4 * (size_t)n);
-      float* r = raws.back().as<float>();
+      float* r = raw.as<float>() + pos;
       hip_check(hipMemcpyAsync(r, sp->sx, sizeof(float) * n, hipMemcpyHostToDevice, s), "upload");
       hip_check(hipMemcpyAsync(r + n, sp->sy, sizeof(float) * n, hipMemcpyHostToDevice, s), "upload");
       hip_check(hipMemcpyAsync(r + 2 * (size_t)n, sp->sz, sizeof(float) * n, hipMemcpyHostToDevice, s), "upload");
       hip_check(hipMemcpyAsync(r + 3 * (size_t)n, sp->sr, sizeof(float) * n, hipMemcpyHostToDevice, s), "upload");
-      sx = r;
-      sy = r + n;
-      sz = r + 2 * (size_t)n;
-      sr = r + 3 * (size_t)n;
+      d.x = r;
+      d.y = r + n;
+      d.z = r + 2 * (size_t)n;
+      d.r = r + 3 * (size_t)n;
+      pos += 4 * (size_t)n;
     }
-    hip_check(launch_validate_sites(sx, sy, sz, sr, n, D.site.as<float4>() + hd[k].site_off, D.status.as<int>(), s),
-              "validate sites");
   }
-  if (!dev) hip_check(hipStreamSynchronize(s), "synchronize");  // the staging buffers are released next
+  u.dsrc.alloc(sizeof(SiteSrc) * std::max<size_t>(src.size(), 1));
+  hip_check(hipMemcpyAsync(u.dsrc.p, src.data(), sizeof(SiteSrc) * src.size(), hipMemcpyHostToDevice, s), "upload");
+  hip_check(launch_validate_sites_multi(u.dsrc.as<SiteSrc>(), (int)src.size(), max_n, D.site.as<float4>(),
+                                        D.status.as<int>(), s),
+            "validate sites");
+  return u;
 }
 
 // All shapes of one call, one attempt. Returns false if a table ran out of room (caller retries larger).
@@ -776,7 +817,7 @@ static bool run_batch(const rpd_mesh* const* meshes, const rpd_sites* sites, int
   DeviceState D;
   D.alloc(nsh, (int)ns_tot, nt_tot, scale, (o.flags & RPD_KEEP_PIECES) != 0, false);
   D.clear(s);
-  upload_sites(D, sites, hd, dev, s);
+  const SiteUpload su = upload_sites(D, sites, hd, dev, s);  // released after the stream is drained (below)
   const int kmax = o.clip_budget > 0 ? std::min(o.clip_budget, KMAX) : KMAX;
   ShapeArgs a = D.args(dshapes.as<ShapeDesc>(), ditems.as<int2>(), (int)items.size(), o.flags, kmax);
   HostPinned ticks_host(sizeof(unsigned) * items.size() + 16);  // pinned: the copy does not stall the host
@@ -1202,7 +1243,11 @@ static bool session_init(rpd_session* S, const rpd_sites* sites, const rpd_sites
   D.alloc(1, S->max_sites, nt, scale, false, true);
   D.clear(s);
   std::vector<ShapeDesc> hd{S->hd};
-  upload_sites(D, sites, hd, dev, s);
+  const SiteUpload su = upload_sites(D, sites, hd, dev, s);
+  struct DrainOnExit {  // the upload's buffers are released only after the stream has drained
+    hipStream_t s;
+    ~DrainOnExit() { (void)hipStreamSynchronize(s); }
+  } drain{s};
   const size_t nslots = S->mode ? 4 * (size_t)nt : (size_t)nt;
   S->tet_used.alloc(sizeof(int) * nslots);
   hip_check(launch_fill_i32(S->tet_used.as<int>(), S->mode ? 1 : 0, nslots, s), "fill");

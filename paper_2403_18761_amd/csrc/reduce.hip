@@ -640,5 +640,52 @@ hipError_t launch_validate_sites(const float* sx, const float* sy, const float* 
   hipLaunchKernelGGL(k_validate_sites, dim3(grid_for(ns, 256)), dim3(256), 0, s, sx, sy, sz, sr, ns, site, status);
   return hipGetLastError();
 }
+// every shape of a call in one launch: shape blockIdx.y
+__global__ void k_validate_sites_multi(const SiteSrc* src, float4* site, int* status) {
+  const SiteSrc d = src[blockIdx.y];
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < d.n; i += gridDim.x * blockDim.x) {
+    float x = d.x[i], y = d.y[i], z = d.z[i], r = d.r[i];
+    if (!on_grid(x, 1.0f) || !on_grid(y, 1.0f) || !on_grid(z, 1.0f) || !on_grid(r, 2.0f) || r < 0.0f)
+      atomicOr(status, ST_INVALID);
+    site[(size_t)d.off + i] = make_float4(x, y, z, r);
+  }
+}
+hipError_t launch_validate_sites_multi(const SiteSrc* src, int nsrc, int max_n, float4* site, int* status,
+                                       hipStream_t s) {
+  if (nsrc <= 0 || max_n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_validate_sites_multi, dim3(std::min(grid_for(max_n, 256), 1024), nsrc), dim3(256), 0, s, src,
+                     site, status);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------------------------------------------
+// per-shape runs of the sorted element lists of a batch (elements sorted by batch-global keys: one contiguous run
+// per shape), then the keys turned into each shape's own site ids. List y of the launch: faces (2 ids per element),
+// edges (3), RPVs (4); start[y][shape] is the first element of the shape, or stays -1 when it has none.
+// ---------------------------------------------------------------------------------------------------------------
+__global__ void k_list_starts(ListsOut L, const ShapeDesc* shapes, int nshapes) {
+  const int y = blockIdx.y, w = L.width[y], n = L.n[y];
+  const int* keys = L.keys[y];
+  for (int q = blockIdx.x * blockDim.x + threadIdx.x; q < n; q += gridDim.x * blockDim.x) {
+    const int sh = shape_of_site(shapes, nshapes, keys[(size_t)w * q]);
+    if (q == 0 || shape_of_site(shapes, nshapes, keys[(size_t)w * (q - 1)]) != sh) L.start[y][sh] = q;
+  }
+}
+__global__ void k_localize(ListsOut L, const ShapeDesc* shapes, int nshapes) {
+  const int y = blockIdx.y, w = L.width[y], n = L.n[y];
+  int* keys = L.keys[y];
+  for (int q = blockIdx.x * blockDim.x + threadIdx.x; q < n; q += gridDim.x * blockDim.x) {
+    const int off = shapes[shape_of_site(shapes, nshapes, keys[(size_t)w * q])].site_off;
+    for (int c = 0; c < w; ++c) keys[(size_t)w * q + c] -= off;
+  }
+}
+hipError_t launch_localize_lists(const ListsOut& L, const ShapeDesc* shapes, int nshapes, hipStream_t s) {
+  const int nmax = std::max(L.n[0], std::max(L.n[1], L.n[2]));
+  if (nmax <= 0) return hipSuccess;
+  const dim3 grid(std::min(grid_for(nmax, 256), 2048), 3);
+  hipLaunchKernelGGL(k_list_starts, grid, dim3(256), 0, s, L, shapes, nshapes);
+  hipLaunchKernelGGL(k_localize, grid, dim3(256), 0, s, L, shapes, nshapes);
+  return hipGetLastError();
+}
 
 }  // namespace rpd

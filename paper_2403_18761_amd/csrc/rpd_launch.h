@@ -79,6 +79,22 @@ hipError_t launch_sort_rpv(const int4* rpv, int n, unsigned long long* ka, unsig
                            hipStream_t s);
 hipError_t launch_validate_sites(const float* sx, const float* sy, const float* sz, const float* sr, int ns,
                                  float4* site, int* status, hipStream_t s);
+// the sites of every shape of a call in one launch (src: device array of nsrc records, max_n = the largest n)
+struct SiteSrc {
+  const float *x, *y, *z, *r;
+  int n, off;
+};
+hipError_t launch_validate_sites_multi(const SiteSrc* src, int nsrc, int max_n, float4* site, int* status,
+                                       hipStream_t s);
+// the three sorted element lists of a batch (faces, edges, RPVs as int keys of width 2, 3, 4): per-shape run starts
+// (start[y][shape], -1 where a shape has no element; fill first) and keys turned into each shape's own site ids
+struct ListsOut {
+  int* keys[3];
+  int n[3];
+  int width[3];
+  int* start[3];
+};
+hipError_t launch_localize_lists(const ListsOut& L, const ShapeDesc* shapes, int nshapes, hipStream_t s);
 
 
 // session.hip

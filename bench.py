@@ -510,7 +510,7 @@ def main():
         "estimated_order": est,
         "all_fp64": out64,
         "stats": {k: st32[k] for k in ("n_candidates", "n_deferred", "n_fp64", "n_exact", "n_faces", "n_edges",
-                                       "n_rpv", "n_defer_block", "n_defer_kmax", "n_defer_clip", "n_split", "n_items",
+                                       "n_rpv", "n_defer_block", "n_defer_kmax", "n_defer_clip", "n_split", "n_items", "n_big",
                                        "ms_clip", "ms_deferred", "ms_reduce", "ms_total")},
         "no_split": nosplit,
         "roofline": roof,

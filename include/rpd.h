@@ -129,9 +129,10 @@ typedef struct rpd_stats {
   double ms_total;        /* whole rpd_build on the stream */
   int64_t n_defer_block;  /* tets deferred because their workgroup's site list overflowed */
   int64_t n_defer_kmax;   /* tets deferred because more candidates than the clip budget remained */
-  int64_t n_defer_clip;   /* pieces deferred because their polytope outgrew the fast path's vertex slots */
+  int64_t n_defer_clip;   /* pieces deferred by the fast path: a predicate undecided in FP64, or over 64 vertices */
   int64_t n_split;        /* workgroup blocks redone in smaller chunks because their site list overflowed */
   int64_t n_items;        /* work items of the fast kernel (blocks, and parts of blocks that were heavy before) */
+  int64_t n_big;          /* pieces over the fast path's 16 vertex slots, redone there with a 64-slot polytope */
 } rpd_stats;
 
 typedef struct rpd_result rpd_result;

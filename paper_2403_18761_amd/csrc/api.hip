@@ -156,10 +156,10 @@ struct DeviceState {
   int nsh = 0, ns_cap = 0;
   long long nt_tot = 0;
   unsigned capF = 0, capE = 0, capQ = 0, capN = 0;
-  int def_cap = 0, piece_cap = 0, term_cap = 0, list_cap = 0;
+  int def_cap = 0, piece_cap = 0, term_cap = 0, list_cap = 0, big_cap = 0;
   DBuf site, status, cell_chi, cell_geo, cell_np, cell_b0;
   DBuf fkeys, face_chi, face_np, face_b0, ekeys, edge_chi, edge_np, edge_len, edge_b0, qkeys, rpv_cnt;
-  DBuf nodes, glist, gseg, clist, cseg, deferred, deferred2, dlist, pieces, terms, counters, tetU, slow, touch, removed;
+  DBuf nodes, glist, gseg, clist, cseg, bigp, deferred, deferred2, dlist, pieces, terms, counters, tetU, slow, touch, removed;
   int waves = 0;
 
   unsigned long long* cnt() const { return counters.as<unsigned long long>(); }
@@ -215,6 +215,10 @@ struct DeviceState {
     // candidate lists of deferred tets and pieces (a few per cent of the tets on the heaviest workloads)
     list_cap = (int)std::min<size_t>((nt / 8 + 4096) * (size_t)scale, (1u << 25) - 1);
     dlist.alloc(sizeof(int) * KRAW * (size_t)list_cap);
+    // pieces over VMAX vertices: about 1 in 10^4 on the benchmark shapes; an incremental session gets room for
+    // four times as many per pass as a build (its pool must never run out)
+    big_cap = (int)std::min<size_t>((nt / (keep_U ? 64 : 256) + 1024) * (size_t)scale, 1u << 20);
+    bigp.alloc(BIG_BYTES * (size_t)big_cap);
     pieces.alloc(sizeof(PieceRec) * (size_t)std::max(piece_cap, 1));
     terms.alloc(sizeof(TermRec) * (size_t)std::max(term_cap, 1));
     counters.alloc(8 * (NCOUNTERS + 8 + (size_t)NSPREAD * NCOUNTERS));
@@ -290,6 +294,8 @@ struct DeviceState {
     a.deferred2_cap = def_cap / 4 + 1024;
     a.deferred_list = dlist.as<int>();
     a.list_cap = list_cap;
+    a.big = bigp.as<unsigned char>();
+    a.big_cap = big_cap;
     a.pieces = pieces.as<PieceRec>();
     a.piece_cap = piece_cap;
     a.terms = terms.as<TermRec>();
@@ -622,6 +628,7 @@ static bool collect(DeviceState& D, const std::vector<ShapeDesc>& hd, const Shap
   st.n_defer_kmax = (int64_t)hc[C_DEFER_KMAX];
   st.n_defer_clip = (int64_t)hc[C_DEFER_CLIP];
   st.n_split = (int64_t)hc[C_SPLIT];
+  st.n_big = (int64_t)hc[C_BIG];
   return true;
 }
 
@@ -1227,7 +1234,7 @@ static void check_status(rpd_session* S) {
 static void clip_pass(rpd_session* S, const ShapeArgs& a) {
   hip_check(launch_fill_u64(S->D.cnt() + C_DEFER_ITEMS, 0, 1, S->stream), "fill");
   hip_check(launch_fill_u64(S->D.cnt() + C_DEFER2, 0, 1, S->stream), "fill");
-  hip_check(launch_fill_u64(S->D.cnt() + C_LISTS, 0, 1, S->stream), "fill");
+  hip_check(launch_fill_u64(S->D.cnt() + C_LISTS, 0, 2, S->stream), "fill");  // C_LISTS and C_BIG
   hip_check(launch_clip_fast(a, S->o.precision, S->o.block, S->stream), "clip kernel");
   hip_check(launch_clip_slow(a, S->D.slow.as<unsigned char>(), S->D.waves, S->stream), "deferred clip kernel");
 }

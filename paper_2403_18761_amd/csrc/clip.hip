@@ -82,6 +82,33 @@ __device__ inline int hand_over_list(const ShapeArgs& a, const unsigned char* ca
   return (int)(idx * 64) + m;
 }
 
+// The environment of the fast kernel's piece (tet t, candidate ci of the tet's candidate bytes) in its shared lists.
+__device__ inline void fast_env(TetEnv& env, const ShapeDesc& sd, int t, const float4* sites, const int* sid,
+                                const unsigned char* cand, int ci) {
+  env.tv = sd.tp + 4 * (size_t)t;
+  env.o = env.tv[0];
+  env.face64 = sd.tf + 4 * (size_t)t;
+  env.sites = sites;
+  env.sid = sid;
+  env.cidx8 = cand;
+  env.cidx32 = nullptr;
+  env.csite = nullptr;
+  env.ncs = 0;
+  env.ci = ci;
+  env.si = sites[cand[ci]];
+  env.site_i = sid[cand[ci]];
+}
+
+// Hands a piece (tet t of the shape, site) with its tet's candidates to the large-capacity kernel.
+__device__ inline void defer_piece(const ShapeArgs& a, int shape, int t, int site, const unsigned char* cand,
+                                   const int* sid, int m) {
+  stat_add(a, C_DEFER_CLIP, 1ull);
+  const int list = hand_over_list(a, cand, sid, m);
+  unsigned long long idx = atomicAdd(&a.counters[C_DEFER_ITEMS], 1ull);
+  if (idx < (unsigned long long)a.deferred_cap) a.deferred[idx] = make_int4(shape, t, site, list);
+  else atomicOr(a.status, ST_TABLE_FULL);
+}
+
 // Workgroup-local sums of the cell terms (chi numerator, piece count, fixed-point volume and moments) for the first
 // n sites of the workgroup's site list; a piece of another site adds to the global arrays directly.
 struct CellSink {
@@ -120,7 +147,7 @@ __device__ inline void acc128(unsigned long long* p, Fix128 v) {
 }
 
 template <typename T, typename Topo, typename Mask, int VCAP, bool EXACT, typename Tab>
-__device__ void emit_piece(Clipper<T, Topo, Mask, VCAP, EXACT, Tab>& c, const ShapeDesc& sd, int tl, const ShapeArgs& a,
+__device__ __forceinline__ void emit_piece(Clipper<T, Topo, Mask, VCAP, EXACT, Tab>& c, const ShapeDesc& sd, int tl, const ShapeArgs& a,
                            const CellSink& sink) {
   typedef typename Topo::W W;
   const int i = c.env.site_i;  // batch-global site id
@@ -317,7 +344,7 @@ __device__ void emit_piece(Clipper<T, Topo, Mask, VCAP, EXACT, Tab>& c, const Sh
 // clipping of one (tet, candidate) piece against the other candidates in order; returns CLIP_* for the piece
 // ---------------------------------------------------------------------------------------------------------------
 template <typename T, typename Topo, typename Mask, int VCAP, bool EXACT, typename Tab>
-__device__ int clip_piece(Clipper<T, Topo, Mask, VCAP, EXACT, Tab>& cl, int m, int* status) {
+__device__ __forceinline__ int clip_piece(Clipper<T, Topo, Mask, VCAP, EXACT, Tab>& cl, int m, int* status) {
   const TetEnv& env = cl.env;
   const float4 o = env.o;
   const double y1x = (double)env.tv[1].x - o.x, y1y = (double)env.tv[1].y - o.y, y1z = (double)env.tv[1].z - o.z;
@@ -428,6 +455,8 @@ __global__ __launch_bounds__(NT) void k_clip_fast(ShapeArgs a) {
   __shared__ int s_nsl;
   __shared__ unsigned long long s_cnt[4];
   __shared__ unsigned s_topo[VMAX * NT];
+  __shared__ int s_over[NT];  // this round's pieces that ran out of vertex slots: tet << 16 | candidate
+  __shared__ int s_nover;
   // per-site sums of the workgroup's cell terms (the first 128 sites of the list, or the first 32 with 64 threads,
   // where the LDS budget for four workgroups per compute unit is tight); pieces of later sites add to the global
   // accumulators directly
@@ -439,6 +468,7 @@ __global__ __launch_bounds__(NT) void k_clip_fast(ShapeArgs a) {
 
   const int tid = threadIdx.x;
   const int lane = tid & 63, wid = tid >> 6;
+  if (tid == 0) s_nover = 0;
   for (int k = tid; k < AGG; k += NT) {
     s_acc_chi[k] = 0;
     s_acc_np[k] = 0;
@@ -686,48 +716,81 @@ __global__ __launch_bounds__(NT) void k_clip_fast(ShapeArgs a) {
   // ---- 4. one thread per (tet, candidate) piece
   const int npairs = s_off[TB];
   n_cand += npairs;
-  for (int p = tid; p < npairs; p += NT) {
-    int lo_ = 0, hi_ = TB - 1;  // last position j with s_off[j] <= p
-    while (lo_ < hi_) {
-      int mid = (lo_ + hi_ + 1) >> 1;
-      if (s_off[mid] <= p) lo_ = mid;
-      else hi_ = mid - 1;
+  for (int base = 0; base < npairs; base += NT) {  // rounds of NT pieces (the same count for every thread)
+    const int p = base + tid;
+    if (p < npairs) {
+      int lo_ = 0, hi_ = TB - 1;  // last position j with s_off[j] <= p
+      while (lo_ < hi_) {
+        int mid = (lo_ + hi_ + 1) >> 1;
+        if (s_off[mid] <= p) lo_ = mid;
+        else hi_ = mid - 1;
+      }
+      const int lt = s_order[lo_];
+      const int ci = p - s_off[lo_];
+      const int m = s_m[lt];
+      Clipper<T, Topo32, unsigned, VMAX, false, RegTab> cl;
+      cl.st.bind(s_share, s_topo, tid, NT);
+      cl.tab.clear(0);
+      cl.a = nullptr;  // only the exact predicates use it (not compiled into this kernel)
+      cl.flags = a.flags;
+      cl.np = 4 + m;
+      cl.n64 = 0;
+      cl.nex = 0;
+      fast_env(cl.env, sd, t0 + lt, s_site, s_sid, s_cand[lt], ci);
+      const int r = clip_piece(cl, m, a.status);
+      n64 += cl.n64;
+      if (r == CLIP_OK) {
+        n_pairs += (unsigned long long)(long long)sd.sign;  // live pieces, in two's complement
+        emit_piece(cl, sd, t0 + lt, a, CellSink{s_acc_chi, s_acc_np, s_acc_lo, s_acc_hi, AGG, (int)s_cand[lt][ci]});
+      } else if (r == CLIP_DEFER) {
+        defer_piece(a, shape, t0 + lt, cl.env.site_i, s_cand[lt], s_sid, m);
+      } else if (r == CLIP_FULL) {  // out of vertex slots: redone below, after this round
+        s_over[atomicAdd(&s_nover, 1)] = (lt << 16) | ci;
+      }
     }
-    const int lt = s_order[lo_];
-    const int ci = p - s_off[lo_];
-    const int m = s_m[lt];
-    Clipper<T, Topo32, unsigned, VMAX, false, RegTab> cl;
-    cl.st.bind(s_share, s_topo, tid, NT);
-    cl.tab.clear(0);
-    cl.a = nullptr;  // only the exact predicates use it (not compiled into this kernel)
-    cl.flags = a.flags;
-    cl.np = 4 + m;
-    cl.n64 = 0;
-    cl.nex = 0;
-    cl.env.tv = sd.tp + 4 * (size_t)(t0 + lt);
-    cl.env.o = cl.env.tv[0];
-    cl.env.face64 = sd.tf + 4 * (size_t)(t0 + lt);
-    cl.env.sites = s_site;
-    cl.env.sid = s_sid;
-    cl.env.cidx8 = s_cand[lt];
-    cl.env.cidx32 = nullptr;
-    cl.env.csite = nullptr;
-    cl.env.ncs = 0;
-    cl.env.ci = ci;
-    cl.env.si = s_site[s_cand[lt][ci]];
-    cl.env.site_i = s_sid[s_cand[lt][ci]];
-    int r = clip_piece(cl, m, a.status);
-    n64 += cl.n64;
-    if (r == CLIP_OK) {
-      n_pairs += (unsigned long long)(long long)sd.sign;  // live pieces, in two's complement
-      const CellSink sink{s_acc_chi, s_acc_np, s_acc_lo, s_acc_hi, AGG, (int)s_cand[lt][ci]};
-      emit_piece(cl, sd, t0 + lt, a, sink);
-    } else if (r == CLIP_DEFER) {
-      stat_add(a, C_DEFER_CLIP, 1ull);
-      const int list = hand_over_list(a, s_cand[lt], s_sid, m);
-      unsigned long long idx = atomicAdd(&a.counters[C_DEFER_ITEMS], 1ull);
-      if (idx < (unsigned long long)a.deferred_cap) a.deferred[idx] = make_int4(shape, t0 + lt, cl.env.site_i, list);
-      else atomicOr(a.status, ST_TABLE_FULL);
+    // Pieces that ran out of vertex slots are redone here, one per thread, with a BIG_VCAP-slot polytope in a
+    // global-memory record (they would otherwise wait for the deferred kernel, after this one). Which path computes
+    // a piece must depend on the piece alone (an incremental update must take back exactly the bits it added), so
+    // a full record pool is a table overflow (the call is redone with larger buffers), never a reason to defer.
+    __syncthreads();
+    const int nover = s_nover;
+    if (nover) {
+      if (tid < nover) {
+        const int lt = s_over[tid] >> 16, ci = s_over[tid] & 0xffff, m = s_m[lt];
+        const unsigned long long slot = atomicAdd(&a.counters[C_BIG], 1ull);
+        if (slot >= (unsigned long long)a.big_cap) {
+          atomicOr(a.status, ST_TABLE_FULL);
+        } else {
+          unsigned char* b = a.big + slot * BIG_BYTES;
+          Clipper<T, Topo64, unsigned long long, BIG_VCAP, false, MemTab> cb;
+          constexpr size_t CB = sizeof(typename Coord4<T>::type) * BIG_VCAP;
+          static_assert(CB + 8 * BIG_VCAP + 32 <= BIG_BYTES, "large-capacity polytope record");
+          cb.st.c = reinterpret_cast<typename Coord4<T>::type*>(b);
+          cb.st.w = reinterpret_cast<unsigned long long*>(b + CB);
+          cb.st.stride = 1;
+          cb.tab.base = b + CB + 8 * BIG_VCAP;
+          cb.tab.stride = 1;
+          cb.tab.clear(4 + m);
+          cb.a = nullptr;
+          cb.flags = a.flags;
+          cb.np = 4 + m;
+          cb.n64 = 0;
+          cb.nex = 0;
+          fast_env(cb.env, sd, t0 + lt, s_site, s_sid, s_cand[lt], ci);
+          const int r = clip_piece(cb, m, a.status);
+          n64 += cb.n64;
+          if (r == CLIP_OK) {
+            n_pairs += (unsigned long long)(long long)sd.sign;
+            emit_piece(cb, sd, t0 + lt, a, CellSink{s_acc_chi, s_acc_np, s_acc_lo, s_acc_hi, AGG,
+                                                    (int)s_cand[lt][ci]});
+          } else if (r != CLIP_EMPTY) {  // a predicate undecided in FP64, or over BIG_VCAP vertices
+            defer_piece(a, shape, t0 + lt, cb.env.site_i, s_cand[lt], s_sid, m);
+          }
+        }
+      }
+      __syncthreads();
+      if (tid == 0) s_nover = 0;
+      __syncthreads();
     }
   }
   // flush the workgroup's cell sums of this pass (the site list changes with the next chunk)
@@ -1000,7 +1063,7 @@ __global__ __launch_bounds__(64, LDS ? 1 : 2) void k_clip_slow(ShapeArgs a, unsi
       int r = clip_piece(cl, m, a.status);
       n64 += cl.n64;
       nex += cl.nex;
-      if (r == CLIP_DEFER) {  // out of vertex slots: the global variant redoes the piece with the same candidates
+      if (r == CLIP_FULL) {  // out of vertex slots: the global variant redoes the piece with the same candidates
         if (LDS) push_overflow(a, make_int4(di.x, t, scand[ci], di.w));
         else atomicOr(a.status, ST_SLOW_CAPACITY);
         continue;

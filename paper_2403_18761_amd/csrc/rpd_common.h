@@ -23,6 +23,11 @@ constexpr int SPLIT_TETS = 16;       // = the width of the tet mask
 constexpr int SLOW_KMAX = 1020;  // candidate sites per tet
 constexpr int SLOW_VMAX = 64;    // vertex slots of one piece
 constexpr int SLOW_PMAX = 4 + SLOW_KMAX;
+// Fast-path pieces that outgrow VMAX vertex slots are redone in the same kernel with a global-memory polytope of
+// BIG_VCAP slots (coordinates + bound in the kernel's precision, 64-bit topology words, a byte per plane for the
+// pairing table).
+constexpr int BIG_VCAP = 64;
+constexpr size_t BIG_BYTES = 32 * BIG_VCAP + 8 * BIG_VCAP + 64;
 
 // status bits raised by kernels (ShapeArgs::status)
 constexpr int ST_DEGENERATE = 1;     // an exact predicate evaluated to zero / duplicate site
@@ -43,6 +48,8 @@ enum {
   C_GLUE_PAIRS,   // glued pairs matched
   C_TERMS,        // per-piece element terms kept with RPD_KEEP_PIECES (cursor)
   C_LISTS,        // candidate lists handed from the fast kernel to the large-capacity kernel (cursor)
+  C_BIG,          // pieces the fast kernel redid in a global-memory polytope after running out of slots (cursor;
+                  // follows C_LISTS: an incremental pass resets both together)
   NCOUNTERS
 };
 // C_RPV counts RPV emissions; the RPV list itself is the set of keys of ShapeArgs::Q with a positive count
@@ -151,6 +158,8 @@ struct ShapeArgs {
   int deferred_cap;
   int* deferred_list;    // [list_cap][KRAW] batch-global site ids
   int list_cap;
+  unsigned char* big;    // [big_cap][BIG_BYTES] global-memory polytopes of the fast kernel's overflowing pieces
+  int big_cap;
   int4* deferred2;       // items the LDS variant of the large-capacity path hands to its global variant
   int deferred2_cap;
   PieceRec* pieces;      // kept with RPD_KEEP_PIECES (t = global tet id)

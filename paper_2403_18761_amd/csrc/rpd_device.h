@@ -610,9 +610,9 @@ __device__ inline int node_elem(unsigned long long key) { return (int)((key >> 3
 struct MemTab {
   unsigned char* base;
   int stride;
-  __device__ int get(int q) const { return base[q * stride]; }
-  __device__ void set(int q, int v) { base[q * stride] = (unsigned char)v; }
-  __device__ void clear(int np) {
+  __device__ __forceinline__ int get(int q) const { return base[q * stride]; }
+  __device__ __forceinline__ void set(int q, int v) { base[q * stride] = (unsigned char)v; }
+  __device__ __forceinline__ void clear(int np) {
     for (int q = 0; q < np; ++q) base[q * stride] = 0;
   }
 };
@@ -637,7 +637,7 @@ struct RegTab {
 // ---------------------------------------------------------------------------------------------------------------
 // The clipper: one convex piece P = t & {clipped half-spaces}, vertices in a Store, live slots in a mask.
 // ---------------------------------------------------------------------------------------------------------------
-enum { CLIP_OK = 0, CLIP_EMPTY = 1, CLIP_DEFER = 2 };
+enum { CLIP_OK = 0, CLIP_EMPTY = 1, CLIP_DEFER = 2, CLIP_FULL = 3 };  // DEFER: undecided predicate; FULL: out of vertex slots
 
 template <typename T, typename Topo, typename Mask, int VCAP, bool EXACT, typename Tab>
 struct Clipper {
@@ -731,9 +731,9 @@ struct Clipper {
       for (int e = 0; e < 3; ++e) {
         int nb = Topo::nb(w, e);
         if (!(out & bit(nb))) continue;
-        if (!freem) {  // out of vertex slots: clear the half-done pairing state and defer the piece
+        if (!freem) {  // out of vertex slots: clear the half-done pairing state and give the piece up
           tab.clear(np);
-          return CLIP_DEFER;
+          return CLIP_FULL;
         }
         int s = ctz_mask(freem);
         freem &= freem - 1;

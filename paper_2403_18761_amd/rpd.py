@@ -62,7 +62,7 @@ class _Stats(C.Structure):
                 ("n_edges", C.c_int64), ("n_rpv", C.c_int64), ("n_glue", C.c_int64), ("ms_clip", C.c_double),
                 ("ms_deferred", C.c_double), ("ms_reduce", C.c_double), ("ms_total", C.c_double),
                 ("n_defer_block", C.c_int64), ("n_defer_kmax", C.c_int64), ("n_defer_clip", C.c_int64), ("n_split", C.c_int64),
-                ("n_items", C.c_int64)]
+                ("n_items", C.c_int64), ("n_big", C.c_int64)]
 
 
 class _SessionOpts(C.Structure):

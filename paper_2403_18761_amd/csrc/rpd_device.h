@@ -557,8 +557,13 @@ __device__ inline unsigned hslot(unsigned long long key, unsigned mask) {  // 64
 __device__ inline int ht_insert(const HashTab& h, unsigned long long key, int* status) {
   unsigned s = hslot(key, h.mask);
   for (unsigned probe = 0; probe <= h.mask; ++probe) {
-    unsigned long long prev = atomicCAS(&h.keys[s], EMPTY_KEY, key);
-    if (prev == EMPTY_KEY || prev == key) return (int)s;
+    // most pieces find their element's key present: a plain read first (a stale empty read only costs the atomic)
+    const unsigned long long seen = h.keys[s];
+    if (seen == key) return (int)s;
+    if (seen == EMPTY_KEY) {
+      const unsigned long long prev = atomicCAS(&h.keys[s], EMPTY_KEY, key);
+      if (prev == EMPTY_KEY || prev == key) return (int)s;
+    }
     s = (s + 1) & h.mask;
   }
   atomicOr(status, ST_TABLE_FULL);

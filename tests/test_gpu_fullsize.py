@@ -233,6 +233,18 @@ def test_fullsize_torus():
 
     prob = synth.torus_inside(64, 2000, 2)
     g, res, info = run_full(prob, "torus N64 n2000")
+    # at the default launch shape (64 threads, budget 28) a few pieces outgrow the fast path's 16 vertex slots and
+    # are redone there with the 64-slot polytope; every launch shape gives the same elements (chi, beta0 and keys
+    # exactly; the geometry of a piece that a smaller budget defers is computed in FP64 instead)
+    from paper_2403_18761_amd import rpd
+
+    mesh, sites = _mesh_sites(prob)
+    d = rpd.build([mesh], [sites], block=64, clip_budget=28)
+    assert d.stats()["n_big"] > 0
+    gd = extract(d, 0)
+    for k in ("cell_chi", "cell_beta0", "face_keys", "face_chi", "face_beta0", "edge_keys", "edge_chi", "edge_beta0",
+              "rpv_keys", "medial"):
+        assert np.array_equal(np.asarray(gd[k]), np.asarray(g[k])), k
     r = oracle.rpd(prob, threads=min(16, os.cpu_count() or 1), assemble=False)
     assert_parity(g, r, label="torus N64 n2000 (whole)")
     assert_digest(g, load_golden("torus2000")[0], prob, "torus N64 n2000 (digest)")

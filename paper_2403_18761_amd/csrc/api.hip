@@ -166,14 +166,9 @@ struct DeviceState {
   unsigned long long* fin_count() const { return cnt() + NCOUNTERS; }  // [0] faces, [1] edges
   unsigned long long* stat() const { return cnt() + NCOUNTERS + 8; }  // [NSPREAD][NCOUNTERS]
   // totals of every counter: the cursor and the sum of its spread copies (synchronises the stream)
-  void totals(unsigned long long* out, hipStream_t s) const {
-    std::vector<unsigned long long> h(NCOUNTERS + 8 + (size_t)NSPREAD * NCOUNTERS);
-    hip_check(hipMemcpyAsync(h.data(), cnt(), 8 * h.size(), hipMemcpyDeviceToHost, s), "download");
-    hip_check(hipStreamSynchronize(s), "synchronize");
-    for (int c = 0; c < NCOUNTERS + 8; ++c) out[c] = h[c];
-    for (int k = 0; k < NSPREAD; ++k)
-      for (int c = 0; c < NCOUNTERS; ++c) out[c] += h[NCOUNTERS + 8 + (size_t)k * NCOUNTERS + c];
-  }
+  // counter totals (cursors, list counts and the sums of the spread statistics) and the status word, in one
+  // round trip through pinned memory
+  void totals(unsigned long long* out, hipStream_t s, int* status_out = nullptr) const;
   size_t touch_words() const { return ((size_t)ns_cap + capF + capE + 3) / 4; }
 
   void alloc(int n_shapes, int ns, long long nt, int scale, bool keep_pieces, bool keep_U) {
@@ -371,6 +366,19 @@ struct HostPinned {
   HostPinned& operator=(const HostPinned&) = delete;
 };
 
+void DeviceState::totals(unsigned long long* out, hipStream_t s, int* status_out) const {
+  const size_t n = NCOUNTERS + 8 + (size_t)NSPREAD * NCOUNTERS;
+  HostPinned h(8 * n + 16);
+  unsigned long long* hv = (unsigned long long*)h.p;
+  hip_check(hipMemcpyAsync(hv, cnt(), 8 * n, hipMemcpyDeviceToHost, s), "download");
+  if (status_out) hip_check(hipMemcpyAsync(hv + n, status.p, sizeof(int), hipMemcpyDeviceToHost, s), "download");
+  hip_check(hipStreamSynchronize(s), "synchronize");
+  for (int c = 0; c < NCOUNTERS + 8; ++c) out[c] = hv[c];
+  for (int k = 0; k < NSPREAD; ++k)
+    for (int c = 0; c < NCOUNTERS; ++c) out[c] += hv[NCOUNTERS + 8 + (size_t)k * NCOUNTERS + c];
+  if (status_out) *status_out = *(const int*)(hv + n);
+}
+
 // Sorted element lists of the current state, copied to the host and split per shape. Returns false when a table
 // overflowed (the caller retries with larger tables). Live entries are compacted first and the counts read back,
 // so that only they are sorted and downloaded.
@@ -384,7 +392,9 @@ static bool collect(DeviceState& D, const std::vector<ShapeDesc>& hd, const Shap
   unsigned long long* fin = D.fin_count();  // [0] faces, [1] edges, [2] RPVs
   DBuf fk(8 * (size_t)capF), fsl(4 * (size_t)capF), ek(8 * (size_t)capE), esl(4 * (size_t)capE),
       rq(16 * (size_t)capQ);
-  hip_check(launch_fill_u64(fin, 0, 3, s), "fill");
+  // the list counts were zeroed with the other counters when the state was cleared; an incremental session collects
+  // again and again from one state
+  if (D.touch.p) hip_check(launch_fill_u64(fin, 0, 3, s), "fill");
   hip_check(launch_compact_live(D.fkeys.as<unsigned long long>(), D.face_np.as<int>(), capF,
                                 fk.as<unsigned long long>(), fsl.as<int>(), fin + 0, s),
             "live faces");
@@ -394,103 +404,102 @@ static bool collect(DeviceState& D, const std::vector<ShapeDesc>& hd, const Shap
   HashTab Q{D.qkeys.as<unsigned long long>(), capQ - 1};
   hip_check(launch_rpv_compact(Q, D.rpv_cnt.as<int>(), D.ekeys.as<unsigned long long>(), rq.as<int4>(), fin + 2, s),
             "live rpvs");
+  const HashTab F{D.fkeys.as<unsigned long long>(), capF - 1}, E{D.ekeys.as<unsigned long long>(), capE - 1};
+  const size_t ncap = std::max<size_t>(std::max(capF, capE), capQ);
   unsigned long long hc[NCOUNTERS + 8];
   int hst = 0;
-  hip_check(hipMemcpyAsync(&hst, D.status.p, sizeof(int), hipMemcpyDeviceToHost, s), "download");
-  D.totals(hc, s);
-  if (hst & ST_TABLE_FULL) return false;
-  if (hc[C_DEFER_ITEMS] > (unsigned long long)D.def_cap || hc[C_LISTS] > (unsigned long long)D.list_cap ||
-      (D.piece_cap && (hc[C_PIECES] > (unsigned long long)D.piece_cap || hc[C_TERMS] > (unsigned long long)D.term_cap)))
-    return false;
-  status_error(hst);
-  const size_t nf = hc[NCOUNTERS + 0], ne = hc[NCOUNTERS + 1], nq = hc[NCOUNTERS + 2];
-
-  // one device buffer for everything that goes to the host: RPVs (int4) first, then the int32 and double arrays
-  const size_t n_int = 2 * (size_t)ns + 4 * nf + 5 * ne + 3 * (size_t)nsh;
-  const size_t off_int = 16 * nq, off_dbl = (off_int + 4 * n_int + 7) / 8 * 8;
-  const size_t out_bytes = off_dbl + 8 * (4 * (size_t)ns + 2 * ne);
-  DBuf out(std::max<size_t>(out_bytes, 16));
-  unsigned char* ob = out.as<unsigned char>();
-  int* c_chi = (int*)(ob + off_int);
-  int* c_b0 = c_chi + ns;
-  int* f_keys = c_b0 + ns;
-  int* f_chi = f_keys + 2 * nf;
-  int* f_b0 = f_chi + nf;
-  int* e_keys = f_b0 + nf;
-  int* e_chi = e_keys + 3 * ne;
-  int* e_b0 = e_chi + ne;
-  int* l_start = e_b0 + ne;  // [3][nsh] first face, edge and RPV of every shape (batches)
-  double* c_vol = (double*)(ob + off_dbl);
-  double* c_cen = c_vol + ns;
-  double* e_len = c_cen + 3 * (size_t)ns;
-  double* e_alpha = e_len + ne;
-
-  const HashTab F{D.fkeys.as<unsigned long long>(), capF - 1}, E{D.ekeys.as<unsigned long long>(), capE - 1};
-  if (ns < (1 << 16) && nf < (1u << 31) && ne < (1u << 31)) {
-    // up to 2^16 sites: the lists are sorted by rows of their first site; slots are looked up again by key
-    DBuf kq(8 * std::max<size_t>(nq, 1)), t0(8 * std::max<size_t>(nf, 1)), t1(8 * std::max<size_t>(ne, 1)),
-        t2(8 * std::max<size_t>(nq, 1)), roff(4 * 3 * ((size_t)ns + 1)), rcur(4 * 3 * (size_t)std::max(ns, 1));
-    hip_check(launch_pack_rpv(rq.as<int4>(), (int)nq, kq.as<unsigned long long>(), s), "pack rpv");
+  // the counters, status and live counts: a false return (a table or buffer overflowed) has the caller retry
+  auto check_totals = [&]() {
+    D.totals(hc, s, &hst);
+    if (hst & ST_TABLE_FULL) return false;
+    if (hc[C_DEFER_ITEMS] > (unsigned long long)D.def_cap || hc[C_LISTS] > (unsigned long long)D.list_cap ||
+        (D.piece_cap &&
+         (hc[C_PIECES] > (unsigned long long)D.piece_cap || hc[C_TERMS] > (unsigned long long)D.term_cap)))
+      return false;
+    status_error(hst);
+    return true;
+  };
+  // one device buffer carries everything to the host (OutLayout); the kernels place their output from the live
+  // counts in device memory
+  DBuf out;
+  OutDesc od{nullptr, fin, ns, nsh};
+  size_t nf = 0, ne = 0, nq = 0;
+  if (ns < (1 << 16)) {
+    // up to 2^16 sites: the lists are sorted by rows of their first site and slots are looked up again by key. The
+    // whole sequence is queued before the host waits for the counts (the buffer is sized for full tables).
+    out.alloc(out_layout(ns, nsh, capF, capE, capQ).bytes);
+    od.base = out.as<unsigned char>();
+    DBuf kq(8 * (size_t)capQ), t0(8 * (size_t)capF), t1(8 * (size_t)capE), t2(8 * (size_t)capQ),
+        roff(4 * 3 * ((size_t)ns + 1)), rcur(4 * 3 * (size_t)std::max(ns, 1));
+    hip_check(launch_pack_rpv(rq.as<int4>(), fin + 2, capQ, kq.as<unsigned long long>(), s), "pack rpv");
     unsigned long long* const keys[3] = {fk.as<unsigned long long>(), ek.as<unsigned long long>(),
                                          kq.as<unsigned long long>()};
     unsigned long long* const tmps[3] = {t0.as<unsigned long long>(), t1.as<unsigned long long>(),
                                          t2.as<unsigned long long>()};
-    const int counts[3] = {(int)nf, (int)ne, (int)nq}, shifts[3] = {32, 42, 48};
-    hip_check(launch_row_sort(keys, tmps, counts, shifts, std::max(ns, 1), roff.as<int>(), rcur.as<int>(), s),
+    const size_t caps[3] = {capF, capE, capQ};
+    const int shifts[3] = {32, 42, 48};
+    hip_check(launch_row_sort(keys, tmps, fin, caps, shifts, std::max(ns, 1), roff.as<int>(), rcur.as<int>(), s),
               "sort lists");
-    hip_check(launch_finalize_faces(fk.as<unsigned long long>(), nullptr, F, (int)nf, D.face_chi.as<long long>(),
-                                    D.face_b0.as<int>(), dshapes, nsh, f_keys, f_chi, f_b0, D.status.as<int>(), s),
+    hip_check(launch_finalize_faces(fk.as<unsigned long long>(), nullptr, F, capF, od, D.face_chi.as<long long>(),
+                                    D.face_b0.as<int>(), dshapes, nsh, D.status.as<int>(), s),
               "finalize faces");
-    hip_check(launch_finalize_edges(ek.as<unsigned long long>(), nullptr, E, (int)ne, D.edge_chi.as<long long>(),
+    hip_check(launch_finalize_edges(ek.as<unsigned long long>(), nullptr, E, capE, od, D.edge_chi.as<long long>(),
                                     D.edge_b0.as<int>(), D.edge_len.as<long long>(), D.site.as<float4>(), dshapes, nsh,
-                                    e_keys, e_chi, e_b0, e_len, e_alpha, D.status.as<int>(), s),
+                                    D.status.as<int>(), s),
               "finalize edges");
-    hip_check(launch_unpack_rpv(kq.as<unsigned long long>(), (int)nq, (int4*)ob, s), "unpack rpv");
+    hip_check(launch_unpack_rpv(kq.as<unsigned long long>(), capQ, od, s), "unpack rpv");
+    if (nsh > 1) hip_check(launch_localize_lists(od, ncap, dshapes, nsh, s), "localize lists");
+    if (ns > 0)
+      hip_check(launch_finalize_cells(ns, D.cell_chi.as<long long>(), D.cell_geo.as<long long>(), D.cell_np.as<int>(),
+                                      D.cell_b0.as<int>(), dshapes, nsh, od, D.status.as<int>(), s),
+                "finalize cells");
+    tm.mark(3, s);
+    if (!check_totals()) return false;
+    nf = hc[NCOUNTERS + 0];
+    ne = hc[NCOUNTERS + 1];
+    nq = hc[NCOUNTERS + 2];
   } else {
+    // more sites: radix sorts, sized by the live counts read first
+    if (!check_totals()) return false;
+    nf = hc[NCOUNTERS + 0];
+    ne = hc[NCOUNTERS + 1];
+    nq = hc[NCOUNTERS + 2];
+    const OutLayout L = out_layout(ns, nsh, nf, ne, nq);
+    out.alloc(L.bytes);
+    od.base = out.as<unsigned char>();
     const size_t maxn = std::max(std::max(nf, ne), std::max(nq, (size_t)1));
     size_t tmpb = sort_tmp_bytes((int)maxn);
     DBuf tmp(tmpb), kA(8 * maxn), kB(8 * maxn), kC(8 * maxn), vA(4 * maxn), vB(4 * maxn);
     hip_check(sort_pairs_u64(tmp.p, tmpb, fk.as<unsigned long long>(), kB.as<unsigned long long>(), fsl.as<int>(),
                              vB.as<int>(), (int)nf, s),
               "sort faces");
-    hip_check(launch_finalize_faces(kB.as<unsigned long long>(), vB.as<int>(), F, (int)nf, D.face_chi.as<long long>(),
-                                    D.face_b0.as<int>(), dshapes, nsh, f_keys, f_chi, f_b0, D.status.as<int>(), s),
+    hip_check(launch_finalize_faces(kB.as<unsigned long long>(), vB.as<int>(), F, std::max<size_t>(nf, 1), od,
+                                    D.face_chi.as<long long>(), D.face_b0.as<int>(), dshapes, nsh, D.status.as<int>(),
+                                    s),
               "finalize faces");
     hip_check(sort_pairs_u64(tmp.p, tmpb, ek.as<unsigned long long>(), kB.as<unsigned long long>(), esl.as<int>(),
                              vB.as<int>(), (int)ne, s),
               "sort edges");
-    hip_check(launch_finalize_edges(kB.as<unsigned long long>(), vB.as<int>(), E, (int)ne, D.edge_chi.as<long long>(),
-                                    D.edge_b0.as<int>(), D.edge_len.as<long long>(), D.site.as<float4>(), dshapes, nsh,
-                                    e_keys, e_chi, e_b0, e_len, e_alpha, D.status.as<int>(), s),
+    hip_check(launch_finalize_edges(kB.as<unsigned long long>(), vB.as<int>(), E, std::max<size_t>(ne, 1), od,
+                                    D.edge_chi.as<long long>(), D.edge_b0.as<int>(), D.edge_len.as<long long>(),
+                                    D.site.as<float4>(), dshapes, nsh, D.status.as<int>(), s),
               "finalize edges");
     hip_check(launch_sort_rpv(rq.as<int4>(), (int)nq, kA.as<unsigned long long>(), kB.as<unsigned long long>(),
-                              kC.as<unsigned long long>(), vA.as<int>(), vB.as<int>(), tmp.p, tmpb, (int4*)ob, s),
+                              kC.as<unsigned long long>(), vA.as<int>(), vB.as<int>(), tmp.p, tmpb,
+                              (int4*)(od.base + L.rpv), s),
               "sort rpv");
+    if (nsh > 1) hip_check(launch_localize_lists(od, std::max(maxn, (size_t)1), dshapes, nsh, s), "localize lists");
+    if (ns > 0)
+      hip_check(launch_finalize_cells(ns, D.cell_chi.as<long long>(), D.cell_geo.as<long long>(), D.cell_np.as<int>(),
+                                      D.cell_b0.as<int>(), dshapes, nsh, od, D.status.as<int>(), s),
+                "finalize cells");
+    tm.mark(3, s);
   }
-  if (nsh > 1) {  // per-shape runs of the lists, and keys in each shape's own site ids
-    ListsOut L;
-    L.keys[0] = f_keys;
-    L.keys[1] = e_keys;
-    L.keys[2] = (int*)ob;
-    L.n[0] = (int)nf;
-    L.n[1] = (int)ne;
-    L.n[2] = (int)nq;
-    L.width[0] = 2;
-    L.width[1] = 3;
-    L.width[2] = 4;
-    for (int y = 0; y < 3; ++y) L.start[y] = l_start + (size_t)y * nsh;
-    hip_check(launch_fill_i32(l_start, -1, 3 * (size_t)nsh, s), "fill");
-    hip_check(launch_localize_lists(L, dshapes, nsh, s), "localize lists");
-  }
-  if (ns > 0)
-    hip_check(launch_finalize_cells(ns, D.cell_chi.as<long long>(), D.cell_geo.as<long long>(), D.cell_np.as<int>(),
-                                    D.cell_b0.as<int>(), dshapes, nsh, c_chi, c_b0, c_vol, c_cen, D.status.as<int>(),
-                                    s),
-              "finalize cells");
-  tm.mark(3, s);
+  const OutLayout L = out_layout(ns, nsh, nf, ne, nq);
+  const size_t out_bytes = L.bytes;
   auto host = std::make_shared<HostPinned>(out_bytes + 16);  // kept by the result (its arrays point into it)
   unsigned char* hb = (unsigned char*)host->p;
-  hip_check(hipMemcpyAsync(hb, ob, out_bytes, hipMemcpyDeviceToHost, s), "download");
+  hip_check(hipMemcpyAsync(hb, od.base, out_bytes, hipMemcpyDeviceToHost, s), "download");
   hip_check(hipMemcpyAsync(hb + out_bytes, D.status.p, sizeof(int), hipMemcpyDeviceToHost, s), "download");
   std::vector<PieceRec> prs;
   if (D.piece_cap) d2h(prs, D.pieces.p, hc[C_PIECES], s);
@@ -499,25 +508,25 @@ static bool collect(DeviceState& D, const std::vector<ShapeDesc>& hd, const Shap
   tm.mark(4, s);
   hip_check(hipStreamSynchronize(s), "synchronize");
   status_error(*(int*)(hb + out_bytes));
-  const int* all_rpv = (const int*)hb;
-  const int* all_cchi = (const int*)(hb + off_int);
-  const int* all_cb0 = all_cchi + ns;
-  const int* all_fk = all_cb0 + ns;
-  const int* all_fchi = all_fk + 2 * nf;
-  const int* all_fb0 = all_fchi + nf;
-  const int* all_ek = all_fb0 + nf;
-  const int* all_echi = all_ek + 3 * ne;
-  const int* all_eb0 = all_echi + ne;
-  const double* all_vol = (const double*)(hb + off_dbl);
-  const double* all_cen = all_vol + ns;
-  const double* all_elen = all_cen + 3 * (size_t)ns;
-  const double* all_ealpha = all_elen + ne;
+  const int* all_rpv = (const int*)(hb + L.rpv);
+  const int* all_cchi = (const int*)(hb + L.cchi);
+  const int* all_cb0 = (const int*)(hb + L.cb0);
+  const int* all_fk = (const int*)(hb + L.fk);
+  const int* all_fchi = (const int*)(hb + L.fchi);
+  const int* all_fb0 = (const int*)(hb + L.fb0);
+  const int* all_ek = (const int*)(hb + L.ek);
+  const int* all_echi = (const int*)(hb + L.echi);
+  const int* all_eb0 = (const int*)(hb + L.eb0);
+  const double* all_vol = (const double*)(hb + L.vol);
+  const double* all_cen = (const double*)(hb + L.cen);
+  const double* all_elen = (const double*)(hb + L.elen);
+  const double* all_ealpha = (const double*)(hb + L.ealpha);
   // ---- split per shape (element lists are sorted by batch-global keys, so each shape is one contiguous run; the
   //      device found the runs and turned the keys into shape-local site ids)
   std::vector<size_t> run[3];
   {
     const size_t tot[3] = {nf, ne, nq};
-    const int* starts = all_eb0 + ne;
+    const int* starts = (const int*)(hb + L.start);
     for (int y = 0; y < 3; ++y) {
       run[y].assign((size_t)nsh + 1, tot[y]);
       if (nsh == 1) run[y][0] = 0;

@@ -382,16 +382,16 @@ hipError_t launch_rpv_compact(const HashTab& Q, const int* cnt, const unsigned l
 struct RowLists {
   unsigned long long* keys[3];  // in: keys (any order); out: sorted
   unsigned long long* tmp[3];   // scratch of the same size
-  int n[3];
+  const unsigned long long* n;  // [3] key counts, in device memory
   int shift[3];                 // row = key >> shift
   int* off;                     // [3][rows + 1]
   int* cur;                     // [3][rows]
   int rows;
 };
 __global__ void k_row_count(RowLists L) {
-  const int l = blockIdx.y;
+  const int l = blockIdx.y, n = (int)L.n[l];
   int* off = L.off + l * (L.rows + 1);
-  for (int q = blockIdx.x * blockDim.x + threadIdx.x; q < L.n[l]; q += gridDim.x * blockDim.x)
+  for (int q = blockIdx.x * blockDim.x + threadIdx.x; q < n; q += gridDim.x * blockDim.x)
     atomicAdd(&off[(int)(L.keys[l][q] >> L.shift[l]) + 1], 1);
 }
 // exclusive scan of the row counts in place (one workgroup per list)
@@ -417,10 +417,10 @@ __global__ __launch_bounds__(1024) void k_row_scan(RowLists L) {
   }
 }
 __global__ void k_row_scatter(RowLists L) {
-  const int l = blockIdx.y;
+  const int l = blockIdx.y, n = (int)L.n[l];
   const int* off = L.off + l * (L.rows + 1);
   int* cur = L.cur + l * L.rows;
-  for (int q = blockIdx.x * blockDim.x + threadIdx.x; q < L.n[l]; q += gridDim.x * blockDim.x) {
+  for (int q = blockIdx.x * blockDim.x + threadIdx.x; q < n; q += gridDim.x * blockDim.x) {
     const unsigned long long k = L.keys[l][q];
     const int r = (int)(k >> L.shift[l]);
     L.tmp[l][off[r] + atomicAdd(&cur[r], 1)] = k;
@@ -428,10 +428,10 @@ __global__ void k_row_scatter(RowLists L) {
 }
 // every key finds its place within its row by counting the smaller keys of the row (rows are short; keys unique)
 __global__ void k_row_rank(RowLists L) {
-  const int l = blockIdx.y;
+  const int l = blockIdx.y, n = (int)L.n[l];
   const int* off = L.off + l * (L.rows + 1);
   const unsigned long long* t = L.tmp[l];
-  for (int q = blockIdx.x * blockDim.x + threadIdx.x; q < L.n[l]; q += gridDim.x * blockDim.x) {
+  for (int q = blockIdx.x * blockDim.x + threadIdx.x; q < n; q += gridDim.x * blockDim.x) {
     const unsigned long long k = t[q];
     const int r = (int)(k >> L.shift[l]);
     const int a = off[r], b = off[r + 1];
@@ -440,17 +440,19 @@ __global__ void k_row_rank(RowLists L) {
     L.keys[l][a + rank] = k;
   }
 }
-hipError_t launch_row_sort(unsigned long long* const keys[3], unsigned long long* const tmp[3], const int n[3],
-                           const int shift[3], int rows, int* off, int* cur, hipStream_t s) {
+hipError_t launch_row_sort(unsigned long long* const keys[3], unsigned long long* const tmp[3],
+                           const unsigned long long* n, const size_t ncap[3], const int shift[3], int rows, int* off,
+                           int* cur, hipStream_t s) {
   RowLists L;
-  int nmax = 1;
+  size_t nmax = 1;
   for (int l = 0; l < 3; ++l) {
     L.keys[l] = keys[l];
     L.tmp[l] = tmp[l];
-    L.n[l] = n[l];
     L.shift[l] = shift[l];
-    nmax = std::max(nmax, n[l]);
+    nmax = std::max(nmax, ncap[l]);
   }
+  L.n = n;
+  const int grid = std::min(grid_for(nmax, 256), 2048);
   L.off = off;
   L.cur = cur;
   L.rows = rows;
@@ -459,35 +461,37 @@ hipError_t launch_row_sort(unsigned long long* const keys[3], unsigned long long
   Z.add(cur, 0, 3 * (size_t)rows, 4);
   hipError_t e = launch_fill_multi(Z, s);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_row_count, dim3(grid_for(nmax, 256), 3), dim3(256), 0, s, L);
+  hipLaunchKernelGGL(k_row_count, dim3(grid, 3), dim3(256), 0, s, L);
   hipLaunchKernelGGL(k_row_scan, dim3(3), dim3(1024), 0, s, L);
-  hipLaunchKernelGGL(k_row_scatter, dim3(grid_for(nmax, 256), 3), dim3(256), 0, s, L);
-  hipLaunchKernelGGL(k_row_rank, dim3(grid_for(nmax, 256), 3), dim3(256), 0, s, L);
+  hipLaunchKernelGGL(k_row_scatter, dim3(grid, 3), dim3(256), 0, s, L);
+  hipLaunchKernelGGL(k_row_rank, dim3(grid, 3), dim3(256), 0, s, L);
   return hipGetLastError();
 }
 
 // RPV quadruples with every id below 2^16 packed into one 64-bit key (and back) for the small sort
-__global__ void k_pack_rpv(const int4* in, int n, unsigned long long* out) {
+__global__ void k_pack_rpv(const int4* in, const unsigned long long* count, unsigned long long* out) {
+  const int n = (int)*count;
   for (int q = blockIdx.x * blockDim.x + threadIdx.x; q < n; q += gridDim.x * blockDim.x) {
     const int4 r = in[q];
     out[q] = ((unsigned long long)r.x << 48) | ((unsigned long long)r.y << 32) | ((unsigned long long)r.z << 16) |
              (unsigned long long)r.w;
   }
 }
-__global__ void k_unpack_rpv(const unsigned long long* in, int n, int4* out) {
+__global__ void k_unpack_rpv(const unsigned long long* in, OutDesc od) {
+  const int n = (int)od.n[2];
+  int4* out = (int4*)(od.base + od.layout().rpv);
   for (int q = blockIdx.x * blockDim.x + threadIdx.x; q < n; q += gridDim.x * blockDim.x) {
     const unsigned long long k = in[q];
     out[q] = make_int4((int)(k >> 48), (int)((k >> 32) & 0xffff), (int)((k >> 16) & 0xffff), (int)(k & 0xffff));
   }
 }
-hipError_t launch_pack_rpv(const int4* in, int n, unsigned long long* out, hipStream_t s) {
-  if (n <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_pack_rpv, dim3(grid_for(n, 256)), dim3(256), 0, s, in, n, out);
+hipError_t launch_pack_rpv(const int4* in, const unsigned long long* count, size_t ncap, unsigned long long* out,
+                           hipStream_t s) {
+  hipLaunchKernelGGL(k_pack_rpv, dim3(std::min(grid_for(ncap, 256), 2048)), dim3(256), 0, s, in, count, out);
   return hipGetLastError();
 }
-hipError_t launch_unpack_rpv(const unsigned long long* in, int n, int4* out, hipStream_t s) {
-  if (n <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_unpack_rpv, dim3(grid_for(n, 256)), dim3(256), 0, s, in, n, out);
+hipError_t launch_unpack_rpv(const unsigned long long* in, size_t ncap, const OutDesc& od, hipStream_t s) {
+  hipLaunchKernelGGL(k_unpack_rpv, dim3(std::min(grid_for(ncap, 256), 2048)), dim3(256), 0, s, in, od);
   return hipGetLastError();
 }
 
@@ -497,9 +501,14 @@ hipError_t sort_pairs_u64(void* tmp, size_t& tmp_bytes, const unsigned long long
   return rocprim::radix_sort_pairs(tmp, tmp_bytes, kin, kout, vin, vout, (size_t)n, 0, 64, s);
 }
 
-__global__ void k_finalize_faces(const unsigned long long* keys, const int* slots, HashTab T, int n,
+__global__ void k_finalize_faces(const unsigned long long* keys, const int* slots, HashTab T, OutDesc od,
                                  const long long* chi_num, const int* b0, const ShapeDesc* shapes, int nshapes,
-                                 int* out_keys, int* out_chi, int* out_b0, int* status) {
+                                 int* status) {
+  const int n = (int)od.n[0];
+  const OutLayout L = od.layout();
+  int* out_keys = (int*)(od.base + L.fk);
+  int* out_chi = (int*)(od.base + L.fchi);
+  int* out_b0 = (int*)(od.base + L.fb0);
   for (int q = blockIdx.x * blockDim.x + threadIdx.x; q < n; q += gridDim.x * blockDim.x) {
     unsigned long long k = keys[q];
     int s = slots ? slots[q] : ht_find(T, k);
@@ -513,10 +522,16 @@ __global__ void k_finalize_faces(const unsigned long long* keys, const int* slot
   }
 }
 // RPE length (fixed point -> double) and the thinning importance alpha = length / mean diameter of the three spheres
-__global__ void k_finalize_edges(const unsigned long long* keys, const int* slots, HashTab T, int n,
+__global__ void k_finalize_edges(const unsigned long long* keys, const int* slots, HashTab T, OutDesc od,
                                  const long long* chi_num, const int* b0, const long long* len_num,
-                                 const float4* site, const ShapeDesc* shapes, int nshapes, int* out_keys, int* out_chi,
-                                 int* out_b0, double* out_len, double* out_alpha, int* status) {
+                                 const float4* site, const ShapeDesc* shapes, int nshapes, int* status) {
+  const int n = (int)od.n[1];
+  const OutLayout L = od.layout();
+  int* out_keys = (int*)(od.base + L.ek);
+  int* out_chi = (int*)(od.base + L.echi);
+  int* out_b0 = (int*)(od.base + L.eb0);
+  double* out_len = (double*)(od.base + L.elen);
+  double* out_alpha = (double*)(od.base + L.ealpha);
   for (int q = blockIdx.x * blockDim.x + threadIdx.x; q < n; q += gridDim.x * blockDim.x) {
     unsigned long long k = keys[q];
     int s = slots ? slots[q] : ht_find(T, k);
@@ -536,8 +551,12 @@ __global__ void k_finalize_edges(const unsigned long long* keys, const int* slot
   }
 }
 __global__ void k_finalize_cells(int ns, const long long* chi_num, const long long* geo, const int* np, const int* b0,
-                                 const ShapeDesc* shapes, int nshapes, int* out_chi, int* out_b0, double* out_vol,
-                                 double* out_cen, int* status) {
+                                 const ShapeDesc* shapes, int nshapes, OutDesc od, int* status) {
+  const OutLayout L = od.layout();
+  int* out_chi = (int*)(od.base + L.cchi);
+  int* out_b0 = (int*)(od.base + L.cb0);
+  double* out_vol = (double*)(od.base + L.vol);
+  double* out_cen = (double*)(od.base + L.cen);
   for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < ns; i += gridDim.x * blockDim.x) {
     const long long L = shapes[shape_of_site(shapes, nshapes, i)].L;
     long long c = chi_num[i];
@@ -556,28 +575,25 @@ __global__ void k_finalize_cells(int ns, const long long* chi_num, const long lo
   }
 }
 
-hipError_t launch_finalize_faces(const unsigned long long* keys, const int* slots, const HashTab& T, int n,
-                                 const long long* chi_num, const int* b0, const ShapeDesc* shapes, int nshapes,
-                                 int* out_keys, int* out_chi, int* out_b0, int* status, hipStream_t s) {
-  if (n <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_finalize_faces, dim3(grid_for(n, 256)), dim3(256), 0, s, keys, slots, T, n, chi_num, b0,
-                     shapes, nshapes, out_keys, out_chi, out_b0, status);
+hipError_t launch_finalize_faces(const unsigned long long* keys, const int* slots, const HashTab& T, size_t ncap,
+                                 const OutDesc& od, const long long* chi_num, const int* b0, const ShapeDesc* shapes,
+                                 int nshapes, int* status, hipStream_t s) {
+  hipLaunchKernelGGL(k_finalize_faces, dim3(std::min(grid_for(ncap, 256), 2048)), dim3(256), 0, s, keys, slots, T, od,
+                     chi_num, b0, shapes, nshapes, status);
   return hipGetLastError();
 }
-hipError_t launch_finalize_edges(const unsigned long long* keys, const int* slots, const HashTab& T, int n,
-                                 const long long* chi_num, const int* b0, const long long* len_num,
-                                 const float4* site, const ShapeDesc* shapes, int nshapes, int* out_keys, int* out_chi,
-                                 int* out_b0, double* out_len, double* out_alpha, int* status, hipStream_t s) {
-  if (n <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_finalize_edges, dim3(grid_for(n, 256)), dim3(256), 0, s, keys, slots, T, n, chi_num, b0,
-                     len_num, site, shapes, nshapes, out_keys, out_chi, out_b0, out_len, out_alpha, status);
+hipError_t launch_finalize_edges(const unsigned long long* keys, const int* slots, const HashTab& T, size_t ncap,
+                                 const OutDesc& od, const long long* chi_num, const int* b0, const long long* len_num,
+                                 const float4* site, const ShapeDesc* shapes, int nshapes, int* status,
+                                 hipStream_t s) {
+  hipLaunchKernelGGL(k_finalize_edges, dim3(std::min(grid_for(ncap, 256), 2048)), dim3(256), 0, s, keys, slots, T, od,
+                     chi_num, b0, len_num, site, shapes, nshapes, status);
   return hipGetLastError();
 }
 hipError_t launch_finalize_cells(int ns, const long long* chi_num, const long long* geo, const int* np, const int* b0,
-                                 const ShapeDesc* shapes, int nshapes, int* out_chi, int* out_b0, double* out_vol,
-                                 double* out_cen, int* status, hipStream_t s) {
+                                 const ShapeDesc* shapes, int nshapes, const OutDesc& od, int* status, hipStream_t s) {
   hipLaunchKernelGGL(k_finalize_cells, dim3(grid_for(ns, 256)), dim3(256), 0, s, ns, chi_num, geo, np, b0, shapes,
-                     nshapes, out_chi, out_b0, out_vol, out_cen, status);
+                     nshapes, od, status);
   return hipGetLastError();
 }
 
@@ -663,28 +679,42 @@ hipError_t launch_validate_sites_multi(const SiteSrc* src, int nsrc, int max_n, 
 // per shape), then the keys turned into each shape's own site ids. List y of the launch: faces (2 ids per element),
 // edges (3), RPVs (4); start[y][shape] is the first element of the shape, or stays -1 when it has none.
 // ---------------------------------------------------------------------------------------------------------------
-__global__ void k_list_starts(ListsOut L, const ShapeDesc* shapes, int nshapes) {
-  const int y = blockIdx.y, w = L.width[y], n = L.n[y];
-  const int* keys = L.keys[y];
+// the three lists of the output buffer: faces (2 ids per element), edges (3), RPVs (4)
+__device__ inline void list_of(const OutDesc& od, const OutLayout& L, int y, int** keys, int* n, int* w) {
+  *keys = (int*)(od.base + (y == 0 ? L.fk : y == 1 ? L.ek : L.rpv));
+  *n = (int)od.n[y];
+  *w = y + 2;
+}
+__global__ void k_list_starts(OutDesc od, const ShapeDesc* shapes, int nshapes) {
+  const OutLayout L = od.layout();
+  int* keys;
+  int n, w;
+  list_of(od, L, blockIdx.y, &keys, &n, &w);
+  int* start = (int*)(od.base + L.start) + (size_t)blockIdx.y * nshapes;
   for (int q = blockIdx.x * blockDim.x + threadIdx.x; q < n; q += gridDim.x * blockDim.x) {
     const int sh = shape_of_site(shapes, nshapes, keys[(size_t)w * q]);
-    if (q == 0 || shape_of_site(shapes, nshapes, keys[(size_t)w * (q - 1)]) != sh) L.start[y][sh] = q;
+    if (q == 0 || shape_of_site(shapes, nshapes, keys[(size_t)w * (q - 1)]) != sh) start[sh] = q;
   }
 }
-__global__ void k_localize(ListsOut L, const ShapeDesc* shapes, int nshapes) {
-  const int y = blockIdx.y, w = L.width[y], n = L.n[y];
-  int* keys = L.keys[y];
+__global__ void k_localize(OutDesc od, const ShapeDesc* shapes, int nshapes) {
+  const OutLayout L = od.layout();
+  int* keys;
+  int n, w;
+  list_of(od, L, blockIdx.y, &keys, &n, &w);
   for (int q = blockIdx.x * blockDim.x + threadIdx.x; q < n; q += gridDim.x * blockDim.x) {
     const int off = shapes[shape_of_site(shapes, nshapes, keys[(size_t)w * q])].site_off;
     for (int c = 0; c < w; ++c) keys[(size_t)w * q + c] -= off;
   }
 }
-hipError_t launch_localize_lists(const ListsOut& L, const ShapeDesc* shapes, int nshapes, hipStream_t s) {
-  const int nmax = std::max(L.n[0], std::max(L.n[1], L.n[2]));
-  if (nmax <= 0) return hipSuccess;
-  const dim3 grid(std::min(grid_for(nmax, 256), 2048), 3);
-  hipLaunchKernelGGL(k_list_starts, grid, dim3(256), 0, s, L, shapes, nshapes);
-  hipLaunchKernelGGL(k_localize, grid, dim3(256), 0, s, L, shapes, nshapes);
+__global__ void k_fill_starts(OutDesc od, int nshapes) {
+  int* start = (int*)(od.base + od.layout().start);
+  for (int q = blockIdx.x * blockDim.x + threadIdx.x; q < 3 * nshapes; q += gridDim.x * blockDim.x) start[q] = -1;
+}
+hipError_t launch_localize_lists(const OutDesc& od, size_t ncap, const ShapeDesc* shapes, int nshapes, hipStream_t s) {
+  const dim3 grid(std::min(grid_for(ncap, 256), 2048), 3);
+  hipLaunchKernelGGL(k_fill_starts, dim3(grid_for(3 * (size_t)nshapes, 256)), dim3(256), 0, s, od, nshapes);
+  hipLaunchKernelGGL(k_list_starts, grid, dim3(256), 0, s, od, shapes, nshapes);
+  hipLaunchKernelGGL(k_localize, grid, dim3(256), 0, s, od, shapes, nshapes);
   return hipGetLastError();
 }
 

@@ -86,6 +86,56 @@ struct NodeTab {
   unsigned int mask;  // capacity - 1, capacity a power of two
 };
 
+// The byte layout of the one buffer that carries a call's results to the host, a function of the site count, the
+// shape count and the live face, edge and RPV counts (so that kernels can place their output from the counts in
+// device memory before the host knows them): doubles first, then the RPVs (int4), then the int32 arrays.
+struct OutLayout {
+  size_t vol, cen, elen, ealpha, rpv, cchi, cb0, fk, fchi, fb0, ek, echi, eb0, start, bytes;
+};
+__host__ __device__ inline OutLayout out_layout(size_t ns, size_t nsh, size_t nf, size_t ne, size_t nq) {
+  OutLayout L;
+  size_t o = 0;
+  L.vol = o;
+  o += 8 * ns;
+  L.cen = o;
+  o += 24 * ns;
+  L.elen = o;
+  o += 8 * ne;
+  L.ealpha = o;
+  o += 8 * ne;
+  o = (o + 15) / 16 * 16;
+  L.rpv = o;
+  o += 16 * nq;
+  L.cchi = o;
+  o += 4 * ns;
+  L.cb0 = o;
+  o += 4 * ns;
+  L.fk = o;
+  o += 8 * nf;
+  L.fchi = o;
+  o += 4 * nf;
+  L.fb0 = o;
+  o += 4 * nf;
+  L.ek = o;
+  o += 12 * ne;
+  L.echi = o;
+  o += 4 * ne;
+  L.eb0 = o;
+  o += 4 * ne;
+  L.start = o;  // [3][nsh] first face, edge and RPV of every shape (batches)
+  o += 12 * nsh;
+  L.bytes = (o + 15) / 16 * 16;
+  return L;
+}
+// The output buffer as kernels see it: base, site and shape counts, and the live counts [faces, edges, RPVs] in
+// device memory.
+struct OutDesc {
+  unsigned char* base;
+  const unsigned long long* n;
+  int ns, nsh;
+  __device__ OutLayout layout() const { return out_layout(ns, nsh, n[0], n[1], n[2]); }
+};
+
 // per-piece record kept with RPD_KEEP_PIECES
 struct PieceRec {
   int t;  // internal tet id

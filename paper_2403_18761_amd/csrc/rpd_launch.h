@@ -57,23 +57,24 @@ hipError_t sort_pairs_u64(void* tmp, size_t& tmp_bytes, const unsigned long long
 size_t sort_tmp_bytes(int n);
 // element lists over exactly n sorted live entries
 // (slots may be null: each key's slot is then looked up in T)
-hipError_t launch_finalize_faces(const unsigned long long* keys, const int* slots, const HashTab& T, int n,
-                                 const long long* chi_num, const int* b0, const ShapeDesc* shapes, int nshapes,
-                                 int* out_keys, int* out_chi, int* out_b0, int* status, hipStream_t s);
-hipError_t launch_finalize_edges(const unsigned long long* keys, const int* slots, const HashTab& T, int n,
-                                 const long long* chi_num, const int* b0, const long long* len_num,
-                                 const float4* site, const ShapeDesc* shapes, int nshapes, int* out_keys, int* out_chi,
-                                 int* out_b0, double* out_len, double* out_alpha, int* status, hipStream_t s);
+hipError_t launch_finalize_faces(const unsigned long long* keys, const int* slots, const HashTab& T, size_t ncap,
+                                 const OutDesc& od, const long long* chi_num, const int* b0, const ShapeDesc* shapes,
+                                 int nshapes, int* status, hipStream_t s);
+hipError_t launch_finalize_edges(const unsigned long long* keys, const int* slots, const HashTab& T, size_t ncap,
+                                 const OutDesc& od, const long long* chi_num, const int* b0, const long long* len_num,
+                                 const float4* site, const ShapeDesc* shapes, int nshapes, int* status,
+                                 hipStream_t s);
 // three lists of keys whose row (key >> shift) is below rows, sorted ascending in place; tmp[l] holds n[l] keys;
 // off holds 3 (rows + 1) ints, cur 3 rows ints
-hipError_t launch_row_sort(unsigned long long* const keys[3], unsigned long long* const tmp[3], const int n[3],
-                           const int shift[3], int rows, int* off, int* cur, hipStream_t s);
+hipError_t launch_row_sort(unsigned long long* const keys[3], unsigned long long* const tmp[3],
+                           const unsigned long long* n, const size_t ncap[3], const int shift[3], int rows, int* off,
+                           int* cur, hipStream_t s);
 // RPV quadruples whose ids are all below 2^16, packed into single keys and back
-hipError_t launch_pack_rpv(const int4* in, int n, unsigned long long* out, hipStream_t s);
-hipError_t launch_unpack_rpv(const unsigned long long* in, int n, int4* out, hipStream_t s);
+hipError_t launch_pack_rpv(const int4* in, const unsigned long long* count, size_t ncap, unsigned long long* out,
+                           hipStream_t s);
+hipError_t launch_unpack_rpv(const unsigned long long* in, size_t ncap, const OutDesc& od, hipStream_t s);
 hipError_t launch_finalize_cells(int ns, const long long* chi_num, const long long* geo, const int* np, const int* b0,
-                                 const ShapeDesc* shapes, int nshapes, int* out_chi, int* out_b0, double* out_vol,
-                                 double* out_cen, int* status, hipStream_t s);
+                                 const ShapeDesc* shapes, int nshapes, const OutDesc& od, int* status, hipStream_t s);
 hipError_t launch_sort_rpv(const int4* rpv, int n, unsigned long long* ka, unsigned long long* kb,
                            unsigned long long* kc, int* va, int* vb, void* tmp, size_t tmp_bytes, int4* out,
                            hipStream_t s);
@@ -86,15 +87,9 @@ struct SiteSrc {
 };
 hipError_t launch_validate_sites_multi(const SiteSrc* src, int nsrc, int max_n, float4* site, int* status,
                                        hipStream_t s);
-// the three sorted element lists of a batch (faces, edges, RPVs as int keys of width 2, 3, 4): per-shape run starts
-// (start[y][shape], -1 where a shape has no element; fill first) and keys turned into each shape's own site ids
-struct ListsOut {
-  int* keys[3];
-  int n[3];
-  int width[3];
-  int* start[3];
-};
-hipError_t launch_localize_lists(const ListsOut& L, const ShapeDesc* shapes, int nshapes, hipStream_t s);
+// the output buffer's face, edge and RPV lists of a batch: per-shape run starts (-1 where a shape has no element)
+// and keys turned into each shape's own site ids (ncap: the largest list capacity)
+hipError_t launch_localize_lists(const OutDesc& od, size_t ncap, const ShapeDesc* shapes, int nshapes, hipStream_t s);
 
 
 // session.hip

@@ -762,16 +762,12 @@ struct SiteUpload {
   std::vector<SiteSrc> src;
 };
 
-static SiteUpload upload_sites(DeviceState& D, const rpd_sites* sites, const std::vector<ShapeDesc>& hd, bool dev,
-                               hipStream_t s) {
-  // host arrays are staged into one device buffer; then one launch validates and packs every shape's sites
+// The site arrays of every shape as the validation kernel reads them: the caller's device arrays, or host arrays
+// staged into one device buffer (copies queued on s).
+static SiteUpload site_sources(const rpd_sites* sites, const std::vector<ShapeDesc>& hd, bool dev, hipStream_t s) {
   SiteUpload u;
   size_t total = 0;
-  int max_n = 0;
-  for (size_t k = 0; k < hd.size(); ++k) {
-    total += (size_t)sites[k].n_sites;
-    max_n = std::max(max_n, sites[k].n_sites);
-  }
+  for (size_t k = 0; k < hd.size(); ++k) total += (size_t)sites[k].n_sites;
   DBuf& raw = u.raw;
   if (!dev) raw.alloc(sizeof(float) * 4 * total);
   std::vector<SiteSrc>& src = u.src;
@@ -800,6 +796,16 @@ static SiteUpload upload_sites(DeviceState& D, const rpd_sites* sites, const std
       pos += 4 * (size_t)n;
     }
   }
+  return u;
+}
+
+// the sites of every shape validated and packed into D.site by one launch
+static SiteUpload upload_sites(DeviceState& D, const rpd_sites* sites, const std::vector<ShapeDesc>& hd, bool dev,
+                               hipStream_t s) {
+  SiteUpload u = site_sources(sites, hd, dev, s);
+  const std::vector<SiteSrc>& src = u.src;
+  int max_n = 0;
+  for (const SiteSrc& d : src) max_n = std::max(max_n, d.n);
   u.dsrc.alloc(sizeof(SiteSrc) * std::max<size_t>(src.size(), 1));
   hip_check(hipMemcpyAsync(u.dsrc.p, src.data(), sizeof(SiteSrc) * src.size(), hipMemcpyHostToDevice, s), "upload");
   hip_check(launch_validate_sites_multi(u.dsrc.as<SiteSrc>(), (int)src.size(), max_n, D.site.as<float4>(),
@@ -816,6 +822,10 @@ static bool run_batch(const rpd_mesh* const* meshes, const rpd_sites* sites, int
   for (int k = 0; k < nsh; ++k) nsites[k] = sites[k].n_sites;
   long long ns_tot = 0, nt_tot = 0;
   std::vector<ShapeDesc> hd = shape_table(meshes, nsites.data(), nsh, &ns_tot, &nt_tot);
+  // the tables are cleared on the device while the host orders the work
+  DeviceState D;
+  D.alloc(nsh, (int)ns_tot, nt_tot, scale, (o.flags & RPD_KEEP_PIECES) != 0, false);
+  D.clear(s);
   std::vector<int2> items = work_items(hd, meshes, o.flags);
   if (o.flags & RPD_SHUFFLE_QUEUE) {  // a fixed permutation: results must not depend on the processing order
     unsigned long long x = 0x9E3779B97F4A7C15ull;
@@ -826,16 +836,27 @@ static bool run_batch(const rpd_mesh* const* meshes, const rpd_sites* sites, int
       std::swap(items[k - 1], items[x % k]);
     }
   }
-  DBuf dshapes(sizeof(ShapeDesc) * nsh), ditems(sizeof(int2) * std::max<size_t>(items.size(), 1));
-  hip_check(hipMemcpyAsync(dshapes.p, hd.data(), sizeof(ShapeDesc) * nsh, hipMemcpyHostToDevice, s), "upload");
-  if (!items.empty())
-    hip_check(hipMemcpyAsync(ditems.p, items.data(), sizeof(int2) * items.size(), hipMemcpyHostToDevice, s), "upload");
-  DeviceState D;
-  D.alloc(nsh, (int)ns_tot, nt_tot, scale, (o.flags & RPD_KEEP_PIECES) != 0, false);
-  D.clear(s);
-  const SiteUpload su = upload_sites(D, sites, hd, dev, s);  // released after the stream is drained (below)
+  // the shape table, the site sources and the work items go up in one copy from pinned memory; then one launch
+  // validates and packs every shape's sites (host site arrays are staged first)
+  const size_t off_src = (sizeof(ShapeDesc) * nsh + 15) / 16 * 16;
+  const size_t off_items = off_src + (sizeof(SiteSrc) * nsh + 15) / 16 * 16;
+  const size_t stage_bytes = off_items + sizeof(int2) * std::max<size_t>(items.size(), 1);
+  HostPinned stage(stage_bytes);  // released (back to the pool) after the stream is drained (below)
+  DBuf dstage(stage_bytes);
+  SiteUpload su = site_sources(sites, hd, dev, s);
+  std::memcpy(stage.p, hd.data(), sizeof(ShapeDesc) * nsh);
+  std::memcpy((unsigned char*)stage.p + off_src, su.src.data(), sizeof(SiteSrc) * nsh);
+  if (!items.empty()) std::memcpy((unsigned char*)stage.p + off_items, items.data(), sizeof(int2) * items.size());
+  hip_check(hipMemcpyAsync(dstage.p, stage.p, stage_bytes, hipMemcpyHostToDevice, s), "upload");
+  const ShapeDesc* dshapes_p = (const ShapeDesc*)dstage.p;
+  const int2* ditems_p = (const int2*)(dstage.as<unsigned char>() + off_items);
+  int max_n = 0;
+  for (int k = 0; k < nsh; ++k) max_n = std::max(max_n, sites[k].n_sites);
+  hip_check(launch_validate_sites_multi((const SiteSrc*)(dstage.as<unsigned char>() + off_src), nsh, max_n,
+                                        D.site.as<float4>(), D.status.as<int>(), s),
+            "validate sites");
   const int kmax = o.clip_budget > 0 ? std::min(o.clip_budget, KMAX) : KMAX;
-  ShapeArgs a = D.args(dshapes.as<ShapeDesc>(), ditems.as<int2>(), (int)items.size(), o.flags, kmax);
+  ShapeArgs a = D.args(dshapes_p, ditems_p, (int)items.size(), o.flags, kmax);
   HostPinned ticks_host(sizeof(unsigned) * items.size() + 16);  // pinned: the copy does not stall the host
   struct DrainOnExit {  // an early exit (exception) must not leave the copy into ticks_host pending
     hipStream_t s;
@@ -853,7 +874,7 @@ static bool run_batch(const rpd_mesh* const* meshes, const rpd_sites* sites, int
   hip_check(launch_clip_slow(a, D.slow.as<unsigned char>(), D.waves, s), "deferred clip kernel");
   tm.mark(2, s);
   D.components(a, s);
-  if (!collect(D, hd, dshapes.as<ShapeDesc>(), meshes, s, tm, outs, st)) return false;
+  if (!collect(D, hd, dshapes_p, meshes, s, tm, outs, st)) return false;
   learn_costs(items, (const unsigned*)ticks_host.p, hd, meshes);
   st.n_items = (int64_t)items.size();
   st.ms_clip = tm.ms(0, 1);

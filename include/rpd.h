@@ -127,7 +127,7 @@ typedef struct rpd_stats {
   double ms_deferred;     /* deferred kernel */
   double ms_reduce;       /* gluing, union-find, compaction and sorting */
   double ms_total;        /* whole rpd_build on the stream */
-  int64_t n_defer_block;  /* tets deferred because their workgroup's site list overflowed */
+  int64_t n_defer_block;  /* tets deferred because their own candidates overflow the fast path's site list */
   int64_t n_defer_kmax;   /* tets deferred because more candidates than the clip budget remained */
   int64_t n_defer_clip;   /* pieces deferred by the fast path: a predicate undecided in FP64, or over 64 vertices */
   int64_t n_split;        /* workgroup blocks redone in smaller chunks because their site list overflowed */

@@ -82,6 +82,25 @@ __device__ inline int hand_over_list(const ShapeArgs& a, const unsigned char* ca
   return (int)(idx * 64) + m;
 }
 
+// The next chunk of a split item: the next tet while tets are taken one at a time (up to single_end), else the next
+// SUB tets. False past the item's last tet.
+__device__ inline bool next_chunk(int& sub, int& sub_n, int& single_end, int ntb_all) {
+  if (single_end > sub + 1) {
+    sub += 1;
+    sub_n = 1;
+    return true;
+  }
+  if (single_end > sub) {  // the last single tet of its chunk: on with the chunk after it
+    sub = single_end;
+    single_end = 0;
+  } else {
+    sub += SUB;
+  }
+  if (sub >= ntb_all) return false;
+  sub_n = min(SUB, ntb_all - sub);
+  return true;
+}
+
 // The environment of the fast kernel's piece (tet t, candidate ci of the tet's candidate bytes) in its shared lists.
 __device__ inline void fast_env(TetEnv& env, const ShapeDesc& sd, int t, const float4* sites, const int* sid,
                                 const unsigned char* cand, int ci) {
@@ -499,18 +518,20 @@ __global__ __launch_bounds__(NT) void k_clip_fast(ShapeArgs a) {
     tb0 += (part - 1) * SPLIT_TETS;
     ntb_all = min(SPLIT_TETS, ntb_all - (part - 1) * SPLIT_TETS);
   }
-  // A block whose shared site list overflows is redone in chunks of SUB tets (smaller boxes, shorter lists);
-  // only tets of a chunk that still overflows go to the large-capacity kernel.
-  int sub = 0, sub_n = ntb_all;
+  // A block whose shared site list overflows is redone in chunks of SUB tets (smaller boxes, shorter lists), and a
+  // chunk that still overflows one tet at a time, each with its own candidates found among all of the shape's
+  // sites. A tet then goes to the large-capacity kernel only for reasons that depend on its own candidates (more
+  // than fit the list, or the clip budget), never on its neighbours' or on sites that own nothing in it: an
+  // incremental update, which recomputes a tet's pieces to take them back, must take the path that added them.
+  int sub = 0, sub_n = ntb_all, single_end = 0;  // tets [sub, single_end): one at a time
   bool split = false;
   while (true) {
   const int t0 = tb0 + sub;
   const int ntb = sub_n;
+  const bool single = single_end > sub;
   const unsigned long long cmask = item_mask >> sub;  // bit lt: tet t0 + lt is clipped
   if (split && !(cmask & (ntb >= 64 ? ~0ull : (1ull << ntb) - 1ull))) {  // a chunk without such tets
-    sub += SUB;
-    if (sub >= ntb_all) break;
-    sub_n = min(SUB, ntb_all - sub);
+    if (!next_chunk(sub, sub_n, single_end, ntb_all)) break;
     continue;
   }
   int tpt = TPT;  // threads per tet in the candidate phase
@@ -520,7 +541,7 @@ __global__ __launch_bounds__(NT) void k_clip_fast(ShapeArgs a) {
   //        the caches: on chip, the LDS budget goes to the polytopes, so that more workgroups fit a compute unit)
   float lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
   if (tid < TB) {
-    if (tid < ntb && ((cmask >> tid) & 1ull)) {
+    if (!single && tid < ntb && ((cmask >> tid) & 1ull)) {
       const float4* tp = sd.tp + 4 * (size_t)(t0 + tid);
       for (int v = 0; v < 4; ++v) {
         float4 p = tp[v];
@@ -545,11 +566,50 @@ __global__ __launch_bounds__(NT) void k_clip_fast(ShapeArgs a) {
   __syncthreads();
 
   // ---- 2. sites that can own a point of the box: min over the box of g_j <= min over j of max over the box
-  //        (g_j(x) = d_j(x) - |x - o|^2 is affine; values exact in FP64)
+  //        (g_j(x) = d_j(x) - |x - o|^2 is affine; values exact in FP64); for a single tet, the same test on the
+  //        tet itself (its exact candidates)
+  const float4* ssite = a.site + sd.site_off;
+  if (single) {
+    const float4* tv = sd.tp + 4 * (size_t)t0;
+    const float4 o = tv[0];
+    double y[3][3];
+    for (int v = 1; v < 4; ++v) {
+      y[v - 1][0] = (double)tv[v].x - o.x;
+      y[v - 1][1] = (double)tv[v].y - o.y;
+      y[v - 1][2] = (double)tv[v].z - o.z;
+    }
+    double umin = INFINITY;
+    for (int j = tid; j < sd.ns; j += NT) {
+      const float4 s = ssite[j];
+      const double ax_ = (double)s.x - o.x, ay_ = (double)s.y - o.y, az_ = (double)s.z - o.z;
+      const double D = ax_ * ax_ + ay_ * ay_ + az_ * az_ - (double)s.w * s.w;
+      double gmx = D;
+      for (int v = 0; v < 3; ++v) gmx = fmax(gmx, D - 2.0 * (y[v][0] * ax_ + y[v][1] * ay_ + y[v][2] * az_));
+      umin = fmin(umin, gmx);
+    }
+    umin = wave_min(umin);
+    if (lane == 0) s_red[wid] = umin;
+    __syncthreads();
+    double U = s_red[0];
+    for (int w = 1; w < NT / 64; ++w) U = fmin(U, s_red[w]);
+    for (int j = tid; j < sd.ns; j += NT) {
+      const float4 s = ssite[j];
+      const double ax_ = (double)s.x - o.x, ay_ = (double)s.y - o.y, az_ = (double)s.z - o.z;
+      const double D = ax_ * ax_ + ay_ * ay_ + az_ * az_ - (double)s.w * s.w;
+      double gmn = D;
+      for (int v = 0; v < 3; ++v) gmn = fmin(gmn, D - 2.0 * (y[v][0] * ax_ + y[v][1] * ay_ + y[v][2] * az_));
+      if (gmn <= U) {
+        const int q = atomicAdd(&s_nsl, 1);
+        if (q < SLMAX) {
+          s_site[q] = s;
+          s_sid[q] = sd.site_off + j;
+        }
+      }
+    }
+  } else {
   const double bx = s_box[0], by = s_box[1], bz = s_box[2];
   const double ex = (double)s_box[3] - bx, ey = (double)s_box[4] - by, ez = (double)s_box[5] - bz;
   double umin = INFINITY;
-  const float4* ssite = a.site + sd.site_off;
   for (int j = tid; j < sd.ns; j += NT) {
     float4 s = ssite[j];
     double ax_ = (double)s.x - bx, ay_ = (double)s.y - by, az_ = (double)s.z - bz;
@@ -575,14 +635,24 @@ __global__ __launch_bounds__(NT) void k_clip_fast(ShapeArgs a) {
       }
     }
   }
+  }
   __syncthreads();
   const int nsl = s_nsl;
-  if (nsl > SLMAX && !split && ntb > SUB && !(a.flags & RPD_FORCE_SLOW_PATH)) {
-    split = true;
-    sub_n = SUB;
-    if (tid == 0) stat_add(a, C_SPLIT, 1ull);
-    __syncthreads();
-    continue;
+  if (nsl > SLMAX && !(a.flags & RPD_FORCE_SLOW_PATH)) {
+    if (!split && ntb > SUB) {  // chunks of SUB tets
+      split = true;
+      sub_n = SUB;
+      if (tid == 0) stat_add(a, C_SPLIT, 1ull);
+      __syncthreads();
+      continue;
+    }
+    if (!single) {  // one tet at a time, each with its exact candidates
+      split = true;
+      single_end = sub + ntb;
+      sub_n = 1;
+      __syncthreads();
+      continue;
+    }
   }
   const bool block_overflow = nsl > SLMAX || (a.flags & RPD_FORCE_SLOW_PATH);
 
@@ -810,10 +880,7 @@ __global__ __launch_bounds__(NT) void k_clip_fast(ShapeArgs a) {
     s_acc_chi[q] = 0;
     s_acc_np[q] = 0;
   }
-  if (!split) break;
-  sub += SUB;
-  if (sub >= ntb_all) break;
-  sub_n = min(SUB, ntb_all - sub);
+  if (!split || !next_chunk(sub, sub_n, single_end, ntb_all)) break;
   __syncthreads();  // the next chunk reuses every shared array
   }
   __syncthreads();  // the next item reuses every shared array

@@ -39,7 +39,7 @@ constexpr int ST_INVALID = 16;       // invalid site value (off grid, out of ran
 // counters (ShapeArgs::counters)
 enum {
   C_PAIRS = 0, C_CAND, C_FP64, C_EXACT, C_DEFER_ITEMS, C_GLUE, C_RPV, C_PIECES, C_NODES,
-  C_DEFER_BLOCK,  // tets deferred because the workgroup's site list overflowed
+  C_DEFER_BLOCK,  // tets deferred because their own candidates overflow the workgroup's site list
   C_DEFER_KMAX,   // tets deferred because they kept more than the candidate budget
   C_DEFER_CLIP,   // pieces deferred because the polytope outgrew the vertex slots
   C_SPLIT,        // workgroup blocks redone in chunks because their site list overflowed

@@ -73,6 +73,32 @@ def test_session_equals_rebuild():
     assert info["n_dirty_blocks"] < info["n_blocks"] * info["rounds"]
 
 
+def test_session_dense_sites_equals_rebuild():
+    """Dense sites, where workgroup site lists overflow and tets are taken one at a time with their own candidates:
+    a tet's path depends on its own candidates only, so the rounds' removals take back exactly what was added and
+    the state stays equal to a rebuild bit for bit (volumes included)."""
+    from paper_2403_18761_amd import rpd
+
+    prob = synth.torus_inside(16, 4000, 3)  # about 5 sites per tet; 6 cells violate the topology constraints
+    table = synth.centroid_table(prob, 0.03)
+    log(f"case: session dense torus N16 n4000 tets {prob.n_tets}")
+    mesh = _mesh(prob)
+    st = _rebuild(mesh, np.stack([prob.sx, prob.sy, prob.sz, prob.sr], axis=1))["stats"]
+    log("initial build: split", st["n_split"], "deferred", st["n_defer_block"], st["n_defer_kmax"])
+    assert st["n_split"] > 0
+    sess = rpd.Session(mesh, (_dev(prob.sx), _dev(prob.sy), _dev(prob.sz), _dev(prob.sr)),
+                       tuple(_dev(x) for x in table), max_sites=4000 + 4 * 64, max_insert=64)
+    for rounds in (1, 2, 3):
+        sess.run(1)
+        info = sess.info()
+        res = sess.result()
+        cur = extract(res, 0)
+        cur["stats"] = res.stats()
+        _same(cur, _rebuild(mesh, sess.sites()), f"dense torus after {info['rounds']} rounds")
+    log("session", info)
+    assert info["n_inserted"] > 0
+
+
 @pytest.mark.parametrize("rounds", [1, 4])
 def test_session_matches_oracle(rounds):
     """The oracle runs the same insertion loop on its own results (oracle.repair): the session inserts the same

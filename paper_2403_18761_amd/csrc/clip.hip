@@ -818,23 +818,26 @@ __global__ __launch_bounds__(NT) void k_clip_fast(ShapeArgs a) {
         s_over[atomicAdd(&s_nover, 1)] = (lt << 16) | ci;
       }
     }
-    // Pieces that ran out of vertex slots are redone here, one per thread, with a BIG_VCAP-slot polytope in a
-    // global-memory record (they would otherwise wait for the deferred kernel, after this one). Which path computes
-    // a piece must depend on the piece alone (an incremental update must take back exactly the bits it added), so
-    // a full record pool is a table overflow (the call is redone with larger buffers), never a reason to defer.
+    // Pieces that ran out of vertex slots are redone here, one per thread, with a BIG_VCAP-slot polytope (they
+    // would otherwise wait for the deferred kernel, after this one). The round's small polytopes are dead by now,
+    // so the first records live in their LDS; more go to a global-memory pool (same arithmetic, same bits). Which
+    // path computes a piece must depend on the piece alone (an incremental update must take back exactly the bits
+    // it added), so a full pool is a table overflow (the call is redone with larger buffers), never a deferral.
     __syncthreads();
     const int nover = s_nover;
     if (nover) {
       if (tid < nover) {
         const int lt = s_over[tid] >> 16, ci = s_over[tid] & 0xffff, m = s_m[lt];
+        constexpr size_t CB = sizeof(typename Coord4<T>::type) * BIG_VCAP;
+        constexpr size_t REC = (CB + 8 * BIG_VCAP + 64 + 15) / 16 * 16;
+        constexpr int NLDS = (int)(sizeof(s_share) / REC);
+        static_assert(CB + 8 * BIG_VCAP + 32 <= BIG_BYTES, "large-capacity polytope record");
         const unsigned long long slot = atomicAdd(&a.counters[C_BIG], 1ull);
-        if (slot >= (unsigned long long)a.big_cap) {
+        if (tid >= NLDS && slot >= (unsigned long long)a.big_cap) {
           atomicOr(a.status, ST_TABLE_FULL);
         } else {
-          unsigned char* b = a.big + slot * BIG_BYTES;
+          unsigned char* b = tid < NLDS ? s_share + (size_t)tid * REC : a.big + slot * BIG_BYTES;
           Clipper<T, Topo64, unsigned long long, BIG_VCAP, false, MemTab> cb;
-          constexpr size_t CB = sizeof(typename Coord4<T>::type) * BIG_VCAP;
-          static_assert(CB + 8 * BIG_VCAP + 32 <= BIG_BYTES, "large-capacity polytope record");
           cb.st.c = reinterpret_cast<typename Coord4<T>::type*>(b);
           cb.st.w = reinterpret_cast<unsigned long long*>(b + CB);
           cb.st.stride = 1;

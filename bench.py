@@ -96,7 +96,7 @@ def workload(name):
     raise SystemExit(f"unknown workload {name}")
 
 
-def time_builds(meshes, sites, precision, steps, warmup, stream, block=0, clip_budget=0, flags=0):
+def time_builds(meshes, sites, precision, steps, warmup, stream, block=0, clip_budget=0, flags=0, slots=0):
     """Times `steps` rpd_build calls (each returns with its results on the host, its stream synchronised).
     Returns a dict: mean ms per call over the timed region, median and p90 of the per-call times, the mean
     HIP-event time of the fast clipping kernel, the pieces and the last call's statistics."""
@@ -105,7 +105,7 @@ def time_builds(meshes, sites, precision, steps, warmup, stream, block=0, clip_b
     from paper_2403_18761_amd import rpd
 
     flags |= rpd.RPD_TIMING
-    kw = dict(precision=precision, flags=flags, stream=stream, block=block, clip_budget=clip_budget)
+    kw = dict(precision=precision, flags=flags, stream=stream, block=block, clip_budget=clip_budget, slots=slots)
     for _ in range(warmup):
         rpd.build(meshes, sites, **kw)
     torch.cuda.synchronize()
@@ -146,7 +146,8 @@ def batch_comparison(args, stream):
     prep_s = time.perf_counter() - t0
     tuned = rpd.autotune(meshes, sites, stream=stream)
     steps = args.batch_steps
-    a = time_builds(meshes, sites, rpd.RPD_FP32_FALLBACK, steps, 1, stream, tuned["block"], tuned["clip_budget"])
+    a = time_builds(meshes, sites, rpd.RPD_FP32_FALLBACK, steps, 1, stream, tuned["block"], tuned["clip_budget"],
+                    slots=tuned["slots"])
     b = time_builds(meshes, sites, rpd.RPD_FP64, steps, 1, stream)
     assert a["n_pairs"] == b["n_pairs"]
     out = {"workload": WORKLOADS["batch256"]["desc"], "n_tets": sum(p.n_tets for p in probs),
@@ -165,7 +166,7 @@ def invariants(meshes, sites, tuned):
     partition each mesh, Euler additivity over the diagram equals the mesh's chi, every live element has beta0 >= 1."""
     from paper_2403_18761_amd import rpd
 
-    res = rpd.build(meshes, sites, block=tuned["block"], clip_budget=tuned["clip_budget"])
+    res = rpd.build(meshes, sites, block=tuned["block"], clip_budget=tuned["clip_budget"], slots=tuned["slots"])
     worst_vol, bad = 0.0, 0
     medial = {"chi_mismatch_after_thinning": 0, "thin_ms": 0.0, "tets_left": 0}
     for k, m in enumerate(meshes):
@@ -353,9 +354,10 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-estimated", action="store_true",
                     help="skip the timing of the same builds in the static-estimate dispatch order")
-    ap.add_argument("--no-autotune", action="store_true", help="use the default launch shape (64 threads, k=28)")
-    ap.add_argument("--launch", default=None, metavar="BLOCK,K",
-                    help="use this launch shape (threads per workgroup, clip budget) instead of autotuning")
+    ap.add_argument("--no-autotune", action="store_true", help="use the default launch shape (64 threads, k=28, 16 vertex slots)")
+    ap.add_argument("--launch", default=None, metavar="BLOCK,K[,SLOTS]",
+                    help="use this launch shape (threads per workgroup, clip budget, vertex slots: 16 if not given) "
+                         "instead of autotuning")
     ap.add_argument("--cpu-frac", type=float, default=None)
     ap.add_argument("--no-batch", action="store_true",
                     help="torus workload: skip the 256-shape batch comparison of FP32 + fallback against all-FP64")
@@ -439,16 +441,16 @@ def main():
     torch.cuda.synchronize()
     # the autotuner picks the launch shape for this bucket of shapes (untimed); rpd_build then uses it
     if args.launch:
-        b, k = (int(x) for x in args.launch.split(","))
-        tuned = {"block": b, "clip_budget": k}
+        v = [int(x) for x in args.launch.split(",")]
+        tuned = {"block": v[0], "clip_budget": v[1], "slots": v[2] if len(v) > 2 else 16}
     elif args.no_autotune:
-        tuned = {"block": 64, "clip_budget": 28}
+        tuned = {"block": 64, "clip_budget": 28, "slots": 16}
     else:
         tuned = rpd.autotune(meshes, sites, stream=stream)
     print(f"# autotuned launch shape: {tuned}", file=sys.stderr, flush=True)
 
     f32 = time_builds(meshes, sites, rpd.RPD_FP32_FALLBACK, args.steps, args.warmup, stream, tuned["block"],
-                      tuned["clip_budget"])
+                      tuned["clip_budget"], slots=tuned["slots"])
     pairs, st32 = f32["n_pairs"], f32["stats"]
     print(f"# fp32+fallback: {f32['ms']:.3f} ms/RPD (median {f32['ms_median']:.3f}, p90 {f32['ms_p90']:.3f}), clip "
           f"kernel {f32['clip_ms']:.3f} ms, pairs {pairs}", file=sys.stderr, flush=True)
@@ -456,13 +458,13 @@ def main():
     est = None
     if not args.no_estimated:
         e = time_builds(meshes, sites, rpd.RPD_FP32_FALLBACK, args.steps, 1, stream, tuned["block"],
-                        tuned["clip_budget"], flags=rpd.RPD_ESTIMATED_ORDER)
+                        tuned["clip_budget"], flags=rpd.RPD_ESTIMATED_ORDER, slots=tuned["slots"])
         est = {"ms_per_rpd": e["ms"], "ms_median": e["ms_median"], "clip_kernel_ms": e["clip_ms"]}
         print(f"# fp32+fallback, estimated dispatch order: {e['ms']:.3f} ms/RPD, clip kernel {e['clip_ms']:.3f} ms",
               file=sys.stderr, flush=True)
     # the same builds without dispatching heavy blocks in parts
     ns_ = time_builds(meshes, sites, rpd.RPD_FP32_FALLBACK, args.steps, 1, stream, tuned["block"],
-                      tuned["clip_budget"], flags=rpd.RPD_NO_SPLIT)
+                      tuned["clip_budget"], flags=rpd.RPD_NO_SPLIT, slots=tuned["slots"])
     nosplit = {"ms_per_rpd": ns_["ms"], "ms_median": ns_["ms_median"], "clip_kernel_ms": ns_["clip_ms"]}
     print(f"# fp32+fallback, heavy blocks not split: {ns_['ms']:.3f} ms/RPD, clip kernel {ns_['clip_ms']:.3f} ms",
           file=sys.stderr, flush=True)
@@ -477,7 +479,7 @@ def main():
 
     fpp = flop_per_piece(args.workload)
     achieved = fpp * pairs / (f32["clip_ms"] * 1e-3) / 1e12
-    kernel = f"k_clip_fast<float,{tuned['block']}>"
+    kernel = f"k_clip_fast<float,{tuned['block']},{tuned['slots'] if tuned['block'] == 64 else 16}>"
     cnt = measured_counters(args.workload, kernel, tuned) if len(probs) == 1 else None
     roof = {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
             "frac": achieved / PEAK_FP32_TFLOPS, "traffic": cnt["bytes_per_launch"] if cnt else None,

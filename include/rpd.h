@@ -113,6 +113,10 @@ typedef struct rpd_opts {
                           (the FP64 path always runs 64) */
   uint32_t flags;      /* RPD_* flags above */
   void* stream;        /* hipStream_t to run on; NULL = the null stream */
+  int32_t slots;       /* vertex slots per piece polytope of the 64-thread FP32 clipping kernel: 0 = tuned or 16;
+                          16 (six workgroups per compute unit) or 12 (eight: two waves per SIMD, at the cost of
+                          more pieces redone with 64 slots and more blocks split); blocks of 128 or 256 threads
+                          and the FP64 path use 16. Every value gives the same elements */
 } rpd_opts;
 
 typedef struct rpd_stats {
@@ -274,12 +278,15 @@ rpd_status rpd_piece_terms(const rpd_result* r, int32_t shape, int32_t kind, int
 void rpd_free(rpd_result* r);
 
 /* Autotuner for the batched FP32 path: runs rpd_build on these inputs once per launch shape (block of 64, 128 or 256
- * threads x clip budget 8, 16 or 28, each timed by HIP events over the clipping kernels, best of two after a warm-up),
- * writes the fastest into *best (a copy of *opts with block and clip_budget set; the default 64 x 28 is kept unless
- * another shape is more than 2% faster) and caches it for the process under
- * the bucket (floor log2 of the mean sites per shape, floor log2 of the mean tets per shape). Later rpd_build calls
- * whose block or clip_budget is 0 take the cached value of their bucket (else 64 and 28), and so does a session. Every launch shape gives
- * identical results; only the time differs. Synchronises. Errors as rpd_build; RPD_E_INVALID for RPD_FP64. */
+ * threads x clip budget 8, 16 or 28 with 16 vertex slots, and 64 threads with 12 slots x budget 16 or 28), each
+ * timed by HIP events over the clipping kernels, best of two after a warm-up, writes the fastest into *best (a copy
+ * of *opts with block, clip_budget and slots set; the default 64 x 28 x 16 is kept unless another shape is more than
+ * 2% faster) and caches it for the process under the bucket (floor log2 of the mean sites per shape, floor log2 of
+ * the mean tets per shape). Later rpd_build calls take the cached value of their bucket for each of block,
+ * clip_budget and slots that is 0 (else 64, 28 and 16), and so does a session. Every launch shape gives the same
+ * elements (keys, chi, beta0); a piece that one shape defers to the large-capacity kernel and another does not has
+ * its geometry built in FP64 instead of FP32, which can move volumes and moments in their last bits. Synchronises.
+ * Errors as rpd_build; RPD_E_INVALID for RPD_FP64. */
 rpd_status rpd_autotune(const rpd_mesh* const* meshes, const rpd_sites* sites, int32_t n_shapes, const rpd_opts* opts,
                         rpd_opts* best);
 

@@ -148,6 +148,11 @@ static void d2h(std::vector<T>& v, const void* src, size_t n, hipStream_t s) {
   if (n) hip_check(hipMemcpyAsync(v.data(), src, sizeof(T) * n, hipMemcpyDeviceToHost, s), "download");
 }
 
+// vertex slots per piece of the FP32 fast kernel: 12 only where asked for with 64 threads, else 16
+static int fast_slots(const rpd_opts& o) {
+  return (o.precision == RPD_FP32_FALLBACK && (o.block == 0 || o.block == 64) && o.slots == 12) ? 12 : 16;
+}
+
 // ---------------------------------------------------------------------------------------------------------------
 // Device state of one computation: tables, accumulators, counters. Used once by rpd_build and kept across rounds
 // by a session.
@@ -171,7 +176,7 @@ struct DeviceState {
   void totals(unsigned long long* out, hipStream_t s, int* status_out = nullptr) const;
   size_t touch_words() const { return ((size_t)ns_cap + capF + capE + 3) / 4; }
 
-  void alloc(int n_shapes, int ns, long long nt, int scale, bool keep_pieces, bool keep_U) {
+  void alloc(int n_shapes, int ns, long long nt, int scale, bool keep_pieces, bool keep_U, int slots) {
     nsh = n_shapes;
     ns_cap = ns;
     nt_tot = nt;
@@ -210,9 +215,11 @@ struct DeviceState {
     // candidate lists of deferred tets and pieces (a few per cent of the tets on the heaviest workloads)
     list_cap = (int)std::min<size_t>((nt / 8 + 4096) * (size_t)scale, (1u << 25) - 1);
     dlist.alloc(sizeof(int) * KRAW * (size_t)list_cap);
-    // pieces over VMAX vertices: about 1 in 10^4 on the benchmark shapes; an incremental session gets room for
-    // four times as many per pass as a build (its pool must never run out)
-    big_cap = (int)std::min<size_t>((nt / (keep_U ? 64 : 256) + 1024) * (size_t)scale, 1u << 20);
+    // pieces over the fast kernel's vertex slots: about 1 in 10^4 on the benchmark shapes with 16 slots, up to 1 in
+    // 10^2 with 12; an incremental session gets room for four times as many per pass as a build (its pool must
+    // never run out)
+    const long long per_big = slots == 12 ? (keep_U ? 8 : 32) : (keep_U ? 64 : 256);
+    big_cap = (int)std::min<size_t>((nt / per_big + 1024) * (size_t)scale, 1u << 20);
     bigp.alloc(BIG_BYTES * (size_t)big_cap);
     pieces.alloc(sizeof(PieceRec) * (size_t)std::max(piece_cap, 1));
     terms.alloc(sizeof(TermRec) * (size_t)std::max(term_cap, 1));
@@ -824,7 +831,7 @@ static bool run_batch(const rpd_mesh* const* meshes, const rpd_sites* sites, int
   std::vector<ShapeDesc> hd = shape_table(meshes, nsites.data(), nsh, &ns_tot, &nt_tot);
   // the tables are cleared on the device while the host orders the work
   DeviceState D;
-  D.alloc(nsh, (int)ns_tot, nt_tot, scale, (o.flags & RPD_KEEP_PIECES) != 0, false);
+  D.alloc(nsh, (int)ns_tot, nt_tot, scale, (o.flags & RPD_KEEP_PIECES) != 0, false, fast_slots(o));
   D.clear(s);
   std::vector<int2> items = work_items(hd, meshes, o.flags);
   if (o.flags & RPD_SHUFFLE_QUEUE) {  // a fixed permutation: results must not depend on the processing order
@@ -866,7 +873,7 @@ static bool run_batch(const rpd_mesh* const* meshes, const rpd_sites* sites, int
   a.item_cost = dcost.as<unsigned>();
   Timing tm((o.flags & RPD_TIMING) != 0);
   tm.mark(0, s);
-  hip_check(launch_clip_fast(a, o.precision, o.block, s), "clip kernel");
+  hip_check(launch_clip_fast(a, o.precision, o.block, fast_slots(o), s), "clip kernel");
   tm.mark(1, s);
   if (!items.empty())  // read by the host after collect's synchronisation
     hip_check(hipMemcpyAsync(ticks_host.p, dcost.p, sizeof(unsigned) * items.size(), hipMemcpyDeviceToHost, s),
@@ -960,6 +967,7 @@ static void check_opts(const rpd_opts& o) {
     throw Failure{RPD_E_INVALID, "clip_budget must be 0 or in [4, 28]"};
   if (o.block != 0 && o.block != 64 && o.block != 128 && o.block != 256)
     throw Failure{RPD_E_INVALID, "block must be 0, 64, 128 or 256"};
+  if (o.slots != 0 && o.slots != 12 && o.slots != 16) throw Failure{RPD_E_INVALID, "slots must be 0, 12 or 16"};
 }
 
 static void check_shapes(const rpd_mesh* const* meshes, const rpd_sites* sites, int32_t n_shapes) {
@@ -973,10 +981,15 @@ static void check_shapes(const rpd_mesh* const* meshes, const rpd_sites* sites, 
   }
 }
 
-// Autotuner cache: launch shape (block, clip budget) of the FP32 path per (log2 mean sites per shape, log2 mean tets
-// per shape) bucket, filled by rpd_autotune and read by rpd_build when block or clip_budget is 0.
+// Autotuner cache: launch shape (block, clip budget, vertex slots) of the FP32 path per (log2 mean sites per shape,
+// log2 mean tets per shape) bucket, filled by rpd_autotune and read by rpd_build where block, clip_budget or slots
+// is 0.
+struct TuneShape {
+  int block, budget, slots;
+};
 static std::mutex g_tune_mu;
-static std::map<std::pair<int, int>, std::pair<int, int>> g_tune;
+static std::map<std::pair<int, int>, TuneShape> g_tune;
+
 
 static std::pair<int, int> tune_bucket(const rpd_mesh* const* meshes, const rpd_sites* sites, int32_t n) {
   double ns = 0, nt = 0;
@@ -985,6 +998,16 @@ static std::pair<int, int> tune_bucket(const rpd_mesh* const* meshes, const rpd_
     nt += meshes[k]->nt;
   }
   return {(int)std::floor(std::log2(std::max(1.0, ns / n))), (int)std::floor(std::log2(std::max(1.0, nt / n)))};
+}
+
+static void apply_tuned(rpd_opts& o, const rpd_mesh* const* meshes, const rpd_sites* sites, int32_t n) {
+  if (o.precision != RPD_FP32_FALLBACK || (o.block != 0 && o.clip_budget != 0 && o.slots != 0)) return;
+  std::lock_guard<std::mutex> g(g_tune_mu);
+  auto it = g_tune.find(tune_bucket(meshes, sites, n));
+  if (it == g_tune.end()) return;
+  if (o.block == 0) o.block = it->second.block;
+  if (o.clip_budget == 0) o.clip_budget = it->second.budget;
+  if (o.slots == 0) o.slots = it->second.slots;
 }
 
 static bool run_with_retry(const rpd_mesh* const* meshes, const rpd_sites* sites, int32_t n_shapes, const rpd_opts& o,
@@ -1006,14 +1029,7 @@ rpd_status rpd_build(const rpd_mesh* const* meshes, const rpd_sites* sites, int3
   if (opts) o = *opts;
   check_opts(o);
   check_shapes(meshes, sites, n_shapes);
-  if (o.precision == RPD_FP32_FALLBACK && (o.block == 0 || o.clip_budget == 0)) {
-    std::lock_guard<std::mutex> g(g_tune_mu);
-    auto it = g_tune.find(tune_bucket(meshes, sites, n_shapes));
-    if (it != g_tune.end()) {
-      if (o.block == 0) o.block = it->second.first;
-      if (o.clip_budget == 0) o.clip_budget = it->second.second;
-    }
-  }
+  apply_tuned(o, meshes, sites, n_shapes);
   rpd_result* r = new rpd_result();
   std::memset(&r->stats, 0, sizeof(r->stats));
   try {
@@ -1044,14 +1060,16 @@ rpd_status rpd_autotune(const rpd_mesh* const* meshes, const rpd_sites* sites, i
   o.flags &= ~(uint32_t)RPD_KEEP_PIECES;
   // the default shape (64 threads, the full budget) is timed first; another shape replaces it only when it is
   // faster by more than 2%, so that shapes within the timing noise do not alternate from run to run
-  const int cand[9][2] = {{64, rpd::KMAX}, {64, 8}, {64, 16}, {128, 8}, {128, 16}, {128, rpd::KMAX},
-                          {256, 8}, {256, 16}, {256, rpd::KMAX}};
+  const int cand[11][3] = {{64, rpd::KMAX, 16}, {64, 8, 16},  {64, 16, 16},  {128, 8, 16},         {128, 16, 16},
+                           {128, rpd::KMAX, 16}, {256, 8, 16}, {256, 16, 16}, {256, rpd::KMAX, 16}, {64, rpd::KMAX, 12},
+                           {64, 16, 12}};
   double best_ms = INFINITY;
-  int bb = 64, bk = rpd::KMAX;
+  int bb = 64, bk = rpd::KMAX, bs = 16;
   for (const auto& sh : cand) {
     rpd_opts c = o;
     c.block = sh[0];
     c.clip_budget = sh[1];
+    c.slots = sh[2];
     double ms = INFINITY;
     for (int rep = 0; rep < 3; ++rep) {  // the first run warms the allocator and the caches
       std::vector<rpd::ShapeOut> shapes(n_shapes);
@@ -1065,15 +1083,17 @@ rpd_status rpd_autotune(const rpd_mesh* const* meshes, const rpd_sites* sites, i
       best_ms = ms;
       bb = sh[0];
       bk = sh[1];
+      bs = sh[2];
     }
   }
   {
     std::lock_guard<std::mutex> g(g_tune_mu);
-    g_tune[tune_bucket(meshes, sites, n_shapes)] = {bb, bk};
+    g_tune[tune_bucket(meshes, sites, n_shapes)] = {bb, bk, bs};
   }
   *best = opts ? *opts : o;
   best->block = bb;
   best->clip_budget = bk;
+  best->slots = bs;
   return RPD_OK;
   RPD_GUARD_END
 }
@@ -1265,7 +1285,7 @@ static void clip_pass(rpd_session* S, const ShapeArgs& a) {
   hip_check(launch_fill_u64(S->D.cnt() + C_DEFER_ITEMS, 0, 1, S->stream), "fill");
   hip_check(launch_fill_u64(S->D.cnt() + C_DEFER2, 0, 1, S->stream), "fill");
   hip_check(launch_fill_u64(S->D.cnt() + C_LISTS, 0, 2, S->stream), "fill");  // C_LISTS and C_BIG
-  hip_check(launch_clip_fast(a, S->o.precision, S->o.block, S->stream), "clip kernel");
+  hip_check(launch_clip_fast(a, S->o.precision, S->o.block, fast_slots(S->o), S->stream), "clip kernel");
   hip_check(launch_clip_slow(a, S->D.slow.as<unsigned char>(), S->D.waves, S->stream), "deferred clip kernel");
 }
 
@@ -1277,7 +1297,7 @@ static bool session_init(rpd_session* S, const rpd_sites* sites, const rpd_sites
   const int nt = m->nt, nblk = m->nblk;
   if (nblk >= (1 << ITEM_PART_SHIFT)) throw Failure{RPD_E_INVALID, "mesh with 2^20 or more workgroup blocks"};
   DeviceState& D = S->D;
-  D.alloc(1, S->max_sites, nt, scale, false, true);
+  D.alloc(1, S->max_sites, nt, scale, false, true, fast_slots(S->o));
   D.clear(s);
   std::vector<ShapeDesc> hd{S->hd};
   const SiteUpload su = upload_sites(D, sites, hd, dev, s);
@@ -1473,14 +1493,9 @@ rpd_status rpd_session_create(const rpd_mesh* mesh, const rpd_sites* sites, cons
   if (opts->insertion == RPD_INSERT_TABLE && !table) throw Failure{RPD_E_INVALID, "null table"};
   rpd_opts o = opts->build;
   check_opts(o);
-  if (o.precision == RPD_FP32_FALLBACK && (o.block == 0 || o.clip_budget == 0)) {  // the autotuner's launch shape
-    std::lock_guard<std::mutex> g(g_tune_mu);
+  {  // the autotuner's launch shape
     const rpd_mesh* ms1[1] = {mesh};
-    auto it = g_tune.find(tune_bucket(ms1, sites, 1));
-    if (it != g_tune.end()) {
-      if (o.block == 0) o.block = it->second.first;
-      if (o.clip_budget == 0) o.clip_budget = it->second.second;
-    }
+    apply_tuned(o, ms1, sites, 1);
   }
   if (o.flags & (RPD_KEEP_PIECES | RPD_FORCE_SLOW_PATH))
     throw Failure{RPD_E_INVALID, "RPD_KEEP_PIECES and RPD_FORCE_SLOW_PATH are not available in a session"};

@@ -128,17 +128,6 @@ __device__ inline void defer_piece(const ShapeArgs& a, int shape, int t, int sit
   else atomicOr(a.status, ST_TABLE_FULL);
 }
 
-// Workgroup-local sums of the cell terms (chi numerator, piece count, fixed-point volume and moments) for the first
-// n sites of the workgroup's site list; a piece of another site adds to the global arrays directly.
-struct CellSink {
-  long long* chi;  // [n] (LDS)
-  int* np;         // [n]
-  unsigned long long* geo_lo;  // [4 n] low words of the workgroup's 128-bit sums
-  int* geo_hi;                 // [4 n] their high words (a workgroup's sum stays below 2^84: 32 bits suffice)
-  int n;
-  int q;           // the piece's index in the workgroup's site list, or -1
-};
-
 __device__ inline long long fixed56(double v) { return llrint(v * 72057594037927936.0); }  // 2^-56 units
 
 // Cell volumes and first moments are exact sums of 128-bit integers in units of 2^-80 (resolution 8e-25, range
@@ -164,6 +153,17 @@ __device__ inline void acc128(unsigned long long* p, Fix128 v) {
   const long long h = v.hi + (old + v.lo < old ? 1 : 0);  // carry out of the low word
   if (h) atomicAdd(p + 1, (unsigned long long)h);
 }
+
+// Workgroup-local sums of the cell terms (chi numerator, piece count, fixed-point volume and moments) in n slots,
+// each holding one site of the workgroup's list; a piece whose site has no slot adds to the global arrays directly.
+struct CellSink {
+  long long* chi;  // [n] (LDS)
+  int* np;         // [n]
+  unsigned long long* geo_lo;  // [4 n] low words of the workgroup's 128-bit sums
+  int* geo_hi;                 // [4 n] their high words (a workgroup's sum stays below 2^84: 32 bits suffice)
+  int n;
+  int q;           // the slot of the piece's site, or -1 or >= n: none
+};
 
 template <typename T, typename Topo, typename Mask, int VCAP, bool EXACT, typename Tab>
 __device__ __forceinline__ void emit_piece(Clipper<T, Topo, Mask, VCAP, EXACT, Tab>& c, const ShapeDesc& sd, int tl, const ShapeArgs& a,
@@ -452,8 +452,30 @@ __device__ __forceinline__ int refine_candidates(const float4* tv, const float4*
   return m;
 }
 
-template <typename T, int NT>
+// Two LDS layouts of the fast kernel (64 threads). With 16 vertex slots per piece, 256 sites in the shared list, 40
+// raw candidates per tet and the cell sums of 32 sites, a workgroup takes about 27 KB and six fit a compute unit; with
+// 12 slots, 192 sites, 36 raw candidates and the sums of 16 sites it takes under 20 KB and eight fit (two waves per
+// SIMD). Pieces that outgrow their slots are redone inside the kernel with the 64-slot polytope, and a tet's path to
+// the large-capacity kernel depends on its own candidates only, so both layouts give the same elements; the 12-slot
+// one redoes more pieces and splits more blocks, and wins where occupancy, not the longest items, bounds the kernel.
+template <int SLOTS>
+struct FastCfg;
+template <>
+struct FastCfg<16> {
+  static constexpr int VCAP = 16, SL = 256, KR = 40, AGG64 = 32;
+  static constexpr bool USED_FIRST = false;
+};
+template <>
+struct FastCfg<12> {
+  static constexpr int VCAP = 12, SL = 192, KR = 36, AGG64 = 16;
+  static constexpr bool USED_FIRST = true;
+};
+
+template <typename T, int NT, int SLOTS>
 __global__ __launch_bounds__(NT) void k_clip_fast(ShapeArgs a) {
+  typedef FastCfg<SLOTS> FC;
+  constexpr int SLMAX = FC::SL, KRAW = FC::KR, VMAX = FC::VCAP;
+  static_assert(KRAW <= rpd::KRAW && SLMAX <= 256, "candidate bytes index the site list; hand-over lists hold rpd::KRAW");
   static_assert(NT % TB == 0 && NT >= TB, "threads per block must be a multiple of the tets per block");
   constexpr int TPT = NT / TB;  // threads per tet in the candidate phase
   __shared__ float4 s_site[SLMAX];
@@ -479,11 +501,18 @@ __global__ __launch_bounds__(NT) void k_clip_fast(ShapeArgs a) {
   // per-site sums of the workgroup's cell terms (the first 128 sites of the list, or the first 32 with 64 threads,
   // where the LDS budget for four workgroups per compute unit is tight); pieces of later sites add to the global
   // accumulators directly
-  constexpr int AGG = NT == 64 ? 32 : 128;
+  constexpr int AGG = NT == 64 ? FC::AGG64 : 128;
   __shared__ long long s_acc_chi[AGG];
   __shared__ int s_acc_np[AGG];
   __shared__ unsigned long long s_acc_lo[4 * AGG];
   __shared__ int s_acc_hi[4 * AGG];
+  // the sums' slot of each site of the list (255: none): with USED_FIRST, the sites that are candidates of a tet
+  // clipped here take the first AGG slots in list order, so that the few sums cover the sites that own the pieces;
+  // else slot q holds list position q (no map: its bytes would cost the 16-slot layout its sixth workgroup)
+  constexpr bool UF = FC::USED_FIRST;
+  __shared__ unsigned char s_agg[UF ? SLMAX : 1];
+  __shared__ unsigned char s_aggq[UF ? AGG : 1];  // the list position of each slot's site
+  __shared__ int s_nagg;
 
   const int tid = threadIdx.x;
   const int lane = tid & 63, wid = tid >> 6;
@@ -655,6 +684,8 @@ __global__ __launch_bounds__(NT) void k_clip_fast(ShapeArgs a) {
     }
   }
   const bool block_overflow = nsl > SLMAX || (a.flags & RPD_FORCE_SLOW_PATH);
+  if constexpr (UF)
+    for (int q = tid; q < min(nsl, SLMAX); q += NT) s_agg[q] = 0;
 
   // ---- 3. candidates of every tet: sites whose minimum over the tet is <= min_j max over the tet
   if (!block_overflow) {
@@ -757,6 +788,8 @@ __global__ __launch_bounds__(NT) void k_clip_fast(ShapeArgs a) {
       else atomicOr(a.status, ST_TABLE_FULL);
     } else {
       s_m[tid] = m;
+      if constexpr (UF)
+        for (int x = 0; x < m; ++x) s_agg[s_cand[tid][x]] = 1;
     }
   }
   __syncthreads();
@@ -772,6 +805,23 @@ __global__ __launch_bounds__(NT) void k_clip_fast(ShapeArgs a) {
     s_order[rank] = tid;
   }
   __syncthreads();
+  if (wid == 0) {
+    const int nl = min(nsl, SLMAX);
+    int nagg = nl;
+    if constexpr (UF) {
+      nagg = 0;
+      for (int c = 0; c < nl; c += 64) {
+        const int q = c + lane;
+        const bool used = q < nl && s_agg[q] != 0;
+        const unsigned long long mk = __ballot(used);
+        const int r = nagg + __popcll(mk & ((1ull << lane) - 1ull));
+        if (q < nl) s_agg[q] = (used && r < AGG) ? (unsigned char)r : (unsigned char)255;
+        if (used && r < AGG) s_aggq[r] = (unsigned char)q;
+        nagg += __popcll(mk);
+      }
+    }
+    if (lane == 0) s_nagg = min(nagg, AGG);
+  }
   if (tid == 0) {
     int acc = 0;
     for (int j = 0; j < TB; ++j) {
@@ -811,7 +861,8 @@ __global__ __launch_bounds__(NT) void k_clip_fast(ShapeArgs a) {
       n64 += cl.n64;
       if (r == CLIP_OK) {
         n_pairs += (unsigned long long)(long long)sd.sign;  // live pieces, in two's complement
-        emit_piece(cl, sd, t0 + lt, a, CellSink{s_acc_chi, s_acc_np, s_acc_lo, s_acc_hi, AGG, (int)s_cand[lt][ci]});
+        const int slot = UF ? (int)s_agg[s_cand[lt][ci]] : (int)s_cand[lt][ci];
+        emit_piece(cl, sd, t0 + lt, a, CellSink{s_acc_chi, s_acc_np, s_acc_lo, s_acc_hi, AGG, slot});
       } else if (r == CLIP_DEFER) {
         defer_piece(a, shape, t0 + lt, cl.env.site_i, s_cand[lt], s_sid, m);
       } else if (r == CLIP_FULL) {  // out of vertex slots: redone below, after this round
@@ -854,8 +905,8 @@ __global__ __launch_bounds__(NT) void k_clip_fast(ShapeArgs a) {
           n64 += cb.n64;
           if (r == CLIP_OK) {
             n_pairs += (unsigned long long)(long long)sd.sign;
-            emit_piece(cb, sd, t0 + lt, a, CellSink{s_acc_chi, s_acc_np, s_acc_lo, s_acc_hi, AGG,
-                                                    (int)s_cand[lt][ci]});
+            const int slot = UF ? (int)s_agg[s_cand[lt][ci]] : (int)s_cand[lt][ci];
+            emit_piece(cb, sd, t0 + lt, a, CellSink{s_acc_chi, s_acc_np, s_acc_lo, s_acc_hi, AGG, slot});
           } else if (r != CLIP_EMPTY) {  // a predicate undecided in FP64, or over BIG_VCAP vertices
             defer_piece(a, shape, t0 + lt, cb.env.site_i, s_cand[lt], s_sid, m);
           }
@@ -868,10 +919,10 @@ __global__ __launch_bounds__(NT) void k_clip_fast(ShapeArgs a) {
   }
   // flush the workgroup's cell sums of this pass (the site list changes with the next chunk)
   __syncthreads();
-  for (int q = tid; q < min(nsl, AGG); q += NT) {
+  for (int q = tid; q < s_nagg; q += NT) {  // q: the slot
     const int np_q = s_acc_np[q];
     if (np_q == 0) continue;
-    const int i = s_sid[q];
+    const int i = s_sid[UF ? (int)s_aggq[q] : q];
     atomicAdd((unsigned long long*)&a.cell_chi[i], (unsigned long long)(sd.sign * s_acc_chi[q]));
     atomicAdd(&a.cell_np[i], sd.sign * np_q);
     for (int d = 0; d < 4; ++d) {
@@ -1160,18 +1211,19 @@ __global__ __launch_bounds__(64, LDS ? 1 : 2) void k_clip_slow(ShapeArgs a, unsi
 // ---------------------------------------------------------------------------------------------------------------
 // launchers
 // ---------------------------------------------------------------------------------------------------------------
-template <typename T, int NT>
+template <typename T, int NT, int SLOTS>
 static hipError_t launch_items(const ShapeArgs& a, hipStream_t s) {
-  hipLaunchKernelGGL((k_clip_fast<T, NT>), dim3(a.nitems), dim3(NT), 0, s, a);
+  hipLaunchKernelGGL((k_clip_fast<T, NT, SLOTS>), dim3(a.nitems), dim3(NT), 0, s, a);
   return hipGetLastError();
 }
 
-hipError_t launch_clip_fast(const ShapeArgs& a, int precision, int block, hipStream_t s) {
+hipError_t launch_clip_fast(const ShapeArgs& a, int precision, int block, int slots, hipStream_t s) {
   if (a.nitems == 0) return hipSuccess;
-  if (precision == RPD_FP64) return launch_items<double, 64>(a, s);
-  if (block == 128) return launch_items<float, 128>(a, s);
-  if (block == 256) return launch_items<float, 256>(a, s);
-  return launch_items<float, 64>(a, s);  // 64 threads (also for block 0): five workgroups per compute unit
+  if (precision == RPD_FP64) return launch_items<double, 64, 16>(a, s);
+  if (block == 128) return launch_items<float, 128, 16>(a, s);
+  if (block == 256) return launch_items<float, 256, 16>(a, s);
+  if (slots == 12) return launch_items<float, 64, 12>(a, s);  // eight workgroups per compute unit
+  return launch_items<float, 64, 16>(a, s);  // 64 threads (also for block 0): six workgroups per compute unit
 }
 
 size_t slow_scratch_bytes(int waves) { return (size_t)waves * SlowScratch::bytes; }

@@ -389,23 +389,28 @@ struct Coord4<double> {
 };
 
 // vertex storage with a per-thread stride (LDS slices, stride = threads per block) or contiguous (global scratch)
-// (slot indices are masked to the power-of-two capacity so that every access stays inside the thread's slice)
+// (slot indices are masked to the capacity, or clamped below it when it is not a power of two, so that every access
+// stays inside the thread's slice; live slots are always below the capacity)
+template <int VCAP>
+__device__ __forceinline__ int vslot(int k) {
+  return (VCAP & (VCAP - 1)) == 0 ? (k & (VCAP - 1)) : min(k, VCAP - 1);
+}
 template <typename T, typename Topo, int VCAP>
 struct Store {
   typename Coord4<T>::type* c;
   typename Topo::W* w;
   int stride;
-  __device__ typename Coord4<T>::type get(int k) const { return c[(k & (VCAP - 1)) * stride]; }
+  __device__ typename Coord4<T>::type get(int k) const { return c[vslot<VCAP>(k) * stride]; }
   __device__ void put(int k, T x, T y, T z, T F) {
     typename Coord4<T>::type v;
     v.x = x;
     v.y = y;
     v.z = z;
     v.w = F;
-    c[(k & (VCAP - 1)) * stride] = v;
+    c[vslot<VCAP>(k) * stride] = v;
   }
-  __device__ typename Topo::W topo(int k) const { return w[(k & (VCAP - 1)) * stride]; }
-  __device__ void set_topo(int k, typename Topo::W t) { w[(k & (VCAP - 1)) * stride] = t; }
+  __device__ typename Topo::W topo(int k) const { return w[vslot<VCAP>(k) * stride]; }
+  __device__ void set_topo(int k, typename Topo::W t) { w[vslot<VCAP>(k) * stride] = t; }
   __device__ static typename Topo::W with_F(typename Topo::W t, T) { return t; }  // F is stored with the coordinates
   __device__ void bind(void* coords, typename Topo::W* topo_words, int lane, int nthreads) {
     c = reinterpret_cast<typename Coord4<T>::type*>(coords) + lane;
@@ -436,17 +441,17 @@ struct StoreP {
   unsigned* w;
   int stride;
   __device__ float4 get(int k) const {
-    const int o = (k & (VCAP - 1)) * stride;
+    const int o = vslot<VCAP>(k) * stride;
     const float2 p = xy[o];
     return make_float4(p.x, p.y, zz[o], decode_F(w[o] >> 27));
   }
   __device__ void put(int k, float x, float y, float z, float) {  // F travels in the topology word (with_F)
-    const int o = (k & (VCAP - 1)) * stride;
+    const int o = vslot<VCAP>(k) * stride;
     xy[o] = make_float2(x, y);
     zz[o] = z;
   }
-  __device__ unsigned topo(int k) const { return w[(k & (VCAP - 1)) * stride]; }
-  __device__ void set_topo(int k, unsigned t) { w[(k & (VCAP - 1)) * stride] = t; }
+  __device__ unsigned topo(int k) const { return w[vslot<VCAP>(k) * stride]; }
+  __device__ void set_topo(int k, unsigned t) { w[vslot<VCAP>(k) * stride] = t; }
   __device__ static unsigned with_F(unsigned t, float F) { return (t & 0x07ffffffu) | (encode_F(F) << 27); }
   __device__ void bind(void* coords, unsigned* topo_words, int lane, int nthreads) {
     xy = reinterpret_cast<float2*>(coords) + lane;
@@ -647,7 +652,6 @@ enum { CLIP_OK = 0, CLIP_EMPTY = 1, CLIP_DEFER = 2, CLIP_FULL = 3 };  // DEFER: 
 template <typename T, typename Topo, typename Mask, int VCAP, bool EXACT, typename Tab>
 struct Clipper {
   typedef typename Topo::W W;
-  static_assert((VCAP & (VCAP - 1)) == 0, "vertex capacity must be a power of two");
   typename StoreOf<T, Topo, VCAP>::type st;
   Tab tab;  // per plane id: 0 or (slot + 1); all zero between operations
   Mask live;

@@ -8,7 +8,7 @@
 namespace rpd {
 
 // clip.hip
-hipError_t launch_clip_fast(const ShapeArgs& a, int precision, int block, hipStream_t s);
+hipError_t launch_clip_fast(const ShapeArgs& a, int precision, int block, int slots, hipStream_t s);
 size_t slow_scratch_bytes(int waves);
 // the item count is read on the device from counters[C_DEFER_ITEMS] (no host synchronisation)
 hipError_t launch_clip_slow(const ShapeArgs& a, unsigned char* scratch, int waves, hipStream_t s);

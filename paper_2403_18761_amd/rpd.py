@@ -53,7 +53,7 @@ class _Sites(C.Structure):
 
 class _Opts(C.Structure):
     _fields_ = [("precision", C.c_int32), ("clip_budget", C.c_int32), ("block", C.c_int32), ("flags", C.c_uint32),
-                ("stream", C.c_void_p)]
+                ("stream", C.c_void_p), ("slots", C.c_int32)]
 
 
 class _Stats(C.Structure):
@@ -323,7 +323,7 @@ class Result:
 
 
 def build(meshes, sites, precision: int = RPD_FP32_FALLBACK, clip_budget: int = 0, block: int = 0,
-          flags: int = 0, stream=None) -> Result:
+          flags: int = 0, stream=None, slots: int = 0) -> Result:
     """rpd_build over shapes: ``meshes`` a list of Mesh, ``sites`` a list of (sx, sy, sz, sr) arrays or tensors."""
     lib = load()
     n = len(meshes)
@@ -335,15 +335,15 @@ def build(meshes, sites, precision: int = RPD_FP32_FALLBACK, clip_budget: int = 
         dev = dev or (_is_torch(sx) and sx.is_cuda)
         st[k] = _Sites(int(sx.shape[0]), _ptr(sx, C.c_float, keep), _ptr(sy, C.c_float, keep),
                        _ptr(sz, C.c_float, keep), _ptr(sr, C.c_float, keep))
-    o = _Opts(precision, clip_budget, block, flags | (RPD_DEVICE_PTRS if dev else 0), _stream_ptr(stream))
+    o = _Opts(precision, clip_budget, block, flags | (RPD_DEVICE_PTRS if dev else 0), _stream_ptr(stream), slots)
     h = C.c_void_p()
     _check(lib.rpd_build(handles, st, n, C.byref(o), C.byref(h)))
     return Result(h, n)
 
 
 def autotune(meshes, sites, flags: int = 0, stream=None) -> dict:
-    """rpd_autotune: time every launch shape on these inputs; returns the chosen {"block", "clip_budget"} (also
-    cached in the library for rpd_build calls that leave them at 0)."""
+    """rpd_autotune: time every launch shape on these inputs; returns the chosen {"block", "clip_budget", "slots"}
+    (also cached in the library for rpd_build calls that leave them at 0)."""
     lib = load()
     n = len(meshes)
     keep = []
@@ -354,10 +354,10 @@ def autotune(meshes, sites, flags: int = 0, stream=None) -> dict:
         dev = dev or (_is_torch(sx) and sx.is_cuda)
         st[k] = _Sites(int(sx.shape[0]), _ptr(sx, C.c_float, keep), _ptr(sy, C.c_float, keep),
                        _ptr(sz, C.c_float, keep), _ptr(sr, C.c_float, keep))
-    o = _Opts(RPD_FP32_FALLBACK, 0, 0, flags | (RPD_DEVICE_PTRS if dev else 0), _stream_ptr(stream))
+    o = _Opts(RPD_FP32_FALLBACK, 0, 0, flags | (RPD_DEVICE_PTRS if dev else 0), _stream_ptr(stream), 0)
     best = _Opts()
     _check(lib.rpd_autotune(handles, st, n, C.byref(o), C.byref(best)))
-    return {"block": best.block, "clip_budget": best.clip_budget}
+    return {"block": best.block, "clip_budget": best.clip_budget, "slots": best.slots}
 
 
 def thin(n_vertices: int, edges, tris, alpha, tets, sigma: float):
@@ -482,7 +482,7 @@ class Session:
 
     def __init__(self, mesh: Mesh, sites, table, max_sites: int, max_insert: int = 64,
                  precision: int = RPD_FP32_FALLBACK, clip_budget: int = 0, block: int = 0, flags: int = 0,
-                 stream=None, insertion: int = RPD_INSERT_TABLE):
+                 stream=None, insertion: int = RPD_INSERT_TABLE, slots: int = 0):
         lib = load()
         keep = []
         dev = _is_torch(sites[0]) and sites[0].is_cuda
@@ -496,7 +496,7 @@ class Session:
         tb = mk(table) if table is not None else None
         o = _SessionOpts(max_sites, max_insert,
                          _Opts(precision, clip_budget, block, flags | (RPD_DEVICE_PTRS if dev else 0),
-                               _stream_ptr(stream)), insertion)
+                               _stream_ptr(stream), slots), insertion)
         h = C.c_void_p()
         _check(lib.rpd_session_create(mesh.handle, C.byref(st), C.byref(tb) if tb is not None else None, C.byref(o),
                                       C.byref(h)))

@@ -4,7 +4,7 @@ import sys
 import numpy as np
 
 
-def run_gpu(prob, precision=0, clip_budget=0, block=0, flags=0, device_ptrs=True):
+def run_gpu(prob, precision=0, clip_budget=0, block=0, flags=0, device_ptrs=True, slots=0):
     import torch
 
     from paper_2403_18761_amd import rpd
@@ -20,7 +20,8 @@ def run_gpu(prob, precision=0, clip_budget=0, block=0, flags=0, device_ptrs=True
     else:
         mesh = rpd.Mesh(prob.vx, prob.vy, prob.vz, prob.tv.reshape(-1))
         sites = (prob.sx, prob.sy, prob.sz, prob.sr)
-    res = rpd.build([mesh], [sites], precision=precision, clip_budget=clip_budget, block=block, flags=flags)
+    res = rpd.build([mesh], [sites], precision=precision, clip_budget=clip_budget, block=block, flags=flags,
+                    slots=slots)
     out = extract(res, 0)
     out["stats"] = res.stats()
     out["mesh_info"] = mesh.info()

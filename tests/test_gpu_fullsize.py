@@ -215,7 +215,8 @@ def run_full(prob, label, keep=True):
     best = rpd.autotune([mesh], [sites])
     log(label, "tets", prob.n_tets, "sites", prob.n_sites, "launch", best)
     flags = rpd.RPD_KEEP_PIECES if keep else 0
-    res = rpd.build([mesh], [sites], block=best["block"], clip_budget=best["clip_budget"], flags=flags)
+    res = rpd.build([mesh], [sites], block=best["block"], clip_budget=best["clip_budget"], slots=best["slots"],
+                    flags=flags)
     g = extract(res, 0)
     g["stats"] = res.stats()
     g["radii"] = np.asarray(prob.sr, np.float64)
@@ -234,17 +235,21 @@ def test_fullsize_torus():
     prob = synth.torus_inside(64, 2000, 2)
     g, res, info = run_full(prob, "torus N64 n2000")
     # at the default launch shape (64 threads, budget 28) a few pieces outgrow the fast path's 16 vertex slots and
-    # are redone there with the 64-slot polytope; every launch shape gives the same elements (chi, beta0 and keys
-    # exactly; the geometry of a piece that a smaller budget defers is computed in FP64 instead)
+    # are redone there with the 64-slot polytope, and many more with 12 slots; every launch shape gives the same
+    # elements (chi, beta0 and keys exactly; the geometry of a piece that one shape defers is computed in FP64)
     from paper_2403_18761_amd import rpd
 
     mesh, sites = _mesh_sites(prob)
-    d = rpd.build([mesh], [sites], block=64, clip_budget=28)
-    assert d.stats()["n_big"] > 0
-    gd = extract(d, 0)
-    for k in ("cell_chi", "cell_beta0", "face_keys", "face_chi", "face_beta0", "edge_keys", "edge_chi", "edge_beta0",
-              "rpv_keys", "medial"):
-        assert np.array_equal(np.asarray(gd[k]), np.asarray(g[k])), k
+    n_big = {}
+    for slots in (16, 12):
+        d = rpd.build([mesh], [sites], block=64, clip_budget=28, slots=slots)
+        n_big[slots] = d.stats()["n_big"]
+        gd = extract(d, 0)
+        for k in ("cell_chi", "cell_beta0", "face_keys", "face_chi", "face_beta0", "edge_keys", "edge_chi",
+                  "edge_beta0", "rpv_keys", "medial"):
+            assert np.array_equal(np.asarray(gd[k]), np.asarray(g[k])), (slots, k)
+    log("pieces redone with 64 slots, by vertex slots", n_big)
+    assert 0 < n_big[16] < n_big[12]
     r = oracle.rpd(prob, threads=min(16, os.cpu_count() or 1), assemble=False)
     assert_parity(g, r, label="torus N64 n2000 (whole)")
     assert_digest(g, load_golden("torus2000")[0], prob, "torus N64 n2000 (digest)")
@@ -273,7 +278,7 @@ def test_fullsize_batch():
     meshes, sites = [m for m, _ in made], [x for _, x in made]
     best = rpd.autotune(meshes, sites)
     log("batch tets", sum(p.n_tets for p in probs), "launch", best)
-    res = rpd.build(meshes, sites, block=best["block"], clip_budget=best["clip_budget"])
+    res = rpd.build(meshes, sites, block=best["block"], clip_budget=best["clip_budget"], slots=best["slots"])
     st = res.stats()
     if complete:
         assert st["n_pairs"] == sum(rec["n_pairs"] for rec in recs)
@@ -296,7 +301,8 @@ def test_fullsize_batch_subset_pieces():
     meshes, sites = [m for m, _ in made], [x for _, x in made]
     best = rpd.autotune(meshes, sites)
     log("batch subset tets", sum(p.n_tets for p in probs), "launch", best)
-    res = rpd.build(meshes, sites, block=best["block"], clip_budget=best["clip_budget"], flags=rpd.RPD_KEEP_PIECES)
+    res = rpd.build(meshes, sites, block=best["block"], clip_budget=best["clip_budget"], slots=best["slots"],
+                    flags=rpd.RPD_KEEP_PIECES)
     total = np.zeros(4, np.int64)
     for k, p in enumerate(probs):
         g = extract(res, k)

@@ -47,7 +47,7 @@ def test_small_torus_fp64():
     assert_parity(g, r, vol_rtol=1e-9, label="torus16 fp64")
 
 
-@pytest.mark.parametrize("flag", ["force_fp64", "force_exact", "force_slow", "budget4", "host_ptrs"])
+@pytest.mark.parametrize("flag", ["force_fp64", "force_exact", "force_slow", "budget4", "host_ptrs", "slots12"])
 def test_forced_paths_identical(flag):
     from paper_2403_18761_amd import rpd
 
@@ -56,7 +56,7 @@ def test_forced_paths_identical(flag):
     r = _oracle(prob)
     kw = dict(force_fp64=dict(flags=rpd.RPD_FORCE_FP64), force_exact=dict(flags=rpd.RPD_FORCE_EXACT),
               force_slow=dict(flags=rpd.RPD_FORCE_SLOW_PATH), budget4=dict(clip_budget=4),
-              host_ptrs=dict(device_ptrs=False))[flag]
+              host_ptrs=dict(device_ptrs=False), slots12=dict(block=64, slots=12))[flag]
     g = run_gpu(prob, **kw)
     assert_parity(g, r, label=flag)
     if flag == "force_exact":
@@ -220,8 +220,8 @@ def test_dense_sites_split_blocks(N, n):
 
 
 def test_launch_shapes_and_autotuner():
-    """Every launch shape the autotuner chooses from gives the same elements (bit for bit) and, for one clip budget,
-    the same volumes; the autotuner returns one of them and rpd_build then uses it."""
+    """Every launch shape the autotuner chooses from (both vertex-slot layouts of the 64-thread kernel included) gives
+    the same elements, bit for bit; the autotuner returns one of them and rpd_build then uses it."""
     import torch
 
     from paper_2403_18761_amd import rpd
@@ -231,13 +231,13 @@ def test_launch_shapes_and_autotuner():
     log("case: launch shapes")
     r = _oracle(prob, assemble=False)
     outs = {}
-    for block in (64, 128, 256):
+    for block, slots in ((64, 16), (128, 16), (256, 16), (64, 12)):
         for k in (8, 16, 28):
-            g = run_gpu(prob, block=block, clip_budget=k)
-            assert_parity(g, r, label=f"block {block} k {k}")
-            outs[(block, k)] = g
+            g = run_gpu(prob, block=block, clip_budget=k, slots=slots)
+            assert_parity(g, r, label=f"block {block} k {k} slots {slots}")
+            outs[(block, k, slots)] = g
     for key, g in outs.items():
-        ref = outs[(128, key[1])]
+        ref = outs[(128, key[1], 16)]
         for name in ELEMENT_ARRAYS:
             np.testing.assert_array_equal(g[name], ref[name], err_msg=f"{key} {name}")
     dev = torch.device("cuda:0")
@@ -249,7 +249,7 @@ def test_launch_shapes_and_autotuner():
     sites = (t(prob.sx), t(prob.sy), t(prob.sz), t(prob.sr))
     best = rpd.autotune([mesh], [sites])
     log("autotuned", best)
-    assert best["block"] in (64, 128, 256) and best["clip_budget"] in (8, 16, 28)
+    assert best["block"] in (64, 128, 256) and best["clip_budget"] in (8, 16, 28) and best["slots"] in (12, 16)
     res = rpd.build([mesh], [sites])
     _, chi = res.euler(0, rpd.RPD_CELL)
     np.testing.assert_array_equal(chi, r["cell_chi"])

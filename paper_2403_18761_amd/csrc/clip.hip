@@ -701,51 +701,66 @@ __global__ __launch_bounds__(NT) void k_clip_fast(ShapeArgs a) {
       }
       const double ycx = (y[0][0] + y[1][0] + y[2][0]) * 0.25, ycy = (y[0][1] + y[1][1] + y[2][1]) * 0.25,
                    ycz = (y[0][2] + y[1][2] + y[2][2]) * 0.25;
-      double U = INFINITY;
-      int qU = 0, idU = 0x7fffffff;  // the site attaining U: its list position and id (lowest id on ties, so the
-                                     // choice does not depend on the list's order)
+      // five dominators, each a site with its list position and id (the lowest id on ties, so that the choice does
+      // not depend on the list's order): [0] attains U = min over sites of the maximum of g over the tet, [1 + v]
+      // the minimum of g at vertex v (that vertex's owner)
+      double dv[5];
+      int dq[5], did[5];
+      for (int k = 0; k < 5; ++k) {
+        dv[k] = INFINITY;
+        dq[k] = 0;
+        did[k] = 0x7fffffff;
+      }
       for (int q = h; q < nsl; q += tpt) {
         float4 s = s_site[q];
         double ax_ = (double)s.x - o.x, ay_ = (double)s.y - o.y, az_ = (double)s.z - o.z;
-        double D = ax_ * ax_ + ay_ * ay_ + az_ * az_ - (double)s.w * s.w;
-        double gmx = D;
-        for (int v = 0; v < 3; ++v) gmx = fmax(gmx, D - 2.0 * (y[v][0] * ax_ + y[v][1] * ay_ + y[v][2] * az_));
-        if (gmx < U || (gmx == U && s_sid[q] < idU)) {
-          U = gmx;
-          qU = q;
-          idU = s_sid[q];
+        double gq[4];
+        gq[0] = ax_ * ax_ + ay_ * ay_ + az_ * az_ - (double)s.w * s.w;
+        for (int v = 0; v < 3; ++v) gq[v + 1] = gq[0] - 2.0 * (y[v][0] * ax_ + y[v][1] * ay_ + y[v][2] * az_);
+        const double gmx = fmax(fmax(gq[0], gq[1]), fmax(gq[2], gq[3]));
+        const int id = s_sid[q];
+        for (int k = 0; k < 5; ++k) {
+          const double x = k == 0 ? gmx : gq[k - 1];
+          if (x < dv[k] || (x == dv[k] && id < did[k])) {
+            dv[k] = x;
+            dq[k] = q;
+            did[k] = id;
+          }
         }
       }
-      for (int off = 1; off < tpt; off <<= 1) {
-        const double U2 = __shfl_xor(U, off);
-        const int q2 = __shfl_xor(qU, off), id2 = __shfl_xor(idU, off);
-        if (U2 < U || (U2 == U && id2 < idU)) {
-          U = U2;
-          qU = q2;
-          idU = id2;
+      for (int off = 1; off < tpt; off <<= 1)
+        for (int k = 0; k < 5; ++k) {
+          const double x2 = __shfl_xor(dv[k], off);
+          const int q2 = __shfl_xor(dq[k], off), id2 = __shfl_xor(did[k], off);
+          if (x2 < dv[k] || (x2 == dv[k] && id2 < did[k])) {
+            dv[k] = x2;
+            dq[k] = q2;
+            did[k] = id2;
+          }
         }
-      }
+      const double U = dv[0];
       if (a.tet_U && sd.sign > 0 && h == 0) a.tet_U[sd.tet_off + t0 + lt] = U;
-      // that site's g at the four vertices: a site it beats at all four owns no point of the tet and its bisector
-      // constrains no piece (the dominator's own bisector already does), so it is not a candidate
-      double gb[4];
-      {
-        const float4 s = s_site[qU];
+      // the dominators' g at the four vertices: a site that one of them beats at all four owns no point of the tet
+      // and its bisector constrains no piece (the dominator is a candidate, and its own bisector already does), so
+      // it is not a candidate; the same test among all candidates follows once they are sorted
+      double gb[5][4];
+      for (int k = 0; k < 5; ++k) {
+        const float4 s = s_site[dq[k]];
         const double ax_ = (double)s.x - o.x, ay_ = (double)s.y - o.y, az_ = (double)s.z - o.z;
-        gb[0] = ax_ * ax_ + ay_ * ay_ + az_ * az_ - (double)s.w * s.w;
-        for (int v = 0; v < 3; ++v) gb[v + 1] = gb[0] - 2.0 * (y[v][0] * ax_ + y[v][1] * ay_ + y[v][2] * az_);
+        gb[k][0] = ax_ * ax_ + ay_ * ay_ + az_ * az_ - (double)s.w * s.w;
+        for (int v = 0; v < 3; ++v) gb[k][v + 1] = gb[k][0] - 2.0 * (y[v][0] * ax_ + y[v][1] * ay_ + y[v][2] * az_);
       }
       for (int q = h; q < nsl; q += tpt) {
         float4 s = s_site[q];
         double ax_ = (double)s.x - o.x, ay_ = (double)s.y - o.y, az_ = (double)s.z - o.z;
-        double D = ax_ * ax_ + ay_ * ay_ + az_ * az_ - (double)s.w * s.w;
-        double gmn = D;
-        bool dom = D > gb[0];
-        for (int v = 0; v < 3; ++v) {
-          const double gv = D - 2.0 * (y[v][0] * ax_ + y[v][1] * ay_ + y[v][2] * az_);
-          gmn = fmin(gmn, gv);
-          dom = dom && gv > gb[v + 1];
-        }
+        double g[4];
+        g[0] = ax_ * ax_ + ay_ * ay_ + az_ * az_ - (double)s.w * s.w;
+        for (int v = 0; v < 3; ++v) g[v + 1] = g[0] - 2.0 * (y[v][0] * ax_ + y[v][1] * ay_ + y[v][2] * az_);
+        const double gmn = fmin(fmin(g[0], g[1]), fmin(g[2], g[3]));
+        bool dom = false;
+        for (int k = 0; k < 5; ++k)
+          dom = dom || (g[0] > gb[k][0] && g[1] > gb[k][1] && g[2] > gb[k][2] && g[3] > gb[k][3]);
+        const double D = g[0];
         if (gmn <= U && !dom) {
           int pos = atomicAdd(&s_m[lt], 1);
           if (pos < KRAW) {

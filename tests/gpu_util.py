@@ -25,6 +25,7 @@ def run_gpu(prob, precision=0, clip_budget=0, block=0, flags=0, device_ptrs=True
     out = extract(res, 0)
     out["stats"] = res.stats()
     out["mesh_info"] = mesh.info()
+    out["max_tet_vol"] = max_tet_volume(prob)
     out["radii"] = np.asarray(prob.sr, np.float64)
     if flags & rpd.RPD_KEEP_PIECES:
         out["pieces"] = res.pieces(0)
@@ -54,6 +55,24 @@ def extract(res, k):
     return out
 
 
+def max_tet_volume(prob):
+    v = np.stack([prob.vx, prob.vy, prob.vz], axis=1).astype(np.float64)
+    p = v[prob.tv]
+    d = np.einsum("ij,ij->i", p[:, 1] - p[:, 0], np.cross(p[:, 2] - p[:, 0], p[:, 3] - p[:, 0]))
+    return float(np.abs(d).max()) / 6.0
+
+
+def volume_floor(g, r, vol_rtol):
+    """Absolute volume tolerance: a piece built from rounded vertices errs by about 6 u vol(t), at the scale of the
+    tet it cuts and not of its own volume, so a cell of a few slivers carries that error whatever its size; the
+    floor is vol_rtol / 10 times the largest tet volume (1e-6 vol(t) on the FP32 path), and never below vol_rtol
+    1e-6 times the largest cell volume."""
+    f = vol_rtol * 1e-6 * max(float(r["cell_vol"].max()), 1e-30)
+    if "max_tet_vol" in g:
+        f = max(f, 0.1 * vol_rtol * g["max_tet_vol"])
+    return f
+
+
 def assert_parity(g, r, vol_rtol=1e-5, label=""):
     """Bit-exact chi / beta0 / adjacency; volumes and first moments within FP32 tolerance."""
     # the oracle's own cross-checks (divisibility, cross-side symmetry, gluing symmetry) must hold before its result
@@ -71,15 +90,14 @@ def assert_parity(g, r, vol_rtol=1e-5, label=""):
     np.testing.assert_array_equal(g["rpv_keys"], r["rpv_keys"], err_msg=f"{label} rpv keys")
     assert g["stats"]["n_pairs"] == r["n_pairs"], (label, g["stats"]["n_pairs"], r["n_pairs"])
     vr = r["cell_vol"]
-    np.testing.assert_allclose(g["cell_vol"], vr, rtol=vol_rtol, atol=vol_rtol * 1e-6 * max(vr.max(), 1e-30),
-                               err_msg=f"{label} volumes")
+    atol = volume_floor(g, r, vol_rtol)
+    np.testing.assert_allclose(g["cell_vol"], vr, rtol=vol_rtol, atol=atol, err_msg=f"{label} volumes")
     ne = vr > 0
     np.testing.assert_array_equal(np.isnan(g["cell_cen"][:, 0]), ~ne, err_msg=f"{label} empty cells")
     # First moments M = vol * centroid, for every nonempty cell however small: a piece's moment is its volume times
     # a position with |x| <= sqrt 3 (plus the position's own rounding, far below), so the moment error of a cell is
     # at most sqrt 3 times its volume error; both volume terms (relative and absolute floor) carry over. Tiny cells are
     # held to the same absolute floor as their volumes.
-    atol = vol_rtol * 1e-6 * max(vr.max(), 1e-30)
     mg = g["cell_cen"][ne] * g["cell_vol"][ne, None]
     mr = r["cell_cen"][ne] * vr[ne, None]
     err = np.abs(mg - mr).max(axis=1, initial=0.0)
@@ -129,6 +147,7 @@ def run_gpu_batch(probs, precision=0, flags=0):
     for k in range(len(probs)):
         out = extract(res, k)
         out["mesh_info"] = meshes[k].info()
+        out["max_tet_vol"] = max_tet_volume(probs[k])
         out["radii"] = np.asarray(probs[k].sr, np.float64)
         outs.append(out)
     return outs, res.stats()

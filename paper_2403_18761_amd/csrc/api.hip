@@ -324,9 +324,10 @@ struct DeviceState {
       L.add(cell_b0.p, 0, (size_t)ns_cap, 4);
       L.add(face_b0.p, 0, capF, 4);
       L.add(edge_b0.p, 0, capE, 4);
+      L.add_stats_zero(stat(), NSPREAD, C_NODES, 1, C_GLUE_BITS, 2);
       hip_check(launch_fill_multi(L, s), "fill");
     }
-    hip_check(launch_zero_stats(stat(), C_NODES, 1, C_GLUE_BITS, 2, s), "fill");
+    if (a.touch_cell) hip_check(launch_zero_stats(stat(), C_NODES, 1, C_GLUE_BITS, 2, s), "fill");
     hip_check(launch_glue(a, glist.as<int>(), gseg.as<int>(), clist.as<int>(), cseg.as<int>(), s), "glue");
     hip_check(launch_count_roots(a, glist.as<int>(), gseg.as<int>(), cell_b0.as<int>(), face_b0.as<int>(),
                                  edge_b0.as<int>(), s),
@@ -410,15 +411,20 @@ static bool collect(DeviceState& D, const std::vector<ShapeDesc>& hd, const Shap
   // the list counts were zeroed with the other counters when the state was cleared; an incremental session collects
   // again and again from one state
   if (D.touch.p) hip_check(launch_fill_u64(fin, 0, 3, s), "fill");
-  hip_check(launch_compact_live(D.fkeys.as<unsigned long long>(), D.face_np.as<int>(), capF,
-                                fk.as<unsigned long long>(), fsl.as<int>(), fin + 0, s),
-            "live faces");
-  hip_check(launch_compact_live(D.ekeys.as<unsigned long long>(), D.edge_np.as<int>(), capE,
-                                ek.as<unsigned long long>(), esl.as<int>(), fin + 1, s),
-            "live edges");
-  HashTab Q{D.qkeys.as<unsigned long long>(), capQ - 1};
-  hip_check(launch_rpv_compact(Q, D.rpv_cnt.as<int>(), D.ekeys.as<unsigned long long>(), rq.as<int4>(), fin + 2, s),
-            "live rpvs");
+  {
+    CompactLists J;
+    J.live[0] = {D.fkeys.as<unsigned long long>(), D.face_np.as<int>(), capF, 0, fk.as<unsigned long long>(),
+                 fsl.as<int>(), fin + 0};
+    J.live[1] = {D.ekeys.as<unsigned long long>(), D.edge_np.as<int>(), capE, 0, ek.as<unsigned long long>(),
+                 esl.as<int>(), fin + 1};
+    J.Q = HashTab{D.qkeys.as<unsigned long long>(), capQ - 1};
+    J.rpv_cnt = D.rpv_cnt.as<int>();
+    J.ekeys = D.ekeys.as<unsigned long long>();
+    J.rpv_cpt = 0;
+    J.rpv_out = rq.as<int4>();
+    J.rpv_count = fin + 2;
+    hip_check(launch_compact_lists(J, s), "live faces, edges and rpvs");
+  }
   const HashTab F{D.fkeys.as<unsigned long long>(), capF - 1}, E{D.ekeys.as<unsigned long long>(), capE - 1};
   const size_t ncap = std::max<size_t>(std::max(capF, capE), capQ);
   unsigned long long hc[NCOUNTERS + 8];
@@ -458,19 +464,25 @@ static bool collect(DeviceState& D, const std::vector<ShapeDesc>& hd, const Shap
     const int shifts[3] = {32, 42, 48};
     hip_check(launch_row_sort(keys, tmps, fin, caps, shifts, std::max(ns, 1), roff.as<int>(), rcur.as<int>(), s),
               "sort lists");
-    hip_check(launch_finalize_faces(fk.as<unsigned long long>(), nullptr, F, capF, od, D.face_chi.as<long long>(),
-                                    D.face_b0.as<int>(), dshapes, nsh, D.status.as<int>(), s),
-              "finalize faces");
-    hip_check(launch_finalize_edges(ek.as<unsigned long long>(), nullptr, E, capE, od, D.edge_chi.as<long long>(),
-                                    D.edge_b0.as<int>(), D.edge_len.as<long long>(), D.site.as<float4>(), dshapes, nsh,
-                                    D.status.as<int>(), s),
-              "finalize edges");
-    hip_check(launch_unpack_rpv(kq.as<unsigned long long>(), capQ, od, s), "unpack rpv");
+    FinalizeRows R;
+    R.fkeys = fk.as<unsigned long long>();
+    R.ekeys = ek.as<unsigned long long>();
+    R.qkeys = kq.as<unsigned long long>();
+    R.F = F;
+    R.E = E;
+    R.face_chi = D.face_chi.as<long long>();
+    R.edge_chi = D.edge_chi.as<long long>();
+    R.edge_len = D.edge_len.as<long long>();
+    R.cell_chi = D.cell_chi.as<long long>();
+    R.cell_geo = D.cell_geo.as<long long>();
+    R.face_b0 = D.face_b0.as<int>();
+    R.edge_b0 = D.edge_b0.as<int>();
+    R.cell_np = D.cell_np.as<int>();
+    R.cell_b0 = D.cell_b0.as<int>();
+    R.site = D.site.as<float4>();
+    R.ns = ns;
+    hip_check(launch_finalize_rows(R, ncap, od, dshapes, nsh, D.status.as<int>(), s), "finalize lists and cells");
     if (nsh > 1) hip_check(launch_localize_lists(od, ncap, dshapes, nsh, s), "localize lists");
-    if (ns > 0)
-      hip_check(launch_finalize_cells(ns, D.cell_chi.as<long long>(), D.cell_geo.as<long long>(), D.cell_np.as<int>(),
-                                      D.cell_b0.as<int>(), dshapes, nsh, od, D.status.as<int>(), s),
-                "finalize cells");
     tm.mark(3, s);
     if (!D.piece_cap) {
       std::lock_guard<std::mutex> g(g_spec_mu);

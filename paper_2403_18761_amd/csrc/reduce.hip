@@ -24,6 +24,16 @@ __global__ void k_fill_i32(int* p, int v, size_t n) {
 __global__ void k_fill_multi(FillList L) {
   const FillJob j = L.job[blockIdx.y];
   const size_t tid = blockIdx.x * (size_t)blockDim.x + threadIdx.x, step = (size_t)gridDim.x * blockDim.x;
+  if (j.width == 0) {  // counters of every copy of the statistics (FillList::add_stats_zero)
+    const int c0 = (int)(j.v & 0xffff), n0 = (int)((j.v >> 16) & 0xffff), c1 = (int)((j.v >> 32) & 0xffff),
+              n1 = (int)(j.v >> 48);
+    unsigned long long* st = (unsigned long long*)j.p;
+    for (size_t k = tid; k < j.n; k += step) {
+      for (int c = 0; c < n0; ++c) st[k * NCOUNTERS + c0 + c] = 0;
+      for (int c = 0; c < n1; ++c) st[k * NCOUNTERS + c1 + c] = 0;
+    }
+    return;
+  }
   if (j.width == 16) {  // a 16-byte pattern over a 16-byte aligned array
     const uint4 val = make_uint4((unsigned)j.v, (unsigned)(j.v >> 32), (unsigned)j.v2, (unsigned)(j.v2 >> 32));
     for (size_t k = tid; k < j.n; k += step) ((uint4*)j.p)[k] = val;
@@ -314,10 +324,10 @@ static unsigned compact_cpt(size_t cap) {
   return (unsigned)std::min<size_t>(std::max<size_t>(c, 1), 16);
 }
 
-__global__ __launch_bounds__(256) void k_compact_live(const unsigned long long* keys, const int* np, unsigned cap,
-                                                      unsigned cpt, unsigned long long* out_keys, int* out_slots,
-                                                      unsigned long long* count) {
-  const size_t q0 = (size_t)blockIdx.x * cpt * 256 + threadIdx.x;
+__device__ __forceinline__ void compact_live_block(unsigned bx, const unsigned long long* keys, const int* np,
+                                                   unsigned cap, unsigned cpt, unsigned long long* out_keys,
+                                                   int* out_slots, unsigned long long* count) {
+  const size_t q0 = (size_t)bx * cpt * 256 + threadIdx.x;
   int n = 0;
   for (unsigned k = 0; k < cpt; ++k) {
     const size_t q = q0 + 256 * (size_t)k;
@@ -334,21 +344,13 @@ __global__ __launch_bounds__(256) void k_compact_live(const unsigned long long* 
     }
   }
 }
-hipError_t launch_compact_live(const unsigned long long* keys, const int* np, unsigned cap,
-                               unsigned long long* out_keys, int* out_slots, unsigned long long* count,
-                               hipStream_t s) {
-  const unsigned cpt = compact_cpt(cap);
-  const size_t per = 256 * (size_t)cpt;
-  hipLaunchKernelGGL(k_compact_live, dim3((unsigned)((cap + per - 1) / per)), dim3(256), 0, s, keys, np, cap, cpt,
-                     out_keys, out_slots, count);
-  return hipGetLastError();
-}
 
 // RPV quadruples (i, j, k, l) of the counted set (key = edge slot of (i, j, k) << 21 | l), compacted
-__global__ __launch_bounds__(256) void k_rpv_compact(HashTab Q, const int* cnt, const unsigned long long* ekeys,
-                                                     unsigned cpt, int4* out, unsigned long long* count) {
+__device__ __forceinline__ void rpv_compact_block(unsigned bx, const HashTab& Q, const int* cnt,
+                                                  const unsigned long long* ekeys, unsigned cpt, int4* out,
+                                                  unsigned long long* count) {
   const size_t cap = (size_t)Q.mask + 1;
-  const size_t q0 = (size_t)blockIdx.x * cpt * 256 + threadIdx.x;
+  const size_t q0 = (size_t)bx * cpt * 256 + threadIdx.x;
   int n = 0;
   for (unsigned k = 0; k < cpt; ++k) {
     const size_t q = q0 + 256 * (size_t)k;
@@ -366,13 +368,31 @@ __global__ __launch_bounds__(256) void k_rpv_compact(HashTab Q, const int* cnt, 
     }
   }
 }
-hipError_t launch_rpv_compact(const HashTab& Q, const int* cnt, const unsigned long long* ekeys, int4* out,
-                              unsigned long long* count, hipStream_t s) {
-  const size_t cap = (size_t)Q.mask + 1;
-  const unsigned cpt = compact_cpt(cap);
-  const size_t per = 256 * (size_t)cpt;
-  hipLaunchKernelGGL(k_rpv_compact, dim3((unsigned)((cap + per - 1) / per)), dim3(256), 0, s, Q, cnt, ekeys, cpt, out,
-                     count);
+
+// The three compactions of the collect step in one launch (blockIdx.y: live faces, live edges, counted RPVs); each
+// takes the workgroups of x that its table needs, the others return at once.
+__global__ __launch_bounds__(256) void k_compact_lists(CompactLists J) {
+  const unsigned bx = blockIdx.x;
+  if (blockIdx.y < 2) {
+    const CompactLists::Live& L = J.live[blockIdx.y];
+    if ((size_t)bx * L.cpt * 256 >= L.cap) return;
+    compact_live_block(bx, L.keys, L.np, L.cap, L.cpt, L.out_keys, L.out_slots, L.count);
+  } else {
+    if ((size_t)bx * J.rpv_cpt * 256 >= (size_t)J.Q.mask + 1) return;
+    rpv_compact_block(bx, J.Q, J.rpv_cnt, J.ekeys, J.rpv_cpt, J.rpv_out, J.rpv_count);
+  }
+}
+hipError_t launch_compact_lists(CompactLists J, hipStream_t s) {
+  size_t gx = 1;
+  for (int y = 0; y < 2; ++y) {
+    J.live[y].cpt = compact_cpt(J.live[y].cap);
+    const size_t per = 256 * (size_t)J.live[y].cpt;
+    gx = std::max(gx, (J.live[y].cap + per - 1) / per);
+  }
+  const size_t capQ = (size_t)J.Q.mask + 1;
+  J.rpv_cpt = compact_cpt(capQ);
+  gx = std::max(gx, (capQ + 256 * (size_t)J.rpv_cpt - 1) / (256 * (size_t)J.rpv_cpt));
+  hipLaunchKernelGGL(k_compact_lists, dim3((unsigned)gx, 3), dim3(256), 0, s, J);
   return hipGetLastError();
 }
 
@@ -477,21 +497,18 @@ __global__ void k_pack_rpv(const int4* in, const unsigned long long* count, unsi
              (unsigned long long)r.w;
   }
 }
-__global__ void k_unpack_rpv(const unsigned long long* in, OutDesc od) {
+__device__ __forceinline__ void unpack_rpv_body(int t0, int stride, const unsigned long long* in, const OutDesc& od) {
   const int n = (int)od.n[2];
   int4* out = (int4*)(od.base + od.layout().rpv);
-  for (int q = blockIdx.x * blockDim.x + threadIdx.x; q < n; q += gridDim.x * blockDim.x) {
+  for (int q = t0; q < n; q += stride) {
     const unsigned long long k = in[q];
     out[q] = make_int4((int)(k >> 48), (int)((k >> 32) & 0xffff), (int)((k >> 16) & 0xffff), (int)(k & 0xffff));
   }
 }
+
 hipError_t launch_pack_rpv(const int4* in, const unsigned long long* count, size_t ncap, unsigned long long* out,
                            hipStream_t s) {
   hipLaunchKernelGGL(k_pack_rpv, dim3(std::min(grid_for(ncap, 256), 2048)), dim3(256), 0, s, in, count, out);
-  return hipGetLastError();
-}
-hipError_t launch_unpack_rpv(const unsigned long long* in, size_t ncap, const OutDesc& od, hipStream_t s) {
-  hipLaunchKernelGGL(k_unpack_rpv, dim3(std::min(grid_for(ncap, 256), 2048)), dim3(256), 0, s, in, od);
   return hipGetLastError();
 }
 
@@ -501,15 +518,16 @@ hipError_t sort_pairs_u64(void* tmp, size_t& tmp_bytes, const unsigned long long
   return rocprim::radix_sort_pairs(tmp, tmp_bytes, kin, kout, vin, vout, (size_t)n, 0, 64, s);
 }
 
-__global__ void k_finalize_faces(const unsigned long long* keys, const int* slots, HashTab T, OutDesc od,
-                                 const long long* chi_num, const int* b0, const ShapeDesc* shapes, int nshapes,
-                                 int* status) {
+__device__ __forceinline__ void finalize_faces_body(int t0, int stride, const unsigned long long* keys,
+                                                    const int* slots, const HashTab& T, const OutDesc& od,
+                                                    const long long* chi_num, const int* b0, const ShapeDesc* shapes,
+                                                    int nshapes, int* status) {
   const int n = (int)od.n[0];
   const OutLayout L = od.layout();
   int* out_keys = (int*)(od.base + L.fk);
   int* out_chi = (int*)(od.base + L.fchi);
   int* out_b0 = (int*)(od.base + L.fb0);
-  for (int q = blockIdx.x * blockDim.x + threadIdx.x; q < n; q += gridDim.x * blockDim.x) {
+  for (int q = t0; q < n; q += stride) {
     unsigned long long k = keys[q];
     int s = slots ? slots[q] : ht_find(T, k);
     out_keys[2 * q] = (int)(k >> 32);
@@ -521,10 +539,18 @@ __global__ void k_finalize_faces(const unsigned long long* keys, const int* slot
     out_b0[q] = b0[s];
   }
 }
+__global__ void k_finalize_faces(const unsigned long long* keys, const int* slots, HashTab T, OutDesc od,
+                                 const long long* chi_num, const int* b0, const ShapeDesc* shapes, int nshapes,
+                                 int* status) {
+  finalize_faces_body(blockIdx.x * blockDim.x + threadIdx.x, gridDim.x * blockDim.x, keys, slots, T, od, chi_num, b0,
+                      shapes, nshapes, status);
+}
 // RPE length (fixed point -> double) and the thinning importance alpha = length / mean diameter of the three spheres
-__global__ void k_finalize_edges(const unsigned long long* keys, const int* slots, HashTab T, OutDesc od,
-                                 const long long* chi_num, const int* b0, const long long* len_num,
-                                 const float4* site, const ShapeDesc* shapes, int nshapes, int* status) {
+__device__ __forceinline__ void finalize_edges_body(int t0, int stride, const unsigned long long* keys,
+                                                    const int* slots, const HashTab& T, const OutDesc& od,
+                                                    const long long* chi_num, const int* b0, const long long* len_num,
+                                                    const float4* site, const ShapeDesc* shapes, int nshapes,
+                                                    int* status) {
   const int n = (int)od.n[1];
   const OutLayout L = od.layout();
   int* out_keys = (int*)(od.base + L.ek);
@@ -532,7 +558,7 @@ __global__ void k_finalize_edges(const unsigned long long* keys, const int* slot
   int* out_b0 = (int*)(od.base + L.eb0);
   double* out_len = (double*)(od.base + L.elen);
   double* out_alpha = (double*)(od.base + L.ealpha);
-  for (int q = blockIdx.x * blockDim.x + threadIdx.x; q < n; q += gridDim.x * blockDim.x) {
+  for (int q = t0; q < n; q += stride) {
     unsigned long long k = keys[q];
     int s = slots ? slots[q] : ht_find(T, k);
     out_keys[3 * q] = (int)(k >> 42);
@@ -550,14 +576,22 @@ __global__ void k_finalize_edges(const unsigned long long* keys, const int* slot
     out_alpha[q] = dsum > 0.0 ? 3.0 * len / dsum : INFINITY;
   }
 }
-__global__ void k_finalize_cells(int ns, const long long* chi_num, const long long* geo, const int* np, const int* b0,
-                                 const ShapeDesc* shapes, int nshapes, OutDesc od, int* status) {
+__global__ void k_finalize_edges(const unsigned long long* keys, const int* slots, HashTab T, OutDesc od,
+                                 const long long* chi_num, const int* b0, const long long* len_num,
+                                 const float4* site, const ShapeDesc* shapes, int nshapes, int* status) {
+  finalize_edges_body(blockIdx.x * blockDim.x + threadIdx.x, gridDim.x * blockDim.x, keys, slots, T, od, chi_num, b0,
+                      len_num, site, shapes, nshapes, status);
+}
+__device__ __forceinline__ void finalize_cells_body(int t0, int stride, int ns, const long long* chi_num,
+                                                    const long long* geo, const int* np, const int* b0,
+                                                    const ShapeDesc* shapes, int nshapes, const OutDesc& od,
+                                                    int* status) {
   const OutLayout L = od.layout();
   int* out_chi = (int*)(od.base + L.cchi);
   int* out_b0 = (int*)(od.base + L.cb0);
   double* out_vol = (double*)(od.base + L.vol);
   double* out_cen = (double*)(od.base + L.cen);
-  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < ns; i += gridDim.x * blockDim.x) {
+  for (int i = t0; i < ns; i += stride) {
     const long long L = shapes[shape_of_site(shapes, nshapes, i)].L;
     long long c = chi_num[i];
     if (c % L != 0) atomicOr(status, ST_INTERNAL);
@@ -573,6 +607,35 @@ __global__ void k_finalize_cells(int ns, const long long* chi_num, const long lo
     out_vol[i] = v;
     for (int d = 0; d < 3; ++d) out_cen[3 * (size_t)i + d] = np[i] ? value(1 + d) / v : NAN;
   }
+}
+__global__ void k_finalize_cells(int ns, const long long* chi_num, const long long* geo, const int* np, const int* b0,
+                                 const ShapeDesc* shapes, int nshapes, OutDesc od, int* status) {
+  finalize_cells_body(blockIdx.x * blockDim.x + threadIdx.x, gridDim.x * blockDim.x, ns, chi_num, geo, np, b0, shapes,
+                      nshapes, od, status);
+}
+// blockIdx.y: faces, edges, RPVs, cells
+__global__ void k_finalize_rows(FinalizeRows R, OutDesc od, const ShapeDesc* shapes, int nshapes, int* status) {
+  const int t0 = blockIdx.x * blockDim.x + threadIdx.x, stride = gridDim.x * blockDim.x;
+  switch (blockIdx.y) {
+    case 0:
+      finalize_faces_body(t0, stride, R.fkeys, nullptr, R.F, od, R.face_chi, R.face_b0, shapes, nshapes, status);
+      break;
+    case 1:
+      finalize_edges_body(t0, stride, R.ekeys, nullptr, R.E, od, R.edge_chi, R.edge_b0, R.edge_len, R.site, shapes,
+                          nshapes, status);
+      break;
+    case 2:
+      unpack_rpv_body(t0, stride, R.qkeys, od);
+      break;
+    default:
+      finalize_cells_body(t0, stride, R.ns, R.cell_chi, R.cell_geo, R.cell_np, R.cell_b0, shapes, nshapes, od, status);
+  }
+}
+hipError_t launch_finalize_rows(const FinalizeRows& R, size_t ncap, const OutDesc& od, const ShapeDesc* shapes,
+                                int nshapes, int* status, hipStream_t s) {
+  const int gx = std::min(grid_for(std::max(ncap, (size_t)R.ns), 256), 2048);
+  hipLaunchKernelGGL(k_finalize_rows, dim3(gx, 4), dim3(256), 0, s, R, od, shapes, nshapes, status);
+  return hipGetLastError();
 }
 
 hipError_t launch_finalize_faces(const unsigned long long* keys, const int* slots, const HashTab& T, size_t ncap,

@@ -30,6 +30,14 @@ struct FillList {
     if (n < 24) job[n++] = FillJob{ptr, val, val2, count, w};
     else overflow = true;
   }
+  // zero counters [c0, c0 + n0) and [c1, c1 + n1) of each of the copies of the statistics (NCOUNTERS apart): a job
+  // of width 0 with the four bounds packed in val
+  void add_stats_zero(unsigned long long* stats, int copies, int c0, int n0, int c1, int n1) {
+    const unsigned long long packed = (unsigned long long)(c0 & 0xffff) | ((unsigned long long)(n0 & 0xffff) << 16) |
+                                      ((unsigned long long)(c1 & 0xffff) << 32) |
+                                      ((unsigned long long)(n1 & 0xffff) << 48);
+    add(stats, packed, (size_t)copies, 0);
+  }
 };
 hipError_t launch_fill_multi(const FillList& L, hipStream_t s);
 hipError_t launch_fill_i32(int* p, int v, size_t n, hipStream_t s);
@@ -46,12 +54,25 @@ hipError_t launch_touch_removed(const ShapeArgs& a, hipStream_t s);
 // components per element: the roots among the pieces launch_glue listed
 hipError_t launch_count_roots(const ShapeArgs& a, const int* list, const int* seg, int* cell_b0, int* face_b0,
                               int* edge_b0, hipStream_t s);
-// live entries of a counted table, compacted in any order (count += their number)
-hipError_t launch_compact_live(const unsigned long long* keys, const int* np, unsigned cap,
-                               unsigned long long* out_keys, int* out_slots, unsigned long long* count,
-                               hipStream_t s);
-hipError_t launch_rpv_compact(const HashTab& Q, const int* cnt, const unsigned long long* ekeys, int4* out,
-                              unsigned long long* count, hipStream_t s);
+// the live entries of the face and edge tables (keys and slots) and the counted RPVs (as site quadruples), each
+// compacted in any order (its count += their number), in one launch
+struct CompactLists {
+  struct Live {
+    const unsigned long long* keys;
+    const int* np;
+    unsigned cap, cpt;  // cpt: set by the launcher
+    unsigned long long* out_keys;
+    int* out_slots;
+    unsigned long long* count;
+  } live[2];
+  HashTab Q;
+  const int* rpv_cnt;
+  const unsigned long long* ekeys;
+  unsigned rpv_cpt;  // set by the launcher
+  int4* rpv_out;
+  unsigned long long* rpv_count;
+};
+hipError_t launch_compact_lists(CompactLists J, hipStream_t s);
 hipError_t sort_pairs_u64(void* tmp, size_t& tmp_bytes, const unsigned long long* kin, unsigned long long* kout,
                           const int* vin, int* vout, int n, hipStream_t s);
 size_t sort_tmp_bytes(int n);
@@ -69,12 +90,23 @@ hipError_t launch_finalize_edges(const unsigned long long* keys, const int* slot
 hipError_t launch_row_sort(unsigned long long* const keys[3], unsigned long long* const tmp[3],
                            const unsigned long long* n, const size_t ncap[3], const int shift[3], int rows, int* off,
                            int* cur, hipStream_t s);
-// RPV quadruples whose ids are all below 2^16, packed into single keys and back
+// RPV quadruples whose ids are all below 2^16, packed into single keys (launch_finalize_rows unpacks them)
 hipError_t launch_pack_rpv(const int4* in, const unsigned long long* count, size_t ncap, unsigned long long* out,
                            hipStream_t s);
-hipError_t launch_unpack_rpv(const unsigned long long* in, size_t ncap, const OutDesc& od, hipStream_t s);
 hipError_t launch_finalize_cells(int ns, const long long* chi_num, const long long* geo, const int* np, const int* b0,
                                  const ShapeDesc* shapes, int nshapes, const OutDesc& od, int* status, hipStream_t s);
+// the row-sorted path's four last steps in one launch: face and edge lists (slots looked up by key), the packed RPVs
+// unpacked, and the cells
+struct FinalizeRows {
+  const unsigned long long *fkeys, *ekeys, *qkeys;
+  HashTab F, E;
+  const long long *face_chi, *edge_chi, *edge_len, *cell_chi, *cell_geo;
+  const int *face_b0, *edge_b0, *cell_np, *cell_b0;
+  const float4* site;
+  int ns;
+};
+hipError_t launch_finalize_rows(const FinalizeRows& R, size_t ncap, const OutDesc& od, const ShapeDesc* shapes,
+                                int nshapes, int* status, hipStream_t s);
 hipError_t launch_sort_rpv(const int4* rpv, int n, unsigned long long* ka, unsigned long long* kb,
                            unsigned long long* kc, int* va, int* vb, void* tmp, size_t tmp_bytes, int4* out,
                            hipStream_t s);

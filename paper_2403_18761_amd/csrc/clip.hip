@@ -607,27 +607,77 @@ __global__ __launch_bounds__(NT) void k_clip_fast(ShapeArgs a) {
       y[v - 1][1] = (double)tv[v].y - o.y;
       y[v - 1][2] = (double)tv[v].z - o.z;
     }
-    double umin = INFINITY;
-    for (int j = tid; j < sd.ns; j += NT) {
-      const float4 s = ssite[j];
-      const double ax_ = (double)s.x - o.x, ay_ = (double)s.y - o.y, az_ = (double)s.z - o.z;
-      const double D = ax_ * ax_ + ay_ * ay_ + az_ * az_ - (double)s.w * s.w;
-      double gmx = D;
-      for (int v = 0; v < 3; ++v) gmx = fmax(gmx, D - 2.0 * (y[v][0] * ax_ + y[v][1] * ay_ + y[v][2] * az_));
-      umin = fmin(umin, gmx);
+    // the five dominators of the candidate phase among all of the shape's sites (lowest index on ties): the site
+    // attaining U and the owner of each vertex; a site one of them beats at all four vertices is not collected, so
+    // that the list holds the tet's exact candidates less those (which the candidate phase drops anyway)
+    double dv[5];
+    int dj[5];
+    for (int k = 0; k < 5; ++k) {
+      dv[k] = INFINITY;
+      dj[k] = 0x7fffffff;
     }
-    umin = wave_min(umin);
-    if (lane == 0) s_red[wid] = umin;
-    __syncthreads();
-    double U = s_red[0];
-    for (int w = 1; w < NT / 64; ++w) U = fmin(U, s_red[w]);
     for (int j = tid; j < sd.ns; j += NT) {
       const float4 s = ssite[j];
       const double ax_ = (double)s.x - o.x, ay_ = (double)s.y - o.y, az_ = (double)s.z - o.z;
-      const double D = ax_ * ax_ + ay_ * ay_ + az_ * az_ - (double)s.w * s.w;
-      double gmn = D;
-      for (int v = 0; v < 3; ++v) gmn = fmin(gmn, D - 2.0 * (y[v][0] * ax_ + y[v][1] * ay_ + y[v][2] * az_));
-      if (gmn <= U) {
+      double gq[4];
+      gq[0] = ax_ * ax_ + ay_ * ay_ + az_ * az_ - (double)s.w * s.w;
+      for (int v = 0; v < 3; ++v) gq[v + 1] = gq[0] - 2.0 * (y[v][0] * ax_ + y[v][1] * ay_ + y[v][2] * az_);
+      const double gmx = fmax(fmax(gq[0], gq[1]), fmax(gq[2], gq[3]));
+      for (int k = 0; k < 5; ++k) {
+        const double x = k == 0 ? gmx : gq[k - 1];
+        if (x < dv[k] || (x == dv[k] && j < dj[k])) {
+          dv[k] = x;
+          dj[k] = j;
+        }
+      }
+    }
+    for (int off = 32; off > 0; off >>= 1)
+      for (int k = 0; k < 5; ++k) {
+        const double x2 = __shfl_xor(dv[k], off);
+        const int j2 = __shfl_xor(dj[k], off);
+        if (x2 < dv[k] || (x2 == dv[k] && j2 < dj[k])) {
+          dv[k] = x2;
+          dj[k] = j2;
+        }
+      }
+    if constexpr (NT > 64) {  // across the waves, through the polytope area (unused until the pieces)
+      double* xv = reinterpret_cast<double*>(s_share);
+      int* xj = reinterpret_cast<int*>(s_share + sizeof(double) * 5 * (NT / 64));
+      if (lane == 0)
+        for (int k = 0; k < 5; ++k) {
+          xv[5 * wid + k] = dv[k];
+          xj[5 * wid + k] = dj[k];
+        }
+      __syncthreads();
+      for (int w = 0; w < NT / 64; ++w)
+        for (int k = 0; k < 5; ++k) {
+          const double x2 = xv[5 * w + k];
+          const int j2 = xj[5 * w + k];
+          if (x2 < dv[k] || (x2 == dv[k] && j2 < dj[k])) {
+            dv[k] = x2;
+            dj[k] = j2;
+          }
+        }
+    }
+    const double U = dv[0];
+    double gb[5][4];
+    for (int k = 0; k < 5; ++k) {
+      const float4 s = ssite[dj[k]];
+      const double ax_ = (double)s.x - o.x, ay_ = (double)s.y - o.y, az_ = (double)s.z - o.z;
+      gb[k][0] = ax_ * ax_ + ay_ * ay_ + az_ * az_ - (double)s.w * s.w;
+      for (int v = 0; v < 3; ++v) gb[k][v + 1] = gb[k][0] - 2.0 * (y[v][0] * ax_ + y[v][1] * ay_ + y[v][2] * az_);
+    }
+    for (int j = tid; j < sd.ns; j += NT) {
+      const float4 s = ssite[j];
+      const double ax_ = (double)s.x - o.x, ay_ = (double)s.y - o.y, az_ = (double)s.z - o.z;
+      double g[4];
+      g[0] = ax_ * ax_ + ay_ * ay_ + az_ * az_ - (double)s.w * s.w;
+      for (int v = 0; v < 3; ++v) g[v + 1] = g[0] - 2.0 * (y[v][0] * ax_ + y[v][1] * ay_ + y[v][2] * az_);
+      const double gmn = fmin(fmin(g[0], g[1]), fmin(g[2], g[3]));
+      bool dom = false;
+      for (int k = 0; k < 5; ++k)
+        dom = dom || (g[0] > gb[k][0] && g[1] > gb[k][1] && g[2] > gb[k][2] && g[3] > gb[k][3]);
+      if (gmn <= U && !dom) {
         const int q = atomicAdd(&s_nsl, 1);
         if (q < SLMAX) {
           s_site[q] = s;

@@ -32,11 +32,11 @@ def _mesh(prob):
     return rpd.Mesh(_dev(prob.vx), _dev(prob.vy), _dev(prob.vz), _dev(prob.tv.reshape(-1), torch.int32))
 
 
-def _rebuild(mesh, sites):
+def _rebuild(mesh, sites, slots=0):
     from paper_2403_18761_amd import rpd
 
     s = tuple(_dev(sites[:, k]) for k in range(4))
-    res = rpd.build([mesh], [s])
+    res = rpd.build([mesh], [s], slots=slots, block=64 if slots else 0)
     out = extract(res, 0)
     out["stats"] = res.stats()
     return out
@@ -73,28 +73,30 @@ def test_session_equals_rebuild():
     assert info["n_dirty_blocks"] < info["n_blocks"] * info["rounds"]
 
 
-def test_session_dense_sites_equals_rebuild():
+@pytest.mark.parametrize("slots", [16, 12])
+def test_session_dense_sites_equals_rebuild(slots):
     """Dense sites, where workgroup site lists overflow and tets are taken one at a time with their own candidates:
     a tet's path depends on its own candidates only, so the rounds' removals take back exactly what was added and
-    the state stays equal to a rebuild bit for bit (volumes included)."""
+    the state stays equal to a rebuild bit for bit (volumes included), with either vertex-slot layout of the fast
+    kernel (12 slots: many more pieces redone with 64 slots, inside the kernel)."""
     from paper_2403_18761_amd import rpd
 
     prob = synth.torus_inside(16, 4000, 3)  # about 5 sites per tet; 6 cells violate the topology constraints
     table = synth.centroid_table(prob, 0.03)
     log(f"case: session dense torus N16 n4000 tets {prob.n_tets}")
     mesh = _mesh(prob)
-    st = _rebuild(mesh, np.stack([prob.sx, prob.sy, prob.sz, prob.sr], axis=1))["stats"]
-    log("initial build: split", st["n_split"], "deferred", st["n_defer_block"], st["n_defer_kmax"])
+    st = _rebuild(mesh, np.stack([prob.sx, prob.sy, prob.sz, prob.sr], axis=1), slots)["stats"]
+    log("initial build: split", st["n_split"], "deferred", st["n_defer_block"], st["n_defer_kmax"], "big", st["n_big"])
     assert st["n_split"] > 0
     sess = rpd.Session(mesh, (_dev(prob.sx), _dev(prob.sy), _dev(prob.sz), _dev(prob.sr)),
-                       tuple(_dev(x) for x in table), max_sites=4000 + 4 * 64, max_insert=64)
+                       tuple(_dev(x) for x in table), max_sites=4000 + 4 * 64, max_insert=64, block=64, slots=slots)
     for rounds in (1, 2, 3):
         sess.run(1)
         info = sess.info()
         res = sess.result()
         cur = extract(res, 0)
         cur["stats"] = res.stats()
-        _same(cur, _rebuild(mesh, sess.sites()), f"dense torus after {info['rounds']} rounds")
+        _same(cur, _rebuild(mesh, sess.sites(), slots), f"dense torus after {info['rounds']} rounds")
     log("session", info)
     assert info["n_inserted"] > 0
 

@@ -411,6 +411,9 @@ static bool collect(DeviceState& D, const std::vector<ShapeDesc>& hd, const Shap
   // the list counts were zeroed with the other counters when the state was cleared; an incremental session collects
   // again and again from one state
   if (D.touch.p) hip_check(launch_fill_u64(fin, 0, 3, s), "fill");
+  // the row sort's per-row counts and cursors (3 (ns + 1) and 3 ns ints), for up to 2^16 sites
+  const size_t n_rowc = ns < (1 << 16) ? 3 * ((size_t)ns + 1) + 3 * (size_t)std::max(ns, 1) : 0;
+  DBuf rowc(4 * std::max<size_t>(n_rowc, 1));
   {
     CompactLists J;
     J.live[0] = {D.fkeys.as<unsigned long long>(), D.face_np.as<int>(), capF, 0, fk.as<unsigned long long>(),
@@ -423,6 +426,8 @@ static bool collect(DeviceState& D, const std::vector<ShapeDesc>& hd, const Shap
     J.rpv_cpt = 0;
     J.rpv_out = rq.as<int4>();
     J.rpv_count = fin + 2;
+    J.zero = rowc.as<int>();  // the row sort's counters (up to 2^16 sites), cleared in the same launch
+    J.n_zero = n_rowc;
     hip_check(launch_compact_lists(J, s), "live faces, edges and rpvs");
   }
   const HashTab F{D.fkeys.as<unsigned long long>(), capF - 1}, E{D.ekeys.as<unsigned long long>(), capE - 1};
@@ -453,16 +458,15 @@ static bool collect(DeviceState& D, const std::vector<ShapeDesc>& hd, const Shap
     // whole sequence is queued before the host waits for the counts (the buffer is sized for full tables).
     out.alloc(out_layout(ns, nsh, capF, capE, capQ).bytes);
     od.base = out.as<unsigned char>();
-    DBuf kq(8 * (size_t)capQ), t0(8 * (size_t)capF), t1(8 * (size_t)capE), t2(8 * (size_t)capQ),
-        roff(4 * 3 * ((size_t)ns + 1)), rcur(4 * 3 * (size_t)std::max(ns, 1));
-    hip_check(launch_pack_rpv(rq.as<int4>(), fin + 2, capQ, kq.as<unsigned long long>(), s), "pack rpv");
+    DBuf kq(8 * (size_t)capQ), t0(8 * (size_t)capF), t1(8 * (size_t)capE), t2(8 * (size_t)capQ);
     unsigned long long* const keys[3] = {fk.as<unsigned long long>(), ek.as<unsigned long long>(),
                                          kq.as<unsigned long long>()};
     unsigned long long* const tmps[3] = {t0.as<unsigned long long>(), t1.as<unsigned long long>(),
                                          t2.as<unsigned long long>()};
     const size_t caps[3] = {capF, capE, capQ};
     const int shifts[3] = {32, 42, 48};
-    hip_check(launch_row_sort(keys, tmps, fin, caps, shifts, std::max(ns, 1), roff.as<int>(), rcur.as<int>(), s),
+    hip_check(launch_row_sort(keys, tmps, fin, caps, shifts, std::max(ns, 1), rowc.as<int>(),
+                              rowc.as<int>() + 3 * ((size_t)ns + 1), rq.as<int4>(), s),
               "sort lists");
     FinalizeRows R;
     R.fkeys = fk.as<unsigned long long>();

@@ -373,6 +373,11 @@ __device__ __forceinline__ void rpv_compact_block(unsigned bx, const HashTab& Q,
 // takes the workgroups of x that its table needs, the others return at once.
 __global__ __launch_bounds__(256) void k_compact_lists(CompactLists J) {
   const unsigned bx = blockIdx.x;
+  if (blockIdx.y == 3) {
+    for (size_t k = bx * (size_t)blockDim.x + threadIdx.x; k < J.n_zero; k += (size_t)gridDim.x * blockDim.x)
+      J.zero[k] = 0;
+    return;
+  }
   if (blockIdx.y < 2) {
     const CompactLists::Live& L = J.live[blockIdx.y];
     if ((size_t)bx * L.cpt * 256 >= L.cap) return;
@@ -392,7 +397,7 @@ hipError_t launch_compact_lists(CompactLists J, hipStream_t s) {
   const size_t capQ = (size_t)J.Q.mask + 1;
   J.rpv_cpt = compact_cpt(capQ);
   gx = std::max(gx, (capQ + 256 * (size_t)J.rpv_cpt - 1) / (256 * (size_t)J.rpv_cpt));
-  hipLaunchKernelGGL(k_compact_lists, dim3((unsigned)gx, 3), dim3(256), 0, s, J);
+  hipLaunchKernelGGL(k_compact_lists, dim3((unsigned)gx, J.zero && J.n_zero ? 4 : 3), dim3(256), 0, s, J);
   return hipGetLastError();
 }
 
@@ -407,12 +412,23 @@ struct RowLists {
   int* off;                     // [3][rows + 1]
   int* cur;                     // [3][rows]
   int rows;
+  const int4* pack;             // or null: list 2 is packed from these RPV quadruples while it is counted
 };
 __global__ void k_row_count(RowLists L) {
   const int l = blockIdx.y, n = (int)L.n[l];
   int* off = L.off + l * (L.rows + 1);
-  for (int q = blockIdx.x * blockDim.x + threadIdx.x; q < n; q += gridDim.x * blockDim.x)
-    atomicAdd(&off[(int)(L.keys[l][q] >> L.shift[l]) + 1], 1);
+  for (int q = blockIdx.x * blockDim.x + threadIdx.x; q < n; q += gridDim.x * blockDim.x) {
+    unsigned long long k;
+    if (l == 2 && L.pack) {  // RPV quadruple with every id below 2^16, packed into one key
+      const int4 r = L.pack[q];
+      k = ((unsigned long long)r.x << 48) | ((unsigned long long)r.y << 32) | ((unsigned long long)r.z << 16) |
+          (unsigned long long)r.w;
+      L.keys[2][q] = k;
+    } else {
+      k = L.keys[l][q];
+    }
+    atomicAdd(&off[(int)(k >> L.shift[l]) + 1], 1);
+  }
 }
 // exclusive scan of the row counts in place (one workgroup per list)
 __global__ __launch_bounds__(1024) void k_row_scan(RowLists L) {
@@ -462,7 +478,7 @@ __global__ void k_row_rank(RowLists L) {
 }
 hipError_t launch_row_sort(unsigned long long* const keys[3], unsigned long long* const tmp[3],
                            const unsigned long long* n, const size_t ncap[3], const int shift[3], int rows, int* off,
-                           int* cur, hipStream_t s) {
+                           int* cur, const int4* pack_rpv, hipStream_t s) {
   RowLists L;
   size_t nmax = 1;
   for (int l = 0; l < 3; ++l) {
@@ -476,11 +492,7 @@ hipError_t launch_row_sort(unsigned long long* const keys[3], unsigned long long
   L.off = off;
   L.cur = cur;
   L.rows = rows;
-  FillList Z{};
-  Z.add(off, 0, 3 * (size_t)(rows + 1), 4);
-  Z.add(cur, 0, 3 * (size_t)rows, 4);
-  hipError_t e = launch_fill_multi(Z, s);
-  if (e != hipSuccess) return e;
+  L.pack = pack_rpv;
   hipLaunchKernelGGL(k_row_count, dim3(grid, 3), dim3(256), 0, s, L);
   hipLaunchKernelGGL(k_row_scan, dim3(3), dim3(1024), 0, s, L);
   hipLaunchKernelGGL(k_row_scatter, dim3(grid, 3), dim3(256), 0, s, L);
@@ -488,15 +500,7 @@ hipError_t launch_row_sort(unsigned long long* const keys[3], unsigned long long
   return hipGetLastError();
 }
 
-// RPV quadruples with every id below 2^16 packed into one 64-bit key (and back) for the small sort
-__global__ void k_pack_rpv(const int4* in, const unsigned long long* count, unsigned long long* out) {
-  const int n = (int)*count;
-  for (int q = blockIdx.x * blockDim.x + threadIdx.x; q < n; q += gridDim.x * blockDim.x) {
-    const int4 r = in[q];
-    out[q] = ((unsigned long long)r.x << 48) | ((unsigned long long)r.y << 32) | ((unsigned long long)r.z << 16) |
-             (unsigned long long)r.w;
-  }
-}
+// packed RPV keys (see k_row_count) back to quadruples
 __device__ __forceinline__ void unpack_rpv_body(int t0, int stride, const unsigned long long* in, const OutDesc& od) {
   const int n = (int)od.n[2];
   int4* out = (int4*)(od.base + od.layout().rpv);
@@ -506,11 +510,6 @@ __device__ __forceinline__ void unpack_rpv_body(int t0, int stride, const unsign
   }
 }
 
-hipError_t launch_pack_rpv(const int4* in, const unsigned long long* count, size_t ncap, unsigned long long* out,
-                           hipStream_t s) {
-  hipLaunchKernelGGL(k_pack_rpv, dim3(std::min(grid_for(ncap, 256), 2048)), dim3(256), 0, s, in, count, out);
-  return hipGetLastError();
-}
 
 hipError_t sort_pairs_u64(void* tmp, size_t& tmp_bytes, const unsigned long long* kin, unsigned long long* kout,
                           const int* vin, int* vout, int n, hipStream_t s) {

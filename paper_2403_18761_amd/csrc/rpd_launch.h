@@ -71,6 +71,8 @@ struct CompactLists {
   unsigned rpv_cpt;  // set by the launcher
   int4* rpv_out;
   unsigned long long* rpv_count;
+  int* zero;     // or null: n_zero ints set to 0 in the same launch (the row sort's counters)
+  size_t n_zero;
 };
 hipError_t launch_compact_lists(CompactLists J, hipStream_t s);
 hipError_t sort_pairs_u64(void* tmp, size_t& tmp_bytes, const unsigned long long* kin, unsigned long long* kout,
@@ -87,12 +89,10 @@ hipError_t launch_finalize_edges(const unsigned long long* keys, const int* slot
                                  hipStream_t s);
 // three lists of keys whose row (key >> shift) is below rows, sorted ascending in place; tmp[l] holds n[l] keys;
 // off holds 3 (rows + 1) ints, cur 3 rows ints
+// (off and cur must be zero; with pack_rpv set, list 2 is first packed from those RPV quadruples, ids below 2^16)
 hipError_t launch_row_sort(unsigned long long* const keys[3], unsigned long long* const tmp[3],
                            const unsigned long long* n, const size_t ncap[3], const int shift[3], int rows, int* off,
-                           int* cur, hipStream_t s);
-// RPV quadruples whose ids are all below 2^16, packed into single keys (launch_finalize_rows unpacks them)
-hipError_t launch_pack_rpv(const int4* in, const unsigned long long* count, size_t ncap, unsigned long long* out,
-                           hipStream_t s);
+                           int* cur, const int4* pack_rpv, hipStream_t s);
 hipError_t launch_finalize_cells(int ns, const long long* chi_num, const long long* geo, const int* np, const int* b0,
                                  const ShapeDesc* shapes, int nshapes, const OutDesc& od, int* status, hipStream_t s);
 // the row-sorted path's four last steps in one launch: face and edge lists (slots looked up by key), the packed RPVs

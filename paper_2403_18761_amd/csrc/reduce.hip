@@ -238,13 +238,13 @@ __global__ void k_glue(ShapeArgs a, const int* list, const int* seg, unsigned le
     const ShapeDesc& sd = a.shapes[shape_of_tet(a.shapes, a.nshapes, gt)];
     const int t = (int)(gt - sd.tet_off);
     unsigned long long hi = key & ~0xffffffffull;
+    const int4 nb = reinterpret_cast<const int4*>(sd.tn)[t];  // the four face neighbours, one 16-byte load
     for (int f = 0; f < 4; ++f) {
       if (!(g & (1 << f))) continue;
-      int t2 = sd.tn[4 * (size_t)t + f];
+      const int t2 = f == 0 ? nb.x : f == 1 ? nb.y : f == 2 ? nb.z : nb.w;
       if (t2 < t) continue;  // the boundary never carries a bit; the other side matches smaller ids
-      int f2 = -1;
-      for (int q = 0; q < 4; ++q)
-        if (sd.tn[4 * (size_t)t2 + q] == t) f2 = q;
+      const int4 nb2 = reinterpret_cast<const int4*>(sd.tn)[t2];
+      const int f2 = nb2.x == t ? 0 : nb2.y == t ? 1 : nb2.z == t ? 2 : nb2.w == t ? 3 : -1;
       int s2 = node_find(a.N, hi | (unsigned)(sd.tet_off + t2));
       const int st2 = s2 >= 0 ? a.N.rec[s2].st : 0;
       if (s2 < 0 || f2 < 0 || !node_live(st2) || !(node_glue_bits(st2) & (1 << f2))) {

@@ -172,7 +172,9 @@ __device__ __forceinline__ void emit_piece(Clipper<T, Topo, Mask, VCAP, EXACT, T
   const int i = c.env.site_i;  // batch-global site id
   const unsigned* nu = sd.nu + 14 * (size_t)tl;
   const long long L = sd.L;
-  const int* tn = sd.tn + 4 * (size_t)tl;
+  const int4 tn4 = reinterpret_cast<const int4*>(sd.tn)[tl];  // face neighbours (-1: boundary), one load
+  const unsigned interior = (tn4.x >= 0 ? 1u : 0u) | (tn4.y >= 0 ? 2u : 0u) | (tn4.z >= 0 ? 4u : 0u) |
+                            (tn4.w >= 0 ? 8u : 0u);  // bit f: face f is shared with another tet
   const int t = (int)(sd.tet_off + tl);  // batch-global tet id (node keys, piece records)
   const int sign = sd.sign;
   int* status = a.status;
@@ -225,7 +227,7 @@ __device__ __forceinline__ void emit_piece(Clipper<T, Topo, Mask, VCAP, EXACT, T
     c.tab.set(p, 0);
     r -= 1;
     sf += (p < 4) ? (long long)nu[10 + p] : L;
-    if (p < 4) cell_glue |= tn[p] >= 0 ? 1 << p : 16 << p;  // glue across an interior face; boundary contact
+    if (p < 4) cell_glue |= ((interior >> p) & 1u) ? 1 << p : 16 << p;  // glue across an interior face; boundary contact
     const int sp = c.env.plane_site(p);
     const bool felem = (p >= 4) && (sp > i);
     long long fv = 0, fe = 0;
@@ -252,7 +254,7 @@ __device__ __forceinline__ void emit_piece(Clipper<T, Topo, Mask, VCAP, EXACT, T
       if (felem) {  // the edge cur -> nxt lies on planes {p, acur}
         fe += w_edge(p, acur, nu, L);
         if (acur < 4) {
-          if (tn[acur] >= 0) fglue |= 1 << acur;
+          if ((interior >> acur) & 1u) fglue |= 1 << acur;
         } else if (acur > p) {
           int sa = c.env.plane_site(acur);
           if (sa > i) {  // RPE piece of {i, sp, sa}, counted from its smaller plane id
@@ -269,7 +271,8 @@ __device__ __forceinline__ void emit_piece(Clipper<T, Topo, Mask, VCAP, EXACT, T
               const T lx = N.x - C.x, ly = N.y - C.y, lz = N.z - C.z;
               const double len = (double)sqrt(lx * lx + ly * ly + lz * lz);
               atomicAdd((unsigned long long*)&a.edge_len[es], (unsigned long long)(sign * fixed56(len)));
-              int g = ((t1 < 4 && tn[t1] >= 0) ? (1 << t1) : 0) | ((t2 < 4 && tn[t2] >= 0) ? (1 << t2) : 0);
+              int g = ((t1 < 4 && ((interior >> t1) & 1u)) ? (1 << t1) : 0) |
+                      ((t2 < 4 && ((interior >> t2) & 1u)) ? (1 << t2) : 0);
               node_emit(a, sign, node_key(3, es, t), g);
               keep_term(a, 3, t, i, j, k, -1, g, ev);
             }

@@ -225,6 +225,13 @@ __global__ void k_clear_touched_b0(const unsigned char* touch, int* b0, size_t n
 // Every gluing bit is matched from the tet with the smaller id only (one lookup and one union per glued pair); the
 // symmetry of the records is checked by counting: the bits set must be twice the pairs matched.
 __global__ void k_glue(ShapeArgs a, const int* list, const int* seg, unsigned len) {
+  // the shapes' first tets, for the lookup of a piece's shape in LDS (up to 256 shapes; more search in memory)
+  constexpr int LS = 256;
+  __shared__ long long s_toff[LS];
+  const bool local = a.nshapes > 1 && a.nshapes <= LS;
+  if (local)
+    for (int k = threadIdx.x; k < a.nshapes; k += blockDim.x) s_toff[k] = a.shapes[k].tet_off;
+  __syncthreads();
   const int n = seg[blockIdx.x];
   unsigned long long bits = 0, pairs = 0;
   for (int k = threadIdx.x; k < n; k += blockDim.x) {
@@ -235,7 +242,19 @@ __global__ void k_glue(ShapeArgs a, const int* list, const int* seg, unsigned le
     if (!g) continue;
     bits += __popc(g);
     const long long gt = (long long)(key & 0xffffffffull);
-    const ShapeDesc& sd = a.shapes[shape_of_tet(a.shapes, a.nshapes, gt)];
+    int sh = 0;
+    if (local) {  // the last shape whose first tet is at most gt
+      int lo = 0, hi = a.nshapes - 1;
+      while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (s_toff[mid] <= gt) lo = mid;
+        else hi = mid - 1;
+      }
+      sh = lo;
+    } else if (a.nshapes > 1) {
+      sh = shape_of_tet(a.shapes, a.nshapes, gt);
+    }
+    const ShapeDesc& sd = a.shapes[sh];
     const int t = (int)(gt - sd.tet_off);
     unsigned long long hi = key & ~0xffffffffull;
     const int4 nb = reinterpret_cast<const int4*>(sd.tn)[t];  // the four face neighbours, one 16-byte load

@@ -370,7 +370,7 @@ def main():
                          "FETCH_SIZE / WRITE_SIZE counters to bytes) and exit")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("this build runs on one GPU only: multi-GPU sharding is a design note, not an implemented path",
+        print("the benchmark runs on one GPU only: sharding across GPUs is described, not implemented",
               file=sys.stderr)
         sys.exit(2)
 

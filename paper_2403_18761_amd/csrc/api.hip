@@ -411,8 +411,8 @@ static bool collect(DeviceState& D, const std::vector<ShapeDesc>& hd, const Shap
   // the list counts were zeroed with the other counters when the state was cleared; an incremental session collects
   // again and again from one state
   if (D.touch.p) hip_check(launch_fill_u64(fin, 0, 3, s), "fill");
-  // the row sort's per-row counts and cursors (3 (ns + 1) and 3 ns ints), for up to 2^16 sites
-  const size_t n_rowc = ns < (1 << 16) ? 3 * ((size_t)ns + 1) + 3 * (size_t)std::max(ns, 1) : 0;
+  // the row sort's per-row counts and cursors (3 (ns + 1) and 3 ns ints)
+  const size_t n_rowc = 3 * ((size_t)ns + 1) + 3 * (size_t)std::max(ns, 1);
   DBuf rowc(4 * std::max<size_t>(n_rowc, 1));
   {
     CompactLists J;
@@ -426,7 +426,7 @@ static bool collect(DeviceState& D, const std::vector<ShapeDesc>& hd, const Shap
     J.rpv_cpt = 0;
     J.rpv_out = rq.as<int4>();
     J.rpv_count = fin + 2;
-    J.zero = rowc.as<int>();  // the row sort's counters (up to 2^16 sites), cleared in the same launch
+    J.zero = rowc.as<int>();  // the row sort's counters, cleared in the same launch
     J.n_zero = n_rowc;
     hip_check(launch_compact_lists(J, s), "live faces, edges and rpvs");
   }
@@ -453,25 +453,27 @@ static bool collect(DeviceState& D, const std::vector<ShapeDesc>& hd, const Shap
   const auto spec_key = std::make_tuple(ns, nsh, capF, capE, capQ);
   std::shared_ptr<HostPinned> host;  // kept by the result (its arrays point into it)
   size_t spec = 0;                   // bytes downloaded before the counts were known
-  if (ns < (1 << 16)) {
-    // up to 2^16 sites: the lists are sorted by rows of their first site and slots are looked up again by key. The
-    // whole sequence is queued before the host waits for the counts (the buffer is sized for full tables).
+  {
+    // the lists are sorted by rows of their first site and slots are looked up again by key; the whole sequence is
+    // queued before the host waits for the counts (the buffer is sized for full tables)
     out.alloc(out_layout(ns, nsh, capF, capE, capQ).bytes);
     od.base = out.as<unsigned char>();
-    DBuf kq(8 * (size_t)capQ), t0(8 * (size_t)capF), t1(8 * (size_t)capE), t2(8 * (size_t)capQ);
+    DBuf kq(8 * (size_t)capQ), t0(8 * (size_t)capF), t1(8 * (size_t)capE), t2(8 * (size_t)capQ),
+        qrow(4 * (size_t)capQ);
     unsigned long long* const keys[3] = {fk.as<unsigned long long>(), ek.as<unsigned long long>(),
                                          kq.as<unsigned long long>()};
     unsigned long long* const tmps[3] = {t0.as<unsigned long long>(), t1.as<unsigned long long>(),
                                          t2.as<unsigned long long>()};
     const size_t caps[3] = {capF, capE, capQ};
-    const int shifts[3] = {32, 42, 48};
+    const int shifts[3] = {32, 42, 0};  // RPVs: rows carried beside the keys
     hip_check(launch_row_sort(keys, tmps, fin, caps, shifts, std::max(ns, 1), rowc.as<int>(),
-                              rowc.as<int>() + 3 * ((size_t)ns + 1), rq.as<int4>(), s),
+                              rowc.as<int>() + 3 * ((size_t)ns + 1), rq.as<int4>(), qrow.as<int>(), s),
               "sort lists");
     FinalizeRows R;
     R.fkeys = fk.as<unsigned long long>();
     R.ekeys = ek.as<unsigned long long>();
     R.qkeys = kq.as<unsigned long long>();
+    R.qrows = qrow.as<int>();
     R.F = F;
     R.E = E;
     R.face_chi = D.face_chi.as<long long>();
@@ -502,46 +504,10 @@ static bool collect(DeviceState& D, const std::vector<ShapeDesc>& hd, const Shap
     nf = hc[NCOUNTERS + 0];
     ne = hc[NCOUNTERS + 1];
     nq = hc[NCOUNTERS + 2];
-  } else {
-    // more sites: radix sorts, sized by the live counts read first
-    if (!check_totals()) return false;
-    nf = hc[NCOUNTERS + 0];
-    ne = hc[NCOUNTERS + 1];
-    nq = hc[NCOUNTERS + 2];
-    const OutLayout L = out_layout(ns, nsh, nf, ne, nq);
-    out.alloc(L.bytes);
-    od.base = out.as<unsigned char>();
-    const size_t maxn = std::max(std::max(nf, ne), std::max(nq, (size_t)1));
-    size_t tmpb = sort_tmp_bytes((int)maxn);
-    DBuf tmp(tmpb), kA(8 * maxn), kB(8 * maxn), kC(8 * maxn), vA(4 * maxn), vB(4 * maxn);
-    hip_check(sort_pairs_u64(tmp.p, tmpb, fk.as<unsigned long long>(), kB.as<unsigned long long>(), fsl.as<int>(),
-                             vB.as<int>(), (int)nf, s),
-              "sort faces");
-    hip_check(launch_finalize_faces(kB.as<unsigned long long>(), vB.as<int>(), F, std::max<size_t>(nf, 1), od,
-                                    D.face_chi.as<long long>(), D.face_b0.as<int>(), dshapes, nsh, D.status.as<int>(),
-                                    s),
-              "finalize faces");
-    hip_check(sort_pairs_u64(tmp.p, tmpb, ek.as<unsigned long long>(), kB.as<unsigned long long>(), esl.as<int>(),
-                             vB.as<int>(), (int)ne, s),
-              "sort edges");
-    hip_check(launch_finalize_edges(kB.as<unsigned long long>(), vB.as<int>(), E, std::max<size_t>(ne, 1), od,
-                                    D.edge_chi.as<long long>(), D.edge_b0.as<int>(), D.edge_len.as<long long>(),
-                                    D.site.as<float4>(), dshapes, nsh, D.status.as<int>(), s),
-              "finalize edges");
-    hip_check(launch_sort_rpv(rq.as<int4>(), (int)nq, kA.as<unsigned long long>(), kB.as<unsigned long long>(),
-                              kC.as<unsigned long long>(), vA.as<int>(), vB.as<int>(), tmp.p, tmpb,
-                              (int4*)(od.base + L.rpv), s),
-              "sort rpv");
-    if (nsh > 1) hip_check(launch_localize_lists(od, std::max(maxn, (size_t)1), dshapes, nsh, s), "localize lists");
-    if (ns > 0)
-      hip_check(launch_finalize_cells(ns, D.cell_chi.as<long long>(), D.cell_geo.as<long long>(), D.cell_np.as<int>(),
-                                      D.cell_b0.as<int>(), dshapes, nsh, od, D.status.as<int>(), s),
-                "finalize cells");
-    tm.mark(3, s);
   }
   const OutLayout L = out_layout(ns, nsh, nf, ne, nq);
   const size_t out_bytes = L.bytes;
-  if (ns < (1 << 16) && !D.piece_cap) {
+  if (!D.piece_cap) {
     std::lock_guard<std::mutex> g(g_spec_mu);
     g_spec[spec_key] = out_bytes;
   }

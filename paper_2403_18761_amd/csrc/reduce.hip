@@ -5,7 +5,6 @@
 #include <cstring>
 
 #include <hip/hip_runtime.h>
-#include <rocprim/device/device_radix_sort.hpp>
 
 #include "rpd_device.h"
 #include "rpd_launch.h"
@@ -420,33 +419,38 @@ hipError_t launch_compact_lists(CompactLists J, hipStream_t s) {
   return hipGetLastError();
 }
 
-// Lists whose keys lead with a site id below 2^16 (one row per site) are sorted by rows: count the keys of every
-// row, scan the counts, scatter the keys to their rows, then place each key by its rank within its (short) row. Up to three lists per launch
-// (blockIdx.y selects the list); the row arrays hold 3 x (rows + 1) counts and 3 x rows cursors.
+// The element lists are sorted by rows, one row per first site: count the keys of every row, scan the counts,
+// scatter the keys to their rows, then place each key by its rank within its (short) row. Three lists per launch
+// (blockIdx.y selects the list); the row arrays hold 3 x (rows + 1) counts and 3 x rows cursors. Faces and edges
+// carry their first site in the key's top bits; an RPV (i, j, k, l) is keyed by (j, k, l) in 63 bits with its row i
+// kept beside it (the scatter writes it next to the key's row position, which the ranking only permutes).
 struct RowLists {
-  unsigned long long* keys[3];  // in: keys (any order); out: sorted
+  unsigned long long* keys[3];  // in: keys (lists 0 and 1; list 2 is built from rpv); out: sorted
   unsigned long long* tmp[3];   // scratch of the same size
   const unsigned long long* n;  // [3] key counts, in device memory
-  int shift[3];                 // row = key >> shift
+  int shift[3];                 // row = key >> shift (lists 0 and 1)
   int* off;                     // [3][rows + 1]
   int* cur;                     // [3][rows]
   int rows;
-  const int4* pack;             // or null: list 2 is packed from these RPV quadruples while it is counted
+  const int4* rpv;              // list 2's RPV quadruples, in any order
+  int* rpv_row;                 // [n[2]]: the row (first site) of each sorted position of list 2
 };
+__device__ __forceinline__ unsigned long long rpv_key(const int4& r) {  // (j, k, l), 21 bits each
+  return ((unsigned long long)r.y << 42) | ((unsigned long long)r.z << 21) | (unsigned long long)r.w;
+}
 __global__ void k_row_count(RowLists L) {
   const int l = blockIdx.y, n = (int)L.n[l];
   int* off = L.off + l * (L.rows + 1);
   for (int q = blockIdx.x * blockDim.x + threadIdx.x; q < n; q += gridDim.x * blockDim.x) {
-    unsigned long long k;
-    if (l == 2 && L.pack) {  // RPV quadruple with every id below 2^16, packed into one key
-      const int4 r = L.pack[q];
-      k = ((unsigned long long)r.x << 48) | ((unsigned long long)r.y << 32) | ((unsigned long long)r.z << 16) |
-          (unsigned long long)r.w;
-      L.keys[2][q] = k;
+    int row;
+    if (l == 2) {
+      const int4 r = L.rpv[q];
+      L.keys[2][q] = rpv_key(r);
+      row = r.x;
     } else {
-      k = L.keys[l][q];
+      row = (int)(L.keys[l][q] >> L.shift[l]);
     }
-    atomicAdd(&off[(int)(k >> L.shift[l]) + 1], 1);
+    atomicAdd(&off[row + 1], 1);
   }
 }
 // exclusive scan of the row counts in place (one workgroup per list)
@@ -477,8 +481,10 @@ __global__ void k_row_scatter(RowLists L) {
   int* cur = L.cur + l * L.rows;
   for (int q = blockIdx.x * blockDim.x + threadIdx.x; q < n; q += gridDim.x * blockDim.x) {
     const unsigned long long k = L.keys[l][q];
-    const int r = (int)(k >> L.shift[l]);
-    L.tmp[l][off[r] + atomicAdd(&cur[r], 1)] = k;
+    const int r = l == 2 ? L.rpv[q].x : (int)(k >> L.shift[l]);
+    const int pos = off[r] + atomicAdd(&cur[r], 1);
+    L.tmp[l][pos] = k;
+    if (l == 2) L.rpv_row[pos] = r;
   }
 }
 // every key finds its place within its row by counting the smaller keys of the row (rows are short; keys unique)
@@ -488,7 +494,7 @@ __global__ void k_row_rank(RowLists L) {
   const unsigned long long* t = L.tmp[l];
   for (int q = blockIdx.x * blockDim.x + threadIdx.x; q < n; q += gridDim.x * blockDim.x) {
     const unsigned long long k = t[q];
-    const int r = (int)(k >> L.shift[l]);
+    const int r = l == 2 ? L.rpv_row[q] : (int)(k >> L.shift[l]);
     const int a = off[r], b = off[r + 1];
     int rank = 0;
     for (int x = a; x < b; ++x) rank += t[x] < k ? 1 : 0;
@@ -497,7 +503,7 @@ __global__ void k_row_rank(RowLists L) {
 }
 hipError_t launch_row_sort(unsigned long long* const keys[3], unsigned long long* const tmp[3],
                            const unsigned long long* n, const size_t ncap[3], const int shift[3], int rows, int* off,
-                           int* cur, const int4* pack_rpv, hipStream_t s) {
+                           int* cur, const int4* rpv, int* rpv_row, hipStream_t s) {
   RowLists L;
   size_t nmax = 1;
   for (int l = 0; l < 3; ++l) {
@@ -511,7 +517,8 @@ hipError_t launch_row_sort(unsigned long long* const keys[3], unsigned long long
   L.off = off;
   L.cur = cur;
   L.rows = rows;
-  L.pack = pack_rpv;
+  L.rpv = rpv;
+  L.rpv_row = rpv_row;
   hipLaunchKernelGGL(k_row_count, dim3(grid, 3), dim3(256), 0, s, L);
   hipLaunchKernelGGL(k_row_scan, dim3(3), dim3(1024), 0, s, L);
   hipLaunchKernelGGL(k_row_scatter, dim3(grid, 3), dim3(256), 0, s, L);
@@ -519,21 +526,15 @@ hipError_t launch_row_sort(unsigned long long* const keys[3], unsigned long long
   return hipGetLastError();
 }
 
-// packed RPV keys (see k_row_count) back to quadruples
-__device__ __forceinline__ void unpack_rpv_body(int t0, int stride, const unsigned long long* in, const OutDesc& od) {
+// sorted RPV keys and their rows (see k_row_count) back to quadruples
+__device__ __forceinline__ void unpack_rpv_body(int t0, int stride, const unsigned long long* in, const int* row,
+                                                const OutDesc& od) {
   const int n = (int)od.n[2];
   int4* out = (int4*)(od.base + od.layout().rpv);
   for (int q = t0; q < n; q += stride) {
     const unsigned long long k = in[q];
-    out[q] = make_int4((int)(k >> 48), (int)((k >> 32) & 0xffff), (int)((k >> 16) & 0xffff), (int)(k & 0xffff));
+    out[q] = make_int4(row[q], (int)(k >> 42), (int)((k >> 21) & 0x1fffff), (int)(k & 0x1fffff));
   }
-}
-
-
-hipError_t sort_pairs_u64(void* tmp, size_t& tmp_bytes, const unsigned long long* kin, unsigned long long* kout,
-                          const int* vin, int* vout, int n, hipStream_t s) {
-  if (n <= 0) return hipSuccess;
-  return rocprim::radix_sort_pairs(tmp, tmp_bytes, kin, kout, vin, vout, (size_t)n, 0, 64, s);
 }
 
 __device__ __forceinline__ void finalize_faces_body(int t0, int stride, const unsigned long long* keys,
@@ -556,12 +557,6 @@ __device__ __forceinline__ void finalize_faces_body(int t0, int stride, const un
     out_chi[q] = (int)(c / L);
     out_b0[q] = b0[s];
   }
-}
-__global__ void k_finalize_faces(const unsigned long long* keys, const int* slots, HashTab T, OutDesc od,
-                                 const long long* chi_num, const int* b0, const ShapeDesc* shapes, int nshapes,
-                                 int* status) {
-  finalize_faces_body(blockIdx.x * blockDim.x + threadIdx.x, gridDim.x * blockDim.x, keys, slots, T, od, chi_num, b0,
-                      shapes, nshapes, status);
 }
 // RPE length (fixed point -> double) and the thinning importance alpha = length / mean diameter of the three spheres
 __device__ __forceinline__ void finalize_edges_body(int t0, int stride, const unsigned long long* keys,
@@ -594,12 +589,6 @@ __device__ __forceinline__ void finalize_edges_body(int t0, int stride, const un
     out_alpha[q] = dsum > 0.0 ? 3.0 * len / dsum : INFINITY;
   }
 }
-__global__ void k_finalize_edges(const unsigned long long* keys, const int* slots, HashTab T, OutDesc od,
-                                 const long long* chi_num, const int* b0, const long long* len_num,
-                                 const float4* site, const ShapeDesc* shapes, int nshapes, int* status) {
-  finalize_edges_body(blockIdx.x * blockDim.x + threadIdx.x, gridDim.x * blockDim.x, keys, slots, T, od, chi_num, b0,
-                      len_num, site, shapes, nshapes, status);
-}
 __device__ __forceinline__ void finalize_cells_body(int t0, int stride, int ns, const long long* chi_num,
                                                     const long long* geo, const int* np, const int* b0,
                                                     const ShapeDesc* shapes, int nshapes, const OutDesc& od,
@@ -626,11 +615,6 @@ __device__ __forceinline__ void finalize_cells_body(int t0, int stride, int ns, 
     for (int d = 0; d < 3; ++d) out_cen[3 * (size_t)i + d] = np[i] ? value(1 + d) / v : NAN;
   }
 }
-__global__ void k_finalize_cells(int ns, const long long* chi_num, const long long* geo, const int* np, const int* b0,
-                                 const ShapeDesc* shapes, int nshapes, OutDesc od, int* status) {
-  finalize_cells_body(blockIdx.x * blockDim.x + threadIdx.x, gridDim.x * blockDim.x, ns, chi_num, geo, np, b0, shapes,
-                      nshapes, od, status);
-}
 // blockIdx.y: faces, edges, RPVs, cells
 __global__ void k_finalize_rows(FinalizeRows R, OutDesc od, const ShapeDesc* shapes, int nshapes, int* status) {
   const int t0 = blockIdx.x * blockDim.x + threadIdx.x, stride = gridDim.x * blockDim.x;
@@ -643,7 +627,7 @@ __global__ void k_finalize_rows(FinalizeRows R, OutDesc od, const ShapeDesc* sha
                           nshapes, status);
       break;
     case 2:
-      unpack_rpv_body(t0, stride, R.qkeys, od);
+      unpack_rpv_body(t0, stride, R.qkeys, R.qrows, od);
       break;
     default:
       finalize_cells_body(t0, stride, R.ns, R.cell_chi, R.cell_geo, R.cell_np, R.cell_b0, shapes, nshapes, od, status);
@@ -656,64 +640,7 @@ hipError_t launch_finalize_rows(const FinalizeRows& R, size_t ncap, const OutDes
   return hipGetLastError();
 }
 
-hipError_t launch_finalize_faces(const unsigned long long* keys, const int* slots, const HashTab& T, size_t ncap,
-                                 const OutDesc& od, const long long* chi_num, const int* b0, const ShapeDesc* shapes,
-                                 int nshapes, int* status, hipStream_t s) {
-  hipLaunchKernelGGL(k_finalize_faces, dim3(std::min(grid_for(ncap, 256), 2048)), dim3(256), 0, s, keys, slots, T, od,
-                     chi_num, b0, shapes, nshapes, status);
-  return hipGetLastError();
-}
-hipError_t launch_finalize_edges(const unsigned long long* keys, const int* slots, const HashTab& T, size_t ncap,
-                                 const OutDesc& od, const long long* chi_num, const int* b0, const long long* len_num,
-                                 const float4* site, const ShapeDesc* shapes, int nshapes, int* status,
-                                 hipStream_t s) {
-  hipLaunchKernelGGL(k_finalize_edges, dim3(std::min(grid_for(ncap, 256), 2048)), dim3(256), 0, s, keys, slots, T, od,
-                     chi_num, b0, len_num, site, shapes, nshapes, status);
-  return hipGetLastError();
-}
-hipError_t launch_finalize_cells(int ns, const long long* chi_num, const long long* geo, const int* np, const int* b0,
-                                 const ShapeDesc* shapes, int nshapes, const OutDesc& od, int* status, hipStream_t s) {
-  hipLaunchKernelGGL(k_finalize_cells, dim3(grid_for(ns, 256)), dim3(256), 0, s, ns, chi_num, geo, np, b0, shapes,
-                     nshapes, od, status);
-  return hipGetLastError();
-}
 
-// RPV quadruples: two stable radix passes, by (k, l) and then by (i, j)
-__global__ void k_rpv_keys(const int4* rpv, int n, unsigned long long* k_hi, unsigned long long* k_lo, int* idx) {
-  for (int q = blockIdx.x * blockDim.x + threadIdx.x; q < n; q += gridDim.x * blockDim.x) {
-    int4 r = rpv[q];
-    k_hi[q] = ((unsigned long long)(unsigned)r.x << 32) | (unsigned)r.y;
-    k_lo[q] = ((unsigned long long)(unsigned)r.z << 32) | (unsigned)r.w;
-    idx[q] = q;
-  }
-}
-__global__ void k_gather_u64(const unsigned long long* src, const int* idx, unsigned long long* dst, int n) {
-  for (int q = blockIdx.x * blockDim.x + threadIdx.x; q < n; q += gridDim.x * blockDim.x) dst[q] = src[idx[q]];
-}
-__global__ void k_gather_rpv(const int4* src, const int* idx, int4* dst, int n) {
-  for (int q = blockIdx.x * blockDim.x + threadIdx.x; q < n; q += gridDim.x * blockDim.x) dst[q] = src[idx[q]];
-}
-
-// buffers: ka, kb, kc of n u64 each; va, vb of n ints
-hipError_t launch_sort_rpv(const int4* rpv, int n, unsigned long long* ka, unsigned long long* kb,
-                           unsigned long long* kc, int* va, int* vb, void* tmp, size_t tmp_bytes, int4* out,
-                           hipStream_t s) {
-  if (n <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_rpv_keys, dim3(grid_for(n, 256)), dim3(256), 0, s, rpv, n, ka, kb, va);
-  hipError_t e = rocprim::radix_sort_pairs(tmp, tmp_bytes, kb, kc, va, vb, (size_t)n, 0, 64, s);
-  if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_gather_u64, dim3(grid_for(n, 256)), dim3(256), 0, s, ka, vb, kb, n);
-  e = rocprim::radix_sort_pairs(tmp, tmp_bytes, kb, kc, vb, va, (size_t)n, 0, 64, s);
-  if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_gather_rpv, dim3(grid_for(n, 256)), dim3(256), 0, s, rpv, va, out, n);
-  return hipGetLastError();
-}
-size_t sort_tmp_bytes(int n) {
-  size_t b = 0;
-  (void)rocprim::radix_sort_pairs(nullptr, b, (unsigned long long*)nullptr, (unsigned long long*)nullptr,
-                                  (int*)nullptr, (int*)nullptr, (size_t)n, 0, 64, (hipStream_t)0);
-  return b;
-}
 
 // ---------------------------------------------------------------------------------------------------------------
 // site validation: finite, on the 2^-20 grid, |centre| <= 1, 0 <= r <= 2; packs (x, y, z, r)

@@ -75,30 +75,18 @@ struct CompactLists {
   size_t n_zero;
 };
 hipError_t launch_compact_lists(CompactLists J, hipStream_t s);
-hipError_t sort_pairs_u64(void* tmp, size_t& tmp_bytes, const unsigned long long* kin, unsigned long long* kout,
-                          const int* vin, int* vout, int n, hipStream_t s);
-size_t sort_tmp_bytes(int n);
-// element lists over exactly n sorted live entries
-// (slots may be null: each key's slot is then looked up in T)
-hipError_t launch_finalize_faces(const unsigned long long* keys, const int* slots, const HashTab& T, size_t ncap,
-                                 const OutDesc& od, const long long* chi_num, const int* b0, const ShapeDesc* shapes,
-                                 int nshapes, int* status, hipStream_t s);
-hipError_t launch_finalize_edges(const unsigned long long* keys, const int* slots, const HashTab& T, size_t ncap,
-                                 const OutDesc& od, const long long* chi_num, const int* b0, const long long* len_num,
-                                 const float4* site, const ShapeDesc* shapes, int nshapes, int* status,
-                                 hipStream_t s);
 // three lists of keys whose row (key >> shift) is below rows, sorted ascending in place; tmp[l] holds n[l] keys;
 // off holds 3 (rows + 1) ints, cur 3 rows ints
-// (off and cur must be zero; with pack_rpv set, list 2 is first packed from those RPV quadruples, ids below 2^16)
+// (off and cur must be zero; list 2 is built from the RPV quadruples rpv: keys[2] receives their (j, k, l) keys
+// sorted by (i, j, k, l) and rpv_row their first sites i)
 hipError_t launch_row_sort(unsigned long long* const keys[3], unsigned long long* const tmp[3],
                            const unsigned long long* n, const size_t ncap[3], const int shift[3], int rows, int* off,
-                           int* cur, const int4* pack_rpv, hipStream_t s);
-hipError_t launch_finalize_cells(int ns, const long long* chi_num, const long long* geo, const int* np, const int* b0,
-                                 const ShapeDesc* shapes, int nshapes, const OutDesc& od, int* status, hipStream_t s);
-// the row-sorted path's four last steps in one launch: face and edge lists (slots looked up by key), the packed RPVs
-// unpacked, and the cells
+                           int* cur, const int4* rpv, int* rpv_row, hipStream_t s);
+// the collect step's four last steps in one launch: face and edge lists over the sorted keys (slots looked up by
+// key), the sorted RPVs as quadruples, and the cells
 struct FinalizeRows {
   const unsigned long long *fkeys, *ekeys, *qkeys;
+  const int* qrows;  // the first site of each sorted RPV
   HashTab F, E;
   const long long *face_chi, *edge_chi, *edge_len, *cell_chi, *cell_geo;
   const int *face_b0, *edge_b0, *cell_np, *cell_b0;
@@ -107,9 +95,6 @@ struct FinalizeRows {
 };
 hipError_t launch_finalize_rows(const FinalizeRows& R, size_t ncap, const OutDesc& od, const ShapeDesc* shapes,
                                 int nshapes, int* status, hipStream_t s);
-hipError_t launch_sort_rpv(const int4* rpv, int n, unsigned long long* ka, unsigned long long* kb,
-                           unsigned long long* kc, int* va, int* vb, void* tmp, size_t tmp_bytes, int4* out,
-                           hipStream_t s);
 hipError_t launch_validate_sites(const float* sx, const float* sy, const float* sz, const float* sr, int ns,
                                  float4* site, int* status, hipStream_t s);
 // the sites of every shape of a call in one launch (src: device array of nsrc records, max_n = the largest n)

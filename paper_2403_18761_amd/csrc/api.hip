@@ -411,9 +411,9 @@ static bool collect(DeviceState& D, const std::vector<ShapeDesc>& hd, const Shap
   // the list counts were zeroed with the other counters when the state was cleared; an incremental session collects
   // again and again from one state
   if (D.touch.p) hip_check(launch_fill_u64(fin, 0, 3, s), "fill");
-  // the row sort's per-row counts and cursors (3 (ns + 1) and 3 ns ints)
+  // the row sort's per-row counts and cursors (3 (ns + 1) and 3 ns ints), cleared, and its tile sums
   const size_t n_rowc = 3 * ((size_t)ns + 1) + 3 * (size_t)std::max(ns, 1);
-  DBuf rowc(4 * std::max<size_t>(n_rowc, 1));
+  DBuf rowc(4 * (n_rowc + 3 * (size_t)row_tiles(std::max(ns, 1))));
   {
     CompactLists J;
     J.live[0] = {D.fkeys.as<unsigned long long>(), D.face_np.as<int>(), capF, 0, fk.as<unsigned long long>(),
@@ -467,7 +467,8 @@ static bool collect(DeviceState& D, const std::vector<ShapeDesc>& hd, const Shap
     const size_t caps[3] = {capF, capE, capQ};
     const int shifts[3] = {32, 42, 0};  // RPVs: rows carried beside the keys
     hip_check(launch_row_sort(keys, tmps, fin, caps, shifts, std::max(ns, 1), rowc.as<int>(),
-                              rowc.as<int>() + 3 * ((size_t)ns + 1), rq.as<int4>(), qrow.as<int>(), s),
+                              rowc.as<int>() + 3 * ((size_t)ns + 1), rq.as<int4>(), qrow.as<int>(),
+                              rowc.as<int>() + n_rowc, s),
               "sort lists");
     FinalizeRows R;
     R.fkeys = fk.as<unsigned long long>();

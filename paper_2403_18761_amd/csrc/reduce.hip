@@ -434,7 +434,15 @@ struct RowLists {
   int rows;
   const int4* rpv;              // list 2's RPV quadruples, in any order
   int* rpv_row;                 // [n[2]]: the row (first site) of each sorted position of list 2
+  int* tsum;                    // [3][ntiles]: per tile of ROW_TILE counts, the sum of the tiles before it
+  int ntiles;
 };
+constexpr int ROW_TILE = 4096;  // row counts scanned per workgroup
+// the first position of row r of list l (the tile's scan plus the tiles before it)
+__device__ __forceinline__ int row_start(const RowLists& L, int l, int r) {
+  const int v = L.off[l * (L.rows + 1) + r];
+  return L.ntiles > 1 ? v + L.tsum[l * L.ntiles + r / ROW_TILE] : v;
+}
 __device__ __forceinline__ unsigned long long rpv_key(const int4& r) {  // (j, k, l), 21 bits each
   return ((unsigned long long)r.y << 42) | ((unsigned long long)r.z << 21) | (unsigned long long)r.w;
 }
@@ -453,36 +461,64 @@ __global__ void k_row_count(RowLists L) {
     atomicAdd(&off[row + 1], 1);
   }
 }
-// exclusive scan of the row counts in place (one workgroup per list)
+// the row counts scanned in place, one tile of ROW_TILE per workgroup (grid.y = list): off[q] held the count of row
+// q - 1 and becomes the sum of the counts of the rows before q within its tile; the tile's total goes to tsum
 __global__ __launch_bounds__(1024) void k_row_scan(RowLists L) {
+  __shared__ int s_v[ROW_TILE];
   __shared__ int s_part[1024];
-  const int l = blockIdx.x;
+  const int l = blockIdx.y, t = threadIdx.x;
   int* off = L.off + l * (L.rows + 1);
-  const int n = L.rows + 1, per = (n + 1023) / 1024, b0 = threadIdx.x * per, b1 = min(n, b0 + per);
-  int sum = 0;
-  for (int q = b0; q < b1; ++q) sum += off[q];
-  s_part[threadIdx.x] = sum;
+  const int n = L.rows + 1, base = blockIdx.x * ROW_TILE;
+  for (int k = 0; k < ROW_TILE / 1024; ++k) {
+    const int q = base + k * 1024 + t;
+    s_v[k * 1024 + t] = q < n ? off[q] : 0;
+  }
+  __syncthreads();
+  int v[ROW_TILE / 1024], sum = 0;
+  for (int k = 0; k < ROW_TILE / 1024; ++k) {
+    sum += s_v[t * (ROW_TILE / 1024) + k];
+    v[k] = sum;
+  }
+  s_part[t] = sum;
   __syncthreads();
   for (int d = 1; d < 1024; d <<= 1) {  // inclusive scan of the per-thread sums
-    const int v = threadIdx.x >= d ? s_part[threadIdx.x - d] : 0;
+    const int x = t >= d ? s_part[t - d] : 0;
     __syncthreads();
-    s_part[threadIdx.x] += v;
+    s_part[t] += x;
     __syncthreads();
   }
-  int run = threadIdx.x ? s_part[threadIdx.x - 1] : 0;
-  for (int q = b0; q < b1; ++q) {  // off[q] held the count of row q - 1
-    run += off[q];
-    off[q] = run;
+  const int run = t ? s_part[t - 1] : 0;
+  for (int k = 0; k < ROW_TILE / 1024; ++k) s_v[t * (ROW_TILE / 1024) + k] = run + v[k];
+  __syncthreads();
+  for (int k = 0; k < ROW_TILE / 1024; ++k) {
+    const int q = base + k * 1024 + t;
+    if (q < n) off[q] = s_v[k * 1024 + t];
   }
+  if (t == 1023 && L.ntiles > 1) L.tsum[l * L.ntiles + blockIdx.x] = s_part[1023];
+}
+// the tile totals of each list turned into the sums of the tiles before each (one workgroup per list)
+__global__ __launch_bounds__(1024) void k_row_tiles(RowLists L) {
+  __shared__ int s_part[1024];
+  const int l = blockIdx.x, t = threadIdx.x;
+  int* ts = L.tsum + l * L.ntiles;
+  const int x0 = t < L.ntiles ? ts[t] : 0;
+  s_part[t] = x0;
+  __syncthreads();
+  for (int d = 1; d < 1024; d <<= 1) {
+    const int x = t >= d ? s_part[t - d] : 0;
+    __syncthreads();
+    s_part[t] += x;
+    __syncthreads();
+  }
+  if (t < L.ntiles) ts[t] = s_part[t] - x0;
 }
 __global__ void k_row_scatter(RowLists L) {
   const int l = blockIdx.y, n = (int)L.n[l];
-  const int* off = L.off + l * (L.rows + 1);
   int* cur = L.cur + l * L.rows;
   for (int q = blockIdx.x * blockDim.x + threadIdx.x; q < n; q += gridDim.x * blockDim.x) {
     const unsigned long long k = L.keys[l][q];
     const int r = l == 2 ? L.rpv[q].x : (int)(k >> L.shift[l]);
-    const int pos = off[r] + atomicAdd(&cur[r], 1);
+    const int pos = row_start(L, l, r) + atomicAdd(&cur[r], 1);
     L.tmp[l][pos] = k;
     if (l == 2) L.rpv_row[pos] = r;
   }
@@ -490,20 +526,21 @@ __global__ void k_row_scatter(RowLists L) {
 // every key finds its place within its row by counting the smaller keys of the row (rows are short; keys unique)
 __global__ void k_row_rank(RowLists L) {
   const int l = blockIdx.y, n = (int)L.n[l];
-  const int* off = L.off + l * (L.rows + 1);
   const unsigned long long* t = L.tmp[l];
   for (int q = blockIdx.x * blockDim.x + threadIdx.x; q < n; q += gridDim.x * blockDim.x) {
     const unsigned long long k = t[q];
     const int r = l == 2 ? L.rpv_row[q] : (int)(k >> L.shift[l]);
-    const int a = off[r], b = off[r + 1];
+    const int a = row_start(L, l, r), b = row_start(L, l, r + 1);
     int rank = 0;
     for (int x = a; x < b; ++x) rank += t[x] < k ? 1 : 0;
     L.keys[l][a + rank] = k;
   }
 }
+int row_tiles(int rows) { return (rows + 1 + ROW_TILE - 1) / ROW_TILE; }
+
 hipError_t launch_row_sort(unsigned long long* const keys[3], unsigned long long* const tmp[3],
                            const unsigned long long* n, const size_t ncap[3], const int shift[3], int rows, int* off,
-                           int* cur, const int4* rpv, int* rpv_row, hipStream_t s) {
+                           int* cur, const int4* rpv, int* rpv_row, int* tsum, hipStream_t s) {
   RowLists L;
   size_t nmax = 1;
   for (int l = 0; l < 3; ++l) {
@@ -519,8 +556,12 @@ hipError_t launch_row_sort(unsigned long long* const keys[3], unsigned long long
   L.rows = rows;
   L.rpv = rpv;
   L.rpv_row = rpv_row;
+  L.tsum = tsum;
+  L.ntiles = row_tiles(rows);
+  if (L.ntiles > 1024) return hipErrorInvalidValue;
   hipLaunchKernelGGL(k_row_count, dim3(grid, 3), dim3(256), 0, s, L);
-  hipLaunchKernelGGL(k_row_scan, dim3(3), dim3(1024), 0, s, L);
+  hipLaunchKernelGGL(k_row_scan, dim3(L.ntiles, 3), dim3(1024), 0, s, L);
+  if (L.ntiles > 1) hipLaunchKernelGGL(k_row_tiles, dim3(3), dim3(1024), 0, s, L);
   hipLaunchKernelGGL(k_row_scatter, dim3(grid, 3), dim3(256), 0, s, L);
   hipLaunchKernelGGL(k_row_rank, dim3(grid, 3), dim3(256), 0, s, L);
   return hipGetLastError();

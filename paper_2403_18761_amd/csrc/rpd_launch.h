@@ -78,10 +78,11 @@ hipError_t launch_compact_lists(CompactLists J, hipStream_t s);
 // three lists of keys whose row (key >> shift) is below rows, sorted ascending in place; tmp[l] holds n[l] keys;
 // off holds 3 (rows + 1) ints, cur 3 rows ints
 // (off and cur must be zero; list 2 is built from the RPV quadruples rpv: keys[2] receives their (j, k, l) keys
-// sorted by (i, j, k, l) and rpv_row their first sites i)
+// sorted by (i, j, k, l) and rpv_row their first sites i; tsum holds 3 row_tiles(rows) ints of scratch)
+int row_tiles(int rows);
 hipError_t launch_row_sort(unsigned long long* const keys[3], unsigned long long* const tmp[3],
                            const unsigned long long* n, const size_t ncap[3], const int shift[3], int rows, int* off,
-                           int* cur, const int4* rpv, int* rpv_row, hipStream_t s);
+                           int* cur, const int4* rpv, int* rpv_row, int* tsum, hipStream_t s);
 // the collect step's four last steps in one launch: face and edge lists over the sorted keys (slots looked up by
 // key), the sorted RPVs as quadruples, and the cells
 struct FinalizeRows {

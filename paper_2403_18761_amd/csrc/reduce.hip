@@ -307,8 +307,6 @@ hipError_t launch_clear_touched_b0(const unsigned char* touch, int* b0, size_t n
   return hipGetLastError();
 }
 
-// scans that end in a per-workgroup reduction run on a grid of at most 4096 workgroups (16 per compute unit)
-static int scan_grid(size_t n) { return std::min(grid_for(n, 256), 4096); }
 
 // segment length of the gluing list: a power of two, at least 256 slots and at most 4,096 segments
 static unsigned glue_seg_len(size_t cap) { return (unsigned)std::max<size_t>(256, cap / 4096); }
